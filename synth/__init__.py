@@ -1,0 +1,405 @@
+"""Seeded synthetic inputs for the Classic3D objective (sky cubes, uv tracks, beams,
+interpolation grids, flags, noise, single-dish geometry).
+
+This module only *draws inputs*: it holds none of the arithmetic of the method itself
+(no Fourier transform, no reprojection, no regulariser).  Model visibilities are
+computed by whoever consumes a problem (the FP64 oracle in tests, the HIP path in the
+benchmark) and attached with :func:`attach_data`, which only adds the drawn noise.
+
+Every concern draws from its own sub-stream of ``numpy.random.SeedSequence(seed)``
+(layout, field, tracks, flags, noise, sources) so that changing one size does not
+reshuffle the others.
+
+Geometry follows the paper's setting: a 36-antenna array observing with Earth-rotation
+synthesis (Sect. 4, 5), Gaussian primary beams of 1 degree FWHM (Sect. 4.4), an
+orthographic (SIN) sub-image per pointing reached by bilinear interpolation on a
+precomputed grid (Sect. 2.1, Eq. sin_projection; Sect. 3.3), and a Gaussian
+single-dish beam of 16 arcmin (Sect. 4.4).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+ARCSEC = np.pi / (180.0 * 3600.0)
+ARCMIN = 60.0 * ARCSEC
+DEG = np.pi / 180.0
+C_LIGHT = 299_792_458.0
+K_BOLTZMANN = 1.380649e-23
+JY = 1e-26
+
+# LMC centre used for the paper's simulations (Sect. 4.2, 4.4): 05h17m36s, -69d02m.
+LMC_RA = (5.0 + 17.0 / 60.0 + 36.0 / 3600.0) * 15.0 * DEG
+LMC_DEC = -(69.0 + 2.0 / 60.0) * DEG
+ASKAP_LAT = -26.7 * DEG
+
+
+@dataclass
+class Problem:
+    """One objective: sky cube [C][N][N], P pointings with n_sub x n_sub sub-images,
+    visibilities stored block-wise, block index = k * n_chan + c (pointing-major)."""
+
+    name: str
+    n_chan: int
+    n_sky: int
+    pixel_rad: float
+    n_point: int
+    n_sub: int
+    flux_scale: np.ndarray  # [C] float64, Jy per pixel per sky unit
+    lambda_r: float
+    lambda_s: float
+    uv: np.ndarray  # [M, 2] float32, wavelengths
+    vis_offsets: np.ndarray  # [P*C + 1] int64
+    weight: np.ndarray  # [M] float32 (1 / sigma^2)
+    flags: Optional[np.ndarray]  # [M] uint8, 1 = flagged, or None
+    beams: np.ndarray  # [P][n_sub][n_sub] float32, peak 1
+    interp: np.ndarray  # [P][n_sub][n_sub][2] float32, (row, col) sky coordinates
+    x_true: np.ndarray  # [C][N][N] float64
+    noise: np.ndarray  # [M] complex128, unit variance per component
+    noise_rule: tuple  # ("abs", sigma) or ("frac_peak", fraction)
+    sd_n: int = 0
+    sd_stride: int = 0
+    sd_offset: int = 0
+    sd_fwhm_rad: float = 0.0
+    sd_sigma: float = 0.0
+    sd_map: Optional[np.ndarray] = None  # [C][sd_n][sd_n] float32
+    sd_noise_frac: float = 0.01
+    vis: Optional[np.ndarray] = None  # [M] complex64, filled by attach_data
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_vis(self) -> int:
+        return int(self.vis_offsets[-1])
+
+    @property
+    def n_items(self) -> int:
+        return self.n_point * self.n_chan
+
+    def block(self, k: int, c: int) -> slice:
+        i = k * self.n_chan + c
+        return slice(int(self.vis_offsets[i]), int(self.vis_offsets[i + 1]))
+
+
+# ----------------------------------------------------------------------------- streams
+
+def _streams(seed: int, names):
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(len(names))
+    return {n: np.random.Generator(np.random.PCG64(s)) for n, s in zip(names, kids)}
+
+
+_STREAMS = ("layout", "field", "tracks", "flags", "noise", "sources", "extra")
+
+
+# ----------------------------------------------------------------------------- array
+
+def antenna_layout(rng, n_ant: int = 36, radius_m: float = 3000.0) -> np.ndarray:
+    """East/North antenna positions [n_ant][2] uniform in a disk (max baseline <= 2R)."""
+    r = radius_m * np.sqrt(rng.uniform(0.0, 1.0, n_ant))
+    th = rng.uniform(0.0, 2.0 * np.pi, n_ant)
+    return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+
+
+def baselines(enu: np.ndarray) -> np.ndarray:
+    """All i<j antenna differences [n_bl][2] (East, North), metres."""
+    i, j = np.triu_indices(enu.shape[0], k=1)
+    return enu[j] - enu[i]
+
+
+def uv_tracks(bl_en: np.ndarray, n_time: int, dec: float, freq_hz: float,
+              lat: float = ASKAP_LAT, ha_hours: float = 6.0) -> np.ndarray:
+    """Earth-rotation synthesis tracks (textbook ENU -> XYZ -> uv rotation), time-major:
+    returns [n_time * n_bl][2] (u, v) in wavelengths, hour angle uniform over
+    [-ha/2, +ha/2].  The w coordinate is not formed (coplanar model, Sect. 2.1)."""
+    east, north = bl_en[:, 0], bl_en[:, 1]
+    X = -np.sin(lat) * north
+    Y = east
+    Z = np.cos(lat) * north
+    ha = np.linspace(-0.5, 0.5, n_time) * ha_hours * (2.0 * np.pi / 24.0)
+    sH, cH = np.sin(ha)[:, None], np.cos(ha)[:, None]
+    u = sH * X[None, :] + cH * Y[None, :]
+    v = -np.sin(dec) * cH * X[None, :] + np.sin(dec) * sH * Y[None, :] + np.cos(dec) * Z[None, :]
+    lam = C_LIGHT / freq_hz
+    return np.stack([u.ravel(), v.ravel()], axis=1) / lam
+
+
+# ----------------------------------------------------------------------------- skies
+
+def grf_k3(rng, n: int, slope: float = 3.0) -> np.ndarray:
+    """Periodic Gaussian random field with P(k) ~ k^-slope, zero mean, unit variance."""
+    ky = np.fft.fftfreq(n)[:, None]
+    kx = np.fft.rfftfreq(n)[None, :]
+    kk = np.sqrt(kx * kx + ky * ky)
+    amp = np.zeros_like(kk)
+    amp[kk > 0] = kk[kk > 0] ** (-slope / 2.0)
+    white = rng.standard_normal((n, n))
+    g = np.fft.irfft2(np.fft.rfft2(white) * amp, s=(n, n))
+    g -= g.mean()
+    return g / g.std()
+
+
+def lognormal_field(g: np.ndarray, peak: float = 50.0) -> np.ndarray:
+    """exp of a Gaussian field, min-max scaled to [0, peak] (positive diffuse sky)."""
+    e = np.exp(g)
+    return peak * (e - e.min()) / (e.max() - e.min())
+
+
+def ar1_cube(rng, n_chan: int, n: int, rho: float = 0.9, peak: float = 50.0) -> np.ndarray:
+    """Channel-correlated log-normal cube: g_c = rho g_{c-1} + sqrt(1-rho^2) eps_c,
+    exp, cube-global min-max to [0, peak]."""
+    g = np.empty((n_chan, n, n))
+    g[0] = grf_k3(rng, n)
+    s = np.sqrt(1.0 - rho * rho)
+    for c in range(1, n_chan):
+        g[c] = rho * g[c - 1] + s * grf_k3(rng, n)
+    e = np.exp(g)
+    return peak * (e - e.min()) / (e.max() - e.min())
+
+
+def rj_flux_scale(freq_hz: float, pixel_rad: float) -> float:
+    """Rayleigh-Jeans K -> Jy per pixel: 2 k_B nu^2 / c^2 * Omega_pix / 1e-26 (App. B)."""
+    return 2.0 * K_BOLTZMANN * freq_hz ** 2 / C_LIGHT ** 2 * pixel_rad ** 2 / JY
+
+
+# ----------------------------------------------------------------------------- beams
+
+def gaussian_pb(n_sub: int, pixel_rad: float, fwhm_rad: float) -> np.ndarray:
+    """Primary beam A(l, m) = exp(-4 ln2 (l^2+m^2)/FWHM^2), peak 1 at sub-pixel
+    (n_sub/2, n_sub/2); l along columns, m along rows."""
+    t = (np.arange(n_sub) - n_sub // 2) * pixel_rad
+    r2 = t[:, None] ** 2 + t[None, :] ** 2
+    return np.exp(-4.0 * np.log(2.0) * r2 / fwhm_rad ** 2)
+
+
+def identity_interp(n_sub: int, row0: float = 0.0, col0: float = 0.0) -> np.ndarray:
+    """Interpolation grid of an integer (or constant) translation: sub-pixel (a, b)
+    samples sky coordinate (row0 + a, col0 + b)."""
+    a = np.arange(n_sub, dtype=np.float64)
+    g = np.empty((n_sub, n_sub, 2))
+    g[..., 0] = row0 + a[:, None]
+    g[..., 1] = col0 + a[None, :]
+    return g
+
+
+def _sin_fwd(ra, dec, ra0, dec0):
+    """Orthographic (SIN) direction cosines of (ra, dec) about (ra0, dec0)."""
+    l = np.cos(dec) * np.sin(ra - ra0)
+    m = np.sin(dec) * np.cos(dec0) - np.cos(dec) * np.sin(dec0) * np.cos(ra - ra0)
+    return l, m
+
+
+def _sin_inv(l, m, ra0, dec0):
+    n = np.sqrt(np.maximum(0.0, 1.0 - l * l - m * m))
+    dec = np.arcsin(m * np.cos(dec0) + n * np.sin(dec0))
+    ra = ra0 + np.arctan2(l, n * np.cos(dec0) - m * np.sin(dec0))
+    return ra, dec
+
+
+def sin_interp(n_sky: int, n_sub: int, pixel_rad: float, centre_rowcol, ra0=LMC_RA, dec0=LMC_DEC):
+    """Interpolation grid of one pointing (Sect. 3.3): for every sub-pixel (a, b) of a SIN
+    sub-image centred on sky pixel ``centre_rowcol`` (both frames share the pixel size),
+    the (row, col) position of the same sky direction in the mosaic's SIN frame centred
+    on (ra0, dec0) at pixel (n_sky/2, n_sky/2).  Returns the grid and the pointing
+    centre (ra, dec)."""
+    pr, pc = centre_rowcol
+    lk = (pc - n_sky / 2) * pixel_rad
+    mk = (pr - n_sky / 2) * pixel_rad
+    rak, deck = _sin_inv(lk, mk, ra0, dec0)
+    t = (np.arange(n_sub) - n_sub // 2) * pixel_rad
+    L, M = np.meshgrid(t, t)  # L varies along columns, M along rows
+    ra, dec = _sin_inv(L, M, rak, deck)
+    l, m = _sin_fwd(ra, dec, ra0, dec0)
+    g = np.empty((n_sub, n_sub, 2))
+    g[..., 0] = m / pixel_rad + n_sky / 2
+    g[..., 1] = l / pixel_rad + n_sky / 2
+    return g, (float(rak), float(deck))
+
+
+def hex_centres(n_rows: int, n_cols: int, pitch_px: float, n_sky: int) -> np.ndarray:
+    """Close-packed hexagonal footprint (Sect. 4.4): rows spaced pitch*sqrt(3)/2, odd
+    rows offset by half a pitch, centred on the sky.  Returns [P][2] (row, col)."""
+    dy = pitch_px * np.sqrt(3.0) / 2.0
+    pts = []
+    for r in range(n_rows):
+        for c in range(n_cols):
+            pts.append((r * dy, c * pitch_px + (0.5 * pitch_px if r % 2 else 0.0)))
+    pts = np.array(pts)
+    pts -= pts.mean(axis=0)
+    return pts + n_sky / 2
+
+
+# ----------------------------------------------------------------------------- data
+
+def attach_data(p: Problem, model_vis: np.ndarray) -> Problem:
+    """y = model + sigma * noise, with natural weights 1/sigma^2.  The noise rule is
+    ("abs", sigma) or ("frac_peak", f): sigma = f * max |model| of each block."""
+    model_vis = np.asarray(model_vis, dtype=np.complex128)
+    y = np.empty(p.n_vis, dtype=np.complex128)
+    w = np.empty(p.n_vis, dtype=np.float32)
+    kind, val = p.noise_rule
+    for i in range(p.n_items):
+        s = slice(int(p.vis_offsets[i]), int(p.vis_offsets[i + 1]))
+        if s.stop == s.start:
+            continue
+        if kind == "abs":
+            sig = val
+        else:
+            live = model_vis[s] if p.flags is None else model_vis[s][p.flags[s] == 0]
+            peak = np.abs(live).max() if live.size else 1.0
+            sig = val * (peak if peak > 0 else 1.0)
+        y[s] = model_vis[s] + sig * p.noise[s]
+        w[s] = 1.0 / (sig * sig)
+    p.vis = y.astype(np.complex64)
+    p.weight = w
+    return p
+
+
+def attach_sd(p: Problem, sd_model: np.ndarray) -> Problem:
+    """Single-dish map T = model + noise, sigma_sd = frac * max T (per channel, Sect. 2.4)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(p.meta.get("seed", 0) + 17)))
+    t = np.asarray(sd_model, dtype=np.float64)
+    sig = p.sd_noise_frac * float(np.abs(t).max() if t.size else 1.0)
+    p.sd_sigma = sig if sig > 0 else 1.0
+    p.sd_map = (t + p.sd_sigma * rng.standard_normal(t.shape)).astype(np.float32)
+    return p
+
+
+# ----------------------------------------------------------------------------- configs
+
+def single_pointing(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_time: int,
+                    n_keep: Optional[int], sky: str, lambda_r: float, noise_rule,
+                    freq_hz: float = 1.4e9, fwhm_deg: float = 1.0, flag_rate: float = 0.0,
+                    n_ant: int = 36, radius_m: float = 3000.0, n_src: int = 5) -> Problem:
+    """One pointing, one channel, identity interpolation grid (sub-image = sky)."""
+    st = _streams(seed, _STREAMS)
+    pix = pixel_arcsec * ARCSEC
+    enu = antenna_layout(st["layout"], n_ant, radius_m)
+    uv = uv_tracks(baselines(enu), n_time, LMC_DEC, freq_hz)
+    if n_keep is not None:
+        uv = uv[:n_keep]
+    m = uv.shape[0]
+    if sky == "points":
+        x = np.zeros((1, n_sky, n_sky))
+        lo, hi = n_sky // 8, n_sky - n_sky // 8
+        cells = st["sources"].choice((hi - lo) ** 2, size=n_src, replace=False)
+        flux = st["sources"].uniform(0.1, 1.0, n_src)
+        for cidx, f in zip(cells, flux):
+            x[0, lo + cidx // (hi - lo), lo + cidx % (hi - lo)] = f
+        scale = 1.0
+    else:
+        x = lognormal_field(grf_k3(st["field"], n_sky))[None]
+        scale = rj_flux_scale(freq_hz, pix)
+    flags = None
+    if flag_rate > 0:
+        flags = (st["flags"].uniform(size=m) < flag_rate).astype(np.uint8)
+    noise = st["noise"].standard_normal(m) + 1j * st["noise"].standard_normal(m)
+    return Problem(
+        name=name, n_chan=1, n_sky=n_sky, pixel_rad=pix, n_point=1, n_sub=n_sky,
+        flux_scale=np.array([scale]), lambda_r=lambda_r, lambda_s=0.0,
+        uv=uv.astype(np.float32), vis_offsets=np.array([0, m], dtype=np.int64),
+        weight=np.ones(m, dtype=np.float32), flags=flags,
+        beams=gaussian_pb(n_sky, pix, fwhm_deg * DEG)[None].astype(np.float32),
+        interp=identity_interp(n_sky)[None].astype(np.float32),
+        x_true=x, noise=noise, noise_rule=noise_rule,
+        meta={"seed": seed, "freq_hz": freq_hz, "fwhm_deg": fwhm_deg},
+    )
+
+
+def config_c1(seed: int = 1001, lambda_r: float = 0.0) -> Problem:
+    """64x64 sky, 10 arcsec pixels, 5 point sources U[0.1,1] Jy, 1 deg PB, 36-antenna
+    6 km array at 1.4 GHz over 6 h, first 20,000 visibilities, sigma = 0.01 Jy."""
+    return single_pointing("c1-points-64", seed, 64, 10.0, 32, 20_000, "points", lambda_r,
+                           ("abs", 0.01))
+
+
+def config_c2(seed: int = 2001, n_time: int = 1000, n_sky: int = 512) -> Problem:
+    """512x512 sky at 7 arcsec of a k^-3 log-normal field (0-50 K), 630 baselines x 1000
+    samples = 630,000 visibilities, noise 1% of peak, lambda_r = 1e-2."""
+    return single_pointing("c2-diffuse-512", seed, n_sky, 7.0, n_time, None, "diffuse", 1e-2,
+                           ("frac_peak", 0.01))
+
+
+def mosaic(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_rows: int, n_cols: int,
+           pitch_px: float, fwhm_px: float, n_sub: int, time_range, flag_max: float,
+           n_chan: int = 1, lambda_r: float = 1e-2, lambda_s: float = 1.0,
+           sd_n: int = 64, sd_fwhm_arcmin: float = 16.0, freq_hz: float = 1.4e9,
+           n_keep: Optional[int] = None, max_vis_per_block: Optional[int] = None) -> Problem:
+    """Hexagonal mosaic of Gaussian-beam pointings over one sky (Sect. 4.4 geometry):
+    each pointing has its own track length T_k ~ U{time_range} and flag rate
+    f_k ~ U[0, flag_max] (Bernoulli per visibility), giving uneven counts."""
+    st = _streams(seed, _STREAMS)
+    pix = pixel_arcsec * ARCSEC
+    enu = antenna_layout(st["layout"], 36, 3000.0)
+    bl = baselines(enu)
+    centres = hex_centres(n_rows, n_cols, pitch_px, n_sky)
+    P = centres.shape[0]
+    if n_chan == 1:
+        x = lognormal_field(grf_k3(st["field"], n_sky))[None]
+    else:
+        x = ar1_cube(st["field"], n_chan, n_sky)
+    beams, grids, uvs, flags, offs = [], [], [], [], [0]
+    pb = gaussian_pb(n_sub, pix, fwhm_px * pix)
+    for k in range(P):
+        g, (rak, deck) = sin_interp(n_sky, n_sub, pix, centres[k])
+        grids.append(g)
+        beams.append(pb)
+        n_t = int(st["tracks"].integers(time_range[0], time_range[1] + 1))
+        uvk = uv_tracks(bl, n_t, deck, freq_hz)
+        if n_keep is not None:
+            uvk = uvk[:n_keep]
+        if max_vis_per_block is not None:
+            uvk = uvk[:max_vis_per_block]
+        fr = st["flags"].uniform(0.0, flag_max)
+        for c in range(n_chan):
+            uvs.append(uvk)
+            flags.append((st["flags"].uniform(size=uvk.shape[0]) < fr).astype(np.uint8))
+            offs.append(offs[-1] + uvk.shape[0])
+    uv = np.concatenate(uvs).astype(np.float32)
+    m = uv.shape[0]
+    noise = st["noise"].standard_normal(m) + 1j * st["noise"].standard_normal(m)
+    sd_stride = n_sky // sd_n if sd_n else 0
+    return Problem(
+        name=name, n_chan=n_chan, n_sky=n_sky, pixel_rad=pix, n_point=P, n_sub=n_sub,
+        flux_scale=np.full(n_chan, rj_flux_scale(freq_hz, pix)), lambda_r=lambda_r,
+        lambda_s=lambda_s, uv=uv, vis_offsets=np.array(offs, dtype=np.int64),
+        weight=np.ones(m, dtype=np.float32), flags=np.concatenate(flags),
+        beams=np.stack(beams).astype(np.float32), interp=np.stack(grids).astype(np.float32),
+        x_true=x, noise=noise, noise_rule=("frac_peak", 0.01),
+        sd_n=sd_n, sd_stride=sd_stride, sd_offset=sd_stride // 2,
+        sd_fwhm_rad=sd_fwhm_arcmin * ARCMIN,
+        meta={"seed": seed, "freq_hz": freq_hz, "centres": centres},
+    )
+
+
+def config_c3(seed: int = 3001, time_range=(1400, 2000), n_keep=None) -> Problem:
+    """36 pointings (6x6 hex, 1 deg pitch = 120 px at 30 arcsec) over a 1024^2 sky, 1 deg
+    PB, 384^2 sub-images, T_k ~ U{1400..2000} samples x 630 baselines, 0-30% flags,
+    64x64 single-dish map under a 16 arcmin beam, lambda_r = 1e-2, lambda_s = 1."""
+    return mosaic("c3-mosaic-36x1024", seed, 1024, 30.0, 6, 6, 120.0, 120.0, 384, time_range,
+                  0.3, n_keep=n_keep)
+
+
+def config_c3_mini(seed: int = 3101) -> Problem:
+    """Reduced mosaic with the C3 structure (hex footprint, SIN grids, uneven flagged
+    counts, SD map) at a size the oracle evaluates in seconds: 2x2 pointings, 128^2 sky,
+    64^2 sub-images, 30-60 samples x 630 baselines."""
+    return mosaic("c3-mini", seed, 128, 30.0, 2, 2, 30.0, 30.0, 64, (30, 60), 0.3,
+                  sd_n=16, sd_fwhm_arcmin=4.0)
+
+
+def config_c5_geometry(seed: int = 5001) -> Problem:
+    """Warm-start geometry: 256^2 sky at 30 arcsec, 3x3 hex of 20 arcmin beams (pitch
+    40 px), 128^2 sub-images, 200,000 visibilities per pointing, lambda_s = 0."""
+    return mosaic("c5-warmstart-256", seed, 256, 30.0, 3, 3, 40.0, 40.0, 128, (318, 318), 0.0,
+                  lambda_s=0.0, sd_n=0, max_vis_per_block=200_000)
+
+
+CONFIGS = {
+    "c1": config_c1,
+    "c2": config_c2,
+    "c3": config_c3,
+    "c3-mini": config_c3_mini,
+    "c5": config_c5_geometry,
+}
