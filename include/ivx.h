@@ -1,0 +1,187 @@
+/*
+ * ivx — objective and gradient of the Classic3D joint-deconvolution criterion on one
+ * MI355X (gfx950).  C ABI: plain pointers and sizes, no C++ or framework types.
+ *
+ * What is evaluated (Sect. 2.1, 2.2, 2.4; Eq. Q, Eq. 3, Eq. fusion_cost):
+ *
+ *   Q_tot(x) = sum_{k,c} J_kc(x) + lambda_s sum_c K_c(x) + lambda_r sum_c R_c(x)
+ *
+ *   J_kc = 1/2 sum_j w_j | V_j - y_j |^2   over the unflagged visibilities of pointing k,
+ *          channel c, with w_j = 1/sigma_j^2 (the SIGMA column, Sect. 2.2) and the model
+ *   V_j  = sum_{a,b} s_c A_k[a][b] x'_kc[a][b] exp(-2 pi i (u_j l_b + v_j m_a))
+ *          (coplanar forward model, Sect. 2.1), l_b = (b - n/2) delta along columns,
+ *          m_a = (a - n/2) delta along rows, n = n_sub;
+ *   x'_kc = bilinear sample of sky channel c on pointing k's interpolation grid
+ *          (SIN reprojection, Eq. sin_projection; grids precomputed, Sect. 3.3):
+ *          sub-pixel (a,b) reads sky coordinate (row, col) = interp[k][a][b][0..1],
+ *          sky pixel (i,j) sits at coordinate (i,j), pixels outside [0,N)^2 read 0;
+ *   R_c  = 1/2 || D x_c ||^2, D = 3x3 Laplacian [[0,-1,0],[-1,4,-1],[0,-1,0]] with zero
+ *          padding (Eq. 3);
+ *   K_c  = 1/2 sum_{p,q} ((T~_c[p][q] - T_c[p][q]) / sigma_sd)^2, T~ = the sky convolved
+ *          with a unit-sum Gaussian single-dish beam (FWHM sd_fwhm_rad, truncated at
+ *          4 sigma, zero padding), point-sampled at rows/cols sd_offset + p*sd_stride
+ *          (fusion term, Sect. 2.4).
+ *
+ * The gradient returned is dQ_tot/dx over the whole cube, in the same layout as x.
+ * The visibility model is evaluated with a non-uniform FFT (exponential-of-semicircle
+ * kernel, Barnett et al. 2019 — the paper's NUFFT reference, Sect. 2.1) whose accuracy is
+ * set by nufft_eps or an explicit kernel width; all work runs in hand-written gfx950
+ * kernels.  The floating-point type of every real array below is ivx_real: float in
+ * libivx.so, double in the FP64 test build libivx_f64.so (same symbols).
+ *
+ * Layouts (all row-major, C order):
+ *   sky, grad, image    [n_chan][n_sky][n_sky]
+ *   uv                  [M][2]  (u, v) in wavelengths, ivx_real
+ *   vis, model_vis      [M][2]  (re, im) interleaved, ivx_real
+ *   weight              [M]     ivx_real, natural weights 1/sigma^2
+ *   flags               [M]     uint8, non-zero = flagged (dropped at set_data), or NULL
+ *   beams               [n_point][n_sub][n_sub]       ivx_real, primary beam A_k
+ *   interp              [n_point][n_sub][n_sub][2]    ivx_real, (row, col) sky coordinate
+ *   sd_map              [n_chan][sd_n][sd_n]          ivx_real, or NULL
+ *   The M visibilities are stored block after block, block b = k * n_chan + c
+ *   (pointing-major); vis_offsets[b] .. vis_offsets[b+1] is block b.
+ *
+ * Memory: every pointer argument may be host memory or device memory of the current
+ * device (the library copies with hipMemcpyDefault).  The caller keeps ownership of
+ * everything it passes; set_data copies, compacts and reorders what it needs into plan-
+ * owned device memory, so caller buffers may be freed as soon as it returns.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ * evaluation calls are asynchronous on that stream except where a host pointer receives
+ * results (terms), which synchronises the stream.
+ *
+ * Errors: every call returns an ivx_status; a negative value means nothing was written
+ * to the caller's outputs.  ivx_last_error() gives a thread-local message for the last
+ * failure.  No C++ exception crosses this boundary.  Calls on one plan are not
+ * re-entrant: one plan must not be used from two threads at once.
+ */
+#ifndef IVX_H
+#define IVX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifdef IVX_REAL_DOUBLE
+typedef double ivx_real;
+#else
+typedef float ivx_real;
+#endif
+
+#define IVX_VERSION 1
+
+typedef enum {
+    IVX_OK = 0,
+    IVX_EINVAL = -1,     /* bad shape, size, pointer or parameter */
+    IVX_ENOMEM = -2,     /* device or host allocation failed; plan left unallocated */
+    IVX_EHIP = -3,       /* HIP runtime error (message in ivx_last_error) */
+    IVX_ENONFINITE = -4, /* NaN/Inf found in unflagged input data by set_data */
+    IVX_ESTATE = -5      /* call out of order (e.g. evaluation before set_data) */
+} ivx_status;
+
+typedef struct ivx_plan ivx_plan;
+
+/* Problem geometry and hyper-parameters (Sect. 2.2 lambda_r, Sect. 2.4 lambda_s). */
+typedef struct {
+    int32_t n_chan;             /* C >= 1 spectral channels */
+    int32_t n_sky;              /* N: sky is N x N pixels */
+    double pixel_rad;           /* delta > 0: pixel size of sky and sub-images, radians */
+    int32_t n_point;            /* P >= 1 pointings */
+    int32_t n_sub;              /* n: sub-image size (even, >= 4); phase centre (n/2, n/2) */
+    const int64_t *vis_offsets; /* host, P*C+1 non-decreasing entries, [0] = 0 */
+    const double *flux_scale;   /* host, [C]: s_c, sky units -> Jy per pixel */
+    double lambda_r;            /* Laplacian regularisation weight, >= 0 */
+    double lambda_s;            /* single-dish fusion weight, >= 0 (0 ignores sd_map) */
+    int32_t sd_n;               /* single-dish map is sd_n x sd_n (0 = no fusion term) */
+    int32_t sd_stride;          /* sampling stride in sky pixels */
+    int32_t sd_offset;          /* first sample row/column */
+    double sd_fwhm_rad;         /* single-dish beam FWHM, radians */
+    double sd_sigma;            /* single-dish noise sigma_sd > 0 */
+    double nufft_eps;           /* requested NUFFT accuracy (0 = 1e-7 float, 1e-12 double) */
+    int32_t kernel_width;       /* spreading kernel width in fine cells (0 = from eps) */
+    int32_t fine_size;          /* fine grid n_f, power of two >= 2 n_sub (0 = auto) */
+    int32_t tile;               /* gridding tile edge in fine cells (0 = auto) */
+    int32_t reserved;           /* must be 0 */
+} ivx_problem;
+
+/* Validate `d`, choose the NUFFT parameters and allocate the plan.  No device memory is
+ * touched until set_data.  *out is NULL on failure. */
+ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out);
+
+/* Copy the data of every block into the plan (Sect. 3.2: all pointings concatenated):
+ * drops flagged visibilities, folds u<0 onto u>0 by Hermitian symmetry of a real sky,
+ * sorts by fine-grid tile and builds the work list.  beams and interp are required;
+ * flags and sd_map may be NULL (sd_map is required when lambda_s > 0 and sd_n > 0).
+ * Returns IVX_ENONFINITE if an unflagged visibility, weight or uv is not finite, or a
+ * weight is negative.  May be called again to replace the data (same sizes). */
+ivx_status ivx_plan_set_data(ivx_plan *plan, const ivx_real *uv, const ivx_real *vis,
+                             const ivx_real *weight, const uint8_t *flags,
+                             const ivx_real *beams, const ivx_real *interp,
+                             const ivx_real *sd_map, void *stream);
+
+/* One evaluation of Q_tot and its gradient at sky x (Eq. fusion_cost).
+ * sky, grad: device, [C][N][N]; grad is overwritten.  terms (host or device, 4 doubles)
+ * receives {Q_tot, Q, K, R} with Q = sum J_kc; NULL skips it.  Host `terms`
+ * synchronises the stream. */
+ivx_status ivx_objective_grad(ivx_plan *plan, const ivx_real *sky, ivx_real *grad,
+                              double *terms, void *stream);
+
+/* Model visibilities V(sky) of every block in the caller's original order (flagged
+ * entries are written as 0).  sky: device [C][N][N]; model_vis: device [M][2]. */
+ivx_status ivx_forward(ivx_plan *plan, const ivx_real *sky, ivx_real *model_vis,
+                       void *stream);
+
+/* Weighted adjoint: image = Re sum_k P_k^T s_c A_k F^H W v  (flagged entries ignored),
+ * the transpose of ivx_forward with the natural weights; it equals -grad Q at x = 0
+ * when v = y.  vis: device [M][2] caller order; image: device [C][N][N], overwritten. */
+ivx_status ivx_adjoint(ivx_plan *plan, const ivx_real *vis, ivx_real *image, void *stream);
+
+/* Time the gridding stage for each candidate tile edge that fits the LDS and keep the
+ * fastest (the result is accuracy-neutral: only the blocking changes).  budget_ms bounds
+ * the time spent; *chosen_tile (host, may be NULL) receives the tile kept. */
+ivx_status ivx_autotune(ivx_plan *plan, double budget_ms, int32_t *chosen_tile, void *stream);
+
+/* Stages of one evaluation, in launch order (bit i of a stage mask = stage i). */
+enum {
+    IVX_STAGE_IMAGE_ROWS = 0, /* reprojection x beam x deapodization + row FFTs */
+    IVX_STAGE_COL_FWD = 1,    /* column FFTs -> extended fine grid */
+    IVX_STAGE_GRID = 2,       /* degrid, residual, data term, spread (per tile) */
+    IVX_STAGE_FOLD = 3,       /* slot reduction + Hermitian symmetrisation */
+    IVX_STAGE_COL_INV = 4,    /* inverse column FFTs */
+    IVX_STAGE_ROW_INV = 5,    /* inverse row FFTs x deapodization x beam */
+    IVX_STAGE_SD = 6,         /* single-dish model and residual */
+    IVX_STAGE_SKY = 7,        /* reprojection transpose + Laplacian + single-dish gradient */
+    IVX_STAGE_FINAL = 8,      /* FP64 reduction of the four terms */
+    IVX_NSTAGE = 9
+};
+
+/* Device timing of ivx_objective_grad: while stage_mask != 0, each evaluation records a
+ * HIP event pair on the evaluation stream around every stage in the mask.  The events
+ * are owned by the plan.  ivx_stage_times waits for them, writes the summed milliseconds
+ * per stage into ms[IVX_NSTAGE] (host) and the number of timed evaluations into *n_eval
+ * (host), and resets the sums. */
+ivx_status ivx_set_timing(ivx_plan *plan, uint32_t stage_mask);
+ivx_status ivx_stage_times(ivx_plan *plan, double *ms, int64_t *n_eval);
+
+/* Plan facts, host array of 16 int64: {n_fine, kernel_width, tile, n_work_items,
+ * n_live_vis, n_slots, device_bytes, n_items, ext_rows, ext_cols, graph_nodes,
+ * window, 0, 0, 0, 0}. */
+ivx_status ivx_plan_info(const ivx_plan *plan, int64_t *info16);
+
+/* Release every resource of the plan (NULL is accepted). */
+ivx_status ivx_plan_destroy(ivx_plan *plan);
+
+/* Thread-local description of the last failure ("" if none). */
+const char *ivx_last_error(void);
+
+/* IVX_VERSION of the library; sizeof(ivx_real) is returned by ivx_real_size(). */
+int ivx_version(void);
+int ivx_real_size(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IVX_H */

@@ -62,6 +62,9 @@ def _load():
         lib.orc_dft_forward.restype = None
         lib.orc_dft_adjoint.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, dp, dp]
         lib.orc_dft_adjoint.restype = None
+        lib.orc_dft_adjoint_pixels.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, dp,
+                                               ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), dp]
+        lib.orc_dft_adjoint_pixels.restype = None
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -98,6 +101,19 @@ def dft_adjoint(coef: np.ndarray, uv: np.ndarray, delta: float, n: int) -> np.nd
     if uv.shape[0]:
         _load().orc_dft_adjoint(int(n), float(delta), uv.shape[0], _dp(uv), _dp(cc), _dp(g))
     return g
+
+
+def dft_adjoint_pixels(coef: np.ndarray, uv: np.ndarray, delta: float, n: int, pixels) -> np.ndarray:
+    """O5 at selected pixels (a, b) only: one direct sum over all visibilities each."""
+    coef = np.asarray(coef, dtype=np.complex128).ravel()
+    cc = np.ascontiguousarray(np.stack([coef.real, coef.imag], axis=1))
+    uv = np.ascontiguousarray(uv, dtype=np.float64).reshape(-1, 2)
+    pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+    out = np.zeros(pix.shape[0])
+    if uv.shape[0] and pix.shape[0]:
+        _load().orc_dft_adjoint_pixels(int(n), float(delta), uv.shape[0], _dp(uv), _dp(cc), pix.shape[0],
+                                       pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(out))
+    return out
 
 
 # ----------------------------------------------------------------------------- O1 / O6

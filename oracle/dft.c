@@ -118,3 +118,24 @@ void orc_dft_adjoint(int n, double delta, int64_t m, const double *uv, const dou
     }
     free(acc);
 }
+
+/* The adjoint evaluated at selected pixels only (one direct sum over all visibilities per
+ * pixel), for sampled checks at sizes where the full adjoint image is too slow.
+ * pix: [np][2] (a, b); out: [np]. */
+void orc_dft_adjoint_pixels(int n, double delta, int64_t m, const double *uv, const double *coef,
+                            int64_t np, const int32_t *pix, double *out)
+{
+    const int c = n / 2;
+    #pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < np; ++q) {
+        const int a = pix[2 * q], b = pix[2 * q + 1];
+        double s = 0.0;
+        for (int64_t j = 0; j < m; ++j) {
+            const double fu = frac_part(uv[2 * j] * delta);
+            const double fv = frac_part(uv[2 * j + 1] * delta);
+            const double th = 2.0 * M_PI * (fu * (double)(b - c) + fv * (double)(a - c));
+            s += coef[2 * j] * cos(th) - coef[2 * j + 1] * sin(th);
+        }
+        out[q] = s;
+    }
+}

@@ -1,0 +1,902 @@
+// C ABI of the Classic3D objective/gradient engine: plan creation, plan-time data
+// preparation (Sect. 3.2 concatenation of all pointings; flag compaction; Hermitian fold;
+// tile binning), evaluation sequencing on a HIP stream, and error reporting.
+#include "ivx_internal.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace ivx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ivx_status fail(ivx_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+ivx_status hip_fail(hipError_t e, const char *where) {
+    return fail(IVX_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define IVX_HIP(call)                                        \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+    } while (0)
+
+// ------------------------------------------------------------- kernel mathematics
+// Exponential of semicircle, phi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1)), |z| <= W/2
+// (Barnett, Magland & af Klinteberg 2019).
+double es_phi(double z, double W, double beta) {
+    const double t = 2.0 * z / W;
+    const double q = 1.0 - t * t;
+    if (q < 0.0) return 0.0;
+    return std::exp(beta * (std::sqrt(q) - 1.0));
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Fourier transform of the kernel at angular frequency kappa (grid units):
+// phi_hat(kappa) = int_{-W/2}^{W/2} phi(z) cos(kappa z) dz.
+double es_phihat(double kappa, double W, double beta, const std::vector<double> &x,
+                 const std::vector<double> &w) {
+    double s = 0.0;
+    for (size_t i = 0; i < x.size(); ++i) {
+        const double z = 0.5 * W * x[i];
+        s += w[i] * es_phi(z, W, beta) * std::cos(kappa * z);
+    }
+    return 0.5 * W * s;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+// Host copy of one live visibility after the fold (tile-independent part).
+struct HostVis {
+    int32_t er0, ec0; // extended-grid cell of the footprint start (row, col)
+    double fy, fx;    // fractional offsets in [0, 1)
+    int64_t src;      // caller index, bit-inverted when folded
+    real yr, yi;      // data (conjugated when folded)
+    real w;           // weight
+};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+} // namespace
+
+struct ivx_plan {
+    ivx_problem d{};
+    std::vector<int64_t> offsets;
+    std::vector<double> fscale;
+    Geom g{};
+    double beta = 0.0;
+    int nwave = 4;
+    int tile_fixed = 0;
+    std::vector<real> dq_host;
+    std::vector<cpx> tw_host;
+    bool has_data = false;
+    int64_t m_total = 0, m_live = 0;
+    int n_work = 0, n_slots = 0;
+    int sd_rb = 0;
+    std::vector<real> gB_host;
+    std::vector<HostVis> hv;          // live visibilities, block-major, caller order
+    std::vector<int64_t> block_live;  // live count prefix per block
+    // device memory
+    std::vector<DevBuf> bufs;
+    real *d_dq = nullptr, *d_fscale = nullptr;
+    cpx *d_tw = nullptr;
+    real *d_beams = nullptr, *d_interp = nullptr;
+    VisCoord *d_crd = nullptr;
+    cpx *d_vis = nullptr;
+    real *d_wgt = nullptr;
+    int64_t *d_perm = nullptr;
+    WorkItem *d_work = nullptr;
+    int32_t *d_tslot = nullptr;
+    cpx *d_R = nullptr, *d_ext = nullptr, *d_slots = nullptr, *d_hs = nullptr;
+    real *d_gp = nullptr;
+    int32_t *d_cptr = nullptr;
+    CsrEnt *d_cent = nullptr;
+    real *d_sdmap = nullptr, *d_gB = nullptr, *d_U = nullptr, *d_E = nullptr;
+    double *d_jpart = nullptr, *d_rpart = nullptr, *d_kpart = nullptr, *d_terms = nullptr;
+    int n_rpart = 0, n_kpart = 0;
+    size_t dev_bytes = 0;
+    // per-tile device arrays that depend on the tile size
+    size_t tile_bytes = 0;
+    // stage timing
+    uint32_t timing_mask = 0;
+    std::vector<hipEvent_t> ev_pool;            // all events ever created (reused)
+    std::vector<std::pair<int, int>> ev_used;   // (stage, index of start event) pending
+    size_t ev_next = 0;
+    int64_t timed_evals = 0;
+};
+
+namespace {
+
+template <typename T> ivx_status dalloc(ivx_plan *p, T **out, size_t count) {
+    *out = nullptr;
+    if (count == 0) count = 1;
+    void *ptr = nullptr;
+    const size_t bytes = count * sizeof(T);
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(IVX_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    p->bufs.push_back(DevBuf{ptr, bytes});
+    p->dev_bytes += bytes;
+    *out = static_cast<T *>(ptr);
+    return IVX_OK;
+}
+
+void free_all(ivx_plan *p) {
+    for (auto &b : p->bufs) (void)hipFree(b.p);
+    p->bufs.clear();
+    p->dev_bytes = 0;
+    p->d_dq = p->d_fscale = nullptr;
+    p->d_tw = nullptr;
+    p->d_beams = p->d_interp = nullptr;
+    p->d_crd = nullptr;
+    p->d_vis = nullptr;
+    p->d_wgt = nullptr;
+    p->d_perm = nullptr;
+    p->d_work = nullptr;
+    p->d_tslot = nullptr;
+    p->d_R = p->d_ext = p->d_slots = p->d_hs = nullptr;
+    p->d_gp = nullptr;
+    p->d_cptr = nullptr;
+    p->d_cent = nullptr;
+    p->d_sdmap = p->d_gB = p->d_U = p->d_E = nullptr;
+    p->d_jpart = p->d_rpart = p->d_kpart = p->d_terms = nullptr;
+    p->has_data = false;
+}
+
+void free_one(ivx_plan *p, void *ptr) {
+    for (size_t i = 0; i < p->bufs.size(); ++i) {
+        if (p->bufs[i].p == ptr) {
+            (void)hipFree(ptr);
+            p->dev_bytes -= p->bufs[i].bytes;
+            p->bufs.erase(p->bufs.begin() + i);
+            return;
+        }
+    }
+}
+
+int pick_ldw(int win) { return win | 1; }
+
+// Geometry that depends on the tile edge.
+void set_tile(ivx_plan *p, int T) {
+    Geom &g = p->g;
+    g.T = T;
+    g.win = T + g.W - 1;
+    g.ldw = pick_ldw(g.win);
+    // footprint starts reach extended row nf + (O - W/2) + 1 and column nf/2 + 1 + ...
+    const int max_er0 = g.nf + g.O; // generous upper bound on footprint-start rows
+    const int max_ec0 = g.nf / 2 + g.O + 1;
+    g.nty = max_er0 / T + 1;
+    g.ntx = max_ec0 / T + 1;
+    g.eh = g.nty * T + g.W - 1;
+    g.ew = g.ntx * T + g.W - 1;
+    g.ext_stride = (int64_t)g.eh * g.ew;
+    g.win_stride = (int64_t)g.win * g.win;
+}
+
+bool tile_fits(const ivx_plan *p, int T, int nwave) {
+    if (T < p->g.W || T > 255) return false;
+    Geom g = p->g;
+    g.T = T;
+    g.win = T + g.W - 1;
+    g.ldw = pick_ldw(g.win);
+    return grid_lds_bytes(g, nwave) <= 65536;
+}
+
+int auto_tile(const ivx_plan *p) {
+    const int cand[] = {64, 48, 40, 32, 24, 16, 12, 8};
+    for (int T : cand)
+        if (tile_fits(p, T, p->nwave)) return T;
+    return 0;
+}
+
+// Build the tile-dependent device data: sorted records, work list, slot CSR.
+ivx_status build_bins(ivx_plan *p, hipStream_t st) {
+    Geom &g = p->g;
+    const int n_items = g.C * g.P;
+    const int ntiles = g.nty * g.ntx;
+    const int64_t L = p->m_live;
+    const int chunk_max = 2048;
+    std::vector<VisCoord> crd(L > 0 ? L : 1);
+    std::vector<cpx> vis(L > 0 ? L : 1);
+    std::vector<real> wgt(L > 0 ? L : 1);
+    std::vector<int64_t> perm(L > 0 ? L : 1);
+    std::vector<int32_t> tslot((size_t)n_items * (ntiles + 1), 0);
+    std::vector<WorkItem> work;
+    std::vector<int32_t> key;
+    std::vector<int64_t> cnt(ntiles + 1);
+    int slot = 0;
+    for (int it = 0; it < n_items; ++it) {
+        const int64_t b0 = p->block_live[it], b1 = p->block_live[it + 1];
+        const int64_t n = b1 - b0;
+        key.resize(n);
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int64_t i = 0; i < n; ++i) {
+            const HostVis &h = p->hv[b0 + i];
+            const int ty = h.er0 / g.T, tx = h.ec0 / g.T;
+            key[i] = ty * g.ntx + tx;
+            cnt[key[i] + 1]++;
+        }
+        for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
+        std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+        for (int64_t i = 0; i < n; ++i) {
+            const HostVis &h = p->hv[b0 + i];
+            const int64_t o = b0 + pos[key[i]]++;
+            const int ty = key[i] / g.ntx, tx = key[i] - (key[i] / g.ntx) * g.ntx;
+            const uint32_t ix = (uint32_t)(h.ec0 - tx * g.T), iy = (uint32_t)(h.er0 - ty * g.T);
+#ifdef IVX_REAL_DOUBLE
+            crd[o] = VisCoord{ix, iy, h.fx, h.fy};
+#else
+            auto q24 = [](double f) -> uint32_t {
+                double s = std::floor(f * 16777216.0 + 0.5);
+                if (s > 16777215.0) s = 16777215.0;
+                if (s < 0.0) s = 0.0;
+                return (uint32_t)s;
+            };
+            crd[o] = VisCoord{(ix << 24) | q24(h.fx), (iy << 24) | q24(h.fy)};
+#endif
+            vis[o] = cpx{h.yr, h.yi};
+            wgt[o] = h.w;
+            perm[o] = h.src;
+        }
+        int32_t *ts = &tslot[(size_t)it * (ntiles + 1)];
+        for (int t = 0; t < ntiles; ++t) {
+            ts[t] = slot;
+            const int64_t c0 = cnt[t], c1 = cnt[t + 1];
+            for (int64_t s0 = c0; s0 < c1; s0 += chunk_max) {
+                const int64_t c = std::min<int64_t>(chunk_max, c1 - s0);
+                WorkItem w;
+                w.item = it;
+                w.ty = t / g.ntx;
+                w.tx = t - (t / g.ntx) * g.ntx;
+                w.count = (int32_t)c;
+                w.begin = b0 + s0;
+                w.slot = slot++;
+                w.pad = 0;
+                work.push_back(w);
+            }
+        }
+        ts[ntiles] = slot;
+    }
+    // heaviest first: blocks are dispatched roughly in index order
+    std::stable_sort(work.begin(), work.end(),
+                     [](const WorkItem &a, const WorkItem &b) { return a.count > b.count; });
+    p->n_work = (int)work.size();
+    p->n_slots = slot;
+
+    for (void *old : {(void *)p->d_crd, (void *)p->d_vis, (void *)p->d_wgt, (void *)p->d_perm,
+                      (void *)p->d_work, (void *)p->d_tslot, (void *)p->d_ext, (void *)p->d_slots,
+                      (void *)p->d_jpart})
+        if (old) free_one(p, old);
+    p->d_crd = nullptr;
+    p->d_vis = nullptr;
+    p->d_wgt = nullptr;
+    p->d_perm = nullptr;
+    p->d_work = nullptr;
+    p->d_tslot = nullptr;
+    p->d_ext = p->d_slots = nullptr;
+    p->d_jpart = nullptr;
+    ivx_status s;
+    if ((s = dalloc(p, &p->d_crd, crd.size())) != IVX_OK) return s;
+    if ((s = dalloc(p, &p->d_vis, vis.size())) != IVX_OK) return s;
+    if ((s = dalloc(p, &p->d_wgt, wgt.size())) != IVX_OK) return s;
+    if ((s = dalloc(p, &p->d_perm, perm.size())) != IVX_OK) return s;
+    if ((s = dalloc(p, &p->d_work, work.size())) != IVX_OK) return s;
+    if ((s = dalloc(p, &p->d_tslot, tslot.size())) != IVX_OK) return s;
+    if ((s = dalloc(p, &p->d_ext, (size_t)n_items * g.ext_stride)) != IVX_OK) return s;
+    if ((s = dalloc(p, &p->d_slots, (size_t)std::max(1, slot) * g.win_stride)) != IVX_OK) return s;
+    if ((s = dalloc(p, &p->d_jpart, work.size())) != IVX_OK) return s;
+    IVX_HIP(hipMemcpyAsync(p->d_crd, crd.data(), crd.size() * sizeof(VisCoord), hipMemcpyHostToDevice, st));
+    IVX_HIP(hipMemcpyAsync(p->d_vis, vis.data(), vis.size() * sizeof(cpx), hipMemcpyHostToDevice, st));
+    IVX_HIP(hipMemcpyAsync(p->d_wgt, wgt.data(), wgt.size() * sizeof(real), hipMemcpyHostToDevice, st));
+    IVX_HIP(hipMemcpyAsync(p->d_perm, perm.data(), perm.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    if (!work.empty())
+        IVX_HIP(hipMemcpyAsync(p->d_work, work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
+    IVX_HIP(hipMemcpyAsync(p->d_tslot, tslot.data(), tslot.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    IVX_HIP(hipStreamSynchronize(st)); // host vectors die at return
+    return IVX_OK;
+}
+
+ivx_status check_plan(const ivx_plan *p) {
+    if (!p) return fail(IVX_EINVAL, "plan is NULL");
+    if (!p->has_data) return fail(IVX_ESTATE, "ivx_plan_set_data has not succeeded on this plan");
+    return IVX_OK;
+}
+
+ivx_status run_forward_half(ivx_plan *p, const real *sky, hipStream_t st) {
+    const Geom &g = p->g;
+    IVX_HIP(launch_image_rows(g, sky, p->d_beams, p->d_interp, p->d_fscale, p->d_dq, p->d_tw, p->d_R, st));
+    IVX_HIP(launch_col_fwd(g, p->d_R, p->d_tw, p->d_ext, st));
+    return IVX_OK;
+}
+
+ivx_status run_adjoint_half(ivx_plan *p, hipStream_t st) {
+    const Geom &g = p->g;
+    IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_hs, st));
+    IVX_HIP(launch_col_inv(g, p->d_hs, p->d_tw, p->d_R, st));
+    IVX_HIP(launch_row_inv(g, p->d_R, p->d_beams, p->d_fscale, p->d_dq, p->d_tw, p->d_gp, st));
+    return IVX_OK;
+}
+
+bool sd_active(const ivx_plan *p) { return p->d.lambda_s != 0.0 && p->d.sd_n > 0; }
+
+// Event pair around one stage when timing is on (start before the launch, stop after).
+hipEvent_t next_event(ivx_plan *p) {
+    if (p->ev_next == p->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p->ev_pool.push_back(e);
+    }
+    return p->ev_pool[p->ev_next++];
+}
+
+struct StageTimer {
+    ivx_plan *p;
+    hipStream_t st;
+    int stage;
+    hipEvent_t stop = nullptr;
+    StageTimer(ivx_plan *p_, hipStream_t st_, int stage_) : p(p_), st(st_), stage(stage_) {
+        if (!(p->timing_mask & (1u << stage))) return;
+        const size_t i0 = p->ev_next;
+        hipEvent_t start = next_event(p);
+        stop = next_event(p);
+        if (!start || !stop || hipEventRecord(start, st) != hipSuccess) {
+            stop = nullptr;
+            return;
+        }
+        p->ev_used.push_back({stage, (int)i0});
+    }
+    ~StageTimer() {
+        if (stop) (void)hipEventRecord(stop, st);
+    }
+};
+
+ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, hipStream_t st) {
+    const Geom &g = p->g;
+    if (p->timing_mask) p->timed_evals++;
+    {
+        StageTimer t(p, st, IVX_STAGE_IMAGE_ROWS);
+        IVX_HIP(launch_image_rows(g, sky, p->d_beams, p->d_interp, p->d_fscale, p->d_dq, p->d_tw, p->d_R, st));
+    }
+    {
+        StageTimer t(p, st, IVX_STAGE_COL_FWD);
+        IVX_HIP(launch_col_fwd(g, p->d_R, p->d_tw, p->d_ext, st));
+    }
+    {
+        StageTimer t(p, st, IVX_STAGE_GRID);
+        IVX_HIP(launch_grid(MODE_OBJ, g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
+                            p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, st));
+    }
+    {
+        StageTimer t(p, st, IVX_STAGE_FOLD);
+        IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_hs, st));
+    }
+    {
+        StageTimer t(p, st, IVX_STAGE_COL_INV);
+        IVX_HIP(launch_col_inv(g, p->d_hs, p->d_tw, p->d_R, st));
+    }
+    {
+        StageTimer t(p, st, IVX_STAGE_ROW_INV);
+        IVX_HIP(launch_row_inv(g, p->d_R, p->d_beams, p->d_fscale, p->d_dq, p->d_tw, p->d_gp, st));
+    }
+    const bool sd = sd_active(p);
+    if (sd) {
+        StageTimer t(p, st, IVX_STAGE_SD);
+        IVX_HIP(launch_sd_rows(g, sky, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_U, st));
+        IVX_HIP(launch_sd_cols(g, p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_sdmap,
+                               (real)(1.0 / (p->d.sd_sigma * p->d.sd_sigma)), p->d_E, p->d_kpart, st));
+    }
+    {
+        StageTimer t(p, st, IVX_STAGE_SKY);
+        IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r,
+                           sd ? (real)p->d.lambda_s : real(0), p->d_E, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride,
+                           p->d.sd_offset, grad, p->d_rpart, false, st));
+    }
+    {
+        StageTimer t(p, st, IVX_STAGE_FINAL);
+        IVX_HIP(launch_final(p->d_jpart, p->n_work, p->d_rpart, p->n_rpart, p->d_kpart, sd ? p->n_kpart : 0,
+                             p->d.lambda_r, sd ? p->d.lambda_s : 0.0, p->d_terms, st));
+    }
+    return IVX_OK;
+}
+
+} // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char *ivx_last_error(void) { return g_last_error.c_str(); }
+
+int ivx_version(void) { return IVX_VERSION; }
+
+int ivx_real_size(void) { return (int)sizeof(ivx_real); }
+
+ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out) {
+    g_last_error.clear();
+    if (!out) return fail(IVX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(IVX_EINVAL, "problem is NULL");
+    if (d->n_chan < 1 || d->n_point < 1) return fail(IVX_EINVAL, "n_chan and n_point must be >= 1");
+    if (d->n_sky < 4 || d->n_sky > 65536) return fail(IVX_EINVAL, "n_sky must be in [4, 65536]");
+    if (d->n_sub < 4 || (d->n_sub & 1) || d->n_sub > 1024) return fail(IVX_EINVAL, "n_sub must be even in [4, 1024]");
+    if (!(d->pixel_rad > 0.0) || !std::isfinite(d->pixel_rad)) return fail(IVX_EINVAL, "pixel_rad must be > 0");
+    if (!d->vis_offsets || !d->flux_scale) return fail(IVX_EINVAL, "vis_offsets and flux_scale are required");
+    if (!(d->lambda_r >= 0.0) || !(d->lambda_s >= 0.0) || !std::isfinite(d->lambda_r) || !std::isfinite(d->lambda_s))
+        return fail(IVX_EINVAL, "lambda_r and lambda_s must be finite and >= 0");
+    if (d->reserved != 0) return fail(IVX_EINVAL, "reserved must be 0");
+    const int64_t nb = (int64_t)d->n_point * d->n_chan;
+    if (nb > (1 << 24)) return fail(IVX_EINVAL, "too many (pointing, channel) blocks");
+    if (d->vis_offsets[0] != 0) return fail(IVX_EINVAL, "vis_offsets[0] must be 0");
+    for (int64_t i = 0; i < nb; ++i)
+        if (d->vis_offsets[i + 1] < d->vis_offsets[i]) return fail(IVX_EINVAL, "vis_offsets must be non-decreasing");
+    for (int c = 0; c < d->n_chan; ++c)
+        if (!std::isfinite(d->flux_scale[c])) return fail(IVX_EINVAL, "flux_scale must be finite");
+    if (d->sd_n < 0) return fail(IVX_EINVAL, "sd_n must be >= 0");
+    if (d->sd_n > 0) {
+        if (d->sd_stride < 1 || d->sd_offset < 0 || d->sd_offset + (int64_t)(d->sd_n - 1) * d->sd_stride >= d->n_sky)
+            return fail(IVX_EINVAL, "single-dish samples must lie inside the sky");
+        if (!(d->sd_fwhm_rad > 0.0) || !(d->sd_sigma > 0.0)) return fail(IVX_EINVAL, "sd_fwhm_rad and sd_sigma must be > 0");
+    }
+    ivx_plan *p = new (std::nothrow) ivx_plan();
+    if (!p) return fail(IVX_ENOMEM, "host allocation of the plan failed");
+    p->d = *d;
+    p->offsets.assign(d->vis_offsets, d->vis_offsets + nb + 1);
+    p->fscale.assign(d->flux_scale, d->flux_scale + d->n_chan);
+    p->d.vis_offsets = nullptr;
+    p->d.flux_scale = nullptr;
+    p->m_total = p->offsets.back();
+
+    Geom &g = p->g;
+    g.C = d->n_chan;
+    g.P = d->n_point;
+    g.N = d->n_sky;
+    g.nk = d->n_sub;
+    int nf = d->fine_size;
+    if (nf == 0) {
+        nf = 64;
+        while (nf < 2 * d->n_sub) nf *= 2;
+    }
+    if (!is_pow2(nf) || nf < 64 || nf > 2048 || nf * 4 < d->n_sub * 5) {
+        delete p;
+        return fail(IVX_EINVAL, "fine_size must be a power of two in [64, 2048] and >= 1.25 n_sub");
+    }
+    g.nf = nf;
+    g.logn = ilog2(nf);
+    g.rw = nf / 2 + 1;
+    const double sigma = (double)nf / d->n_sub;
+    int W = d->kernel_width;
+    if (W == 0) {
+        double eps = d->nufft_eps;
+        if (eps <= 0.0) eps = sizeof(real) == 4 ? 1e-7 : 1e-12;
+        W = (int)std::ceil(std::log(1.0 / eps) / (M_PI * std::sqrt(1.0 - 1.0 / sigma)));
+        W = std::max(4, std::min(16, W));
+    }
+    if (W < 4 || W > 16) {
+        delete p;
+        return fail(IVX_EINVAL, "kernel_width must be in [4, 16]");
+    }
+    g.W = W;
+    g.O = (W + 1) / 2;
+    // shape parameter scaled from the 2.30 W of two-fold oversampling
+    p->beta = 2.30 * W * (1.0 - 1.0 / (2.0 * sigma)) / 0.75;
+    g.beta = (real)p->beta;
+    g.r_stride = (int64_t)g.nk * g.rw;
+    g.hs_stride = (int64_t)g.nf * g.rw;
+    int T = d->tile;
+    if (T == 0) T = auto_tile(p);
+    if (!tile_fits(p, T, p->nwave)) {
+        delete p;
+        return fail(IVX_EINVAL, "tile must be >= kernel_width and fit the LDS");
+    }
+    p->tile_fixed = d->tile;
+    set_tile(p, T);
+    // deapodization 1 / phi_hat(2 pi p / nf) for p = a - n/2, a in [0, n)
+    std::vector<double> gx, gw;
+    gauss_legendre(std::max(64, 8 * W), gx, gw);
+    p->dq_host.resize(g.nk);
+    for (int a = 0; a < g.nk; ++a) {
+        const double kap = 2.0 * M_PI * (a - g.nk / 2) / nf;
+        p->dq_host[a] = (real)(1.0 / es_phihat(kap, W, p->beta, gx, gw));
+    }
+    p->tw_host.resize(nf);
+    for (int t = 0; t < nf; ++t) {
+        const double th = -2.0 * M_PI * t / nf;
+        p->tw_host[t] = cpx{(real)std::cos(th), (real)std::sin(th)};
+    }
+    if (d->sd_n > 0) {
+        const double sig = d->sd_fwhm_rad / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+        p->sd_rb = (int)std::ceil(4.0 * sig / d->pixel_rad);
+        std::vector<double> taps(2 * p->sd_rb + 1);
+        double sum = 0.0;
+        for (int t = -p->sd_rb; t <= p->sd_rb; ++t) {
+            const double v = std::exp(-(t * d->pixel_rad) * (t * d->pixel_rad) / (2.0 * sig * sig));
+            taps[t + p->sd_rb] = v;
+            sum += v;
+        }
+        p->gB_host.resize(taps.size());
+        for (size_t i = 0; i < taps.size(); ++i) p->gB_host[i] = (real)(taps[i] / sum);
+    }
+    *out = p;
+    return IVX_OK;
+}
+
+ivx_status ivx_set_timing(ivx_plan *p, uint32_t stage_mask) {
+    if (!p) return fail(IVX_EINVAL, "plan is NULL");
+    p->timing_mask = stage_mask & ((1u << IVX_NSTAGE) - 1u);
+    return IVX_OK;
+}
+
+ivx_status ivx_stage_times(ivx_plan *p, double *ms, int64_t *n_eval) {
+    if (!p || !ms) return fail(IVX_EINVAL, "plan and ms must be non-NULL");
+    for (int i = 0; i < IVX_NSTAGE; ++i) ms[i] = 0.0;
+    for (const auto &u : p->ev_used) {
+        hipEvent_t a = p->ev_pool[u.second], b = p->ev_pool[u.second + 1];
+        IVX_HIP(hipEventSynchronize(b));
+        float t = 0.f;
+        IVX_HIP(hipEventElapsedTime(&t, a, b));
+        ms[u.first] += t;
+    }
+    if (n_eval) *n_eval = p->timed_evals;
+    p->ev_used.clear();
+    p->ev_next = 0;
+    p->timed_evals = 0;
+    return IVX_OK;
+}
+
+ivx_status ivx_plan_destroy(ivx_plan *plan) {
+    if (!plan) return IVX_OK;
+    for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
+    plan->ev_pool.clear();
+    free_all(plan);
+    delete plan;
+    return IVX_OK;
+}
+
+ivx_status ivx_plan_info(const ivx_plan *p, int64_t *info) {
+    if (!p || !info) return fail(IVX_EINVAL, "plan and info must be non-NULL");
+    const Geom &g = p->g;
+    const int64_t v[16] = {g.nf, g.W, g.T, p->n_work, p->m_live, p->n_slots, (int64_t)p->dev_bytes,
+                           (int64_t)g.C * g.P, g.eh, g.ew, 0, g.win, 0, 0, 0, 0};
+    std::memcpy(info, v, sizeof(v));
+    return IVX_OK;
+}
+
+ivx_status ivx_plan_set_data(ivx_plan *p, const ivx_real *uv, const ivx_real *vis, const ivx_real *weight,
+                             const uint8_t *flags, const ivx_real *beams, const ivx_real *interp,
+                             const ivx_real *sd_map, void *stream) {
+    g_last_error.clear();
+    if (!p) return fail(IVX_EINVAL, "plan is NULL");
+    const int64_t M = p->m_total;
+    if (M > 0 && (!uv || !vis || !weight)) return fail(IVX_EINVAL, "uv, vis and weight are required");
+    if (!beams || !interp) return fail(IVX_EINVAL, "beams and interp are required");
+    if (sd_active(p) && !sd_map) return fail(IVX_EINVAL, "sd_map is required when lambda_s > 0 and sd_n > 0");
+    hipStream_t st = (hipStream_t)stream;
+    IVX_HIP(hipStreamSynchronize(st));
+    const Geom &g = p->g;
+    const int n_items = g.C * g.P;
+    const int64_t nk2 = (int64_t)g.nk * g.nk;
+    // ---- host copies of the caller's arrays
+    std::vector<real> h_uv, h_vis, h_w, h_beams(g.P * nk2), h_interp(g.P * nk2 * 2);
+    std::vector<uint8_t> h_flags;
+    try {
+        h_uv.resize(2 * M);
+        h_vis.resize(2 * M);
+        h_w.resize(M);
+        if (flags) h_flags.resize(M);
+    } catch (const std::bad_alloc &) {
+        return fail(IVX_ENOMEM, "host staging allocation failed");
+    }
+    if (M > 0) {
+        IVX_HIP(hipMemcpy(h_uv.data(), uv, 2 * M * sizeof(real), hipMemcpyDefault));
+        IVX_HIP(hipMemcpy(h_vis.data(), vis, 2 * M * sizeof(real), hipMemcpyDefault));
+        IVX_HIP(hipMemcpy(h_w.data(), weight, M * sizeof(real), hipMemcpyDefault));
+        if (flags) IVX_HIP(hipMemcpy(h_flags.data(), flags, M, hipMemcpyDefault));
+    }
+    IVX_HIP(hipMemcpy(h_beams.data(), beams, h_beams.size() * sizeof(real), hipMemcpyDefault));
+    IVX_HIP(hipMemcpy(h_interp.data(), interp, h_interp.size() * sizeof(real), hipMemcpyDefault));
+    std::vector<real> h_sd;
+    if (sd_active(p)) {
+        h_sd.resize((size_t)g.C * p->d.sd_n * p->d.sd_n);
+        IVX_HIP(hipMemcpy(h_sd.data(), sd_map, h_sd.size() * sizeof(real), hipMemcpyDefault));
+        for (real v : h_sd)
+            if (!std::isfinite((double)v)) return fail(IVX_ENONFINITE, "sd_map holds a non-finite value");
+    }
+    for (size_t i = 0; i < h_beams.size(); ++i)
+        if (!std::isfinite((double)h_beams[i])) return fail(IVX_ENONFINITE, "beams hold a non-finite value");
+    // ---- live visibilities: finite check, fine-grid coordinates, Hermitian fold
+    std::vector<HostVis> hv;
+    std::vector<int64_t> block_live(n_items + 1, 0);
+    const double delta = p->d.pixel_rad;
+    const double nf = g.nf, hw = 0.5 * g.W;
+    try {
+        hv.reserve(M);
+    } catch (const std::bad_alloc &) {
+        return fail(IVX_ENOMEM, "host staging allocation failed");
+    }
+    for (int it = 0; it < n_items; ++it) {
+        for (int64_t j = p->offsets[it]; j < p->offsets[it + 1]; ++j) {
+            if (flags && h_flags[j]) continue;
+            const double u = h_uv[2 * j], v = h_uv[2 * j + 1];
+            const double yr = h_vis[2 * j], yi = h_vis[2 * j + 1], w = h_w[j];
+            if (!std::isfinite(u) || !std::isfinite(v) || !std::isfinite(yr) || !std::isfinite(yi) ||
+                !std::isfinite(w))
+                return fail(IVX_ENONFINITE, "visibility " + std::to_string(j) + " is not finite");
+            if (w < 0.0) return fail(IVX_EINVAL, "negative weight at visibility " + std::to_string(j));
+            // fine-grid coordinate: the DFT phase only depends on frac(u delta)
+            double gxv = (u * delta - std::floor(u * delta)) * nf;
+            double gyv = (v * delta - std::floor(v * delta)) * nf;
+            if (gxv >= nf) gxv -= nf;
+            if (gyv >= nf) gyv -= nf;
+            bool fold = gxv > 0.5 * nf;
+            if (fold) {
+                gxv = nf - gxv;
+                gyv = nf - gyv;
+                if (gyv >= nf) gyv -= nf;
+            }
+            const double sx = gxv - hw, sy = gyv - hw;
+            const double flx = std::floor(sx), fly = std::floor(sy);
+            HostVis h;
+            h.ec0 = (int32_t)flx + 1 + g.O;
+            h.er0 = (int32_t)fly + 1 + g.O;
+            h.fx = sx - flx;
+            h.fy = sy - fly;
+            h.src = fold ? ~j : j;
+            h.yr = (real)yr;
+            h.yi = fold ? (real)(-yi) : (real)yi;
+            h.w = (real)w;
+            hv.push_back(h);
+        }
+        block_live[it + 1] = (int64_t)hv.size();
+    }
+    free_all(p);
+    p->hv.swap(hv);
+    p->block_live.swap(block_live);
+    p->m_live = (int64_t)p->hv.size();
+    ivx_status s;
+    // ---- constant tables and images
+    if ((s = dalloc(p, &p->d_dq, g.nk)) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_fscale, g.C)) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_tw, g.nf)) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_beams, h_beams.size())) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_interp, h_interp.size())) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_R, (size_t)n_items * g.r_stride)) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_hs, (size_t)n_items * g.hs_stride)) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_gp, (size_t)n_items * nk2)) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_terms, 4)) != IVX_OK) goto fail_free;
+    p->n_rpart = sky_blocks(g);
+    if ((s = dalloc(p, &p->d_rpart, p->n_rpart)) != IVX_OK) goto fail_free;
+    {
+        std::vector<real> fs(g.C);
+        for (int c = 0; c < g.C; ++c) fs[c] = (real)p->fscale[c];
+        hipError_t e;
+        if ((e = hipMemcpy(p->d_dq, p->dq_host.data(), g.nk * sizeof(real), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p->d_fscale, fs.data(), g.C * sizeof(real), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p->d_tw, p->tw_host.data(), g.nf * sizeof(cpx), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p->d_beams, h_beams.data(), h_beams.size() * sizeof(real), hipMemcpyHostToDevice)) !=
+                hipSuccess ||
+            (e = hipMemcpy(p->d_interp, h_interp.data(), h_interp.size() * sizeof(real), hipMemcpyHostToDevice)) !=
+                hipSuccess) {
+            s = hip_fail(e, "hipMemcpy (set_data tables)");
+            goto fail_free;
+        }
+    }
+    // ---- transpose of the bilinear reprojection, pixel-major (fixed summation order)
+    {
+        const int N = g.N;
+        std::vector<int32_t> cptr((size_t)N * N + 1, 0);
+        struct Tap { int64_t pix; CsrEnt e; };
+        std::vector<Tap> taps;
+        taps.reserve((size_t)g.P * nk2 * 4);
+        const int64_t koff = (int64_t)g.C * nk2;
+        if (koff * g.P > INT32_MAX) { s = fail(IVX_EINVAL, "sub-image index exceeds int32"); goto fail_free; }
+        for (int k = 0; k < g.P; ++k) {
+            for (int64_t ab = 0; ab < nk2; ++ab) {
+                const real sy = h_interp[((int64_t)k * nk2 + ab) * 2], sx = h_interp[((int64_t)k * nk2 + ab) * 2 + 1];
+                if (!std::isfinite((double)sy) || !std::isfinite((double)sx)) continue;
+                if (!(sy > real(-1) && sy < real(N) && sx > real(-1) && sx < real(N))) continue;
+                const real fi = std::floor(sy), fj = std::floor(sx);
+                const int i0 = (int)fi, j0 = (int)fj;
+                const real fy = sy - fi, fx = sx - fj;
+                const real wts[4] = {(real(1) - fy) * (real(1) - fx), (real(1) - fy) * fx, fy * (real(1) - fx), fy * fx};
+                const int di[4] = {0, 0, 1, 1}, dj[4] = {0, 1, 0, 1};
+                for (int t = 0; t < 4; ++t) {
+                    const int ii = i0 + di[t], jj = j0 + dj[t];
+                    if (ii < 0 || ii >= N || jj < 0 || jj >= N || wts[t] == real(0)) continue;
+                    taps.push_back(Tap{(int64_t)ii * N + jj, CsrEnt{(int32_t)(k * koff + ab), wts[t]}});
+                }
+            }
+        }
+        for (const Tap &t : taps) cptr[t.pix + 1]++;
+        for (int64_t i = 0; i < (int64_t)N * N; ++i) cptr[i + 1] += cptr[i];
+        if ((int64_t)taps.size() > INT32_MAX) { s = fail(IVX_EINVAL, "too many reprojection taps"); goto fail_free; }
+        std::vector<CsrEnt> cent(taps.size() > 0 ? taps.size() : 1);
+        std::vector<int32_t> fillp(cptr.begin(), cptr.end() - 1);
+        for (const Tap &t : taps) cent[fillp[t.pix]++] = t.e; // stable: (k, a, b, tap) order
+        if ((s = dalloc(p, &p->d_cptr, cptr.size())) != IVX_OK) goto fail_free;
+        if ((s = dalloc(p, &p->d_cent, cent.size())) != IVX_OK) goto fail_free;
+        hipError_t e;
+        if ((e = hipMemcpy(p->d_cptr, cptr.data(), cptr.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p->d_cent, cent.data(), cent.size() * sizeof(CsrEnt), hipMemcpyHostToDevice)) != hipSuccess) {
+            s = hip_fail(e, "hipMemcpy (reprojection transpose)");
+            goto fail_free;
+        }
+    }
+    // ---- single dish
+    if (sd_active(p)) {
+        const int sdn = p->d.sd_n;
+        p->n_kpart = (int)(((int64_t)g.C * sdn * sdn + 255) / 256);
+        if ((s = dalloc(p, &p->d_sdmap, h_sd.size())) != IVX_OK) goto fail_free;
+        if ((s = dalloc(p, &p->d_gB, p->gB_host.size())) != IVX_OK) goto fail_free;
+        if ((s = dalloc(p, &p->d_U, (size_t)g.C * g.N * sdn)) != IVX_OK) goto fail_free;
+        if ((s = dalloc(p, &p->d_E, (size_t)g.C * sdn * sdn)) != IVX_OK) goto fail_free;
+        if ((s = dalloc(p, &p->d_kpart, p->n_kpart)) != IVX_OK) goto fail_free;
+        hipError_t e;
+        if ((e = hipMemcpy(p->d_sdmap, h_sd.data(), h_sd.size() * sizeof(real), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p->d_gB, p->gB_host.data(), p->gB_host.size() * sizeof(real), hipMemcpyHostToDevice)) !=
+                hipSuccess) {
+            s = hip_fail(e, "hipMemcpy (single dish)");
+            goto fail_free;
+        }
+    }
+    if ((s = build_bins(p, st)) != IVX_OK) goto fail_free;
+    p->has_data = true;
+    return IVX_OK;
+fail_free:
+    {
+        const std::string msg = g_last_error;
+        free_all(p);
+        g_last_error = msg;
+    }
+    return s;
+}
+
+ivx_status ivx_objective_grad(ivx_plan *p, const ivx_real *sky, ivx_real *grad, double *terms, void *stream) {
+    ivx_status s = check_plan(p);
+    if (s != IVX_OK) return s;
+    if (!sky || !grad) return fail(IVX_EINVAL, "sky and grad are required");
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = eval_objective(p, sky, grad, st)) != IVX_OK) return s;
+    if (terms) {
+        IVX_HIP(hipMemcpyAsync(terms, p->d_terms, 4 * sizeof(double), hipMemcpyDefault, st));
+        hipPointerAttribute_t attr;
+        bool device = false;
+        if (hipPointerGetAttributes(&attr, terms) == hipSuccess)
+            device = attr.type == hipMemoryTypeDevice;
+        else
+            (void)hipGetLastError();
+        if (!device) IVX_HIP(hipStreamSynchronize(st));
+    }
+    return IVX_OK;
+}
+
+ivx_status ivx_forward(ivx_plan *p, const ivx_real *sky, ivx_real *model_vis, void *stream) {
+    ivx_status s = check_plan(p);
+    if (s != IVX_OK) return s;
+    if (!sky || (!model_vis && p->m_total > 0)) return fail(IVX_EINVAL, "sky and model_vis are required");
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = run_forward_half(p, sky, st)) != IVX_OK) return s;
+    IVX_HIP(launch_zero(model_vis, p->m_total * 2 * (int64_t)sizeof(real), st));
+    IVX_HIP(launch_grid(MODE_FWD, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
+                        p->d_slots, p->d_jpart, nullptr, reinterpret_cast<cpx *>(model_vis), p->nwave, st));
+    return IVX_OK;
+}
+
+ivx_status ivx_adjoint(ivx_plan *p, const ivx_real *vis, ivx_real *image, void *stream) {
+    ivx_status s = check_plan(p);
+    if (s != IVX_OK) return s;
+    if (!image || (!vis && p->m_total > 0)) return fail(IVX_EINVAL, "vis and image are required");
+    hipStream_t st = (hipStream_t)stream;
+    IVX_HIP(launch_grid(MODE_ADJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
+                        p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave, st));
+    if ((s = run_adjoint_half(p, st)) != IVX_OK) return s;
+    IVX_HIP(launch_sky(p->g, image, p->d_gp, p->d_cptr, p->d_cent, real(0), real(0), nullptr, nullptr, 0, 0, 1, 0,
+                       image, p->d_rpart, true, st));
+    return IVX_OK;
+}
+
+ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, void *stream) {
+    ivx_status s = check_plan(p);
+    if (s != IVX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int cand[] = {16, 24, 32, 40, 48, 64};
+    std::vector<int> tiles;
+    for (int T : cand)
+        if (tile_fits(p, T, p->nwave)) tiles.push_back(T);
+    if (tiles.empty()) return fail(IVX_EINVAL, "no tile candidate fits");
+    // time the gridding stage (the only stage that depends on the tile) on a zero sky
+    real *sky = nullptr;
+    const int64_t nsky = (int64_t)p->g.C * p->g.N * p->g.N;
+    IVX_HIP(hipMalloc(&sky, nsky * sizeof(real)));
+    IVX_HIP(hipMemsetAsync(sky, 0, nsky * sizeof(real), st));
+    hipEvent_t e0, e1;
+    IVX_HIP(hipEventCreate(&e0));
+    IVX_HIP(hipEventCreate(&e1));
+    const auto t_start = std::chrono::steady_clock::now();
+    double best_ms = 1e300;
+    int best_T = p->g.T;
+    for (int T : tiles) {
+        set_tile(p, T);
+        if ((s = build_bins(p, st)) != IVX_OK) break;
+        if ((s = run_forward_half(p, sky, st)) != IVX_OK) break;
+        float ms = 0.f, tot = 0.f;
+        const int reps = 5;
+        for (int r = 0; r < reps + 1; ++r) {
+            IVX_HIP(hipEventRecord(e0, st));
+            IVX_HIP(launch_grid(MODE_OBJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm,
+                                p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, st));
+            IVX_HIP(launch_fold(p->g, p->d_tslot, p->d_slots, p->d_hs, st));
+            IVX_HIP(hipEventRecord(e1, st));
+            IVX_HIP(hipEventSynchronize(e1));
+            IVX_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0) tot += ms;
+        }
+        const double avg = tot / reps;
+        if (avg < best_ms) {
+            best_ms = avg;
+            best_T = T;
+        }
+        const double spent = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        if (spent > budget_ms) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(sky);
+    if (s != IVX_OK) return s;
+    set_tile(p, best_T);
+    if ((s = build_bins(p, st)) != IVX_OK) return s;
+    if (chosen_tile) *chosen_tile = best_T;
+    return IVX_OK;
+}
+
+} // extern "C"

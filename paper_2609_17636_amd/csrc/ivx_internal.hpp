@@ -1,0 +1,103 @@
+// Internal types shared by the plan code (ivx_api.hip) and the kernels (ivx_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ivx.h"
+
+namespace ivx {
+
+typedef ivx_real real;
+
+struct alignas(2 * sizeof(real)) cpx {
+    real re, im;
+};
+
+// Sorted-visibility coordinates.  Each visibility stores the fine-grid cell where its
+// w x w kernel footprint starts, relative to its tile origin, and the fractional offset
+// of the footprint (so every tap distance is exact to the precision of real).
+//   float build : 8.24 fixed point per axis, (cell << 24) | round(frac * 2^24)
+//   double build: separate integer cell and FP64 fraction
+#ifdef IVX_REAL_DOUBLE
+struct VisCoord {
+    uint32_t ix, iy;
+    double fx, fy;
+};
+#else
+struct VisCoord {
+    uint32_t xq, yq;
+};
+#endif
+
+// One unit of gridding work: up to `count` visibilities of one fine-grid tile of one
+// (pointing, channel) block, accumulated into its own window-sized slot.
+struct WorkItem {
+    int32_t item;   // block index b = k * n_chan + c
+    int32_t ty, tx; // tile coordinates in the extended grid
+    int32_t count;  // number of visibilities
+    int64_t begin;  // first sorted visibility
+    int32_t slot;   // accumulator slot index
+    int32_t pad;
+};
+
+// Entry of the sky-pixel -> sub-pixel transpose of the bilinear reprojection.
+struct CsrEnt {
+    int32_t off; // k * n_chan * n_sub^2 + a * n_sub + b (add c * n_sub^2 for channel c)
+    real w;      // bilinear weight
+};
+
+// Plan geometry passed by value to kernels.
+struct Geom {
+    int C, P, N;          // channels, pointings, sky edge
+    int nk;               // sub-image edge (even)
+    int nf, logn;         // fine grid edge (power of two) and log2
+    int rw;               // nf/2 + 1 stored half-plane columns
+    int W, O;             // kernel width, extended-grid offset
+    real beta;            // ES kernel shape
+    int T, win, ldw;      // tile edge, window edge T+W-1, LDS window row stride
+    int eh, ew;           // extended grid rows / columns
+    int nty, ntx;         // tiles per block along rows / columns
+    int64_t r_stride;     // nk * rw   (row-FFT buffers per block)
+    int64_t ext_stride;   // eh * ew   (extended grid per block)
+    int64_t hs_stride;    // nf * rw   (Hermitian half-plane per block)
+    int64_t win_stride;   // win * win (slot size)
+};
+
+enum GridMode { MODE_OBJ = 0, MODE_FWD = 1, MODE_ADJ = 2 };
+
+// ---------------------------------------------------------------- kernel launchers
+// Each returns hipSuccess or the launch error.  All run on `st`.
+
+hipError_t launch_image_rows(const Geom &g, const real *sky, const real *beams,
+                             const real *interp, const real *fscale, const real *dq,
+                             const cpx *tw, cpx *R, hipStream_t st);
+hipError_t launch_col_fwd(const Geom &g, const cpx *R, const cpx *tw, cpx *ext, hipStream_t st);
+hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work,
+                       const VisCoord *crd, const cpx *vis, const real *wgt,
+                       const int64_t *perm, const cpx *ext, cpx *slots, double *jpart,
+                       const cpx *caller_in, cpx *caller_out, int nwave, hipStream_t st);
+hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *hs,
+                       hipStream_t st);
+hipError_t launch_col_inv(const Geom &g, const cpx *hs, const cpx *tw, cpx *R, hipStream_t st);
+hipError_t launch_row_inv(const Geom &g, const cpx *R, const real *beams, const real *fscale,
+                          const real *dq, const cpx *tw, real *gp, hipStream_t st);
+hipError_t launch_sd_rows(const Geom &g, const real *sky, const real *gB, int rb, int sd_n,
+                          int stride, int offset, real *U, hipStream_t st);
+hipError_t launch_sd_cols(const Geom &g, const real *U, const real *gB, int rb, int sd_n,
+                          int stride, int offset, const real *sdmap, real inv_var, real *E,
+                          double *kpart, hipStream_t st);
+hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int32_t *cptr,
+                      const CsrEnt *cent, real lambda_r, real lambda_s, const real *E,
+                      const real *gB, int rb, int sd_n, int stride, int offset, real *grad,
+                      double *rpart, bool adjoint_only, hipStream_t st);
+int sky_blocks(const Geom &g);
+hipError_t launch_final(const double *jpart, int nj, const double *rpart, int nr,
+                        const double *kpart, int nkp, double lambda_r, double lambda_s,
+                        double *terms, hipStream_t st);
+hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st);
+
+// Maximum dynamic LDS for the gridding kernel (bytes); used to pick tiles.
+size_t grid_lds_bytes(const Geom &g, int nwave);
+
+} // namespace ivx

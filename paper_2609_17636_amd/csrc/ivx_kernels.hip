@@ -1,0 +1,880 @@
+// gfx950 kernels of one Classic3D objective/gradient evaluation.
+//
+// Forward direction (Sect. 2.1), per (pointing k, channel c) block:
+//   k_image_rows  bilinear SIN reprojection of the sky (Eq. sin_projection) x beam x flux
+//                 scale x deapodization, zero-padded to the fine grid, and the row FFT of
+//                 two real rows packed in one complex transform (half spectrum kept);
+//   k_col_fwd     column FFT of the n_sub non-zero rows, written to an extended grid that
+//                 carries the periodic wrap in rows and the Hermitian mirror in columns,
+//                 so a footprint never needs a modulo;
+//   k_grid        per fine-grid tile: stage the grid window in LDS, interpolate every
+//                 visibility (degridding), form the residual and its weighted square
+//                 (Sect. 2.2, J_k), and spread w * r back into per-wave LDS accumulators
+//                 (no global atomics); the window is written to a private slot.
+// Adjoint direction (gradient, Sect. 3.4):
+//   k_fold        sum the slots covering each cell and symmetrise H -> (H + conj H(-t))/2,
+//                 which makes the real part of the adjoint a half-spectrum inverse FFT;
+//   k_col_inv     inverse column FFT, keeping the n_sub rows of the sub-image;
+//   k_row_inv     inverse row FFT of two rows at once, crop, deapodization x beam x flux;
+//   k_sky         transpose of the bilinear reprojection (gather over a pixel-major CSR,
+//                 fixed order), plus the Laplacian regulariser (Eq. 3) and the single-dish
+//                 gradient (Sect. 2.4); k_sd_rows / k_sd_cols give the single-dish model.
+// The NUFFT is the exponential-of-semicircle scheme of Barnett et al. (2019): kernel
+// phi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1)), deapodization by its Fourier transform.
+#include "ivx_internal.hpp"
+
+#include <math.h>
+
+namespace ivx {
+
+constexpr int NT = 256; // threads per block of every kernel
+
+__device__ __forceinline__ cpx cmul(cpx a, cpx b) {
+    return cpx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cpx cadd(cpx a, cpx b) { return cpx{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cpx csub(cpx a, cpx b) { return cpx{a.re - b.re, a.im - b.im}; }
+
+// ------------------------------------------------------------------------------ FFT
+// In-LDS Stockham autosort FFT (mixed radix 2 then 4) of CB interleaved transforms of
+// length N = 2^LOGN: element i of transform c is buf[i * CB + c].  Each stage reads all
+// of a thread's butterfly inputs into registers, synchronises, then writes the outputs,
+// so the transform runs in place.  Twiddles come from a table tw[t] = exp(-2 pi i t / N)
+// (conjugated for the inverse); no scaling is applied in either direction.
+template <int LOGN, int CB, bool INV>
+__device__ __forceinline__ void fft_lds(cpx *buf, const cpx *__restrict__ tw) {
+    constexpr int N = 1 << LOGN;
+    const int tid = threadIdx.x;
+    int Ns = 1;
+    if constexpr (LOGN & 1) {
+        constexpr int TOT = CB * (N / 2);
+        constexpr int BPT = (TOT + NT - 1) / NT;
+        cpx v0[BPT], v1[BPT];
+#pragma unroll
+        for (int t = 0; t < BPT; ++t) {
+            const int u = tid + t * NT;
+            if (u < TOT) {
+                const int c = u % CB, jj = u / CB;
+                v0[t] = buf[jj * CB + c];
+                v1[t] = buf[(jj + N / 2) * CB + c];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < BPT; ++t) {
+            const int u = tid + t * NT;
+            if (u < TOT) {
+                const int c = u % CB, jj = u / CB;
+                buf[(2 * jj) * CB + c] = cadd(v0[t], v1[t]);
+                buf[(2 * jj + 1) * CB + c] = csub(v0[t], v1[t]);
+            }
+        }
+        __syncthreads();
+        Ns = 2;
+    }
+#pragma unroll
+    for (int s = 0; s < LOGN / 2; ++s) {
+        constexpr int TOT = CB * (N / 4);
+        constexpr int BPT = (TOT + NT - 1) / NT;
+        cpx v[BPT][4];
+        const int st = N / (4 * Ns);
+#pragma unroll
+        for (int t = 0; t < BPT; ++t) {
+            const int u = tid + t * NT;
+            if (u < TOT) {
+                const int c = u % CB, jj = u / CB;
+                const int k = jj & (Ns - 1);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    cpx x = buf[(jj + r * (N / 4)) * CB + c];
+                    if (r > 0) {
+                        cpx w = tw[k * r * st];
+                        if (INV) w.im = -w.im;
+                        x = cmul(x, w);
+                    }
+                    v[t][r] = x;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < BPT; ++t) {
+            const int u = tid + t * NT;
+            if (u < TOT) {
+                const int c = u % CB, jj = u / CB;
+                const int k = jj & (Ns - 1);
+                const cpx a0 = v[t][0], a1 = v[t][1], a2 = v[t][2], a3 = v[t][3];
+                const cpx s02 = cadd(a0, a2), d02 = csub(a0, a2);
+                const cpx s13 = cadd(a1, a3), d13 = csub(a1, a3);
+                // forward: y1 = d02 - i d13, y3 = d02 + i d13; inverse swaps the signs
+                const cpx id13 = INV ? cpx{-d13.im, d13.re} : cpx{d13.im, -d13.re};
+                const int o = ((jj - k) << 2) + k;
+                buf[o * CB + c] = cadd(s02, s13);
+                buf[(o + Ns) * CB + c] = cadd(d02, id13);
+                buf[(o + 2 * Ns) * CB + c] = csub(s02, s13);
+                buf[(o + 3 * Ns) * CB + c] = csub(d02, id13);
+            }
+        }
+        __syncthreads();
+        Ns *= 4;
+    }
+}
+
+template <int LOGN> constexpr int col_batch() {
+    constexpr int b = 65536 / ((1 << LOGN) * (int)sizeof(cpx));
+    return b > 16 ? 16 : (b < 1 ? 1 : b);
+}
+
+// --------------------------------------------------------------------- reprojection
+// Bilinear sample at (row sy, col sx); pixel (i, j) sits at (i, j); outside pixels are 0.
+__device__ __forceinline__ real bilinear(const real *__restrict__ sky, int N, real sy, real sx) {
+    if (!(sy > real(-1) && sy < real(N) && sx > real(-1) && sx < real(N))) return real(0);
+    const real fi = floor(sy), fj = floor(sx);
+    const int i0 = (int)fi, j0 = (int)fj;
+    const real fy = sy - fi, fx = sx - fj;
+    const bool r0 = i0 >= 0, r1 = i0 + 1 < N, c0 = j0 >= 0, c1 = j0 + 1 < N;
+    const real *p = sky + (int64_t)i0 * N + j0;
+    const real x00 = (r0 && c0) ? p[0] : real(0);
+    const real x01 = (r0 && c1) ? p[1] : real(0);
+    const real x10 = (r1 && c0) ? p[N] : real(0);
+    const real x11 = (r1 && c1) ? p[N + 1] : real(0);
+    return (real(1) - fy) * ((real(1) - fx) * x00 + fx * x01) + fy * ((real(1) - fx) * x10 + fx * x11);
+}
+
+// --------------------------------------------------------------- forward row pass
+template <int LOGN>
+__global__ __launch_bounds__(NT) void k_image_rows(Geom g, const real *__restrict__ sky,
+                                                   const real *__restrict__ beams,
+                                                   const real *__restrict__ interp,
+                                                   const real *__restrict__ fscale,
+                                                   const real *__restrict__ dq,
+                                                   const cpx *__restrict__ tw, cpx *__restrict__ R) {
+    constexpr int N = 1 << LOGN;
+    __shared__ cpx buf[N];
+    const int tid = threadIdx.x;
+    const int item = blockIdx.y;
+    const int k = item / g.C, c = item - (item / g.C) * g.C;
+    const int a0 = 2 * blockIdx.x;
+    const int nk = g.nk;
+    const real *x = sky + (int64_t)c * g.N * g.N;
+    const real *A = beams + (int64_t)k * nk * nk;
+    const real *G = interp + (int64_t)k * nk * nk * 2;
+    const real s = fscale[c];
+    for (int i = tid; i < N; i += NT) buf[i] = cpx{0, 0};
+    __syncthreads();
+    const real q0 = s * dq[a0], q1 = s * dq[a0 + 1];
+    for (int b = tid; b < nk; b += NT) {
+        const int64_t e0 = (int64_t)a0 * nk + b, e1 = e0 + nk;
+        const real f0 = q0 * dq[b] * A[e0] * bilinear(x, g.N, G[2 * e0], G[2 * e0 + 1]);
+        const real f1 = q1 * dq[b] * A[e1] * bilinear(x, g.N, G[2 * e1], G[2 * e1 + 1]);
+        buf[(b - nk / 2) & (N - 1)] = cpx{f0, f1};
+    }
+    __syncthreads();
+    fft_lds<LOGN, 1, false>(buf, tw);
+    cpx *R0 = R + (int64_t)item * g.r_stride + (int64_t)a0 * g.rw;
+    cpx *R1 = R0 + g.rw;
+    for (int kk = tid; kk <= N / 2; kk += NT) {
+        const cpx z = buf[kk], zm = buf[(N - kk) & (N - 1)];
+        // X = (Z + conj Zm)/2 (row a0), Y = (Z - conj Zm)/(2i) (row a0+1)
+        R0[kk] = cpx{real(0.5) * (z.re + zm.re), real(0.5) * (z.im - zm.im)};
+        R1[kk] = cpx{real(0.5) * (z.im + zm.im), real(0.5) * (zm.re - z.re)};
+    }
+}
+
+// -------------------------------------------------------------- forward column pass
+template <int LOGN>
+__global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ R,
+                                                const cpx *__restrict__ tw, cpx *__restrict__ ext) {
+    constexpr int N = 1 << LOGN;
+    constexpr int CB = col_batch<LOGN>();
+    constexpr int MAXE = 8 * CB;
+    __shared__ cpx buf[CB * N];
+    __shared__ int ent_col[MAXE];
+    __shared__ int ent_src[MAXE];
+    __shared__ int n_ent;
+    const int tid = threadIdx.x;
+    const int item = blockIdx.y;
+    const int c0 = blockIdx.x * CB;
+    const int nk = g.nk;
+    for (int i = tid; i < CB * N; i += NT) buf[i] = cpx{0, 0};
+    if (tid == 0) {
+        // extended columns fed by this block's source columns: direct copies at
+        // src + O + m N, Hermitian mirrors (conjugate, row-reversed) at N - src + O + m N
+        int n = 0;
+        for (int cc = 0; cc < CB; ++cc) {
+            const int src = c0 + cc;
+            if (src >= g.rw) break;
+            for (int m = -2; m <= 2; ++m) {
+                const int ec = src + g.O + m * N;
+                if (ec >= 0 && ec < g.ew && n < MAXE) { ent_col[n] = ec; ent_src[n] = cc; ++n; }
+            }
+            if (src != 0 && src != N / 2) {
+                for (int m = -2; m <= 2; ++m) {
+                    const int ec = N - src + g.O + m * N;
+                    if (ec >= 0 && ec < g.ew && n < MAXE) { ent_col[n] = ec; ent_src[n] = cc | 0x10000; ++n; }
+                }
+            }
+        }
+        n_ent = n;
+    }
+    __syncthreads();
+    const cpx *Ri = R + (int64_t)item * g.r_stride;
+    for (int e = tid; e < nk * CB; e += NT) {
+        const int a = e / CB, cc = e - (e / CB) * CB;
+        if (c0 + cc < g.rw) buf[((a - nk / 2) & (N - 1)) * CB + cc] = Ri[(int64_t)a * g.rw + c0 + cc];
+    }
+    __syncthreads();
+    fft_lds<LOGN, CB, false>(buf, tw);
+    cpx *E = ext + (int64_t)item * g.ext_stride;
+    const int ne = n_ent;
+    for (int e = tid; e < ne * g.eh; e += NT) {
+        const int er = e / ne, en = e - (e / ne) * ne;
+        const int src = ent_src[en];
+        const int cc = src & 0xFFFF;
+        const int t1 = (er - g.O) & (N - 1);
+        cpx v;
+        if (src & 0x10000) {
+            v = buf[((N - t1) & (N - 1)) * CB + cc];
+            v.im = -v.im;
+        } else {
+            v = buf[t1 * CB + cc];
+        }
+        E[(int64_t)er * g.ew + ent_col[en]] = v;
+    }
+}
+
+// ------------------------------------------------------------------- gridding kernel
+__device__ __forceinline__ real es_kernel(real z, real inv_half_w, real beta) {
+    const real t = z * inv_half_w;
+    const real q = real(1) - t * t;
+    return exp(beta * (sqrt(q > real(0) ? q : real(0)) - real(1)));
+}
+
+__device__ __forceinline__ void decode(const VisCoord &v, int &ix, int &iy, real &fx, real &fy) {
+#ifdef IVX_REAL_DOUBLE
+    ix = (int)v.ix;
+    iy = (int)v.iy;
+    fx = v.fx;
+    fy = v.fy;
+#else
+    ix = (int)(v.xq >> 24);
+    iy = (int)(v.yq >> 24);
+    fx = (real)(v.xq & 0xFFFFFFu) * real(5.9604644775390625e-08); // 2^-24
+    fy = (real)(v.yq & 0xFFFFFFu) * real(5.9604644775390625e-08);
+#endif
+}
+
+struct GridArgs {
+    Geom g;
+    const WorkItem *work;
+    const VisCoord *crd;
+    const cpx *vis;
+    const real *wgt;
+    const int64_t *perm;
+    const cpx *ext;
+    cpx *slots;
+    double *jpart;
+    const cpx *caller_in;
+    cpx *caller_out;
+    int nwave;
+};
+
+// One block per work item.  Lanes work in groups of G (8 for W <= 8, else 16): a group
+// takes one visibility, lane j owns footprint column j.  The W kernel weights along y are
+// computed once per group (one per lane) and shared with cross-lane moves; the degridded
+// value is reduced across the group.  Spreading uses LDS float atomics into the wave's
+// own accumulator, so no two waves touch the same memory and the final window is summed
+// over waves in a fixed order.
+template <int W, int MODE>
+__global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[NT / 64];
+    const Geom &g = a.g;
+    const int win = g.win, ldw = g.ldw;
+    const int wsz = win * ldw;
+    cpx *Fw = reinterpret_cast<cpx *>(smem_raw);
+    cpx *Hw = Fw + (MODE == MODE_ADJ ? 0 : wsz);
+    const WorkItem wi = a.work[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int nwave = a.nwave;
+    if (MODE != MODE_ADJ) {
+        const cpx *F = a.ext + (int64_t)wi.item * g.ext_stride + (int64_t)(wi.ty * g.T) * g.ew + wi.tx * g.T;
+        for (int e = tid; e < win * win; e += blockDim.x) {
+            const int r = e / win, cc = e - (e / win) * win;
+            Fw[r * ldw + cc] = F[(int64_t)r * g.ew + cc];
+        }
+    }
+    if (MODE != MODE_FWD) {
+        for (int e = tid; e < nwave * wsz; e += blockDim.x) Hw[e] = cpx{0, 0};
+    }
+    __syncthreads();
+
+    constexpr int G = (W <= 8) ? 8 : 16;
+    constexpr int VPW = 64 / G;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int grp = lane / G, j = lane - (lane / G) * G;
+    const int gbase = grp * G;
+    cpx *Hm = Hw + wave * wsz;
+    const real inv_hw = real(2) / real(W);
+    const real beta = g.beta;
+    const real zoff = real(0.5) * real(W) - real(1);
+    real jacc = real(0);
+
+    for (int base = wave * VPW; base < wi.count; base += nwave * VPW) {
+        const int v = base + grp;
+        const bool valid = v < wi.count;
+        const int64_t idx = wi.begin + (valid ? v : 0);
+        int ix, iy;
+        real fx, fy;
+        decode(a.crd[idx], ix, iy, fx, fy);
+        real wxj = real(0), wyj = real(0);
+        if (valid && j < W) {
+            wxj = es_kernel(zoff + fx - real(j), inv_hw, beta);
+            wyj = es_kernel(zoff + fy - real(j), inv_hw, beta);
+        }
+        real wy[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) wy[i] = __shfl(wyj, gbase + i, 64);
+
+        cpx V = cpx{0, 0};
+        if (MODE != MODE_ADJ) {
+            real ar = real(0), ai = real(0);
+            if (valid && j < W) {
+                const cpx *col = Fw + iy * ldw + ix + j;
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    const cpx f = col[i * ldw];
+                    ar += wy[i] * f.re;
+                    ai += wy[i] * f.im;
+                }
+            }
+            ar *= wxj;
+            ai *= wxj;
+#pragma unroll
+            for (int m = G / 2; m >= 1; m >>= 1) {
+                ar += __shfl_xor(ar, m, 64);
+                ai += __shfl_xor(ai, m, 64);
+            }
+            V = cpx{ar, ai};
+        }
+        if (MODE == MODE_FWD) {
+            if (valid && j == 0) {
+                const int64_t p = a.perm[idx];
+                if (p < 0) a.caller_out[~p] = cpx{V.re, -V.im};
+                else a.caller_out[p] = V;
+            }
+            continue;
+        }
+        real cr, ci;
+        if (MODE == MODE_OBJ) {
+            const cpx y = a.vis[idx];
+            const real w = a.wgt[idx];
+            const real rr = V.re - y.re, ri = V.im - y.im;
+            if (valid && j == 0) jacc += real(0.5) * w * (rr * rr + ri * ri);
+            cr = w * rr;
+            ci = w * ri;
+        } else {
+            const int64_t p = a.perm[idx];
+            cpx y = a.caller_in[p < 0 ? ~p : p];
+            if (p < 0) y.im = -y.im;
+            const real w = a.wgt[idx];
+            cr = w * y.re;
+            ci = w * y.im;
+        }
+        if (valid && j < W) {
+            cr *= wxj;
+            ci *= wxj;
+            cpx *col = Hm + iy * ldw + ix + j;
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                atomicAdd(&col[i * ldw].re, cr * wy[i]);
+                atomicAdd(&col[i * ldw].im, ci * wy[i]);
+            }
+        }
+    }
+    if (MODE == MODE_FWD) return;
+    __syncthreads();
+    cpx *S = a.slots + (int64_t)wi.slot * g.win_stride;
+    for (int e = tid; e < win * win; e += blockDim.x) {
+        const int r = e / win, cc = e - (e / win) * win;
+        real sr = real(0), si = real(0);
+        for (int w = 0; w < nwave; ++w) {
+            const cpx h = Hw[w * wsz + r * ldw + cc];
+            sr += h.re;
+            si += h.im;
+        }
+        S[e] = cpx{sr, si};
+    }
+    if (MODE == MODE_OBJ) {
+        double d = (double)jacc;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) d += __shfl_xor(d, m, 64);
+        if (lane == 0) red[wave] = d;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < nwave; ++w) s += red[w];
+            a.jpart[blockIdx.x] = s;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------- fold
+__device__ __forceinline__ cpx ext_cell(const Geom &g, const int32_t *__restrict__ ts,
+                                        const cpx *__restrict__ slots, int er, int ec) {
+    real sr = real(0), si = real(0);
+    const int ty1 = er / g.T, tx1 = ec / g.T;
+    for (int ty = ty1; ty >= ty1 - 1 && ty >= 0; --ty) {
+        if (ty >= g.nty) continue;
+        const int lr = er - ty * g.T;
+        if (lr >= g.win) break;
+        for (int tx = tx1; tx >= tx1 - 1 && tx >= 0; --tx) {
+            if (tx >= g.ntx) continue;
+            const int lc = ec - tx * g.T;
+            if (lc >= g.win) break;
+            const int tile = ty * g.ntx + tx;
+            const int s1 = ts[tile + 1];
+            for (int s = ts[tile]; s < s1; ++s) {
+                const cpx h = slots[(int64_t)s * g.win_stride + lr * g.win + lc];
+                sr += h.re;
+                si += h.im;
+            }
+        }
+    }
+    return cpx{sr, si};
+}
+
+// Sum of every extended-grid cell that aliases to periodic fine-grid cell (t1, t2).
+__device__ __forceinline__ cpx periodic_cell(const Geom &g, const int32_t *__restrict__ ts,
+                                             const cpx *__restrict__ slots, int t1, int t2) {
+    cpx s = cpx{0, 0};
+    for (int mr = -2; mr <= 2; ++mr) {
+        const int er = t1 + g.O + mr * g.nf;
+        if (er < 0 || er >= g.eh) continue;
+        for (int mc = -2; mc <= 2; ++mc) {
+            const int ec = t2 + g.O + mc * g.nf;
+            if (ec < 0 || ec >= g.ew) continue;
+            s = cadd(s, ext_cell(g, ts, slots, er, ec));
+        }
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(NT) void k_fold(Geom g, const int32_t *__restrict__ tslot,
+                                             const cpx *__restrict__ slots, cpx *__restrict__ hs) {
+    const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int item = blockIdx.y;
+    if (idx >= (int64_t)g.nf * g.rw) return;
+    const int t1 = (int)(idx / g.rw), t2 = (int)(idx - (idx / g.rw) * g.rw);
+    const int32_t *ts = tslot + (int64_t)item * (g.nty * g.ntx + 1);
+    const cpx h = periodic_cell(g, ts, slots, t1, t2);
+    const cpx m = periodic_cell(g, ts, slots, (g.nf - t1) & (g.nf - 1), (g.nf - t2) & (g.nf - 1));
+    hs[(int64_t)item * g.hs_stride + idx] = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
+}
+
+// ------------------------------------------------------------ adjoint column pass
+template <int LOGN>
+__global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ hs,
+                                                const cpx *__restrict__ tw, cpx *__restrict__ R) {
+    constexpr int N = 1 << LOGN;
+    constexpr int CB = col_batch<LOGN>();
+    __shared__ cpx buf[CB * N];
+    const int tid = threadIdx.x;
+    const int item = blockIdx.y;
+    const int c0 = blockIdx.x * CB;
+    const cpx *H = hs + (int64_t)item * g.hs_stride;
+    for (int e = tid; e < N * CB; e += NT) {
+        const int t1 = e / CB, cc = e - (e / CB) * CB;
+        buf[e] = (c0 + cc < g.rw) ? H[(int64_t)t1 * g.rw + c0 + cc] : cpx{0, 0};
+    }
+    __syncthreads();
+    fft_lds<LOGN, CB, true>(buf, tw);
+    cpx *Ri = R + (int64_t)item * g.r_stride;
+    const int nk = g.nk;
+    for (int e = tid; e < nk * CB; e += NT) {
+        const int a = e / CB, cc = e - (e / CB) * CB;
+        if (c0 + cc < g.rw) Ri[(int64_t)a * g.rw + c0 + cc] = buf[((a - nk / 2) & (N - 1)) * CB + cc];
+    }
+}
+
+// --------------------------------------------------------------- adjoint row pass
+template <int LOGN>
+__global__ __launch_bounds__(NT) void k_row_inv(Geom g, const cpx *__restrict__ R,
+                                                const real *__restrict__ beams,
+                                                const real *__restrict__ fscale,
+                                                const real *__restrict__ dq,
+                                                const cpx *__restrict__ tw, real *__restrict__ gp) {
+    constexpr int N = 1 << LOGN;
+    __shared__ cpx buf[N];
+    const int tid = threadIdx.x;
+    const int item = blockIdx.y;
+    const int k = item / g.C, c = item - (item / g.C) * g.C;
+    const int a0 = 2 * blockIdx.x;
+    const int nk = g.nk;
+    const cpx *X = R + (int64_t)item * g.r_stride + (int64_t)a0 * g.rw;
+    const cpx *Y = X + g.rw;
+    for (int kk = tid; kk < N; kk += NT) {
+        cpx x, y;
+        if (kk <= N / 2) {
+            x = X[kk];
+            y = Y[kk];
+            if (kk == 0 || kk == N / 2) { x.im = real(0); y.im = real(0); }
+        } else {
+            x = X[N - kk];
+            y = Y[N - kk];
+            x.im = -x.im;
+            y.im = -y.im;
+        }
+        buf[kk] = cpx{x.re - y.im, x.im + y.re}; // x + i y
+    }
+    __syncthreads();
+    fft_lds<LOGN, 1, true>(buf, tw);
+    const real *A = beams + (int64_t)k * nk * nk;
+    real *out = gp + (int64_t)item * nk * nk;
+    const real s = fscale[c];
+    const real q0 = s * dq[a0], q1 = s * dq[a0 + 1];
+    for (int b = tid; b < nk; b += NT) {
+        const cpx z = buf[(b - nk / 2) & (N - 1)];
+        const int64_t e0 = (int64_t)a0 * nk + b;
+        out[e0] = q0 * dq[b] * A[e0] * z.re;
+        out[e0 + nk] = q1 * dq[b] * A[e0 + nk] * z.im;
+    }
+}
+
+// ------------------------------------------------------------------- single dish
+__device__ __forceinline__ int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+__device__ __forceinline__ int ceildiv(int a, int b) { return -floordiv(-a, b); }
+
+// U[c][i][q] = sum_j g(o + q S - j) x[c][i][j]   (beam along columns, sampled columns)
+__global__ __launch_bounds__(NT) void k_sd_rows(Geom g, const real *__restrict__ sky,
+                                                const real *__restrict__ gB, int rb, int sd_n,
+                                                int stride, int offset, real *__restrict__ U) {
+    const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t tot = (int64_t)g.C * g.N * sd_n;
+    if (idx >= tot) return;
+    const int q = (int)(idx % sd_n);
+    const int64_t ci = idx / sd_n; // c * N + i
+    const real *row = sky + ci * g.N;
+    const int cen = offset + q * stride;
+    real s = real(0);
+    const int lo = cen - rb < 0 ? -cen : -rb;
+    const int hi = cen + rb >= g.N ? g.N - 1 - cen : rb;
+    for (int t = lo; t <= hi; ++t) s += gB[t + rb] * row[cen + t];
+    U[idx] = s;
+}
+
+// T~[c][p][q] = sum_i g(o + p S - i) U[c][i][q];  E = (T~ - T)/sigma^2;  K partials
+__global__ __launch_bounds__(NT) void k_sd_cols(Geom g, const real *__restrict__ U,
+                                                const real *__restrict__ gB, int rb, int sd_n,
+                                                int stride, int offset, const real *__restrict__ sdmap,
+                                                real inv_var, real *__restrict__ E, double *__restrict__ kpart) {
+    __shared__ double red[NT / 64];
+    const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t tot = (int64_t)g.C * sd_n * sd_n;
+    double kk = 0.0;
+    if (idx < tot) {
+        const int q = (int)(idx % sd_n);
+        const int p = (int)((idx / sd_n) % sd_n);
+        const int c = (int)(idx / ((int64_t)sd_n * sd_n));
+        const int cen = offset + p * stride;
+        const int lo = cen - rb < 0 ? -cen : -rb;
+        const int hi = cen + rb >= g.N ? g.N - 1 - cen : rb;
+        const real *Uc = U + (int64_t)c * g.N * sd_n;
+        real s = real(0);
+        for (int t = lo; t <= hi; ++t) s += gB[t + rb] * Uc[(int64_t)(cen + t) * sd_n + q];
+        const real res = s - sdmap[idx];
+        E[idx] = res * inv_var;
+        kk = 0.5 * (double)res * (double)res * (double)inv_var;
+    }
+    for (int m = 32; m >= 1; m >>= 1) kk += __shfl_xor(kk, m, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = kk;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+        kpart[blockIdx.x] = s;
+    }
+}
+
+// --------------------------------------------------------------------- sky level
+constexpr int SKY_T = 16;
+
+struct SkyArgs {
+    Geom g;
+    const real *sky;
+    const real *gp;
+    const int32_t *cptr;
+    const CsrEnt *cent;
+    real lambda_r, lambda_s;
+    const real *E;
+    const real *gB;
+    int rb, sd_n, stride, offset;
+    real *grad;
+    double *rpart;
+    int adjoint_only;
+};
+
+__global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
+    __shared__ real xs[SKY_T + 4][SKY_T + 5];
+    __shared__ real dxs[SKY_T + 2][SKY_T + 3];
+    __shared__ double red[NT / 64];
+    const Geom &g = a.g;
+    const int N = g.N;
+    const int c = blockIdx.z;
+    const int i0 = blockIdx.y * SKY_T, j0 = blockIdx.x * SKY_T;
+    const int tid = threadIdx.x;
+    const int ti = tid / SKY_T, tj = tid - (tid / SKY_T) * SKY_T;
+    const real *x = a.sky + (int64_t)c * N * N;
+    const bool reg = (a.lambda_r != real(0)) && !a.adjoint_only;
+    const bool sd = (a.lambda_s != real(0)) && (a.sd_n > 0) && !a.adjoint_only;
+    double rloc = 0.0;
+    if (reg) {
+        for (int e = tid; e < (SKY_T + 4) * (SKY_T + 4); e += NT) {
+            const int r = e / (SKY_T + 4), cc = e - (e / (SKY_T + 4)) * (SKY_T + 4);
+            const int gi = i0 - 2 + r, gj = j0 - 2 + cc;
+            xs[r][cc] = (gi >= 0 && gi < N && gj >= 0 && gj < N) ? x[(int64_t)gi * N + gj] : real(0);
+        }
+        __syncthreads();
+        for (int e = tid; e < (SKY_T + 2) * (SKY_T + 2); e += NT) {
+            const int r = e / (SKY_T + 2), cc = e - (e / (SKY_T + 2)) * (SKY_T + 2);
+            const int gi = i0 - 1 + r, gj = j0 - 1 + cc;
+            real d = real(0);
+            if (gi >= 0 && gi < N && gj >= 0 && gj < N)
+                d = real(4) * xs[r + 1][cc + 1] - xs[r][cc + 1] - xs[r + 2][cc + 1] - xs[r + 1][cc] - xs[r + 1][cc + 2];
+            dxs[r][cc] = d;
+        }
+        __syncthreads();
+    }
+    const int i = i0 + ti, j = j0 + tj;
+    if (i < N && j < N) {
+        real gsum = real(0);
+        const int64_t p = (int64_t)i * N + j;
+        const int64_t coff = (int64_t)c * g.nk * g.nk;
+        const int e1 = a.cptr[p + 1];
+        for (int e = a.cptr[p]; e < e1; ++e) {
+            const CsrEnt en = a.cent[e];
+            gsum += en.w * a.gp[(int64_t)en.off + coff];
+        }
+        if (reg) {
+            const real d = dxs[ti + 1][tj + 1];
+            gsum += a.lambda_r * (real(4) * d - dxs[ti][tj + 1] - dxs[ti + 2][tj + 1] - dxs[ti + 1][tj] - dxs[ti + 1][tj + 2]);
+            rloc = 0.5 * (double)d * (double)d;
+        }
+        if (sd) {
+            const int S = a.stride, o = a.offset, rb = a.rb;
+            const int p0 = max(0, ceildiv(i - rb - o, S)), p1 = min(a.sd_n - 1, floordiv(i + rb - o, S));
+            const int q0 = max(0, ceildiv(j - rb - o, S)), q1 = min(a.sd_n - 1, floordiv(j + rb - o, S));
+            const real *Ec = a.E + (int64_t)c * a.sd_n * a.sd_n;
+            real s = real(0);
+            for (int pp = p0; pp <= p1; ++pp) {
+                real row = real(0);
+                for (int qq = q0; qq <= q1; ++qq) row += a.gB[o + qq * S - j + rb] * Ec[pp * a.sd_n + qq];
+                s += a.gB[o + pp * S - i + rb] * row;
+            }
+            gsum += a.lambda_s * s;
+        }
+        a.grad[(int64_t)c * N * N + p] = gsum;
+    }
+    if (!a.adjoint_only) {
+        for (int m = 32; m >= 1; m >>= 1) rloc += __shfl_xor(rloc, m, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = rloc;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s += red[w];
+            a.rpart[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------- reductions
+__global__ __launch_bounds__(NT) void k_final(const double *__restrict__ jpart, int nj,
+                                              const double *__restrict__ rpart, int nr,
+                                              const double *__restrict__ kpart, int nkp,
+                                              double lambda_r, double lambda_s, double *terms) {
+    __shared__ double sh[3][NT];
+    const int tid = threadIdx.x;
+    double sj = 0.0, sr = 0.0, sk = 0.0;
+    for (int i = tid; i < nj; i += NT) sj += jpart[i];
+    for (int i = tid; i < nr; i += NT) sr += rpart[i];
+    for (int i = tid; i < nkp; i += NT) sk += kpart[i];
+    sh[0][tid] = sj;
+    sh[1][tid] = sr;
+    sh[2][tid] = sk;
+    __syncthreads();
+    for (int w = NT / 2; w >= 1; w >>= 1) {
+        if (tid < w) {
+            sh[0][tid] += sh[0][tid + w];
+            sh[1][tid] += sh[1][tid + w];
+            sh[2][tid] += sh[2][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double Q = sh[0][0], R = sh[1][0], K = sh[2][0];
+        terms[0] = Q + lambda_s * K + lambda_r * R;
+        terms[1] = Q;
+        terms[2] = K;
+        terms[3] = R;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_zero(uint32_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) p[i] = 0u;
+}
+
+// ===================================================================== launchers
+
+#define IVX_LOGN_SWITCH(LOGN_VAR, ...)                       \
+    switch (LOGN_VAR) {                                      \
+    case 6: { constexpr int L = 6; __VA_ARGS__; } break;     \
+    case 7: { constexpr int L = 7; __VA_ARGS__; } break;     \
+    case 8: { constexpr int L = 8; __VA_ARGS__; } break;     \
+    case 9: { constexpr int L = 9; __VA_ARGS__; } break;     \
+    case 10: { constexpr int L = 10; __VA_ARGS__; } break;   \
+    case 11: { constexpr int L = 11; __VA_ARGS__; } break;   \
+    default: return hipErrorInvalidValue;                    \
+    }
+
+static int n_items(const Geom &g) { return g.C * g.P; }
+
+hipError_t launch_image_rows(const Geom &g, const real *sky, const real *beams, const real *interp,
+                             const real *fscale, const real *dq, const cpx *tw, cpx *R, hipStream_t st) {
+    dim3 grid(g.nk / 2, n_items(g));
+    IVX_LOGN_SWITCH(g.logn, (k_image_rows<L><<<grid, NT, 0, st>>>(g, sky, beams, interp, fscale, dq, tw, R)));
+    return hipGetLastError();
+}
+
+hipError_t launch_col_fwd(const Geom &g, const cpx *R, const cpx *tw, cpx *ext, hipStream_t st) {
+    IVX_LOGN_SWITCH(g.logn, {
+        dim3 grid((g.rw + col_batch<L>() - 1) / col_batch<L>(), n_items(g));
+        k_col_fwd<L><<<grid, NT, 0, st>>>(g, R, tw, ext);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_col_inv(const Geom &g, const cpx *hs, const cpx *tw, cpx *R, hipStream_t st) {
+    IVX_LOGN_SWITCH(g.logn, {
+        dim3 grid((g.rw + col_batch<L>() - 1) / col_batch<L>(), n_items(g));
+        k_col_inv<L><<<grid, NT, 0, st>>>(g, hs, tw, R);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_row_inv(const Geom &g, const cpx *R, const real *beams, const real *fscale,
+                          const real *dq, const cpx *tw, real *gp, hipStream_t st) {
+    dim3 grid(g.nk / 2, n_items(g));
+    IVX_LOGN_SWITCH(g.logn, (k_row_inv<L><<<grid, NT, 0, st>>>(g, R, beams, fscale, dq, tw, gp)));
+    return hipGetLastError();
+}
+
+size_t grid_lds_bytes(const Geom &g, int nwave) {
+    return (size_t)(1 + nwave) * g.win * g.ldw * sizeof(cpx);
+}
+
+template <int W>
+static hipError_t launch_grid_w(int mode, const GridArgs &a, int n_work, hipStream_t st) {
+    const size_t wsz = (size_t)a.g.win * a.g.ldw * sizeof(cpx);
+    const int threads = 64 * a.nwave;
+    size_t lds;
+    switch (mode) {
+    case MODE_OBJ:
+        lds = (1 + a.nwave) * wsz;
+        if (hipFuncSetAttribute((const void *)k_grid<W, MODE_OBJ>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return hipGetLastError();
+        k_grid<W, MODE_OBJ><<<n_work, threads, lds, st>>>(a);
+        break;
+    case MODE_FWD:
+        lds = wsz;
+        if (hipFuncSetAttribute((const void *)k_grid<W, MODE_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return hipGetLastError();
+        k_grid<W, MODE_FWD><<<n_work, threads, lds, st>>>(a);
+        break;
+    default:
+        lds = a.nwave * wsz;
+        if (hipFuncSetAttribute((const void *)k_grid<W, MODE_ADJ>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return hipGetLastError();
+        k_grid<W, MODE_ADJ><<<n_work, threads, lds, st>>>(a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
+                       const cpx *vis, const real *wgt, const int64_t *perm, const cpx *ext, cpx *slots,
+                       double *jpart, const cpx *caller_in, cpx *caller_out, int nwave, hipStream_t st) {
+    if (n_work <= 0) return hipSuccess;
+    if (nwave < 1 || nwave > NT / 64) return hipErrorInvalidValue;
+    GridArgs a{g, work, crd, vis, wgt, perm, ext, slots, jpart, caller_in, caller_out, nwave};
+    switch (g.W) {
+    case 4: return launch_grid_w<4>(mode, a, n_work, st);
+    case 5: return launch_grid_w<5>(mode, a, n_work, st);
+    case 6: return launch_grid_w<6>(mode, a, n_work, st);
+    case 7: return launch_grid_w<7>(mode, a, n_work, st);
+    case 8: return launch_grid_w<8>(mode, a, n_work, st);
+    case 9: return launch_grid_w<9>(mode, a, n_work, st);
+    case 10: return launch_grid_w<10>(mode, a, n_work, st);
+    case 11: return launch_grid_w<11>(mode, a, n_work, st);
+    case 12: return launch_grid_w<12>(mode, a, n_work, st);
+    case 13: return launch_grid_w<13>(mode, a, n_work, st);
+    case 14: return launch_grid_w<14>(mode, a, n_work, st);
+    case 15: return launch_grid_w<15>(mode, a, n_work, st);
+    case 16: return launch_grid_w<16>(mode, a, n_work, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *hs, hipStream_t st) {
+    const int64_t cells = (int64_t)g.nf * g.rw;
+    dim3 grid((unsigned)((cells + NT - 1) / NT), n_items(g));
+    k_fold<<<grid, NT, 0, st>>>(g, tslot, slots, hs);
+    return hipGetLastError();
+}
+
+hipError_t launch_sd_rows(const Geom &g, const real *sky, const real *gB, int rb, int sd_n, int stride,
+                          int offset, real *U, hipStream_t st) {
+    const int64_t tot = (int64_t)g.C * g.N * sd_n;
+    k_sd_rows<<<(unsigned)((tot + NT - 1) / NT), NT, 0, st>>>(g, sky, gB, rb, sd_n, stride, offset, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_sd_cols(const Geom &g, const real *U, const real *gB, int rb, int sd_n, int stride,
+                          int offset, const real *sdmap, real inv_var, real *E, double *kpart, hipStream_t st) {
+    const int64_t tot = (int64_t)g.C * sd_n * sd_n;
+    k_sd_cols<<<(unsigned)((tot + NT - 1) / NT), NT, 0, st>>>(g, U, gB, rb, sd_n, stride, offset, sdmap,
+                                                              inv_var, E, kpart);
+    return hipGetLastError();
+}
+
+int sky_blocks(const Geom &g) {
+    const int nb = (g.N + SKY_T - 1) / SKY_T;
+    return nb * nb * g.C;
+}
+
+hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int32_t *cptr, const CsrEnt *cent,
+                      real lambda_r, real lambda_s, const real *E, const real *gB, int rb, int sd_n, int stride,
+                      int offset, real *grad, double *rpart, bool adjoint_only, hipStream_t st) {
+    const int nb = (g.N + SKY_T - 1) / SKY_T;
+    SkyArgs a{g, sky, gp, cptr, cent, lambda_r, lambda_s, E, gB, rb, sd_n, stride, offset, grad, rpart,
+              adjoint_only ? 1 : 0};
+    k_sky<<<dim3(nb, nb, g.C), NT, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_final(const double *jpart, int nj, const double *rpart, int nr, const double *kpart, int nkp,
+                        double lambda_r, double lambda_s, double *terms, hipStream_t st) {
+    k_final<<<1, NT, 0, st>>>(jpart, nj, rpart, nr, kpart, nkp, lambda_r, lambda_s, terms);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st) {
+    if (bytes <= 0) return hipSuccess;
+    if (bytes % 4) return hipErrorInvalidValue;
+    const int64_t n = bytes / 4;
+    int64_t blocks = (n + NT - 1) / NT;
+    if (blocks > 4096) blocks = 4096;
+    k_zero<<<(unsigned)blocks, NT, 0, st>>>((uint32_t *)p, n);
+    return hipGetLastError();
+}
+
+} // namespace ivx

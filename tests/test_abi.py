@@ -1,0 +1,108 @@
+"""The C ABI on the CPU: the library loads, exports every symbol include/ivx.h declares,
+its descriptor matches the header's layout, and argument checking happens before any
+device call (no kernel runs here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2609_17636_amd as ivx
+from paper_2609_17636_amd import IvxError, Plan, load_library
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ivx.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ivx_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_library_exports_every_declared_symbol(precision):
+    lib = load_library(precision)
+    names = _declared()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.ivx_version() == 1
+    assert lib.ivx_real_size() == (4 if precision == "f32" else 8)
+
+
+@pytest.mark.parametrize("real_double", [False, True])
+def test_descriptor_layout_matches_header(tmp_path, real_double):
+    c = tmp_path / "probe.c"
+    c.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ivx.h"\n'
+                 'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(ivx_problem),'
+                 ' offsetof(ivx_problem, sd_fwhm_rad), offsetof(ivx_problem, reserved), sizeof(ivx_real));'
+                 'return 0;}\n')
+    exe = tmp_path / "probe"
+    cmd = ["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)]
+    if real_double:
+        cmd.insert(1, "-DIVX_REAL_DOUBLE")
+    subprocess.run(cmd, check=True)
+    size, off_fwhm, off_res, rs = map(int, subprocess.run([str(exe)], capture_output=True, text=True,
+                                                           check=True).stdout.split())
+    assert size == ctypes.sizeof(ivx._Problem)
+    assert off_fwhm == ivx._Problem.sd_fwhm_rad.offset
+    assert off_res == ivx._Problem.reserved.offset
+    assert rs == (8 if real_double else 4)
+
+
+def _args(**over):
+    a = dict(n_chan=1, n_sky=64, pixel_rad=1e-4, n_point=1, n_sub=64,
+             vis_offsets=np.array([0, 10], dtype=np.int64), flux_scale=np.array([1.0]))
+    a.update(over)
+    return a
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_sub=63), dict(n_sub=2), dict(n_chan=0), dict(pixel_rad=-1.0), dict(pixel_rad=float("nan")),
+    dict(vis_offsets=np.array([0, 10, 5], dtype=np.int64), n_chan=2, flux_scale=np.array([1.0, 1.0])),
+    dict(vis_offsets=np.array([3, 10], dtype=np.int64)), dict(lambda_r=-1.0), dict(kernel_width=3),
+    dict(kernel_width=17), dict(fine_size=100), dict(fine_size=64, n_sub=64), dict(tile=4),
+    dict(sd_n=64, sd_stride=2, sd_offset=1, sd_fwhm_rad=1e-3, sd_sigma=1.0),
+    dict(sd_n=8, sd_stride=8, sd_offset=4, sd_fwhm_rad=0.0, sd_sigma=1.0),
+    dict(flux_scale=np.array([np.inf])),
+])
+def test_plan_create_rejects_bad_descriptors(bad):
+    with pytest.raises(IvxError) as e:
+        Plan(**_args(**bad))
+    assert e.value.code == -1
+    assert ivx.load_library().ivx_last_error().decode()
+
+
+def test_plan_create_chooses_parameters():
+    p = Plan(**_args())
+    info = p.info()
+    assert info["n_fine"] == 128 and info["kernel_width"] == 8
+    assert info["tile"] >= info["kernel_width"]
+    assert info["window"] == info["tile"] + info["kernel_width"] - 1
+    p64 = Plan(**_args(), precision="f64")
+    assert p64.info()["kernel_width"] >= 12
+    explicit = Plan(**_args(kernel_width=6, fine_size=256, tile=16))
+    assert (explicit.info()["n_fine"], explicit.info()["kernel_width"], explicit.info()["tile"]) == (256, 6, 16)
+
+
+def test_evaluation_before_data_is_a_state_error():
+    lib = load_library()
+    p = Plan(**_args())
+    terms = np.zeros(4)
+    code = lib.ivx_objective_grad(p._h, ctypes.c_void_p(16), ctypes.c_void_p(16), terms.ctypes.data, None)
+    assert code == -5
+    assert "set_data" in lib.ivx_last_error().decode()
+    assert lib.ivx_forward(p._h, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == -5
+    assert lib.ivx_adjoint(p._h, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == -5
+
+
+def test_null_handling():
+    lib = load_library()
+    assert lib.ivx_plan_destroy(None) == 0
+    out = ctypes.c_void_p()
+    assert lib.ivx_plan_create(None, ctypes.byref(out)) == -1
+    assert out.value is None
+    assert lib.ivx_objective_grad(None, None, None, None, None) == -1
