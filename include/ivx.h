@@ -138,10 +138,17 @@ ivx_status ivx_forward(ivx_plan *plan, const ivx_real *sky, ivx_real *model_vis,
  * when v = y.  vis: device [M][2] caller order; image: device [C][N][N], overwritten. */
 ivx_status ivx_adjoint(ivx_plan *plan, const ivx_real *vis, ivx_real *image, void *stream);
 
-/* Time the gridding stage for each candidate tile edge that fits the LDS and keep the
- * fastest (the result is accuracy-neutral: only the blocking changes).  budget_ms bounds
- * the time spent; *chosen_tile (host, may be NULL) receives the tile kept. */
+/* Time the gridding stage and its slot reduction for candidate blockings (tile edge,
+ * waves per block, visibilities per work item) that fit the LDS, and keep the fastest.
+ * The result is accuracy-neutral: only the blocking changes.  budget_ms bounds the time
+ * spent; *chosen_tile (host, may be NULL) receives the tile edge kept.  The candidates
+ * are timed on this plan's data. */
 ivx_status ivx_autotune(ivx_plan *plan, double budget_ms, int32_t *chosen_tile, void *stream);
+
+/* ivx_objective_grad records its launches into a HIP graph on first use and replays it
+ * while the (sky, grad) pointers stay the same (a new pair re-captures).  enable = 0
+ * launches the kernels one by one instead; results are identical. */
+ivx_status ivx_set_graph(ivx_plan *plan, int enable);
 
 /* Stages of one evaluation, in launch order (bit i of a stage mask = stage i). */
 enum {
@@ -167,7 +174,7 @@ ivx_status ivx_stage_times(ivx_plan *plan, double *ms, int64_t *n_eval);
 
 /* Plan facts, host array of 16 int64: {n_fine, kernel_width, tile, n_work_items,
  * n_live_vis, n_slots, device_bytes, n_items, ext_rows, ext_cols, graph_nodes,
- * window, 0, 0, 0, 0}. */
+ * window, waves_per_block, max_vis_per_work_item, 0, 0}. */
 ivx_status ivx_plan_info(const ivx_plan *plan, int64_t *info16);
 
 /* Release every resource of the plan (NULL is accepted). */

@@ -46,7 +46,7 @@ class _Problem(ctypes.Structure):
 
 EXPORTS = ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_forward", "ivx_adjoint",
            "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_last_error", "ivx_version",
-           "ivx_real_size", "ivx_set_timing", "ivx_stage_times")
+           "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph")
 
 STAGES = ("image_rows", "col_fwd", "grid", "fold", "col_inv", "row_inv", "sd", "sky", "final")
 
@@ -72,12 +72,13 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
     lib.ivx_plan_info.argtypes = [vp, vp]
     lib.ivx_plan_destroy.argtypes = [vp]
     lib.ivx_set_timing.argtypes = [vp, ctypes.c_uint32]
+    lib.ivx_set_graph.argtypes = [vp, ctypes.c_int]
     lib.ivx_stage_times.argtypes = [vp, vp, vp]
     lib.ivx_last_error.restype = ctypes.c_char_p
     lib.ivx_last_error.argtypes = []
     for f in ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_forward",
               "ivx_adjoint", "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_set_timing",
-              "ivx_stage_times"):
+              "ivx_stage_times", "ivx_set_graph"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ivx_version.restype = ctypes.c_int
     lib.ivx_real_size.restype = ctypes.c_int
@@ -230,6 +231,10 @@ class Plan:
         self._check(self.lib.ivx_autotune(self._h, float(budget_ms), ctypes.addressof(t), _stream_ptr(stream)))
         return int(t.value)
 
+    def set_graph(self, enable: bool):
+        """Replay objective evaluations from a captured HIP graph (default) or launch eagerly."""
+        self._check(self.lib.ivx_set_graph(self._h, int(bool(enable))))
+
     def set_timing(self, stages=STAGES):
         """Record device events around the named stages of every objective evaluation."""
         mask = 0
@@ -248,7 +253,8 @@ class Plan:
         a = np.zeros(16, dtype=np.int64)
         self._check(self.lib.ivx_plan_info(self._h, a.ctypes.data))
         keys = ["n_fine", "kernel_width", "tile", "n_work_items", "n_live_vis", "n_slots", "device_bytes",
-                "n_items", "ext_rows", "ext_cols", "graph_nodes", "window"]
+                "n_items", "ext_rows", "ext_cols", "graph_nodes", "window", "waves_per_block",
+                "chunk"]
         return {k: int(v) for k, v in zip(keys, a)}
 
 

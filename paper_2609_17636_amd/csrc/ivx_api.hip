@@ -115,6 +115,7 @@ struct ivx_plan {
     Geom g{};
     double beta = 0.0;
     int nwave = 4;
+    int chunk_max = 512;
     int tile_fixed = 0;
     std::vector<real> dq_host;
     std::vector<cpx> tw_host;
@@ -152,6 +153,13 @@ struct ivx_plan {
     std::vector<std::pair<int, int>> ev_used;   // (stage, index of start event) pending
     size_t ev_next = 0;
     int64_t timed_evals = 0;
+    // one captured evaluation, replayed while (sky, grad) stay the same
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void *g_sky = nullptr;
+    void *g_grad = nullptr;
+    int64_t graph_nodes = 0;
 };
 
 namespace {
@@ -172,7 +180,16 @@ template <typename T> ivx_status dalloc(ivx_plan *p, T **out, size_t count) {
     return IVX_OK;
 }
 
+void drop_graph(ivx_plan *p) {
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->g_sky = nullptr;
+    p->g_grad = nullptr;
+    p->graph_nodes = 0;
+}
+
 void free_all(ivx_plan *p) {
+    drop_graph(p);
     for (auto &b : p->bufs) (void)hipFree(b.p);
     p->bufs.clear();
     p->dev_bytes = 0;
@@ -246,7 +263,7 @@ ivx_status build_bins(ivx_plan *p, hipStream_t st) {
     const int n_items = g.C * g.P;
     const int ntiles = g.nty * g.ntx;
     const int64_t L = p->m_live;
-    const int chunk_max = 2048;
+    const int chunk_max = p->chunk_max;
     std::vector<VisCoord> crd(L > 0 ? L : 1);
     std::vector<cpx> vis(L > 0 ? L : 1);
     std::vector<real> wgt(L > 0 ? L : 1);
@@ -313,6 +330,8 @@ ivx_status build_bins(ivx_plan *p, hipStream_t st) {
                      [](const WorkItem &a, const WorkItem &b) { return a.count > b.count; });
     p->n_work = (int)work.size();
     p->n_slots = slot;
+    drop_graph(p); // kernel arguments change with the tiling
+    IVX_HIP(prepare_grid(g, p->nwave));
 
     for (void *old : {(void *)p->d_crd, (void *)p->d_vis, (void *)p->d_wgt, (void *)p->d_perm,
                       (void *)p->d_work, (void *)p->d_tslot, (void *)p->d_ext, (void *)p->d_slots,
@@ -571,6 +590,13 @@ ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out) {
     return IVX_OK;
 }
 
+ivx_status ivx_set_graph(ivx_plan *p, int enable) {
+    if (!p) return fail(IVX_EINVAL, "plan is NULL");
+    p->use_graph = enable != 0;
+    if (!p->use_graph) drop_graph(p);
+    return IVX_OK;
+}
+
 ivx_status ivx_set_timing(ivx_plan *p, uint32_t stage_mask) {
     if (!p) return fail(IVX_EINVAL, "plan is NULL");
     p->timing_mask = stage_mask & ((1u << IVX_NSTAGE) - 1u);
@@ -599,6 +625,7 @@ ivx_status ivx_plan_destroy(ivx_plan *plan) {
     for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
     plan->ev_pool.clear();
     free_all(plan);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
     return IVX_OK;
 }
@@ -607,7 +634,7 @@ ivx_status ivx_plan_info(const ivx_plan *p, int64_t *info) {
     if (!p || !info) return fail(IVX_EINVAL, "plan and info must be non-NULL");
     const Geom &g = p->g;
     const int64_t v[16] = {g.nf, g.W, g.T, p->n_work, p->m_live, p->n_slots, (int64_t)p->dev_bytes,
-                           (int64_t)g.C * g.P, g.eh, g.ew, 0, g.win, 0, 0, 0, 0};
+                           (int64_t)g.C * g.P, g.eh, g.ew, p->graph_nodes, g.win, p->nwave, p->chunk_max, 0, 0};
     std::memcpy(info, v, sizeof(v));
     return IVX_OK;
 }
@@ -806,7 +833,35 @@ ivx_status ivx_objective_grad(ivx_plan *p, const ivx_real *sky, ivx_real *grad, 
     if (s != IVX_OK) return s;
     if (!sky || !grad) return fail(IVX_EINVAL, "sky and grad are required");
     hipStream_t st = (hipStream_t)stream;
-    if ((s = eval_objective(p, sky, grad, st)) != IVX_OK) return s;
+    if (p->use_graph && p->timing_mask == 0) {
+        if (!(p->gexec && p->g_sky == sky && p->g_grad == grad)) {
+            drop_graph(p);
+            if (!p->cap_stream) IVX_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+            IVX_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+            ivx_status cs = eval_objective(p, sky, grad, p->cap_stream);
+            hipGraph_t graph = nullptr;
+            hipError_t ee = hipStreamEndCapture(p->cap_stream, &graph);
+            if (cs != IVX_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return cs;
+            }
+            if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+            size_t nn = 0;
+            (void)hipGraphGetNodes(graph, nullptr, &nn);
+            hipError_t ie = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                p->gexec = nullptr;
+                return hip_fail(ie, "hipGraphInstantiate");
+            }
+            p->g_sky = sky;
+            p->g_grad = grad;
+            p->graph_nodes = (int64_t)nn;
+        }
+        IVX_HIP(hipGraphLaunch(p->gexec, st));
+    } else {
+        if ((s = eval_objective(p, sky, grad, st)) != IVX_OK) return s;
+    }
     if (terms) {
         IVX_HIP(hipMemcpyAsync(terms, p->d_terms, 4 * sizeof(double), hipMemcpyDefault, st));
         hipPointerAttribute_t attr;
@@ -849,12 +904,18 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     ivx_status s = check_plan(p);
     if (s != IVX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    const int cand[] = {16, 24, 32, 40, 48, 64};
-    std::vector<int> tiles;
-    for (int T : cand)
-        if (tile_fits(p, T, p->nwave)) tiles.push_back(T);
-    if (tiles.empty()) return fail(IVX_EINVAL, "no tile candidate fits");
-    // time the gridding stage (the only stage that depends on the tile) on a zero sky
+    struct Cand { int T, nwave, chunk; };
+    std::vector<Cand> cands;
+    const int tiles[] = {16, 24, 32, 40, 48};
+    const int waves[] = {4, 2};
+    const int chunks[] = {256, 512, 1024};
+    for (int T : tiles)
+        for (int nw : waves)
+            if (tile_fits(p, T, nw))
+                for (int ch : chunks) cands.push_back(Cand{T, nw, ch});
+    if (cands.empty()) return fail(IVX_EINVAL, "no tile candidate fits");
+    // the tiling only changes the gridding stage and the slot reduction: time those two on
+    // the plan's own data (zero sky), keep the fastest; the result is accuracy-neutral
     real *sky = nullptr;
     const int64_t nsky = (int64_t)p->g.C * p->g.N * p->g.N;
     IVX_HIP(hipMalloc(&sky, nsky * sizeof(real)));
@@ -864,9 +925,11 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     IVX_HIP(hipEventCreate(&e1));
     const auto t_start = std::chrono::steady_clock::now();
     double best_ms = 1e300;
-    int best_T = p->g.T;
-    for (int T : tiles) {
-        set_tile(p, T);
+    Cand best{p->g.T, p->nwave, p->chunk_max};
+    for (const Cand &c : cands) {
+        p->nwave = c.nwave;
+        p->chunk_max = c.chunk;
+        set_tile(p, c.T);
         if ((s = build_bins(p, st)) != IVX_OK) break;
         if ((s = run_forward_half(p, sky, st)) != IVX_OK) break;
         float ms = 0.f, tot = 0.f;
@@ -884,7 +947,7 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
         const double avg = tot / reps;
         if (avg < best_ms) {
             best_ms = avg;
-            best_T = T;
+            best = c;
         }
         const double spent = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         if (spent > budget_ms) break;
@@ -893,9 +956,11 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     (void)hipEventDestroy(e1);
     (void)hipFree(sky);
     if (s != IVX_OK) return s;
-    set_tile(p, best_T);
+    p->nwave = best.nwave;
+    p->chunk_max = best.chunk;
+    set_tile(p, best.T);
     if ((s = build_bins(p, st)) != IVX_OK) return s;
-    if (chosen_tile) *chosen_tile = best_T;
+    if (chosen_tile) *chosen_tile = best.T;
     return IVX_OK;
 }
 

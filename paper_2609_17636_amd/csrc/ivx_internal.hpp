@@ -97,6 +97,9 @@ hipError_t launch_final(const double *jpart, int nj, const double *rpart, int nr
                         double *terms, hipStream_t st);
 hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st);
 
+// Raise the dynamic-LDS limit of the gridding kernels for this geometry (call before any
+// stream capture).
+hipError_t prepare_grid(const Geom &g, int nwave);
 // Maximum dynamic LDS for the gridding kernel (bytes); used to pick tiles.
 size_t grid_lds_bytes(const Geom &g, int nwave);
 

@@ -182,11 +182,10 @@ __global__ __launch_bounds__(NT) void k_image_rows(Geom g, const real *__restric
 }
 
 // -------------------------------------------------------------- forward column pass
-template <int LOGN>
+template <int LOGN, int CB>
 __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ R,
                                                 const cpx *__restrict__ tw, cpx *__restrict__ ext) {
     constexpr int N = 1 << LOGN;
-    constexpr int CB = col_batch<LOGN>();
     constexpr int MAXE = 8 * CB;
     __shared__ cpx buf[CB * N];
     __shared__ int ent_col[MAXE];
@@ -228,7 +227,7 @@ __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ 
     cpx *E = ext + (int64_t)item * g.ext_stride;
     const int ne = n_ent;
     for (int e = tid; e < ne * g.eh; e += NT) {
-        const int er = e / ne, en = e - (e / ne) * ne;
+        const int en = e / g.eh, er = e - (e / g.eh) * g.eh;
         const int src = ent_src[en];
         const int cc = src & 0xFFFF;
         const int t1 = (er - g.O) & (N - 1);
@@ -239,7 +238,7 @@ __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ 
         } else {
             v = buf[t1 * CB + cc];
         }
-        E[(int64_t)er * g.ew + ent_col[en]] = v;
+        E[(int64_t)ent_col[en] * g.eh + er] = v; // column-major
     }
 }
 
@@ -279,12 +278,53 @@ struct GridArgs {
     int nwave;
 };
 
-// One block per work item.  Lanes work in groups of G (8 for W <= 8, else 16): a group
-// takes one visibility, lane j owns footprint column j.  The W kernel weights along y are
-// computed once per group (one per lane) and shared with cross-lane moves; the degridded
-// value is reduced across the group.  Spreading uses LDS float atomics into the wave's
-// own accumulator, so no two waves touch the same memory and the final window is summed
-// over waves in a fixed order.
+// ---- cross-lane moves inside a 16-lane DPP row (VALU, no LDS traffic)
+template <int CTRL> __device__ __forceinline__ float dpp(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double v) {
+    const int2 p = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, 0xF, 0xF, false);
+    r.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, r);
+}
+// sum over the 16 lanes of the row, returned in every lane (xor 1, xor 2, half mirror, mirror)
+__device__ __forceinline__ real row_sum16(real v) {
+    v += dpp<0xB1>(v);
+    v += dpp<0x4E>(v);
+    v += dpp<0x141>(v);
+    v += dpp<0x140>(v);
+    return v;
+}
+template <int L> __device__ __forceinline__ real row_bcast(real v) { return dpp<0x150 + L>(v); }
+__device__ __forceinline__ real row_shr8(real v) { return dpp<0x118>(v); }
+
+template <int W> struct Taps {
+    // lane t of a 16-lane group owns footprint column j and rows h, h + S, h + 2S, ...
+    static constexpr int S = (W <= 8) ? 2 : 1;
+    static constexpr int NR = (W + S - 1) / S;
+};
+
+template <int W, int I> struct BcastAll {
+    __device__ __forceinline__ static void run(real v, real *out) {
+        out[I] = row_bcast<(W <= 8 ? 8 : 0) + I>(v);
+        BcastAll<W, I + 1>::run(v, out);
+    }
+};
+template <int W> struct BcastAll<W, W> {
+    __device__ __forceinline__ static void run(real, real *) {}
+};
+
+// One block per work item (a fine-grid tile, or a chunk of one).  The block's waves split
+// into 16-lane groups; group g walks its own contiguous segment of the tile's visibility
+// list, so the four groups of a wave work on visibilities taken far apart along the
+// baseline tracks (their footprints rarely coincide).  In a group, lane t owns footprint
+// column j and a set of rows; the 2W kernel weights are computed once per group (one per
+// lane) and moved across lanes with DPP row broadcasts; the degridded value is a DPP row
+// sum.  Spreading adds into the wave's own LDS accumulator (LDS atomics resolve the rare
+// coincidences between the four groups); the window is summed over waves in a fixed
+// order, so the result does not depend on scheduling.
 template <int W, int MODE>
 __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -298,10 +338,10 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     const int tid = threadIdx.x;
     const int nwave = a.nwave;
     if (MODE != MODE_ADJ) {
-        const cpx *F = a.ext + (int64_t)wi.item * g.ext_stride + (int64_t)(wi.ty * g.T) * g.ew + wi.tx * g.T;
+        const cpx *F = a.ext + (int64_t)wi.item * g.ext_stride + (int64_t)(wi.tx * g.T) * g.eh + wi.ty * g.T;
         for (int e = tid; e < win * win; e += blockDim.x) {
-            const int r = e / win, cc = e - (e / win) * win;
-            Fw[r * ldw + cc] = F[(int64_t)r * g.ew + cc];
+            const int cc = e / win, r = e - (e / win) * win;
+            Fw[r * ldw + cc] = F[(int64_t)cc * g.eh + r];
         }
     }
     if (MODE != MODE_FWD) {
@@ -309,101 +349,134 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     }
     __syncthreads();
 
-    constexpr int G = (W <= 8) ? 8 : 16;
-    constexpr int VPW = 64 / G;
+    constexpr int S = Taps<W>::S, NR = Taps<W>::NR;
     const int lane = tid & 63, wave = tid >> 6;
-    const int grp = lane / G, j = lane - (lane / G) * G;
-    const int gbase = grp * G;
+    const int t = lane & 15;
+    const int j = (S == 2) ? (t & 7) : t;
+    const int h = (S == 2) ? (t >> 3) : 0;
+    const bool colok = j < W;
     cpx *Hm = Hw + wave * wsz;
     const real inv_hw = real(2) / real(W);
     const real beta = g.beta;
     const real zoff = real(0.5) * real(W) - real(1);
     real jacc = real(0);
 
-    for (int base = wave * VPW; base < wi.count; base += nwave * VPW) {
-        const int v = base + grp;
-        const bool valid = v < wi.count;
-        const int64_t idx = wi.begin + (valid ? v : 0);
+    const int ngroups = nwave * 4;
+    const int gid = wave * 4 + (lane >> 4);
+    const int seg = (wi.count + ngroups - 1) / ngroups;
+    const int v0 = gid * seg;
+    const int v1 = min(wi.count, v0 + seg);
+
+    // software pipeline: the record of iteration it+1 is loaded during iteration it
+    auto at = [&](int it) -> int64_t { const int v = v0 + it; return wi.begin + (v < v1 ? v : 0); };
+    VisCoord c_nx = a.crd[at(0)];
+    cpx y_nx = cpx{0, 0};
+    real w_nx = real(0);
+    int64_t p_nx = 0;
+    if (MODE == MODE_OBJ) { y_nx = a.vis[at(0)]; w_nx = a.wgt[at(0)]; }
+    if (MODE == MODE_ADJ) { w_nx = a.wgt[at(0)]; p_nx = a.perm[at(0)]; }
+    if (MODE == MODE_FWD) { p_nx = a.perm[at(0)]; }
+
+    for (int it = 0; it < seg; ++it) {
+        const bool valid = v0 + it < v1;
+        const VisCoord cr = c_nx;
+        const cpx ycur = y_nx;
+        const real wcur = w_nx;
+        const int64_t pcur = p_nx;
+        if (it + 1 < seg) {
+            const int64_t n1 = at(it + 1);
+            c_nx = a.crd[n1];
+            if (MODE == MODE_OBJ) { y_nx = a.vis[n1]; w_nx = a.wgt[n1]; }
+            if (MODE == MODE_ADJ) { w_nx = a.wgt[n1]; p_nx = a.perm[n1]; }
+            if (MODE == MODE_FWD) { p_nx = a.perm[n1]; }
+        }
         int ix, iy;
         real fx, fy;
-        decode(a.crd[idx], ix, iy, fx, fy);
-        real wxj = real(0), wyj = real(0);
-        if (valid && j < W) {
-            wxj = es_kernel(zoff + fx - real(j), inv_hw, beta);
-            wyj = es_kernel(zoff + fy - real(j), inv_hw, beta);
+        decode(cr, ix, iy, fx, fy);
+        // kernel weights: one or two evaluations per lane, then spread across the row
+        real wxj, wy[W];
+        if constexpr (S == 2) {
+            const bool isx = t < 8;
+            const int k = t & 7;
+            real mine = real(0);
+            if (k < W) mine = es_kernel(zoff + (isx ? fx : fy) - real(k), inv_hw, beta);
+            const real sh = row_shr8(mine);
+            wxj = isx ? mine : sh;
+            BcastAll<W, 0>::run(mine, wy);
+        } else {
+            real mx = real(0), my = real(0);
+            if (t < W) {
+                mx = es_kernel(zoff + fx - real(t), inv_hw, beta);
+                my = es_kernel(zoff + fy - real(t), inv_hw, beta);
+            }
+            wxj = mx;
+            BcastAll<W, 0>::run(my, wy);
         }
-        real wy[W];
-#pragma unroll
-        for (int i = 0; i < W; ++i) wy[i] = __shfl(wyj, gbase + i, 64);
-
-        cpx V = cpx{0, 0};
+        if (!valid) wxj = real(0);
+        real ar = real(0), ai = real(0);
         if (MODE != MODE_ADJ) {
-            real ar = real(0), ai = real(0);
-            if (valid && j < W) {
-                const cpx *col = Fw + iy * ldw + ix + j;
+            if (colok && valid) {
+                const cpx *col = Fw + (iy + h) * ldw + ix + j;
 #pragma unroll
-                for (int i = 0; i < W; ++i) {
-                    const cpx f = col[i * ldw];
-                    ar += wy[i] * f.re;
-                    ai += wy[i] * f.im;
+                for (int k = 0; k < NR; ++k) {
+                    const int i = h + S * k;
+                    if (S == 1 || i < W) {
+                        const cpx f = col[S * k * ldw];
+                        const real wyi = (S == 2) ? (h ? wy[(2 * k + 1) < W ? 2 * k + 1 : 0] : wy[2 * k]) : wy[k];
+                        ar += wyi * f.re;
+                        ai += wyi * f.im;
+                    }
                 }
             }
-            ar *= wxj;
-            ai *= wxj;
-#pragma unroll
-            for (int m = G / 2; m >= 1; m >>= 1) {
-                ar += __shfl_xor(ar, m, 64);
-                ai += __shfl_xor(ai, m, 64);
-            }
-            V = cpx{ar, ai};
+            ar = row_sum16(ar * wxj);
+            ai = row_sum16(ai * wxj);
         }
         if (MODE == MODE_FWD) {
-            if (valid && j == 0) {
-                const int64_t p = a.perm[idx];
-                if (p < 0) a.caller_out[~p] = cpx{V.re, -V.im};
-                else a.caller_out[p] = V;
+            if (valid && t == 0) {
+                if (pcur < 0) a.caller_out[~pcur] = cpx{ar, -ai};
+                else a.caller_out[pcur] = cpx{ar, ai};
             }
             continue;
         }
-        real cr, ci;
+        real cre, cim;
         if (MODE == MODE_OBJ) {
-            const cpx y = a.vis[idx];
-            const real w = a.wgt[idx];
-            const real rr = V.re - y.re, ri = V.im - y.im;
-            if (valid && j == 0) jacc += real(0.5) * w * (rr * rr + ri * ri);
-            cr = w * rr;
-            ci = w * ri;
+            const real rr = ar - ycur.re, ri = ai - ycur.im;
+            if (valid && t == 0) jacc += real(0.5) * wcur * (rr * rr + ri * ri);
+            cre = wcur * rr;
+            cim = wcur * ri;
         } else {
-            const int64_t p = a.perm[idx];
-            cpx y = a.caller_in[p < 0 ? ~p : p];
-            if (p < 0) y.im = -y.im;
-            const real w = a.wgt[idx];
-            cr = w * y.re;
-            ci = w * y.im;
+            cpx y = a.caller_in[pcur < 0 ? ~pcur : pcur];
+            if (pcur < 0) y.im = -y.im;
+            cre = wcur * y.re;
+            cim = wcur * y.im;
         }
-        if (valid && j < W) {
-            cr *= wxj;
-            ci *= wxj;
-            cpx *col = Hm + iy * ldw + ix + j;
+        if (colok && valid) {
+            cre *= wxj;
+            cim *= wxj;
+            cpx *col = Hm + (iy + h) * ldw + ix + j;
 #pragma unroll
-            for (int i = 0; i < W; ++i) {
-                atomicAdd(&col[i * ldw].re, cr * wy[i]);
-                atomicAdd(&col[i * ldw].im, ci * wy[i]);
+            for (int k = 0; k < NR; ++k) {
+                const int i = h + S * k;
+                if (S == 1 || i < W) {
+                    const real wyi = (S == 2) ? (h ? wy[(2 * k + 1) < W ? 2 * k + 1 : 0] : wy[2 * k]) : wy[k];
+                    atomicAdd(&col[S * k * ldw].re, cre * wyi);
+                    atomicAdd(&col[S * k * ldw].im, cim * wyi);
+                }
             }
         }
     }
     if (MODE == MODE_FWD) return;
     __syncthreads();
-    cpx *S = a.slots + (int64_t)wi.slot * g.win_stride;
+    cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride; // column-major window
     for (int e = tid; e < win * win; e += blockDim.x) {
-        const int r = e / win, cc = e - (e / win) * win;
+        const int cc = e / win, r = e - (e / win) * win;
         real sr = real(0), si = real(0);
         for (int w = 0; w < nwave; ++w) {
-            const cpx h = Hw[w * wsz + r * ldw + cc];
-            sr += h.re;
-            si += h.im;
+            const cpx hh = Hw[w * wsz + r * ldw + cc];
+            sr += hh.re;
+            si += hh.im;
         }
-        S[e] = cpx{sr, si};
+        Sl[e] = cpx{sr, si};
     }
     if (MODE == MODE_OBJ) {
         double d = (double)jacc;
@@ -412,9 +485,9 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         if (lane == 0) red[wave] = d;
         __syncthreads();
         if (tid == 0) {
-            double s = 0.0;
-            for (int w = 0; w < nwave; ++w) s += red[w];
-            a.jpart[blockIdx.x] = s;
+            double sacc = 0.0;
+            for (int w = 0; w < nwave; ++w) sacc += red[w];
+            a.jpart[blockIdx.x] = sacc;
         }
     }
 }
@@ -435,7 +508,7 @@ __device__ __forceinline__ cpx ext_cell(const Geom &g, const int32_t *__restrict
             const int tile = ty * g.ntx + tx;
             const int s1 = ts[tile + 1];
             for (int s = ts[tile]; s < s1; ++s) {
-                const cpx h = slots[(int64_t)s * g.win_stride + lr * g.win + lc];
+                const cpx h = slots[(int64_t)s * g.win_stride + lc * g.win + lr];
                 sr += h.re;
                 si += h.im;
             }
@@ -465,7 +538,7 @@ __global__ __launch_bounds__(NT) void k_fold(Geom g, const int32_t *__restrict__
     const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
     const int item = blockIdx.y;
     if (idx >= (int64_t)g.nf * g.rw) return;
-    const int t1 = (int)(idx / g.rw), t2 = (int)(idx - (idx / g.rw) * g.rw);
+    const int t2 = (int)(idx / g.nf), t1 = (int)(idx - (idx / g.nf) * g.nf); // column-major
     const int32_t *ts = tslot + (int64_t)item * (g.nty * g.ntx + 1);
     const cpx h = periodic_cell(g, ts, slots, t1, t2);
     const cpx m = periodic_cell(g, ts, slots, (g.nf - t1) & (g.nf - 1), (g.nf - t2) & (g.nf - 1));
@@ -473,19 +546,18 @@ __global__ __launch_bounds__(NT) void k_fold(Geom g, const int32_t *__restrict__
 }
 
 // ------------------------------------------------------------ adjoint column pass
-template <int LOGN>
+template <int LOGN, int CB>
 __global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ hs,
                                                 const cpx *__restrict__ tw, cpx *__restrict__ R) {
     constexpr int N = 1 << LOGN;
-    constexpr int CB = col_batch<LOGN>();
     __shared__ cpx buf[CB * N];
     const int tid = threadIdx.x;
     const int item = blockIdx.y;
     const int c0 = blockIdx.x * CB;
     const cpx *H = hs + (int64_t)item * g.hs_stride;
     for (int e = tid; e < N * CB; e += NT) {
-        const int t1 = e / CB, cc = e - (e / CB) * CB;
-        buf[e] = (c0 + cc < g.rw) ? H[(int64_t)t1 * g.rw + c0 + cc] : cpx{0, 0};
+        const int cc = e / N, t1 = e - (e / N) * N;
+        buf[t1 * CB + cc] = (c0 + cc < g.rw) ? H[(int64_t)(c0 + cc) * N + t1] : cpx{0, 0};
     }
     __syncthreads();
     fft_lds<LOGN, CB, true>(buf, tw);
@@ -745,18 +817,41 @@ hipError_t launch_image_rows(const Geom &g, const real *sky, const real *beams, 
     return hipGetLastError();
 }
 
+// Columns per block: as wide as the LDS allows for coalesced row segments, but narrow
+// enough that the launch has about two blocks per compute unit.
+template <int LOGN> static int pick_cb(const Geom &g) {
+    int cb = col_batch<LOGN>();
+    while (cb > 1 && (int64_t)((g.rw + cb - 1) / cb) * n_items(g) < 512) cb >>= 1;
+    return cb;
+}
+
+#define IVX_CB_SWITCH(CBV, ...)                                                   \
+    switch (CBV) {                                                                \
+    case 1: { constexpr int B = 1; __VA_ARGS__; } break;                          \
+    case 2: { constexpr int B = 2 <= col_batch<L>() ? 2 : 1; __VA_ARGS__; } break;   \
+    case 4: { constexpr int B = 4 <= col_batch<L>() ? 4 : 1; __VA_ARGS__; } break;   \
+    case 8: { constexpr int B = 8 <= col_batch<L>() ? 8 : 1; __VA_ARGS__; } break;   \
+    default: { constexpr int B = 16 <= col_batch<L>() ? 16 : 1; __VA_ARGS__; } break; \
+    }
+
 hipError_t launch_col_fwd(const Geom &g, const cpx *R, const cpx *tw, cpx *ext, hipStream_t st) {
     IVX_LOGN_SWITCH(g.logn, {
-        dim3 grid((g.rw + col_batch<L>() - 1) / col_batch<L>(), n_items(g));
-        k_col_fwd<L><<<grid, NT, 0, st>>>(g, R, tw, ext);
+        const int cb = pick_cb<L>(g);
+        IVX_CB_SWITCH(cb, {
+            dim3 grid((g.rw + B - 1) / B, n_items(g));
+            k_col_fwd<L, B><<<grid, NT, 0, st>>>(g, R, tw, ext);
+        });
     });
     return hipGetLastError();
 }
 
 hipError_t launch_col_inv(const Geom &g, const cpx *hs, const cpx *tw, cpx *R, hipStream_t st) {
     IVX_LOGN_SWITCH(g.logn, {
-        dim3 grid((g.rw + col_batch<L>() - 1) / col_batch<L>(), n_items(g));
-        k_col_inv<L><<<grid, NT, 0, st>>>(g, hs, tw, R);
+        const int cb = pick_cb<L>(g);
+        IVX_CB_SWITCH(cb, {
+            dim3 grid((g.rw + B - 1) / B, n_items(g));
+            k_col_inv<L, B><<<grid, NT, 0, st>>>(g, hs, tw, R);
+        });
     });
     return hipGetLastError();
 }
@@ -776,28 +871,45 @@ template <int W>
 static hipError_t launch_grid_w(int mode, const GridArgs &a, int n_work, hipStream_t st) {
     const size_t wsz = (size_t)a.g.win * a.g.ldw * sizeof(cpx);
     const int threads = 64 * a.nwave;
-    size_t lds;
     switch (mode) {
-    case MODE_OBJ:
-        lds = (1 + a.nwave) * wsz;
-        if (hipFuncSetAttribute((const void *)k_grid<W, MODE_OBJ>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-            return hipGetLastError();
-        k_grid<W, MODE_OBJ><<<n_work, threads, lds, st>>>(a);
-        break;
-    case MODE_FWD:
-        lds = wsz;
-        if (hipFuncSetAttribute((const void *)k_grid<W, MODE_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-            return hipGetLastError();
-        k_grid<W, MODE_FWD><<<n_work, threads, lds, st>>>(a);
-        break;
-    default:
-        lds = a.nwave * wsz;
-        if (hipFuncSetAttribute((const void *)k_grid<W, MODE_ADJ>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-            return hipGetLastError();
-        k_grid<W, MODE_ADJ><<<n_work, threads, lds, st>>>(a);
-        break;
+    case MODE_OBJ: k_grid<W, MODE_OBJ><<<n_work, threads, (1 + a.nwave) * wsz, st>>>(a); break;
+    case MODE_FWD: k_grid<W, MODE_FWD><<<n_work, threads, wsz, st>>>(a); break;
+    default: k_grid<W, MODE_ADJ><<<n_work, threads, a.nwave * wsz, st>>>(a); break;
     }
     return hipGetLastError();
+}
+
+template <int W> static hipError_t prepare_grid_w(const Geom &g, int nwave) {
+    // same limits as launch_grid_w, set ahead of any stream capture
+    hipError_t e;
+    for (int mode = 0; mode < 3; ++mode) {
+        const size_t wsz = (size_t)g.win * g.ldw * sizeof(cpx);
+        const size_t lds = mode == MODE_OBJ ? (1 + nwave) * wsz : (mode == MODE_FWD ? wsz : nwave * wsz);
+        if (mode == MODE_OBJ) e = hipFuncSetAttribute((const void *)k_grid<W, MODE_OBJ>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        else if (mode == MODE_FWD) e = hipFuncSetAttribute((const void *)k_grid<W, MODE_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        else e = hipFuncSetAttribute((const void *)k_grid<W, MODE_ADJ>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t prepare_grid(const Geom &g, int nwave) {
+    switch (g.W) {
+    case 4: return prepare_grid_w<4>(g, nwave);
+    case 5: return prepare_grid_w<5>(g, nwave);
+    case 6: return prepare_grid_w<6>(g, nwave);
+    case 7: return prepare_grid_w<7>(g, nwave);
+    case 8: return prepare_grid_w<8>(g, nwave);
+    case 9: return prepare_grid_w<9>(g, nwave);
+    case 10: return prepare_grid_w<10>(g, nwave);
+    case 11: return prepare_grid_w<11>(g, nwave);
+    case 12: return prepare_grid_w<12>(g, nwave);
+    case 13: return prepare_grid_w<13>(g, nwave);
+    case 14: return prepare_grid_w<14>(g, nwave);
+    case 15: return prepare_grid_w<15>(g, nwave);
+    case 16: return prepare_grid_w<16>(g, nwave);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
