@@ -48,7 +48,7 @@ EXPORTS = ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_fo
            "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_last_error", "ivx_version",
            "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph")
 
-STAGES = ("image_rows", "col_fwd", "grid", "fold", "col_inv", "row_inv", "sd", "sky", "final")
+STAGES = ("image_rows", "col_fwd", "grid", "col_inv", "row_inv", "sd", "sky")
 
 _LIBS = {}
 

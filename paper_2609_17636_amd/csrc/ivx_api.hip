@@ -137,7 +137,8 @@ struct ivx_plan {
     int64_t *d_perm = nullptr;
     WorkItem *d_work = nullptr;
     int32_t *d_tslot = nullptr;
-    cpx *d_R = nullptr, *d_ext = nullptr, *d_slots = nullptr, *d_hs = nullptr;
+    cpx *d_R = nullptr, *d_ext = nullptr, *d_slots = nullptr;
+    unsigned int *d_ticket = nullptr;
     real *d_gp = nullptr;
     int32_t *d_cptr = nullptr;
     CsrEnt *d_cent = nullptr;
@@ -159,6 +160,7 @@ struct ivx_plan {
     hipGraphExec_t gexec = nullptr;
     const void *g_sky = nullptr;
     void *g_grad = nullptr;
+    double *g_terms = nullptr;
     int64_t graph_nodes = 0;
 };
 
@@ -185,6 +187,7 @@ void drop_graph(ivx_plan *p) {
     p->gexec = nullptr;
     p->g_sky = nullptr;
     p->g_grad = nullptr;
+    p->g_terms = nullptr;
     p->graph_nodes = 0;
 }
 
@@ -202,7 +205,8 @@ void free_all(ivx_plan *p) {
     p->d_perm = nullptr;
     p->d_work = nullptr;
     p->d_tslot = nullptr;
-    p->d_R = p->d_ext = p->d_slots = p->d_hs = nullptr;
+    p->d_R = p->d_ext = p->d_slots = nullptr;
+    p->d_ticket = nullptr;
     p->d_gp = nullptr;
     p->d_cptr = nullptr;
     p->d_cent = nullptr;
@@ -247,14 +251,22 @@ bool tile_fits(const ivx_plan *p, int T, int nwave) {
     g.T = T;
     g.win = T + g.W - 1;
     g.ldw = pick_ldw(g.win);
-    return grid_lds_bytes(g, nwave) <= 65536;
+    return grid_lds_bytes(g, nwave) <= 80 * 1024; // two blocks per 160 KB compute unit
 }
 
-int auto_tile(const ivx_plan *p) {
-    const int cand[] = {64, 48, 40, 32, 24, 16, 12, 8};
-    for (int T : cand)
-        if (tile_fits(p, T, p->nwave)) return T;
-    return 0;
+// Default blocking: the widest block (4 waves) and a 16-cell tile when they fit the LDS
+// budget, else fewer waves, else other tile edges.  ivx_autotune refines it by timing.
+bool auto_blocking(ivx_plan *p) {
+    const int waves[] = {4, 2, 1};
+    const int cand[] = {16, 24, 12, 32, 8};
+    for (int nw : waves)
+        for (int T : cand)
+            if (tile_fits(p, T, nw)) {
+                p->nwave = nw;
+                set_tile(p, T);
+                return true;
+            }
+    return false;
 }
 
 // Build the tile-dependent device data: sorted records, work list, slot CSR.
@@ -381,8 +393,7 @@ ivx_status run_forward_half(ivx_plan *p, const real *sky, hipStream_t st) {
 
 ivx_status run_adjoint_half(ivx_plan *p, hipStream_t st) {
     const Geom &g = p->g;
-    IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_hs, st));
-    IVX_HIP(launch_col_inv(g, p->d_hs, p->d_tw, p->d_R, st));
+    IVX_HIP(launch_col_inv(g, p->d_tslot, p->d_slots, p->d_tw, p->d_R, st));
     IVX_HIP(launch_row_inv(g, p->d_R, p->d_beams, p->d_fscale, p->d_dq, p->d_tw, p->d_gp, st));
     return IVX_OK;
 }
@@ -420,7 +431,7 @@ struct StageTimer {
     }
 };
 
-ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, hipStream_t st) {
+ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *terms_dev, hipStream_t st) {
     const Geom &g = p->g;
     if (p->timing_mask) p->timed_evals++;
     {
@@ -437,12 +448,8 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, hipStream_t 
                             p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, st));
     }
     {
-        StageTimer t(p, st, IVX_STAGE_FOLD);
-        IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_hs, st));
-    }
-    {
         StageTimer t(p, st, IVX_STAGE_COL_INV);
-        IVX_HIP(launch_col_inv(g, p->d_hs, p->d_tw, p->d_R, st));
+        IVX_HIP(launch_col_inv(g, p->d_tslot, p->d_slots, p->d_tw, p->d_R, st));
     }
     {
         StageTimer t(p, st, IVX_STAGE_ROW_INV);
@@ -459,12 +466,9 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, hipStream_t 
         StageTimer t(p, st, IVX_STAGE_SKY);
         IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r,
                            sd ? (real)p->d.lambda_s : real(0), p->d_E, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride,
-                           p->d.sd_offset, grad, p->d_rpart, false, st));
-    }
-    {
-        StageTimer t(p, st, IVX_STAGE_FINAL);
-        IVX_HIP(launch_final(p->d_jpart, p->n_work, p->d_rpart, p->n_rpart, p->d_kpart, sd ? p->n_kpart : 0,
-                             p->d.lambda_r, sd ? p->d.lambda_s : 0.0, p->d_terms, st));
+                           p->d.sd_offset, grad, p->d_rpart, false, p->d_jpart, p->n_work, p->d_kpart,
+                           sd ? p->n_kpart : 0, p->d.lambda_r, sd ? p->d.lambda_s : 0.0, p->d_terms, terms_dev,
+                           p->d_ticket, st));
     }
     return IVX_OK;
 }
@@ -552,14 +556,23 @@ ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out) {
     g.beta = (real)p->beta;
     g.r_stride = (int64_t)g.nk * g.rw;
     g.hs_stride = (int64_t)g.nf * g.rw;
-    int T = d->tile;
-    if (T == 0) T = auto_tile(p);
-    if (!tile_fits(p, T, p->nwave)) {
+    p->tile_fixed = d->tile;
+    bool ok = false;
+    if (d->tile == 0) {
+        ok = auto_blocking(p);
+    } else {
+        for (int nw : {4, 2, 1})
+            if (tile_fits(p, d->tile, nw)) {
+                p->nwave = nw;
+                set_tile(p, d->tile);
+                ok = true;
+                break;
+            }
+    }
+    if (!ok) {
         delete p;
         return fail(IVX_EINVAL, "tile must be >= kernel_width and fit the LDS");
     }
-    p->tile_fixed = d->tile;
-    set_tile(p, T);
     // deapodization 1 / phi_hat(2 pi p / nf) for p = a - n/2, a in [0, n)
     std::vector<double> gx, gw;
     gauss_legendre(std::max(64, 8 * W), gx, gw);
@@ -738,7 +751,14 @@ ivx_status ivx_plan_set_data(ivx_plan *p, const ivx_real *uv, const ivx_real *vi
     if ((s = dalloc(p, &p->d_beams, h_beams.size())) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_interp, h_interp.size())) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_R, (size_t)n_items * g.r_stride)) != IVX_OK) goto fail_free;
-    if ((s = dalloc(p, &p->d_hs, (size_t)n_items * g.hs_stride)) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_ticket, 1)) != IVX_OK) goto fail_free;
+    {
+        hipError_t e = hipMemset(p->d_ticket, 0, sizeof(unsigned int));
+        if (e != hipSuccess) {
+            s = hip_fail(e, "hipMemset (ticket)");
+            goto fail_free;
+        }
+    }
     if ((s = dalloc(p, &p->d_gp, (size_t)n_items * nk2)) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_terms, 4)) != IVX_OK) goto fail_free;
     p->n_rpart = sky_blocks(g);
@@ -833,12 +853,22 @@ ivx_status ivx_objective_grad(ivx_plan *p, const ivx_real *sky, ivx_real *grad, 
     if (s != IVX_OK) return s;
     if (!sky || !grad) return fail(IVX_EINVAL, "sky and grad are required");
     hipStream_t st = (hipStream_t)stream;
+    // device `terms` is written by the last kernel itself; host `terms` gets a copy
+    double *terms_dev = nullptr;
+    if (terms) {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, terms) == hipSuccess) {
+            if (attr.type == hipMemoryTypeDevice) terms_dev = terms;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     if (p->use_graph && p->timing_mask == 0) {
-        if (!(p->gexec && p->g_sky == sky && p->g_grad == grad)) {
+        if (!(p->gexec && p->g_sky == sky && p->g_grad == grad && p->g_terms == terms_dev)) {
             drop_graph(p);
             if (!p->cap_stream) IVX_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
             IVX_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-            ivx_status cs = eval_objective(p, sky, grad, p->cap_stream);
+            ivx_status cs = eval_objective(p, sky, grad, terms_dev, p->cap_stream);
             hipGraph_t graph = nullptr;
             hipError_t ee = hipStreamEndCapture(p->cap_stream, &graph);
             if (cs != IVX_OK) {
@@ -856,21 +886,16 @@ ivx_status ivx_objective_grad(ivx_plan *p, const ivx_real *sky, ivx_real *grad, 
             }
             p->g_sky = sky;
             p->g_grad = grad;
+            p->g_terms = terms_dev;
             p->graph_nodes = (int64_t)nn;
         }
         IVX_HIP(hipGraphLaunch(p->gexec, st));
     } else {
-        if ((s = eval_objective(p, sky, grad, st)) != IVX_OK) return s;
+        if ((s = eval_objective(p, sky, grad, terms_dev, st)) != IVX_OK) return s;
     }
-    if (terms) {
-        IVX_HIP(hipMemcpyAsync(terms, p->d_terms, 4 * sizeof(double), hipMemcpyDefault, st));
-        hipPointerAttribute_t attr;
-        bool device = false;
-        if (hipPointerGetAttributes(&attr, terms) == hipSuccess)
-            device = attr.type == hipMemoryTypeDevice;
-        else
-            (void)hipGetLastError();
-        if (!device) IVX_HIP(hipStreamSynchronize(st));
+    if (terms && !terms_dev) {
+        IVX_HIP(hipMemcpyAsync(terms, p->d_terms, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        IVX_HIP(hipStreamSynchronize(st));
     }
     return IVX_OK;
 }
@@ -896,7 +921,7 @@ ivx_status ivx_adjoint(ivx_plan *p, const ivx_real *vis, ivx_real *image, void *
                         p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave, st));
     if ((s = run_adjoint_half(p, st)) != IVX_OK) return s;
     IVX_HIP(launch_sky(p->g, image, p->d_gp, p->d_cptr, p->d_cent, real(0), real(0), nullptr, nullptr, 0, 0, 1, 0,
-                       image, p->d_rpart, true, st));
+                       image, p->d_rpart, true, nullptr, 0, nullptr, 0, 0.0, 0.0, p->d_terms, nullptr, p->d_ticket, st));
     return IVX_OK;
 }
 
@@ -906,8 +931,8 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     hipStream_t st = (hipStream_t)stream;
     struct Cand { int T, nwave, chunk; };
     std::vector<Cand> cands;
-    const int tiles[] = {16, 24, 32, 40, 48};
-    const int waves[] = {4, 2};
+    const int tiles[] = {8, 12, 16, 24, 32};
+    const int waves[] = {4, 2, 1};
     const int chunks[] = {256, 512, 1024};
     for (int T : tiles)
         for (int nw : waves)
@@ -938,7 +963,7 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
             IVX_HIP(hipEventRecord(e0, st));
             IVX_HIP(launch_grid(MODE_OBJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm,
                                 p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, st));
-            IVX_HIP(launch_fold(p->g, p->d_tslot, p->d_slots, p->d_hs, st));
+            IVX_HIP(launch_col_inv(p->g, p->d_tslot, p->d_slots, p->d_tw, p->d_R, st));
             IVX_HIP(hipEventRecord(e1, st));
             IVX_HIP(hipEventSynchronize(e1));
             IVX_HIP(hipEventElapsedTime(&ms, e0, e1));

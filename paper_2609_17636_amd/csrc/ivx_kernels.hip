@@ -243,10 +243,19 @@ __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ 
 }
 
 // ------------------------------------------------------------------- gridding kernel
-__device__ __forceinline__ real es_kernel(real z, real inv_half_w, real beta) {
+// phi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1)).  In the float build the exponential is
+// taken as exp2 of a prescaled argument (v_exp_f32, v_sqrt_f32): an argument error d
+// changes phi by phi * d, and phi * |argument| never exceeds 1/e, so the absolute error
+// stays at the rounding level of the peak weight.  beta2 = beta (double build) or
+// beta * log2(e) (float build).
+__device__ __forceinline__ real es_kernel(real z, real inv_half_w, real beta2) {
     const real t = z * inv_half_w;
     const real q = real(1) - t * t;
-    return exp(beta * (sqrt(q > real(0) ? q : real(0)) - real(1)));
+#ifdef IVX_REAL_DOUBLE
+    return exp(beta2 * (sqrt(q > real(0) ? q : real(0)) - real(1)));
+#else
+    return __builtin_amdgcn_exp2f(beta2 * (__builtin_amdgcn_sqrtf(q > 0.f ? q : 0.f) - 1.f));
+#endif
 }
 
 __device__ __forceinline__ void decode(const VisCoord &v, int &ix, int &iy, real &fx, real &fy) {
@@ -289,54 +298,66 @@ template <int CTRL> __device__ __forceinline__ double dpp(double v) {
     r.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, r);
 }
-// sum over the 16 lanes of the row, returned in every lane (xor 1, xor 2, half mirror, mirror)
-__device__ __forceinline__ real row_sum16(real v) {
-    v += dpp<0xB1>(v);
-    v += dpp<0x4E>(v);
-    v += dpp<0x141>(v);
-    v += dpp<0x140>(v);
-    return v;
-}
 template <int L> __device__ __forceinline__ real row_bcast(real v) { return dpp<0x150 + L>(v); }
-__device__ __forceinline__ real row_shr8(real v) { return dpp<0x118>(v); }
 
-template <int W> struct Taps {
-    // lane t of a 16-lane group owns footprint column j and rows h, h + S, h + 2S, ...
-    static constexpr int S = (W <= 8) ? 2 : 1;
-    static constexpr int NR = (W + S - 1) / S;
+// Lanes per visibility: 8 for W <= 8 (lane j owns footprint column j, all W rows), else 16
+// (lane j < W owns column j).
+template <int W> struct Lanes {
+    static constexpr int G = (W <= 8) ? 8 : 16;
 };
 
-template <int W, int I> struct BcastAll {
-    __device__ __forceinline__ static void run(real v, real *out) {
-        out[I] = row_bcast<(W <= 8 ? 8 : 0) + I>(v);
-        BcastAll<W, I + 1>::run(v, out);
+// Broadcast of the W row weights of the lane's own group.  16-lane groups: lane I of the
+// row holds weight I.  8-lane groups (two per DPP row): lane I of each half holds weight I,
+// so both halves are broadcast and each lane keeps its own half's value.
+template <int W, int G, int I> struct Gather {
+    __device__ __forceinline__ static void run(real v, bool upper, real *out) {
+        if constexpr (G == 16) {
+            out[I] = row_bcast<I>(v);
+        } else {
+            const real lo = row_bcast<I>(v), hi = row_bcast<8 + I>(v);
+            out[I] = upper ? hi : lo;
+        }
+        Gather<W, G, I + 1>::run(v, upper, out);
     }
 };
-template <int W> struct BcastAll<W, W> {
-    __device__ __forceinline__ static void run(real, real *) {}
+template <int W, int G> struct Gather<W, G, W> {
+    __device__ __forceinline__ static void run(real, bool, real *) {}
 };
 
+// sum over the lanes of the group, returned in every lane of the group
+template <int G> __device__ __forceinline__ real group_sum(real v) {
+    v += dpp<0xB1>(v);  // quad xor 1
+    v += dpp<0x4E>(v);  // quad xor 2
+    v += dpp<0x141>(v); // half-row mirror: the other quad of the 8
+    if constexpr (G == 16) v += dpp<0x140>(v); // row mirror: the other half
+    return v;
+}
+
 // One block per work item (a fine-grid tile, or a chunk of one).  The block's waves split
-// into 16-lane groups; group g walks its own contiguous segment of the tile's visibility
-// list, so the four groups of a wave work on visibilities taken far apart along the
-// baseline tracks (their footprints rarely coincide).  In a group, lane t owns footprint
-// column j and a set of rows; the 2W kernel weights are computed once per group (one per
-// lane) and moved across lanes with DPP row broadcasts; the degridded value is a DPP row
-// sum.  Spreading adds into the wave's own LDS accumulator (LDS atomics resolve the rare
-// coincidences between the four groups); the window is summed over waves in a fixed
-// order, so the result does not depend on scheduling.
+// into groups of G lanes; group g walks its own contiguous segment of the tile's
+// visibility list.  In a group, lane j owns footprint column j (all W rows): it evaluates
+// the kernel weights of column j along x and of row j along y, the row weights of the
+// group reach every lane through DPP row broadcasts, and the degridded value is a DPP
+// group sum, so no cross-lane traffic touches the LDS.  Every group spreads into its own
+// LDS accumulator window with plain read-modify-write (the lanes of a group own distinct
+// cells and no other group writes there): no atomics.  The windows are summed in a fixed
+// order at the end, so results do not depend on scheduling.
+// LDS: F window (unless MODE_ADJ) + one accumulator window per group (unless MODE_FWD).
 template <int W, int MODE>
 __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[NT / 64];
+    constexpr int G = Lanes<W>::G;
+    constexpr int GPW = 64 / G; // groups per wave
     const Geom &g = a.g;
     const int win = g.win, ldw = g.ldw;
     const int wsz = win * ldw;
+    const int nwave = a.nwave;
+    const int ngroups = nwave * GPW;
     cpx *Fw = reinterpret_cast<cpx *>(smem_raw);
     cpx *Hw = Fw + (MODE == MODE_ADJ ? 0 : wsz);
     const WorkItem wi = a.work[blockIdx.x];
     const int tid = threadIdx.x;
-    const int nwave = a.nwave;
     if (MODE != MODE_ADJ) {
         const cpx *F = a.ext + (int64_t)wi.item * g.ext_stride + (int64_t)(wi.tx * g.T) * g.eh + wi.ty * g.T;
         for (int e = tid; e < win * win; e += blockDim.x) {
@@ -345,37 +366,42 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         }
     }
     if (MODE != MODE_FWD) {
-        for (int e = tid; e < nwave * wsz; e += blockDim.x) Hw[e] = cpx{0, 0};
+        for (int e = tid; e < ngroups * wsz; e += blockDim.x) Hw[e] = cpx{0, 0};
     }
     __syncthreads();
 
-    constexpr int S = Taps<W>::S, NR = Taps<W>::NR;
     const int lane = tid & 63, wave = tid >> 6;
-    const int t = lane & 15;
-    const int j = (S == 2) ? (t & 7) : t;
-    const int h = (S == 2) ? (t >> 3) : 0;
+    const int j = lane & (G - 1);
+    const bool upper = (G == 8) && (lane & 8);
     const bool colok = j < W;
-    cpx *Hm = Hw + wave * wsz;
+    const int gid = wave * GPW + lane / G;
+    cpx *Hg = Hw + gid * wsz;
     const real inv_hw = real(2) / real(W);
-    const real beta = g.beta;
+#ifdef IVX_REAL_DOUBLE
+    const real beta2 = g.beta;
+#else
+    const real beta2 = g.beta * 1.4426950408889634f;
+#endif
     const real zoff = real(0.5) * real(W) - real(1);
     real jacc = real(0);
 
-    const int ngroups = nwave * 4;
-    const int gid = wave * 4 + (lane >> 4);
     const int seg = (wi.count + ngroups - 1) / ngroups;
     const int v0 = gid * seg;
     const int v1 = min(wi.count, v0 + seg);
+    const VisCoord *crd = a.crd + wi.begin;
+    const cpx *vis = a.vis + wi.begin;
+    const real *wgt = a.wgt + wi.begin;
+    const int64_t *perm = a.perm + wi.begin;
 
     // software pipeline: the record of iteration it+1 is loaded during iteration it
-    auto at = [&](int it) -> int64_t { const int v = v0 + it; return wi.begin + (v < v1 ? v : 0); };
-    VisCoord c_nx = a.crd[at(0)];
+    int vn = v0 < v1 ? v0 : 0;
+    VisCoord c_nx = crd[vn];
     cpx y_nx = cpx{0, 0};
     real w_nx = real(0);
     int64_t p_nx = 0;
-    if (MODE == MODE_OBJ) { y_nx = a.vis[at(0)]; w_nx = a.wgt[at(0)]; }
-    if (MODE == MODE_ADJ) { w_nx = a.wgt[at(0)]; p_nx = a.perm[at(0)]; }
-    if (MODE == MODE_FWD) { p_nx = a.perm[at(0)]; }
+    if (MODE == MODE_OBJ) { y_nx = vis[vn]; w_nx = wgt[vn]; }
+    if (MODE == MODE_ADJ) { w_nx = wgt[vn]; p_nx = perm[vn]; }
+    if (MODE == MODE_FWD) { p_nx = perm[vn]; }
 
     for (int it = 0; it < seg; ++it) {
         const bool valid = v0 + it < v1;
@@ -384,55 +410,39 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         const real wcur = w_nx;
         const int64_t pcur = p_nx;
         if (it + 1 < seg) {
-            const int64_t n1 = at(it + 1);
-            c_nx = a.crd[n1];
-            if (MODE == MODE_OBJ) { y_nx = a.vis[n1]; w_nx = a.wgt[n1]; }
-            if (MODE == MODE_ADJ) { w_nx = a.wgt[n1]; p_nx = a.perm[n1]; }
-            if (MODE == MODE_FWD) { p_nx = a.perm[n1]; }
+            vn = (v0 + it + 1 < v1) ? v0 + it + 1 : 0;
+            c_nx = crd[vn];
+            if (MODE == MODE_OBJ) { y_nx = vis[vn]; w_nx = wgt[vn]; }
+            if (MODE == MODE_ADJ) { w_nx = wgt[vn]; p_nx = perm[vn]; }
+            if (MODE == MODE_FWD) { p_nx = perm[vn]; }
         }
         int ix, iy;
         real fx, fy;
         decode(cr, ix, iy, fx, fy);
-        // kernel weights: one or two evaluations per lane, then spread across the row
-        real wxj, wy[W];
-        if constexpr (S == 2) {
-            const bool isx = t < 8;
-            const int k = t & 7;
-            real mine = real(0);
-            if (k < W) mine = es_kernel(zoff + (isx ? fx : fy) - real(k), inv_hw, beta);
-            const real sh = row_shr8(mine);
-            wxj = isx ? mine : sh;
-            BcastAll<W, 0>::run(mine, wy);
-        } else {
-            real mx = real(0), my = real(0);
-            if (t < W) {
-                mx = es_kernel(zoff + fx - real(t), inv_hw, beta);
-                my = es_kernel(zoff + fy - real(t), inv_hw, beta);
-            }
-            wxj = mx;
-            BcastAll<W, 0>::run(my, wy);
+        real wxj = real(0), wyj = real(0);
+        if (colok) {
+            wxj = es_kernel(zoff + fx - real(j), inv_hw, beta2);
+            wyj = es_kernel(zoff + fy - real(j), inv_hw, beta2);
         }
+        real wy[W];
+        Gather<W, G, 0>::run(wyj, upper, wy);
         if (!valid) wxj = real(0);
+        const int off = iy * ldw + ix + j;
         real ar = real(0), ai = real(0);
         if (MODE != MODE_ADJ) {
-            if (colok && valid) {
-                const cpx *col = Fw + (iy + h) * ldw + ix + j;
+            if (colok) {
 #pragma unroll
-                for (int k = 0; k < NR; ++k) {
-                    const int i = h + S * k;
-                    if (S == 1 || i < W) {
-                        const cpx f = col[S * k * ldw];
-                        const real wyi = (S == 2) ? (h ? wy[(2 * k + 1) < W ? 2 * k + 1 : 0] : wy[2 * k]) : wy[k];
-                        ar += wyi * f.re;
-                        ai += wyi * f.im;
-                    }
+                for (int i = 0; i < W; ++i) {
+                    const cpx f = Fw[off + i * ldw];
+                    ar += wy[i] * f.re;
+                    ai += wy[i] * f.im;
                 }
             }
-            ar = row_sum16(ar * wxj);
-            ai = row_sum16(ai * wxj);
+            ar = group_sum<G>(ar * wxj);
+            ai = group_sum<G>(ai * wxj);
         }
         if (MODE == MODE_FWD) {
-            if (valid && t == 0) {
+            if (valid && j == 0) {
                 if (pcur < 0) a.caller_out[~pcur] = cpx{ar, -ai};
                 else a.caller_out[pcur] = cpx{ar, ai};
             }
@@ -441,27 +451,23 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         real cre, cim;
         if (MODE == MODE_OBJ) {
             const real rr = ar - ycur.re, ri = ai - ycur.im;
-            if (valid && t == 0) jacc += real(0.5) * wcur * (rr * rr + ri * ri);
-            cre = wcur * rr;
-            cim = wcur * ri;
+            if (valid && j == 0) jacc += real(0.5) * wcur * (rr * rr + ri * ri);
+            cre = wcur * rr * wxj;
+            cim = wcur * ri * wxj;
         } else {
             cpx y = a.caller_in[pcur < 0 ? ~pcur : pcur];
             if (pcur < 0) y.im = -y.im;
-            cre = wcur * y.re;
-            cim = wcur * y.im;
+            cre = wcur * y.re * wxj;
+            cim = wcur * y.im * wxj;
         }
-        if (colok && valid) {
-            cre *= wxj;
-            cim *= wxj;
-            cpx *col = Hm + (iy + h) * ldw + ix + j;
+        if (colok) {
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const int i = h + S * k;
-                if (S == 1 || i < W) {
-                    const real wyi = (S == 2) ? (h ? wy[(2 * k + 1) < W ? 2 * k + 1 : 0] : wy[2 * k]) : wy[k];
-                    atomicAdd(&col[S * k * ldw].re, cre * wyi);
-                    atomicAdd(&col[S * k * ldw].im, cim * wyi);
-                }
+            for (int i = 0; i < W; ++i) {
+                cpx *hp = Hg + off + i * ldw;
+                cpx hv = *hp;
+                hv.re += cre * wy[i];
+                hv.im += cim * wy[i];
+                *hp = hv;
             }
         }
     }
@@ -471,8 +477,8 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     for (int e = tid; e < win * win; e += blockDim.x) {
         const int cc = e / win, r = e - (e / win) * win;
         real sr = real(0), si = real(0);
-        for (int w = 0; w < nwave; ++w) {
-            const cpx hh = Hw[w * wsz + r * ldw + cc];
+        for (int q = 0; q < ngroups; ++q) {
+            const cpx hh = Hw[q * wsz + r * ldw + cc];
             sr += hh.re;
             si += hh.im;
         }
@@ -491,6 +497,9 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         }
     }
 }
+
+// Groups per wave for kernel width W (host side, for LDS sizing).
+int grid_groups_per_wave(int W) { return W <= 8 ? 8 : 4; }
 
 // ----------------------------------------------------------------------- fold
 __device__ __forceinline__ cpx ext_cell(const Geom &g, const int32_t *__restrict__ ts,
@@ -533,31 +542,31 @@ __device__ __forceinline__ cpx periodic_cell(const Geom &g, const int32_t *__res
     return s;
 }
 
-__global__ __launch_bounds__(NT) void k_fold(Geom g, const int32_t *__restrict__ tslot,
-                                             const cpx *__restrict__ slots, cpx *__restrict__ hs) {
-    const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
-    const int item = blockIdx.y;
-    if (idx >= (int64_t)g.nf * g.rw) return;
-    const int t2 = (int)(idx / g.nf), t1 = (int)(idx - (idx / g.nf) * g.nf); // column-major
-    const int32_t *ts = tslot + (int64_t)item * (g.nty * g.ntx + 1);
-    const cpx h = periodic_cell(g, ts, slots, t1, t2);
-    const cpx m = periodic_cell(g, ts, slots, (g.nf - t1) & (g.nf - 1), (g.nf - t2) & (g.nf - 1));
-    hs[(int64_t)item * g.hs_stride + idx] = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
-}
-
 // ------------------------------------------------------------ adjoint column pass
+// Reduction of the gridding slots, Hermitian symmetrisation and inverse column FFT in one
+// pass: column t2 of Hs = (H(t1, t2) + conj H(-t1, -t2)) / 2 is gathered straight from the
+// slots covering it (fixed order), transformed, and only the n_sub rows of the sub-image
+// are kept.
 template <int LOGN, int CB>
-__global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ hs,
+__global__ __launch_bounds__(NT) void k_col_inv(Geom g, const int32_t *__restrict__ tslot,
+                                                const cpx *__restrict__ slots,
                                                 const cpx *__restrict__ tw, cpx *__restrict__ R) {
     constexpr int N = 1 << LOGN;
     __shared__ cpx buf[CB * N];
     const int tid = threadIdx.x;
     const int item = blockIdx.y;
     const int c0 = blockIdx.x * CB;
-    const cpx *H = hs + (int64_t)item * g.hs_stride;
+    const int32_t *ts = tslot + (int64_t)item * (g.nty * g.ntx + 1);
     for (int e = tid; e < N * CB; e += NT) {
         const int cc = e / N, t1 = e - (e / N) * N;
-        buf[t1 * CB + cc] = (c0 + cc < g.rw) ? H[(int64_t)(c0 + cc) * N + t1] : cpx{0, 0};
+        const int t2 = c0 + cc;
+        cpx v = cpx{0, 0};
+        if (t2 < g.rw) {
+            const cpx h = periodic_cell(g, ts, slots, t1, t2);
+            const cpx m = periodic_cell(g, ts, slots, (N - t1) & (N - 1), (N - t2) & (N - 1));
+            v = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
+        }
+        buf[t1 * CB + cc] = v;
     }
     __syncthreads();
     fft_lds<LOGN, CB, true>(buf, tw);
@@ -684,6 +693,15 @@ struct SkyArgs {
     real *grad;
     double *rpart;
     int adjoint_only;
+    // final FP64 reduction, done by the last block to finish
+    const double *jpart;
+    int nj;
+    const double *kpart;
+    int nkp;
+    double lambda_r_d, lambda_s_d;
+    double *terms;      // plan-owned, 4 doubles
+    double *terms_user; // optional second destination (device), or null
+    unsigned int *ticket;
 };
 
 __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
@@ -748,49 +766,56 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
         a.grad[(int64_t)c * N * N + p] = gsum;
     }
     if (!a.adjoint_only) {
+        __shared__ double sh[3][NT];
+        __shared__ unsigned int last;
         for (int m = 32; m >= 1; m >>= 1) rloc += __shfl_xor(rloc, m, 64);
         if ((tid & 63) == 0) red[tid >> 6] = rloc;
         __syncthreads();
+        const unsigned int nblk = gridDim.x * gridDim.y * gridDim.z;
         if (tid == 0) {
             double s = 0.0;
             for (int w = 0; w < NT / 64; ++w) s += red[w];
             a.rpart[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+            __threadfence();
+            last = (atomicAdd(a.ticket, 1u) == nblk - 1u) ? 1u : 0u;
+        }
+        __syncthreads();
+        if (last) {
+            // every other block's partial is visible: sum all partials in a fixed order
+            __threadfence();
+            const volatile double *jp = a.jpart;
+            const volatile double *rp = a.rpart;
+            const volatile double *kp = a.kpart;
+            double sj = 0.0, sr = 0.0, sk = 0.0;
+            for (int i = tid; i < a.nj; i += NT) sj += jp[i];
+            for (int i = tid; i < (int)nblk; i += NT) sr += rp[i];
+            for (int i = tid; i < a.nkp; i += NT) sk += kp[i];
+            sh[0][tid] = sj;
+            sh[1][tid] = sr;
+            sh[2][tid] = sk;
+            __syncthreads();
+            for (int w = NT / 2; w >= 1; w >>= 1) {
+                if (tid < w) {
+                    sh[0][tid] += sh[0][tid + w];
+                    sh[1][tid] += sh[1][tid + w];
+                    sh[2][tid] += sh[2][tid + w];
+                }
+                __syncthreads();
+            }
+            if (tid == 0) {
+                const double Q = sh[0][0], R = sh[1][0], K = sh[2][0];
+                const double t4[4] = {Q + a.lambda_s_d * K + a.lambda_r_d * R, Q, K, R};
+                for (int q = 0; q < 4; ++q) {
+                    a.terms[q] = t4[q];
+                    if (a.terms_user) a.terms_user[q] = t4[q];
+                }
+                *a.ticket = 0u; // ready for the next evaluation
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------- reductions
-__global__ __launch_bounds__(NT) void k_final(const double *__restrict__ jpart, int nj,
-                                              const double *__restrict__ rpart, int nr,
-                                              const double *__restrict__ kpart, int nkp,
-                                              double lambda_r, double lambda_s, double *terms) {
-    __shared__ double sh[3][NT];
-    const int tid = threadIdx.x;
-    double sj = 0.0, sr = 0.0, sk = 0.0;
-    for (int i = tid; i < nj; i += NT) sj += jpart[i];
-    for (int i = tid; i < nr; i += NT) sr += rpart[i];
-    for (int i = tid; i < nkp; i += NT) sk += kpart[i];
-    sh[0][tid] = sj;
-    sh[1][tid] = sr;
-    sh[2][tid] = sk;
-    __syncthreads();
-    for (int w = NT / 2; w >= 1; w >>= 1) {
-        if (tid < w) {
-            sh[0][tid] += sh[0][tid + w];
-            sh[1][tid] += sh[1][tid + w];
-            sh[2][tid] += sh[2][tid + w];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const double Q = sh[0][0], R = sh[1][0], K = sh[2][0];
-        terms[0] = Q + lambda_s * K + lambda_r * R;
-        terms[1] = Q;
-        terms[2] = K;
-        terms[3] = R;
-    }
-}
-
 __global__ __launch_bounds__(NT) void k_zero(uint32_t *p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) p[i] = 0u;
 }
@@ -845,12 +870,13 @@ hipError_t launch_col_fwd(const Geom &g, const cpx *R, const cpx *tw, cpx *ext, 
     return hipGetLastError();
 }
 
-hipError_t launch_col_inv(const Geom &g, const cpx *hs, const cpx *tw, cpx *R, hipStream_t st) {
+hipError_t launch_col_inv(const Geom &g, const int32_t *tslot, const cpx *slots, const cpx *tw, cpx *R,
+                          hipStream_t st) {
     IVX_LOGN_SWITCH(g.logn, {
         const int cb = pick_cb<L>(g);
         IVX_CB_SWITCH(cb, {
             dim3 grid((g.rw + B - 1) / B, n_items(g));
-            k_col_inv<L, B><<<grid, NT, 0, st>>>(g, hs, tw, R);
+            k_col_inv<L, B><<<grid, NT, 0, st>>>(g, tslot, slots, tw, R);
         });
     });
     return hipGetLastError();
@@ -864,17 +890,18 @@ hipError_t launch_row_inv(const Geom &g, const cpx *R, const real *beams, const 
 }
 
 size_t grid_lds_bytes(const Geom &g, int nwave) {
-    return (size_t)(1 + nwave) * g.win * g.ldw * sizeof(cpx);
+    return (size_t)(1 + grid_groups_per_wave(g.W) * nwave) * g.win * g.ldw * sizeof(cpx);
 }
 
 template <int W>
 static hipError_t launch_grid_w(int mode, const GridArgs &a, int n_work, hipStream_t st) {
     const size_t wsz = (size_t)a.g.win * a.g.ldw * sizeof(cpx);
     const int threads = 64 * a.nwave;
+    const int ng = grid_groups_per_wave(W) * a.nwave;
     switch (mode) {
-    case MODE_OBJ: k_grid<W, MODE_OBJ><<<n_work, threads, (1 + a.nwave) * wsz, st>>>(a); break;
+    case MODE_OBJ: k_grid<W, MODE_OBJ><<<n_work, threads, (1 + ng) * wsz, st>>>(a); break;
     case MODE_FWD: k_grid<W, MODE_FWD><<<n_work, threads, wsz, st>>>(a); break;
-    default: k_grid<W, MODE_ADJ><<<n_work, threads, a.nwave * wsz, st>>>(a); break;
+    default: k_grid<W, MODE_ADJ><<<n_work, threads, ng * wsz, st>>>(a); break;
     }
     return hipGetLastError();
 }
@@ -884,7 +911,8 @@ template <int W> static hipError_t prepare_grid_w(const Geom &g, int nwave) {
     hipError_t e;
     for (int mode = 0; mode < 3; ++mode) {
         const size_t wsz = (size_t)g.win * g.ldw * sizeof(cpx);
-        const size_t lds = mode == MODE_OBJ ? (1 + nwave) * wsz : (mode == MODE_FWD ? wsz : nwave * wsz);
+        const int ng = grid_groups_per_wave(W) * nwave;
+        const size_t lds = mode == MODE_OBJ ? (1 + ng) * wsz : (mode == MODE_FWD ? wsz : ng * wsz);
         if (mode == MODE_OBJ) e = hipFuncSetAttribute((const void *)k_grid<W, MODE_OBJ>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         else if (mode == MODE_FWD) e = hipFuncSetAttribute((const void *)k_grid<W, MODE_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         else e = hipFuncSetAttribute((const void *)k_grid<W, MODE_ADJ>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -936,13 +964,6 @@ hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work
     }
 }
 
-hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *hs, hipStream_t st) {
-    const int64_t cells = (int64_t)g.nf * g.rw;
-    dim3 grid((unsigned)((cells + NT - 1) / NT), n_items(g));
-    k_fold<<<grid, NT, 0, st>>>(g, tslot, slots, hs);
-    return hipGetLastError();
-}
-
 hipError_t launch_sd_rows(const Geom &g, const real *sky, const real *gB, int rb, int sd_n, int stride,
                           int offset, real *U, hipStream_t st) {
     const int64_t tot = (int64_t)g.C * g.N * sd_n;
@@ -965,17 +986,13 @@ int sky_blocks(const Geom &g) {
 
 hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int32_t *cptr, const CsrEnt *cent,
                       real lambda_r, real lambda_s, const real *E, const real *gB, int rb, int sd_n, int stride,
-                      int offset, real *grad, double *rpart, bool adjoint_only, hipStream_t st) {
+                      int offset, real *grad, double *rpart, bool adjoint_only, const double *jpart, int nj,
+                      const double *kpart, int nkp, double lambda_r_d, double lambda_s_d, double *terms,
+                      double *terms_user, unsigned int *ticket, hipStream_t st) {
     const int nb = (g.N + SKY_T - 1) / SKY_T;
     SkyArgs a{g, sky, gp, cptr, cent, lambda_r, lambda_s, E, gB, rb, sd_n, stride, offset, grad, rpart,
-              adjoint_only ? 1 : 0};
+              adjoint_only ? 1 : 0, jpart, nj, kpart, nkp, lambda_r_d, lambda_s_d, terms, terms_user, ticket};
     k_sky<<<dim3(nb, nb, g.C), NT, 0, st>>>(a);
-    return hipGetLastError();
-}
-
-hipError_t launch_final(const double *jpart, int nj, const double *rpart, int nr, const double *kpart, int nkp,
-                        double lambda_r, double lambda_s, double *terms, hipStream_t st) {
-    k_final<<<1, NT, 0, st>>>(jpart, nj, rpart, nr, kpart, nkp, lambda_r, lambda_s, terms);
     return hipGetLastError();
 }
 
