@@ -155,12 +155,13 @@ enum {
     IVX_STAGE_IMAGE_ROWS = 0, /* reprojection x beam x deapodization + row FFTs */
     IVX_STAGE_COL_FWD = 1,    /* column FFTs -> extended fine grid */
     IVX_STAGE_GRID = 2,       /* degrid, residual, data term, spread (per tile) */
-    IVX_STAGE_COL_INV = 3,    /* slot reduction + Hermitian symmetrisation + inverse column FFTs */
-    IVX_STAGE_ROW_INV = 4,    /* inverse row FFTs x deapodization x beam */
-    IVX_STAGE_SD = 5,         /* single-dish model and residual */
-    IVX_STAGE_SKY = 6,        /* reprojection transpose + Laplacian + single-dish gradient
-                                 + FP64 reduction of the four terms */
-    IVX_NSTAGE = 7
+    IVX_STAGE_FOLD = 3,       /* slot reduction + Hermitian symmetrisation */
+    IVX_STAGE_COL_INV = 4,    /* inverse column FFTs */
+    IVX_STAGE_ROW_INV = 5,    /* inverse row FFTs x deapodization x beam */
+    IVX_STAGE_SD = 6,         /* single-dish model and residual */
+    IVX_STAGE_SKY = 7,        /* reprojection transpose + Laplacian + single-dish gradient */
+    IVX_STAGE_FINAL = 8,      /* FP64 reduction of the four terms */
+    IVX_NSTAGE = 9
 };
 
 /* Device timing of ivx_objective_grad: while stage_mask != 0, each evaluation records a
@@ -173,7 +174,7 @@ ivx_status ivx_stage_times(ivx_plan *plan, double *ms, int64_t *n_eval);
 
 /* Plan facts, host array of 16 int64: {n_fine, kernel_width, tile, n_work_items,
  * n_live_vis, n_slots, device_bytes, n_items, ext_rows, ext_cols, graph_nodes,
- * window, waves_per_block, max_vis_per_work_item, 0, 0}. */
+ * window, waves_per_block, max_vis_per_work_item, lanes_per_visibility, 0}. */
 ivx_status ivx_plan_info(const ivx_plan *plan, int64_t *info16);
 
 /* Release every resource of the plan (NULL is accepted). */

@@ -48,7 +48,7 @@ EXPORTS = ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_fo
            "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_last_error", "ivx_version",
            "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph")
 
-STAGES = ("image_rows", "col_fwd", "grid", "col_inv", "row_inv", "sd", "sky")
+STAGES = ("image_rows", "col_fwd", "grid", "fold", "col_inv", "row_inv", "sd", "sky", "final")
 
 _LIBS = {}
 
@@ -254,7 +254,7 @@ class Plan:
         self._check(self.lib.ivx_plan_info(self._h, a.ctypes.data))
         keys = ["n_fine", "kernel_width", "tile", "n_work_items", "n_live_vis", "n_slots", "device_bytes",
                 "n_items", "ext_rows", "ext_cols", "graph_nodes", "window", "waves_per_block",
-                "chunk"]
+                "chunk", "lanes"]
         return {k: int(v) for k, v in zip(keys, a)}
 
 

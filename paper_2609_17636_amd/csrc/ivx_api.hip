@@ -115,7 +115,8 @@ struct ivx_plan {
     Geom g{};
     double beta = 0.0;
     int nwave = 4;
-    int chunk_max = 512;
+    int lanes = 16;
+    int chunk_max = 256;
     int tile_fixed = 0;
     std::vector<real> dq_host;
     std::vector<cpx> tw_host;
@@ -137,8 +138,7 @@ struct ivx_plan {
     int64_t *d_perm = nullptr;
     WorkItem *d_work = nullptr;
     int32_t *d_tslot = nullptr;
-    cpx *d_R = nullptr, *d_ext = nullptr, *d_slots = nullptr;
-    unsigned int *d_ticket = nullptr;
+    cpx *d_R = nullptr, *d_ext = nullptr, *d_slots = nullptr, *d_hs = nullptr;
     real *d_gp = nullptr;
     int32_t *d_cptr = nullptr;
     CsrEnt *d_cent = nullptr;
@@ -205,8 +205,7 @@ void free_all(ivx_plan *p) {
     p->d_perm = nullptr;
     p->d_work = nullptr;
     p->d_tslot = nullptr;
-    p->d_R = p->d_ext = p->d_slots = nullptr;
-    p->d_ticket = nullptr;
+    p->d_R = p->d_ext = p->d_slots = p->d_hs = nullptr;
     p->d_gp = nullptr;
     p->d_cptr = nullptr;
     p->d_cent = nullptr;
@@ -245,13 +244,14 @@ void set_tile(ivx_plan *p, int T) {
     g.win_stride = (int64_t)g.win * g.win;
 }
 
-bool tile_fits(const ivx_plan *p, int T, int nwave) {
+bool tile_fits(const ivx_plan *p, int T, int nwave, int lanes) {
     if (T < p->g.W || T > 255) return false;
     Geom g = p->g;
     g.T = T;
     g.win = T + g.W - 1;
     g.ldw = pick_ldw(g.win);
-    return grid_lds_bytes(g, nwave) <= 80 * 1024; // two blocks per 160 KB compute unit
+    if (lanes == 8 && g.W > 8) return false;
+    return grid_lds_bytes(g, nwave, lanes) <= 80 * 1024; // two blocks per 160 KB compute unit
 }
 
 // Default blocking: the widest block (4 waves) and a 16-cell tile when they fit the LDS
@@ -261,8 +261,9 @@ bool auto_blocking(ivx_plan *p) {
     const int cand[] = {16, 24, 12, 32, 8};
     for (int nw : waves)
         for (int T : cand)
-            if (tile_fits(p, T, nw)) {
+            if (tile_fits(p, T, nw, 16)) {
                 p->nwave = nw;
+                p->lanes = 16;
                 set_tile(p, T);
                 return true;
             }
@@ -343,7 +344,7 @@ ivx_status build_bins(ivx_plan *p, hipStream_t st) {
     p->n_work = (int)work.size();
     p->n_slots = slot;
     drop_graph(p); // kernel arguments change with the tiling
-    IVX_HIP(prepare_grid(g, p->nwave));
+    IVX_HIP(prepare_grid(g, p->nwave, p->lanes));
 
     for (void *old : {(void *)p->d_crd, (void *)p->d_vis, (void *)p->d_wgt, (void *)p->d_perm,
                       (void *)p->d_work, (void *)p->d_tslot, (void *)p->d_ext, (void *)p->d_slots,
@@ -393,7 +394,8 @@ ivx_status run_forward_half(ivx_plan *p, const real *sky, hipStream_t st) {
 
 ivx_status run_adjoint_half(ivx_plan *p, hipStream_t st) {
     const Geom &g = p->g;
-    IVX_HIP(launch_col_inv(g, p->d_tslot, p->d_slots, p->d_tw, p->d_R, st));
+    IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_hs, st));
+    IVX_HIP(launch_col_inv(g, p->d_hs, p->d_tw, p->d_R, st));
     IVX_HIP(launch_row_inv(g, p->d_R, p->d_beams, p->d_fscale, p->d_dq, p->d_tw, p->d_gp, st));
     return IVX_OK;
 }
@@ -445,11 +447,15 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
     {
         StageTimer t(p, st, IVX_STAGE_GRID);
         IVX_HIP(launch_grid(MODE_OBJ, g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
-                            p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, st));
+                            p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes, st));
+    }
+    {
+        StageTimer t(p, st, IVX_STAGE_FOLD);
+        IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_hs, st));
     }
     {
         StageTimer t(p, st, IVX_STAGE_COL_INV);
-        IVX_HIP(launch_col_inv(g, p->d_tslot, p->d_slots, p->d_tw, p->d_R, st));
+        IVX_HIP(launch_col_inv(g, p->d_hs, p->d_tw, p->d_R, st));
     }
     {
         StageTimer t(p, st, IVX_STAGE_ROW_INV);
@@ -466,9 +472,12 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
         StageTimer t(p, st, IVX_STAGE_SKY);
         IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r,
                            sd ? (real)p->d.lambda_s : real(0), p->d_E, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride,
-                           p->d.sd_offset, grad, p->d_rpart, false, p->d_jpart, p->n_work, p->d_kpart,
-                           sd ? p->n_kpart : 0, p->d.lambda_r, sd ? p->d.lambda_s : 0.0, p->d_terms, terms_dev,
-                           p->d_ticket, st));
+                           p->d.sd_offset, grad, p->d_rpart, false, st));
+    }
+    {
+        StageTimer t(p, st, IVX_STAGE_FINAL);
+        IVX_HIP(launch_final(p->d_jpart, p->n_work, p->d_rpart, p->n_rpart, p->d_kpart, sd ? p->n_kpart : 0,
+                             p->d.lambda_r, sd ? p->d.lambda_s : 0.0, p->d_terms, terms_dev, st));
     }
     return IVX_OK;
 }
@@ -562,7 +571,7 @@ ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out) {
         ok = auto_blocking(p);
     } else {
         for (int nw : {4, 2, 1})
-            if (tile_fits(p, d->tile, nw)) {
+            if (tile_fits(p, d->tile, nw, 16)) {
                 p->nwave = nw;
                 set_tile(p, d->tile);
                 ok = true;
@@ -647,7 +656,7 @@ ivx_status ivx_plan_info(const ivx_plan *p, int64_t *info) {
     if (!p || !info) return fail(IVX_EINVAL, "plan and info must be non-NULL");
     const Geom &g = p->g;
     const int64_t v[16] = {g.nf, g.W, g.T, p->n_work, p->m_live, p->n_slots, (int64_t)p->dev_bytes,
-                           (int64_t)g.C * g.P, g.eh, g.ew, p->graph_nodes, g.win, p->nwave, p->chunk_max, 0, 0};
+                           (int64_t)g.C * g.P, g.eh, g.ew, p->graph_nodes, g.win, p->nwave, p->chunk_max, p->lanes, 0};
     std::memcpy(info, v, sizeof(v));
     return IVX_OK;
 }
@@ -751,14 +760,7 @@ ivx_status ivx_plan_set_data(ivx_plan *p, const ivx_real *uv, const ivx_real *vi
     if ((s = dalloc(p, &p->d_beams, h_beams.size())) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_interp, h_interp.size())) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_R, (size_t)n_items * g.r_stride)) != IVX_OK) goto fail_free;
-    if ((s = dalloc(p, &p->d_ticket, 1)) != IVX_OK) goto fail_free;
-    {
-        hipError_t e = hipMemset(p->d_ticket, 0, sizeof(unsigned int));
-        if (e != hipSuccess) {
-            s = hip_fail(e, "hipMemset (ticket)");
-            goto fail_free;
-        }
-    }
+    if ((s = dalloc(p, &p->d_hs, (size_t)n_items * g.hs_stride)) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_gp, (size_t)n_items * nk2)) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_terms, 4)) != IVX_OK) goto fail_free;
     p->n_rpart = sky_blocks(g);
@@ -908,7 +910,7 @@ ivx_status ivx_forward(ivx_plan *p, const ivx_real *sky, ivx_real *model_vis, vo
     if ((s = run_forward_half(p, sky, st)) != IVX_OK) return s;
     IVX_HIP(launch_zero(model_vis, p->m_total * 2 * (int64_t)sizeof(real), st));
     IVX_HIP(launch_grid(MODE_FWD, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
-                        p->d_slots, p->d_jpart, nullptr, reinterpret_cast<cpx *>(model_vis), p->nwave, st));
+                        p->d_slots, p->d_jpart, nullptr, reinterpret_cast<cpx *>(model_vis), p->nwave, p->lanes, st));
     return IVX_OK;
 }
 
@@ -918,10 +920,10 @@ ivx_status ivx_adjoint(ivx_plan *p, const ivx_real *vis, ivx_real *image, void *
     if (!image || (!vis && p->m_total > 0)) return fail(IVX_EINVAL, "vis and image are required");
     hipStream_t st = (hipStream_t)stream;
     IVX_HIP(launch_grid(MODE_ADJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
-                        p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave, st));
+                        p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave, p->lanes, st));
     if ((s = run_adjoint_half(p, st)) != IVX_OK) return s;
     IVX_HIP(launch_sky(p->g, image, p->d_gp, p->d_cptr, p->d_cent, real(0), real(0), nullptr, nullptr, 0, 0, 1, 0,
-                       image, p->d_rpart, true, nullptr, 0, nullptr, 0, 0.0, 0.0, p->d_terms, nullptr, p->d_ticket, st));
+                       image, p->d_rpart, true, st));
     return IVX_OK;
 }
 
@@ -929,15 +931,16 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     ivx_status s = check_plan(p);
     if (s != IVX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    struct Cand { int T, nwave, chunk; };
+    struct Cand { int T, nwave, chunk, lanes; };
     std::vector<Cand> cands;
     const int tiles[] = {8, 12, 16, 24, 32};
     const int waves[] = {4, 2, 1};
-    const int chunks[] = {256, 512, 1024};
-    for (int T : tiles)
-        for (int nw : waves)
-            if (tile_fits(p, T, nw))
-                for (int ch : chunks) cands.push_back(Cand{T, nw, ch});
+    const int chunks[] = {128, 256, 512};
+    for (int lanes : {16, 8})
+        for (int T : tiles)
+            for (int nw : waves)
+                if (tile_fits(p, T, nw, lanes))
+                    for (int ch : chunks) cands.push_back(Cand{T, nw, ch, lanes});
     if (cands.empty()) return fail(IVX_EINVAL, "no tile candidate fits");
     // the tiling only changes the gridding stage and the slot reduction: time those two on
     // the plan's own data (zero sky), keep the fastest; the result is accuracy-neutral
@@ -950,9 +953,10 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     IVX_HIP(hipEventCreate(&e1));
     const auto t_start = std::chrono::steady_clock::now();
     double best_ms = 1e300;
-    Cand best{p->g.T, p->nwave, p->chunk_max};
+    Cand best{p->g.T, p->nwave, p->chunk_max, p->lanes};
     for (const Cand &c : cands) {
         p->nwave = c.nwave;
+        p->lanes = c.lanes;
         p->chunk_max = c.chunk;
         set_tile(p, c.T);
         if ((s = build_bins(p, st)) != IVX_OK) break;
@@ -962,8 +966,8 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
         for (int r = 0; r < reps + 1; ++r) {
             IVX_HIP(hipEventRecord(e0, st));
             IVX_HIP(launch_grid(MODE_OBJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm,
-                                p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, st));
-            IVX_HIP(launch_col_inv(p->g, p->d_tslot, p->d_slots, p->d_tw, p->d_R, st));
+                                p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes, st));
+            IVX_HIP(launch_fold(p->g, p->d_tslot, p->d_slots, p->d_hs, st));
             IVX_HIP(hipEventRecord(e1, st));
             IVX_HIP(hipEventSynchronize(e1));
             IVX_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -982,6 +986,7 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     (void)hipFree(sky);
     if (s != IVX_OK) return s;
     p->nwave = best.nwave;
+    p->lanes = best.lanes;
     p->chunk_max = best.chunk;
     set_tile(p, best.T);
     if ((s = build_bins(p, st)) != IVX_OK) return s;

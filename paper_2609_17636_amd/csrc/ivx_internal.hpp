@@ -76,9 +76,11 @@ hipError_t launch_col_fwd(const Geom &g, const cpx *R, const cpx *tw, cpx *ext, 
 hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work,
                        const VisCoord *crd, const cpx *vis, const real *wgt,
                        const int64_t *perm, const cpx *ext, cpx *slots, double *jpart,
-                       const cpx *caller_in, cpx *caller_out, int nwave, hipStream_t st);
-hipError_t launch_col_inv(const Geom &g, const int32_t *tslot, const cpx *slots, const cpx *tw,
-                          cpx *R, hipStream_t st);
+                       const cpx *caller_in, cpx *caller_out, int nwave, int lanes,
+                       hipStream_t st);
+hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *hs,
+                       hipStream_t st);
+hipError_t launch_col_inv(const Geom &g, const cpx *hs, const cpx *tw, cpx *R, hipStream_t st);
 hipError_t launch_row_inv(const Geom &g, const cpx *R, const real *beams, const real *fscale,
                           const real *dq, const cpx *tw, real *gp, hipStream_t st);
 hipError_t launch_sd_rows(const Geom &g, const real *sky, const real *gB, int rb, int sd_n,
@@ -86,24 +88,24 @@ hipError_t launch_sd_rows(const Geom &g, const real *sky, const real *gB, int rb
 hipError_t launch_sd_cols(const Geom &g, const real *U, const real *gB, int rb, int sd_n,
                           int stride, int offset, const real *sdmap, real inv_var, real *E,
                           double *kpart, hipStream_t st);
-// Sky-level pass: reprojection transpose, Laplacian and single-dish gradients; unless
-// adjoint_only, the last block to finish also reduces every partial (data term, Laplacian,
-// single dish) in FP64 and writes {Q_tot, Q, K, R} to terms (and terms_user if non-null).
 hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int32_t *cptr,
                       const CsrEnt *cent, real lambda_r, real lambda_s, const real *E,
                       const real *gB, int rb, int sd_n, int stride, int offset, real *grad,
-                      double *rpart, bool adjoint_only, const double *jpart, int nj,
-                      const double *kpart, int nkp, double lambda_r_d, double lambda_s_d,
-                      double *terms, double *terms_user, unsigned int *ticket, hipStream_t st);
+                      double *rpart, bool adjoint_only, hipStream_t st);
 int sky_blocks(const Geom &g);
+// FP64 reduction of all partials into {Q_tot, Q, K, R} (terms, and terms_user if non-null).
+hipError_t launch_final(const double *jpart, int nj, const double *rpart, int nr,
+                        const double *kpart, int nkp, double lambda_r, double lambda_s,
+                        double *terms, double *terms_user, hipStream_t st);
 hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st);
 
 // Raise the dynamic-LDS limit of the gridding kernels for this geometry (call before any
 // stream capture).
-hipError_t prepare_grid(const Geom &g, int nwave);
+hipError_t prepare_grid(const Geom &g, int nwave, int lanes);
 // Lane groups per wave of the gridding kernel for kernel width W (one LDS accumulator each).
-int grid_groups_per_wave(int W);
+// lanes = 8 (W <= 8 only) or 16 visibility lanes per group.
+int grid_groups_per_wave(int W, int lanes);
 // Dynamic LDS of the gridding kernel (bytes); used to pick tiles.
-size_t grid_lds_bytes(const Geom &g, int nwave);
+size_t grid_lds_bytes(const Geom &g, int nwave, int lanes);
 
 } // namespace ivx

@@ -300,27 +300,38 @@ template <int CTRL> __device__ __forceinline__ double dpp(double v) {
 }
 template <int L> __device__ __forceinline__ real row_bcast(real v) { return dpp<0x150 + L>(v); }
 
-// Lanes per visibility: 8 for W <= 8 (lane j owns footprint column j, all W rows), else 16
-// (lane j < W owns column j).
-template <int W> struct Lanes {
-    static constexpr int G = (W <= 8) ? 8 : 16;
+__device__ __forceinline__ real row_shr8(real v) { return dpp<0x118>(v); }
+
+// Lane layout of a G-lane group (one visibility at a time):
+//   G = 8  (W <= 8): lane j owns footprint column j, all W rows (two groups per DPP row);
+//   G = 16, W <= 8 : lane t owns column t & 7 and every other row starting at t >> 3;
+//   G = 16, W > 8  : lane t < W owns column t, all W rows.
+template <int W, int G> struct Layout {
+    static_assert(G == 16 || W <= 8, "8-lane groups need W <= 8");
+    static constexpr int S = (G == 16 && W <= 8) ? 2 : 1; // row stride of a lane
+    static constexpr int NR = (W + S - 1) / S;            // rows per lane (upper bound)
 };
 
-// Broadcast of the W row weights of the lane's own group.  16-lane groups: lane I of the
-// row holds weight I.  8-lane groups (two per DPP row): lane I of each half holds weight I,
-// so both halves are broadcast and each lane keeps its own half's value.
-template <int W, int G, int I> struct Gather {
-    __device__ __forceinline__ static void run(real v, bool upper, real *out) {
-        if constexpr (G == 16) {
-            out[I] = row_bcast<I>(v);
+// Row weights of the group in every lane: wsel[k] is the weight of the lane's k-th row.
+template <int W, int G, int I> struct RowWeights {
+    __device__ __forceinline__ static void run(real mine, bool upper, real *wsel) {
+        if constexpr (G == 8) {
+            const real lo = row_bcast<I>(mine), hi = row_bcast<8 + I>(mine);
+            wsel[I] = upper ? hi : lo;
+        } else if constexpr (Layout<W, G>::S == 2) {
+            // rows 2k (lanes h = 0) and 2k + 1 (h = 1) come from lanes 8 + 2k and 8 + 2k + 1
+            if constexpr (I % 2 == 0) {
+                const real e0 = row_bcast<8 + I>(mine);
+                const real e1 = (I + 1 < W) ? row_bcast<8 + ((I + 1 < W) ? I + 1 : I)>(mine) : real(0);
+                wsel[I / 2] = upper ? e1 : e0;
+            }
         } else {
-            const real lo = row_bcast<I>(v), hi = row_bcast<8 + I>(v);
-            out[I] = upper ? hi : lo;
+            wsel[I] = row_bcast<I>(mine);
         }
-        Gather<W, G, I + 1>::run(v, upper, out);
+        RowWeights<W, G, I + 1>::run(mine, upper, wsel);
     }
 };
-template <int W, int G> struct Gather<W, G, W> {
+template <int W, int G> struct RowWeights<W, G, W> {
     __device__ __forceinline__ static void run(real, bool, real *) {}
 };
 
@@ -335,19 +346,18 @@ template <int G> __device__ __forceinline__ real group_sum(real v) {
 
 // One block per work item (a fine-grid tile, or a chunk of one).  The block's waves split
 // into groups of G lanes; group g walks its own contiguous segment of the tile's
-// visibility list.  In a group, lane j owns footprint column j (all W rows): it evaluates
-// the kernel weights of column j along x and of row j along y, the row weights of the
-// group reach every lane through DPP row broadcasts, and the degridded value is a DPP
+// visibility list.  Inside a group the kernel weights are evaluated once (one or two per
+// lane) and moved across lanes with DPP row operations, and the degridded value is a DPP
 // group sum, so no cross-lane traffic touches the LDS.  Every group spreads into its own
 // LDS accumulator window with plain read-modify-write (the lanes of a group own distinct
 // cells and no other group writes there): no atomics.  The windows are summed in a fixed
 // order at the end, so results do not depend on scheduling.
 // LDS: F window (unless MODE_ADJ) + one accumulator window per group (unless MODE_FWD).
-template <int W, int MODE>
+template <int W, int MODE, int G>
 __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[NT / 64];
-    constexpr int G = Lanes<W>::G;
+    constexpr int S = Layout<W, G>::S, NR = Layout<W, G>::NR;
     constexpr int GPW = 64 / G; // groups per wave
     const Geom &g = a.g;
     const int win = g.win, ldw = g.ldw;
@@ -371,8 +381,10 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6;
-    const int j = lane & (G - 1);
-    const bool upper = (G == 8) && (lane & 8);
+    const int t = lane & (G - 1);
+    const int j = (S == 2) ? (t & 7) : t;   // footprint column owned
+    const int h = (S == 2) ? (t >> 3) : 0;  // first footprint row owned
+    const bool upper = (lane & 8) != 0;      // second half of the DPP row
     const bool colok = j < W;
     const int gid = wave * GPW + lane / G;
     cpx *Hg = Hw + gid * wsz;
@@ -419,30 +431,44 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         int ix, iy;
         real fx, fy;
         decode(cr, ix, iy, fx, fy);
-        real wxj = real(0), wyj = real(0);
-        if (colok) {
-            wxj = es_kernel(zoff + fx - real(j), inv_hw, beta2);
-            wyj = es_kernel(zoff + fy - real(j), inv_hw, beta2);
+        // kernel weights: x weight of the owned column, y weights of the owned rows
+        real wxj, wsel[NR];
+        if constexpr (G == 16 && S == 2) {
+            const bool isx = t < 8;
+            const int k = t & 7;
+            real mine = real(0);
+            if (k < W) mine = es_kernel(zoff + (isx ? fx : fy) - real(k), inv_hw, beta2);
+            const real sh = row_shr8(mine);
+            wxj = isx ? mine : sh;
+            RowWeights<W, G, 0>::run(mine, upper, wsel);
+        } else {
+            real mx = real(0), my = real(0);
+            if (colok) {
+                mx = es_kernel(zoff + fx - real(j), inv_hw, beta2);
+                my = es_kernel(zoff + fy - real(j), inv_hw, beta2);
+            }
+            wxj = mx;
+            RowWeights<W, G, 0>::run(my, upper, wsel);
         }
-        real wy[W];
-        Gather<W, G, 0>::run(wyj, upper, wy);
         if (!valid) wxj = real(0);
-        const int off = iy * ldw + ix + j;
+        const int off = (iy + h) * ldw + ix + j;
         real ar = real(0), ai = real(0);
         if (MODE != MODE_ADJ) {
             if (colok) {
 #pragma unroll
-                for (int i = 0; i < W; ++i) {
-                    const cpx f = Fw[off + i * ldw];
-                    ar += wy[i] * f.re;
-                    ai += wy[i] * f.im;
+                for (int k = 0; k < NR; ++k) {
+                    if (S == 1 || h + S * k < W) {
+                        const cpx f = Fw[off + S * k * ldw];
+                        ar += wsel[k] * f.re;
+                        ai += wsel[k] * f.im;
+                    }
                 }
             }
             ar = group_sum<G>(ar * wxj);
             ai = group_sum<G>(ai * wxj);
         }
         if (MODE == MODE_FWD) {
-            if (valid && j == 0) {
+            if (valid && t == 0) {
                 if (pcur < 0) a.caller_out[~pcur] = cpx{ar, -ai};
                 else a.caller_out[pcur] = cpx{ar, ai};
             }
@@ -451,7 +477,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         real cre, cim;
         if (MODE == MODE_OBJ) {
             const real rr = ar - ycur.re, ri = ai - ycur.im;
-            if (valid && j == 0) jacc += real(0.5) * wcur * (rr * rr + ri * ri);
+            if (valid && t == 0) jacc += real(0.5) * wcur * (rr * rr + ri * ri);
             cre = wcur * rr * wxj;
             cim = wcur * ri * wxj;
         } else {
@@ -462,12 +488,14 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         }
         if (colok) {
 #pragma unroll
-            for (int i = 0; i < W; ++i) {
-                cpx *hp = Hg + off + i * ldw;
-                cpx hv = *hp;
-                hv.re += cre * wy[i];
-                hv.im += cim * wy[i];
-                *hp = hv;
+            for (int k = 0; k < NR; ++k) {
+                if (S == 1 || h + S * k < W) {
+                    cpx *hp = Hg + off + S * k * ldw;
+                    cpx hv = *hp;
+                    hv.re += cre * wsel[k];
+                    hv.im += cim * wsel[k];
+                    *hp = hv;
+                }
             }
         }
     }
@@ -498,8 +526,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     }
 }
 
-// Groups per wave for kernel width W (host side, for LDS sizing).
-int grid_groups_per_wave(int W) { return W <= 8 ? 8 : 4; }
+int grid_groups_per_wave(int W, int lanes) { return (lanes == 8 && W <= 8) ? 8 : 4; }
 
 // ----------------------------------------------------------------------- fold
 __device__ __forceinline__ cpx ext_cell(const Geom &g, const int32_t *__restrict__ ts,
@@ -543,30 +570,31 @@ __device__ __forceinline__ cpx periodic_cell(const Geom &g, const int32_t *__res
 }
 
 // ------------------------------------------------------------ adjoint column pass
-// Reduction of the gridding slots, Hermitian symmetrisation and inverse column FFT in one
-// pass: column t2 of Hs = (H(t1, t2) + conj H(-t1, -t2)) / 2 is gathered straight from the
-// slots covering it (fixed order), transformed, and only the n_sub rows of the sub-image
-// are kept.
+__global__ __launch_bounds__(NT) void k_fold(Geom g, const int32_t *__restrict__ tslot,
+                                             const cpx *__restrict__ slots, cpx *__restrict__ hs) {
+    const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int item = blockIdx.y;
+    if (idx >= (int64_t)g.nf * g.rw) return;
+    const int t2 = (int)(idx / g.nf), t1 = (int)(idx - (idx / g.nf) * g.nf); // column-major
+    const int32_t *ts = tslot + (int64_t)item * (g.nty * g.ntx + 1);
+    const cpx h = periodic_cell(g, ts, slots, t1, t2);
+    const cpx m = periodic_cell(g, ts, slots, (g.nf - t1) & (g.nf - 1), (g.nf - t2) & (g.nf - 1));
+    hs[(int64_t)item * g.hs_stride + idx] = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
+}
+
+// ------------------------------------------------------------ adjoint column pass
 template <int LOGN, int CB>
-__global__ __launch_bounds__(NT) void k_col_inv(Geom g, const int32_t *__restrict__ tslot,
-                                                const cpx *__restrict__ slots,
+__global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ hs,
                                                 const cpx *__restrict__ tw, cpx *__restrict__ R) {
     constexpr int N = 1 << LOGN;
     __shared__ cpx buf[CB * N];
     const int tid = threadIdx.x;
     const int item = blockIdx.y;
     const int c0 = blockIdx.x * CB;
-    const int32_t *ts = tslot + (int64_t)item * (g.nty * g.ntx + 1);
+    const cpx *H = hs + (int64_t)item * g.hs_stride;
     for (int e = tid; e < N * CB; e += NT) {
         const int cc = e / N, t1 = e - (e / N) * N;
-        const int t2 = c0 + cc;
-        cpx v = cpx{0, 0};
-        if (t2 < g.rw) {
-            const cpx h = periodic_cell(g, ts, slots, t1, t2);
-            const cpx m = periodic_cell(g, ts, slots, (N - t1) & (N - 1), (N - t2) & (N - 1));
-            v = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
-        }
-        buf[t1 * CB + cc] = v;
+        buf[t1 * CB + cc] = (c0 + cc < g.rw) ? H[(int64_t)(c0 + cc) * N + t1] : cpx{0, 0};
     }
     __syncthreads();
     fft_lds<LOGN, CB, true>(buf, tw);
@@ -693,15 +721,6 @@ struct SkyArgs {
     real *grad;
     double *rpart;
     int adjoint_only;
-    // final FP64 reduction, done by the last block to finish
-    const double *jpart;
-    int nj;
-    const double *kpart;
-    int nkp;
-    double lambda_r_d, lambda_s_d;
-    double *terms;      // plan-owned, 4 doubles
-    double *terms_user; // optional second destination (device), or null
-    unsigned int *ticket;
 };
 
 __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
@@ -766,56 +785,51 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
         a.grad[(int64_t)c * N * N + p] = gsum;
     }
     if (!a.adjoint_only) {
-        __shared__ double sh[3][NT];
-        __shared__ unsigned int last;
         for (int m = 32; m >= 1; m >>= 1) rloc += __shfl_xor(rloc, m, 64);
         if ((tid & 63) == 0) red[tid >> 6] = rloc;
         __syncthreads();
-        const unsigned int nblk = gridDim.x * gridDim.y * gridDim.z;
         if (tid == 0) {
             double s = 0.0;
             for (int w = 0; w < NT / 64; ++w) s += red[w];
             a.rpart[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
-            __threadfence();
-            last = (atomicAdd(a.ticket, 1u) == nblk - 1u) ? 1u : 0u;
-        }
-        __syncthreads();
-        if (last) {
-            // every other block's partial is visible: sum all partials in a fixed order
-            __threadfence();
-            const volatile double *jp = a.jpart;
-            const volatile double *rp = a.rpart;
-            const volatile double *kp = a.kpart;
-            double sj = 0.0, sr = 0.0, sk = 0.0;
-            for (int i = tid; i < a.nj; i += NT) sj += jp[i];
-            for (int i = tid; i < (int)nblk; i += NT) sr += rp[i];
-            for (int i = tid; i < a.nkp; i += NT) sk += kp[i];
-            sh[0][tid] = sj;
-            sh[1][tid] = sr;
-            sh[2][tid] = sk;
-            __syncthreads();
-            for (int w = NT / 2; w >= 1; w >>= 1) {
-                if (tid < w) {
-                    sh[0][tid] += sh[0][tid + w];
-                    sh[1][tid] += sh[1][tid + w];
-                    sh[2][tid] += sh[2][tid + w];
-                }
-                __syncthreads();
-            }
-            if (tid == 0) {
-                const double Q = sh[0][0], R = sh[1][0], K = sh[2][0];
-                const double t4[4] = {Q + a.lambda_s_d * K + a.lambda_r_d * R, Q, K, R};
-                for (int q = 0; q < 4; ++q) {
-                    a.terms[q] = t4[q];
-                    if (a.terms_user) a.terms_user[q] = t4[q];
-                }
-                *a.ticket = 0u; // ready for the next evaluation
-            }
         }
     }
 }
 
 // ---------------------------------------------------------------------- reductions
+__global__ __launch_bounds__(NT) void k_final(const double *__restrict__ jpart, int nj,
+                                              const double *__restrict__ rpart, int nr,
+                                              const double *__restrict__ kpart, int nkp,
+                                              double lambda_r, double lambda_s, double *terms,
+                                              double *terms_user) {
+    __shared__ double sh[3][NT];
+    const int tid = threadIdx.x;
+    double sj = 0.0, sr = 0.0, sk = 0.0;
+    for (int i = tid; i < nj; i += NT) sj += jpart[i];
+    for (int i = tid; i < nr; i += NT) sr += rpart[i];
+    for (int i = tid; i < nkp; i += NT) sk += kpart[i];
+    sh[0][tid] = sj;
+    sh[1][tid] = sr;
+    sh[2][tid] = sk;
+    __syncthreads();
+    for (int w = NT / 2; w >= 1; w >>= 1) {
+        if (tid < w) {
+            sh[0][tid] += sh[0][tid + w];
+            sh[1][tid] += sh[1][tid + w];
+            sh[2][tid] += sh[2][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double Q = sh[0][0], R = sh[1][0], K = sh[2][0];
+        const double t4[4] = {Q + lambda_s * K + lambda_r * R, Q, K, R};
+        for (int q = 0; q < 4; ++q) {
+            terms[q] = t4[q];
+            if (terms_user) terms_user[q] = t4[q];
+        }
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_zero(uint32_t *p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) p[i] = 0u;
 }
@@ -870,15 +884,21 @@ hipError_t launch_col_fwd(const Geom &g, const cpx *R, const cpx *tw, cpx *ext, 
     return hipGetLastError();
 }
 
-hipError_t launch_col_inv(const Geom &g, const int32_t *tslot, const cpx *slots, const cpx *tw, cpx *R,
-                          hipStream_t st) {
+hipError_t launch_col_inv(const Geom &g, const cpx *hs, const cpx *tw, cpx *R, hipStream_t st) {
     IVX_LOGN_SWITCH(g.logn, {
         const int cb = pick_cb<L>(g);
         IVX_CB_SWITCH(cb, {
             dim3 grid((g.rw + B - 1) / B, n_items(g));
-            k_col_inv<L, B><<<grid, NT, 0, st>>>(g, tslot, slots, tw, R);
+            k_col_inv<L, B><<<grid, NT, 0, st>>>(g, hs, tw, R);
         });
     });
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *hs, hipStream_t st) {
+    const int64_t cells = (int64_t)g.nf * g.rw;
+    dim3 grid((unsigned)((cells + NT - 1) / NT), n_items(g));
+    k_fold<<<grid, NT, 0, st>>>(g, tslot, slots, hs);
     return hipGetLastError();
 }
 
@@ -889,79 +909,79 @@ hipError_t launch_row_inv(const Geom &g, const cpx *R, const real *beams, const 
     return hipGetLastError();
 }
 
-size_t grid_lds_bytes(const Geom &g, int nwave) {
-    return (size_t)(1 + grid_groups_per_wave(g.W) * nwave) * g.win * g.ldw * sizeof(cpx);
+size_t grid_lds_bytes(const Geom &g, int nwave, int lanes) {
+    return (size_t)(1 + grid_groups_per_wave(g.W, lanes) * nwave) * g.win * g.ldw * sizeof(cpx);
 }
 
-template <int W>
-static hipError_t launch_grid_w(int mode, const GridArgs &a, int n_work, hipStream_t st) {
+template <int W, int G>
+static hipError_t launch_grid_wg(int mode, const GridArgs &a, int n_work, hipStream_t st) {
     const size_t wsz = (size_t)a.g.win * a.g.ldw * sizeof(cpx);
     const int threads = 64 * a.nwave;
-    const int ng = grid_groups_per_wave(W) * a.nwave;
+    const int ng = (64 / G) * a.nwave;
     switch (mode) {
-    case MODE_OBJ: k_grid<W, MODE_OBJ><<<n_work, threads, (1 + ng) * wsz, st>>>(a); break;
-    case MODE_FWD: k_grid<W, MODE_FWD><<<n_work, threads, wsz, st>>>(a); break;
-    default: k_grid<W, MODE_ADJ><<<n_work, threads, ng * wsz, st>>>(a); break;
+    case MODE_OBJ: k_grid<W, MODE_OBJ, G><<<n_work, threads, (1 + ng) * wsz, st>>>(a); break;
+    case MODE_FWD: k_grid<W, MODE_FWD, G><<<n_work, threads, wsz, st>>>(a); break;
+    default: k_grid<W, MODE_ADJ, G><<<n_work, threads, ng * wsz, st>>>(a); break;
     }
     return hipGetLastError();
 }
 
-template <int W> static hipError_t prepare_grid_w(const Geom &g, int nwave) {
-    // same limits as launch_grid_w, set ahead of any stream capture
+template <int W, int G> static hipError_t prepare_grid_wg(const Geom &g, int nwave) {
+    // raise the dynamic-LDS limit of the three modes ahead of any stream capture
+    const size_t wsz = (size_t)g.win * g.ldw * sizeof(cpx);
+    const int ng = (64 / G) * nwave;
     hipError_t e;
-    for (int mode = 0; mode < 3; ++mode) {
-        const size_t wsz = (size_t)g.win * g.ldw * sizeof(cpx);
-        const int ng = grid_groups_per_wave(W) * nwave;
-        const size_t lds = mode == MODE_OBJ ? (1 + ng) * wsz : (mode == MODE_FWD ? wsz : ng * wsz);
-        if (mode == MODE_OBJ) e = hipFuncSetAttribute((const void *)k_grid<W, MODE_OBJ>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        else if (mode == MODE_FWD) e = hipFuncSetAttribute((const void *)k_grid<W, MODE_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        else e = hipFuncSetAttribute((const void *)k_grid<W, MODE_ADJ>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    if ((e = hipFuncSetAttribute((const void *)k_grid<W, MODE_OBJ, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)((1 + ng) * wsz))) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)k_grid<W, MODE_FWD, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)wsz)) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute((const void *)k_grid<W, MODE_ADJ, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(ng * wsz));
 }
 
-hipError_t prepare_grid(const Geom &g, int nwave) {
-    switch (g.W) {
-    case 4: return prepare_grid_w<4>(g, nwave);
-    case 5: return prepare_grid_w<5>(g, nwave);
-    case 6: return prepare_grid_w<6>(g, nwave);
-    case 7: return prepare_grid_w<7>(g, nwave);
-    case 8: return prepare_grid_w<8>(g, nwave);
-    case 9: return prepare_grid_w<9>(g, nwave);
-    case 10: return prepare_grid_w<10>(g, nwave);
-    case 11: return prepare_grid_w<11>(g, nwave);
-    case 12: return prepare_grid_w<12>(g, nwave);
-    case 13: return prepare_grid_w<13>(g, nwave);
-    case 14: return prepare_grid_w<14>(g, nwave);
-    case 15: return prepare_grid_w<15>(g, nwave);
-    case 16: return prepare_grid_w<16>(g, nwave);
+template <int W>
+static hipError_t dispatch_w(bool prepare, int lanes, int mode, const GridArgs &a, int n_work, hipStream_t st) {
+    if constexpr (W <= 8) {
+        if (lanes == 8) return prepare ? prepare_grid_wg<W, 8>(a.g, a.nwave) : launch_grid_wg<W, 8>(mode, a, n_work, st);
+    }
+    return prepare ? prepare_grid_wg<W, 16>(a.g, a.nwave) : launch_grid_wg<W, 16>(mode, a, n_work, st);
+}
+
+static hipError_t dispatch(bool prepare, int lanes, int mode, const GridArgs &a, int n_work, hipStream_t st) {
+    switch (a.g.W) {
+    case 4: return dispatch_w<4>(prepare, lanes, mode, a, n_work, st);
+    case 5: return dispatch_w<5>(prepare, lanes, mode, a, n_work, st);
+    case 6: return dispatch_w<6>(prepare, lanes, mode, a, n_work, st);
+    case 7: return dispatch_w<7>(prepare, lanes, mode, a, n_work, st);
+    case 8: return dispatch_w<8>(prepare, lanes, mode, a, n_work, st);
+    case 9: return dispatch_w<9>(prepare, lanes, mode, a, n_work, st);
+    case 10: return dispatch_w<10>(prepare, lanes, mode, a, n_work, st);
+    case 11: return dispatch_w<11>(prepare, lanes, mode, a, n_work, st);
+    case 12: return dispatch_w<12>(prepare, lanes, mode, a, n_work, st);
+    case 13: return dispatch_w<13>(prepare, lanes, mode, a, n_work, st);
+    case 14: return dispatch_w<14>(prepare, lanes, mode, a, n_work, st);
+    case 15: return dispatch_w<15>(prepare, lanes, mode, a, n_work, st);
+    case 16: return dispatch_w<16>(prepare, lanes, mode, a, n_work, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t prepare_grid(const Geom &g, int nwave, int lanes) {
+    GridArgs a{};
+    a.g = g;
+    a.nwave = nwave;
+    return dispatch(true, lanes, MODE_OBJ, a, 0, nullptr);
 }
 
 hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
                        const cpx *vis, const real *wgt, const int64_t *perm, const cpx *ext, cpx *slots,
-                       double *jpart, const cpx *caller_in, cpx *caller_out, int nwave, hipStream_t st) {
+                       double *jpart, const cpx *caller_in, cpx *caller_out, int nwave, int lanes, hipStream_t st) {
     if (n_work <= 0) return hipSuccess;
     if (nwave < 1 || nwave > NT / 64) return hipErrorInvalidValue;
     GridArgs a{g, work, crd, vis, wgt, perm, ext, slots, jpart, caller_in, caller_out, nwave};
-    switch (g.W) {
-    case 4: return launch_grid_w<4>(mode, a, n_work, st);
-    case 5: return launch_grid_w<5>(mode, a, n_work, st);
-    case 6: return launch_grid_w<6>(mode, a, n_work, st);
-    case 7: return launch_grid_w<7>(mode, a, n_work, st);
-    case 8: return launch_grid_w<8>(mode, a, n_work, st);
-    case 9: return launch_grid_w<9>(mode, a, n_work, st);
-    case 10: return launch_grid_w<10>(mode, a, n_work, st);
-    case 11: return launch_grid_w<11>(mode, a, n_work, st);
-    case 12: return launch_grid_w<12>(mode, a, n_work, st);
-    case 13: return launch_grid_w<13>(mode, a, n_work, st);
-    case 14: return launch_grid_w<14>(mode, a, n_work, st);
-    case 15: return launch_grid_w<15>(mode, a, n_work, st);
-    case 16: return launch_grid_w<16>(mode, a, n_work, st);
-    default: return hipErrorInvalidValue;
-    }
+    return dispatch(false, lanes, mode, a, n_work, st);
 }
 
 hipError_t launch_sd_rows(const Geom &g, const real *sky, const real *gB, int rb, int sd_n, int stride,
@@ -986,13 +1006,17 @@ int sky_blocks(const Geom &g) {
 
 hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int32_t *cptr, const CsrEnt *cent,
                       real lambda_r, real lambda_s, const real *E, const real *gB, int rb, int sd_n, int stride,
-                      int offset, real *grad, double *rpart, bool adjoint_only, const double *jpart, int nj,
-                      const double *kpart, int nkp, double lambda_r_d, double lambda_s_d, double *terms,
-                      double *terms_user, unsigned int *ticket, hipStream_t st) {
+                      int offset, real *grad, double *rpart, bool adjoint_only, hipStream_t st) {
     const int nb = (g.N + SKY_T - 1) / SKY_T;
     SkyArgs a{g, sky, gp, cptr, cent, lambda_r, lambda_s, E, gB, rb, sd_n, stride, offset, grad, rpart,
-              adjoint_only ? 1 : 0, jpart, nj, kpart, nkp, lambda_r_d, lambda_s_d, terms, terms_user, ticket};
+              adjoint_only ? 1 : 0};
     k_sky<<<dim3(nb, nb, g.C), NT, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_final(const double *jpart, int nj, const double *rpart, int nr, const double *kpart, int nkp,
+                        double lambda_r, double lambda_s, double *terms, double *terms_user, hipStream_t st) {
+    k_final<<<1, NT, 0, st>>>(jpart, nj, rpart, nr, kpart, nkp, lambda_r, lambda_s, terms, terms_user);
     return hipGetLastError();
 }
 
