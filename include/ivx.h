@@ -174,7 +174,8 @@ ivx_status ivx_stage_times(ivx_plan *plan, double *ms, int64_t *n_eval);
 
 /* Plan facts, host array of 16 int64: {n_fine, kernel_width, tile, n_work_items,
  * n_live_vis, n_slots, device_bytes, n_items, ext_rows, ext_cols, graph_nodes,
- * window, waves_per_block, max_vis_per_work_item, lanes_per_visibility, 0}. */
+ * window, waves_per_block, max_vis_per_work_item, lanes_per_visibility,
+ * visibilities_per_group_iteration}. */
 ivx_status ivx_plan_info(const ivx_plan *plan, int64_t *info16);
 
 /* Release every resource of the plan (NULL is accepted). */

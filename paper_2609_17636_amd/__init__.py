@@ -254,7 +254,7 @@ class Plan:
         self._check(self.lib.ivx_plan_info(self._h, a.ctypes.data))
         keys = ["n_fine", "kernel_width", "tile", "n_work_items", "n_live_vis", "n_slots", "device_bytes",
                 "n_items", "ext_rows", "ext_cols", "graph_nodes", "window", "waves_per_block",
-                "chunk", "lanes"]
+                "chunk", "lanes", "vpi"]
         return {k: int(v) for k, v in zip(keys, a)}
 
 

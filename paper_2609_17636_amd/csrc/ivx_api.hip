@@ -116,6 +116,7 @@ struct ivx_plan {
     double beta = 0.0;
     int nwave = 4;
     int lanes = 16;
+    int vpi = 2;
     int chunk_max = 256;
     int tile_fixed = 0;
     std::vector<real> dq_host;
@@ -344,7 +345,7 @@ ivx_status build_bins(ivx_plan *p, hipStream_t st) {
     p->n_work = (int)work.size();
     p->n_slots = slot;
     drop_graph(p); // kernel arguments change with the tiling
-    IVX_HIP(prepare_grid(g, p->nwave, p->lanes));
+    IVX_HIP(prepare_grid(g, p->nwave, p->lanes * 10 + p->vpi));
 
     for (void *old : {(void *)p->d_crd, (void *)p->d_vis, (void *)p->d_wgt, (void *)p->d_perm,
                       (void *)p->d_work, (void *)p->d_tslot, (void *)p->d_ext, (void *)p->d_slots,
@@ -447,7 +448,7 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
     {
         StageTimer t(p, st, IVX_STAGE_GRID);
         IVX_HIP(launch_grid(MODE_OBJ, g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
-                            p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes, st));
+                            p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, st));
     }
     {
         StageTimer t(p, st, IVX_STAGE_FOLD);
@@ -656,7 +657,7 @@ ivx_status ivx_plan_info(const ivx_plan *p, int64_t *info) {
     if (!p || !info) return fail(IVX_EINVAL, "plan and info must be non-NULL");
     const Geom &g = p->g;
     const int64_t v[16] = {g.nf, g.W, g.T, p->n_work, p->m_live, p->n_slots, (int64_t)p->dev_bytes,
-                           (int64_t)g.C * g.P, g.eh, g.ew, p->graph_nodes, g.win, p->nwave, p->chunk_max, p->lanes, 0};
+                           (int64_t)g.C * g.P, g.eh, g.ew, p->graph_nodes, g.win, p->nwave, p->chunk_max, p->lanes, p->vpi};
     std::memcpy(info, v, sizeof(v));
     return IVX_OK;
 }
@@ -910,7 +911,7 @@ ivx_status ivx_forward(ivx_plan *p, const ivx_real *sky, ivx_real *model_vis, vo
     if ((s = run_forward_half(p, sky, st)) != IVX_OK) return s;
     IVX_HIP(launch_zero(model_vis, p->m_total * 2 * (int64_t)sizeof(real), st));
     IVX_HIP(launch_grid(MODE_FWD, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
-                        p->d_slots, p->d_jpart, nullptr, reinterpret_cast<cpx *>(model_vis), p->nwave, p->lanes, st));
+                        p->d_slots, p->d_jpart, nullptr, reinterpret_cast<cpx *>(model_vis), p->nwave, p->lanes * 10 + p->vpi, st));
     return IVX_OK;
 }
 
@@ -920,7 +921,7 @@ ivx_status ivx_adjoint(ivx_plan *p, const ivx_real *vis, ivx_real *image, void *
     if (!image || (!vis && p->m_total > 0)) return fail(IVX_EINVAL, "vis and image are required");
     hipStream_t st = (hipStream_t)stream;
     IVX_HIP(launch_grid(MODE_ADJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
-                        p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave, p->lanes, st));
+                        p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave, p->lanes * 10 + p->vpi, st));
     if ((s = run_adjoint_half(p, st)) != IVX_OK) return s;
     IVX_HIP(launch_sky(p->g, image, p->d_gp, p->d_cptr, p->d_cent, real(0), real(0), nullptr, nullptr, 0, 0, 1, 0,
                        image, p->d_rpart, true, st));
@@ -931,16 +932,17 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     ivx_status s = check_plan(p);
     if (s != IVX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    struct Cand { int T, nwave, chunk, lanes; };
+    struct Cand { int T, nwave, chunk, lanes, vpi; };
     std::vector<Cand> cands;
     const int tiles[] = {8, 12, 16, 24, 32};
     const int waves[] = {4, 2, 1};
     const int chunks[] = {128, 256, 512};
     for (int lanes : {16, 8})
-        for (int T : tiles)
-            for (int nw : waves)
-                if (tile_fits(p, T, nw, lanes))
-                    for (int ch : chunks) cands.push_back(Cand{T, nw, ch, lanes});
+        for (int vpi : {2, 1})
+            for (int T : tiles)
+                for (int nw : waves)
+                    if (tile_fits(p, T, nw, lanes))
+                        for (int ch : chunks) cands.push_back(Cand{T, nw, ch, lanes, vpi});
     if (cands.empty()) return fail(IVX_EINVAL, "no tile candidate fits");
     // the tiling only changes the gridding stage and the slot reduction: time those two on
     // the plan's own data (zero sky), keep the fastest; the result is accuracy-neutral
@@ -953,10 +955,11 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     IVX_HIP(hipEventCreate(&e1));
     const auto t_start = std::chrono::steady_clock::now();
     double best_ms = 1e300;
-    Cand best{p->g.T, p->nwave, p->chunk_max, p->lanes};
+    Cand best{p->g.T, p->nwave, p->chunk_max, p->lanes, p->vpi};
     for (const Cand &c : cands) {
         p->nwave = c.nwave;
         p->lanes = c.lanes;
+        p->vpi = c.vpi;
         p->chunk_max = c.chunk;
         set_tile(p, c.T);
         if ((s = build_bins(p, st)) != IVX_OK) break;
@@ -966,7 +969,7 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
         for (int r = 0; r < reps + 1; ++r) {
             IVX_HIP(hipEventRecord(e0, st));
             IVX_HIP(launch_grid(MODE_OBJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm,
-                                p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes, st));
+                                p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, st));
             IVX_HIP(launch_fold(p->g, p->d_tslot, p->d_slots, p->d_hs, st));
             IVX_HIP(hipEventRecord(e1, st));
             IVX_HIP(hipEventSynchronize(e1));
@@ -987,6 +990,7 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     if (s != IVX_OK) return s;
     p->nwave = best.nwave;
     p->lanes = best.lanes;
+    p->vpi = best.vpi;
     p->chunk_max = best.chunk;
     set_tile(p, best.T);
     if ((s = build_bins(p, st)) != IVX_OK) return s;

@@ -76,7 +76,7 @@ hipError_t launch_col_fwd(const Geom &g, const cpx *R, const cpx *tw, cpx *ext, 
 hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work,
                        const VisCoord *crd, const cpx *vis, const real *wgt,
                        const int64_t *perm, const cpx *ext, cpx *slots, double *jpart,
-                       const cpx *caller_in, cpx *caller_out, int nwave, int lanes,
+                       const cpx *caller_in, cpx *caller_out, int nwave, int variant,
                        hipStream_t st);
 hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *hs,
                        hipStream_t st);
@@ -101,7 +101,8 @@ hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st);
 
 // Raise the dynamic-LDS limit of the gridding kernels for this geometry (call before any
 // stream capture).
-hipError_t prepare_grid(const Geom &g, int nwave, int lanes);
+// variant = 10 * lanes per visibility (8 or 16) + visibilities per group per iteration (1, 2)
+hipError_t prepare_grid(const Geom &g, int nwave, int variant);
 // Lane groups per wave of the gridding kernel for kernel width W (one LDS accumulator each).
 // lanes = 8 (W <= 8 only) or 16 visibility lanes per group.
 int grid_groups_per_wave(int W, int lanes);

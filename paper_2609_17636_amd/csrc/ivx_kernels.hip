@@ -353,7 +353,7 @@ template <int G> __device__ __forceinline__ real group_sum(real v) {
 // cells and no other group writes there): no atomics.  The windows are summed in a fixed
 // order at the end, so results do not depend on scheduling.
 // LDS: F window (unless MODE_ADJ) + one accumulator window per group (unless MODE_FWD).
-template <int W, int MODE, int G>
+template <int W, int MODE, int G, int VPI>
 __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[NT / 64];
@@ -397,104 +397,152 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     const real zoff = real(0.5) * real(W) - real(1);
     real jacc = real(0);
 
+    // this group's segment of the tile's list, walked VPI visibilities at a time
     const int seg = (wi.count + ngroups - 1) / ngroups;
     const int v0 = gid * seg;
     const int v1 = min(wi.count, v0 + seg);
+    const int nit = (seg + VPI - 1) / VPI;
     const VisCoord *crd = a.crd + wi.begin;
     const cpx *vis = a.vis + wi.begin;
     const real *wgt = a.wgt + wi.begin;
     const int64_t *perm = a.perm + wi.begin;
 
-    // software pipeline: the record of iteration it+1 is loaded during iteration it
-    int vn = v0 < v1 ? v0 : 0;
-    VisCoord c_nx = crd[vn];
-    cpx y_nx = cpx{0, 0};
-    real w_nx = real(0);
-    int64_t p_nx = 0;
-    if (MODE == MODE_OBJ) { y_nx = vis[vn]; w_nx = wgt[vn]; }
-    if (MODE == MODE_ADJ) { w_nx = wgt[vn]; p_nx = perm[vn]; }
-    if (MODE == MODE_FWD) { p_nx = perm[vn]; }
+    // software pipeline: the records of iteration it+1 are loaded during iteration it
+    VisCoord c_nx[VPI];
+    cpx y_nx[VPI];
+    real w_nx[VPI];
+    int64_t p_nx[VPI];
+#pragma unroll
+    for (int u = 0; u < VPI; ++u) {
+        const int vv = v0 + u;
+        const int vn = vv < v1 ? vv : 0;
+        c_nx[u] = crd[vn];
+        y_nx[u] = cpx{0, 0};
+        w_nx[u] = real(0);
+        p_nx[u] = 0;
+        if (MODE == MODE_OBJ) { y_nx[u] = vis[vn]; w_nx[u] = wgt[vn]; }
+        if (MODE == MODE_ADJ) { w_nx[u] = wgt[vn]; p_nx[u] = perm[vn]; }
+        if (MODE == MODE_FWD) { p_nx[u] = perm[vn]; }
+    }
 
-    for (int it = 0; it < seg; ++it) {
-        const bool valid = v0 + it < v1;
-        const VisCoord cr = c_nx;
-        const cpx ycur = y_nx;
-        const real wcur = w_nx;
-        const int64_t pcur = p_nx;
-        if (it + 1 < seg) {
-            vn = (v0 + it + 1 < v1) ? v0 + it + 1 : 0;
-            c_nx = crd[vn];
-            if (MODE == MODE_OBJ) { y_nx = vis[vn]; w_nx = wgt[vn]; }
-            if (MODE == MODE_ADJ) { w_nx = wgt[vn]; p_nx = perm[vn]; }
-            if (MODE == MODE_FWD) { p_nx = perm[vn]; }
+    for (int it = 0; it < nit; ++it) {
+        VisCoord cr[VPI];
+        cpx ycur[VPI];
+        real wcur[VPI];
+        int64_t pcur[VPI];
+        bool valid[VPI];
+#pragma unroll
+        for (int u = 0; u < VPI; ++u) {
+            valid[u] = v0 + it * VPI + u < v1;
+            cr[u] = c_nx[u];
+            ycur[u] = y_nx[u];
+            wcur[u] = w_nx[u];
+            pcur[u] = p_nx[u];
         }
-        int ix, iy;
-        real fx, fy;
-        decode(cr, ix, iy, fx, fy);
-        // kernel weights: x weight of the owned column, y weights of the owned rows
-        real wxj, wsel[NR];
-        if constexpr (G == 16 && S == 2) {
-            const bool isx = t < 8;
-            const int k = t & 7;
-            real mine = real(0);
-            if (k < W) mine = es_kernel(zoff + (isx ? fx : fy) - real(k), inv_hw, beta2);
-            const real sh = row_shr8(mine);
-            wxj = isx ? mine : sh;
-            RowWeights<W, G, 0>::run(mine, upper, wsel);
-        } else {
-            real mx = real(0), my = real(0);
-            if (colok) {
-                mx = es_kernel(zoff + fx - real(j), inv_hw, beta2);
-                my = es_kernel(zoff + fy - real(j), inv_hw, beta2);
+        if (it + 1 < nit) {
+#pragma unroll
+            for (int u = 0; u < VPI; ++u) {
+                const int vv = v0 + (it + 1) * VPI + u;
+                const int vn = vv < v1 ? vv : 0;
+                c_nx[u] = crd[vn];
+                if (MODE == MODE_OBJ) { y_nx[u] = vis[vn]; w_nx[u] = wgt[vn]; }
+                if (MODE == MODE_ADJ) { w_nx[u] = wgt[vn]; p_nx[u] = perm[vn]; }
+                if (MODE == MODE_FWD) { p_nx[u] = perm[vn]; }
             }
-            wxj = mx;
-            RowWeights<W, G, 0>::run(my, upper, wsel);
         }
-        if (!valid) wxj = real(0);
-        const int off = (iy + h) * ldw + ix + j;
-        real ar = real(0), ai = real(0);
+        int off[VPI];
+        real wxj[VPI], wsel[VPI][NR];
+#pragma unroll
+        for (int u = 0; u < VPI; ++u) {
+            int ix, iy;
+            real fx, fy;
+            decode(cr[u], ix, iy, fx, fy);
+            // kernel weights: x weight of the owned column, y weights of the owned rows
+            if constexpr (G == 16 && S == 2) {
+                const bool isx = t < 8;
+                const int k = t & 7;
+                real mine = real(0);
+                if (k < W) mine = es_kernel(zoff + (isx ? fx : fy) - real(k), inv_hw, beta2);
+                const real sh = row_shr8(mine);
+                wxj[u] = isx ? mine : sh;
+                RowWeights<W, G, 0>::run(mine, upper, wsel[u]);
+            } else {
+                real mx = real(0), my = real(0);
+                if (colok) {
+                    mx = es_kernel(zoff + fx - real(j), inv_hw, beta2);
+                    my = es_kernel(zoff + fy - real(j), inv_hw, beta2);
+                }
+                wxj[u] = mx;
+                RowWeights<W, G, 0>::run(my, upper, wsel[u]);
+            }
+            if (!valid[u]) wxj[u] = real(0);
+            off[u] = (iy + h) * ldw + ix + j;
+        }
+        real ar[VPI], ai[VPI];
+#pragma unroll
+        for (int u = 0; u < VPI; ++u) {
+            ar[u] = real(0);
+            ai[u] = real(0);
+        }
         if (MODE != MODE_ADJ) {
             if (colok) {
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
                     if (S == 1 || h + S * k < W) {
-                        const cpx f = Fw[off + S * k * ldw];
-                        ar += wsel[k] * f.re;
-                        ai += wsel[k] * f.im;
+#pragma unroll
+                        for (int u = 0; u < VPI; ++u) {
+                            const cpx f = Fw[off[u] + S * k * ldw];
+                            ar[u] += wsel[u][k] * f.re;
+                            ai[u] += wsel[u][k] * f.im;
+                        }
                     }
                 }
             }
-            ar = group_sum<G>(ar * wxj);
-            ai = group_sum<G>(ai * wxj);
+#pragma unroll
+            for (int u = 0; u < VPI; ++u) {
+                ar[u] = group_sum<G>(ar[u] * wxj[u]);
+                ai[u] = group_sum<G>(ai[u] * wxj[u]);
+            }
         }
         if (MODE == MODE_FWD) {
-            if (valid && t == 0) {
-                if (pcur < 0) a.caller_out[~pcur] = cpx{ar, -ai};
-                else a.caller_out[pcur] = cpx{ar, ai};
+#pragma unroll
+            for (int u = 0; u < VPI; ++u) {
+                if (valid[u] && t == 0) {
+                    if (pcur[u] < 0) a.caller_out[~pcur[u]] = cpx{ar[u], -ai[u]};
+                    else a.caller_out[pcur[u]] = cpx{ar[u], ai[u]};
+                }
             }
             continue;
         }
-        real cre, cim;
-        if (MODE == MODE_OBJ) {
-            const real rr = ar - ycur.re, ri = ai - ycur.im;
-            if (valid && t == 0) jacc += real(0.5) * wcur * (rr * rr + ri * ri);
-            cre = wcur * rr * wxj;
-            cim = wcur * ri * wxj;
-        } else {
-            cpx y = a.caller_in[pcur < 0 ? ~pcur : pcur];
-            if (pcur < 0) y.im = -y.im;
-            cre = wcur * y.re * wxj;
-            cim = wcur * y.im * wxj;
+        real cre[VPI], cim[VPI];
+#pragma unroll
+        for (int u = 0; u < VPI; ++u) {
+            if (MODE == MODE_OBJ) {
+                const real rr = ar[u] - ycur[u].re, ri = ai[u] - ycur[u].im;
+                if (valid[u] && t == 0) jacc += real(0.5) * wcur[u] * (rr * rr + ri * ri);
+                cre[u] = wcur[u] * rr * wxj[u];
+                cim[u] = wcur[u] * ri * wxj[u];
+            } else {
+                cpx y = a.caller_in[pcur[u] < 0 ? ~pcur[u] : pcur[u]];
+                if (pcur[u] < 0) y.im = -y.im;
+                cre[u] = wcur[u] * y.re * wxj[u];
+                cim[u] = wcur[u] * y.im * wxj[u];
+            }
         }
+        // spread: the visibilities of one iteration go in program order, so a cell shared
+        // by two of them (owned by different lanes) sees both updates
         if (colok) {
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                if (S == 1 || h + S * k < W) {
-                    cpx *hp = Hg + off + S * k * ldw;
-                    cpx hv = *hp;
-                    hv.re += cre * wsel[k];
-                    hv.im += cim * wsel[k];
-                    *hp = hv;
+            for (int u = 0; u < VPI; ++u) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    if (S == 1 || h + S * k < W) {
+                        cpx *hp = Hg + off[u] + S * k * ldw;
+                        cpx hv = *hp;
+                        hv.re += cre[u] * wsel[u][k];
+                        hv.im += cim[u] * wsel[u][k];
+                        *hp = hv;
+                    }
                 }
             }
         }
@@ -553,23 +601,17 @@ __device__ __forceinline__ cpx ext_cell(const Geom &g, const int32_t *__restrict
     return cpx{sr, si};
 }
 
-// Sum of every extended-grid cell that aliases to periodic fine-grid cell (t1, t2).
+// Sum of every extended-grid cell that aliases to periodic fine-grid cell (t1, t2): rows
+// t1 + O + m nf inside [0, eh), columns t2 + O + m nf inside [0, ew) (t1, t2 >= 0).
 __device__ __forceinline__ cpx periodic_cell(const Geom &g, const int32_t *__restrict__ ts,
                                              const cpx *__restrict__ slots, int t1, int t2) {
     cpx s = cpx{0, 0};
-    for (int mr = -2; mr <= 2; ++mr) {
-        const int er = t1 + g.O + mr * g.nf;
-        if (er < 0 || er >= g.eh) continue;
-        for (int mc = -2; mc <= 2; ++mc) {
-            const int ec = t2 + g.O + mc * g.nf;
-            if (ec < 0 || ec >= g.ew) continue;
-            s = cadd(s, ext_cell(g, ts, slots, er, ec));
-        }
-    }
+    const int r0 = t1 + g.O, c0 = t2 + g.O;
+    for (int er = r0 - (r0 / g.nf) * g.nf; er < g.eh; er += g.nf)
+        for (int ec = c0 - (c0 / g.nf) * g.nf; ec < g.ew; ec += g.nf) s = cadd(s, ext_cell(g, ts, slots, er, ec));
     return s;
 }
 
-// ------------------------------------------------------------ adjoint column pass
 __global__ __launch_bounds__(NT) void k_fold(Geom g, const int32_t *__restrict__ tslot,
                                              const cpx *__restrict__ slots, cpx *__restrict__ hs) {
     const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -797,31 +839,31 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
 }
 
 // ---------------------------------------------------------------------- reductions
-__global__ __launch_bounds__(NT) void k_final(const double *__restrict__ jpart, int nj,
-                                              const double *__restrict__ rpart, int nr,
-                                              const double *__restrict__ kpart, int nkp,
-                                              double lambda_r, double lambda_s, double *terms,
-                                              double *terms_user) {
-    __shared__ double sh[3][NT];
+constexpr int NT_FINAL = 1024;
+__global__ __launch_bounds__(NT_FINAL) void k_final(const double *__restrict__ jpart, int nj,
+                                                    const double *__restrict__ rpart, int nr,
+                                                    const double *__restrict__ kpart, int nkp,
+                                                    double lambda_r, double lambda_s, double *terms,
+                                                    double *terms_user) {
+    __shared__ double sh[3][NT_FINAL / 64];
     const int tid = threadIdx.x;
-    double sj = 0.0, sr = 0.0, sk = 0.0;
-    for (int i = tid; i < nj; i += NT) sj += jpart[i];
-    for (int i = tid; i < nr; i += NT) sr += rpart[i];
-    for (int i = tid; i < nkp; i += NT) sk += kpart[i];
-    sh[0][tid] = sj;
-    sh[1][tid] = sr;
-    sh[2][tid] = sk;
-    __syncthreads();
-    for (int w = NT / 2; w >= 1; w >>= 1) {
-        if (tid < w) {
-            sh[0][tid] += sh[0][tid + w];
-            sh[1][tid] += sh[1][tid + w];
-            sh[2][tid] += sh[2][tid + w];
-        }
-        __syncthreads();
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = tid; i < nj; i += NT_FINAL) v[0] += jpart[i];
+    for (int i = tid; i < nr; i += NT_FINAL) v[1] += rpart[i];
+    for (int i = tid; i < nkp; i += NT_FINAL) v[2] += kpart[i];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        for (int m = 32; m >= 1; m >>= 1) v[q] += __shfl_xor(v[q], m, 64);
+        if ((tid & 63) == 0) sh[q][tid >> 6] = v[q];
     }
+    __syncthreads();
     if (tid == 0) {
-        const double Q = sh[0][0], R = sh[1][0], K = sh[2][0];
+        double Q = 0.0, R = 0.0, K = 0.0;
+        for (int w = 0; w < NT_FINAL / 64; ++w) {
+            Q += sh[0][w];
+            R += sh[1][w];
+            K += sh[2][w];
+        }
         const double t4[4] = {Q + lambda_s * K + lambda_r * R, Q, K, R};
         for (int q = 0; q < 4; ++q) {
             terms[q] = t4[q];
@@ -913,75 +955,83 @@ size_t grid_lds_bytes(const Geom &g, int nwave, int lanes) {
     return (size_t)(1 + grid_groups_per_wave(g.W, lanes) * nwave) * g.win * g.ldw * sizeof(cpx);
 }
 
-template <int W, int G>
+template <int W, int G, int VPI>
 static hipError_t launch_grid_wg(int mode, const GridArgs &a, int n_work, hipStream_t st) {
     const size_t wsz = (size_t)a.g.win * a.g.ldw * sizeof(cpx);
     const int threads = 64 * a.nwave;
     const int ng = (64 / G) * a.nwave;
     switch (mode) {
-    case MODE_OBJ: k_grid<W, MODE_OBJ, G><<<n_work, threads, (1 + ng) * wsz, st>>>(a); break;
-    case MODE_FWD: k_grid<W, MODE_FWD, G><<<n_work, threads, wsz, st>>>(a); break;
-    default: k_grid<W, MODE_ADJ, G><<<n_work, threads, ng * wsz, st>>>(a); break;
+    case MODE_OBJ: k_grid<W, MODE_OBJ, G, VPI><<<n_work, threads, (1 + ng) * wsz, st>>>(a); break;
+    case MODE_FWD: k_grid<W, MODE_FWD, G, VPI><<<n_work, threads, wsz, st>>>(a); break;
+    default: k_grid<W, MODE_ADJ, G, VPI><<<n_work, threads, ng * wsz, st>>>(a); break;
     }
     return hipGetLastError();
 }
 
-template <int W, int G> static hipError_t prepare_grid_wg(const Geom &g, int nwave) {
+template <int W, int G, int VPI> static hipError_t prepare_grid_wg(const Geom &g, int nwave) {
     // raise the dynamic-LDS limit of the three modes ahead of any stream capture
     const size_t wsz = (size_t)g.win * g.ldw * sizeof(cpx);
     const int ng = (64 / G) * nwave;
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)k_grid<W, MODE_OBJ, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)((1 + ng) * wsz))) != hipSuccess)
+    if ((e = hipFuncSetAttribute((const void *)k_grid<W, MODE_OBJ, G, VPI>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)((1 + ng) * wsz))) != hipSuccess)
         return e;
-    if ((e = hipFuncSetAttribute((const void *)k_grid<W, MODE_FWD, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)wsz)) != hipSuccess)
+    if ((e = hipFuncSetAttribute((const void *)k_grid<W, MODE_FWD, G, VPI>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)wsz)) != hipSuccess)
         return e;
-    return hipFuncSetAttribute((const void *)k_grid<W, MODE_ADJ, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    return hipFuncSetAttribute((const void *)k_grid<W, MODE_ADJ, G, VPI>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(ng * wsz));
 }
 
-template <int W>
-static hipError_t dispatch_w(bool prepare, int lanes, int mode, const GridArgs &a, int n_work, hipStream_t st) {
-    if constexpr (W <= 8) {
-        if (lanes == 8) return prepare ? prepare_grid_wg<W, 8>(a.g, a.nwave) : launch_grid_wg<W, 8>(mode, a, n_work, st);
-    }
-    return prepare ? prepare_grid_wg<W, 16>(a.g, a.nwave) : launch_grid_wg<W, 16>(mode, a, n_work, st);
+template <int W, int G>
+static hipError_t dispatch_wg(bool prepare, int vpi, int mode, const GridArgs &a, int n_work, hipStream_t st) {
+    if (vpi == 2) return prepare ? prepare_grid_wg<W, G, 2>(a.g, a.nwave) : launch_grid_wg<W, G, 2>(mode, a, n_work, st);
+    return prepare ? prepare_grid_wg<W, G, 1>(a.g, a.nwave) : launch_grid_wg<W, G, 1>(mode, a, n_work, st);
 }
 
-static hipError_t dispatch(bool prepare, int lanes, int mode, const GridArgs &a, int n_work, hipStream_t st) {
+// variant = 10 * lanes + visibilities per group per iteration (81, 82, 161, 162)
+template <int W>
+static hipError_t dispatch_w(bool prepare, int variant, int mode, const GridArgs &a, int n_work, hipStream_t st) {
+    const int lanes = variant / 10, vpi = variant % 10;
+    if constexpr (W <= 8) {
+        if (lanes == 8) return dispatch_wg<W, 8>(prepare, vpi, mode, a, n_work, st);
+    }
+    return dispatch_wg<W, 16>(prepare, vpi, mode, a, n_work, st);
+}
+
+static hipError_t dispatch(bool prepare, int variant, int mode, const GridArgs &a, int n_work, hipStream_t st) {
     switch (a.g.W) {
-    case 4: return dispatch_w<4>(prepare, lanes, mode, a, n_work, st);
-    case 5: return dispatch_w<5>(prepare, lanes, mode, a, n_work, st);
-    case 6: return dispatch_w<6>(prepare, lanes, mode, a, n_work, st);
-    case 7: return dispatch_w<7>(prepare, lanes, mode, a, n_work, st);
-    case 8: return dispatch_w<8>(prepare, lanes, mode, a, n_work, st);
-    case 9: return dispatch_w<9>(prepare, lanes, mode, a, n_work, st);
-    case 10: return dispatch_w<10>(prepare, lanes, mode, a, n_work, st);
-    case 11: return dispatch_w<11>(prepare, lanes, mode, a, n_work, st);
-    case 12: return dispatch_w<12>(prepare, lanes, mode, a, n_work, st);
-    case 13: return dispatch_w<13>(prepare, lanes, mode, a, n_work, st);
-    case 14: return dispatch_w<14>(prepare, lanes, mode, a, n_work, st);
-    case 15: return dispatch_w<15>(prepare, lanes, mode, a, n_work, st);
-    case 16: return dispatch_w<16>(prepare, lanes, mode, a, n_work, st);
+    case 4: return dispatch_w<4>(prepare, variant, mode, a, n_work, st);
+    case 5: return dispatch_w<5>(prepare, variant, mode, a, n_work, st);
+    case 6: return dispatch_w<6>(prepare, variant, mode, a, n_work, st);
+    case 7: return dispatch_w<7>(prepare, variant, mode, a, n_work, st);
+    case 8: return dispatch_w<8>(prepare, variant, mode, a, n_work, st);
+    case 9: return dispatch_w<9>(prepare, variant, mode, a, n_work, st);
+    case 10: return dispatch_w<10>(prepare, variant, mode, a, n_work, st);
+    case 11: return dispatch_w<11>(prepare, variant, mode, a, n_work, st);
+    case 12: return dispatch_w<12>(prepare, variant, mode, a, n_work, st);
+    case 13: return dispatch_w<13>(prepare, variant, mode, a, n_work, st);
+    case 14: return dispatch_w<14>(prepare, variant, mode, a, n_work, st);
+    case 15: return dispatch_w<15>(prepare, variant, mode, a, n_work, st);
+    case 16: return dispatch_w<16>(prepare, variant, mode, a, n_work, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t prepare_grid(const Geom &g, int nwave, int lanes) {
+hipError_t prepare_grid(const Geom &g, int nwave, int variant) {
     GridArgs a{};
     a.g = g;
     a.nwave = nwave;
-    return dispatch(true, lanes, MODE_OBJ, a, 0, nullptr);
+    return dispatch(true, variant, MODE_OBJ, a, 0, nullptr);
 }
 
 hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
                        const cpx *vis, const real *wgt, const int64_t *perm, const cpx *ext, cpx *slots,
-                       double *jpart, const cpx *caller_in, cpx *caller_out, int nwave, int lanes, hipStream_t st) {
+                       double *jpart, const cpx *caller_in, cpx *caller_out, int nwave, int variant, hipStream_t st) {
     if (n_work <= 0) return hipSuccess;
     if (nwave < 1 || nwave > NT / 64) return hipErrorInvalidValue;
     GridArgs a{g, work, crd, vis, wgt, perm, ext, slots, jpart, caller_in, caller_out, nwave};
-    return dispatch(false, lanes, mode, a, n_work, st);
+    return dispatch(false, variant, mode, a, n_work, st);
 }
 
 hipError_t launch_sd_rows(const Geom &g, const real *sky, const real *gB, int rb, int sd_n, int stride,
@@ -1016,7 +1066,7 @@ hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int3
 
 hipError_t launch_final(const double *jpart, int nj, const double *rpart, int nr, const double *kpart, int nkp,
                         double lambda_r, double lambda_s, double *terms, double *terms_user, hipStream_t st) {
-    k_final<<<1, NT, 0, st>>>(jpart, nj, rpart, nr, kpart, nkp, lambda_r, lambda_s, terms, terms_user);
+    k_final<<<1, NT_FINAL, 0, st>>>(jpart, nj, rpart, nr, kpart, nkp, lambda_r, lambda_s, terms, terms_user);
     return hipGetLastError();
 }
 
