@@ -39,6 +39,42 @@ def grid_algorithmic_bytes(n_live: int, n_fine: int, real_bytes: int = 4) -> flo
     return n_live * per_vis + G
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grid_traffic_c2.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2609_17636_amd", "csrc", "ivx_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the gridding kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def copy_probe(steps: int):
+    """Plain device copy of 1 GiB, `steps` times: the calibration kernel for the FETCH_SIZE /
+    WRITE_SIZE counters (each dispatch reads and writes exactly 2^30 bytes)."""
+    import torch
+
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_per_dispatch": 1 << 30, "steps": steps}), flush=True)
+
+
 def build_workload(seed=2001):
     import synth
 
@@ -84,7 +120,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true", help="run the counter calibration copy only")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.steps)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
               f"(the channel/pointing sharding is a design note only)", file=sys.stderr)
@@ -144,7 +184,7 @@ def main():
                    "kernel_width": info["kernel_width"], "tile": tile, "parallelism": "1 GPU"},
         "evals_per_s": 1e3 / ms_step,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_grid",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(), "kernel": "k_grid",
                      "kernel_ms": grid_ms, "algorithmic_bytes": alg},
     }
     if not args.no_cpu_baseline:
