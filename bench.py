@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true", help="run the counter calibration copy only")
+    ap.add_argument("--blocking", default="",
+                    help="tile,waves,chunk,lanes,vpi for the gridding kernel instead of the autotuner")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.steps)
@@ -146,8 +148,12 @@ def main():
     mv = plan.forward(x_true).double().cpu().numpy()
     synth.attach_data(p, mv[:, 0] + 1j * mv[:, 1])
     plan.set_problem_data(p)
-    tile = plan.autotune(2000.0)
+    if args.blocking:
+        plan.set_blocking(*[int(v) for v in args.blocking.split(",")])
+    else:
+        plan.autotune(2000.0)
     info = plan.info()
+    tile = info["tile"]
     print(f"# plan {info}", file=sys.stderr, flush=True)
 
     rng = np.random.default_rng(0)
@@ -181,7 +187,8 @@ def main():
         "config": {"workload": "single-pointing 512x512 sky (7 arcsec, k^-3 log-normal 0-50 K), "
                                "630 baselines x 1000 samples = 630,000 visibilities, lambda_r=1e-2",
                    "n_sky": p.n_sky, "n_vis": p.n_vis, "n_fine": info["n_fine"],
-                   "kernel_width": info["kernel_width"], "tile": tile, "parallelism": "1 GPU"},
+                   "kernel_width": info["kernel_width"], "tile": tile, "parallelism": "1 GPU",
+                   "blocking": {k: info[k] for k in ("tile", "waves_per_block", "chunk", "lanes", "vpi")}},
         "evals_per_s": 1e3 / ms_step,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(), "kernel": "k_grid",

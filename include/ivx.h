@@ -121,6 +121,14 @@ ivx_status ivx_plan_set_data(ivx_plan *plan, const ivx_real *uv, const ivx_real 
                              const ivx_real *beams, const ivx_real *interp,
                              const ivx_real *sd_map, void *stream);
 
+/* Replace the visibility data (and, if `weight` is non-NULL, the weights) of a plan whose
+ * uv coverage, flags, beams and grids stay the same: vis [M][2] and weight [M] in the
+ * caller's order, device memory.  The reordering runs on the device; IVX_ENONFINITE if an
+ * unflagged value is not finite or a weight is negative (checked on the device, then the
+ * stream is synchronised).  Same observation, new data: no re-sort. */
+ivx_status ivx_plan_set_vis(ivx_plan *plan, const ivx_real *vis, const ivx_real *weight,
+                            void *stream);
+
 /* One evaluation of Q_tot and its gradient at sky x (Eq. fusion_cost).
  * sky, grad: device, [C][N][N]; grad is overwritten.  terms (host or device, 4 doubles)
  * receives {Q_tot, Q, K, R} with Q = sum J_kc; NULL skips it.  Host `terms`
@@ -171,6 +179,14 @@ enum {
  * (host), and resets the sums. */
 ivx_status ivx_set_timing(ivx_plan *plan, uint32_t stage_mask);
 ivx_status ivx_stage_times(ivx_plan *plan, double *ms, int64_t *n_eval);
+
+/* Set the gridding blocking explicitly instead of ivx_autotune: tile edge (>= kernel
+ * width), waves per block (1, 2 or 4), visibilities per work item (>= 16), lanes per
+ * visibility (16, or 8 when kernel_width <= 8) and visibilities per lane group per loop
+ * iteration (1 or 2).  IVX_EINVAL if the combination does not fit the LDS; results are
+ * identical for every accepted blocking. */
+ivx_status ivx_set_blocking(ivx_plan *plan, int32_t tile, int32_t waves, int32_t chunk,
+                            int32_t lanes, int32_t vpi, void *stream);
 
 /* Plan facts, host array of 16 int64: {n_fine, kernel_width, tile, n_work_items,
  * n_live_vis, n_slots, device_bytes, n_items, ext_rows, ext_cols, graph_nodes,

@@ -19,7 +19,7 @@ import numpy as np
 
 from .build import lib_path
 
-__all__ = ["Plan", "Objective", "solve", "load_library", "IvxError", "STATUS", "STAGES"]
+__all__ = ["Plan", "Objective", "solve", "UNet", "load_library", "IvxError", "STATUS", "STAGES"]
 
 STATUS = {0: "IVX_OK", -1: "IVX_EINVAL", -2: "IVX_ENOMEM", -3: "IVX_EHIP", -4: "IVX_ENONFINITE",
           -5: "IVX_ESTATE"}
@@ -46,7 +46,8 @@ class _Problem(ctypes.Structure):
 
 EXPORTS = ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_forward", "ivx_adjoint",
            "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_last_error", "ivx_version",
-           "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph")
+           "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking",
+           "ivx_plan_set_vis")
 
 STAGES = ("image_rows", "col_fwd", "grid", "fold", "col_inv", "row_inv", "sd", "sky", "final")
 
@@ -73,12 +74,14 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
     lib.ivx_plan_destroy.argtypes = [vp]
     lib.ivx_set_timing.argtypes = [vp, ctypes.c_uint32]
     lib.ivx_set_graph.argtypes = [vp, ctypes.c_int]
+    lib.ivx_set_blocking.argtypes = [vp, i32, i32, i32, i32, i32, vp]
+    lib.ivx_plan_set_vis.argtypes = [vp, vp, vp, vp]
     lib.ivx_stage_times.argtypes = [vp, vp, vp]
     lib.ivx_last_error.restype = ctypes.c_char_p
     lib.ivx_last_error.argtypes = []
     for f in ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_forward",
               "ivx_adjoint", "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_set_timing",
-              "ivx_stage_times", "ivx_set_graph"):
+              "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking", "ivx_plan_set_vis"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ivx_version.restype = ctypes.c_int
     lib.ivx_real_size.restype = ctypes.c_int
@@ -189,6 +192,20 @@ class Plan:
         self._check(self.lib.ivx_plan_set_data(self._h, _ptr(uv_), _ptr(vis_), _ptr(w_), _ptr(fl),
                                                 _ptr(b_), _ptr(g_), _ptr(sd_), _stream_ptr(stream)))
 
+    def set_vis(self, vis, weight=None, stream=None):
+        """New data (and weights) for the same observation: cuda tensors [M][2] (or complex
+        numpy) and [M], caller order."""
+        torch = _torch()
+        if isinstance(vis, np.ndarray):
+            if np.iscomplexobj(vis):
+                vis = np.stack([vis.real, vis.imag], axis=-1)
+            vis = torch.tensor(vis, dtype=self.torch_dtype, device="cuda")
+        if isinstance(weight, np.ndarray):
+            weight = torch.tensor(weight, dtype=self.torch_dtype, device="cuda")
+        v = vis.to(self.torch_dtype).contiguous()
+        w = None if weight is None else weight.to(self.torch_dtype).contiguous()
+        self._check(self.lib.ivx_plan_set_vis(self._h, _ptr(v), _ptr(w), _stream_ptr(stream)))
+
     def set_problem_data(self, p, stream=None):
         sd = p.sd_map if (p.sd_n > 0 and p.lambda_s != 0.0) else None
         self.set_data(p.uv, p.vis, p.weight, p.beams, p.interp, flags=p.flags, sd_map=sd, stream=stream)
@@ -230,6 +247,11 @@ class Plan:
         t = ctypes.c_int32(0)
         self._check(self.lib.ivx_autotune(self._h, float(budget_ms), ctypes.addressof(t), _stream_ptr(stream)))
         return int(t.value)
+
+    def set_blocking(self, tile, waves, chunk, lanes, vpi, stream=None):
+        """Explicit gridding blocking (see ivx_set_blocking); accuracy-neutral."""
+        self._check(self.lib.ivx_set_blocking(self._h, int(tile), int(waves), int(chunk), int(lanes), int(vpi),
+                                              _stream_ptr(stream)))
 
     def set_graph(self, enable: bool):
         """Replay objective evaluations from a captured HIP graph (default) or launch eagerly."""
@@ -301,3 +323,4 @@ def __getattr__(name):
 
 
 from .solver import solve  # noqa: E402
+from .unet import UNet  # noqa: E402

@@ -27,6 +27,15 @@ ivx_status hip_fail(hipError_t e, const char *where) {
     return fail(IVX_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+} // namespace
+
+namespace ivx {
+// Error reporting shared with the warm-start network (same thread-local message).
+ivx_status set_error(ivx_status s, const std::string &msg) { return fail(s, msg); }
+} // namespace ivx
+
+namespace {
+
 #define IVX_HIP(call)                                        \
     do {                                                     \
         hipError_t e_ = (call);                              \
@@ -613,6 +622,25 @@ ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out) {
     return IVX_OK;
 }
 
+ivx_status ivx_set_blocking(ivx_plan *p, int32_t tile, int32_t waves, int32_t chunk, int32_t lanes, int32_t vpi,
+                            void *stream) {
+    if (!p) return fail(IVX_EINVAL, "plan is NULL");
+    if (!(waves == 1 || waves == 2 || waves == 4) || chunk < 16 || !(lanes == 8 || lanes == 16) ||
+        !(vpi == 1 || vpi == 2))
+        return fail(IVX_EINVAL, "blocking out of range");
+    if (!tile_fits(p, tile, waves, lanes)) return fail(IVX_EINVAL, "blocking does not fit the LDS");
+    p->nwave = waves;
+    p->chunk_max = chunk;
+    p->lanes = lanes;
+    p->vpi = vpi;
+    set_tile(p, tile);
+    if (p->has_data) {
+        ivx_status s = build_bins(p, (hipStream_t)stream);
+        if (s != IVX_OK) return s;
+    }
+    return IVX_OK;
+}
+
 ivx_status ivx_set_graph(ivx_plan *p, int enable) {
     if (!p) return fail(IVX_EINVAL, "plan is NULL");
     p->use_graph = enable != 0;
@@ -849,6 +877,38 @@ fail_free:
         g_last_error = msg;
     }
     return s;
+}
+
+ivx_status ivx_plan_set_vis(ivx_plan *p, const ivx_real *vis, const ivx_real *weight, void *stream) {
+    ivx_status s = check_plan(p);
+    if (s != IVX_OK) return s;
+    if (!vis && p->m_total > 0) return fail(IVX_EINVAL, "vis is required");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned int *bad = nullptr;
+    IVX_HIP(hipMalloc(&bad, sizeof(unsigned int)));
+    hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned int), st);
+    if (e == hipSuccess)
+        e = launch_gather_vis(p->d_perm, p->m_live, reinterpret_cast<const cpx *>(vis), weight, p->d_vis, p->d_wgt, bad, st);
+    unsigned int hb = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(unsigned int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return hip_fail(e, "ivx_plan_set_vis");
+    if (hb) return fail(IVX_ENONFINITE, "ivx_plan_set_vis: non-finite value or negative weight");
+    // keep the host copy used by re-binning in step with the device data
+    std::vector<real> hv(2 * p->m_total), hw;
+    IVX_HIP(hipMemcpy(hv.data(), vis, hv.size() * sizeof(real), hipMemcpyDefault));
+    if (weight) {
+        hw.resize(p->m_total);
+        IVX_HIP(hipMemcpy(hw.data(), weight, hw.size() * sizeof(real), hipMemcpyDefault));
+    }
+    for (HostVis &h : p->hv) {
+        const int64_t j = h.src < 0 ? ~h.src : h.src;
+        h.yr = hv[2 * j];
+        h.yi = h.src < 0 ? -hv[2 * j + 1] : hv[2 * j + 1];
+        if (weight) h.w = hw[j];
+    }
+    return IVX_OK;
 }
 
 ivx_status ivx_objective_grad(ivx_plan *p, const ivx_real *sky, ivx_real *grad, double *terms, void *stream) {

@@ -98,6 +98,8 @@ hipError_t launch_final(const double *jpart, int nj, const double *rpart, int nr
                         const double *kpart, int nkp, double lambda_r, double lambda_s,
                         double *terms, double *terms_user, hipStream_t st);
 hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st);
+hipError_t launch_gather_vis(const int64_t *perm, int64_t n, const cpx *vis, const real *wgt, cpx *svis,
+                             real *swgt, unsigned int *bad, hipStream_t st);
 
 // Raise the dynamic-LDS limit of the gridding kernels for this geometry (call before any
 // stream capture).

@@ -872,6 +872,28 @@ __global__ __launch_bounds__(NT_FINAL) void k_final(const double *__restrict__ j
     }
 }
 
+// Data update in sorted order: sorted[s] = caller[perm[s]] (conjugated when folded);
+// bad[0] is set when a value is not finite or a weight negative.
+__global__ __launch_bounds__(NT) void k_gather_vis(const int64_t *__restrict__ perm, int64_t n,
+                                                   const cpx *__restrict__ vis, const real *__restrict__ wgt,
+                                                   cpx *__restrict__ svis, real *__restrict__ swgt,
+                                                   unsigned int *__restrict__ bad) {
+    const int64_t s = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (s >= n) return;
+    const int64_t p = perm[s];
+    const int64_t src = p < 0 ? ~p : p;
+    cpx y = vis[src];
+    if (p < 0) y.im = -y.im;
+    bool ok = isfinite(y.re) && isfinite(y.im);
+    svis[s] = y;
+    if (wgt) {
+        const real w = wgt[src];
+        ok = ok && isfinite(w) && w >= real(0);
+        swgt[s] = w;
+    }
+    if (!ok) bad[0] = 1u;
+}
+
 __global__ __launch_bounds__(NT) void k_zero(uint32_t *p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) p[i] = 0u;
 }
@@ -1067,6 +1089,13 @@ hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int3
 hipError_t launch_final(const double *jpart, int nj, const double *rpart, int nr, const double *kpart, int nkp,
                         double lambda_r, double lambda_s, double *terms, double *terms_user, hipStream_t st) {
     k_final<<<1, NT_FINAL, 0, st>>>(jpart, nj, rpart, nr, kpart, nkp, lambda_r, lambda_s, terms, terms_user);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_vis(const int64_t *perm, int64_t n, const cpx *vis, const real *wgt, cpx *svis, real *swgt,
+                             unsigned int *bad, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_gather_vis<<<(unsigned)((n + NT - 1) / NT), NT, 0, st>>>(perm, n, vis, wgt, svis, swgt, bad);
     return hipGetLastError();
 }
 

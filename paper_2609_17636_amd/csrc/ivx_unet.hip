@@ -1,0 +1,858 @@
+// Learned warm start: a U-Net (Ronneberger et al. 2015) on the dirty mosaic, trained on
+// converged cold-start solutions of the Classic3D objective.  Every layer is a kernel
+// here; the 3x3 convolutions are implicit GEMMs on the bf16 matrix cores.
+//
+// Implicit GEMM of a 3x3 convolution, NHWC: rows = output pixels p, columns = output
+// channels o, reduction index k = (dy * 3 + dx) * Cin + c.  A[p][k] is the input pixel
+// shifted by (dy - 1, dx - 1) (zero outside), B[k][o] = W[o][dy][dx][c].  One wave owns
+// 16 pixels x 16*NTW channels and issues v_mfma_f32_16x16x16_bf16 per 16-wide k step:
+//   A operand : lane l holds A[l % 16][4 (l / 16) + v], v = 0..3 (4 consecutive channels)
+//   B operand : lane l holds B[4 (l / 16) + v][l % 16]  (4 consecutive weights of one o)
+//   result    : lane l holds D[4 (l / 16) + v][l % 16]
+// The transposed correlation (gradient of the input) is the same kernel on flipped
+// weights, and the weight gradient is a second implicit GEMM (rows o, columns k, reduction
+// over pixels) split over pixel ranges with a fixed-order reduction of the partials.
+#include "ivx_internal.hpp"
+#include "ivx_unet.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+namespace ivx {
+ivx_status set_error(ivx_status s, const std::string &msg); // defined with the objective ABI
+}
+
+using namespace ivx;
+
+namespace {
+
+constexpr int NT = 256;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------- 3x3 convolution
+template <int NTW>
+__global__ __launch_bounds__(NT) void k_conv3x3(const float *__restrict__ x, int n, int h, int w, int cin,
+                                                const uint16_t *__restrict__ wt, const float *__restrict__ bias,
+                                                int cout, int relu, const float *__restrict__ mask, int accumulate,
+                                                float *__restrict__ y) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t P = (int64_t)n * h * w;
+    const int64_t pbase = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int cobase = blockIdx.y * (16 * NTW);
+    const int K = 9 * cin;
+    const int row = lane & 15, kq = lane >> 4;
+    const int64_t p = pbase + row;
+    const bool pv = p < P;
+    int pn = 0, py = 0, px = 0;
+    if (pv) {
+        pn = (int)(p / ((int64_t)h * w));
+        const int r = (int)(p - (int64_t)pn * h * w);
+        py = r / w;
+        px = r - py * w;
+    }
+    f32x4 acc[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const int k = k0 + 4 * kq;
+        bf16x4 a = {0, 0, 0, 0};
+        if (pv && k < K) {
+            const int tap = k / cin, c = k - (k / cin) * cin;
+            const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+            if (yy >= 0 && yy < h && xx >= 0 && xx < w) {
+                const float4 v = *reinterpret_cast<const float4 *>(x + (((int64_t)pn * h + yy) * w + xx) * cin + c);
+                a[0] = (short)f2bf(v.x);
+                a[1] = (short)f2bf(v.y);
+                a[2] = (short)f2bf(v.z);
+                a[3] = (short)f2bf(v.w);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            const int co = cobase + t * 16 + row;
+            bf16x4 b = {0, 0, 0, 0};
+            if (co < cout && k < K) {
+                const uint2 u = *reinterpret_cast<const uint2 *>(wt + (int64_t)co * K + k);
+                b[0] = (short)(u.x & 0xFFFFu);
+                b[1] = (short)(u.x >> 16);
+                b[2] = (short)(u.y & 0xFFFFu);
+                b[3] = (short)(u.y >> 16);
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        const int co = cobase + t * 16 + row;
+        if (co >= cout) continue;
+        const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t pp = pbase + 4 * kq + v;
+            if (pp >= P) continue;
+            const int64_t o = pp * cout + co;
+            float val = acc[t][v] + bb;
+            if (relu) val = fmaxf(val, 0.f);
+            if (mask && !(mask[o] > 0.f)) val = 0.f;
+            if (accumulate) val += y[o];
+            y[o] = val;
+        }
+    }
+}
+
+// Weight-gradient partials: block (k tile of 64, o tile of 64, pixel range z).
+constexpr int GW_PIX = 1024;
+__global__ __launch_bounds__(NT) void k_conv3x3_gw(const float *__restrict__ x, const float *__restrict__ dy,
+                                                   int n, int h, int w, int cin, int cout,
+                                                   float *__restrict__ part) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t P = (int64_t)n * h * w;
+    const int K = 9 * cin;
+    const int row = lane & 15, q = lane >> 4;
+    const int co = blockIdx.y * 64 + wave * 16 + row;   // A row
+    const int kbase = blockIdx.x * 64;                   // 4 column tiles
+    const int64_t p0 = (int64_t)blockIdx.z * GW_PIX;
+    const int64_t p1 = p0 + GW_PIX < P ? p0 + GW_PIX : P;
+    int tapy[4], tapx[4], tc[4];
+    bool kv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int k = kbase + t * 16 + row;
+        kv[t] = k < K;
+        const int tap = kv[t] ? k / cin : 0;
+        tc[t] = kv[t] ? k - tap * cin : 0;
+        tapy[t] = tap / 3 - 1;
+        tapx[t] = tap % 3 - 1;
+    }
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t pb = p0; pb < p1; pb += 16) {
+        bf16x4 a = {0, 0, 0, 0};
+        bf16x4 b[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) b[t] = bf16x4{0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t p = pb + 4 * q + v;
+            if (p >= p1) continue;
+            if (co < cout) a[v] = (short)f2bf(dy[p * cout + co]);
+            const int pn = (int)(p / ((int64_t)h * w));
+            const int r = (int)(p - (int64_t)pn * h * w);
+            const int py = r / w, px = r - (r / w) * w;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int yy = py + tapy[t], xx = px + tapx[t];
+                if (kv[t] && yy >= 0 && yy < h && xx >= 0 && xx < w)
+                    b[t][v] = (short)f2bf(x[(((int64_t)pn * h + yy) * w + xx) * cin + tc[t]]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[t], 0, 0, 0);
+    }
+    // D rows = output channels (4 q + v of this wave's 16), columns = k
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int k = kbase + t * 16 + row;
+        if (k >= K) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int o = blockIdx.y * 64 + wave * 16 + 4 * q + v;
+            if (o < cout) part[((int64_t)blockIdx.z * cout + o) * K + k] = acc[t][v];
+        }
+    }
+}
+
+// dw[i] = sum over splits of part[s][i] (fixed order)
+__global__ __launch_bounds__(NT) void k_sum_parts(const float *__restrict__ part, int splits, int64_t len,
+                                                  float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i >= len) return;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * len + i];
+    out[i] = s;
+}
+
+// db[o] = sum over pixels of dy[p][o]; one block per channel, fixed-order tree
+__global__ __launch_bounds__(NT) void k_colsum(const float *__restrict__ dy, int64_t P, int c, float *__restrict__ out) {
+    __shared__ float sh[NT];
+    const int o = blockIdx.x;
+    float s = 0.f;
+    for (int64_t p = threadIdx.x; p < P; p += NT) s += dy[p * c + o];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int m = NT / 2; m >= 1; m >>= 1) {
+        if (threadIdx.x < m) sh[threadIdx.x] += sh[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[o] = sh[0];
+}
+
+// wt[c][a][b][o] = W[o][2-a][2-b][c]
+__global__ __launch_bounds__(NT) void k_flip(const uint16_t *__restrict__ W, int cin, int cout, uint16_t *__restrict__ wt) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t tot = (int64_t)9 * cin * cout;
+    if (i >= tot) return;
+    const int o = (int)(i % cout);
+    const int ab = (int)((i / cout) % 9);
+    const int c = (int)(i / ((int64_t)cout * 9));
+    const int a = ab / 3, b = ab % 3;
+    wt[i] = W[((int64_t)o * 9 + (2 - a) * 3 + (2 - b)) * cin + c];
+}
+
+__global__ __launch_bounds__(NT) void k_to_bf16(const float *__restrict__ x, int64_t n, uint16_t *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// ---------------------------------------------------------------- other layers
+__global__ __launch_bounds__(NT) void k_pool2(const float *__restrict__ x, int n, int h, int w, int c,
+                                              float *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int ho = h / 2, wo = w / 2;
+    const int64_t tot = (int64_t)n * ho * wo * c;
+    if (i >= tot) return;
+    const int ch = (int)(i % c);
+    const int64_t pix = i / c;
+    const int xo = (int)(pix % wo), yo = (int)((pix / wo) % ho), nn = (int)(pix / ((int64_t)wo * ho));
+    const float *b = x + (((int64_t)nn * h + 2 * yo) * w + 2 * xo) * c + ch;
+    y[i] = fmaxf(fmaxf(b[0], b[c]), fmaxf(b[(int64_t)w * c], b[(int64_t)w * c + c]));
+}
+
+__global__ __launch_bounds__(NT) void k_pool2_grad(const float *__restrict__ x, const float *__restrict__ dy, int n,
+                                                   int h, int w, int c, int accumulate, float *__restrict__ dx) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int ho = h / 2, wo = w / 2;
+    const int64_t tot = (int64_t)n * ho * wo * c;
+    if (i >= tot) return;
+    const int ch = (int)(i % c);
+    const int64_t pix = i / c;
+    const int xo = (int)(pix % wo), yo = (int)((pix / wo) % ho), nn = (int)(pix / ((int64_t)wo * ho));
+    const int64_t o00 = (((int64_t)nn * h + 2 * yo) * w + 2 * xo) * c + ch;
+    const int64_t off[4] = {o00, o00 + c, o00 + (int64_t)w * c, o00 + (int64_t)w * c + c};
+    float m = x[off[0]];
+    for (int q = 1; q < 4; ++q) m = fmaxf(m, x[off[q]]);
+    bool taken = false;
+    for (int q = 0; q < 4; ++q) {
+        float g = 0.f;
+        if (!taken && x[off[q]] == m) {
+            g = dy[i];
+            taken = true;
+        }
+        dx[off[q]] = accumulate ? dx[off[q]] + g : g;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_up2(const float *__restrict__ x, int n, int h, int w, int c,
+                                            float *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t tot = (int64_t)n * (2 * h) * (2 * w) * c;
+    if (i >= tot) return;
+    const int ch = (int)(i % c);
+    const int64_t pix = i / c;
+    const int xo = (int)(pix % (2 * w)), yo = (int)((pix / (2 * w)) % (2 * h)), nn = (int)(pix / ((int64_t)4 * w * h));
+    y[i] = x[(((int64_t)nn * h + yo / 2) * w + xo / 2) * c + ch];
+}
+
+__global__ __launch_bounds__(NT) void k_up2_grad(const float *__restrict__ dy, int n, int h, int w, int c,
+                                                 float *__restrict__ dx) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t tot = (int64_t)n * h * w * c;
+    if (i >= tot) return;
+    const int ch = (int)(i % c);
+    const int64_t pix = i / c;
+    const int xx = (int)(pix % w), yy = (int)((pix / w) % h), nn = (int)(pix / ((int64_t)w * h));
+    const int W2 = 2 * w;
+    const int64_t b = (((int64_t)nn * 2 * h + 2 * yy) * W2 + 2 * xx) * c + ch;
+    dx[i] = dy[b] + dy[b + c] + dy[b + (int64_t)W2 * c] + dy[b + (int64_t)W2 * c + c];
+}
+
+// out[p] = [a[p] (ca channels), b[p] (cb channels)]
+__global__ __launch_bounds__(NT) void k_concat(const float *__restrict__ a, int ca, const float *__restrict__ b, int cb,
+                                               int64_t P, float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int c = ca + cb;
+    if (i >= P * c) return;
+    const int ch = (int)(i % c);
+    const int64_t p = i / c;
+    out[i] = ch < ca ? a[p * ca + ch] : b[p * cb + ch - ca];
+}
+
+// da[p] = d[p][:ca]; db[p] (+)= d[p][ca:]
+__global__ __launch_bounds__(NT) void k_split(const float *__restrict__ d, int ca, int cb, int64_t P,
+                                              float *__restrict__ da, float *__restrict__ db, int accumulate_b) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int c = ca + cb;
+    if (i >= P * c) return;
+    const int ch = (int)(i % c);
+    const int64_t p = i / c;
+    if (ch < ca) {
+        da[p * ca + ch] = d[i];
+    } else {
+        const int64_t o = p * cb + ch - ca;
+        db[o] = accumulate_b ? db[o] + d[i] : d[i];
+    }
+}
+
+// network input [n][h][w] -> [n][h][w][4] (channel 0)
+__global__ __launch_bounds__(NT) void k_pad_input(const float *__restrict__ x, int64_t P, float *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i >= P) return;
+    reinterpret_cast<float4 *>(y)[i] = float4{x[i], 0.f, 0.f, 0.f};
+}
+
+// 1x1 head: y[p] = b + sum_c w[c] x[p][c]
+__global__ __launch_bounds__(NT) void k_head(const float *__restrict__ x, int c, int64_t P, const float *__restrict__ wt,
+                                             const float *__restrict__ b, float *__restrict__ y) {
+    const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (p >= P) return;
+    float s = b[0];
+    for (int k = 0; k < c; ++k) s += wt[k] * x[p * c + k];
+    y[p] = s;
+}
+
+// head backward: dx[p][c] = w[c] dy[p] [x > 0]; per-block partials of dw[c] and db
+__global__ __launch_bounds__(NT) void k_head_grad(const float *__restrict__ x, int c, int64_t P,
+                                                  const float *__restrict__ wt, const float *__restrict__ dy,
+                                                  float *__restrict__ dx, float *__restrict__ part) {
+    __shared__ float sh[NT];
+    const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const float g = p < P ? dy[p] : 0.f;
+    for (int k = 0; k <= c; ++k) {
+        float v = 0.f;
+        if (p < P) {
+            if (k < c) {
+                const float xv = x[p * c + k];
+                dx[p * c + k] = xv > 0.f ? wt[k] * g : 0.f;
+                v = g * xv;
+            } else {
+                v = g;
+            }
+        }
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int m = NT / 2; m >= 1; m >>= 1) {
+            if (threadIdx.x < m) sh[threadIdx.x] += sh[threadIdx.x + m];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (c + 1) + k] = sh[0];
+        __syncthreads();
+    }
+}
+
+// MSE: dy = 2 (y - t) / count; per-block partial sums of (y - t)^2
+__global__ __launch_bounds__(NT) void k_mse(const float *__restrict__ y, const float *__restrict__ t, int64_t count,
+                                            float *__restrict__ dy, double *__restrict__ part) {
+    __shared__ double sh[NT];
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    double v = 0.0;
+    if (i < count) {
+        const float d = y[i] - t[i];
+        dy[i] = 2.f * d / (float)count;
+        v = (double)d * (double)d;
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int m = NT / 2; m >= 1; m >>= 1) {
+        if (threadIdx.x < m) sh[threadIdx.x] += sh[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(NT) void k_sum_double(const double *__restrict__ part, int n, double scale,
+                                                   double *__restrict__ out) {
+    __shared__ double sh[NT];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int m = NT / 2; m >= 1; m >>= 1) {
+        if (threadIdx.x < m) sh[threadIdx.x] += sh[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0] * scale;
+}
+
+// head gradient partials -> grads (fixed order)
+__global__ void k_head_reduce(const float *__restrict__ part, int nblk, int c, float *__restrict__ dw,
+                              float *__restrict__ db) {
+    const int k = threadIdx.x;
+    if (k > c) return;
+    float s = 0.f;
+    for (int i = 0; i < nblk; ++i) s += part[(int64_t)i * (c + 1) + k];
+    if (k < c) dw[k] = s;
+    else db[0] = s;
+}
+
+// Adam (Kingma & Ba 2015) with bias correction folded into lr_t and eps_t
+__global__ __launch_bounds__(NT) void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                                             float *__restrict__ v, int64_t n, float lr_t, float eps_t) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr_t * mi / (sqrtf(vi) + eps_t);
+}
+
+unsigned nblocks(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+
+// ------------------------------------------------------------------ launchers
+hipError_t conv3x3(const float *x, int n, int h, int w, int cin, const uint16_t *wt, const float *bias, int cout,
+                   int relu, const float *mask, int accumulate, float *y, hipStream_t st) {
+    const int64_t P = (int64_t)n * h * w;
+    const unsigned gx = (unsigned)((P + 63) / 64);
+    if (cout % 64 == 0) k_conv3x3<4><<<dim3(gx, cout / 64), NT, 0, st>>>(x, n, h, w, cin, wt, bias, cout, relu, mask, accumulate, y);
+    else if (cout % 32 == 0) k_conv3x3<2><<<dim3(gx, cout / 32), NT, 0, st>>>(x, n, h, w, cin, wt, bias, cout, relu, mask, accumulate, y);
+    else k_conv3x3<1><<<dim3(gx, (cout + 15) / 16), NT, 0, st>>>(x, n, h, w, cin, wt, bias, cout, relu, mask, accumulate, y);
+    return hipGetLastError();
+}
+
+int64_t gw_splits(int n, int h, int w) { return ((int64_t)n * h * w + GW_PIX - 1) / GW_PIX; }
+
+hipError_t conv3x3_grad_weight(const float *x, const float *dy, int n, int h, int w, int cin, int cout, float *part,
+                               float *dw, float *db, hipStream_t st) {
+    const int K = 9 * cin;
+    const int64_t splits = gw_splits(n, h, w);
+    k_conv3x3_gw<<<dim3((K + 63) / 64, (cout + 63) / 64, (unsigned)splits), NT, 0, st>>>(x, dy, n, h, w, cin, cout, part);
+    const int64_t len = (int64_t)cout * K;
+    k_sum_parts<<<nblocks(len), NT, 0, st>>>(part, (int)splits, len, dw);
+    k_colsum<<<cout, NT, 0, st>>>(dy, (int64_t)n * h * w, cout, db);
+    return hipGetLastError();
+}
+
+} // namespace
+
+// ======================================================================= network
+struct ConvLayer {
+    int cin, cout, h, w;       // input channels, output channels, spatial size
+    int64_t w_off, b_off;      // offsets into the master parameter vector
+    uint16_t *wbf = nullptr;   // bf16 weights [cout][3][3][cin]
+    uint16_t *wflip = nullptr; // bf16 flipped weights [cin][3][3][cout]
+};
+
+struct ivx_unet {
+    int L = 0, base = 0, maxb = 0, H = 0, W = 0;
+    std::vector<int> ch;
+    std::vector<ConvLayer> conv; // enc0a enc0b enc1a ... dec{L-2}a dec{L-2}b ... dec0a dec0b
+    int64_t head_w = 0, head_b = 0, nparam = 0;
+    int64_t step = 0;
+    std::vector<void *> bufs;
+    float *params = nullptr, *grads = nullptr, *mom = nullptr, *vel = nullptr;
+    float *xin = nullptr, *xin_grad_dummy = nullptr;
+    std::vector<float *> ea, eb, pool, up, cat, da, db; // forward activations
+    std::vector<float *> g_ea, g_eb, g_pool, g_up, g_cat, g_da, g_db;
+    float *out = nullptr, *gout = nullptr;
+    float *part = nullptr;
+    int64_t part_len = 0;
+    float *head_part = nullptr;
+    double *loss_part = nullptr, *loss = nullptr;
+};
+
+namespace {
+
+template <typename T> ivx_status ualloc(ivx_unet *u, T **p, int64_t count) {
+    void *q = nullptr;
+    if (hipMalloc(&q, (size_t)(count > 0 ? count : 1) * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(IVX_ENOMEM, "hipMalloc failed in ivx_unet_create");
+    }
+    u->bufs.push_back(q);
+    *p = (T *)q;
+    return IVX_OK;
+}
+
+void ufree(ivx_unet *u) {
+    for (void *p : u->bufs) (void)hipFree(p);
+    u->bufs.clear();
+}
+
+int lvl_h(const ivx_unet *u, int l) { return u->H >> l; }
+int lvl_w(const ivx_unet *u, int l) { return u->W >> l; }
+
+// conv layer indices
+int enc_a(int l) { return 2 * l; }
+int enc_b(int l) { return 2 * l + 1; }
+int dec_a(const ivx_unet *u, int l) { return 2 * u->L + 2 * (u->L - 2 - l); }
+int dec_b(const ivx_unet *u, int l) { return dec_a(u, l) + 1; }
+
+hipError_t refresh_bf16(ivx_unet *u, hipStream_t st) {
+    for (ConvLayer &c : u->conv) {
+        const int64_t nw = (int64_t)9 * c.cin * c.cout;
+        k_to_bf16<<<nblocks(nw), NT, 0, st>>>(u->params + c.w_off, nw, c.wbf);
+        k_flip<<<nblocks(nw), NT, 0, st>>>(c.wbf, c.cin, c.cout, c.wflip);
+    }
+    return hipGetLastError();
+}
+
+hipError_t forward(ivx_unet *u, const float *x, int B, hipStream_t st) {
+    const int64_t P0 = (int64_t)B * u->H * u->W;
+    k_pad_input<<<nblocks(P0), NT, 0, st>>>(x, P0, u->xin);
+    hipError_t e;
+    const float *hin = u->xin;
+    for (int l = 0; l < u->L; ++l) {
+        const int h = lvl_h(u, l), w = lvl_w(u, l);
+        if (l > 0) {
+            const int64_t tot = (int64_t)B * h * w * u->ch[l - 1];
+            k_pool2<<<nblocks(tot), NT, 0, st>>>(u->eb[l - 1], B, 2 * h, 2 * w, u->ch[l - 1], u->pool[l]);
+            hin = u->pool[l];
+        }
+        const ConvLayer &a = u->conv[enc_a(l)], &b = u->conv[enc_b(l)];
+        if ((e = conv3x3(hin, B, h, w, a.cin, a.wbf, u->params + a.b_off, a.cout, 1, nullptr, 0, u->ea[l], st)) != hipSuccess) return e;
+        if ((e = conv3x3(u->ea[l], B, h, w, b.cin, b.wbf, u->params + b.b_off, b.cout, 1, nullptr, 0, u->eb[l], st)) != hipSuccess) return e;
+    }
+    const float *hcur = u->eb[u->L - 1];
+    for (int l = u->L - 2; l >= 0; --l) {
+        const int h = lvl_h(u, l), w = lvl_w(u, l);
+        const int64_t P = (int64_t)B * h * w;
+        k_up2<<<nblocks(P * u->ch[l + 1]), NT, 0, st>>>(hcur, B, h / 2, w / 2, u->ch[l + 1], u->up[l]);
+        k_concat<<<nblocks(P * (u->ch[l + 1] + u->ch[l])), NT, 0, st>>>(u->up[l], u->ch[l + 1], u->eb[l], u->ch[l], P, u->cat[l]);
+        const ConvLayer &a = u->conv[dec_a(u, l)], &b = u->conv[dec_b(u, l)];
+        if ((e = conv3x3(u->cat[l], B, h, w, a.cin, a.wbf, u->params + a.b_off, a.cout, 1, nullptr, 0, u->da[l], st)) != hipSuccess) return e;
+        if ((e = conv3x3(u->da[l], B, h, w, b.cin, b.wbf, u->params + b.b_off, b.cout, 1, nullptr, 0, u->db[l], st)) != hipSuccess) return e;
+        hcur = u->db[l];
+    }
+    const float *top = u->L > 1 ? u->db[0] : u->eb[0];
+    k_head<<<nblocks(P0), NT, 0, st>>>(top, u->ch[0], P0, u->params + u->head_w, u->params + u->head_b, u->out);
+    return hipGetLastError();
+}
+
+// conv layer backward: weight/bias gradients into grads, input gradient (masked by the
+// input activation > 0, accumulated if asked) unless gin is null
+hipError_t conv_backward(ivx_unet *u, const ConvLayer &c, int B, const float *in, const float *gout, float *gin,
+                         int accumulate, hipStream_t st) {
+    hipError_t e;
+    if ((e = conv3x3_grad_weight(in, gout, B, c.h, c.w, c.cin, c.cout, u->part, u->grads + c.w_off, u->grads + c.b_off,
+                                 st)) != hipSuccess)
+        return e;
+    if (gin) return conv3x3(gout, B, c.h, c.w, c.cout, c.wflip, nullptr, c.cin, 0, in, accumulate, gin, st);
+    return hipSuccess;
+}
+
+hipError_t backward(ivx_unet *u, int B, hipStream_t st) {
+    hipError_t e;
+    const int64_t P0 = (int64_t)B * u->H * u->W;
+    const float *top = u->L > 1 ? u->db[0] : u->eb[0];
+    float *gtop = u->L > 1 ? u->g_db[0] : u->g_eb[0];
+    const unsigned hb = nblocks(P0);
+    k_head_grad<<<hb, NT, 0, st>>>(top, u->ch[0], P0, u->params + u->head_w, u->gout, gtop, u->head_part);
+    k_head_reduce<<<1, 64, 0, st>>>(u->head_part, (int)hb, u->ch[0], u->grads + u->head_w, u->grads + u->head_b);
+    // decoder, top level first
+    for (int l = 0; l <= u->L - 2; ++l) {
+        const int h = lvl_h(u, l), w = lvl_w(u, l);
+        const int64_t P = (int64_t)B * h * w;
+        const ConvLayer &a = u->conv[dec_a(u, l)], &b = u->conv[dec_b(u, l)];
+        if ((e = conv_backward(u, b, B, u->da[l], u->g_db[l], u->g_da[l], 0, st)) != hipSuccess) return e;
+        if ((e = conv_backward(u, a, B, u->cat[l], u->g_da[l], u->g_cat[l], 0, st)) != hipSuccess) return e;
+        // skip half goes to the encoder output of this level, upsampled half to the level below
+        k_split<<<nblocks(P * (u->ch[l + 1] + u->ch[l])), NT, 0, st>>>(u->g_cat[l], u->ch[l + 1], u->ch[l], P,
+                                                                        u->g_up[l], u->g_eb[l], 0);
+        float *below = (l + 1 <= u->L - 2) ? u->g_db[l + 1] : u->g_eb[u->L - 1];
+        k_up2_grad<<<nblocks((int64_t)B * (h / 2) * (w / 2) * u->ch[l + 1]), NT, 0, st>>>(u->g_up[l], B, h / 2, w / 2,
+                                                                                           u->ch[l + 1], below);
+    }
+    // encoder, bottom level first; g_eb[l] for l < L-1 already holds the skip gradient
+    for (int l = u->L - 1; l >= 0; --l) {
+        const int h = lvl_h(u, l), w = lvl_w(u, l);
+        const ConvLayer &a = u->conv[enc_a(l)], &b = u->conv[enc_b(l)];
+        if ((e = conv_backward(u, b, B, u->ea[l], u->g_eb[l], u->g_ea[l], 0, st)) != hipSuccess) return e;
+        if (l == 0) {
+            if ((e = conv_backward(u, a, B, u->xin, u->g_ea[l], nullptr, 0, st)) != hipSuccess) return e;
+        } else {
+            if ((e = conv_backward(u, a, B, u->pool[l], u->g_ea[l], u->g_pool[l], 0, st)) != hipSuccess) return e;
+            const int64_t tot = (int64_t)B * h * w * u->ch[l - 1];
+            k_pool2_grad<<<nblocks(tot), NT, 0, st>>>(u->eb[l - 1], u->g_pool[l], B, 2 * h, 2 * w, u->ch[l - 1], 1,
+                                                      u->g_eb[l - 1]);
+        }
+    }
+    return hipGetLastError();
+}
+
+ivx_status check_net(const ivx_unet *u) {
+    if (!u) return set_error(IVX_EINVAL, "network is NULL");
+    return IVX_OK;
+}
+
+#define UHIP(call)                                                                            \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return set_error(IVX_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+} // namespace
+
+extern "C" {
+
+ivx_status ivx_unet_create(int32_t levels, int32_t base, int32_t max_batch, int32_t height, int32_t width, uint64_t seed,
+                           ivx_unet **out) {
+    if (!out) return set_error(IVX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (levels < 1 || levels > 5 || base < 16 || base % 16 || max_batch < 1 || height < 1 || width < 1 ||
+        height % (1 << (levels - 1)) || width % (1 << (levels - 1)))
+        return set_error(IVX_EINVAL, "bad network geometry");
+    ivx_unet *u = new ivx_unet();
+    u->L = levels;
+    u->base = base;
+    u->maxb = max_batch;
+    u->H = height;
+    u->W = width;
+    for (int l = 0; l < levels; ++l) u->ch.push_back(base << l);
+    int64_t off = 0;
+    auto add_conv = [&](int cin, int cout, int l) {
+        ConvLayer c;
+        c.cin = cin;
+        c.cout = cout;
+        c.h = height >> l;
+        c.w = width >> l;
+        c.w_off = off;
+        off += (int64_t)9 * cin * cout;
+        c.b_off = off;
+        off += cout;
+        u->conv.push_back(c);
+    };
+    int prev = 4;
+    for (int l = 0; l < levels; ++l) {
+        add_conv(prev, u->ch[l], l);
+        add_conv(u->ch[l], u->ch[l], l);
+        prev = u->ch[l];
+    }
+    for (int l = levels - 2; l >= 0; --l) {
+        add_conv(u->ch[l + 1] + u->ch[l], u->ch[l], l);
+        add_conv(u->ch[l], u->ch[l], l);
+    }
+    u->head_w = off;
+    off += u->ch[0];
+    u->head_b = off;
+    off += 1;
+    u->nparam = off;
+    ivx_status s;
+    const int64_t B = max_batch;
+    auto fail = [&](ivx_status st) {
+        ufree(u);
+        delete u;
+        return st;
+    };
+    if ((s = ualloc(u, &u->params, off)) || (s = ualloc(u, &u->grads, off)) || (s = ualloc(u, &u->mom, off)) ||
+        (s = ualloc(u, &u->vel, off)))
+        return fail(s);
+    for (ConvLayer &c : u->conv) {
+        if ((s = ualloc(u, &c.wbf, (int64_t)9 * c.cin * c.cout)) || (s = ualloc(u, &c.wflip, (int64_t)9 * c.cin * c.cout)))
+            return fail(s);
+    }
+    const int64_t P0 = B * height * width;
+    if ((s = ualloc(u, &u->xin, P0 * 4))) return fail(s);
+    u->ea.resize(levels); u->eb.resize(levels); u->pool.resize(levels); u->up.resize(levels); u->cat.resize(levels);
+    u->da.resize(levels); u->db.resize(levels);
+    u->g_ea.resize(levels); u->g_eb.resize(levels); u->g_pool.resize(levels); u->g_up.resize(levels);
+    u->g_cat.resize(levels); u->g_da.resize(levels); u->g_db.resize(levels);
+    int64_t maxpart = 1;
+    for (int l = 0; l < levels; ++l) {
+        const int64_t P = B * (height >> l) * (width >> l);
+        const int c = u->ch[l];
+        if ((s = ualloc(u, &u->ea[l], P * c)) || (s = ualloc(u, &u->eb[l], P * c)) || (s = ualloc(u, &u->g_ea[l], P * c)) ||
+            (s = ualloc(u, &u->g_eb[l], P * c)))
+            return fail(s);
+        if (l > 0 && ((s = ualloc(u, &u->pool[l], P * u->ch[l - 1])) || (s = ualloc(u, &u->g_pool[l], P * u->ch[l - 1]))))
+            return fail(s);
+        if (l <= levels - 2) {
+            const int cc = u->ch[l + 1] + c;
+            if ((s = ualloc(u, &u->up[l], P * u->ch[l + 1])) || (s = ualloc(u, &u->cat[l], P * cc)) ||
+                (s = ualloc(u, &u->da[l], P * c)) || (s = ualloc(u, &u->db[l], P * c)) ||
+                (s = ualloc(u, &u->g_up[l], P * u->ch[l + 1])) || (s = ualloc(u, &u->g_cat[l], P * cc)) ||
+                (s = ualloc(u, &u->g_da[l], P * c)) || (s = ualloc(u, &u->g_db[l], P * c)))
+                return fail(s);
+        }
+    }
+    for (const ConvLayer &c : u->conv) maxpart = std::max<int64_t>(maxpart, gw_splits((int)B, c.h, c.w) * c.cout * 9 * c.cin);
+    if ((s = ualloc(u, &u->part, maxpart)) || (s = ualloc(u, &u->out, P0)) || (s = ualloc(u, &u->gout, P0)) ||
+        (s = ualloc(u, &u->head_part, (int64_t)nblocks(P0) * (u->ch[0] + 1))) ||
+        (s = ualloc(u, &u->loss_part, (int64_t)nblocks(P0))) || (s = ualloc(u, &u->loss, 1)))
+        return fail(s);
+    u->part_len = maxpart;
+    // He-normal initialisation, zero biases
+    std::vector<float> h(off, 0.f);
+    std::mt19937_64 rng(seed);
+    for (const ConvLayer &c : u->conv) {
+        std::normal_distribution<double> nd(0.0, std::sqrt(2.0 / (9.0 * c.cin)));
+        for (int64_t i = 0; i < (int64_t)9 * c.cin * c.cout; ++i) h[c.w_off + i] = (float)nd(rng);
+    }
+    {
+        std::normal_distribution<double> nd(0.0, std::sqrt(1.0 / u->ch[0]));
+        for (int k = 0; k < u->ch[0]; ++k) h[u->head_w + k] = (float)nd(rng);
+    }
+    if ((s = ivx_unet_set_params(u, h.data())) != IVX_OK) return fail(s);
+    *out = u;
+    return IVX_OK;
+}
+
+ivx_status ivx_unet_destroy(ivx_unet *u) {
+    if (!u) return IVX_OK;
+    ufree(u);
+    delete u;
+    return IVX_OK;
+}
+
+int64_t ivx_unet_param_count(const ivx_unet *u) { return u ? u->nparam : -1; }
+
+ivx_status ivx_unet_get_params(const ivx_unet *u, float *params) {
+    ivx_status s = check_net(u);
+    if (s) return s;
+    if (!params) return set_error(IVX_EINVAL, "params is NULL");
+    UHIP(hipMemcpy(params, u->params, u->nparam * sizeof(float), hipMemcpyDefault));
+    return IVX_OK;
+}
+
+ivx_status ivx_unet_set_params(ivx_unet *u, const float *params) {
+    ivx_status s = check_net(u);
+    if (s) return s;
+    if (!params) return set_error(IVX_EINVAL, "params is NULL");
+    UHIP(hipMemcpy(u->params, params, u->nparam * sizeof(float), hipMemcpyDefault));
+    UHIP(hipMemset(u->mom, 0, u->nparam * sizeof(float)));
+    UHIP(hipMemset(u->vel, 0, u->nparam * sizeof(float)));
+    u->step = 0;
+    UHIP(refresh_bf16(u, nullptr));
+    UHIP(hipDeviceSynchronize());
+    return IVX_OK;
+}
+
+ivx_status ivx_unet_forward(ivx_unet *u, const float *x, float *y, int32_t batch, void *stream) {
+    ivx_status s = check_net(u);
+    if (s) return s;
+    if (!x || !y || batch < 1 || batch > u->maxb) return set_error(IVX_EINVAL, "bad forward arguments");
+    hipStream_t st = (hipStream_t)stream;
+    UHIP(forward(u, x, batch, st));
+    UHIP(hipMemcpyAsync(y, u->out, (size_t)batch * u->H * u->W * sizeof(float), hipMemcpyDeviceToDevice, st));
+    return IVX_OK;
+}
+
+ivx_status ivx_unet_train_step(ivx_unet *u, const float *x, const float *target, int32_t batch, float lr, double *loss,
+                               void *stream) {
+    ivx_status s = check_net(u);
+    if (s) return s;
+    if (!x || !target || batch < 1 || batch > u->maxb || !(lr > 0.f)) return set_error(IVX_EINVAL, "bad train arguments");
+    hipStream_t st = (hipStream_t)stream;
+    UHIP(forward(u, x, batch, st));
+    const int64_t P0 = (int64_t)batch * u->H * u->W;
+    k_mse<<<nblocks(P0), NT, 0, st>>>(u->out, target, P0, u->gout, u->loss_part);
+    k_sum_double<<<1, NT, 0, st>>>(u->loss_part, (int)nblocks(P0), 1.0 / (double)P0, u->loss);
+    UHIP(backward(u, batch, st));
+    u->step += 1;
+    const double b1t = 1.0 - std::pow(0.9, (double)u->step), b2t = 1.0 - std::pow(0.999, (double)u->step);
+    // m_hat / (sqrt(v_hat) + eps) = (sqrt(b2t) / b1t) m / (sqrt(v) + eps sqrt(b2t))
+    const float lr_t = (float)(lr * std::sqrt(b2t) / b1t), eps_t = (float)(1e-8 * std::sqrt(b2t));
+    k_adam<<<nblocks(u->nparam), NT, 0, st>>>(u->params, u->grads, u->mom, u->vel, u->nparam, lr_t, eps_t);
+    UHIP(refresh_bf16(u, st));
+    if (loss) {
+        UHIP(hipMemcpyAsync(loss, u->loss, sizeof(double), hipMemcpyDefault, st));
+        hipPointerAttribute_t a;
+        bool dev = false;
+        if (hipPointerGetAttributes(&a, loss) == hipSuccess) dev = a.type == hipMemoryTypeDevice;
+        else (void)hipGetLastError();
+        if (!dev) UHIP(hipStreamSynchronize(st));
+    }
+    return IVX_OK;
+}
+
+ivx_status ivx_unet_loss_grad(ivx_unet *u, const float *x, const float *target, int32_t batch, float *grads, double *loss,
+                              void *stream) {
+    ivx_status s = check_net(u);
+    if (s) return s;
+    if (!x || !target || !grads || batch < 1 || batch > u->maxb) return set_error(IVX_EINVAL, "bad loss_grad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    UHIP(forward(u, x, batch, st));
+    const int64_t P0 = (int64_t)batch * u->H * u->W;
+    k_mse<<<nblocks(P0), NT, 0, st>>>(u->out, target, P0, u->gout, u->loss_part);
+    k_sum_double<<<1, NT, 0, st>>>(u->loss_part, (int)nblocks(P0), 1.0 / (double)P0, u->loss);
+    UHIP(backward(u, batch, st));
+    UHIP(hipMemcpyAsync(grads, u->grads, u->nparam * sizeof(float), hipMemcpyDefault, st));
+    if (loss) UHIP(hipMemcpyAsync(loss, u->loss, sizeof(double), hipMemcpyDefault, st));
+    UHIP(hipStreamSynchronize(st));
+    return IVX_OK;
+}
+
+// ------------------------------------------------------------------ single layers
+ivx_status ivx_nn_conv3x3(const float *x, int32_t n, int32_t h, int32_t w, int32_t cin, const uint16_t *weight,
+                          const float *bias, int32_t cout, int32_t relu, const float *mask, int32_t accumulate, float *y,
+                          void *stream) {
+    if (!x || !weight || !y || n < 1 || h < 1 || w < 1 || cin < 4 || cin % 4 || cout < 16 || cout % 16)
+        return set_error(IVX_EINVAL, "bad conv3x3 arguments");
+    UHIP(conv3x3(x, n, h, w, cin, weight, bias, cout, relu, mask, accumulate, y, (hipStream_t)stream));
+    return IVX_OK;
+}
+
+ivx_status ivx_nn_conv3x3_grad_weight(const float *x, const float *dy, int32_t n, int32_t h, int32_t w, int32_t cin,
+                                      int32_t cout, float *dw, float *db, void *stream) {
+    if (!x || !dy || !dw || !db || n < 1 || h < 1 || w < 1 || cin < 1 || cout < 1)
+        return set_error(IVX_EINVAL, "bad conv3x3_grad_weight arguments");
+    hipStream_t st = (hipStream_t)stream;
+    float *part = nullptr;
+    UHIP(hipMalloc(&part, (size_t)gw_splits(n, h, w) * cout * 9 * cin * sizeof(float)));
+    hipError_t e = conv3x3_grad_weight(x, dy, n, h, w, cin, cout, part, dw, db, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(part);
+    if (e != hipSuccess) return set_error(IVX_EHIP, std::string("conv3x3_grad_weight: ") + hipGetErrorString(e));
+    return IVX_OK;
+}
+
+ivx_status ivx_nn_conv3x3_flip(const uint16_t *weight, int32_t cin, int32_t cout, uint16_t *flipped, void *stream) {
+    if (!weight || !flipped || cin < 1 || cout < 1) return set_error(IVX_EINVAL, "bad flip arguments");
+    const int64_t nw = (int64_t)9 * cin * cout;
+    k_flip<<<nblocks(nw), NT, 0, (hipStream_t)stream>>>(weight, cin, cout, flipped);
+    UHIP(hipGetLastError());
+    return IVX_OK;
+}
+
+ivx_status ivx_nn_to_bf16(const float *x, int64_t count, uint16_t *out, void *stream) {
+    if (!x || !out || count < 0) return set_error(IVX_EINVAL, "bad to_bf16 arguments");
+    if (count) k_to_bf16<<<nblocks(count), NT, 0, (hipStream_t)stream>>>(x, count, out);
+    UHIP(hipGetLastError());
+    return IVX_OK;
+}
+
+ivx_status ivx_nn_pool2(const float *x, int32_t n, int32_t h, int32_t w, int32_t c, float *y, void *stream) {
+    if (!x || !y || n < 1 || h < 2 || w < 2 || h % 2 || w % 2 || c < 1) return set_error(IVX_EINVAL, "bad pool2 arguments");
+    k_pool2<<<nblocks((int64_t)n * (h / 2) * (w / 2) * c), NT, 0, (hipStream_t)stream>>>(x, n, h, w, c, y);
+    UHIP(hipGetLastError());
+    return IVX_OK;
+}
+
+ivx_status ivx_nn_pool2_grad(const float *x, const float *dy, int32_t n, int32_t h, int32_t w, int32_t c,
+                             int32_t accumulate, float *dx, void *stream) {
+    if (!x || !dy || !dx || n < 1 || h < 2 || w < 2 || h % 2 || w % 2 || c < 1)
+        return set_error(IVX_EINVAL, "bad pool2_grad arguments");
+    k_pool2_grad<<<nblocks((int64_t)n * (h / 2) * (w / 2) * c), NT, 0, (hipStream_t)stream>>>(x, dy, n, h, w, c,
+                                                                                              accumulate, dx);
+    UHIP(hipGetLastError());
+    return IVX_OK;
+}
+
+ivx_status ivx_nn_up2(const float *x, int32_t n, int32_t h, int32_t w, int32_t c, float *y, void *stream) {
+    if (!x || !y || n < 1 || h < 1 || w < 1 || c < 1) return set_error(IVX_EINVAL, "bad up2 arguments");
+    k_up2<<<nblocks((int64_t)n * 4 * h * w * c), NT, 0, (hipStream_t)stream>>>(x, n, h, w, c, y);
+    UHIP(hipGetLastError());
+    return IVX_OK;
+}
+
+ivx_status ivx_nn_up2_grad(const float *dy, int32_t n, int32_t h, int32_t w, int32_t c, float *dx, void *stream) {
+    if (!dy || !dx || n < 1 || h < 1 || w < 1 || c < 1) return set_error(IVX_EINVAL, "bad up2_grad arguments");
+    k_up2_grad<<<nblocks((int64_t)n * h * w * c), NT, 0, (hipStream_t)stream>>>(dy, n, h, w, c, dx);
+    UHIP(hipGetLastError());
+    return IVX_OK;
+}
+
+} // extern "C"
