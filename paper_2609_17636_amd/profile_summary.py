@@ -1,6 +1,8 @@
 """Summarise a rocprofv3 results database (kernel trace, optionally PMC counters).
 
     python -m paper_2609_17636_amd.profile_summary RESULTS.db [--last N] [--kernel REGEX]
+    python -m paper_2609_17636_amd.profile_summary --traffic FETCH.db WRITE.db COPY_FETCH.db \
+        COPY_WRITE.db --kernel REGEX --last N [--note TEXT]
 
 Per kernel: dispatch count, average / min / max duration (us) and share of the total,
 over all dispatches or over the last N dispatches of each kernel (the timed region of
@@ -74,13 +76,72 @@ def summarise(db: str, last: int = 0, kernel: str = "") -> str:
     return "\n".join(lines)
 
 
+def counter_avg(db: str, kernel: str, counter: str, last: int = 0) -> float:
+    """Per-dispatch average of one PMC counter over the (last N) dispatches of the kernels
+    matching `kernel`."""
+    con, rows = kernel_rows(db)
+    pmc = pmc_by_dispatch(con)
+    vals = [pmc[d][counter] for name, _, _, d in rows if re.search(kernel, name) and counter in pmc.get(d, {})]
+    if last:
+        vals = vals[-last:]
+    if not vals:
+        raise SystemExit(f"no {counter} values for /{kernel}/ in {db}")
+    return sum(vals) / len(vals)
+
+
+COPY_BYTES = 1 << 30   # bytes read and written by one dispatch of bench.py --copy-probe
+
+
+def traffic_report(fetch_db, write_db, copy_fetch_db, copy_write_db, kernel, last, note="", blocking="") -> str:
+    """HBM bytes per launch of `kernel` from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    each scaled by the factor that makes the same counter read the known 1 GiB of the
+    calibration copy."""
+    import hashlib
+    import os
+
+    f_k = counter_avg(fetch_db, kernel, "FETCH_SIZE", last)
+    w_k = counter_avg(write_db, kernel, "WRITE_SIZE", last)
+    f_c = counter_avg(copy_fetch_db, "copyBuffer", "FETCH_SIZE")
+    w_c = counter_avg(copy_write_db, "copyBuffer", "WRITE_SIZE")
+    ff = COPY_BYTES / (f_c * 1024.0)
+    fw = COPY_BYTES / (w_c * 1024.0)
+    fetch_b = f_k * 1024.0 * ff
+    write_b = w_k * 1024.0 * fw
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "ivx_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    out = [f"# HBM traffic of /{kernel}/ per launch (rocprofv3 PMC, last {last} dispatches)"]
+    if note:
+        out.append(f"# {note}")
+    if blocking:
+        out.append(f"blocking: {blocking}")
+    out += [f"kernel: {kernel}",
+            f"fetch_kib_per_dispatch: {f_k:.1f}",
+            f"write_kib_per_dispatch: {w_k:.1f}",
+            f"copy_fetch_kib_per_dispatch: {f_c:.1f}",
+            f"copy_write_kib_per_dispatch: {w_c:.1f}",
+            f"fetch_factor: {ff:.4f}",
+            f"write_factor: {fw:.4f}",
+            f"fetch_bytes_per_launch: {fetch_b:.0f}",
+            f"write_bytes_per_launch: {write_b:.0f}",
+            f"traffic_bytes_per_launch: {fetch_b + write_b:.0f}",
+            f"kernel_source_sha256: {sha}"]
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("db")
+    ap.add_argument("db", nargs="?")
     ap.add_argument("--last", type=int, default=0)
     ap.add_argument("--kernel", default="")
+    ap.add_argument("--traffic", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"))
+    ap.add_argument("--note", default="")
+    ap.add_argument("--blocking", default="", help="gridding blocking the counters were taken with")
     a = ap.parse_args()
-    print(summarise(a.db, a.last, a.kernel))
+    if a.traffic:
+        print(traffic_report(*a.traffic, kernel=a.kernel, last=a.last, note=a.note,
+                             blocking=a.blocking))
+    else:
+        print(summarise(a.db, a.last, a.kernel))
 
 
 if __name__ == "__main__":
