@@ -19,7 +19,7 @@ import numpy as np
 
 from .build import lib_path
 
-__all__ = ["Plan", "Objective", "solve", "UNet", "load_library", "IvxError", "STATUS", "STAGES"]
+__all__ = ["Plan", "Objective", "solve", "DeviceSolver", "UNet", "load_library", "IvxError", "STATUS", "STAGES"]
 
 STATUS = {0: "IVX_OK", -1: "IVX_EINVAL", -2: "IVX_ENOMEM", -3: "IVX_EHIP", -4: "IVX_ENONFINITE",
           -5: "IVX_ESTATE"}
@@ -322,5 +322,5 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-from .solver import solve  # noqa: E402
+from .solver import DeviceSolver, solve  # noqa: E402
 from .unet import UNet  # noqa: E402

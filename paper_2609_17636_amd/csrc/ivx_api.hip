@@ -496,6 +496,11 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
 
 // ====================================================================== C ABI
 
+namespace ivx {
+// Number of sky variables of a plan (n_chan * n_sky^2), for the bounded solver.
+int64_t plan_sky_count(const ivx_plan *p) { return p ? (int64_t)p->g.C * p->g.N * p->g.N : 0; }
+} // namespace ivx
+
 extern "C" {
 
 const char *ivx_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,106 @@
+"""The device L-BFGS-B loop (include/ivx_lbfgsb.h) against the FP64 oracle L-BFGS-B.
+
+Driven by the FP64 build's objective, the device loop takes the same decisions as the
+oracle loop driven by the oracle's direct-DFT objective: the two objectives agree to
+~1e-12, so the iterates agree to ~1e-8 for the first iterations and both spend exactly the
+same number of evaluations.  The float build converges to the optimum the host scipy loop
+finds.  The regularised point-source field (lambda_r = 1e-2, x >= 0) makes the Cauchy
+search cross breakpoints, so the sorted-walk path runs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import lbfgsb as L
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2609_17636_amd import DeviceSolver, IvxError, Plan, solve  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def c1r():
+    return oracle.synthesize(synth.config_c1(lambda_r=1e-2))
+
+
+@pytest.fixture(scope="module")
+def reference(c1r):
+    p = c1r
+    fvals = []
+
+    def fun(x):
+        t, g = oracle.objective_grad(p, x)
+        fvals.append(t["Q_tot"])
+        return t["Q_tot"], g.reshape(-1)
+
+    r = L.lbfgsb(fun, np.zeros(p.n_chan * p.n_sky ** 2), maxiter=12)
+    return r, fvals
+
+
+@pytest.fixture(scope="module")
+def plan64(c1r):
+    plan = Plan.from_problem(c1r, precision="f64")
+    plan.set_problem_data(c1r)
+    return plan
+
+
+def test_device_iterates_follow_the_oracle(c1r, plan64, reference):
+    ref, fvals = reference
+    solver = DeviceSolver(plan64)
+    for k in (1, 2, 4, 8, 12):
+        r = solver.solve(maxiter=k)
+        x = r.x.cpu().numpy().reshape(-1)
+        xr = ref["history"][k][0]
+        rel = np.linalg.norm(x - xr) / np.linalg.norm(xr)
+        print(f"iteration {k}: rel {rel:.2e}, f {r.fun:.12e} vs {ref['history'][k][1]:.12e}, walks {r.n_walks}")
+        assert r.nit == k and r.message == "maxiter"
+        assert rel <= 1e-6
+        assert r.fun == pytest.approx(ref["history"][k][1], rel=1e-10)
+    # same evaluations, same values: the line searches took the same decisions
+    assert r.nfev == len(fvals)
+    np.testing.assert_allclose([f for _, f in r.history], fvals, rtol=1e-10)
+    assert r.n_walks >= 1
+
+
+def test_float_build_reaches_the_host_optimum(c1r):
+    plan = Plan.from_problem(c1r)
+    plan.set_problem_data(c1r)
+    dev = DeviceSolver(plan).solve()
+    host = solve(plan, maxiter=15000)
+    print("device", dev.fun, dev.nit, dev.nfev, dev.message, "host", host.fun, host.nit, host.nfev, host.message)
+    assert dev.message in ("pgtol", "ftol")
+    assert dev.fun == pytest.approx(host.fun, rel=1e-6)
+    assert float(dev.x.min()) >= 0.0
+
+
+def test_target_stop_and_history(c1r):
+    plan = Plan.from_problem(c1r)
+    plan.set_problem_data(c1r)
+    solver = DeviceSolver(plan)
+    full = solver.solve()
+    target = full.fun * (1 + 1e-3)
+    r = solver.solve(target=target)
+    assert r.message == "target" and r.reached_target
+    assert r.fun <= target and r.nfev < full.nfev
+    assert r.history[-1][1] == r.fun
+    ts = [t for t, _ in r.history]
+    assert all(b >= a for a, b in zip(ts, ts[1:]))
+
+
+def test_unbounded_mode_is_plain_lbfgs(c1r, plan64):
+    _, g0 = plan64.objective_grad(torch.zeros((1, c1r.n_sky, c1r.n_sky), dtype=torch.float64, device="cuda"))
+    g0 = float(g0.abs().max())
+    r = DeviceSolver(plan64).solve(positivity=False, gtol=1e-8 * g0, maxiter=5000)
+    print("unbounded", r.message, r.nit, r.nfev, r.fun)
+    assert r.message in ("pgtol", "ftol")
+    _, g = plan64.objective_grad(r.x)
+    assert float(g.abs().max()) <= 1e-5 * g0
+    assert float(r.x.min()) < 0.0          # noise drives some pixels negative without the bound
+
+
+def test_bad_options_are_rejected(plan64):
+    s = DeviceSolver(plan64, m_max=5)
+    with pytest.raises(IvxError):
+        s.solve(m=6)
