@@ -1,0 +1,55 @@
+"""Learned warm start on the warm-start mosaic (GPU), at a small scale.
+
+* the device solver converges on the mosaic and time-to-tolerance reaches the target from
+  both starts;
+* a start at the converged solution itself reaches the tolerance at the first
+  evaluation (the target bookkeeping of the measurement);
+* training the network on a few cold solutions lowers its loss, and its warm start begins
+  below the cold start's objective value Q_tot(0).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ws():
+    from paper_2609_17636_amd import warmstart
+
+    return warmstart
+
+
+@pytest.fixture(scope="module")
+def mosaic(ws):
+    return ws.Mosaic(autotune_ms=0)
+
+
+def test_cold_solve_converges_and_targets_are_met(ws, mosaic):
+    m = mosaic
+    m.simulate(ws.HELDOUT_BASE + 7)
+    r = m.solve()
+    assert r.message in ("pgtol", "ftol") and float(r.x.min()) >= 0.0
+    # starting at the solution: the first evaluation already meets (1 + 1e-4) J*
+    again = m.solve(x0=r.x, target=(1 + ws.TOL) * r.fun)
+    assert again.reached_target and again.nfev == 1
+
+
+def test_training_and_warm_start(ws, mosaic):
+    from paper_2609_17636_amd.unet import UNet
+
+    m = mosaic
+    D, X, info = ws.cold_solves(m, list(range(12)), maxiter=300)
+    assert all(i["nit"] == 300 or i["message"] in ("pgtol", "ftol") for i in info)
+    net = UNet(levels=4, base=32, max_batch=4, height=256, width=256, seed=1)
+    hist = ws.train(net, D, X, epochs=6, batch=4, lr=1e-3)
+    print("train mse", hist)
+    assert hist[-1] < 0.5 * hist[0]
+    held = ws.HELDOUT_BASE + 3
+    m.simulate(held)
+    j = m.solve().fun
+    row = ws.time_to_tolerance(m, net, held, j, x_mean=X.mean(dim=0, keepdim=True) * ws.PEAK_K)
+    print(row)
+    assert np.isfinite(row["cold_s"]) and np.isfinite(row["warm_s"]) and np.isfinite(row["mean_s"])
+    assert row["q_warm_start"] < row["q_cold_start"]
