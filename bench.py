@@ -33,14 +33,14 @@ DEFAULT_BLOCKING = "8,1,256,16,1"
 METRIC = "visibilities/s fwd+adjoint NUFFT; time-to-tol cold vs learned warm start"
 
 
-def grid_algorithmic_bytes(n_live: int, n_fine: int, real_bytes: int = 4) -> float:
+def grid_algorithmic_bytes(n_live: int, n_fine: int, real_bytes: int = 4, n_items: int = 1) -> float:
     """Algorithmic HBM bytes of the fused degrid/residual/spread stage for one evaluation:
-    the visibility stream (coordinates 2x4 B, data 2 reals, weight 1 real) plus reading the
-    fine-grid half-plane once and writing the adjoint half-plane once (G/2 each, G = n_f^2
-    complex values)."""
+    the visibility stream (coordinates 2x4 B, data 2 reals, weight 1 real) plus, for each of
+    the n_items (pointing, channel) blocks, reading the fine-grid half-plane once and writing
+    the adjoint half-plane once (G/2 each, G = n_f^2 complex values)."""
     per_vis = 8 + 3 * real_bytes
     G = n_fine * n_fine * 2 * real_bytes
-    return n_live * per_vis + G
+    return n_live * per_vis + n_items * G
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grid_traffic_c2.txt")
@@ -121,6 +121,70 @@ def _subsample(p, m):
     return q
 
 
+def run_mosaic(args):
+    """The 36-pointing mosaic: 1024^2 sky at 30", 6 x 6 hex of 1 deg beams, 384^2
+    sub-images, 1400-2000 samples x 630 baselines per pointing with 0-30% flags (about 34 M
+    live visibilities), 64 x 64 single-dish map, lambda_r = 1e-2, lambda_s = 1.  Data from the
+    FP64 HIP forward of the true sky plus 1% noise per pointing.  Prints one JSON line."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_2609_17636_amd import Plan
+
+    dev = torch.device("cuda:0")
+    p = synth.config_c3()
+    synth.attach_sd(p, oracle.sd_model(p, p.x_true))
+    p.vis = np.zeros(p.n_vis, dtype=np.complex64)
+    print(f"# workload {p.name}: N={p.n_sky} vis={p.n_vis} live={int((p.flags == 0).sum())}", file=sys.stderr,
+          flush=True)
+    plan64 = Plan.from_problem(p, precision="f64")
+    plan64.set_problem_data(p)
+    mv = plan64.forward(torch.tensor(p.x_true, dtype=torch.float64, device=dev)).cpu().numpy()
+    del plan64
+    synth.attach_data(p, mv[:, 0] + 1j * mv[:, 1])
+    plan = Plan.from_problem(p)
+    plan.set_problem_data(p)
+    plan.autotune(3000.0)
+    info = plan.info()
+    print(f"# plan {info}", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(0)
+    x = torch.tensor(rng.uniform(0, 50, size=p.x_true.shape), dtype=torch.float32, device=dev)
+    grad = torch.empty_like(x)
+    terms = torch.zeros(4, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        plan.objective_grad(x, grad=grad, terms=terms)
+    torch.cuda.synchronize()
+    plan.set_timing(("grid",))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.objective_grad(x, grad=grad, terms=terms)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stage_ms, n_timed = plan.stage_times()
+    plan.set_timing(())
+    n_live = info["n_live_vis"]
+    grid_ms = stage_ms["grid"] / max(n_timed, 1)
+    alg = grid_algorithmic_bytes(n_live, info["n_fine"], n_items=info["n_items"])
+    achieved = alg / (grid_ms * 1e-3) / 1e9
+    ms = 1e3 * dt / args.steps
+    out = {"metric": METRIC, "value": n_live * args.steps / dt, "unit": "vis/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "36-pointing mosaic, 1024^2 sky at 30 arcsec, 384^2 sub-images, "
+                                  f"{n_live} live visibilities, single-dish 64x64, lambda_r=1e-2, lambda_s=1",
+                      "n_sky": p.n_sky, "n_vis": n_live, "n_fine": info["n_fine"],
+                      "kernel_width": info["kernel_width"], "parallelism": "1 GPU",
+                      "blocking": {k: info[k] for k in ("tile", "waves_per_block", "chunk", "lanes", "vpi")}},
+           "evals_per_s": 1e3 / ms,
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_grid",
+                        "kernel_ms": grid_ms, "algorithmic_bytes": alg}}
+    print(f"# {ms:.4f} ms/eval, grid {grid_ms:.4f} ms/launch, Q_tot={terms[0].item():.6e}", file=sys.stderr,
+          flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +197,9 @@ def main():
                     help="tile,waves,chunk,lanes,vpi of the gridding kernel (default: the autotuner's "
                          "choice for this workload, recorded)")
     ap.add_argument("--autotune", action="store_true", help="run the plan autotuner instead of --blocking")
+    ap.add_argument("--workload", default="single", choices=("single", "mosaic"),
+                    help="single: the 512^2 single-pointing benchmark (default); mosaic: the 36-pointing "
+                         "1024^2 mosaic (separate measurement line, autotuned)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.steps)
@@ -141,6 +208,9 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
               f"(the channel/pointing sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "mosaic":
+        run_mosaic(args)
+        return
 
     import torch
 
