@@ -235,14 +235,22 @@ void free_one(ivx_plan *p, void *ptr) {
     }
 }
 
-int pick_ldw(int win) { return win | 1; }
+// Column stride of a (column-major) gridding window in LDS, in complex cells.  A lane of a
+// 16-lane group with W <= 8 reads column j, row h (j < 8, h < 2) of a footprint: with a
+// stride of twice an odd number the 16 values j * ldw + h are distinct mod 16, i.e. the
+// lanes hit distinct 8-byte bank pairs.  Other layouts walk up to 16 columns at one row:
+// an odd stride spreads those.
+int pick_ldw(int win, int W, int lanes) {
+    if (lanes == 16 && W <= 8) return win + ((2 - win % 4) + 4) % 4;
+    return win | 1;
+}
 
 // Geometry that depends on the tile edge.
 void set_tile(ivx_plan *p, int T) {
     Geom &g = p->g;
     g.T = T;
     g.win = T + g.W - 1;
-    g.ldw = pick_ldw(g.win);
+    g.ldw = pick_ldw(g.win, g.W, p->lanes);
     // footprint starts reach extended row nf + (O - W/2) + 1 and column nf/2 + 1 + ...
     const int max_er0 = g.nf + g.O; // generous upper bound on footprint-start rows
     const int max_ec0 = g.nf / 2 + g.O + 1;
@@ -259,7 +267,7 @@ bool tile_fits(const ivx_plan *p, int T, int nwave, int lanes) {
     Geom g = p->g;
     g.T = T;
     g.win = T + g.W - 1;
-    g.ldw = pick_ldw(g.win);
+    g.ldw = pick_ldw(g.win, g.W, lanes);
     if (lanes == 8 && g.W > 8) return false;
     return grid_lds_bytes(g, nwave, lanes) <= 80 * 1024; // two blocks per 160 KB compute unit
 }

@@ -25,6 +25,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace ivx {
 
 constexpr int NT = 256; // threads per block of every kernel
@@ -288,14 +290,16 @@ struct GridArgs {
 };
 
 // ---- cross-lane moves inside a 16-lane DPP row (VALU, no LDS traffic)
+// (mov_dpp with bound_ctrl: lanes without a source read 0, and no old value has to be
+// materialised first)
 template <int CTRL> __device__ __forceinline__ float dpp(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL> __device__ __forceinline__ double dpp(double v) {
     const int2 p = __builtin_bit_cast(int2, v);
     int2 r;
-    r.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, 0xF, 0xF, false);
-    r.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, 0xF, 0xF, false);
+    r.x = __builtin_amdgcn_mov_dpp(p.x, CTRL, 0xF, 0xF, true);
+    r.y = __builtin_amdgcn_mov_dpp(p.y, CTRL, 0xF, 0xF, true);
     return __builtin_bit_cast(double, r);
 }
 template <int L> __device__ __forceinline__ real row_bcast(real v) { return dpp<0x150 + L>(v); }
@@ -352,7 +356,9 @@ template <int G> __device__ __forceinline__ real group_sum(real v) {
 // LDS accumulator window with plain read-modify-write (the lanes of a group own distinct
 // cells and no other group writes there): no atomics.  The windows are summed in a fixed
 // order at the end, so results do not depend on scheduling.
-// LDS: F window (unless MODE_ADJ) + one accumulator window per group (unless MODE_FWD).
+// LDS: F window (unless MODE_ADJ) + one accumulator window per group (unless MODE_FWD),
+// each column-major with column stride ldw: the rows a lane owns in one footprint column
+// are then a few cells apart, so their offsets are immediates of the LDS instructions.
 template <int W, int MODE, int G, int VPI>
 __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -368,11 +374,14 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     cpx *Hw = Fw + (MODE == MODE_ADJ ? 0 : wsz);
     const WorkItem wi = a.work[blockIdx.x];
     const int tid = threadIdx.x;
+    // e = cc * win + r without an integer division: (e + 1/2) / win is never within float
+    // rounding of an integer for e < 2^16
+    const float inv_win = 1.0f / (float)win;
     if (MODE != MODE_ADJ) {
         const cpx *F = a.ext + (int64_t)wi.item * g.ext_stride + (int64_t)(wi.tx * g.T) * g.eh + wi.ty * g.T;
         for (int e = tid; e < win * win; e += blockDim.x) {
-            const int cc = e / win, r = e - (e / win) * win;
-            Fw[r * ldw + cc] = F[(int64_t)cc * g.eh + r];
+            const int cc = (int)(((float)e + 0.5f) * inv_win), r = e - cc * win;
+            Fw[cc * ldw + r] = F[cc * g.eh + r];
         }
     }
     if (MODE != MODE_FWD) {
@@ -406,6 +415,13 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     const cpx *vis = a.vis + wi.begin;
     const real *wgt = a.wgt + wi.begin;
     const int64_t *perm = a.perm + wi.begin;
+    // per-lane record index as an unsigned 32-bit byte offset from the block's (uniform)
+    // bases, so the loads take the scalar-base + 32-bit vector-offset form
+    auto rec = [&](int vv) -> unsigned { return (unsigned)(vv < v1 ? vv : 0); };
+    auto at = [](const auto *base, unsigned i) {
+        using T = std::remove_cv_t<std::remove_pointer_t<decltype(base)>>;
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (unsigned)sizeof(T));
+    };
 
     // software pipeline: the records of iteration it+1 are loaded during iteration it
     VisCoord c_nx[VPI];
@@ -414,15 +430,14 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     int64_t p_nx[VPI];
 #pragma unroll
     for (int u = 0; u < VPI; ++u) {
-        const int vv = v0 + u;
-        const int vn = vv < v1 ? vv : 0;
-        c_nx[u] = crd[vn];
+        const unsigned vn = rec(v0 + u);
+        c_nx[u] = at(crd, vn);
         y_nx[u] = cpx{0, 0};
         w_nx[u] = real(0);
         p_nx[u] = 0;
-        if (MODE == MODE_OBJ) { y_nx[u] = vis[vn]; w_nx[u] = wgt[vn]; }
-        if (MODE == MODE_ADJ) { w_nx[u] = wgt[vn]; p_nx[u] = perm[vn]; }
-        if (MODE == MODE_FWD) { p_nx[u] = perm[vn]; }
+        if (MODE == MODE_OBJ) { y_nx[u] = at(vis, vn); w_nx[u] = at(wgt, vn); }
+        if (MODE == MODE_ADJ) { w_nx[u] = at(wgt, vn); p_nx[u] = at(perm, vn); }
+        if (MODE == MODE_FWD) { p_nx[u] = at(perm, vn); }
     }
 
     for (int it = 0; it < nit; ++it) {
@@ -442,12 +457,11 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         if (it + 1 < nit) {
 #pragma unroll
             for (int u = 0; u < VPI; ++u) {
-                const int vv = v0 + (it + 1) * VPI + u;
-                const int vn = vv < v1 ? vv : 0;
-                c_nx[u] = crd[vn];
-                if (MODE == MODE_OBJ) { y_nx[u] = vis[vn]; w_nx[u] = wgt[vn]; }
-                if (MODE == MODE_ADJ) { w_nx[u] = wgt[vn]; p_nx[u] = perm[vn]; }
-                if (MODE == MODE_FWD) { p_nx[u] = perm[vn]; }
+                const unsigned vn = rec(v0 + (it + 1) * VPI + u);
+                c_nx[u] = at(crd, vn);
+                if (MODE == MODE_OBJ) { y_nx[u] = at(vis, vn); w_nx[u] = at(wgt, vn); }
+                if (MODE == MODE_ADJ) { w_nx[u] = at(wgt, vn); p_nx[u] = at(perm, vn); }
+                if (MODE == MODE_FWD) { p_nx[u] = at(perm, vn); }
             }
         }
         int off[VPI];
@@ -476,7 +490,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
                 RowWeights<W, G, 0>::run(my, upper, wsel[u]);
             }
             if (!valid[u]) wxj[u] = real(0);
-            off[u] = (iy + h) * ldw + ix + j;
+            off[u] = (int)__umul24((unsigned)(ix + j), (unsigned)ldw) + iy + h;
         }
         real ar[VPI], ai[VPI];
 #pragma unroll
@@ -491,7 +505,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
                     if (S == 1 || h + S * k < W) {
 #pragma unroll
                         for (int u = 0; u < VPI; ++u) {
-                            const cpx f = Fw[off[u] + S * k * ldw];
+                            const cpx f = Fw[off[u] + S * k];
                             ar[u] += wsel[u][k] * f.re;
                             ai[u] += wsel[u][k] * f.im;
                         }
@@ -537,7 +551,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
                     if (S == 1 || h + S * k < W) {
-                        cpx *hp = Hg + off[u] + S * k * ldw;
+                        cpx *hp = Hg + off[u] + S * k;
                         cpx hv = *hp;
                         hv.re += cre[u] * wsel[u][k];
                         hv.im += cim[u] * wsel[u][k];
@@ -551,10 +565,10 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     __syncthreads();
     cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride; // column-major window
     for (int e = tid; e < win * win; e += blockDim.x) {
-        const int cc = e / win, r = e - (e / win) * win;
+        const int cc = (int)(((float)e + 0.5f) * inv_win), r = e - cc * win;
         real sr = real(0), si = real(0);
         for (int q = 0; q < ngroups; ++q) {
-            const cpx hh = Hw[q * wsz + r * ldw + cc];
+            const cpx hh = Hw[q * wsz + cc * ldw + r];
             sr += hh.re;
             si += hh.im;
         }
