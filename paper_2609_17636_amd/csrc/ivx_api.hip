@@ -385,7 +385,7 @@ ivx_status build_bins(ivx_plan *p, hipStream_t st) {
     if ((s = dalloc(p, &p->d_tslot, tslot.size())) != IVX_OK) return s;
     if ((s = dalloc(p, &p->d_ext, (size_t)n_items * g.ext_stride)) != IVX_OK) return s;
     if ((s = dalloc(p, &p->d_slots, (size_t)std::max(1, slot) * g.win_stride)) != IVX_OK) return s;
-    if ((s = dalloc(p, &p->d_jpart, work.size())) != IVX_OK) return s;
+    if ((s = dalloc(p, &p->d_jpart, work.size() + final_scratch((int)work.size()) + 1)) != IVX_OK) return s;
     IVX_HIP(hipMemcpyAsync(p->d_crd, crd.data(), crd.size() * sizeof(VisCoord), hipMemcpyHostToDevice, st));
     IVX_HIP(hipMemcpyAsync(p->d_vis, vis.data(), vis.size() * sizeof(cpx), hipMemcpyHostToDevice, st));
     IVX_HIP(hipMemcpyAsync(p->d_wgt, wgt.data(), wgt.size() * sizeof(real), hipMemcpyHostToDevice, st));
@@ -412,7 +412,7 @@ ivx_status run_forward_half(ivx_plan *p, const real *sky, hipStream_t st) {
 
 ivx_status run_adjoint_half(ivx_plan *p, hipStream_t st) {
     const Geom &g = p->g;
-    IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_hs, st));
+    IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, p->d_hs, st));
     IVX_HIP(launch_col_inv(g, p->d_hs, p->d_tw, p->d_R, st));
     IVX_HIP(launch_row_inv(g, p->d_R, p->d_beams, p->d_fscale, p->d_dq, p->d_tw, p->d_gp, st));
     return IVX_OK;
@@ -469,7 +469,7 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
     }
     {
         StageTimer t(p, st, IVX_STAGE_FOLD);
-        IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_hs, st));
+        IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, p->d_hs, st));
     }
     {
         StageTimer t(p, st, IVX_STAGE_COL_INV);
@@ -485,16 +485,19 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
         IVX_HIP(launch_sd_rows(g, sky, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_U, st));
         IVX_HIP(launch_sd_cols(g, p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_sdmap,
                                (real)(1.0 / (p->d.sd_sigma * p->d.sd_sigma)), p->d_E, p->d_kpart, st));
+        // U is free again: it receives the column half of the adjoint for the sky pass
+        IVX_HIP(launch_sd_back(g, p->d_E, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_U, st));
     }
     {
         StageTimer t(p, st, IVX_STAGE_SKY);
         IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r,
-                           sd ? (real)p->d.lambda_s : real(0), p->d_E, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride,
+                           sd ? (real)p->d.lambda_s : real(0), p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride,
                            p->d.sd_offset, grad, p->d_rpart, false, st));
     }
     {
         StageTimer t(p, st, IVX_STAGE_FINAL);
-        IVX_HIP(launch_final(p->d_jpart, p->n_work, p->d_rpart, p->n_rpart, p->d_kpart, sd ? p->n_kpart : 0,
+        IVX_HIP(launch_final(p->d_jpart, p->n_work, p->d_jpart + p->n_work, p->d_rpart, p->n_rpart, p->d_kpart,
+                             sd ? p->n_kpart : 0,
                              p->d.lambda_r, sd ? p->d.lambda_s : 0.0, p->d_terms, terms_dev, st));
     }
     return IVX_OK;
@@ -1040,15 +1043,18 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
         float ms = 0.f, tot = 0.f;
         const int reps = 5;
         for (int r = 0; r < reps + 1; ++r) {
+            // the fold overwrites the forward grid: rebuild it (untimed) for every repetition
+            if (r > 0 && (s = run_forward_half(p, sky, st)) != IVX_OK) break;
             IVX_HIP(hipEventRecord(e0, st));
             IVX_HIP(launch_grid(MODE_OBJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm,
                                 p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, st));
-            IVX_HIP(launch_fold(p->g, p->d_tslot, p->d_slots, p->d_hs, st));
+            IVX_HIP(launch_fold(p->g, p->d_tslot, p->d_slots, p->d_ext, p->d_hs, st));
             IVX_HIP(hipEventRecord(e1, st));
             IVX_HIP(hipEventSynchronize(e1));
             IVX_HIP(hipEventElapsedTime(&ms, e0, e1));
             if (r > 0) tot += ms;
         }
+        if (s != IVX_OK) break;
         const double avg = tot / reps;
         if (avg < best_ms) {
             best_ms = avg;

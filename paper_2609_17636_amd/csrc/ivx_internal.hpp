@@ -78,8 +78,9 @@ hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work
                        const int64_t *perm, const cpx *ext, cpx *slots, double *jpart,
                        const cpx *caller_in, cpx *caller_out, int nwave, int variant,
                        hipStream_t st);
-hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *hs,
-                       hipStream_t st);
+// adjoint fold; `ext` (the forward extended grid, consumed by then) receives the summed
+// adjoint extended grid on the way
+hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, cpx *hs, hipStream_t st);
 hipError_t launch_col_inv(const Geom &g, const cpx *hs, const cpx *tw, cpx *R, hipStream_t st);
 hipError_t launch_row_inv(const Geom &g, const cpx *R, const real *beams, const real *fscale,
                           const real *dq, const cpx *tw, real *gp, hipStream_t st);
@@ -88,15 +89,20 @@ hipError_t launch_sd_rows(const Geom &g, const real *sky, const real *gB, int rb
 hipError_t launch_sd_cols(const Geom &g, const real *U, const real *gB, int rb, int sd_n,
                           int stride, int offset, const real *sdmap, real inv_var, real *E,
                           double *kpart, hipStream_t st);
+// V[c][p][j] = sum_q g(o + q S - j) E[c][p][q] (column half of the single-dish adjoint)
+hipError_t launch_sd_back(const Geom &g, const real *E, const real *gB, int rb, int sd_n, int stride, int offset,
+                          real *V, hipStream_t st);
 hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int32_t *cptr,
                       const CsrEnt *cent, real lambda_r, real lambda_s, const real *E,
                       const real *gB, int rb, int sd_n, int stride, int offset, real *grad,
                       double *rpart, bool adjoint_only, hipStream_t st);
 int sky_blocks(const Geom &g);
 // FP64 reduction of all partials into {Q_tot, Q, K, R} (terms, and terms_user if non-null).
-hipError_t launch_final(const double *jpart, int nj, const double *rpart, int nr,
-                        const double *kpart, int nkp, double lambda_r, double lambda_s,
-                        double *terms, double *terms_user, hipStream_t st);
+// jpart: per-work-item partials of J; scratch: final_scratch(nj) doubles (may be 0)
+int final_scratch(int nj);
+hipError_t launch_final(const double *jpart, int nj, double *scratch, const double *rpart, int nr,
+                        const double *kpart, int nkp, double lambda_r, double lambda_s, double *terms,
+                        double *terms_user, hipStream_t st);
 hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st);
 hipError_t launch_gather_vis(const int64_t *perm, int64_t n, const cpx *vis, const real *wgt, cpx *svis,
                              real *swgt, unsigned int *bad, hipStream_t st);

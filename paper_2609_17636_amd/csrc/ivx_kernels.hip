@@ -591,50 +591,77 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
 int grid_groups_per_wave(int W, int lanes) { return (lanes == 8 && W <= 8) ? 8 : 4; }
 
 // ----------------------------------------------------------------------- fold
-__device__ __forceinline__ cpx ext_cell(const Geom &g, const int32_t *__restrict__ ts,
-                                        const cpx *__restrict__ slots, int er, int ec) {
-    real sr = real(0), si = real(0);
-    const int ty1 = er / g.T, tx1 = ec / g.T;
-    for (int ty = ty1; ty >= ty1 - 1 && ty >= 0; --ty) {
-        if (ty >= g.nty) continue;
-        const int lr = er - ty * g.T;
-        if (lr >= g.win) break;
-        for (int tx = tx1; tx >= tx1 - 1 && tx >= 0; --tx) {
-            if (tx >= g.ntx) continue;
-            const int lc = ec - tx * g.T;
-            if (lc >= g.win) break;
-            const int tile = ty * g.ntx + tx;
-            const int s1 = ts[tile + 1];
-            for (int s = ts[tile]; s < s1; ++s) {
-                const cpx h = slots[(int64_t)s * g.win_stride + lc * g.win + lr];
+// Two passes.  (1) k_ext_sum: the adjoint extended grid E = sum of every work item's
+// window placed at its tile, computed owner-wise: the block of (virtual) tile (vy, vx)
+// owns the T x T cells starting at (vy T, vx T), which only the windows of tiles
+// (vy - dy, vx - dx), dy, dx in {0, 1}, reach (a window spans T + W - 1 <= 2T cells);
+// their slot lists are uniform per block and the window reads are contiguous along
+// rows.  E overwrites the forward extended grid, which the gridding pass has consumed.
+// (2) k_fold: every half-plane cell sums the extended-grid cells that alias to it
+// (periodic rows and columns) and is symmetrised, Hs = (H(t) + conj H(-t)) / 2.
+__global__ __launch_bounds__(NT) void k_ext_sum(Geom g, int tiles_per_block, const int32_t *__restrict__ tslot,
+                                                const cpx *__restrict__ slots, cpx *__restrict__ E) {
+    const int item = blockIdx.y;
+    const int T = g.T, win = g.win, TT = T * T;
+    const int nvx = g.ntx + 1, nvt = (g.nty + 1) * nvx;
+    // several small virtual tiles per block so that every thread owns a cell
+    const int sub = threadIdx.x / TT;
+    const int vt = blockIdx.x * tiles_per_block + sub;
+    if (sub >= tiles_per_block || vt >= nvt) return;
+    const int vy = vt / nvx, vx = vt - (vt / nvx) * nvx;
+    const int32_t *ts = tslot + (int64_t)item * (g.nty * g.ntx + 1);
+    int s_lo[4], s_hi[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int ty = vy - (q >> 1), tx = vx - (q & 1);
+        s_lo[q] = s_hi[q] = 0;
+        if (ty >= 0 && tx >= 0 && ty < g.nty && tx < g.ntx) {
+            s_lo[q] = ts[ty * g.ntx + tx];
+            s_hi[q] = ts[ty * g.ntx + tx + 1];
+        }
+    }
+    const float inv_t = 1.0f / (float)T;
+    cpx *Ei = E + (int64_t)item * g.ext_stride;
+    for (int e = threadIdx.x - sub * TT; e < TT; e += NT) {
+        const int c = (int)(((float)e + 0.5f) * inv_t), r = e - c * T;
+        const int er = vy * T + r, ec = vx * T + c;
+        if (er >= g.eh || ec >= g.ew) continue;
+        real sr = real(0), si = real(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int lr = r + (q >> 1) * T, lc = c + (q & 1) * T;
+            if (lr >= win || lc >= win) continue;
+            const int off = lc * win + lr;
+            for (int sidx = s_lo[q]; sidx < s_hi[q]; ++sidx) {
+                const cpx h = slots[(int64_t)sidx * g.win_stride + off];
                 sr += h.re;
                 si += h.im;
             }
         }
+        Ei[(int64_t)ec * g.eh + er] = cpx{sr, si};
     }
+}
+
+__device__ __forceinline__ cpx alias_sum(const Geom &g, const cpx *__restrict__ Ei, int t1, int t2) {
+    const int msk = g.nf - 1;
+    real sr = real(0), si = real(0);
+    for (int ec = (t2 + g.O) & msk; ec < g.ew; ec += g.nf)
+        for (int er = (t1 + g.O) & msk; er < g.eh; er += g.nf) {
+            const cpx h = Ei[(int64_t)ec * g.eh + er];
+            sr += h.re;
+            si += h.im;
+        }
     return cpx{sr, si};
 }
 
-// Sum of every extended-grid cell that aliases to periodic fine-grid cell (t1, t2): rows
-// t1 + O + m nf inside [0, eh), columns t2 + O + m nf inside [0, ew) (t1, t2 >= 0).
-__device__ __forceinline__ cpx periodic_cell(const Geom &g, const int32_t *__restrict__ ts,
-                                             const cpx *__restrict__ slots, int t1, int t2) {
-    cpx s = cpx{0, 0};
-    const int r0 = t1 + g.O, c0 = t2 + g.O;
-    for (int er = r0 - (r0 / g.nf) * g.nf; er < g.eh; er += g.nf)
-        for (int ec = c0 - (c0 / g.nf) * g.nf; ec < g.ew; ec += g.nf) s = cadd(s, ext_cell(g, ts, slots, er, ec));
-    return s;
-}
-
-__global__ __launch_bounds__(NT) void k_fold(Geom g, const int32_t *__restrict__ tslot,
-                                             const cpx *__restrict__ slots, cpx *__restrict__ hs) {
+__global__ __launch_bounds__(NT) void k_fold(Geom g, const cpx *__restrict__ E, cpx *__restrict__ hs) {
     const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
     const int item = blockIdx.y;
     if (idx >= (int64_t)g.nf * g.rw) return;
-    const int t2 = (int)(idx / g.nf), t1 = (int)(idx - (idx / g.nf) * g.nf); // column-major
-    const int32_t *ts = tslot + (int64_t)item * (g.nty * g.ntx + 1);
-    const cpx h = periodic_cell(g, ts, slots, t1, t2);
-    const cpx m = periodic_cell(g, ts, slots, (g.nf - t1) & (g.nf - 1), (g.nf - t2) & (g.nf - 1));
+    const int t2 = (int)(idx >> g.logn), t1 = (int)(idx & (g.nf - 1)); // column-major half-plane
+    const cpx *Ei = E + (int64_t)item * g.ext_stride;
+    const cpx h = alias_sum(g, Ei, t1, t2);
+    const cpx m = alias_sum(g, Ei, (g.nf - t1) & (g.nf - 1), (g.nf - t2) & (g.nf - 1));
     hs[(int64_t)item * g.hs_stride + idx] = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
 }
 
@@ -761,6 +788,22 @@ __global__ __launch_bounds__(NT) void k_sd_cols(Geom g, const real *__restrict__
     }
 }
 
+// V[c][p][j] = sum_q g(o + q S - j) E[c][p][q]: the column half of B^T S^T E, so that the
+// sky pass needs only the row sum over the few p whose beam reaches row i
+__global__ __launch_bounds__(NT) void k_sd_back(Geom g, const real *__restrict__ E, const real *__restrict__ gB,
+                                                int rb, int sd_n, int stride, int offset, real *__restrict__ V) {
+    const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t tot = (int64_t)g.C * sd_n * g.N;
+    if (idx >= tot) return;
+    const int j = (int)(idx % g.N);
+    const int64_t cp = idx / g.N; // c * sd_n + p
+    const int q0 = max(0, ceildiv(j - rb - offset, stride)), q1 = min(sd_n - 1, floordiv(j + rb - offset, stride));
+    const real *Ep = E + cp * sd_n;
+    real s = real(0);
+    for (int q = q0; q <= q1; ++q) s += gB[offset + q * stride - j + rb] * Ep[q];
+    V[idx] = s;
+}
+
 // --------------------------------------------------------------------- sky level
 constexpr int SKY_T = 16;
 
@@ -828,14 +871,9 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
         if (sd) {
             const int S = a.stride, o = a.offset, rb = a.rb;
             const int p0 = max(0, ceildiv(i - rb - o, S)), p1 = min(a.sd_n - 1, floordiv(i + rb - o, S));
-            const int q0 = max(0, ceildiv(j - rb - o, S)), q1 = min(a.sd_n - 1, floordiv(j + rb - o, S));
-            const real *Ec = a.E + (int64_t)c * a.sd_n * a.sd_n;
+            const real *Vc = a.E + (int64_t)c * a.sd_n * N; // V of k_sd_back
             real s = real(0);
-            for (int pp = p0; pp <= p1; ++pp) {
-                real row = real(0);
-                for (int qq = q0; qq <= q1; ++qq) row += a.gB[o + qq * S - j + rb] * Ec[pp * a.sd_n + qq];
-                s += a.gB[o + pp * S - i + rb] * row;
-            }
+            for (int pp = p0; pp <= p1; ++pp) s += a.gB[o + pp * S - i + rb] * Vc[(int64_t)pp * N + j];
             gsum += a.lambda_s * s;
         }
         a.grad[(int64_t)c * N * N + p] = gsum;
@@ -853,7 +891,25 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
 }
 
 // ---------------------------------------------------------------------- reductions
+// out[b] = sum of in[b * per .. (b + 1) * per) (fixed order: strided per thread, then tree)
+__global__ __launch_bounds__(NT) void k_partial_sums(const double *__restrict__ in, int n, int per,
+                                                     double *__restrict__ out) {
+    __shared__ double red[NT / 64];
+    const int b0 = blockIdx.x * per, b1 = min(n, b0 + per);
+    double v = 0.0;
+    for (int i = b0 + threadIdx.x; i < b1; i += NT) v += in[i];
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+        out[blockIdx.x] = s;
+    }
+}
+
 constexpr int NT_FINAL = 1024;
+constexpr int FINAL_PER = 1024; // work-item partials per pre-reduction block
 __global__ __launch_bounds__(NT_FINAL) void k_final(const double *__restrict__ jpart, int nj,
                                                     const double *__restrict__ rpart, int nr,
                                                     const double *__restrict__ kpart, int nkp,
@@ -973,10 +1029,13 @@ hipError_t launch_col_inv(const Geom &g, const cpx *hs, const cpx *tw, cpx *R, h
     return hipGetLastError();
 }
 
-hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *hs, hipStream_t st) {
+hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, cpx *hs, hipStream_t st) {
+    const int tpb = g.T * g.T >= NT ? 1 : NT / (g.T * g.T);
+    const int nvt = (g.nty + 1) * (g.ntx + 1);
+    k_ext_sum<<<dim3((unsigned)((nvt + tpb - 1) / tpb), n_items(g)), NT, 0, st>>>(g, tpb, tslot, slots, ext);
     const int64_t cells = (int64_t)g.nf * g.rw;
     dim3 grid((unsigned)((cells + NT - 1) / NT), n_items(g));
-    k_fold<<<grid, NT, 0, st>>>(g, tslot, slots, hs);
+    k_fold<<<grid, NT, 0, st>>>(g, ext, hs);
     return hipGetLastError();
 }
 
@@ -1085,6 +1144,13 @@ hipError_t launch_sd_cols(const Geom &g, const real *U, const real *gB, int rb, 
     return hipGetLastError();
 }
 
+hipError_t launch_sd_back(const Geom &g, const real *E, const real *gB, int rb, int sd_n, int stride, int offset,
+                          real *V, hipStream_t st) {
+    const int64_t tot = (int64_t)g.C * sd_n * g.N;
+    k_sd_back<<<(unsigned)((tot + NT - 1) / NT), NT, 0, st>>>(g, E, gB, rb, sd_n, stride, offset, V);
+    return hipGetLastError();
+}
+
 int sky_blocks(const Geom &g) {
     const int nb = (g.N + SKY_T - 1) / SKY_T;
     return nb * nb * g.C;
@@ -1100,8 +1166,18 @@ hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int3
     return hipGetLastError();
 }
 
-hipError_t launch_final(const double *jpart, int nj, const double *rpart, int nr, const double *kpart, int nkp,
-                        double lambda_r, double lambda_s, double *terms, double *terms_user, hipStream_t st) {
+int final_scratch(int nj) { return nj > 4 * FINAL_PER ? (nj + FINAL_PER - 1) / FINAL_PER : 0; }
+
+hipError_t launch_final(const double *jpart, int nj, double *scratch, const double *rpart, int nr,
+                        const double *kpart, int nkp, double lambda_r, double lambda_s, double *terms,
+                        double *terms_user, hipStream_t st) {
+    const int nb = final_scratch(nj);
+    if (nb > 0) {
+        // long per-work-item lists (large mosaics): pre-reduce in fixed blocks first
+        k_partial_sums<<<nb, NT, 0, st>>>(jpart, nj, FINAL_PER, scratch);
+        jpart = scratch;
+        nj = nb;
+    }
     k_final<<<1, NT_FINAL, 0, st>>>(jpart, nj, rpart, nr, kpart, nkp, lambda_r, lambda_s, terms, terms_user);
     return hipGetLastError();
 }
