@@ -150,8 +150,8 @@ struct ivx_plan {
     int32_t *d_tslot = nullptr;
     cpx *d_R = nullptr, *d_ext = nullptr, *d_slots = nullptr, *d_hs = nullptr;
     real *d_gp = nullptr;
-    int32_t *d_cptr = nullptr;
-    CsrEnt *d_cent = nullptr;
+    int32_t *d_cptr = nullptr; // reprojection transpose: slice offsets (sliced layout)
+    CsrEnt *d_cent = nullptr;  // and entries
     real *d_sdmap = nullptr, *d_gB = nullptr, *d_U = nullptr, *d_E = nullptr;
     double *d_jpart = nullptr, *d_rpart = nullptr, *d_kpart = nullptr, *d_terms = nullptr;
     int n_rpart = 0, n_kpart = 0;
@@ -855,13 +855,50 @@ ivx_status ivx_plan_set_data(ivx_plan *p, const ivx_real *uv, const ivx_real *vi
         for (int64_t i = 0; i < (int64_t)N * N; ++i) cptr[i + 1] += cptr[i];
         if ((int64_t)taps.size() > INT32_MAX) { s = fail(IVX_EINVAL, "too many reprojection taps"); goto fail_free; }
         std::vector<CsrEnt> cent(taps.size() > 0 ? taps.size() : 1);
-        std::vector<int32_t> fillp(cptr.begin(), cptr.end() - 1);
-        for (const Tap &t : taps) cent[fillp[t.pix]++] = t.e; // stable: (k, a, b, tap) order
-        if ((s = dalloc(p, &p->d_cptr, cptr.size())) != IVX_OK) goto fail_free;
-        if ((s = dalloc(p, &p->d_cent, cent.size())) != IVX_OK) goto fail_free;
+        {
+            std::vector<int32_t> fillp(cptr.begin(), cptr.end() - 1);
+            for (const Tap &t : taps) cent[fillp[t.pix]++] = t.e; // stable: (k, a, b, tap) order
+        }
+        // sliced layout for the sky pass: one slice per wave of its 16 x 16 pixel blocks
+        // (4 rows of 16 pixels), entries stored entry-major within the slice (lane-
+        // contiguous) and padded to the slice's longest pixel with zero weights
+        const int nb = (N + SKY_T - 1) / SKY_T;
+        const int64_t nslice = (int64_t)nb * nb * (SKY_T * SKY_T / 64);
+        std::vector<int32_t> soff(nslice + 1, 0);
+        auto slice_pixel = [&](int64_t sl, int lane, int64_t &pix) {
+            const int64_t blk = sl / (SKY_T * SKY_T / 64);
+            const int w = (int)(sl % (SKY_T * SKY_T / 64));
+            const int by = (int)(blk / nb), bx = (int)(blk % nb);
+            const int tid = w * 64 + lane;
+            const int i = by * SKY_T + tid / SKY_T, j = bx * SKY_T + tid % SKY_T;
+            if (i >= N || j >= N) return false;
+            pix = (int64_t)i * N + j;
+            return true;
+        };
+        int64_t tot = 0;
+        for (int64_t sl = 0; sl < nslice; ++sl) {
+            int len = 0;
+            for (int lane = 0; lane < 64; ++lane) {
+                int64_t pix;
+                if (slice_pixel(sl, lane, pix)) len = std::max(len, cptr[pix + 1] - cptr[pix]);
+            }
+            soff[sl] = (int32_t)tot;
+            tot += (int64_t)len * 64;
+            if (tot > INT32_MAX) { s = fail(IVX_EINVAL, "too many reprojection taps"); goto fail_free; }
+        }
+        soff[nslice] = (int32_t)tot;
+        std::vector<CsrEnt> sell(tot > 0 ? tot : 1, CsrEnt{0, real(0)});
+        for (int64_t sl = 0; sl < nslice; ++sl)
+            for (int lane = 0; lane < 64; ++lane) {
+                int64_t pix;
+                if (!slice_pixel(sl, lane, pix)) continue;
+                for (int t = 0; t < cptr[pix + 1] - cptr[pix]; ++t) sell[soff[sl] + (int64_t)t * 64 + lane] = cent[cptr[pix] + t];
+            }
+        if ((s = dalloc(p, &p->d_cptr, soff.size())) != IVX_OK) goto fail_free;
+        if ((s = dalloc(p, &p->d_cent, sell.size())) != IVX_OK) goto fail_free;
         hipError_t e;
-        if ((e = hipMemcpy(p->d_cptr, cptr.data(), cptr.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(p->d_cent, cent.data(), cent.size() * sizeof(CsrEnt), hipMemcpyHostToDevice)) != hipSuccess) {
+        if ((e = hipMemcpy(p->d_cptr, soff.data(), soff.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p->d_cent, sell.data(), sell.size() * sizeof(CsrEnt), hipMemcpyHostToDevice)) != hipSuccess) {
             s = hip_fail(e, "hipMemcpy (reprojection transpose)");
             goto fail_free;
         }

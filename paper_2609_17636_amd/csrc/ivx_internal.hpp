@@ -66,6 +66,11 @@ struct Geom {
 
 enum GridMode { MODE_OBJ = 0, MODE_FWD = 1, MODE_ADJ = 2 };
 
+// Sky pass tiling: blocks of SKY_T x SKY_T pixels, 256 threads, thread t at row t / SKY_T,
+// column t % SKY_T of the block; the reprojection transpose is stored per wave ("slice":
+// 64 consecutive threads) in entry-major order.
+constexpr int SKY_T = 16;
+
 // ---------------------------------------------------------------- kernel launchers
 // Each returns hipSuccess or the launch error.  All run on `st`.
 

@@ -805,7 +805,7 @@ __global__ __launch_bounds__(NT) void k_sd_back(Geom g, const real *__restrict__
 }
 
 // --------------------------------------------------------------------- sky level
-constexpr int SKY_T = 16;
+static_assert(SKY_T * SKY_T == NT, "one thread per pixel of a sky block");
 
 struct SkyArgs {
     Geom g;
@@ -858,10 +858,14 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
         real gsum = real(0);
         const int64_t p = (int64_t)i * N + j;
         const int64_t coff = (int64_t)c * g.nk * g.nk;
-        const int e1 = a.cptr[p + 1];
-        for (int e = a.cptr[p]; e < e1; ++e) {
-            const CsrEnt en = a.cent[e];
-            gsum += en.w * a.gp[(int64_t)en.off + coff];
+        (void)p;
+        // this wave's slice: entries lane-contiguous, padded with zero weights
+        const int slice = (blockIdx.y * gridDim.x + blockIdx.x) * (NT / 64) + (tid >> 6);
+        const int e0 = a.cptr[slice], len = (a.cptr[slice + 1] - e0) >> 6;
+        const CsrEnt *en = a.cent + e0 + (tid & 63);
+        for (int t = 0; t < len; ++t) {
+            const CsrEnt q = en[t * 64];
+            gsum += q.w * a.gp[(int64_t)q.off + coff];
         }
         if (reg) {
             const real d = dxs[ti + 1][tj + 1];
