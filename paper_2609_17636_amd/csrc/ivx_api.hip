@@ -148,7 +148,7 @@ struct ivx_plan {
     int64_t *d_perm = nullptr;
     WorkItem *d_work = nullptr;
     int32_t *d_tslot = nullptr;
-    cpx *d_R = nullptr, *d_ext = nullptr, *d_slots = nullptr, *d_hs = nullptr;
+    cpx *d_R = nullptr, *d_ext = nullptr, *d_slots = nullptr;
     real *d_gp = nullptr;
     int32_t *d_cptr = nullptr; // reprojection transpose: slice offsets (sliced layout)
     CsrEnt *d_cent = nullptr;  // and entries
@@ -215,7 +215,7 @@ void free_all(ivx_plan *p) {
     p->d_perm = nullptr;
     p->d_work = nullptr;
     p->d_tslot = nullptr;
-    p->d_R = p->d_ext = p->d_slots = p->d_hs = nullptr;
+    p->d_R = p->d_ext = p->d_slots = nullptr;
     p->d_gp = nullptr;
     p->d_cptr = nullptr;
     p->d_cent = nullptr;
@@ -412,8 +412,8 @@ ivx_status run_forward_half(ivx_plan *p, const real *sky, hipStream_t st) {
 
 ivx_status run_adjoint_half(ivx_plan *p, hipStream_t st) {
     const Geom &g = p->g;
-    IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, p->d_hs, st));
-    IVX_HIP(launch_col_inv(g, p->d_hs, p->d_tw, p->d_R, st));
+    IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, st));
+    IVX_HIP(launch_col_inv(g, p->d_ext, p->d_tw, p->d_R, st));
     IVX_HIP(launch_row_inv(g, p->d_R, p->d_beams, p->d_fscale, p->d_dq, p->d_tw, p->d_gp, st));
     return IVX_OK;
 }
@@ -469,11 +469,11 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
     }
     {
         StageTimer t(p, st, IVX_STAGE_FOLD);
-        IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, p->d_hs, st));
+        IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, st));
     }
     {
         StageTimer t(p, st, IVX_STAGE_COL_INV);
-        IVX_HIP(launch_col_inv(g, p->d_hs, p->d_tw, p->d_R, st));
+        IVX_HIP(launch_col_inv(g, p->d_ext, p->d_tw, p->d_R, st));
     }
     {
         StageTimer t(p, st, IVX_STAGE_ROW_INV);
@@ -805,7 +805,6 @@ ivx_status ivx_plan_set_data(ivx_plan *p, const ivx_real *uv, const ivx_real *vi
     if ((s = dalloc(p, &p->d_beams, h_beams.size())) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_interp, h_interp.size())) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_R, (size_t)n_items * g.r_stride)) != IVX_OK) goto fail_free;
-    if ((s = dalloc(p, &p->d_hs, (size_t)n_items * g.hs_stride)) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_gp, (size_t)n_items * nk2)) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_terms, 4)) != IVX_OK) goto fail_free;
     p->n_rpart = sky_blocks(g);
@@ -1085,7 +1084,7 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
             IVX_HIP(hipEventRecord(e0, st));
             IVX_HIP(launch_grid(MODE_OBJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm,
                                 p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, st));
-            IVX_HIP(launch_fold(p->g, p->d_tslot, p->d_slots, p->d_ext, p->d_hs, st));
+            IVX_HIP(launch_fold(p->g, p->d_tslot, p->d_slots, p->d_ext, st));
             IVX_HIP(hipEventRecord(e1, st));
             IVX_HIP(hipEventSynchronize(e1));
             IVX_HIP(hipEventElapsedTime(&ms, e0, e1));

@@ -60,7 +60,7 @@ struct Geom {
     int nty, ntx;         // tiles per block along rows / columns
     int64_t r_stride;     // nk * rw   (row-FFT buffers per block)
     int64_t ext_stride;   // eh * ew   (extended grid per block)
-    int64_t hs_stride;    // nf * rw   (Hermitian half-plane per block)
+    int64_t hs_stride;    // nf * rw   (Hermitian half-plane per block; layout reference)
     int64_t win_stride;   // win * win (slot size)
 };
 
@@ -83,10 +83,11 @@ hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work
                        const int64_t *perm, const cpx *ext, cpx *slots, double *jpart,
                        const cpx *caller_in, cpx *caller_out, int nwave, int variant,
                        hipStream_t st);
-// adjoint fold; `ext` (the forward extended grid, consumed by then) receives the summed
-// adjoint extended grid on the way
-hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, cpx *hs, hipStream_t st);
-hipError_t launch_col_inv(const Geom &g, const cpx *hs, const cpx *tw, cpx *R, hipStream_t st);
+// adjoint extended grid: the windows summed into `ext` (the forward extended grid, which
+// the gridding pass has consumed by then)
+hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, hipStream_t st);
+// inverse column FFT of the symmetrised half plane, folded from the adjoint extended grid
+hipError_t launch_col_inv(const Geom &g, const cpx *E, const cpx *tw, cpx *R, hipStream_t st);
 hipError_t launch_row_inv(const Geom &g, const cpx *R, const real *beams, const real *fscale,
                           const real *dq, const cpx *tw, real *gp, hipStream_t st);
 hipError_t launch_sd_rows(const Geom &g, const real *sky, const real *gB, int rb, int sd_n,

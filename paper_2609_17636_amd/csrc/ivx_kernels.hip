@@ -597,8 +597,9 @@ int grid_groups_per_wave(int W, int lanes) { return (lanes == 8 && W <= 8) ? 8 :
 // (vy - dy, vx - dx), dy, dx in {0, 1}, reach (a window spans T + W - 1 <= 2T cells);
 // their slot lists are uniform per block and the window reads are contiguous along
 // rows.  E overwrites the forward extended grid, which the gridding pass has consumed.
-// (2) k_fold: every half-plane cell sums the extended-grid cells that alias to it
-// (periodic rows and columns) and is symmetrised, Hs = (H(t) + conj H(-t)) / 2.
+// (2) in the adjoint column pass, every half-plane cell sums the extended-grid cells that
+// alias to it (periodic rows and columns) and is symmetrised, Hs = (H(t) + conj H(-t)) / 2,
+// as it is loaded for the inverse column FFT.
 __global__ __launch_bounds__(NT) void k_ext_sum(Geom g, int tiles_per_block, const int32_t *__restrict__ tslot,
                                                 const cpx *__restrict__ slots, cpx *__restrict__ E) {
     const int item = blockIdx.y;
@@ -654,30 +655,26 @@ __device__ __forceinline__ cpx alias_sum(const Geom &g, const cpx *__restrict__ 
     return cpx{sr, si};
 }
 
-__global__ __launch_bounds__(NT) void k_fold(Geom g, const cpx *__restrict__ E, cpx *__restrict__ hs) {
-    const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
-    const int item = blockIdx.y;
-    if (idx >= (int64_t)g.nf * g.rw) return;
-    const int t2 = (int)(idx >> g.logn), t1 = (int)(idx & (g.nf - 1)); // column-major half-plane
-    const cpx *Ei = E + (int64_t)item * g.ext_stride;
-    const cpx h = alias_sum(g, Ei, t1, t2);
-    const cpx m = alias_sum(g, Ei, (g.nf - t1) & (g.nf - 1), (g.nf - t2) & (g.nf - 1));
-    hs[(int64_t)item * g.hs_stride + idx] = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
-}
-
 // ------------------------------------------------------------ adjoint column pass
 template <int LOGN, int CB>
-__global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ hs,
+__global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ E,
                                                 const cpx *__restrict__ tw, cpx *__restrict__ R) {
     constexpr int N = 1 << LOGN;
     __shared__ cpx buf[CB * N];
     const int tid = threadIdx.x;
     const int item = blockIdx.y;
     const int c0 = blockIdx.x * CB;
-    const cpx *H = hs + (int64_t)item * g.hs_stride;
+    const cpx *Ei = E + (int64_t)item * g.ext_stride;
     for (int e = tid; e < N * CB; e += NT) {
-        const int cc = e / N, t1 = e - (e / N) * N;
-        buf[t1 * CB + cc] = (c0 + cc < g.rw) ? H[(int64_t)(c0 + cc) * N + t1] : cpx{0, 0};
+        const int cc = e >> LOGN, t1 = e & (N - 1);
+        const int t2 = c0 + cc;
+        cpx v = cpx{0, 0};
+        if (t2 < g.rw) {
+            const cpx h = alias_sum(g, Ei, t1, t2);
+            const cpx m = alias_sum(g, Ei, (N - t1) & (N - 1), (N - t2) & (N - 1));
+            v = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
+        }
+        buf[t1 * CB + cc] = v;
     }
     __syncthreads();
     fft_lds<LOGN, CB, true>(buf, tw);
@@ -1022,24 +1019,21 @@ hipError_t launch_col_fwd(const Geom &g, const cpx *R, const cpx *tw, cpx *ext, 
     return hipGetLastError();
 }
 
-hipError_t launch_col_inv(const Geom &g, const cpx *hs, const cpx *tw, cpx *R, hipStream_t st) {
+hipError_t launch_col_inv(const Geom &g, const cpx *E, const cpx *tw, cpx *R, hipStream_t st) {
     IVX_LOGN_SWITCH(g.logn, {
         const int cb = pick_cb<L>(g);
         IVX_CB_SWITCH(cb, {
             dim3 grid((g.rw + B - 1) / B, n_items(g));
-            k_col_inv<L, B><<<grid, NT, 0, st>>>(g, hs, tw, R);
+            k_col_inv<L, B><<<grid, NT, 0, st>>>(g, E, tw, R);
         });
     });
     return hipGetLastError();
 }
 
-hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, cpx *hs, hipStream_t st) {
+hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, hipStream_t st) {
     const int tpb = g.T * g.T >= NT ? 1 : NT / (g.T * g.T);
     const int nvt = (g.nty + 1) * (g.ntx + 1);
     k_ext_sum<<<dim3((unsigned)((nvt + tpb - 1) / tpb), n_items(g)), NT, 0, st>>>(g, tpb, tslot, slots, ext);
-    const int64_t cells = (int64_t)g.nf * g.rw;
-    dim3 grid((unsigned)((cells + NT - 1) / NT), n_items(g));
-    k_fold<<<grid, NT, 0, st>>>(g, ext, hs);
     return hipGetLastError();
 }
 
@@ -1170,7 +1164,7 @@ hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int3
     return hipGetLastError();
 }
 
-int final_scratch(int nj) { return nj > 4 * FINAL_PER ? (nj + FINAL_PER - 1) / FINAL_PER : 0; }
+int final_scratch(int nj) { return nj > 32 * FINAL_PER ? (nj + FINAL_PER - 1) / FINAL_PER : 0; }
 
 hipError_t launch_final(const double *jpart, int nj, double *scratch, const double *rpart, int nr,
                         const double *kpart, int nkp, double lambda_r, double lambda_s, double *terms,
