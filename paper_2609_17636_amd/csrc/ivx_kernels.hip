@@ -41,10 +41,18 @@ __device__ __forceinline__ cpx csub(cpx a, cpx b) { return cpx{a.re - b.re, a.im
 // In-LDS Stockham autosort FFT (mixed radix 2 then 4) of CB interleaved transforms of
 // length N = 2^LOGN: element i of transform c is buf[i * CB + c].  Each stage reads all
 // of a thread's butterfly inputs into registers, synchronises, then writes the outputs,
-// so the transform runs in place.  Twiddles come from a table tw[t] = exp(-2 pi i t / N)
-// (conjugated for the inverse); no scaling is applied in either direction.
+// so the transform runs in place.  Twiddles come from a table tw[t] = exp(-2 pi i t / N),
+// t < 3N/4, staged in LDS by load_twiddles (conjugated for the inverse); no scaling is
+// applied in either direction.
+template <int LOGN> constexpr int tw_len() { return 3 * (1 << LOGN) / 4; }
+
+template <int LOGN>
+__device__ __forceinline__ void load_twiddles(cpx *tws, const cpx *__restrict__ tw) {
+    for (int i = threadIdx.x; i < tw_len<LOGN>(); i += NT) tws[i] = tw[i];
+}
+
 template <int LOGN, int CB, bool INV>
-__device__ __forceinline__ void fft_lds(cpx *buf, const cpx *__restrict__ tw) {
+__device__ __forceinline__ void fft_lds(cpx *buf, const cpx *tw) {
     constexpr int N = 1 << LOGN;
     const int tid = threadIdx.x;
     int Ns = 1;
@@ -153,6 +161,8 @@ __global__ __launch_bounds__(NT) void k_image_rows(Geom g, const real *__restric
                                                    const cpx *__restrict__ tw, cpx *__restrict__ R) {
     constexpr int N = 1 << LOGN;
     __shared__ cpx buf[N];
+    __shared__ cpx tws[tw_len<LOGN>()];
+    load_twiddles<LOGN>(tws, tw);
     const int tid = threadIdx.x;
     const int item = blockIdx.y;
     const int k = item / g.C, c = item - (item / g.C) * g.C;
@@ -172,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_image_rows(Geom g, const real *__restric
         buf[(b - nk / 2) & (N - 1)] = cpx{f0, f1};
     }
     __syncthreads();
-    fft_lds<LOGN, 1, false>(buf, tw);
+    fft_lds<LOGN, 1, false>(buf, tws);
     cpx *R0 = R + (int64_t)item * g.r_stride + (int64_t)a0 * g.rw;
     cpx *R1 = R0 + g.rw;
     for (int kk = tid; kk <= N / 2; kk += NT) {
@@ -190,6 +200,8 @@ __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ 
     constexpr int N = 1 << LOGN;
     constexpr int MAXE = 8 * CB;
     __shared__ cpx buf[CB * N];
+    __shared__ cpx tws[tw_len<LOGN>()];
+    load_twiddles<LOGN>(tws, tw);
     __shared__ int ent_col[MAXE];
     __shared__ int ent_src[MAXE];
     __shared__ int n_ent;
@@ -225,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ 
         if (c0 + cc < g.rw) buf[((a - nk / 2) & (N - 1)) * CB + cc] = Ri[(int64_t)a * g.rw + c0 + cc];
     }
     __syncthreads();
-    fft_lds<LOGN, CB, false>(buf, tw);
+    fft_lds<LOGN, CB, false>(buf, tws);
     cpx *E = ext + (int64_t)item * g.ext_stride;
     const int ne = n_ent;
     for (int e = tid; e < ne * g.eh; e += NT) {
@@ -661,6 +673,8 @@ __global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ 
                                                 const cpx *__restrict__ tw, cpx *__restrict__ R) {
     constexpr int N = 1 << LOGN;
     __shared__ cpx buf[CB * N];
+    __shared__ cpx tws[tw_len<LOGN>()];
+    load_twiddles<LOGN>(tws, tw);
     const int tid = threadIdx.x;
     const int item = blockIdx.y;
     const int c0 = blockIdx.x * CB;
@@ -677,7 +691,7 @@ __global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ 
         buf[t1 * CB + cc] = v;
     }
     __syncthreads();
-    fft_lds<LOGN, CB, true>(buf, tw);
+    fft_lds<LOGN, CB, true>(buf, tws);
     cpx *Ri = R + (int64_t)item * g.r_stride;
     const int nk = g.nk;
     for (int e = tid; e < nk * CB; e += NT) {
@@ -695,6 +709,8 @@ __global__ __launch_bounds__(NT) void k_row_inv(Geom g, const cpx *__restrict__ 
                                                 const cpx *__restrict__ tw, real *__restrict__ gp) {
     constexpr int N = 1 << LOGN;
     __shared__ cpx buf[N];
+    __shared__ cpx tws[tw_len<LOGN>()];
+    load_twiddles<LOGN>(tws, tw);
     const int tid = threadIdx.x;
     const int item = blockIdx.y;
     const int k = item / g.C, c = item - (item / g.C) * g.C;
@@ -717,7 +733,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(Geom g, const cpx *__restrict__ 
         buf[kk] = cpx{x.re - y.im, x.im + y.re}; // x + i y
     }
     __syncthreads();
-    fft_lds<LOGN, 1, true>(buf, tw);
+    fft_lds<LOGN, 1, true>(buf, tws);
     const real *A = beams + (int64_t)k * nk * nk;
     real *out = gp + (int64_t)item * nk * nk;
     const real s = fscale[c];
