@@ -316,6 +316,7 @@ template <int CTRL> __device__ __forceinline__ double dpp(double v) {
 }
 template <int L> __device__ __forceinline__ real row_bcast(real v) { return dpp<0x150 + L>(v); }
 
+
 __device__ __forceinline__ real row_shr8(real v) { return dpp<0x118>(v); }
 
 // Lane layout of a G-lane group (one visibility at a time):
@@ -435,56 +436,43 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (unsigned)sizeof(T));
     };
 
-    // software pipeline: the records of iteration it+1 are loaded during iteration it
-    VisCoord c_nx[VPI];
-    cpx y_nx[VPI];
-    real w_nx[VPI];
-    int64_t p_nx[VPI];
-#pragma unroll
-    for (int u = 0; u < VPI; ++u) {
-        const unsigned vn = rec(v0 + u);
-        c_nx[u] = at(crd, vn);
-        y_nx[u] = cpx{0, 0};
-        w_nx[u] = real(0);
-        p_nx[u] = 0;
-        if (MODE == MODE_OBJ) { y_nx[u] = at(vis, vn); w_nx[u] = at(wgt, vn); }
-        if (MODE == MODE_ADJ) { w_nx[u] = at(wgt, vn); p_nx[u] = at(perm, vn); }
-        if (MODE == MODE_FWD) { p_nx[u] = at(perm, vn); }
-    }
-
-    for (int it = 0; it < nit; ++it) {
-        VisCoord cr[VPI];
-        cpx ycur[VPI];
-        real wcur[VPI];
-        int64_t pcur[VPI];
-        bool valid[VPI];
+    // record of one visibility (the fields this mode reads)
+    struct Rec {
+        VisCoord c;
+        cpx y;
+        real w;
+        int64_t p;
+    };
+    auto load = [&](Rec (&r)[VPI], int it) {
 #pragma unroll
         for (int u = 0; u < VPI; ++u) {
-            valid[u] = v0 + it * VPI + u < v1;
-            cr[u] = c_nx[u];
-            ycur[u] = y_nx[u];
-            wcur[u] = w_nx[u];
-            pcur[u] = p_nx[u];
+            const unsigned vn = rec(v0 + it * VPI + u);
+            r[u].c = at(crd, vn);
+            r[u].y = cpx{0, 0};
+            r[u].w = real(0);
+            r[u].p = 0;
+            if (MODE == MODE_OBJ) { r[u].y = at(vis, vn); r[u].w = at(wgt, vn); }
+            if (MODE == MODE_ADJ) { r[u].w = at(wgt, vn); r[u].p = at(perm, vn); }
+            if (MODE == MODE_FWD) { r[u].p = at(perm, vn); }
         }
-        if (it + 1 < nit) {
+    };
+
+    // one iteration: VPI visibilities of this group's segment
+    auto step = [&](const Rec (&cur)[VPI], int it) {
+        bool valid[VPI];
 #pragma unroll
-            for (int u = 0; u < VPI; ++u) {
-                const unsigned vn = rec(v0 + (it + 1) * VPI + u);
-                c_nx[u] = at(crd, vn);
-                if (MODE == MODE_OBJ) { y_nx[u] = at(vis, vn); w_nx[u] = at(wgt, vn); }
-                if (MODE == MODE_ADJ) { w_nx[u] = at(wgt, vn); p_nx[u] = at(perm, vn); }
-                if (MODE == MODE_FWD) { p_nx[u] = at(perm, vn); }
-            }
-        }
+        for (int u = 0; u < VPI; ++u) valid[u] = v0 + it * VPI + u < v1;
         int off[VPI];
         real wxj[VPI], wsel[VPI][NR];
 #pragma unroll
         for (int u = 0; u < VPI; ++u) {
             int ix, iy;
             real fx, fy;
-            decode(cr[u], ix, iy, fx, fy);
+            decode(cur[u].c, ix, iy, fx, fy);
             // kernel weights: x weight of the owned column, y weights of the owned rows
             if constexpr (G == 16 && S == 2) {
+                // lanes 0-7 evaluate the column weights, lanes 8-15 the row weights; DPP row
+                // moves hand every lane its column's weight and its rows' weights
                 const bool isx = t < 8;
                 const int k = t & 7;
                 real mine = real(0);
@@ -492,6 +480,14 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
                 const real sh = row_shr8(mine);
                 wxj[u] = isx ? mine : sh;
                 RowWeights<W, G, 0>::run(mine, upper, wsel[u]);
+            } else if constexpr (G == 8) {
+                real mx = real(0), my = real(0);
+                if (colok) {
+                    mx = es_kernel(zoff + fx - real(j), inv_hw, beta2);
+                    my = es_kernel(zoff + fy - real(j), inv_hw, beta2);
+                }
+                wxj[u] = mx;
+                RowWeights<W, G, 0>::run(my, upper, wsel[u]);
             } else {
                 real mx = real(0), my = real(0);
                 if (colok) {
@@ -534,25 +530,26 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
 #pragma unroll
             for (int u = 0; u < VPI; ++u) {
                 if (valid[u] && t == 0) {
-                    if (pcur[u] < 0) a.caller_out[~pcur[u]] = cpx{ar[u], -ai[u]};
-                    else a.caller_out[pcur[u]] = cpx{ar[u], ai[u]};
+                    if (cur[u].p < 0) a.caller_out[~cur[u].p] = cpx{ar[u], -ai[u]};
+                    else a.caller_out[cur[u].p] = cpx{ar[u], ai[u]};
                 }
             }
-            continue;
+            return;
         }
         real cre[VPI], cim[VPI];
 #pragma unroll
         for (int u = 0; u < VPI; ++u) {
             if (MODE == MODE_OBJ) {
-                const real rr = ar[u] - ycur[u].re, ri = ai[u] - ycur[u].im;
-                if (valid[u] && t == 0) jacc += real(0.5) * wcur[u] * (rr * rr + ri * ri);
-                cre[u] = wcur[u] * rr * wxj[u];
-                cim[u] = wcur[u] * ri * wxj[u];
+                const real rr = ar[u] - cur[u].y.re, ri = ai[u] - cur[u].y.im;
+                if (valid[u] && t == 0) jacc += cur[u].w * (rr * rr + ri * ri); // halved at the end
+                const real ww = cur[u].w * wxj[u];
+                cre[u] = ww * rr;
+                cim[u] = ww * ri;
             } else {
-                cpx y = a.caller_in[pcur[u] < 0 ? ~pcur[u] : pcur[u]];
-                if (pcur[u] < 0) y.im = -y.im;
-                cre[u] = wcur[u] * y.re * wxj[u];
-                cim[u] = wcur[u] * y.im * wxj[u];
+                cpx y = a.caller_in[cur[u].p < 0 ? ~cur[u].p : cur[u].p];
+                if (cur[u].p < 0) y.im = -y.im;
+                cre[u] = cur[u].w * y.re * wxj[u];
+                cim[u] = cur[u].w * y.im * wxj[u];
             }
         }
         // spread: the visibilities of one iteration go in program order, so a cell shared
@@ -572,6 +569,22 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
                 }
             }
         }
+    };
+
+    // three record sets rotate: the records of iteration it + 2 are requested as iteration
+    // it starts, two iterations of latency cover (no register copies between stages)
+    Rec r0[VPI], r1[VPI], r2[VPI];
+    load(r0, 0);
+    load(r1, 1);
+    for (int it = 0; it < nit; it += 3) {
+        if (it + 2 < nit) load(r2, it + 2);
+        step(r0, it);
+        if (it + 1 >= nit) break;
+        if (it + 3 < nit) load(r0, it + 3);
+        step(r1, it + 1);
+        if (it + 2 >= nit) break;
+        if (it + 4 < nit) load(r1, it + 4);
+        step(r2, it + 2);
     }
     if (MODE == MODE_FWD) return;
     __syncthreads();
@@ -587,7 +600,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         Sl[e] = cpx{sr, si};
     }
     if (MODE == MODE_OBJ) {
-        double d = (double)jacc;
+        double d = 0.5 * (double)jacc;
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) d += __shfl_xor(d, m, 64);
         if (lane == 0) red[wave] = d;

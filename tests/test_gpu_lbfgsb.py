@@ -70,7 +70,11 @@ def test_float_build_reaches_the_host_optimum(c1r):
     dev = DeviceSolver(plan).solve()
     host = solve(plan, maxiter=15000)
     print("device", dev.fun, dev.nit, dev.nfev, dev.message, "host", host.fun, host.nit, host.nfev, host.message)
-    assert dev.message in ("pgtol", "ftol")
+    # near the optimum the FP32 objective's rounding can defeat the line search; scipy then
+    # stops with an abnormal line search too, and the two loops must agree on that as well
+    assert dev.message in ("pgtol", "ftol", "abnormal")
+    if dev.message == "abnormal":
+        assert host.message.upper().startswith("ABNORMAL")
     assert dev.fun == pytest.approx(host.fun, rel=1e-6)
     assert float(dev.x.min()) >= 0.0
 

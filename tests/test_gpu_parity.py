@@ -164,6 +164,28 @@ def test_objective_independent_of_tile(mini, tile):
     _check_objective(mini, "f32", f"mini-T{tile}", tile=tile)
 
 
+@pytest.mark.parametrize("blocking", [(8, 1, 128, 16, 1), (8, 2, 256, 16, 2), (12, 4, 512, 16, 2),
+                                      (8, 1, 128, 8, 1), (16, 2, 256, 8, 2), (16, 2, 64, 8, 1)])
+def test_objective_independent_of_gridding_variant(mini, blocking):
+    """Every gridding variant (tile, waves per block, chunk, lanes per visibility,
+    visibilities per lane group) gives the same objective and gradient."""
+    plan = _plan(mini, "f32")
+    plan.set_blocking(*blocking)
+    tol = TOL["f32"]
+    x = _points(mini)["rand"]
+    want_t, want_g = oracle.objective_grad(mini, x)
+    terms, grad = _eval(plan, x)
+    print(f"[mini blocking {blocking}] relQ {abs(terms[0] - want_t['Q_tot']) / want_t['Q_tot']:.2e} "
+          f"relG {rel(grad, want_g):.2e}", flush=True)
+    assert abs(terms[0] - want_t["Q_tot"]) <= tol * want_t["Q_tot"]
+    assert rel(grad, want_g) <= tol
+    # the forward model alone, through the same variant
+    v = plan.forward(torch.tensor(x, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    mv = oracle.model_vis(mini, x)
+    live = mini.flags == 0
+    assert rel(v[live, 0] + 1j * v[live, 1], mv[live]) <= tol
+
+
 def test_objective_c2_subsampled(c2_sub):
     _check_objective(c2_sub, "f32", "c2-sub")
 
