@@ -112,6 +112,145 @@ __global__ __launch_bounds__(NT) void k_conv3x3(const float *__restrict__ x, int
     }
 }
 
+// LDS-tiled implicit GEMM for the 3x3 convolution: block tile 64 pixels x BN channels
+// (BN = 32 NJ), k chunks of 32 staged in LDS as bf16 (A: [pixel][k], B: [channel][k], rows
+// padded to 40 elements), 4 waves in a 2 x 2 arrangement, each wave 2 x NJ tiles of
+// v_mfma_f32_16x16x16_bf16.  The next chunk's global loads are issued before the current
+// chunk's matrix products.
+constexpr int TBM = 64, TBK = 32, TLD = 40;
+template <int NJ>
+__global__ __launch_bounds__(NT) void k_conv3x3_tiled(const float *__restrict__ x, int n, int h, int w, int cin,
+                                                      const uint16_t *__restrict__ wt, const float *__restrict__ bias,
+                                                      int cout, int relu, const float *__restrict__ mask,
+                                                      int accumulate, float *__restrict__ y) {
+    constexpr int BN = 32 * NJ;
+    __shared__ __align__(16) uint16_t As[TBM * TLD];
+    __shared__ __align__(16) uint16_t Bs[BN * TLD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t P = (int64_t)n * h * w;
+    const int K = 9 * cin;
+    const int64_t m0 = (int64_t)blockIdx.x * TBM;
+    const int n0 = blockIdx.y * BN;
+    // ---- global -> register staging: A (pixel am, k quarter aq), B (channel rows)
+    const int am = tid >> 2, aq = (tid & 3) * 8;
+    const int64_t ap = m0 + am;
+    int apn = 0, apy = 0, apx = 0;
+    const bool apv = ap < P;
+    if (apv) {
+        apn = (int)(ap / ((int64_t)h * w));
+        const int r = (int)(ap - (int64_t)apn * h * w);
+        apy = r / w;
+        apx = r - apy * w;
+    }
+    constexpr int BPIECES = BN * (TBK / 8);           // 8-element pieces of one B chunk
+    constexpr int BROWS = (BPIECES + NT - 1) / NT;    // per thread (1 or 2)
+    uint16_t ra[8];
+    uint16_t rb[BROWS][8];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int hlf = 0; hlf < 2; ++hlf) {
+            const int k = k0 + aq + 4 * hlf;
+            float4 v = float4{0.f, 0.f, 0.f, 0.f};
+            if (apv && k < K) {
+                const int tap = k / cin, c = k - tap * cin;
+                const int yy = apy + tap / 3 - 1, xx = apx + tap % 3 - 1;
+                if (yy >= 0 && yy < h && xx >= 0 && xx < w)
+                    v = *reinterpret_cast<const float4 *>(x + (((int64_t)apn * h + yy) * w + xx) * cin + c);
+            }
+            ra[4 * hlf + 0] = f2bf(v.x);
+            ra[4 * hlf + 1] = f2bf(v.y);
+            ra[4 * hlf + 2] = f2bf(v.z);
+            ra[4 * hlf + 3] = f2bf(v.w);
+        }
+#pragma unroll
+        for (int b = 0; b < BROWS; ++b) {
+            const int e = tid + b * NT;
+            const int o = e >> 2, bq = (e & 3) * 8;
+#pragma unroll
+            for (int hlf = 0; hlf < 2; ++hlf) {
+                const int k = k0 + bq + 4 * hlf;
+                uint2 u = uint2{0u, 0u};
+                if (e < BPIECES && n0 + o < cout && k < K) u = *reinterpret_cast<const uint2 *>(wt + (int64_t)(n0 + o) * K + k);
+                rb[b][4 * hlf + 0] = (uint16_t)(u.x & 0xFFFFu);
+                rb[b][4 * hlf + 1] = (uint16_t)(u.x >> 16);
+                rb[b][4 * hlf + 2] = (uint16_t)(u.y & 0xFFFFu);
+                rb[b][4 * hlf + 3] = (uint16_t)(u.y >> 16);
+            }
+        }
+    };
+    auto sstore = [&]() {
+        uint4 va;
+        va.x = ra[0] | ((uint32_t)ra[1] << 16);
+        va.y = ra[2] | ((uint32_t)ra[3] << 16);
+        va.z = ra[4] | ((uint32_t)ra[5] << 16);
+        va.w = ra[6] | ((uint32_t)ra[7] << 16);
+        *reinterpret_cast<uint4 *>(&As[am * TLD + aq]) = va;
+#pragma unroll
+        for (int b = 0; b < BROWS; ++b) {
+            const int e = tid + b * NT;
+            if (e >= BPIECES) continue;
+            const int o = e >> 2, bq = (e & 3) * 8;
+            uint4 vb;
+            vb.x = rb[b][0] | ((uint32_t)rb[b][1] << 16);
+            vb.y = rb[b][2] | ((uint32_t)rb[b][3] << 16);
+            vb.z = rb[b][4] | ((uint32_t)rb[b][5] << 16);
+            vb.w = rb[b][6] | ((uint32_t)rb[b][7] << 16);
+            *reinterpret_cast<uint4 *>(&Bs[o * TLD + bq]) = vb;
+        }
+    };
+    // ---- matrix products: wave (wr, wc) owns rows 32 wr .. +32, columns 16 NJ wc .. +16 NJ
+    const int wr = wave >> 1, wc = wave & 1;
+    const int row = lane & 15, kq = lane >> 4;
+    f32x4 acc[2][NJ];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nch = (K + TBK - 1) / TBK;
+    gload(0);
+    for (int kc = 0; kc < nch; ++kc) {
+        __syncthreads();
+        sstore();
+        __syncthreads();
+        if (kc + 1 < nch) gload((kc + 1) * TBK);
+#pragma unroll
+        for (int ks = 0; ks < TBK / 16; ++ks) {
+            bf16x4 af[2], bfr[NJ];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                af[i] = *reinterpret_cast<const bf16x4 *>(&As[(wr * 32 + i * 16 + row) * TLD + ks * 16 + 4 * kq]);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+                bfr[j] = *reinterpret_cast<const bf16x4 *>(&Bs[(wc * 16 * NJ + j * 16 + row) * TLD + ks * 16 + 4 * kq]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // ---- epilogue: D row (pixel) 4 kq + v, column (channel) = row index of the lane
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int co = n0 + wc * 16 * NJ + j * 16 + row;
+            if (co >= cout) continue;
+            const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t pp = m0 + wr * 32 + i * 16 + 4 * kq + v;
+                if (pp >= P) continue;
+                const int64_t o = pp * cout + co;
+                float val = acc[i][j][v] + bb;
+                if (relu) val = fmaxf(val, 0.f);
+                if (mask && !(mask[o] > 0.f)) val = 0.f;
+                if (accumulate) val += y[o];
+                y[o] = val;
+            }
+        }
+}
+
 // Weight-gradient partials: block (k tile of 64, o tile of 64, pixel range z).
 constexpr int GW_PIX = 1024;
 __global__ __launch_bounds__(NT) void k_conv3x3_gw(const float *__restrict__ x, const float *__restrict__ dy,
@@ -172,6 +311,137 @@ __global__ __launch_bounds__(NT) void k_conv3x3_gw(const float *__restrict__ x, 
             const int o = blockIdx.y * 64 + wave * 16 + 4 * q + v;
             if (o < cout) part[((int64_t)blockIdx.z * cout + o) * K + k] = acc[t][v];
         }
+    }
+}
+
+// Weight and bias gradient partials, LDS-tiled: block (k tile of 64, o tile of 64, pixel
+// range z of `ps` pixels).  The pixel range is walked in chunks of 32: dy (A, [o][pixel]) and
+// the im2col view of x (B, [k][pixel]) are staged in LDS as bf16, transposed so that each
+// lane's four reduction elements are contiguous; 4 waves in a 2 x 2 arrangement each own
+// 32 x 32 outputs (2 x 2 tiles of v_mfma_f32_16x16x16_bf16).  Blocks of the first k tile also
+// sum dy in FP32 for the bias.  part[z] = [dw partial (cout x K) | db partial (cout)].
+// Requires cin % 4 == 0 and cout % 4 == 0.
+constexpr int GW_PC = 32, GW_LD = 40, GW_TARGET_BLOCKS = 2048, GW_MIN_PIX = 256;
+__global__ __launch_bounds__(NT) void k_conv3x3_gw_tiled(const float *__restrict__ x, const float *__restrict__ dy,
+                                                         int n, int h, int w, int cin, int cout, int64_t ps,
+                                                         float *__restrict__ part) {
+    __shared__ __align__(16) uint16_t As[64 * GW_LD];
+    __shared__ __align__(16) uint16_t Bs[64 * GW_LD];
+    __shared__ float sb[16][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t P = (int64_t)n * h * w;
+    const int64_t hw = (int64_t)h * w;
+    const int K = 9 * cin;
+    const int64_t len = (int64_t)cout * K + cout;
+    const int o0 = blockIdx.y * 64, k0 = blockIdx.x * 64;
+    const int64_t p0 = (int64_t)blockIdx.z * ps;
+    const int64_t p1 = p0 + ps < P ? p0 + ps : P;
+    // staging: pixel pair 2 sp (fastest within a wave), 4 rows g4 .. g4 + 3 of A and of B
+    const int sp = tid & 15, g4 = (tid >> 4) * 4;
+    const bool ov = o0 + g4 < cout;
+    const int kk = k0 + g4;
+    const bool kv = kk < K;
+    const int tap = kv ? kk / cin : 0;
+    const int tc = kk - tap * cin, tdy = tap / 3 - 1, tdx = tap % 3 - 1;
+    const bool do_bias = blockIdx.x == 0;
+    float4 ra[2], rb[2];
+    float bs[4] = {0.f, 0.f, 0.f, 0.f};
+    auto gload = [&](int64_t pc) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int64_t p = pc + 2 * sp + e;
+            ra[e] = float4{0.f, 0.f, 0.f, 0.f};
+            rb[e] = float4{0.f, 0.f, 0.f, 0.f};
+            if (p < p1) {
+                if (ov) ra[e] = *reinterpret_cast<const float4 *>(dy + p * cout + o0 + g4);
+                const int pn = (int)(p / hw);
+                const int r = (int)(p - pn * hw);
+                const int yy = r / w + tdy, xx = r % w + tdx;
+                if (kv && yy >= 0 && yy < h && xx >= 0 && xx < w)
+                    rb[e] = *reinterpret_cast<const float4 *>(x + (((int64_t)pn * h + yy) * w + xx) * cin + tc);
+            }
+        }
+    };
+    auto sstore = [&]() {
+        const float *a0 = reinterpret_cast<const float *>(&ra[0]), *a1 = reinterpret_cast<const float *>(&ra[1]);
+        const float *b0 = reinterpret_cast<const float *>(&rb[0]), *b1 = reinterpret_cast<const float *>(&rb[1]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            *reinterpret_cast<uint32_t *>(&As[(g4 + i) * GW_LD + 2 * sp]) = f2bf(a0[i]) | ((uint32_t)f2bf(a1[i]) << 16);
+            *reinterpret_cast<uint32_t *>(&Bs[(g4 + i) * GW_LD + 2 * sp]) = f2bf(b0[i]) | ((uint32_t)f2bf(b1[i]) << 16);
+            bs[i] += a0[i] + a1[i];
+        }
+    };
+    const int wr = wave >> 1, wc = wave & 1;
+    const int row = lane & 15, kq = lane >> 4;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    gload(p0);
+    for (int64_t pc = p0; pc < p1; pc += GW_PC) {
+        __syncthreads();
+        sstore();
+        __syncthreads();
+        if (pc + GW_PC < p1) gload(pc + GW_PC);
+#pragma unroll
+        for (int ks = 0; ks < GW_PC / 16; ++ks) {
+            bf16x4 af[2], bfr[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                af[i] = *reinterpret_cast<const bf16x4 *>(&As[(wr * 32 + i * 16 + row) * GW_LD + ks * 16 + 4 * kq]);
+                bfr[i] = *reinterpret_cast<const bf16x4 *>(&Bs[(wc * 32 + i * 16 + row) * GW_LD + ks * 16 + 4 * kq]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    float *pz = part + (int64_t)blockIdx.z * len;
+    // D row (o) 4 kq + v, column (k) = the lane's row index
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int k = k0 + wc * 32 + j * 16 + row;
+            if (k >= K) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int o = o0 + wr * 32 + i * 16 + 4 * kq + v;
+                if (o < cout) pz[(int64_t)o * K + k] = acc[i][j][v];
+            }
+        }
+    if (do_bias) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sb[sp][g4 + i] = bs[i];
+        __syncthreads();
+        if (tid < 64 && o0 + tid < cout) {
+            float s = 0.f;
+            for (int q = 0; q < 16; ++q) s += sb[q][tid];
+            pz[(int64_t)cout * K + o0 + tid] = s;
+        }
+    }
+}
+
+// out[i] = sum over splits of part[z][i] in a fixed order: block = 64 consecutive i x 4
+// interleaved split groups, combined in LDS.  i < nw goes to dw, the rest to db.
+__global__ __launch_bounds__(NT) void k_sum_splits(const float *__restrict__ part, int splits, int64_t len,
+                                                   int64_t nw, float *__restrict__ dw, float *__restrict__ db) {
+    __shared__ float sh[4][64];
+    const int64_t i = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    const int g = threadIdx.x >> 6;
+    float s = 0.f;
+    if (i < len)
+        for (int z = g; z < splits; z += 4) s += part[(int64_t)z * len + i];
+    sh[g][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (g == 0 && i < len) {
+        const float t = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+        if (i < nw) dw[i] = t;
+        else db[i - nw] = t;
     }
 }
 
@@ -417,7 +687,11 @@ hipError_t conv3x3(const float *x, int n, int h, int w, int cin, const uint16_t 
                    int relu, const float *mask, int accumulate, float *y, hipStream_t st) {
     const int64_t P = (int64_t)n * h * w;
     const unsigned gx = (unsigned)((P + 63) / 64);
-    if (cout % 64 == 0) k_conv3x3<4><<<dim3(gx, cout / 64), NT, 0, st>>>(x, n, h, w, cin, wt, bias, cout, relu, mask, accumulate, y);
+    if (cin >= 16 && cout % 64 == 0)
+        k_conv3x3_tiled<2><<<dim3(gx, cout / 64), NT, 0, st>>>(x, n, h, w, cin, wt, bias, cout, relu, mask, accumulate, y);
+    else if (cin >= 16 && cout % 32 == 0)
+        k_conv3x3_tiled<1><<<dim3(gx, cout / 32), NT, 0, st>>>(x, n, h, w, cin, wt, bias, cout, relu, mask, accumulate, y);
+    else if (cout % 64 == 0) k_conv3x3<4><<<dim3(gx, cout / 64), NT, 0, st>>>(x, n, h, w, cin, wt, bias, cout, relu, mask, accumulate, y);
     else if (cout % 32 == 0) k_conv3x3<2><<<dim3(gx, cout / 32), NT, 0, st>>>(x, n, h, w, cin, wt, bias, cout, relu, mask, accumulate, y);
     else k_conv3x3<1><<<dim3(gx, (cout + 15) / 16), NT, 0, st>>>(x, n, h, w, cin, wt, bias, cout, relu, mask, accumulate, y);
     return hipGetLastError();
@@ -425,9 +699,44 @@ hipError_t conv3x3(const float *x, int n, int h, int w, int cin, const uint16_t 
 
 int64_t gw_splits(int n, int h, int w) { return ((int64_t)n * h * w + GW_PIX - 1) / GW_PIX; }
 
+bool gw_tiled(int cin, int cout) { return cin % 4 == 0 && cout % 4 == 0; }
+
+// Split count asked for by the tiled weight gradient: about GW_TARGET_BLOCKS blocks in all
+// and at least GW_MIN_PIX pixels per split; non-decreasing in P.
+int64_t gw_want_splits(int64_t P, int cin, int cout) {
+    const int64_t tiles = (int64_t)((9 * cin + 63) / 64) * ((cout + 63) / 64);
+    const int64_t want = std::min((GW_TARGET_BLOCKS + tiles - 1) / tiles, (P + GW_MIN_PIX - 1) / GW_MIN_PIX);
+    return std::max<int64_t>(want, 1);
+}
+
+// Pixels per split: a whole number of 32-pixel chunks, so at most gw_want_splits splits.
+int64_t gw_split_pixels(int64_t P, int cin, int cout) {
+    const int64_t want = gw_want_splits(P, cin, cout);
+    const int64_t ps = (P + want - 1) / want;
+    return (ps + GW_PC - 1) / GW_PC * GW_PC;
+}
+
+// Floats of split partials conv3x3_grad_weight needs for this shape; enough for any
+// smaller n as well.
+int64_t gw_part_len(int n, int h, int w, int cin, int cout) {
+    const int64_t P = (int64_t)n * h * w;
+    if (!gw_tiled(cin, cout)) return gw_splits(n, h, w) * cout * 9 * cin;
+    return gw_want_splits(P, cin, cout) * ((int64_t)cout * 9 * cin + cout);
+}
+
 hipError_t conv3x3_grad_weight(const float *x, const float *dy, int n, int h, int w, int cin, int cout, float *part,
                                float *dw, float *db, hipStream_t st) {
     const int K = 9 * cin;
+    if (gw_tiled(cin, cout)) {
+        const int64_t P = (int64_t)n * h * w;
+        const int64_t ps = gw_split_pixels(P, cin, cout);
+        const int64_t splits = (P + ps - 1) / ps;
+        k_conv3x3_gw_tiled<<<dim3((K + 63) / 64, (cout + 63) / 64, (unsigned)splits), NT, 0, st>>>(
+            x, dy, n, h, w, cin, cout, ps, part);
+        const int64_t len = (int64_t)cout * K + cout;
+        k_sum_splits<<<(unsigned)((len + 63) / 64), NT, 0, st>>>(part, (int)splits, len, (int64_t)cout * K, dw, db);
+        return hipGetLastError();
+    }
     const int64_t splits = gw_splits(n, h, w);
     k_conv3x3_gw<<<dim3((K + 63) / 64, (cout + 63) / 64, (unsigned)splits), NT, 0, st>>>(x, dy, n, h, w, cin, cout, part);
     const int64_t len = (int64_t)cout * K;
@@ -678,7 +987,7 @@ ivx_status ivx_unet_create(int32_t levels, int32_t base, int32_t max_batch, int3
                 return fail(s);
         }
     }
-    for (const ConvLayer &c : u->conv) maxpart = std::max<int64_t>(maxpart, gw_splits((int)B, c.h, c.w) * c.cout * 9 * c.cin);
+    for (const ConvLayer &c : u->conv) maxpart = std::max<int64_t>(maxpart, gw_part_len((int)B, c.h, c.w, c.cin, c.cout));
     if ((s = ualloc(u, &u->part, maxpart)) || (s = ualloc(u, &u->out, P0)) || (s = ualloc(u, &u->gout, P0)) ||
         (s = ualloc(u, &u->head_part, (int64_t)nblocks(P0) * (u->ch[0] + 1))) ||
         (s = ualloc(u, &u->loss_part, (int64_t)nblocks(P0))) || (s = ualloc(u, &u->loss, 1)))
@@ -801,7 +1110,7 @@ ivx_status ivx_nn_conv3x3_grad_weight(const float *x, const float *dy, int32_t n
         return set_error(IVX_EINVAL, "bad conv3x3_grad_weight arguments");
     hipStream_t st = (hipStream_t)stream;
     float *part = nullptr;
-    UHIP(hipMalloc(&part, (size_t)gw_splits(n, h, w) * cout * 9 * cin * sizeof(float)));
+    UHIP(hipMalloc(&part, (size_t)gw_part_len(n, h, w, cin, cout) * sizeof(float)));
     hipError_t e = conv3x3_grad_weight(x, dy, n, h, w, cin, cout, part, dw, db, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(part);

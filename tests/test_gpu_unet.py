@@ -56,7 +56,7 @@ def test_to_bf16_rounds_to_nearest_even(nn):
 
 
 @pytest.mark.parametrize("cin,cout,relu", [(4, 16, False), (8, 32, True), (12, 48, True), (16, 64, False),
-                                           (20, 128, True)])
+                                           (20, 128, True), (24, 96, False), (64, 32, True)])
 def test_conv3x3_matches_oracle(nn, cin, cout, relu):
     rng = np.random.default_rng(cin * 100 + cout)
     n, h, w = 2, 11, 19          # 418 pixels: six full 64-pixel blocks and a ragged one
@@ -72,9 +72,10 @@ def test_conv3x3_matches_oracle(nn, cin, cout, relu):
     assert np.abs(want).max() > 1.0
 
 
-def test_conv3x3_mask_and_accumulate(nn):
-    rng = np.random.default_rng(11)
-    n, h, w, cin, cout = 1, 9, 13, 8, 32
+@pytest.mark.parametrize("cin", [8, 32])
+def test_conv3x3_mask_and_accumulate(nn, cin):
+    rng = np.random.default_rng(11 + cin)
+    n, h, w, cout = 1, 9, 13, 32
     x = rng.standard_normal((n, h, w, cin)).astype(np.float32)
     wt = rng.standard_normal((cout, 3, 3, cin)).astype(np.float32)
     mask = np.maximum(rng.standard_normal((n, h, w, cout)), 0).astype(np.float32)
@@ -105,7 +106,8 @@ def test_flip_gives_the_transposed_correlation(nn):
     assert np.all(np.abs(gin - want) <= bound)
 
 
-@pytest.mark.parametrize("n,h,w,cin,cout", [(1, 6, 10, 4, 16), (2, 23, 33, 16, 32), (3, 32, 32, 8, 80)])
+@pytest.mark.parametrize("n,h,w,cin,cout", [(1, 6, 10, 4, 16), (2, 23, 33, 16, 32), (3, 32, 32, 8, 80),
+                                             (2, 40, 51, 96, 64), (1, 7, 9, 6, 16), (1, 9, 11, 8, 18)])
 def test_conv3x3_grad_weight_matches_oracle(nn, n, h, w, cin, cout):
     rng = np.random.default_rng(n * 1000 + h)
     x = rng.standard_normal((n, h, w, cin)).astype(np.float32)
