@@ -112,20 +112,39 @@ ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out);
 
 /* Copy the data of every block into the plan (Sect. 3.2: all pointings concatenated):
  * drops flagged visibilities, folds u<0 onto u>0 by Hermitian symmetry of a real sky,
- * sorts by fine-grid tile and builds the work list.  beams and interp are required;
- * flags and sd_map may be NULL (sd_map is required when lambda_s > 0 and sd_n > 0).
- * Returns IVX_ENONFINITE if an unflagged visibility, weight or uv is not finite, or a
- * weight is negative.  May be called again to replace the data (same sizes). */
+ * sorts by fine-grid tile and builds the work list, on the device, one block at a time
+ * (host arrays are staged block by block, so host inputs need no device copy of the whole
+ * data set).  beams and interp are required; flags and sd_map may be NULL (sd_map is
+ * required when lambda_s > 0 and sd_n > 0).  Every block must hold fewer than 2^31
+ * visibilities (IVX_EINVAL otherwise).  Returns IVX_ENONFINITE if an unflagged
+ * visibility, weight or uv is not finite, IVX_EINVAL if a weight is negative (whichever
+ * comes first in caller order).  May be called again to replace the data (same sizes).
+ * Device memory kept: 20 B (float build; 28 B FP64) per live visibility plus the grids. */
 ivx_status ivx_plan_set_data(ivx_plan *plan, const ivx_real *uv, const ivx_real *vis,
                              const ivx_real *weight, const uint8_t *flags,
                              const ivx_real *beams, const ivx_real *interp,
                              const ivx_real *sd_map, void *stream);
 
+/* As ivx_plan_set_data for a spectral cube whose channels share one uv track per
+ * pointing (Sect. 2.2: the same baselines observed at every frequency):
+ *   uv      [sum_k M_k][2]  pointing k's samples at rows pt_k .. pt_k + M_k - 1 (pointing
+ *                           order), in wavelengths at a reference frequency
+ *   weight  [sum_k M_k]     natural weights, the same for every channel
+ *   uv_scale[C]             host; channel c sees uv * uv_scale[c] (nu_c / nu_ref), > 0
+ *   vis     [M][2], flags [M] (or NULL): per (pointing, channel) block as in set_data
+ * Every channel of pointing k must have M_k visibilities in vis_offsets (IVX_EINVAL
+ * otherwise).  ivx_plan_set_vis on such a plan takes weights in the [sum_k M_k] layout. */
+ivx_status ivx_plan_set_data_shared(ivx_plan *plan, const ivx_real *uv, const ivx_real *weight,
+                                    const double *uv_scale, const ivx_real *vis,
+                                    const uint8_t *flags, const ivx_real *beams,
+                                    const ivx_real *interp, const ivx_real *sd_map, void *stream);
+
 /* Replace the visibility data (and, if `weight` is non-NULL, the weights) of a plan whose
- * uv coverage, flags, beams and grids stay the same: vis [M][2] and weight [M] in the
- * caller's order, device memory.  The reordering runs on the device; IVX_ENONFINITE if an
- * unflagged value is not finite or a weight is negative (checked on the device, then the
- * stream is synchronised).  Same observation, new data: no re-sort. */
+ * uv coverage, flags, beams and grids stay the same: vis [M][2] and weight [M] (or
+ * [sum_k M_k] for a shared-uv plan) in the caller's order, host or device memory.  The
+ * reordering runs on the device; IVX_ENONFINITE if an unflagged value is not finite or a
+ * weight is negative (checked on the device, then the stream is synchronised).  Same
+ * observation, new data: no re-sort. */
 ivx_status ivx_plan_set_vis(ivx_plan *plan, const ivx_real *vis, const ivx_real *weight,
                             void *stream);
 

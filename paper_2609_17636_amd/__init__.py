@@ -66,6 +66,7 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.ivx_plan_create.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(vp)]
     lib.ivx_plan_set_data.argtypes = [vp] * 9
+    lib.ivx_plan_set_data_shared.argtypes = [vp] * 10
     lib.ivx_objective_grad.argtypes = [vp, vp, vp, vp, vp]
     lib.ivx_forward.argtypes = [vp, vp, vp, vp]
     lib.ivx_adjoint.argtypes = [vp, vp, vp, vp]
@@ -104,6 +105,13 @@ def _ptr(a) -> Optional[int]:
         return a.ctypes.data
     assert a.is_contiguous()
     return a.data_ptr()
+
+
+def _flags(f):
+    if isinstance(f, np.ndarray):
+        return np.ascontiguousarray(f, dtype=np.uint8)
+    torch = _torch()
+    return f.to(torch.uint8).contiguous()
 
 
 def _stream_ptr(stream=None) -> Optional[int]:
@@ -180,17 +188,39 @@ class Plan:
         return torch.float32 if self.precision == "f32" else torch.float64
 
     # ----------------------------------------------------------------------- data
+    def _pairs(self, vis):
+        """Complex numpy visibilities as a [M][2] real array (a view when the precision
+        matches, so large host arrays are not copied)."""
+        if isinstance(vis, np.ndarray) and np.iscomplexobj(vis):
+            want = np.complex64 if self.precision == "f32" else np.complex128
+            if vis.dtype == want and vis.flags.c_contiguous:
+                return vis.view(self.np_real).reshape(-1, 2)
+            return np.stack([vis.real, vis.imag], axis=-1)
+        return vis
+
     def set_data(self, uv, vis, weight, beams, interp, flags=None, sd_map=None, stream=None):
         """uv [M][2], vis [M] complex or [M][2], weight [M], beams [P][n][n], interp
-        [P][n][n][2], flags [M] uint8 or None, sd_map [C][sd][sd] or None."""
-        if isinstance(vis, np.ndarray) and np.iscomplexobj(vis):
-            vis = np.stack([vis.real, vis.imag], axis=-1)
-        keep = [self._real(uv), self._real(vis), self._real(weight), self._real(beams),
+        [P][n][n][2], flags [M] uint8 or None, sd_map [C][sd][sd] or None (host numpy or
+        cuda tensors)."""
+        keep = [self._real(uv), self._real(self._pairs(vis)), self._real(weight), self._real(beams),
                 self._real(interp), self._real(sd_map)]
-        fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.uint8)
+        fl = None if flags is None else _flags(flags)
         uv_, vis_, w_, b_, g_, sd_ = keep
         self._check(self.lib.ivx_plan_set_data(self._h, _ptr(uv_), _ptr(vis_), _ptr(w_), _ptr(fl),
                                                 _ptr(b_), _ptr(g_), _ptr(sd_), _stream_ptr(stream)))
+
+    def set_data_shared(self, uv, weight, uv_scale, vis, beams, interp, flags=None, sd_map=None, stream=None):
+        """Spectral cube with one uv track per pointing: uv [sum_k M_k][2] and weight
+        [sum_k M_k] in pointing order, uv_scale [C] (channel c sees uv * uv_scale[c]),
+        vis [M] complex or [M][2] and flags [M] per (pointing, channel) block."""
+        keep = [self._real(uv), self._real(weight), self._real(self._pairs(vis)), self._real(beams),
+                self._real(interp), self._real(sd_map)]
+        sc = np.ascontiguousarray(uv_scale, dtype=np.float64)
+        fl = None if flags is None else _flags(flags)
+        uv_, w_, vis_, b_, g_, sd_ = keep
+        self._check(self.lib.ivx_plan_set_data_shared(self._h, _ptr(uv_), _ptr(w_), sc.ctypes.data, _ptr(vis_),
+                                                       _ptr(fl), _ptr(b_), _ptr(g_), _ptr(sd_),
+                                                       _stream_ptr(stream)))
 
     def set_vis(self, vis, weight=None, stream=None):
         """New data (and weights) for the same observation: cuda tensors [M][2] (or complex

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
-SOURCES = ["ivx_api.hip", "ivx_kernels.hip", "ivx_unet.hip", "ivx_lbfgsb.hip"]
+SOURCES = ["ivx_api.hip", "ivx_build.hip", "ivx_kernels.hip", "ivx_unet.hip", "ivx_lbfgsb.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 LIBS = {"f32": "libivx.so", "f64": "libivx_f64.so"}

@@ -101,15 +101,6 @@ int ilog2(int v) {
     return l;
 }
 
-// Host copy of one live visibility after the fold (tile-independent part).
-struct HostVis {
-    int32_t er0, ec0; // extended-grid cell of the footprint start (row, col)
-    double fy, fx;    // fractional offsets in [0, 1)
-    int64_t src;      // caller index, bit-inverted when folded
-    real yr, yi;      // data (conjugated when folded)
-    real w;           // weight
-};
-
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -135,8 +126,12 @@ struct ivx_plan {
     int n_work = 0, n_slots = 0;
     int sd_rb = 0;
     std::vector<real> gB_host;
-    std::vector<HostVis> hv;          // live visibilities, block-major, caller order
     std::vector<int64_t> block_live;  // live count prefix per block
+    bool shared_uv = false;           // uv and weights given once per pointing
+    std::vector<int64_t> pt_off;      // shared_uv: pointing offsets into uv / weights
+    // tiling the records are currently sorted for, and their per-(block, tile) counts
+    int bin_T = 0, bin_ntx = 0, bin_ntiles = 0;
+    std::vector<int32_t> tcount;      // [n_items][bin_ntiles]
     // device memory
     std::vector<DevBuf> bufs;
     real *d_dq = nullptr, *d_fscale = nullptr;
@@ -145,7 +140,9 @@ struct ivx_plan {
     VisCoord *d_crd = nullptr;
     cpx *d_vis = nullptr;
     real *d_wgt = nullptr;
-    int64_t *d_perm = nullptr;
+    int32_t *d_perm = nullptr;   // caller index within the block (bit-inverted when folded)
+    int64_t *d_boff = nullptr;   // caller offset of each block
+    int32_t *d_tstart = nullptr; // [n_items][bin_ntiles + 1] tile prefix of each block's records
     WorkItem *d_work = nullptr;
     int32_t *d_tslot = nullptr;
     cpx *d_R = nullptr, *d_ext = nullptr, *d_slots = nullptr;
@@ -213,6 +210,10 @@ void free_all(ivx_plan *p) {
     p->d_vis = nullptr;
     p->d_wgt = nullptr;
     p->d_perm = nullptr;
+    p->d_boff = nullptr;
+    p->d_tstart = nullptr;
+    p->bin_T = p->bin_ntx = p->bin_ntiles = 0;
+    p->tcount.clear();
     p->d_work = nullptr;
     p->d_tslot = nullptr;
     p->d_R = p->d_ext = p->d_slots = nullptr;
@@ -288,59 +289,258 @@ bool auto_blocking(ivx_plan *p) {
     return false;
 }
 
-// Build the tile-dependent device data: sorted records, work list, slot CSR.
-ivx_status build_bins(ivx_plan *p, hipStream_t st) {
-    Geom &g = p->g;
+// Plan-time temporary device buffer (not counted in the plan's memory).
+struct TmpBuf {
+    void *p = nullptr;
+    ~TmpBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t get(size_t bytes) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        return hipMalloc(&p, bytes > 0 ? bytes : 1);
+    }
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+bool on_device(const void *ptr) {
+    if (!ptr) return false;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// The caller's visibility arrays.  Per block b = k * C + c: vis / flags at the block's
+// caller offset; uv / weights at the same offset, or (shared_uv) at pointing k's offset,
+// with uv multiplied by scale[c].
+struct VisSource {
+    const real *uv = nullptr, *vis = nullptr, *w = nullptr;
+    const uint8_t *flags = nullptr;
+    const double *scale = nullptr;
+};
+
+// One (possibly staged) array of a block: the caller's device pointer, or a copy of the
+// caller's host data in `stage`.
+template <typename T>
+ivx_status block_view(const T *base, bool dev, int64_t off, int64_t count, const TmpBuf &stage, const T **out,
+                      hipStream_t st) {
+    if (dev || count == 0) {
+        *out = base + off;
+        return IVX_OK;
+    }
+    IVX_HIP(hipMemcpyAsync(stage.p, base + off, count * sizeof(T), hipMemcpyHostToDevice, st));
+    *out = stage.as<T>();
+    return IVX_OK;
+}
+
+int key_bits(int ntiles) {
+    int b = 1;
+    while ((1 << b) <= ntiles) ++b;
+    return 32 + b;
+}
+
+// Record counts per (block, tile) -> host copy, and the per-block tile prefix on the device
+// in `tstart` (a plan buffer of n_items * (ntiles + 1) entries that replaces the old one).
+ivx_status store_counts(ivx_plan *p, const int32_t *d_counts, int ntiles, int32_t *tstart, hipStream_t st) {
+    const int n_items = p->g.C * p->g.P;
+    std::vector<int32_t> cnt((size_t)n_items * ntiles);
+    IVX_HIP(hipMemcpyAsync(cnt.data(), d_counts, cnt.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    IVX_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> ts((size_t)n_items * (ntiles + 1));
+    for (int b = 0; b < n_items; ++b) {
+        int32_t acc = 0;
+        for (int t = 0; t < ntiles; ++t) {
+            ts[(size_t)b * (ntiles + 1) + t] = acc;
+            acc += cnt[(size_t)b * ntiles + t];
+        }
+        ts[(size_t)b * (ntiles + 1) + ntiles] = acc;
+        if (acc != p->block_live[b + 1] - p->block_live[b]) return fail(IVX_EHIP, "binning lost records");
+    }
+    if (p->d_tstart) free_one(p, p->d_tstart);
+    p->d_tstart = tstart;
+    IVX_HIP(hipMemcpyAsync(p->d_tstart, ts.data(), ts.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    IVX_HIP(hipStreamSynchronize(st));
+    p->tcount.swap(cnt);
+    p->bin_T = p->g.T;
+    p->bin_ntx = p->g.ntx;
+    p->bin_ntiles = ntiles;
+    return IVX_OK;
+}
+
+// Live records of every block from the caller's arrays, sorted by (tile, caller index) for
+// the current tile edge.  Fails with IVX_ENONFINITE / IVX_EINVAL at the first bad sample.
+ivx_status bin_from_caller(ivx_plan *p, const VisSource &src, hipStream_t st) {
+    const Geom &g = p->g;
     const int n_items = g.C * g.P;
     const int ntiles = g.nty * g.ntx;
-    const int64_t L = p->m_live;
+    std::vector<int64_t> nb(n_items), live(n_items);
+    int64_t maxn = 0, maxuv = 0;
+    for (int b = 0; b < n_items; ++b) {
+        nb[b] = p->offsets[b + 1] - p->offsets[b];
+        if (nb[b] > (int64_t)INT32_MAX)
+            return fail(IVX_EINVAL, "a (pointing, channel) block holds more than 2^31 - 1 visibilities");
+        maxn = std::max(maxn, nb[b]);
+    }
+    if (p->shared_uv)
+        for (int k = 0; k < g.P; ++k) maxuv = std::max(maxuv, p->pt_off[k + 1] - p->pt_off[k]);
+    else
+        maxuv = maxn;
+    const bool uv_dev = on_device(src.uv), vis_dev = on_device(src.vis), w_dev = on_device(src.w);
+    const bool fl_dev = on_device(src.flags);
+    // ---- live counts (from the flags alone)
+    if (!src.flags) {
+        live = nb;
+    } else if (fl_dev) {
+        TmpBuf dc;
+        IVX_HIP(dc.get(n_items * sizeof(unsigned long long)));
+        IVX_HIP(hipMemsetAsync(dc.p, 0, n_items * sizeof(unsigned long long), st));
+        for (int b = 0; b < n_items; ++b)
+            IVX_HIP(launch_count_live(src.flags + p->offsets[b], nb[b], dc.as<unsigned long long>() + b, st));
+        std::vector<unsigned long long> h(n_items);
+        IVX_HIP(hipMemcpyAsync(h.data(), dc.p, n_items * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        IVX_HIP(hipStreamSynchronize(st));
+        for (int b = 0; b < n_items; ++b) live[b] = (int64_t)h[b];
+    } else {
+        for (int b = 0; b < n_items; ++b)
+            live[b] = (int64_t)std::count(src.flags + p->offsets[b], src.flags + p->offsets[b + 1], (uint8_t)0);
+    }
+    p->block_live.assign(n_items + 1, 0);
+    for (int b = 0; b < n_items; ++b) p->block_live[b + 1] = p->block_live[b] + live[b];
+    p->m_live = p->block_live[n_items];
+    ivx_status s;
+    const size_t L = (size_t)std::max<int64_t>(p->m_live, 1);
+    if ((s = dalloc(p, &p->d_crd, L)) != IVX_OK || (s = dalloc(p, &p->d_vis, L)) != IVX_OK ||
+        (s = dalloc(p, &p->d_wgt, L)) != IVX_OK || (s = dalloc(p, &p->d_perm, L)) != IVX_OK)
+        return s;
+    // ---- temporaries
+    const int end_bit = key_bits(ntiles);
+    size_t sort_bytes = 0;
+    IVX_HIP(sort_keys(nullptr, sort_bytes, nullptr, nullptr, (int)std::max<int64_t>(maxn, 1), end_bit, st));
+    TmpBuf keys, keys2, temp, counts, bad, s_uv, s_vis, s_w, s_fl;
+    IVX_HIP(keys.get(maxn * sizeof(uint64_t)));
+    IVX_HIP(keys2.get(maxn * sizeof(uint64_t)));
+    IVX_HIP(temp.get(sort_bytes));
+    IVX_HIP(counts.get((size_t)n_items * ntiles * sizeof(int32_t)));
+    IVX_HIP(bad.get(2 * sizeof(unsigned long long)));
+    if (!uv_dev) IVX_HIP(s_uv.get(2 * maxuv * sizeof(real)));
+    if (!w_dev) IVX_HIP(s_w.get(maxuv * sizeof(real)));
+    if (!vis_dev) IVX_HIP(s_vis.get(2 * maxn * sizeof(real)));
+    if (src.flags && !fl_dev) IVX_HIP(s_fl.get(maxn));
+    int32_t *tstart = nullptr;
+    if ((s = dalloc(p, &tstart, (size_t)n_items * (ntiles + 1))) != IVX_OK) return s;
+    IVX_HIP(hipMemsetAsync(counts.p, 0, (size_t)n_items * ntiles * sizeof(int32_t), st));
+    IVX_HIP(hipMemsetAsync(bad.p, 0xFF, 2 * sizeof(unsigned long long), st));
+    const BinGeom bg{p->d.pixel_rad, (double)g.nf, 0.5 * g.W, g.O, g.T, g.ntx};
+    int staged_k = -1;
+    const real *uvb = nullptr, *wb = nullptr;
+    for (int b = 0; b < n_items; ++b) {
+        if (nb[b] == 0) continue;
+        const int k = b / g.C, c = b - (b / g.C) * g.C;
+        const int64_t off = p->offsets[b];
+        double scale = 1.0;
+        if (p->shared_uv) {
+            scale = src.scale[c];
+            if (k != staged_k) {
+                const int64_t po = p->pt_off[k], pn = p->pt_off[k + 1] - p->pt_off[k];
+                if ((s = block_view(src.uv, uv_dev, 2 * po, 2 * pn, s_uv, &uvb, st)) != IVX_OK ||
+                    (s = block_view(src.w, w_dev, po, pn, s_w, &wb, st)) != IVX_OK)
+                    return s;
+                staged_k = k;
+            }
+        } else if ((s = block_view(src.uv, uv_dev, 2 * off, 2 * nb[b], s_uv, &uvb, st)) != IVX_OK ||
+                   (s = block_view(src.w, w_dev, off, nb[b], s_w, &wb, st)) != IVX_OK) {
+            return s;
+        }
+        const real *vb = nullptr;
+        const uint8_t *fb = nullptr;
+        if ((s = block_view(src.vis, vis_dev, 2 * off, 2 * nb[b], s_vis, &vb, st)) != IVX_OK) return s;
+        if (src.flags && (s = block_view(src.flags, fl_dev, off, nb[b], s_fl, &fb, st)) != IVX_OK) return s;
+        IVX_HIP(launch_bin_keys(nb[b], uvb, scale, vb, wb, fb, bg, off, keys.as<uint64_t>(),
+                                bad.as<unsigned long long>(), st));
+        size_t tb = sort_bytes;
+        IVX_HIP(sort_keys(temp.p, tb, keys.as<uint64_t>(), keys2.as<uint64_t>(), (int)nb[b], end_bit, st));
+        const int64_t L0 = p->block_live[b];
+        IVX_HIP(launch_bin_emit(live[b], keys2.as<uint64_t>(), uvb, scale, vb, wb, bg, p->d_crd + L0, p->d_vis + L0,
+                                p->d_wgt + L0, p->d_perm + L0, counts.as<int32_t>() + (size_t)b * ntiles, st));
+    }
+    unsigned long long hb[2];
+    IVX_HIP(hipMemcpyAsync(hb, bad.p, sizeof(hb), hipMemcpyDeviceToHost, st));
+    IVX_HIP(hipStreamSynchronize(st));
+    if (hb[0] != ~0ull || hb[1] != ~0ull) {
+        if (hb[0] < hb[1]) return fail(IVX_ENONFINITE, "visibility " + std::to_string(hb[0]) + " is not finite");
+        return fail(IVX_EINVAL, "negative weight at visibility " + std::to_string(hb[1]));
+    }
+    return store_counts(p, counts.as<int32_t>(), ntiles, tstart, st);
+}
+
+// Re-sort every block's records for the current tile edge (after a tile change).
+ivx_status rebin(ivx_plan *p, hipStream_t st) {
+    const Geom &g = p->g;
+    const int n_items = g.C * g.P;
+    const int ntiles = g.nty * g.ntx;
+    int64_t maxn = 0;
+    for (int b = 0; b < n_items; ++b) maxn = std::max(maxn, p->block_live[b + 1] - p->block_live[b]);
+    const int end_bit = key_bits(ntiles);
+    size_t sort_bytes = 0;
+    IVX_HIP(sort_pairs(nullptr, sort_bytes, nullptr, nullptr, nullptr, nullptr, (int)std::max<int64_t>(maxn, 1),
+                       end_bit, st));
+    TmpBuf k1, k2, v1, v2, foot, temp, counts, sc, sv, sw, sp;
+    if (k1.get(maxn * sizeof(uint64_t)) != hipSuccess || k2.get(maxn * sizeof(uint64_t)) != hipSuccess ||
+        v1.get(maxn * sizeof(uint32_t)) != hipSuccess || v2.get(maxn * sizeof(uint32_t)) != hipSuccess ||
+        foot.get(maxn * sizeof(int2)) != hipSuccess || temp.get(sort_bytes) != hipSuccess ||
+        counts.get((size_t)n_items * ntiles * sizeof(int32_t)) != hipSuccess ||
+        sc.get(maxn * sizeof(VisCoord)) != hipSuccess || sv.get(maxn * sizeof(cpx)) != hipSuccess ||
+        sw.get(maxn * sizeof(real)) != hipSuccess || sp.get(maxn * sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(IVX_ENOMEM, "device memory for re-binning");
+    }
+    // every allocation happens before the first record moves: a failure leaves the plan as it was
+    int32_t *tstart = nullptr;
+    ivx_status s;
+    if ((s = dalloc(p, &tstart, (size_t)n_items * (ntiles + 1))) != IVX_OK) return s;
+    IVX_HIP(hipMemsetAsync(counts.p, 0, (size_t)n_items * ntiles * sizeof(int32_t), st));
+    for (int b = 0; b < n_items; ++b) {
+        const int64_t L0 = p->block_live[b], n = p->block_live[b + 1] - L0;
+        if (n == 0) continue;
+        IVX_HIP(launch_rekey(n, p->d_crd + L0, p->d_perm + L0, p->d_tstart + (size_t)b * (p->bin_ntiles + 1),
+                             p->bin_ntiles, p->bin_ntx, p->bin_T, g.ntx, g.T, k1.as<uint64_t>(), v1.as<uint32_t>(),
+                             foot.as<int2>(), st));
+        size_t tb = sort_bytes;
+        IVX_HIP(sort_pairs(temp.p, tb, k1.as<uint64_t>(), k2.as<uint64_t>(), v1.as<uint32_t>(), v2.as<uint32_t>(),
+                           (int)n, end_bit, st));
+        IVX_HIP(launch_rebin_emit(n, k2.as<uint64_t>(), v2.as<uint32_t>(), foot.as<int2>(), p->d_crd + L0,
+                                  p->d_vis + L0, p->d_wgt + L0, p->d_perm + L0, g.ntx, g.T, sc.as<VisCoord>(),
+                                  sv.as<cpx>(), sw.as<real>(), sp.as<int32_t>(),
+                                  counts.as<int32_t>() + (size_t)b * ntiles, st));
+        IVX_HIP(hipMemcpyAsync(p->d_crd + L0, sc.p, n * sizeof(VisCoord), hipMemcpyDeviceToDevice, st));
+        IVX_HIP(hipMemcpyAsync(p->d_vis + L0, sv.p, n * sizeof(cpx), hipMemcpyDeviceToDevice, st));
+        IVX_HIP(hipMemcpyAsync(p->d_wgt + L0, sw.p, n * sizeof(real), hipMemcpyDeviceToDevice, st));
+        IVX_HIP(hipMemcpyAsync(p->d_perm + L0, sp.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    }
+    return store_counts(p, counts.as<int32_t>(), ntiles, tstart, st);
+}
+
+// Work list (heavy-first), slot map and the tile-dependent buffers, from the record
+// counts per (block, tile).
+ivx_status build_work(ivx_plan *p, hipStream_t st) {
+    Geom &g = p->g;
+    const int n_items = g.C * g.P;
+    const int ntiles = p->bin_ntiles;
     const int chunk_max = p->chunk_max;
-    std::vector<VisCoord> crd(L > 0 ? L : 1);
-    std::vector<cpx> vis(L > 0 ? L : 1);
-    std::vector<real> wgt(L > 0 ? L : 1);
-    std::vector<int64_t> perm(L > 0 ? L : 1);
     std::vector<int32_t> tslot((size_t)n_items * (ntiles + 1), 0);
     std::vector<WorkItem> work;
-    std::vector<int32_t> key;
-    std::vector<int64_t> cnt(ntiles + 1);
-    int slot = 0;
+    int64_t slot = 0;
     for (int it = 0; it < n_items; ++it) {
-        const int64_t b0 = p->block_live[it], b1 = p->block_live[it + 1];
-        const int64_t n = b1 - b0;
-        key.resize(n);
-        std::fill(cnt.begin(), cnt.end(), 0);
-        for (int64_t i = 0; i < n; ++i) {
-            const HostVis &h = p->hv[b0 + i];
-            const int ty = h.er0 / g.T, tx = h.ec0 / g.T;
-            key[i] = ty * g.ntx + tx;
-            cnt[key[i] + 1]++;
-        }
-        for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
-        std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
-        for (int64_t i = 0; i < n; ++i) {
-            const HostVis &h = p->hv[b0 + i];
-            const int64_t o = b0 + pos[key[i]]++;
-            const int ty = key[i] / g.ntx, tx = key[i] - (key[i] / g.ntx) * g.ntx;
-            const uint32_t ix = (uint32_t)(h.ec0 - tx * g.T), iy = (uint32_t)(h.er0 - ty * g.T);
-#ifdef IVX_REAL_DOUBLE
-            crd[o] = VisCoord{ix, iy, h.fx, h.fy};
-#else
-            auto q24 = [](double f) -> uint32_t {
-                double s = std::floor(f * 16777216.0 + 0.5);
-                if (s > 16777215.0) s = 16777215.0;
-                if (s < 0.0) s = 0.0;
-                return (uint32_t)s;
-            };
-            crd[o] = VisCoord{(ix << 24) | q24(h.fx), (iy << 24) | q24(h.fy)};
-#endif
-            vis[o] = cpx{h.yr, h.yi};
-            wgt[o] = h.w;
-            perm[o] = h.src;
-        }
+        const int64_t b0 = p->block_live[it];
+        const int32_t *cnt = &p->tcount[(size_t)it * ntiles];
         int32_t *ts = &tslot[(size_t)it * (ntiles + 1)];
+        int64_t c0 = 0;
         for (int t = 0; t < ntiles; ++t) {
-            ts[t] = slot;
-            const int64_t c0 = cnt[t], c1 = cnt[t + 1];
+            ts[t] = (int32_t)slot;
+            const int64_t c1 = c0 + cnt[t];
             for (int64_t s0 = c0; s0 < c1; s0 += chunk_max) {
                 const int64_t c = std::min<int64_t>(chunk_max, c1 - s0);
                 WorkItem w;
@@ -349,52 +549,51 @@ ivx_status build_bins(ivx_plan *p, hipStream_t st) {
                 w.tx = t - (t / g.ntx) * g.ntx;
                 w.count = (int32_t)c;
                 w.begin = b0 + s0;
-                w.slot = slot++;
+                w.slot = (int32_t)slot++;
                 w.pad = 0;
                 work.push_back(w);
             }
+            c0 = c1;
         }
-        ts[ntiles] = slot;
+        ts[ntiles] = (int32_t)slot;
+        if (slot > INT32_MAX) return fail(IVX_EINVAL, "too many gridding work items: use a larger tile or chunk");
     }
     // heaviest first: blocks are dispatched roughly in index order
     std::stable_sort(work.begin(), work.end(),
                      [](const WorkItem &a, const WorkItem &b) { return a.count > b.count; });
     p->n_work = (int)work.size();
-    p->n_slots = slot;
+    p->n_slots = (int)slot;
     drop_graph(p); // kernel arguments change with the tiling
     IVX_HIP(prepare_grid(g, p->nwave, p->lanes * 10 + p->vpi));
-
-    for (void *old : {(void *)p->d_crd, (void *)p->d_vis, (void *)p->d_wgt, (void *)p->d_perm,
-                      (void *)p->d_work, (void *)p->d_tslot, (void *)p->d_ext, (void *)p->d_slots,
-                      (void *)p->d_jpart})
+    for (void *old : {(void *)p->d_work, (void *)p->d_tslot, (void *)p->d_ext, (void *)p->d_slots, (void *)p->d_jpart})
         if (old) free_one(p, old);
-    p->d_crd = nullptr;
-    p->d_vis = nullptr;
-    p->d_wgt = nullptr;
-    p->d_perm = nullptr;
     p->d_work = nullptr;
     p->d_tslot = nullptr;
     p->d_ext = p->d_slots = nullptr;
     p->d_jpart = nullptr;
     ivx_status s;
-    if ((s = dalloc(p, &p->d_crd, crd.size())) != IVX_OK) return s;
-    if ((s = dalloc(p, &p->d_vis, vis.size())) != IVX_OK) return s;
-    if ((s = dalloc(p, &p->d_wgt, wgt.size())) != IVX_OK) return s;
-    if ((s = dalloc(p, &p->d_perm, perm.size())) != IVX_OK) return s;
-    if ((s = dalloc(p, &p->d_work, work.size())) != IVX_OK) return s;
+    if ((s = dalloc(p, &p->d_work, std::max<size_t>(work.size(), 1))) != IVX_OK) return s;
     if ((s = dalloc(p, &p->d_tslot, tslot.size())) != IVX_OK) return s;
     if ((s = dalloc(p, &p->d_ext, (size_t)n_items * g.ext_stride)) != IVX_OK) return s;
-    if ((s = dalloc(p, &p->d_slots, (size_t)std::max(1, slot) * g.win_stride)) != IVX_OK) return s;
+    if ((s = dalloc(p, &p->d_slots, (size_t)std::max<int64_t>(1, slot) * g.win_stride)) != IVX_OK) return s;
     if ((s = dalloc(p, &p->d_jpart, work.size() + final_scratch((int)work.size()) + 1)) != IVX_OK) return s;
-    IVX_HIP(hipMemcpyAsync(p->d_crd, crd.data(), crd.size() * sizeof(VisCoord), hipMemcpyHostToDevice, st));
-    IVX_HIP(hipMemcpyAsync(p->d_vis, vis.data(), vis.size() * sizeof(cpx), hipMemcpyHostToDevice, st));
-    IVX_HIP(hipMemcpyAsync(p->d_wgt, wgt.data(), wgt.size() * sizeof(real), hipMemcpyHostToDevice, st));
-    IVX_HIP(hipMemcpyAsync(p->d_perm, perm.data(), perm.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
     if (!work.empty())
         IVX_HIP(hipMemcpyAsync(p->d_work, work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
     IVX_HIP(hipMemcpyAsync(p->d_tslot, tslot.data(), tslot.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     IVX_HIP(hipStreamSynchronize(st)); // host vectors die at return
     return IVX_OK;
+}
+
+// Tile-dependent device data for the current blocking: records re-sorted when the tile
+// edge changed, then the work list.
+// A failure leaves the plan without a work list: it needs a successful rebuild (another
+// blocking) or set_data before the next evaluation.
+ivx_status build_bins(ivx_plan *p, hipStream_t st) {
+    ivx_status s = IVX_OK;
+    if (p->bin_T != p->g.T) s = rebin(p, st);
+    if (s == IVX_OK) s = build_work(p, st);
+    p->has_data = s == IVX_OK;
+    return s;
 }
 
 ivx_status check_plan(const ivx_plan *p) {
@@ -464,7 +663,7 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
     }
     {
         StageTimer t(p, st, IVX_STAGE_GRID);
-        IVX_HIP(launch_grid(MODE_OBJ, g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
+        IVX_HIP(launch_grid(MODE_OBJ, g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff, p->d_ext,
                             p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, st));
     }
     {
@@ -506,6 +705,11 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
 } // namespace
 
 // ====================================================================== C ABI
+
+namespace {
+ivx_status set_data_impl(ivx_plan *p, const VisSource &src, bool shared, const ivx_real *beams,
+                         const ivx_real *interp, const ivx_real *sd_map, void *stream);
+} // namespace
 
 namespace ivx {
 // Number of sky variables of a plan (n_chan * n_sky^2), for the bounded solver.
@@ -650,7 +854,7 @@ ivx_status ivx_set_blocking(ivx_plan *p, int32_t tile, int32_t waves, int32_t ch
     p->lanes = lanes;
     p->vpi = vpi;
     set_tile(p, tile);
-    if (p->has_data) {
+    if (p->bin_T > 0) { // records exist (set_data succeeded)
         ivx_status s = build_bins(p, (hipStream_t)stream);
         if (s != IVX_OK) return s;
     }
@@ -711,8 +915,48 @@ ivx_status ivx_plan_set_data(ivx_plan *p, const ivx_real *uv, const ivx_real *vi
                              const ivx_real *sd_map, void *stream) {
     g_last_error.clear();
     if (!p) return fail(IVX_EINVAL, "plan is NULL");
+    VisSource src;
+    src.uv = uv;
+    src.vis = vis;
+    src.w = weight;
+    src.flags = flags;
+    return set_data_impl(p, src, false, beams, interp, sd_map, stream);
+}
+
+ivx_status ivx_plan_set_data_shared(ivx_plan *p, const ivx_real *uv, const ivx_real *weight, const double *uv_scale,
+                                    const ivx_real *vis, const uint8_t *flags, const ivx_real *beams,
+                                    const ivx_real *interp, const ivx_real *sd_map, void *stream) {
+    g_last_error.clear();
+    if (!p) return fail(IVX_EINVAL, "plan is NULL");
+    if (!uv_scale) return fail(IVX_EINVAL, "uv_scale is required");
+    for (int c = 0; c < p->g.C; ++c)
+        if (!std::isfinite(uv_scale[c]) || !(uv_scale[c] > 0.0))
+            return fail(IVX_EINVAL, "uv_scale must be finite and positive");
+    for (int k = 0; k < p->g.P; ++k) {
+        const int64_t m0 = p->offsets[(size_t)k * p->g.C + 1] - p->offsets[(size_t)k * p->g.C];
+        for (int c = 1; c < p->g.C; ++c) {
+            const int64_t b = (int64_t)k * p->g.C + c;
+            if (p->offsets[b + 1] - p->offsets[b] != m0)
+                return fail(IVX_EINVAL, "shared uv needs the same visibility count in every channel of a pointing");
+        }
+    }
+    VisSource src;
+    src.uv = uv;
+    src.vis = vis;
+    src.w = weight;
+    src.flags = flags;
+    src.scale = uv_scale;
+    return set_data_impl(p, src, true, beams, interp, sd_map, stream);
+}
+
+} // extern "C"
+
+namespace {
+
+ivx_status set_data_impl(ivx_plan *p, const VisSource &src, bool shared, const ivx_real *beams,
+                         const ivx_real *interp, const ivx_real *sd_map, void *stream) {
     const int64_t M = p->m_total;
-    if (M > 0 && (!uv || !vis || !weight)) return fail(IVX_EINVAL, "uv, vis and weight are required");
+    if (M > 0 && (!src.uv || !src.vis || !src.w)) return fail(IVX_EINVAL, "uv, vis and weight are required");
     if (!beams || !interp) return fail(IVX_EINVAL, "beams and interp are required");
     if (sd_active(p) && !sd_map) return fail(IVX_EINVAL, "sd_map is required when lambda_s > 0 and sd_n > 0");
     hipStream_t st = (hipStream_t)stream;
@@ -720,23 +964,8 @@ ivx_status ivx_plan_set_data(ivx_plan *p, const ivx_real *uv, const ivx_real *vi
     const Geom &g = p->g;
     const int n_items = g.C * g.P;
     const int64_t nk2 = (int64_t)g.nk * g.nk;
-    // ---- host copies of the caller's arrays
-    std::vector<real> h_uv, h_vis, h_w, h_beams(g.P * nk2), h_interp(g.P * nk2 * 2);
-    std::vector<uint8_t> h_flags;
-    try {
-        h_uv.resize(2 * M);
-        h_vis.resize(2 * M);
-        h_w.resize(M);
-        if (flags) h_flags.resize(M);
-    } catch (const std::bad_alloc &) {
-        return fail(IVX_ENOMEM, "host staging allocation failed");
-    }
-    if (M > 0) {
-        IVX_HIP(hipMemcpy(h_uv.data(), uv, 2 * M * sizeof(real), hipMemcpyDefault));
-        IVX_HIP(hipMemcpy(h_vis.data(), vis, 2 * M * sizeof(real), hipMemcpyDefault));
-        IVX_HIP(hipMemcpy(h_w.data(), weight, M * sizeof(real), hipMemcpyDefault));
-        if (flags) IVX_HIP(hipMemcpy(h_flags.data(), flags, M, hipMemcpyDefault));
-    }
+    // ---- host copies of the small per-pointing and single-dish arrays
+    std::vector<real> h_beams(g.P * nk2), h_interp(g.P * nk2 * 2);
     IVX_HIP(hipMemcpy(h_beams.data(), beams, h_beams.size() * sizeof(real), hipMemcpyDefault));
     IVX_HIP(hipMemcpy(h_interp.data(), interp, h_interp.size() * sizeof(real), hipMemcpyDefault));
     std::vector<real> h_sd;
@@ -748,55 +977,11 @@ ivx_status ivx_plan_set_data(ivx_plan *p, const ivx_real *uv, const ivx_real *vi
     }
     for (size_t i = 0; i < h_beams.size(); ++i)
         if (!std::isfinite((double)h_beams[i])) return fail(IVX_ENONFINITE, "beams hold a non-finite value");
-    // ---- live visibilities: finite check, fine-grid coordinates, Hermitian fold
-    std::vector<HostVis> hv;
-    std::vector<int64_t> block_live(n_items + 1, 0);
-    const double delta = p->d.pixel_rad;
-    const double nf = g.nf, hw = 0.5 * g.W;
-    try {
-        hv.reserve(M);
-    } catch (const std::bad_alloc &) {
-        return fail(IVX_ENOMEM, "host staging allocation failed");
-    }
-    for (int it = 0; it < n_items; ++it) {
-        for (int64_t j = p->offsets[it]; j < p->offsets[it + 1]; ++j) {
-            if (flags && h_flags[j]) continue;
-            const double u = h_uv[2 * j], v = h_uv[2 * j + 1];
-            const double yr = h_vis[2 * j], yi = h_vis[2 * j + 1], w = h_w[j];
-            if (!std::isfinite(u) || !std::isfinite(v) || !std::isfinite(yr) || !std::isfinite(yi) ||
-                !std::isfinite(w))
-                return fail(IVX_ENONFINITE, "visibility " + std::to_string(j) + " is not finite");
-            if (w < 0.0) return fail(IVX_EINVAL, "negative weight at visibility " + std::to_string(j));
-            // fine-grid coordinate: the DFT phase only depends on frac(u delta)
-            double gxv = (u * delta - std::floor(u * delta)) * nf;
-            double gyv = (v * delta - std::floor(v * delta)) * nf;
-            if (gxv >= nf) gxv -= nf;
-            if (gyv >= nf) gyv -= nf;
-            bool fold = gxv > 0.5 * nf;
-            if (fold) {
-                gxv = nf - gxv;
-                gyv = nf - gyv;
-                if (gyv >= nf) gyv -= nf;
-            }
-            const double sx = gxv - hw, sy = gyv - hw;
-            const double flx = std::floor(sx), fly = std::floor(sy);
-            HostVis h;
-            h.ec0 = (int32_t)flx + 1 + g.O;
-            h.er0 = (int32_t)fly + 1 + g.O;
-            h.fx = sx - flx;
-            h.fy = sy - fly;
-            h.src = fold ? ~j : j;
-            h.yr = (real)yr;
-            h.yi = fold ? (real)(-yi) : (real)yi;
-            h.w = (real)w;
-            hv.push_back(h);
-        }
-        block_live[it + 1] = (int64_t)hv.size();
-    }
     free_all(p);
-    p->hv.swap(hv);
-    p->block_live.swap(block_live);
-    p->m_live = (int64_t)p->hv.size();
+    p->shared_uv = shared;
+    p->pt_off.assign(g.P + 1, 0);
+    for (int k = 0; k < g.P; ++k)
+        p->pt_off[k + 1] = p->pt_off[k] + (p->offsets[(size_t)k * g.C + 1] - p->offsets[(size_t)k * g.C]);
     ivx_status s;
     // ---- constant tables and images
     if ((s = dalloc(p, &p->d_dq, g.nk)) != IVX_OK) goto fail_free;
@@ -919,7 +1104,16 @@ ivx_status ivx_plan_set_data(ivx_plan *p, const ivx_real *uv, const ivx_real *vi
             goto fail_free;
         }
     }
-    if ((s = build_bins(p, st)) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_boff, (size_t)n_items + 1)) != IVX_OK) goto fail_free;
+    {
+        hipError_t e = hipMemcpy(p->d_boff, p->offsets.data(), ((size_t)n_items + 1) * sizeof(int64_t),
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            s = hip_fail(e, "hipMemcpy (block offsets)");
+            goto fail_free;
+        }
+    }
+    if ((s = bin_from_caller(p, src, st)) != IVX_OK || (s = build_work(p, st)) != IVX_OK) goto fail_free;
     p->has_data = true;
     return IVX_OK;
 fail_free:
@@ -931,35 +1125,56 @@ fail_free:
     return s;
 }
 
+} // namespace
+
+extern "C" {
+
 ivx_status ivx_plan_set_vis(ivx_plan *p, const ivx_real *vis, const ivx_real *weight, void *stream) {
     ivx_status s = check_plan(p);
     if (s != IVX_OK) return s;
     if (!vis && p->m_total > 0) return fail(IVX_EINVAL, "vis is required");
     hipStream_t st = (hipStream_t)stream;
-    unsigned int *bad = nullptr;
-    IVX_HIP(hipMalloc(&bad, sizeof(unsigned int)));
-    hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned int), st);
-    if (e == hipSuccess)
-        e = launch_gather_vis(p->d_perm, p->m_live, reinterpret_cast<const cpx *>(vis), weight, p->d_vis, p->d_wgt, bad, st);
+    const Geom &g = p->g;
+    const int n_items = g.C * g.P;
+    const bool vis_dev = on_device(vis), w_dev = on_device(weight);
+    int64_t maxn = 0, maxw = 0;
+    for (int b = 0; b < n_items; ++b) maxn = std::max(maxn, p->offsets[b + 1] - p->offsets[b]);
+    if (p->shared_uv)
+        for (int k = 0; k < g.P; ++k) maxw = std::max(maxw, p->pt_off[k + 1] - p->pt_off[k]);
+    else
+        maxw = maxn;
+    TmpBuf bad, s_vis, s_w;
+    IVX_HIP(bad.get(sizeof(unsigned int)));
+    if (!vis_dev) IVX_HIP(s_vis.get(2 * maxn * sizeof(real)));
+    if (weight && !w_dev) IVX_HIP(s_w.get(maxw * sizeof(real)));
+    IVX_HIP(hipMemsetAsync(bad.p, 0, sizeof(unsigned int), st));
+    int staged_k = -1;
+    const real *wb = nullptr;
+    for (int b = 0; b < n_items; ++b) {
+        const int64_t L0 = p->block_live[b], n = p->block_live[b + 1] - L0;
+        if (n == 0) continue;
+        const int k = b / g.C;
+        const int64_t off = p->offsets[b], nb = p->offsets[b + 1] - off;
+        const real *vb = nullptr;
+        if ((s = block_view(vis, vis_dev, 2 * off, 2 * nb, s_vis, &vb, st)) != IVX_OK) return s;
+        if (weight) {
+            if (p->shared_uv) {
+                if (k != staged_k) {
+                    const int64_t po = p->pt_off[k], pn = p->pt_off[k + 1] - po;
+                    if ((s = block_view(weight, w_dev, po, pn, s_w, &wb, st)) != IVX_OK) return s;
+                    staged_k = k;
+                }
+            } else if ((s = block_view(weight, w_dev, off, nb, s_w, &wb, st)) != IVX_OK) {
+                return s;
+            }
+        }
+        IVX_HIP(launch_gather_block(n, p->d_perm + L0, vb, weight ? wb : nullptr, p->d_vis + L0, p->d_wgt + L0,
+                                    bad.as<unsigned int>(), st));
+    }
     unsigned int hb = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(unsigned int), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(bad);
-    if (e != hipSuccess) return hip_fail(e, "ivx_plan_set_vis");
+    IVX_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+    IVX_HIP(hipStreamSynchronize(st));
     if (hb) return fail(IVX_ENONFINITE, "ivx_plan_set_vis: non-finite value or negative weight");
-    // keep the host copy used by re-binning in step with the device data
-    std::vector<real> hv(2 * p->m_total), hw;
-    IVX_HIP(hipMemcpy(hv.data(), vis, hv.size() * sizeof(real), hipMemcpyDefault));
-    if (weight) {
-        hw.resize(p->m_total);
-        IVX_HIP(hipMemcpy(hw.data(), weight, hw.size() * sizeof(real), hipMemcpyDefault));
-    }
-    for (HostVis &h : p->hv) {
-        const int64_t j = h.src < 0 ? ~h.src : h.src;
-        h.yr = hv[2 * j];
-        h.yi = h.src < 0 ? -hv[2 * j + 1] : hv[2 * j + 1];
-        if (weight) h.w = hw[j];
-    }
     return IVX_OK;
 }
 
@@ -1022,7 +1237,7 @@ ivx_status ivx_forward(ivx_plan *p, const ivx_real *sky, ivx_real *model_vis, vo
     hipStream_t st = (hipStream_t)stream;
     if ((s = run_forward_half(p, sky, st)) != IVX_OK) return s;
     IVX_HIP(launch_zero(model_vis, p->m_total * 2 * (int64_t)sizeof(real), st));
-    IVX_HIP(launch_grid(MODE_FWD, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
+    IVX_HIP(launch_grid(MODE_FWD, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff, p->d_ext,
                         p->d_slots, p->d_jpart, nullptr, reinterpret_cast<cpx *>(model_vis), p->nwave, p->lanes * 10 + p->vpi, st));
     return IVX_OK;
 }
@@ -1032,7 +1247,7 @@ ivx_status ivx_adjoint(ivx_plan *p, const ivx_real *vis, ivx_real *image, void *
     if (s != IVX_OK) return s;
     if (!image || (!vis && p->m_total > 0)) return fail(IVX_EINVAL, "vis and image are required");
     hipStream_t st = (hipStream_t)stream;
-    IVX_HIP(launch_grid(MODE_ADJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_ext,
+    IVX_HIP(launch_grid(MODE_ADJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff, p->d_ext,
                         p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave, p->lanes * 10 + p->vpi, st));
     if ((s = run_adjoint_half(p, st)) != IVX_OK) return s;
     IVX_HIP(launch_sky(p->g, image, p->d_gp, p->d_cptr, p->d_cent, real(0), real(0), nullptr, nullptr, 0, 0, 1, 0,
@@ -1074,7 +1289,11 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
         p->vpi = c.vpi;
         p->chunk_max = c.chunk;
         set_tile(p, c.T);
-        if ((s = build_bins(p, st)) != IVX_OK) break;
+        if ((s = build_bins(p, st)) == IVX_ENOMEM) {
+            s = IVX_OK; // this blocking does not fit next to the data: skip it
+            continue;
+        }
+        if (s != IVX_OK) break;
         if ((s = run_forward_half(p, sky, st)) != IVX_OK) break;
         float ms = 0.f, tot = 0.f;
         const int reps = 5;
@@ -1082,7 +1301,7 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
             // the fold overwrites the forward grid: rebuild it (untimed) for every repetition
             if (r > 0 && (s = run_forward_half(p, sky, st)) != IVX_OK) break;
             IVX_HIP(hipEventRecord(e0, st));
-            IVX_HIP(launch_grid(MODE_OBJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm,
+            IVX_HIP(launch_grid(MODE_OBJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff,
                                 p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, st));
             IVX_HIP(launch_fold(p->g, p->d_tslot, p->d_slots, p->d_ext, st));
             IVX_HIP(hipEventRecord(e1, st));

@@ -78,9 +78,11 @@ hipError_t launch_image_rows(const Geom &g, const real *sky, const real *beams,
                              const real *interp, const real *fscale, const real *dq,
                              const cpx *tw, cpx *R, hipStream_t st);
 hipError_t launch_col_fwd(const Geom &g, const cpx *R, const cpx *tw, cpx *ext, hipStream_t st);
+// perm: caller index of each sorted record within its block (bit-inverted when folded);
+// boff: caller offset of every block (forward / adjoint modes only)
 hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work,
                        const VisCoord *crd, const cpx *vis, const real *wgt,
-                       const int64_t *perm, const cpx *ext, cpx *slots, double *jpart,
+                       const int32_t *perm, const int64_t *boff, const cpx *ext, cpx *slots, double *jpart,
                        const cpx *caller_in, cpx *caller_out, int nwave, int variant,
                        hipStream_t st);
 // adjoint extended grid: the windows summed into `ext` (the forward extended grid, which
@@ -110,8 +112,41 @@ hipError_t launch_final(const double *jpart, int nj, double *scratch, const doub
                         const double *kpart, int nkp, double lambda_r, double lambda_s, double *terms,
                         double *terms_user, hipStream_t st);
 hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st);
-hipError_t launch_gather_vis(const int64_t *perm, int64_t n, const cpx *vis, const real *wgt, cpx *svis,
-                             real *swgt, unsigned int *bad, hipStream_t st);
+
+// ---------------------------------------------------------------- plan-time binning
+// Fine-grid geometry of the footprint computation (pixel size, fine grid edge, half kernel
+// width, extended-grid offset) and the tiling the records are sorted for.
+struct BinGeom {
+    double delta, nf, hw;
+    int O, T, ntx;
+};
+hipError_t launch_count_live(const uint8_t *flags, int64_t n, unsigned long long *out, hipStream_t st);
+// keys[j] = (tile << 32) | j of sample j of a block (all ones when flagged or bad); uv is
+// multiplied by `scale`; bad[0] / bad[1]: smallest gbase + j that is non-finite / has a
+// negative weight (atomicMin, start from all ones)
+hipError_t launch_bin_keys(int64_t n, const real *uv, double scale, const real *vis, const real *w,
+                           const uint8_t *flags, const BinGeom &b, int64_t gbase, uint64_t *keys,
+                           unsigned long long *bad, hipStream_t st);
+// records of the first n sorted keys; counts[tile] += 1 per record
+hipError_t launch_bin_emit(int64_t n, const uint64_t *keys, const real *uv, double scale, const real *vis,
+                           const real *w, const BinGeom &b, VisCoord *crd, cpx *svis, real *swgt, int32_t *perm,
+                           int32_t *counts, hipStream_t st);
+// keys of a block's records for tile edge T_new (tstart: the block's old tile prefix)
+hipError_t launch_rekey(int64_t n, const VisCoord *crd, const int32_t *perm, const int32_t *tstart, int ntiles_old,
+                        int ntx_old, int T_old, int ntx_new, int T_new, uint64_t *keys, uint32_t *vals, int2 *foot,
+                        hipStream_t st);
+hipError_t launch_rebin_emit(int64_t n, const uint64_t *keys, const uint32_t *vals, const int2 *foot,
+                             const VisCoord *crd, const cpx *vis, const real *wgt, const int32_t *perm, int ntx,
+                             int T, VisCoord *crd_o, cpx *vis_o, real *wgt_o, int32_t *perm_o, int32_t *counts,
+                             hipStream_t st);
+// sorted data of one block from the caller's block arrays (w may be NULL: weights kept)
+hipError_t launch_gather_block(int64_t n, const int32_t *perm, const real *vis, const real *w, cpx *svis,
+                               real *swgt, unsigned int *bad, hipStream_t st);
+// hipCUB radix sorts over bits [0, end_bit); temp == NULL queries temp_bytes
+hipError_t sort_keys(void *temp, size_t &temp_bytes, const uint64_t *in, uint64_t *out, int n, int end_bit,
+                     hipStream_t st);
+hipError_t sort_pairs(void *temp, size_t &temp_bytes, const uint64_t *kin, uint64_t *kout, const uint32_t *vin,
+                      uint32_t *vout, int n, int end_bit, hipStream_t st);
 
 // Raise the dynamic-LDS limit of the gridding kernels for this geometry (call before any
 // stream capture).

@@ -292,7 +292,8 @@ struct GridArgs {
     const VisCoord *crd;
     const cpx *vis;
     const real *wgt;
-    const int64_t *perm;
+    const int32_t *perm;
+    const int64_t *boff;
     const cpx *ext;
     cpx *slots;
     double *jpart;
@@ -427,7 +428,11 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     const VisCoord *crd = a.crd + wi.begin;
     const cpx *vis = a.vis + wi.begin;
     const real *wgt = a.wgt + wi.begin;
-    const int64_t *perm = a.perm + wi.begin;
+    const int32_t *perm = a.perm + wi.begin;
+    cpx *caller_out = nullptr;
+    const cpx *caller_in = nullptr;
+    if (MODE == MODE_FWD) caller_out = a.caller_out + a.boff[wi.item];
+    if (MODE == MODE_ADJ) caller_in = a.caller_in + a.boff[wi.item];
     // per-lane record index as an unsigned 32-bit byte offset from the block's (uniform)
     // bases, so the loads take the scalar-base + 32-bit vector-offset form
     auto rec = [&](int vv) -> unsigned { return (unsigned)(vv < v1 ? vv : 0); };
@@ -441,7 +446,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         VisCoord c;
         cpx y;
         real w;
-        int64_t p;
+        int32_t p;
     };
     auto load = [&](Rec (&r)[VPI], int it) {
 #pragma unroll
@@ -530,8 +535,8 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
 #pragma unroll
             for (int u = 0; u < VPI; ++u) {
                 if (valid[u] && t == 0) {
-                    if (cur[u].p < 0) a.caller_out[~cur[u].p] = cpx{ar[u], -ai[u]};
-                    else a.caller_out[cur[u].p] = cpx{ar[u], ai[u]};
+                    if (cur[u].p < 0) caller_out[~cur[u].p] = cpx{ar[u], -ai[u]};
+                    else caller_out[cur[u].p] = cpx{ar[u], ai[u]};
                 }
             }
             return;
@@ -546,7 +551,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
                 cre[u] = ww * rr;
                 cim[u] = ww * ri;
             } else {
-                cpx y = a.caller_in[cur[u].p < 0 ? ~cur[u].p : cur[u].p];
+                cpx y = caller_in[cur[u].p < 0 ? ~cur[u].p : cur[u].p];
                 if (cur[u].p < 0) y.im = -y.im;
                 cre[u] = cur[u].w * y.re * wxj[u];
                 cim[u] = cur[u].w * y.im * wxj[u];
@@ -972,28 +977,6 @@ __global__ __launch_bounds__(NT_FINAL) void k_final(const double *__restrict__ j
     }
 }
 
-// Data update in sorted order: sorted[s] = caller[perm[s]] (conjugated when folded);
-// bad[0] is set when a value is not finite or a weight negative.
-__global__ __launch_bounds__(NT) void k_gather_vis(const int64_t *__restrict__ perm, int64_t n,
-                                                   const cpx *__restrict__ vis, const real *__restrict__ wgt,
-                                                   cpx *__restrict__ svis, real *__restrict__ swgt,
-                                                   unsigned int *__restrict__ bad) {
-    const int64_t s = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (s >= n) return;
-    const int64_t p = perm[s];
-    const int64_t src = p < 0 ? ~p : p;
-    cpx y = vis[src];
-    if (p < 0) y.im = -y.im;
-    bool ok = isfinite(y.re) && isfinite(y.im);
-    svis[s] = y;
-    if (wgt) {
-        const real w = wgt[src];
-        ok = ok && isfinite(w) && w >= real(0);
-        swgt[s] = w;
-    }
-    if (!ok) bad[0] = 1u;
-}
-
 __global__ __launch_bounds__(NT) void k_zero(uint32_t *p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) p[i] = 0u;
 }
@@ -1148,11 +1131,12 @@ hipError_t prepare_grid(const Geom &g, int nwave, int variant) {
 }
 
 hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
-                       const cpx *vis, const real *wgt, const int64_t *perm, const cpx *ext, cpx *slots,
-                       double *jpart, const cpx *caller_in, cpx *caller_out, int nwave, int variant, hipStream_t st) {
+                       const cpx *vis, const real *wgt, const int32_t *perm, const int64_t *boff, const cpx *ext,
+                       cpx *slots, double *jpart, const cpx *caller_in, cpx *caller_out, int nwave, int variant,
+                       hipStream_t st) {
     if (n_work <= 0) return hipSuccess;
     if (nwave < 1 || nwave > NT / 64) return hipErrorInvalidValue;
-    GridArgs a{g, work, crd, vis, wgt, perm, ext, slots, jpart, caller_in, caller_out, nwave};
+    GridArgs a{g, work, crd, vis, wgt, perm, boff, ext, slots, jpart, caller_in, caller_out, nwave};
     return dispatch(false, variant, mode, a, n_work, st);
 }
 
@@ -1206,13 +1190,6 @@ hipError_t launch_final(const double *jpart, int nj, double *scratch, const doub
         nj = nb;
     }
     k_final<<<1, NT_FINAL, 0, st>>>(jpart, nj, rpart, nr, kpart, nkp, lambda_r, lambda_s, terms, terms_user);
-    return hipGetLastError();
-}
-
-hipError_t launch_gather_vis(const int64_t *perm, int64_t n, const cpx *vis, const real *wgt, cpx *svis, real *swgt,
-                             unsigned int *bad, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    k_gather_vis<<<(unsigned)((n + NT - 1) / NT), NT, 0, st>>>(perm, n, vis, wgt, svis, swgt, bad);
     return hipGetLastError();
 }
 
