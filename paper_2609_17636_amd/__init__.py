@@ -236,6 +236,12 @@ class Plan:
         w = None if weight is None else weight.to(self.torch_dtype).contiguous()
         self._check(self.lib.ivx_plan_set_vis(self._h, _ptr(v), _ptr(w), _stream_ptr(stream)))
 
+    def set_cube_data(self, p, stream=None):
+        """Data of a shared-uv spectral cube (synth.CubeProblem layout)."""
+        sd = p.sd_map if (p.sd_n > 0 and p.lambda_s != 0.0) else None
+        self.set_data_shared(p.uv, p.weight, p.uv_scale, p.vis, p.beams, p.interp, flags=p.flags, sd_map=sd,
+                             stream=stream)
+
     def set_problem_data(self, p, stream=None):
         sd = p.sd_map if (p.sd_n > 0 and p.lambda_s != 0.0) else None
         self.set_data(p.uv, p.vis, p.weight, p.beams, p.interp, flags=p.flags, sd_map=sd, stream=stream)

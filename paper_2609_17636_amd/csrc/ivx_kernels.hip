@@ -300,7 +300,12 @@ struct GridArgs {
     const cpx *caller_in;
     cpx *caller_out;
     int nwave;
+    int n_work;
 };
+
+// Work items per row of the gridding launch: the dispatch packet counts work-items of one
+// grid dimension in 32 bits, so long work lists (spectral cubes) wrap into blockIdx.y.
+constexpr unsigned GRID_ROW = 1u << 22;
 
 // ---- cross-lane moves inside a 16-lane DPP row (VALU, no LDS traffic)
 // (mov_dpp with bound_ctrl: lanes without a source read 0, and no old value has to be
@@ -386,7 +391,9 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     const int ngroups = nwave * GPW;
     cpx *Fw = reinterpret_cast<cpx *>(smem_raw);
     cpx *Hw = Fw + (MODE == MODE_ADJ ? 0 : wsz);
-    const WorkItem wi = a.work[blockIdx.x];
+    const int64_t wid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (wid >= a.n_work) return; // tail of the last row: the whole block leaves together
+    const WorkItem wi = a.work[wid];
     const int tid = threadIdx.x;
     // e = cc * win + r without an integer division: (e + 1/2) / win is never within float
     // rounding of an integer for e < 2^16
@@ -613,7 +620,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         if (tid == 0) {
             double sacc = 0.0;
             for (int w = 0; w < nwave; ++w) sacc += red[w];
-            a.jpart[blockIdx.x] = sacc;
+            a.jpart[wid] = sacc;
         }
     }
 }
@@ -1065,10 +1072,12 @@ static hipError_t launch_grid_wg(int mode, const GridArgs &a, int n_work, hipStr
     const size_t wsz = (size_t)a.g.win * a.g.ldw * sizeof(cpx);
     const int threads = 64 * a.nwave;
     const int ng = (64 / G) * a.nwave;
+    const unsigned gx = (unsigned)n_work < GRID_ROW ? (unsigned)n_work : GRID_ROW;
+    const dim3 grid(gx, (unsigned)((n_work + gx - 1) / gx));
     switch (mode) {
-    case MODE_OBJ: k_grid<W, MODE_OBJ, G, VPI><<<n_work, threads, (1 + ng) * wsz, st>>>(a); break;
-    case MODE_FWD: k_grid<W, MODE_FWD, G, VPI><<<n_work, threads, wsz, st>>>(a); break;
-    default: k_grid<W, MODE_ADJ, G, VPI><<<n_work, threads, ng * wsz, st>>>(a); break;
+    case MODE_OBJ: k_grid<W, MODE_OBJ, G, VPI><<<grid, threads, (1 + ng) * wsz, st>>>(a); break;
+    case MODE_FWD: k_grid<W, MODE_FWD, G, VPI><<<grid, threads, wsz, st>>>(a); break;
+    default: k_grid<W, MODE_ADJ, G, VPI><<<grid, threads, ng * wsz, st>>>(a); break;
     }
     return hipGetLastError();
 }
@@ -1136,7 +1145,7 @@ hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work
                        hipStream_t st) {
     if (n_work <= 0) return hipSuccess;
     if (nwave < 1 || nwave > NT / 64) return hipErrorInvalidValue;
-    GridArgs a{g, work, crd, vis, wgt, perm, boff, ext, slots, jpart, caller_in, caller_out, nwave};
+    GridArgs a{g, work, crd, vis, wgt, perm, boff, ext, slots, jpart, caller_in, caller_out, nwave, n_work};
     return dispatch(false, variant, mode, a, n_work, st);
 }
 

@@ -266,6 +266,17 @@ def attach_sd(p: Problem, sd_model: np.ndarray) -> Problem:
     return p
 
 
+def attach_sd_level(p, level: float = 25.0):
+    """Single-dish map for timing runs that need no meaningful fusion residual: a constant
+    level plus 1% noise per pixel, sigma_sd = 1% of the level.  (Tests synthesise the map
+    from the sky instead; the cost of the evaluation does not depend on these values.)"""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(p.meta.get("seed", 0) + 19)))
+    shape = (p.n_chan, p.sd_n, p.sd_n)
+    p.sd_sigma = p.sd_noise_frac * level
+    p.sd_map = (level + p.sd_sigma * rng.standard_normal(shape)).astype(np.float32)
+    return p
+
+
 # ----------------------------------------------------------------------------- configs
 
 def single_pointing(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_time: int,
@@ -396,10 +407,169 @@ def config_c5_geometry(seed: int = 5001) -> Problem:
                   lambda_s=0.0, sd_n=0, max_vis_per_block=200_000)
 
 
+# ----------------------------------------------------------------------------- cubes
+
+@dataclass
+class CubeProblem:
+    """Spectral cube whose channels share each pointing's uv track and weights (the same
+    baselines observed at every frequency): channel c of pointing k sees
+    uv[pt_offsets[k]:pt_offsets[k+1]] * uv_scale[c].  Visibilities and flags are stored per
+    (pointing, channel) block, block index k * n_chan + c, every channel of pointing k
+    holding M_k samples."""
+
+    name: str
+    n_chan: int
+    n_sky: int
+    pixel_rad: float
+    n_point: int
+    n_sub: int
+    flux_scale: np.ndarray  # [C] float64
+    lambda_r: float
+    lambda_s: float
+    uv: np.ndarray  # [sum M_k, 2] float32, wavelengths at the reference frequency
+    pt_offsets: np.ndarray  # [P + 1] int64
+    uv_scale: np.ndarray  # [C] float64, nu_c / nu_ref
+    weight: np.ndarray  # [sum M_k] float32
+    vis_offsets: np.ndarray  # [P*C + 1] int64
+    flags: np.ndarray  # [M] uint8
+    beams: np.ndarray
+    interp: np.ndarray
+    x_true: Optional[np.ndarray]  # [C][N][N] float32, or None
+    vis: np.ndarray  # [M] complex64: unit-variance complex noise
+    sd_n: int = 0
+    sd_stride: int = 0
+    sd_offset: int = 0
+    sd_fwhm_rad: float = 0.0
+    sd_sigma: float = 0.0
+    sd_map: Optional[np.ndarray] = None
+    sd_noise_frac: float = 0.01
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_vis(self) -> int:
+        return int(self.vis_offsets[-1])
+
+    @property
+    def n_items(self) -> int:
+        return self.n_point * self.n_chan
+
+    def block(self, k: int, c: int) -> slice:
+        i = k * self.n_chan + c
+        return slice(int(self.vis_offsets[i]), int(self.vis_offsets[i + 1]))
+
+    def uv_of(self, k: int, c: int) -> np.ndarray:
+        """FP64 uv of block (k, c), wavelengths at the channel's frequency."""
+        s = slice(int(self.pt_offsets[k]), int(self.pt_offsets[k + 1]))
+        return self.uv[s].astype(np.float64) * self.uv_scale[c]
+
+    def weight_of(self, k: int) -> np.ndarray:
+        return self.weight[int(self.pt_offsets[k]):int(self.pt_offsets[k + 1])]
+
+    def expand(self) -> Problem:
+        """The same data as a per-block Problem (FP64 uv per block); small cubes only."""
+        uv = np.concatenate([self.uv_of(k, c) for k in range(self.n_point) for c in range(self.n_chan)])
+        w = np.concatenate([self.weight_of(k) for k in range(self.n_point) for c in range(self.n_chan)])
+        x = self.x_true if self.x_true is not None else np.zeros((self.n_chan, self.n_sky, self.n_sky))
+        return Problem(
+            name=self.name, n_chan=self.n_chan, n_sky=self.n_sky, pixel_rad=self.pixel_rad,
+            n_point=self.n_point, n_sub=self.n_sub, flux_scale=self.flux_scale, lambda_r=self.lambda_r,
+            lambda_s=self.lambda_s, uv=uv, vis_offsets=self.vis_offsets, weight=w.astype(np.float32),
+            flags=self.flags, beams=self.beams, interp=self.interp, x_true=np.asarray(x, dtype=np.float64),
+            noise=np.zeros(0), noise_rule=("abs", 1.0), sd_n=self.sd_n, sd_stride=self.sd_stride,
+            sd_offset=self.sd_offset, sd_fwhm_rad=self.sd_fwhm_rad, sd_sigma=self.sd_sigma,
+            sd_map=self.sd_map, sd_noise_frac=self.sd_noise_frac, vis=self.vis, meta=dict(self.meta))
+
+
+def channel_freqs(n_chan: int, centre_hz: float, width_hz: float) -> np.ndarray:
+    """Channel centre frequencies, symmetric about centre_hz."""
+    return centre_hz + (np.arange(n_chan) - 0.5 * (n_chan - 1)) * width_hz
+
+
+def cube(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_rows: int, n_cols: int, pitch_px: float,
+         fwhm_px: float, n_sub: int, n_time: int, n_chan: int, flag_max: float, centre_hz: float,
+         width_hz: float, ref_hz: float = 1.4e9, lambda_r: float = 1e-2, lambda_s: float = 1.0,
+         sd_n: int = 64, sd_fwhm_arcmin: float = 16.0, n_keep: Optional[int] = None, with_field: bool = True,
+         threads: Optional[int] = None) -> CubeProblem:
+    """Hexagonal mosaic observed in n_chan channels: one uv track per pointing (n_time
+    samples x 630 baselines at ref_hz, scaled by nu_c / ref_hz per channel), flag rate
+    f_kc ~ U[0, flag_max] per (pointing, channel) with Bernoulli flags, channel-correlated
+    log-normal cube (AR(1), rho = 0.9), Rayleigh-Jeans flux scale per channel.  The
+    visibilities are unit-variance complex noise; flags and noise of block b are drawn
+    from SeedSequence([seed, b]) so the blocks can be filled by parallel threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    st = _streams(seed, _STREAMS)
+    pix = pixel_arcsec * ARCSEC
+    enu = antenna_layout(st["layout"], 36, 3000.0)
+    bl = baselines(enu)
+    centres = hex_centres(n_rows, n_cols, pitch_px, n_sky)
+    P = centres.shape[0]
+    x = ar1_cube(st["field"], n_chan, n_sky).astype(np.float32) if with_field else None
+    pb = gaussian_pb(n_sub, pix, fwhm_px * pix)
+    grids, uvs, pt = [], [], [0]
+    for k in range(P):
+        g, (rak, deck) = sin_interp(n_sky, n_sub, pix, centres[k])
+        grids.append(g)
+        uvk = uv_tracks(bl, n_time, deck, ref_hz)
+        if n_keep is not None:
+            uvk = uvk[:n_keep]
+        uvs.append(uvk)
+        pt.append(pt[-1] + uvk.shape[0])
+    freqs = channel_freqs(n_chan, centre_hz, width_hz)
+    rates = st["flags"].uniform(0.0, flag_max, size=(P, n_chan))
+    mk = np.diff(np.array(pt))
+    offs = np.concatenate([[0], np.cumsum(np.repeat(mk, n_chan))]).astype(np.int64)
+    m = int(offs[-1])
+    flags = np.empty(m, dtype=np.uint8)
+    vis = np.empty(m, dtype=np.complex64)
+    vf = vis.view(np.float32)
+
+    def fill(b: int):
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, b])))
+        k, c = divmod(b, n_chan)
+        a, e = int(offs[b]), int(offs[b + 1])
+        flags[a:e] = rng.random(e - a, dtype=np.float32) < rates[k, c]
+        rng.standard_normal(2 * (e - a), dtype=np.float32, out=vf[2 * a:2 * e])
+
+    with ThreadPoolExecutor(max_workers=threads or min(16, max(1, P * n_chan))) as ex:
+        list(ex.map(fill, range(P * n_chan)))
+    sd_stride = n_sky // sd_n if sd_n else 0
+    return CubeProblem(
+        name=name, n_chan=n_chan, n_sky=n_sky, pixel_rad=pix, n_point=P, n_sub=n_sub,
+        flux_scale=np.array([rj_flux_scale(f, pix) for f in freqs]), lambda_r=lambda_r, lambda_s=lambda_s,
+        uv=np.concatenate(uvs).astype(np.float32), pt_offsets=np.array(pt, dtype=np.int64),
+        uv_scale=freqs / ref_hz, weight=np.ones(pt[-1], dtype=np.float32), vis_offsets=offs, flags=flags,
+        beams=np.repeat(pb[None], P, axis=0).astype(np.float32), interp=np.stack(grids).astype(np.float32),
+        x_true=x, vis=vis, sd_n=sd_n, sd_stride=sd_stride, sd_offset=sd_stride // 2,
+        sd_fwhm_rad=sd_fwhm_arcmin * ARCMIN,
+        meta={"seed": seed, "freqs": freqs, "ref_hz": ref_hz, "centres": centres, "flag_rates": rates},
+    )
+
+
+def config_c4(seed: int = 4001, n_chan: int = 128, n_time: int = 1800, with_field: bool = True,
+              threads: Optional[int] = None) -> CubeProblem:
+    """Spectral cube on the 36-pointing mosaic geometry: 128 channels of 2.315 kHz around
+    1402 MHz, 630 baselines x 1800 samples per pointing (1,134,000 per (pointing,
+    channel), about 5.2e9 in all), 0-5% flags per (pointing, channel), 64x64 single-dish
+    map per channel, lambda_r = 1e-2, lambda_s = 1."""
+    return cube("c4-cube-128x36x1024", seed, 1024, 30.0, 6, 6, 120.0, 120.0, 384, n_time, n_chan, 0.05,
+                1402e6, 2.315e3, with_field=with_field, threads=threads)
+
+
+def config_c4_mini(seed: int = 4101) -> CubeProblem:
+    """The cube structure at a size the oracle evaluates in seconds: 2x2 pointings on a
+    128^2 sky, 64^2 sub-images, 4 channels 25 MHz apart (uv scales 0.97-1.03, so a wrong
+    channel scale shows), 40 samples x 630 baselines per pointing, 0-30% flags."""
+    return cube("c4-mini", seed, 128, 30.0, 2, 2, 30.0, 30.0, 64, 40, 4, 0.3, 1.4e9, 25e6,
+                sd_n=16, sd_fwhm_arcmin=4.0)
+
+
 CONFIGS = {
     "c1": config_c1,
     "c2": config_c2,
     "c3": config_c3,
     "c3-mini": config_c3_mini,
     "c5": config_c5_geometry,
+    "c4": config_c4,
+    "c4-mini": config_c4_mini,
 }

@@ -110,3 +110,24 @@ def test_null_handling():
     assert lib.ivx_plan_create(None, ctypes.byref(out)) == -1
     assert out.value is None
     assert lib.ivx_objective_grad(None, None, None, None, None) == -1
+
+
+def test_shared_uv_arguments_are_checked_before_any_device_call():
+    """ivx_plan_set_data_shared needs equal counts in every channel of a pointing and
+    finite, positive channel scales; both are checked on the host."""
+    offs = np.array([0, 10, 20, 35, 50], dtype=np.int64)  # 2 pointings x 2 channels
+    plan = Plan(2, 32, 1e-4, 2, 32, offs, np.ones(2))
+    uv = np.zeros((25, 2), np.float32)
+    w = np.ones(25, np.float32)
+    vis = np.zeros((50, 2), np.float32)
+    beams = np.ones((2, 32, 32), np.float32)
+    interp = np.zeros((2, 32, 32, 2), np.float32)
+    for scale in ([1.0, 0.0], [1.0, -1.0], [1.0, float("nan")]):
+        with pytest.raises(IvxError) as e:
+            plan.set_data_shared(uv, w, scale, vis, beams, interp)
+        assert e.value.code == -1 and "uv_scale" in str(e.value)
+    bad = np.array([0, 10, 21, 35, 50], dtype=np.int64)  # pointing 0: 10 and 11 samples
+    plan2 = Plan(2, 32, 1e-4, 2, 32, bad, np.ones(2))
+    with pytest.raises(IvxError) as e:
+        plan2.set_data_shared(uv, w, [1.0, 1.01], vis, beams, interp)
+    assert e.value.code == -1 and "same visibility count" in str(e.value)

@@ -1,0 +1,251 @@
+"""Spectral-cube parity (GPU): channels that share one uv track per pointing, scaled by
+nu_c / nu_ref per channel, entered through ivx_plan_set_data_shared.
+
+Mini cube (2x2 pointings, 4 channels 25 MHz apart, 128^2 sky): objective, gradient and
+model visibilities element by element against the FP64 oracle evaluated on the same data
+written out per block.  Full cube (128 channels x 36 pointings x 1024^2, about 5.2e9
+visibilities, every (pointing, channel, tile) work item in one launch per stage): outputs
+the oracle computes one by one -- Q(0) and K(0) in closed form, the gradient at zero on
+sampled pixels of the first and last channel (direct adjoint sums over every visibility
+of every pointing that sees the pixel, exact bilinear transpose, single-dish gradient),
+and sampled model visibilities when the device holds the full forward output beside the
+plan.  Full-cube data: unit-variance complex noise (the objective at zero needs no model).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2609_17636_amd import IvxError, Plan  # noqa: E402
+
+TOL = {"f32": 1e-5, "f64": 1e-10}
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+# ------------------------------------------------------------------------------- mini
+
+@pytest.fixture(scope="module")
+def mini():
+    p = synth.config_c4_mini()
+    e = p.expand()
+    mv = oracle.model_vis(e, e.x_true)
+    live = p.flags == 0
+    sig = 0.01 * float(np.abs(mv[live]).max())
+    p.vis = (mv + sig * p.vis.astype(np.complex128)).astype(np.complex64)
+    p.weight[:] = 1.0 / sig ** 2
+    synth.attach_sd(p, oracle.sd_model(e, p.x_true))
+    return p
+
+
+def _cube_plan(p, precision="f32", **kw):
+    plan = Plan.from_problem(p, precision=precision, **kw)
+    plan.set_cube_data(p)
+    return plan
+
+
+def _eval(plan, x):
+    sky = torch.tensor(np.asarray(x), dtype=plan.torch_dtype, device="cuda")
+    terms, grad = plan.objective_grad(sky)
+    torch.cuda.synchronize()
+    return terms, grad.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_c4_mini_objective_and_gradient(mini, precision):
+    e = mini.expand()
+    plan = _cube_plan(mini, precision)
+    tol = TOL[precision]
+    rng = np.random.default_rng(41)
+    for label, x in (("zero", np.zeros(e.x_true.shape)), ("rand", rng.uniform(0, 50, size=e.x_true.shape))):
+        want_t, want_g = oracle.objective_grad(e, x)
+        terms, grad = _eval(plan, x)
+        rq = abs(terms[0] - want_t["Q_tot"]) / want_t["Q_tot"]
+        print(f"[c4-mini {precision} {label}] relQ {rq:.2e} relK "
+              f"{abs(terms[2] - want_t['K']) / max(want_t['K'], 1e-300):.2e} relG {rel(grad, want_g):.2e}",
+              flush=True)
+        assert rq <= tol
+        assert abs(terms[1] - want_t["Q"]) <= tol * want_t["Q"]
+        assert abs(terms[2] - want_t["K"]) <= tol * want_t["K"]
+        assert abs(terms[3] - want_t["R"]) <= tol * max(want_t["R"], 1e-300) + 1e-300
+        assert rel(grad, want_g) <= tol
+
+
+def test_c4_mini_forward_uses_each_channel_scale(mini):
+    e = mini.expand()
+    plan = _cube_plan(mini)
+    rng = np.random.default_rng(42)
+    x = rng.uniform(0, 50, size=e.x_true.shape)
+    v = plan.forward(torch.tensor(x, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    want = oracle.model_vis(e, x)
+    live = mini.flags == 0
+    assert rel(v[live, 0] + 1j * v[live, 1], want[live]) <= TOL["f32"]
+    assert np.all(v[~live] == 0.0)
+    # a wrong channel scale would be caught: channel 3 evaluated at channel 0's uv differs
+    k, c = 1, 3
+    s = mini.block(k, c)
+    f = oracle.beam_weighted_subimage(e, x[c], k, c)
+    wrong = oracle.dft_forward(f, mini.uv_of(k, 0), e.pixel_rad)
+    assert rel(wrong, want[s]) > 1e3 * TOL["f32"]
+
+
+def test_c4_mini_set_vis_with_per_pointing_weights(mini):
+    """New data and per-pointing weights through set_vis on a shared-uv plan."""
+    plan = _cube_plan(mini)
+    rng = np.random.default_rng(43)
+    vis = (mini.vis * np.float32(0.5) + (rng.standard_normal(mini.n_vis) * 0.1).astype(np.float32))
+    vis = vis.astype(np.complex64)
+    w = np.concatenate([np.full(int(mini.pt_offsets[k + 1] - mini.pt_offsets[k]), 1.0 + k, dtype=np.float32)
+                        * mini.weight[0] for k in range(mini.n_point)])
+    plan.set_vis(vis, w)
+    q = synth.CubeProblem(**{**mini.__dict__, "vis": vis, "weight": w})
+    e = q.expand()
+    x = rng.uniform(0, 50, size=e.x_true.shape)
+    want_t, want_g = oracle.objective_grad(e, x)
+    terms, grad = _eval(plan, x)
+    assert abs(terms[0] - want_t["Q_tot"]) <= TOL["f32"] * want_t["Q_tot"]
+    assert rel(grad, want_g) <= TOL["f32"]
+
+
+def test_c4_mini_rebinning_keeps_the_objective(mini):
+    """Tile changes re-sort the records on the device; the result must not move."""
+    e = mini.expand()
+    plan = _cube_plan(mini)
+    rng = np.random.default_rng(44)
+    x = rng.uniform(0, 50, size=e.x_true.shape)
+    want_t, want_g = oracle.objective_grad(e, x)
+    for blocking in [(12, 4, 512, 16, 2), (8, 1, 128, 8, 1), (16, 2, 64, 8, 1), (8, 2, 256, 16, 2)]:
+        plan.set_blocking(*blocking)
+        terms, grad = _eval(plan, x)
+        assert abs(terms[0] - want_t["Q_tot"]) <= TOL["f32"] * want_t["Q_tot"], blocking
+        assert rel(grad, want_g) <= TOL["f32"], blocking
+
+
+def test_c4_mini_bad_sample_is_reported(mini):
+    plan = Plan.from_problem(mini)
+    vis = mini.vis.copy()
+    live = np.flatnonzero(mini.flags == 0)
+    vis[live[17]] = np.complex64(np.nan)
+    q = synth.CubeProblem(**{**mini.__dict__, "vis": vis})
+    with pytest.raises(IvxError) as ei:
+        plan.set_cube_data(q)
+    assert ei.value.code == -4 and str(live[17]) in str(ei.value)
+    flagged = np.flatnonzero(mini.flags != 0)
+    vis = mini.vis.copy()
+    vis[flagged[:5]] = np.complex64(np.inf)  # flagged samples are never read
+    plan.set_cube_data(synth.CubeProblem(**{**mini.__dict__, "vis": vis}))
+
+
+# ------------------------------------------------------------------------------- full
+
+@pytest.fixture(scope="module")
+def c4():
+    t0 = time.perf_counter()
+    p = synth.config_c4()
+    print(f"[c4] generated {p.n_vis:,} visibilities in {time.perf_counter() - t0:.1f} s", flush=True)
+    synth.attach_sd(p, oracle.sd_model(p, p.x_true))
+    return p
+
+
+@pytest.fixture(scope="module")
+def c4plan(c4):
+    t0 = time.perf_counter()
+    plan = Plan.from_problem(c4, tile=8)
+    plan.set_cube_data(c4)
+    plan.set_blocking(8, 4, 256, 16, 2)
+    torch.cuda.synchronize()
+    info = plan.info()
+    print(f"[c4] plan in {time.perf_counter() - t0:.1f} s: {info}", flush=True)
+    x = torch.zeros((c4.n_chan, c4.n_sky, c4.n_sky), dtype=torch.float32, device="cuda")
+    plan.objective_grad(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        plan.objective_grad(x)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / 3 * 1e3
+    print(f"[c4] {ms:.1f} ms per evaluation, {info['n_live_vis'] / (ms * 1e-3):.3e} vis/s", flush=True)
+    return plan
+
+
+def test_c4_objective_at_zero(c4, c4plan):
+    zero = torch.zeros((c4.n_chan, c4.n_sky, c4.n_sky), dtype=torch.float32, device="cuda")
+    terms, _ = c4plan.objective_grad(zero)
+    q0 = 0.0
+    for k in range(c4.n_point):
+        w = c4.weight_of(k).astype(np.float64)
+        for c in range(c4.n_chan):
+            s = c4.block(k, c)
+            live = c4.flags[s] == 0
+            y = c4.vis[s][live]
+            q0 += 0.5 * float(np.sum(w[live] * (y.real.astype(np.float64) ** 2 + y.imag.astype(np.float64) ** 2)))
+    G = oracle.sd_matrix_for(c4)
+    k0 = sum(oracle.sd_term(np.zeros((c4.n_sky, c4.n_sky)), c4.sd_map[c], c4.sd_sigma, G)[0]
+             for c in range(c4.n_chan))
+    print(f"[c4 Q(0)] Q {terms[1]:.9e} vs {q0:.9e}, K {terms[2]:.9e} vs {k0:.9e}", flush=True)
+    assert abs(terms[1] - q0) <= 1e-6 * q0
+    assert abs(terms[2] - k0) <= 1e-5 * k0
+    assert terms[3] == 0.0
+    assert abs(terms[0] - (q0 + c4.lambda_s * k0)) <= 1e-6 * terms[0]
+
+
+def test_c4_gradient_at_zero_sampled(c4, c4plan):
+    zero = torch.zeros((c4.n_chan, c4.n_sky, c4.n_sky), dtype=torch.float32, device="cuda")
+    _, grad = c4plan.objective_grad(zero)
+    G = oracle.sd_matrix_for(c4)
+    rng = np.random.default_rng(45)
+    pix = rng.integers(200, 824, size=(6, 2))
+    n_sub = c4.n_sub
+    for c in (0, c4.n_chan - 1):
+        got = grad[c].double().cpu().numpy()[pix[:, 0], pix[:, 1]]
+        _, gsd = oracle.sd_term(np.zeros((c4.n_sky, c4.n_sky)), c4.sd_map[c], c4.sd_sigma, G)
+        want = c4.lambda_s * gsd[pix[:, 0], pix[:, 1]]
+        for k in range(c4.n_point):
+            grid = c4.interp[k].astype(np.float64)
+            s = c4.block(k, c)
+            lv = c4.flags[s] == 0
+            coef = c4.vis[s][lv].astype(np.complex128) * c4.weight_of(k)[lv]
+            uv = c4.uv_of(k, c)[lv]
+            for t, (i, j) in enumerate(pix):
+                near = np.argwhere((np.abs(grid[..., 0] - i) < 1.5) & (np.abs(grid[..., 1] - j) < 1.5))
+                if near.size == 0:
+                    continue
+                adj = oracle.dft_adjoint_pixels(coef, uv, c4.pixel_rad, n_sub, near)
+                gp = np.zeros((n_sub, n_sub))
+                gp[near[:, 0], near[:, 1]] = -c4.flux_scale[c] * c4.beams[k][near[:, 0], near[:, 1]] * adj
+                want[t] += oracle.reproject_adjoint(gp, grid, c4.n_sky)[i, j]
+        e = rel(got, want)
+        print(f"[c4 grad(0) channel {c}] rel {e:.2e}", flush=True)
+        assert e <= 1e-5
+
+
+def test_c4_forward_sampled(c4, c4plan):
+    need = c4.n_vis * 8 + c4.n_chan * c4.n_sky ** 2 * 4
+    free, _ = torch.cuda.mem_get_info()
+    if need > 0.95 * free:
+        pytest.skip(f"the {need / 2**30:.1f} GiB forward output does not fit beside the plan "
+                    f"({free / 2**30:.1f} GiB free)")
+    x = torch.tensor(c4.x_true, dtype=torch.float32, device="cuda")
+    out = c4plan.forward(x)
+    rng = np.random.default_rng(46)
+    errs = []
+    for (k, c) in [(0, 0), (17, 64), (35, c4.n_chan - 1)]:
+        s = c4.block(k, c)
+        live = np.flatnonzero(c4.flags[s] == 0)
+        idx = np.sort(rng.choice(live, 200, replace=False))
+        got = out[torch.as_tensor(s.start + idx, device="cuda")].double().cpu().numpy()
+        f = oracle.beam_weighted_subimage(c4, c4.x_true[c], k, c)
+        want = oracle.dft_forward(f, c4.uv_of(k, c)[idx], c4.pixel_rad)
+        errs.append(rel(got[:, 0] + 1j * got[:, 1], want))
+    del out
+    print(f"[c4 forward sampled] rel {max(errs):.2e}", flush=True)
+    assert max(errs) <= 1e-5
