@@ -18,6 +18,12 @@ to the first evaluation with Q_tot <= (1 + 1e-4) J*.  Every solve, cold or warm,
 device L-BFGS-B loop (include/ivx_lbfgsb.h) with the same settings.
 
     python -m paper_2609_17636_amd.warmstart --train 512 --heldout 32 --epochs 40
+
+The cold solves that produce training targets and J* run in several host threads, each
+with its own plan, device solver and stream (the solver waits on a few scalars per
+iteration, so one solve leaves the GPU mostly idle); time-to-tolerance runs one solve at a
+time.  `--phase train --save DIR` stops after training and writes the network, the mean
+training solution and the J* values; `--phase measure --load DIR` times them.
 """
 from __future__ import annotations
 
@@ -39,7 +45,7 @@ class Mosaic:
     """The warm-start mosaic on the GPU: a float plan and its device solver for solving,
     and an FP64 plan that generates the data."""
 
-    def __init__(self, layout_seed: int = LAYOUT_SEED, autotune_ms: float = 500.0):
+    def __init__(self, layout_seed: int = LAYOUT_SEED, autotune_ms: float = 500.0, blocking=None):
         import torch
 
         import synth
@@ -56,7 +62,9 @@ class Mosaic:
         self.offsets = [int(v) for v in p.vis_offsets]
         self.n = p.n_sky
         self.simulate(0)
-        if autotune_ms > 0:
+        if blocking is not None:
+            self.plan.set_blocking(*blocking)
+        elif autotune_ms > 0:
             self.plan.autotune(autotune_ms)
         self.solver = DeviceSolver(self.plan)
         self.zero = torch.zeros((1, self.n, self.n), dtype=torch.float32, device="cuda")
@@ -115,6 +123,59 @@ def cold_solves(m: Mosaic, seeds, maxiter, log=None, every=32):
                      "message": r.message})
         if log and (i + 1) % every == 0:
             log(f"  {i + 1}/{len(seeds)} solves")
+    return D, X, info
+
+
+def blocking_of(m: Mosaic):
+    i = m.plan.info()
+    return (i["tile"], i["waves_per_block"], i["chunk"], i["lanes"], i["vpi"])
+
+
+def cold_solves_parallel(mosaics, seeds, maxiter, log=None, every=64):
+    """cold_solves over several mosaics (one host thread and one stream each); results in
+    seed order, identical to a sequential run (each solve only depends on its seed)."""
+    import threading
+
+    import torch
+
+    n = mosaics[0].n
+    D = torch.empty((len(seeds), n, n), dtype=torch.float32, device="cuda")
+    X = torch.empty_like(D)
+    torch.cuda.synchronize()
+    info = [None] * len(seeds)
+    streams = [torch.cuda.Stream() for _ in mosaics]
+    lock = threading.Lock()
+    state = {"done": 0, "errors": []}
+
+    def work(w):
+        m = mosaics[w]
+        try:
+            with torch.cuda.stream(streams[w]):
+                for i in range(w, len(seeds), len(mosaics)):
+                    s = seeds[i]
+                    m.simulate(s)
+                    D[i] = m.dirty()[0]
+                    r = m.solve(maxiter=maxiter)
+                    X[i] = r.x[0] / PEAK_K
+                    info[i] = {"seed": int(s), "fun": r.fun, "nit": r.nit, "nfev": r.nfev, "seconds": r.seconds,
+                               "message": r.message}
+                    with lock:
+                        state["done"] += 1
+                        k = state["done"]
+                    if log and k % every == 0:
+                        log(f"  {k}/{len(seeds)} solves")
+            streams[w].synchronize()
+        except BaseException as e:  # surfaced after the join
+            state["errors"].append(e)
+
+    threads = [threading.Thread(target=work, args=(w,)) for w in range(len(mosaics))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    if state["errors"]:
+        raise state["errors"][0]
     return D, X, info
 
 
@@ -223,6 +284,10 @@ def main(argv=None):
     ap.add_argument("--solve-iters", type=int, default=600, help="L-BFGS-B iterations of a training target")
     ap.add_argument("--jstar-iters", type=int, default=15000, help="iteration cap of the J* solve")
     ap.add_argument("--out", default="", help="write the JSON report here too")
+    ap.add_argument("--workers", type=int, default=8, help="host threads (plans) for the untimed cold solves")
+    ap.add_argument("--phase", default="all", choices=("all", "train", "measure"))
+    ap.add_argument("--save", default="", help="--phase train: directory for the network, mean image and J*")
+    ap.add_argument("--load", default="", help="--phase measure: directory written by --phase train")
     a = ap.parse_args(argv)
 
     def log(msg):
@@ -232,19 +297,34 @@ def main(argv=None):
 
     from .unet import UNet
 
+    import os
+
     t0 = time.perf_counter()
     m = Mosaic()
     log(f"mosaic ready ({time.perf_counter() - t0:.1f} s): {m.plan.info()}")
+    net = UNet(levels=4, base=32, max_batch=a.batch, height=256, width=256, seed=0)
+    if a.phase == "measure":
+        with open(os.path.join(a.load, "warmstart_train.json")) as f:
+            saved = json.load(f)
+        net.set_params(np.load(os.path.join(a.load, "unet_params.npy")))
+        x_mean = torch.tensor(np.load(os.path.join(a.load, "x_mean.npy")), device="cuda")
+        hv = saved["jstar"]
+        report = dict(saved["report"])
+        log(f"loaded network, mean image and {len(hv)} J* values from {a.load}")
+        return _measure(a, m, net, hv, x_mean, report, t0, log)
+    extra = [Mosaic(autotune_ms=0.0, blocking=blocking_of(m)) for _ in range(max(a.workers, 1) - 1)]
+    log(f"{len(extra) + 1} solver threads ready ({time.perf_counter() - t0:.1f} s)")
     log(f"cold solves: {a.train} training fields x {a.solve_iters} iterations")
-    D, X, tr = cold_solves(m, list(range(a.train)), a.solve_iters, log)
-    log(f"training targets done ({time.perf_counter() - t0:.0f} s; median {np.median([r['seconds'] for r in tr]):.3f} s, "
-        f"{np.median([r['nfev'] for r in tr]):.0f} evaluations per solve)")
+    t_s = time.perf_counter()
+    D, X, tr = cold_solves_parallel([m] + extra, list(range(a.train)), a.solve_iters, log)
+    log(f"training targets done ({time.perf_counter() - t_s:.0f} s; median {np.median([r['seconds'] for r in tr]):.3f} s, "
+        f"{np.median([r['nfev'] for r in tr]):.0f} evaluations per solve, {len(extra) + 1} threads)")
     held = [HELDOUT_BASE + i for i in range(a.heldout)]
-    Dv, Xv, hv = cold_solves(m, held, a.jstar_iters, log, every=8)
+    Dv, Xv, hv = cold_solves_parallel([m] + extra, held, a.jstar_iters, log, every=16)
     log(f"J* solves done ({time.perf_counter() - t0:.0f} s; median {np.median([r['nit'] for r in hv]):.0f} iterations, "
         f"{np.median([r['seconds'] for r in hv]):.2f} s, stop {sorted(set(r['message'] for r in hv))})")
+    del extra
 
-    net = UNet(levels=4, base=32, max_batch=a.batch, height=256, width=256, seed=0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     hist = train(net, D, X, a.epochs, a.batch, a.lr, log=log)
@@ -264,12 +344,6 @@ def main(argv=None):
         f"(mean-image baseline {base_mse:.6f})")
 
     x_mean = X.mean(dim=0, keepdim=True) * PEAK_K
-    rows = []
-    for r in hv:
-        rows.append(time_to_tolerance(m, net, r["seed"], r["fun"], a.jstar_iters, x_mean=x_mean))
-        w = rows[-1]
-        log(f"seed {r['seed']}: cold {w['cold_s']:.3f} s ({w['cold_nfev']} evals), warm {w['warm_s']:.3f} s "
-            f"({w['warm_nfev']} evals), mean image {w['mean_s']:.3f} s ({w['mean_nfev']} evals)")
     report = {"workload": "warm-start mosaic: 256^2 sky at 30 arcsec, 3x3 hex of 20' beams, 1.8 M visibilities, "
                           "lambda_r 1e-2",
               "solver": "device L-BFGS-B (m 10, x >= 0)",
@@ -278,12 +352,32 @@ def main(argv=None):
               "train_step_ms": step_ms, "train_conv_tflops": tflops,
               "train_mse_last": hist[-1] if hist else None, "heldout_mse": val_mse,
               "heldout_mse_mean_image": base_mse, "tolerance": TOL,
-              "summary": summarise(rows), "fields": rows,
               "target_solves": {"seconds_median": float(np.median([r["seconds"] for r in tr])),
-                                "nfev_median": float(np.median([r["nfev"] for r in tr]))},
+                                "nfev_median": float(np.median([r["nfev"] for r in tr])),
+                                "threads": a.workers},
               "jstar_solves": {"seconds_median": float(np.median([r["seconds"] for r in hv])),
-                               "nit_median": float(np.median([r["nit"] for r in hv]))},
-              "total_seconds": time.perf_counter() - t0}
+                               "nit_median": float(np.median([r["nit"] for r in hv]))}}
+    if a.phase == "train":
+        os.makedirs(a.save, exist_ok=True)
+        np.save(os.path.join(a.save, "unet_params.npy"), net.get_params())
+        np.save(os.path.join(a.save, "x_mean.npy"), x_mean.cpu().numpy())
+        with open(os.path.join(a.save, "warmstart_train.json"), "w") as f:
+            json.dump({"jstar": [{"seed": r["seed"], "fun": r["fun"], "nit": r["nit"], "message": r["message"]}
+                                 for r in hv], "report": report}, f)
+        log(f"saved network, mean image and J* to {a.save} ({time.perf_counter() - t0:.0f} s)")
+        return report
+    return _measure(a, m, net, hv, x_mean, report, t0, log)
+
+
+def _measure(a, m, net, hv, x_mean, report, t0, log):
+    rows = []
+    for r in hv:
+        rows.append(time_to_tolerance(m, net, r["seed"], r["fun"], a.jstar_iters, x_mean=x_mean))
+        w = rows[-1]
+        log(f"seed {r['seed']}: cold {w['cold_s']:.3f} s ({w['cold_nfev']} evals), warm {w['warm_s']:.3f} s "
+            f"({w['warm_nfev']} evals), mean image {w['mean_s']:.3f} s ({w['mean_nfev']} evals)")
+    report = dict(report)
+    report.update({"summary": summarise(rows), "fields": rows, "total_seconds": time.perf_counter() - t0})
     line = json.dumps(report)
     print(line, flush=True)
     if a.out:

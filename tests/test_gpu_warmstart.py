@@ -53,3 +53,13 @@ def test_training_and_warm_start(ws, mosaic):
     print(row)
     assert np.isfinite(row["cold_s"]) and np.isfinite(row["warm_s"]) and np.isfinite(row["mean_s"])
     assert row["q_warm_start"] < row["q_cold_start"]
+
+
+def test_parallel_cold_solves_match_sequential(ws, mosaic):
+    """Solver threads (own plan, solver and stream each) give the sequential results."""
+    other = ws.Mosaic(autotune_ms=0, blocking=ws.blocking_of(mosaic))
+    seeds = [21, 22, 23, 24, 25]
+    D1, X1, i1 = ws.cold_solves(mosaic, seeds, maxiter=80)
+    D2, X2, i2 = ws.cold_solves_parallel([mosaic, other], seeds, maxiter=80)
+    assert torch.equal(D1, D2) and torch.equal(X1, X2)
+    assert [r["fun"] for r in i1] == [r["fun"] for r in i2]
