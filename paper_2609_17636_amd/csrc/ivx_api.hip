@@ -265,6 +265,13 @@ void set_tile(ivx_plan *p, int T) {
 
 bool tile_fits(const ivx_plan *p, int T, int nwave, int lanes) {
     if (T < p->g.W || T > 255) return false;
+    if (lanes == GRID_MFMA_LANES) {
+#ifdef IVX_REAL_DOUBLE
+        return false; // the matrix-core gridder is float only
+#else
+        return nwave == 1 && T + p->g.W - 1 <= 16;
+#endif
+    }
     Geom g = p->g;
     g.T = T;
     g.win = T + g.W - 1;
@@ -845,8 +852,9 @@ ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out) {
 ivx_status ivx_set_blocking(ivx_plan *p, int32_t tile, int32_t waves, int32_t chunk, int32_t lanes, int32_t vpi,
                             void *stream) {
     if (!p) return fail(IVX_EINVAL, "plan is NULL");
-    if (!(waves == 1 || waves == 2 || waves == 4) || chunk < 16 || !(lanes == 8 || lanes == 16) ||
-        !(vpi == 1 || vpi == 2))
+    if (!(waves == 1 || waves == 2 || waves == 4) || chunk < 16 ||
+        !(lanes == 8 || lanes == 16 || lanes == GRID_MFMA_LANES) || !(vpi == 1 || vpi == 2) ||
+        (lanes == GRID_MFMA_LANES && vpi != 1))
         return fail(IVX_EINVAL, "blocking out of range");
     if (!tile_fits(p, tile, waves, lanes)) return fail(IVX_EINVAL, "blocking does not fit the LDS");
     p->nwave = waves;
@@ -1270,6 +1278,10 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
                 for (int nw : waves)
                     if (tile_fits(p, T, nw, lanes))
                         for (int ch : chunks) cands.push_back(Cand{T, nw, ch, lanes, vpi});
+    // the matrix-core gridder: one wave per work item, windows of at most 16 x 16
+    for (int T = p->g.W; T <= 17 - p->g.W; ++T)
+        if (tile_fits(p, T, 1, GRID_MFMA_LANES))
+            for (int ch : chunks) cands.push_back(Cand{T, 1, ch, GRID_MFMA_LANES, 1});
     if (cands.empty()) return fail(IVX_EINVAL, "no tile candidate fits");
     // the tiling only changes the gridding stage and the slot reduction: time those two on
     // the plan's own data (zero sky), keep the fastest; the result is accuracy-neutral

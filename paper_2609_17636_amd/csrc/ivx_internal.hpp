@@ -148,6 +148,10 @@ hipError_t sort_keys(void *temp, size_t &temp_bytes, const uint64_t *in, uint64_
 hipError_t sort_pairs(void *temp, size_t &temp_bytes, const uint64_t *kin, uint64_t *kout, const uint32_t *vin,
                       uint32_t *vout, int n, int end_bit, hipStream_t st);
 
+// Gridding on the matrix cores (float build, windows of at most 16 x 16 cells, one wave
+// per work item): selected by lanes = GRID_MFMA_LANES, variant = GRID_MFMA_VARIANT.
+constexpr int GRID_MFMA_LANES = 64;
+constexpr int GRID_MFMA_VARIANT = 10 * GRID_MFMA_LANES + 1;
 // Raise the dynamic-LDS limit of the gridding kernels for this geometry (call before any
 // stream capture).
 // variant = 10 * lanes per visibility (8 or 16) + visibilities per group per iteration (1, 2)

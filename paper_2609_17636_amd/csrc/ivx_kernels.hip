@@ -627,6 +627,200 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
 
 int grid_groups_per_wave(int W, int lanes) { return (lanes == 8 && W <= 8) ? 8 : 4; }
 
+#ifndef IVX_REAL_DOUBLE
+// ---------------------------------------------------- gridding on the matrix cores
+// The same degrid / residual / spread as k_grid, written as per-tile matrix products (float
+// build, windows of at most 16 x 16 cells).  One wave per work item; per batch of 16
+// visibilities the kernel weights of every visibility at the 16 window columns (PX[m][b])
+// and rows (PY[m][a]) -- zero outside its footprint -- go to LDS, then
+//   degrid   Q[a][m] = sum_b F[a][b] PX[m][b]              (v_mfma_f32_16x16x4_f32, K = b)
+//            V_m     = sum_a PY[m][a] Q[a][m]              (4 rows per lane + two lane swaps)
+//   spread   H[a][b] += sum_m PY[m][a] (w_m r_m) PX[m][b]  (v_mfma_f32_16x16x4_f32, K = m)
+// The window F and the accumulation H stay in registers for the whole work item; H is
+// written to the work item's slot at the end.  Operand layout of the 16x16x4 instruction:
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4 (l / 16) + v][l % 16].
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int MX_LD = 17; // row stride of the weight tables (bank spread)
+
+// LDS hand-off between the lanes of the (single-wave) block: a wave's LDS operations are
+// performed in order, so only the compiler has to be kept from moving accesses across;
+// unlike a block barrier this does not wait for the wave's outstanding global loads.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int MODE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_gridmx(GridArgs a) {
+    __shared__ float PX[16 * MX_LD], PY[16 * MX_LD];
+    __shared__ float ZX[16], ZY[16];
+    __shared__ int IX[16], IY[16];
+    __shared__ float WRr[16], WRi[16];
+    const int64_t wid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (wid >= a.n_work) return;
+    const WorkItem wi = a.work[wid];
+    const Geom &g = a.g;
+    const int l = threadIdx.x, c16 = l & 15, g4 = l >> 4;
+    const int W = g.W, win = g.win;
+    const float zoff = 0.5f * (float)W - 1.f;
+    const float inv_hw = 2.f / (float)W;
+    const float beta2 = g.beta * 1.4426950408889634f;
+    // window F[a][b] (tile rows a, columns b), lane holds F[c16][4 i + g4]
+    float fr[4] = {0.f, 0.f, 0.f, 0.f}, fi[4] = {0.f, 0.f, 0.f, 0.f};
+    if (MODE != MODE_ADJ) {
+        const cpx *F = a.ext + (int64_t)wi.item * g.ext_stride + (int64_t)(wi.tx * g.T) * g.eh + wi.ty * g.T;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int b = 4 * i + g4;
+            if (c16 < win && b < win) {
+                const cpx v = F[b * g.eh + c16];
+                fr[i] = v.re;
+                fi[i] = v.im;
+            }
+        }
+    }
+    f32x4 hre = {0.f, 0.f, 0.f, 0.f}, him = {0.f, 0.f, 0.f, 0.f};
+    float jacc = 0.f;
+    const int n = wi.count;
+    const VisCoord *crd = a.crd + wi.begin;
+    const cpx *vis = a.vis + wi.begin;
+    const real *wgt = a.wgt + wi.begin;
+    const int32_t *perm = a.perm + wi.begin;
+    cpx *caller_out = nullptr;
+    const cpx *caller_in = nullptr;
+    if (MODE == MODE_FWD) caller_out = a.caller_out + a.boff[wi.item];
+    if (MODE == MODE_ADJ) caller_in = a.caller_in + a.boff[wi.item];
+    // records of a batch (lanes 0-15); two sets rotate so that the next batch's records are
+    // in flight while the current batch is processed, with no register copies
+    struct MxRec {
+        VisCoord c;
+        cpx y;
+        float w;
+        int p;
+    };
+    auto fetch = [&](MxRec &r, int v0) {
+        const int vi = v0 + c16;
+        if (l < 16 && vi < n) {
+            r.c = crd[vi];
+            if (MODE == MODE_OBJ) { r.y = vis[vi]; r.w = wgt[vi]; }
+            if (MODE == MODE_ADJ) { r.w = wgt[vi]; r.p = perm[vi]; }
+            if (MODE == MODE_FWD) r.p = perm[vi];
+        }
+    };
+    auto batch = [&](const MxRec &r, int v0) {
+        const bool ok = l < 16 && v0 + c16 < n;
+        if (l < 16) {
+            int ix, iy;
+            real fx, fy;
+            decode(r.c, ix, iy, fx, fy);
+            ZX[l] = zoff + fx;
+            ZY[l] = zoff + fy;
+            IX[l] = ok ? ix : -64; // no footprint: every weight of the row is zero
+            IY[l] = ok ? iy : -64;
+            if (MODE == MODE_ADJ) {
+                float yr = 0.f, yi = 0.f;
+                if (ok) {
+                    const cpx y = caller_in[r.p < 0 ? ~r.p : r.p];
+                    yr = r.w * y.re;
+                    yi = r.w * (r.p < 0 ? -y.im : y.im);
+                }
+                WRr[l] = yr;
+                WRi[l] = yi;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = l + 64 * i, m = e >> 4, pos = e & 15;
+            PX[m * MX_LD + pos] = 0.f;
+            PY[m * MX_LD + pos] = 0.f;
+        }
+        wave_sync();
+        {
+            // the W nonzero weights per visibility and axis: lane (m = l / 4, k = l % 4 + 4 j)
+            const int m = l >> 2;
+            const int ixm = IX[m], iym = IY[m];
+            const float zxm = ZX[m], zym = ZY[m];
+            if (ixm >= 0) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = (l & 3) + 4 * j;
+                    if (k < W) {
+                        PX[m * MX_LD + ixm + k] = es_kernel(zxm - (float)k, inv_hw, beta2);
+                        PY[m * MX_LD + iym + k] = es_kernel(zym - (float)k, inv_hw, beta2);
+                    }
+                }
+            }
+        }
+        wave_sync();
+        if (MODE != MODE_ADJ) {
+            f32x4 qre = {0.f, 0.f, 0.f, 0.f}, qim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float bx = PX[c16 * MX_LD + 4 * i + g4];
+                qre = __builtin_amdgcn_mfma_f32_16x16x4f32(fr[i], bx, qre, 0, 0, 0);
+                qim = __builtin_amdgcn_mfma_f32_16x16x4f32(fi[i], bx, qim, 0, 0, 0);
+            }
+            float vr = 0.f, vi = 0.f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float py = PY[c16 * MX_LD + 4 * g4 + v];
+                vr += py * qre[v];
+                vi += py * qim[v];
+            }
+            vr += __shfl_xor(vr, 16, 64);
+            vi += __shfl_xor(vi, 16, 64);
+            vr += __shfl_xor(vr, 32, 64);
+            vi += __shfl_xor(vi, 32, 64);
+            // every lane now holds V of visibility c16 of the batch
+            if (MODE == MODE_FWD) {
+                if (ok) caller_out[r.p < 0 ? ~r.p : r.p] = cpx{vr, r.p < 0 ? -vi : vi};
+                wave_sync();
+                return;
+            }
+            if (l < 16) {
+                const float rr = vr - r.y.re, ri = vi - r.y.im;
+                if (ok) jacc += r.w * (rr * rr + ri * ri); // halved at the end
+                WRr[l] = ok ? r.w * rr : 0.f;
+                WRi[l] = ok ? r.w * ri : 0.f;
+            }
+            wave_sync();
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int m = 4 * s4 + g4;
+            const float ay = PY[m * MX_LD + c16];
+            const float bx = PX[m * MX_LD + c16];
+            hre = __builtin_amdgcn_mfma_f32_16x16x4f32(ay, WRr[m] * bx, hre, 0, 0, 0);
+            him = __builtin_amdgcn_mfma_f32_16x16x4f32(ay, WRi[m] * bx, him, 0, 0, 0);
+        }
+        wave_sync(); // the tables are rewritten by the next batch
+    };
+    MxRec ra{}, rb{};
+    fetch(ra, 0);
+    for (int v0 = 0; v0 < n; v0 += 32) {
+        if (v0 + 16 < n) fetch(rb, v0 + 16);
+        batch(ra, v0);
+        if (v0 + 16 >= n) break;
+        if (v0 + 32 < n) fetch(ra, v0 + 32);
+        batch(rb, v0 + 16);
+    }
+    if (MODE == MODE_FWD) return;
+    cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride; // column-major window
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 4 * g4 + v;
+        if (r < win && c16 < win) Sl[c16 * win + r] = cpx{hre[v], him[v]};
+    }
+    if (MODE == MODE_OBJ) {
+        double d = 0.5 * (double)jacc;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) d += __shfl_xor(d, m, 64);
+        if (l == 0) a.jpart[wid] = d;
+    }
+}
+#endif
+
 // ----------------------------------------------------------------------- fold
 // Two passes.  (1) k_ext_sum: the adjoint extended grid E = sum of every work item's
 // window placed at its tile, computed owner-wise: the block of (virtual) tile (vy, vx)
@@ -1064,6 +1258,7 @@ hipError_t launch_row_inv(const Geom &g, const cpx *R, const real *beams, const 
 }
 
 size_t grid_lds_bytes(const Geom &g, int nwave, int lanes) {
+    if (lanes == GRID_MFMA_LANES) return 0;
     return (size_t)(1 + grid_groups_per_wave(g.W, lanes) * nwave) * g.win * g.ldw * sizeof(cpx);
 }
 
@@ -1133,6 +1328,7 @@ static hipError_t dispatch(bool prepare, int variant, int mode, const GridArgs &
 }
 
 hipError_t prepare_grid(const Geom &g, int nwave, int variant) {
+    if (variant == GRID_MFMA_VARIANT) return hipSuccess; // static LDS only
     GridArgs a{};
     a.g = g;
     a.nwave = nwave;
@@ -1146,6 +1342,21 @@ hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work
     if (n_work <= 0) return hipSuccess;
     if (nwave < 1 || nwave > NT / 64) return hipErrorInvalidValue;
     GridArgs a{g, work, crd, vis, wgt, perm, boff, ext, slots, jpart, caller_in, caller_out, nwave, n_work};
+    if (variant == GRID_MFMA_VARIANT) {
+#ifdef IVX_REAL_DOUBLE
+        return hipErrorInvalidValue;
+#else
+        if (g.win > 16) return hipErrorInvalidValue;
+        const unsigned gx = (unsigned)n_work < GRID_ROW ? (unsigned)n_work : GRID_ROW;
+        const dim3 grid(gx, (unsigned)((n_work + gx - 1) / gx));
+        switch (mode) {
+        case MODE_OBJ: k_gridmx<MODE_OBJ><<<grid, 64, 0, st>>>(a); break;
+        case MODE_FWD: k_gridmx<MODE_FWD><<<grid, 64, 0, st>>>(a); break;
+        default: k_gridmx<MODE_ADJ><<<grid, 64, 0, st>>>(a); break;
+        }
+        return hipGetLastError();
+#endif
+    }
     return dispatch(false, variant, mode, a, n_work, st);
 }
 

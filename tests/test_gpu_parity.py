@@ -165,10 +165,12 @@ def test_objective_independent_of_tile(mini, tile):
 
 
 @pytest.mark.parametrize("blocking", [(8, 1, 128, 16, 1), (8, 2, 256, 16, 2), (12, 4, 512, 16, 2),
-                                      (8, 1, 128, 8, 1), (16, 2, 256, 8, 2), (16, 2, 64, 8, 1)])
+                                      (8, 1, 128, 8, 1), (16, 2, 256, 8, 2), (16, 2, 64, 8, 1),
+                                      (8, 1, 128, 64, 1), (9, 1, 32, 64, 1)])
 def test_objective_independent_of_gridding_variant(mini, blocking):
     """Every gridding variant (tile, waves per block, chunk, lanes per visibility,
-    visibilities per lane group) gives the same objective and gradient."""
+    visibilities per lane group; lanes = 64 is the matrix-core gridder) gives the same
+    objective, gradient and model visibilities."""
     plan = _plan(mini, "f32")
     plan.set_blocking(*blocking)
     tol = TOL["f32"]
@@ -184,6 +186,28 @@ def test_objective_independent_of_gridding_variant(mini, blocking):
     mv = oracle.model_vis(mini, x)
     live = mini.flags == 0
     assert rel(v[live, 0] + 1j * v[live, 1], mv[live]) <= tol
+
+
+@pytest.mark.parametrize("blocking", [(8, 1, 128, 64, 1), (9, 1, 64, 64, 1)])
+def test_adjoint_of_matrix_core_gridder(mini, blocking):
+    """The matrix-core gridder's adjoint mode: weighted adjoint image against the oracle's
+    direct sums, and the adjoint identity with its own forward mode."""
+    plan = _plan(mini, "f32")
+    plan.set_blocking(*blocking)
+    rng = np.random.default_rng(21)
+    v = rng.standard_normal((mini.n_vis, 2))
+    v[mini.flags != 0] = 0.0
+    got = plan.adjoint(torch.tensor(v, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    want = oracle.adjoint_image(mini, v[:, 0] + 1j * v[:, 1])
+    e = rel(got, want)
+    print(f"[mini adjoint {blocking}] rel {e:.2e}", flush=True)
+    assert e <= TOL["f32"]
+    x = rng.standard_normal(mini.x_true.shape)
+    Ax = plan.forward(torch.tensor(x, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    w = mini.weight.astype(np.float64) * (mini.flags == 0)
+    lhs = float(np.sum(w * (Ax[:, 0] * v[:, 0] + Ax[:, 1] * v[:, 1])))
+    rhs = float(np.sum(x * got))
+    assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.sum(w * (Ax ** 2).sum(axis=1)) * np.sum(w * (v ** 2).sum(axis=1)))
 
 
 def test_objective_c2_subsampled(c2_sub):
