@@ -1272,16 +1272,17 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     const int tiles[] = {8, 12, 16, 24, 32};
     const int waves[] = {4, 2, 1};
     const int chunks[] = {128, 256, 512};
+    // the matrix-core gridder first (one wave per work item, windows of at most 16 x 16):
+    // it is the fastest where it fits, and the search may stop at the time budget
+    for (int T = 17 - p->g.W; T >= p->g.W; --T)
+        if (tile_fits(p, T, 1, GRID_MFMA_LANES))
+            for (int ch : chunks) cands.push_back(Cand{T, 1, ch, GRID_MFMA_LANES, 1});
     for (int lanes : {16, 8})
         for (int vpi : {2, 1})
             for (int T : tiles)
                 for (int nw : waves)
                     if (tile_fits(p, T, nw, lanes))
                         for (int ch : chunks) cands.push_back(Cand{T, nw, ch, lanes, vpi});
-    // the matrix-core gridder: one wave per work item, windows of at most 16 x 16
-    for (int T = p->g.W; T <= 17 - p->g.W; ++T)
-        if (tile_fits(p, T, 1, GRID_MFMA_LANES))
-            for (int ch : chunks) cands.push_back(Cand{T, 1, ch, GRID_MFMA_LANES, 1});
     if (cands.empty()) return fail(IVX_EINVAL, "no tile candidate fits");
     // the tiling only changes the gridding stage and the slot reduction: time those two on
     // the plan's own data (zero sky), keep the fastest; the result is accuracy-neutral

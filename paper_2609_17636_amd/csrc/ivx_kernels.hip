@@ -1133,7 +1133,15 @@ __global__ __launch_bounds__(NT) void k_partial_sums(const double *__restrict__ 
     __shared__ double red[NT / 64];
     const int b0 = blockIdx.x * per, b1 = min(n, b0 + per);
     double v = 0.0;
-    for (int i = b0 + threadIdx.x; i < b1; i += NT) v += in[i];
+    int i = b0 + threadIdx.x;
+    for (; i + 7 * NT < b1; i += 8 * NT) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = in[i + u * NT];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += t[u];
+    }
+    for (; i < b1; i += NT) v += in[i];
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -1154,9 +1162,22 @@ __global__ __launch_bounds__(NT_FINAL) void k_final(const double *__restrict__ j
     __shared__ double sh[3][NT_FINAL / 64];
     const int tid = threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};
-    for (int i = tid; i < nj; i += NT_FINAL) v[0] += jpart[i];
-    for (int i = tid; i < nr; i += NT_FINAL) v[1] += rpart[i];
-    for (int i = tid; i < nkp; i += NT_FINAL) v[2] += kpart[i];
+    // each thread sums its strided entries in index order; 8 loads are issued before they
+    // are added, so their latencies overlap instead of chaining
+    auto strided_sum = [&](const double *__restrict__ p, int n, double &acc) {
+        int i = tid;
+        for (; i + 7 * NT_FINAL < n; i += 8 * NT_FINAL) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = p[i + u * NT_FINAL];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += t[u];
+        }
+        for (; i < n; i += NT_FINAL) acc += p[i];
+    };
+    strided_sum(jpart, nj, v[0]);
+    strided_sum(rpart, nr, v[1]);
+    strided_sum(kpart, nkp, v[2]);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         for (int m = 32; m >= 1; m >>= 1) v[q] += __shfl_xor(v[q], m, 64);
