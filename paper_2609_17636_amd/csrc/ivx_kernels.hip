@@ -42,14 +42,31 @@ __device__ __forceinline__ cpx csub(cpx a, cpx b) { return cpx{a.re - b.re, a.im
 // length N = 2^LOGN: element i of transform c is buf[i * CB + c].  Each stage reads all
 // of a thread's butterfly inputs into registers, synchronises, then writes the outputs,
 // so the transform runs in place.  Twiddles come from a table tw[t] = exp(-2 pi i t / N),
-// t < 3N/4, staged in LDS by load_twiddles (conjugated for the inverse); no scaling is
+// t < 3N/4, staged in LDS through TwStage (conjugated for the inverse); no scaling is
 // applied in either direction.
 template <int LOGN> constexpr int tw_len() { return 3 * (1 << LOGN) / 4; }
 
-template <int LOGN>
-__device__ __forceinline__ void load_twiddles(cpx *tws, const cpx *__restrict__ tw) {
-    for (int i = threadIdx.x; i < tw_len<LOGN>(); i += NT) tws[i] = tw[i];
-}
+// The twiddle table is fetched into registers at the start of a kernel and stored to LDS
+// only after the kernel's own data loads have been issued, so the two global-memory
+// latencies overlap instead of following each other.
+template <int LOGN> struct TwStage {
+    static constexpr int PER = (tw_len<LOGN>() + NT - 1) / NT;
+    cpx v[PER];
+    __device__ __forceinline__ void fetch(const cpx *__restrict__ tw) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * NT;
+            if (i < tw_len<LOGN>()) v[u] = tw[i];
+        }
+    }
+    __device__ __forceinline__ void store(cpx *tws) const {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * NT;
+            if (i < tw_len<LOGN>()) tws[i] = v[u];
+        }
+    }
+};
 
 template <int LOGN, int CB, bool INV>
 __device__ __forceinline__ void fft_lds(cpx *buf, const cpx *tw) {
@@ -162,7 +179,8 @@ __global__ __launch_bounds__(NT) void k_image_rows(Geom g, const real *__restric
     constexpr int N = 1 << LOGN;
     __shared__ cpx buf[N];
     __shared__ cpx tws[tw_len<LOGN>()];
-    load_twiddles<LOGN>(tws, tw);
+    TwStage<LOGN> twr;
+    twr.fetch(tw);
     const int tid = threadIdx.x;
     const int item = blockIdx.y;
     const int k = item / g.C, c = item - (item / g.C) * g.C;
@@ -181,6 +199,7 @@ __global__ __launch_bounds__(NT) void k_image_rows(Geom g, const real *__restric
         const real f1 = q1 * dq[b] * A[e1] * bilinear(x, g.N, G[2 * e1], G[2 * e1 + 1]);
         buf[(b - nk / 2) & (N - 1)] = cpx{f0, f1};
     }
+    twr.store(tws);
     __syncthreads();
     fft_lds<LOGN, 1, false>(buf, tws);
     cpx *R0 = R + (int64_t)item * g.r_stride + (int64_t)a0 * g.rw;
@@ -201,7 +220,8 @@ __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ 
     constexpr int MAXE = 8 * CB;
     __shared__ cpx buf[CB * N];
     __shared__ cpx tws[tw_len<LOGN>()];
-    load_twiddles<LOGN>(tws, tw);
+    TwStage<LOGN> twr;
+    twr.fetch(tw);
     __shared__ int ent_col[MAXE];
     __shared__ int ent_src[MAXE];
     __shared__ int n_ent;
@@ -236,6 +256,7 @@ __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ 
         const int a = e / CB, cc = e - (e / CB) * CB;
         if (c0 + cc < g.rw) buf[((a - nk / 2) & (N - 1)) * CB + cc] = Ri[(int64_t)a * g.rw + c0 + cc];
     }
+    twr.store(tws);
     __syncthreads();
     fft_lds<LOGN, CB, false>(buf, tws);
     cpx *E = ext + (int64_t)item * g.ext_stride;
@@ -893,7 +914,8 @@ __global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ 
     constexpr int N = 1 << LOGN;
     __shared__ cpx buf[CB * N];
     __shared__ cpx tws[tw_len<LOGN>()];
-    load_twiddles<LOGN>(tws, tw);
+    TwStage<LOGN> twr;
+    twr.fetch(tw);
     const int tid = threadIdx.x;
     const int item = blockIdx.y;
     const int c0 = blockIdx.x * CB;
@@ -909,6 +931,7 @@ __global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ 
         }
         buf[t1 * CB + cc] = v;
     }
+    twr.store(tws);
     __syncthreads();
     fft_lds<LOGN, CB, true>(buf, tws);
     cpx *Ri = R + (int64_t)item * g.r_stride;
@@ -929,7 +952,8 @@ __global__ __launch_bounds__(NT) void k_row_inv(Geom g, const cpx *__restrict__ 
     constexpr int N = 1 << LOGN;
     __shared__ cpx buf[N];
     __shared__ cpx tws[tw_len<LOGN>()];
-    load_twiddles<LOGN>(tws, tw);
+    TwStage<LOGN> twr;
+    twr.fetch(tw);
     const int tid = threadIdx.x;
     const int item = blockIdx.y;
     const int k = item / g.C, c = item - (item / g.C) * g.C;
@@ -951,6 +975,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(Geom g, const cpx *__restrict__ 
         }
         buf[kk] = cpx{x.re - y.im, x.im + y.re}; // x + i y
     }
+    twr.store(tws);
     __syncthreads();
     fft_lds<LOGN, 1, true>(buf, tws);
     const real *A = beams + (int64_t)k * nk * nk;
