@@ -180,24 +180,50 @@ def cold_solves_parallel(mosaics, seeds, maxiter, log=None, every=64):
 
 
 # ----------------------------------------------------------------------------- training
-def train(net, D, X, epochs, batch, lr, seed=0, log=None):
-    """Adam on the MSE between net(d) and x*/50 K; D, X cuda [n][H][W]."""
+def mse(net, D, X, batch):
+    """Mean squared error of net(D) against X (cuda [n][H][W])."""
+    tot = 0.0
+    for i in range(0, D.shape[0], batch):
+        y = net.forward(D[i:i + batch])
+        tot += float(((y - X[i:i + batch]) ** 2).sum())
+    return tot / max(X.numel(), 1)
+
+
+def train(net, D, X, epochs, batch, lr, seed=0, log=None, Dv=None, Xv=None, val_every=5, lr_final=None):
+    """Adam on the MSE between net(d) and x*/50 K; D, X cuda [n][H][W].  With lr_final the
+    step size follows a cosine from lr to lr_final over the epochs.  With a validation set
+    (Dv, Xv: fields not trained on) the parameters of the epoch with the lowest validation
+    MSE (checked every val_every epochs) are restored at the end.  Returns (per-epoch
+    training MSE, (best validation MSE, its epoch) or None)."""
+    import math
+
     import torch
 
     rng = np.random.default_rng(seed)
     n = D.shape[0]
     hist = []
+    best = (float("inf"), None, 0)
     for ep in range(epochs):
+        step_lr = lr if lr_final is None else lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * ep / epochs))
         order = rng.permutation(n)
         tot, cnt = 0.0, 0
         for i in range(0, n - batch + 1, batch):
             idx = torch.as_tensor(order[i:i + batch], device=D.device)
-            tot += net.train_step(D.index_select(0, idx), X.index_select(0, idx), lr)
+            tot += net.train_step(D.index_select(0, idx), X.index_select(0, idx), step_lr)
             cnt += 1
         hist.append(tot / max(cnt, 1))
+        msg = f"epoch {ep + 1}/{epochs} train mse {hist[-1]:.6f} lr {step_lr:.2e}"
+        if Dv is not None and ((ep + 1) % val_every == 0 or ep + 1 == epochs):
+            v = mse(net, Dv, Xv, batch)
+            msg += f" validation mse {v:.6f}"
+            if v < best[0]:
+                best = (v, net.get_params().copy(), ep + 1)
         if log:
-            log(f"epoch {ep + 1}/{epochs} train mse {hist[-1]:.6f}")
-    return hist
+            log(msg)
+    if best[1] is not None:
+        net.set_params(best[1])
+        return hist, (best[0], best[2])
+    return hist, None
 
 
 def predict(net, d):
@@ -285,6 +311,9 @@ def main(argv=None):
     ap.add_argument("--jstar-iters", type=int, default=15000, help="iteration cap of the J* solve")
     ap.add_argument("--out", default="", help="write the JSON report here too")
     ap.add_argument("--workers", type=int, default=8, help="host threads (plans) for the untimed cold solves")
+    ap.add_argument("--val", type=int, default=0,
+                    help="training fields held back to select the epoch (validation, not the held-out test set)")
+    ap.add_argument("--lr-final", type=float, default=None, help="cosine step-size schedule from --lr to this")
     ap.add_argument("--phase", default="all", choices=("all", "train", "measure"))
     ap.add_argument("--save", default="", help="--phase train: directory for the network, mean image and J*")
     ap.add_argument("--load", default="", help="--phase measure: directory written by --phase train")
@@ -326,11 +355,16 @@ def main(argv=None):
     del extra
 
     torch.cuda.synchronize()
+    n_fit = D.shape[0] - a.val
+    Dt, Xt = D[:n_fit], X[:n_fit]
+    Dval, Xval = (D[n_fit:], X[n_fit:]) if a.val > 0 else (None, None)
     t1 = time.perf_counter()
-    hist = train(net, D, X, a.epochs, a.batch, a.lr, log=log)
+    hist, best = train(net, Dt, Xt, a.epochs, a.batch, a.lr, log=log, Dv=Dval, Xv=Xval, lr_final=a.lr_final)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    steps = a.epochs * (D.shape[0] // a.batch)
+    if best is not None:
+        log(f"validation-selected epoch {best[1]} (validation mse {best[0]:.6f} on {a.val} fields)")
+    steps = a.epochs * (Dt.shape[0] // a.batch)
     step_ms = 1e3 * t_train / max(steps, 1)
     tflops = 3 * unet_flops() * a.batch / (step_ms * 1e-3) / 1e12 if steps else float("nan")
     val = 0.0
@@ -338,12 +372,12 @@ def main(argv=None):
         y = net.forward(Dv[i:i + a.batch])
         val += float(((y - Xv[i:i + a.batch]) ** 2).sum())
     val_mse = val / max(Xv.numel(), 1)
-    base_mse = float(((Xv - X.mean(dim=0, keepdim=True)) ** 2).mean())
+    base_mse = float(((Xv - Xt.mean(dim=0, keepdim=True)) ** 2).mean())
     log(f"trained {a.epochs} epochs in {t_train:.0f} s ({step_ms:.1f} ms per step of {a.batch}, "
         f"~{tflops:.1f} TFLOP/s on the convolutions); held-out mse {val_mse:.6f} "
         f"(mean-image baseline {base_mse:.6f})")
 
-    x_mean = X.mean(dim=0, keepdim=True) * PEAK_K
+    x_mean = Xt.mean(dim=0, keepdim=True) * PEAK_K
     report = {"workload": "warm-start mosaic: 256^2 sky at 30 arcsec, 3x3 hex of 20' beams, 1.8 M visibilities, "
                           "lambda_r 1e-2",
               "solver": "device L-BFGS-B (m 10, x >= 0)",
@@ -351,6 +385,8 @@ def main(argv=None):
               "epochs": a.epochs, "batch": a.batch, "lr": a.lr, "train_seconds": t_train,
               "train_step_ms": step_ms, "train_conv_tflops": tflops,
               "train_mse_last": hist[-1] if hist else None, "heldout_mse": val_mse,
+              "validation_fields": a.val, "lr_final": a.lr_final,
+              "selected_epoch": best[1] if best else a.epochs, "validation_mse": best[0] if best else None,
               "heldout_mse_mean_image": base_mse, "tolerance": TOL,
               "target_solves": {"seconds_median": float(np.median([r["seconds"] for r in tr])),
                                 "nfev_median": float(np.median([r["nfev"] for r in tr])),

@@ -43,9 +43,13 @@ def test_training_and_warm_start(ws, mosaic):
     D, X, info = ws.cold_solves(m, list(range(12)), maxiter=300)
     assert all(i["nit"] == 300 or i["message"] in ("pgtol", "ftol") for i in info)
     net = UNet(levels=4, base=32, max_batch=4, height=256, width=256, seed=1)
-    hist = ws.train(net, D, X, epochs=6, batch=4, lr=1e-3)
-    print("train mse", hist)
+    hist, best = ws.train(net, D[:10], X[:10], epochs=6, batch=4, lr=1e-3, Dv=D[10:], Xv=X[10:], val_every=2,
+                          lr_final=1e-4)
+    print("train mse", hist, "best", best)
     assert hist[-1] < 0.5 * hist[0]
+    # the restored parameters are those of the selected epoch
+    assert best is not None and best[1] in (2, 4, 6)
+    assert abs(ws.mse(net, D[10:], X[10:], 4) - best[0]) <= 1e-6 * best[0]
     held = ws.HELDOUT_BASE + 3
     m.simulate(held)
     j = m.solve().fun
