@@ -289,8 +289,8 @@ def main():
         copy_probe(args.steps)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              f"(the channel/pointing sharding is a design note only)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library runs on one "
+              f"GPU (sharding channels and pointings across GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "mosaic":
         run_mosaic(args)

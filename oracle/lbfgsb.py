@@ -299,7 +299,7 @@ def subspace_direction(x, xc, g, theta, W, M, c, free):
     return -r / theta - (Wz @ u) / theta ** 2
 
 
-# --------------------------------------------------------------------- driver
+# --------------------------------------------------------------------- command line
 def lbfgsb(fun, x0, lower=None, m=10, maxiter=15000, maxfun=15000, ftol=2.2204460492503131e-09,
            gtol=1e-5, maxls=20, target=None):
     """Minimise fun (x -> (f, g)) subject to x >= lower.  Returns a dict with x, f, nit,

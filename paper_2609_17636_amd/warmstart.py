@@ -299,7 +299,7 @@ def summarise(rows):
             "mean_image_nfev_median": q([r.get("mean_nfev", np.nan) for r in rows], 50)}
 
 
-# ----------------------------------------------------------------------------- driver
+# ----------------------------------------------------------------------------- command line
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--train", type=int, default=512, help="training fields (seeds 0..N-1)")
