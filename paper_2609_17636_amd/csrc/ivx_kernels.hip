@@ -672,7 +672,23 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int MODE>
+// Sum of x over the four 16-lane rows, returned in every lane of the column (lanes l, l ^ 16,
+// l ^ 32, l ^ 48), with the VALU row swaps of gfx950 instead of LDS permutes.  Swapping the
+// odd rows of one copy with the even rows of another and adding gives x[r] + x[r ^ 1] in row
+// r; the same with row pairs {2, 3} <-> {0, 1} completes the sum.  The additions pair the
+// same operands as two xor-shuffle steps (16, then 32), so the result is bitwise the same.
+__device__ __forceinline__ float row_sum4(float x) {
+    const unsigned u = __float_as_uint(x);
+    const auto p = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    const float y = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    const unsigned v = __float_as_uint(y);
+    const auto q = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+
+// KW > 0 fixes the kernel width at compile time (the footprint loops unroll without
+// per-lane width tests); KW = 0 reads it from the geometry.
+template <int MODE, int KW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_gridmx(GridArgs a) {
     __shared__ float PX[16 * MX_LD], PY[16 * MX_LD];
     __shared__ float ZX[16], ZY[16];
@@ -683,7 +699,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     const WorkItem wi = a.work[wid];
     const Geom &g = a.g;
     const int l = threadIdx.x, c16 = l & 15, g4 = l >> 4;
-    const int W = g.W, win = g.win;
+    const int W = KW > 0 ? KW : g.W, win = g.win;
     const float zoff = 0.5f * (float)W - 1.f;
     const float inv_hw = 2.f / (float)W;
     const float beta2 = g.beta * 1.4426950408889634f;
@@ -764,9 +780,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
             const float zxm = ZX[m], zym = ZY[m];
             if (ixm >= 0) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < (KW > 0 ? (KW + 3) / 4 : 4); ++j) {
                     const int k = (l & 3) + 4 * j;
-                    if (k < W) {
+                    if ((KW > 0 && 4 * j + 3 < KW) || k < W) {
                         PX[m * MX_LD + ixm + k] = es_kernel(zxm - (float)k, inv_hw, beta2);
                         PY[m * MX_LD + iym + k] = es_kernel(zym - (float)k, inv_hw, beta2);
                     }
@@ -789,10 +805,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
                 vr += py * qre[v];
                 vi += py * qim[v];
             }
-            vr += __shfl_xor(vr, 16, 64);
-            vi += __shfl_xor(vi, 16, 64);
-            vr += __shfl_xor(vr, 32, 64);
-            vi += __shfl_xor(vi, 32, 64);
+            vr = row_sum4(vr);
+            vi = row_sum4(vi);
             // every lane now holds V of visibility c16 of the batch
             if (MODE == MODE_FWD) {
                 if (ok) caller_out[r.p < 0 ? ~r.p : r.p] = cpx{vr, r.p < 0 ? -vi : vi};
@@ -1381,6 +1395,16 @@ hipError_t prepare_grid(const Geom &g, int nwave, int variant) {
     return dispatch(true, variant, MODE_OBJ, a, 0, nullptr);
 }
 
+#ifndef IVX_REAL_DOUBLE
+template <int KW> void launch_gridmx(int mode, dim3 grid, const GridArgs &a, hipStream_t st) {
+    switch (mode) {
+    case MODE_OBJ: k_gridmx<MODE_OBJ, KW><<<grid, 64, 0, st>>>(a); break;
+    case MODE_FWD: k_gridmx<MODE_FWD, KW><<<grid, 64, 0, st>>>(a); break;
+    default: k_gridmx<MODE_ADJ, KW><<<grid, 64, 0, st>>>(a); break;
+    }
+}
+#endif
+
 hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
                        const cpx *vis, const real *wgt, const int32_t *perm, const int64_t *boff, const cpx *ext,
                        cpx *slots, double *jpart, const cpx *caller_in, cpx *caller_out, int nwave, int variant,
@@ -1395,10 +1419,10 @@ hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work
         if (g.win > 16) return hipErrorInvalidValue;
         const unsigned gx = (unsigned)n_work < GRID_ROW ? (unsigned)n_work : GRID_ROW;
         const dim3 grid(gx, (unsigned)((n_work + gx - 1) / gx));
-        switch (mode) {
-        case MODE_OBJ: k_gridmx<MODE_OBJ><<<grid, 64, 0, st>>>(a); break;
-        case MODE_FWD: k_gridmx<MODE_FWD><<<grid, 64, 0, st>>>(a); break;
-        default: k_gridmx<MODE_ADJ><<<grid, 64, 0, st>>>(a); break;
+        switch (g.W) {
+        case 7: launch_gridmx<7>(mode, grid, a, st); break;
+        case 8: launch_gridmx<8>(mode, grid, a, st); break;
+        default: launch_gridmx<0>(mode, grid, a, st); break;
         }
         return hipGetLastError();
 #endif
