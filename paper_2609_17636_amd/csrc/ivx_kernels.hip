@@ -147,6 +147,11 @@ __device__ __forceinline__ void fft_lds(cpx *buf, const cpx *tw) {
     }
 }
 
+// Global loads each thread of a column pass issues before it waits for the first: with two
+// blocks of LDS-resident columns per compute unit, one load at a time leaves the latency of
+// every row exposed.
+constexpr int COL_LOADS = 8;
+
 template <int LOGN> constexpr int col_batch() {
     constexpr int b = 65536 / ((1 << LOGN) * (int)sizeof(cpx));
     return b > 16 ? 16 : (b < 1 ? 1 : b);
@@ -252,9 +257,20 @@ __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ 
     }
     __syncthreads();
     const cpx *Ri = R + (int64_t)item * g.r_stride;
-    for (int e = tid; e < nk * CB; e += NT) {
-        const int a = e / CB, cc = e - (e / CB) * CB;
-        if (c0 + cc < g.rw) buf[((a - nk / 2) & (N - 1)) * CB + cc] = Ri[(int64_t)a * g.rw + c0 + cc];
+    // COL_LOADS rows of the source per thread are requested before the first is stored, so
+    // that a block keeps that many loads per lane in flight instead of one
+    for (int e0 = tid; e0 < nk * CB; e0 += COL_LOADS * NT) {
+        cpx v[COL_LOADS];
+#pragma unroll
+        for (int u = 0; u < COL_LOADS; ++u) {
+            const int e = e0 + u * NT, a = e / CB, cc = e - (e / CB) * CB;
+            if (e < nk * CB && c0 + cc < g.rw) v[u] = Ri[(int64_t)a * g.rw + c0 + cc];
+        }
+#pragma unroll
+        for (int u = 0; u < COL_LOADS; ++u) {
+            const int e = e0 + u * NT, a = e / CB, cc = e - (e / CB) * CB;
+            if (e < nk * CB && c0 + cc < g.rw) buf[((a - nk / 2) & (N - 1)) * CB + cc] = v[u];
+        }
     }
     twr.store(tws);
     __syncthreads();
@@ -866,6 +882,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
 // (2) in the adjoint column pass, every half-plane cell sums the extended-grid cells that
 // alias to it (periodic rows and columns) and is symmetrised, Hs = (H(t) + conj H(-t)) / 2,
 // as it is loaded for the inverse column FFT.
+constexpr int FOLD_LOADS = 8; // slot loads per thread in flight in k_ext_sum
+
 __global__ __launch_bounds__(NT) void k_ext_sum(Geom g, int tiles_per_block, const int32_t *__restrict__ tslot,
                                                 const cpx *__restrict__ slots, cpx *__restrict__ E) {
     const int item = blockIdx.y;
@@ -893,16 +911,36 @@ __global__ __launch_bounds__(NT) void k_ext_sum(Geom g, int tiles_per_block, con
         const int c = (int)(((float)e + 0.5f) * inv_t), r = e - c * T;
         const int er = vy * T + r, ec = vx * T + c;
         if (er >= g.eh || ec >= g.ew) continue;
-        real sr = real(0), si = real(0);
+        // the (quadrant, slot) terms of the cell in one list, quadrant-major: FOLD_LOADS of
+        // them are loaded at a time and then added in list order (the order of a plain
+        // quadrant-by-quadrant, slot-by-slot sum)
+        int off[4], p[5];
+        p[0] = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int lr = r + (q >> 1) * T, lc = c + (q & 1) * T;
-            if (lr >= win || lc >= win) continue;
-            const int off = lc * win + lr;
-            for (int sidx = s_lo[q]; sidx < s_hi[q]; ++sidx) {
-                const cpx h = slots[(int64_t)sidx * g.win_stride + off];
-                sr += h.re;
-                si += h.im;
+            const bool in = lr < win && lc < win;
+            off[q] = lc * win + lr;
+            p[q + 1] = p[q] + (in ? s_hi[q] - s_lo[q] : 0);
+        }
+        real sr = real(0), si = real(0);
+        for (int i0 = 0; i0 < p[4]; i0 += FOLD_LOADS) {
+            cpx h[FOLD_LOADS];
+#pragma unroll
+            for (int u = 0; u < FOLD_LOADS; ++u) {
+                const int i = i0 + u;
+                const int q = (i >= p[1]) + (i >= p[2]) + (i >= p[3]);
+                const int pq = q == 0 ? p[0] : q == 1 ? p[1] : q == 2 ? p[2] : p[3];
+                const int lo = q == 0 ? s_lo[0] : q == 1 ? s_lo[1] : q == 2 ? s_lo[2] : s_lo[3];
+                const int oq = q == 0 ? off[0] : q == 1 ? off[1] : q == 2 ? off[2] : off[3];
+                if (i < p[4]) h[u] = slots[(int64_t)(lo + i - pq) * g.win_stride + oq];
+            }
+#pragma unroll
+            for (int u = 0; u < FOLD_LOADS; ++u) {
+                if (i0 + u < p[4]) {
+                    sr += h[u].re;
+                    si += h[u].im;
+                }
             }
         }
         Ei[(int64_t)ec * g.eh + er] = cpx{sr, si};
@@ -921,6 +959,32 @@ __device__ __forceinline__ cpx alias_sum(const Geom &g, const cpx *__restrict__ 
     return cpx{sr, si};
 }
 
+// alias_sum for grids whose extended rows stop below 2 n_f and columns below n_f: the cell's
+// column exists at most once and its row at most twice.  alias_pair loads the (up to) two
+// values; pair_sum adds them in alias_sum's order (starting from zero, so a lone -0 reads
+// as +0 there as well).
+__device__ __forceinline__ void alias_pair(const Geom &g, const cpx *__restrict__ Ei, int t1, int t2, cpx &a,
+                                           cpx &b) {
+    const int msk = g.nf - 1;
+    const int ec = (t2 + g.O) & msk, er = (t1 + g.O) & msk;
+    if (ec < g.ew) {
+        const cpx *col = Ei + (int64_t)ec * g.eh;
+        if (er < g.eh) a = col[er];
+        if (er + g.nf < g.eh) b = col[er + g.nf];
+    }
+}
+
+__device__ __forceinline__ cpx pair_sum(const Geom &g, int t1, int t2, cpx a, cpx b) {
+    const int msk = g.nf - 1;
+    const int ec = (t2 + g.O) & msk, er = (t1 + g.O) & msk;
+    real sr = real(0), si = real(0);
+    if (ec < g.ew) {
+        if (er < g.eh) { sr += a.re; si += a.im; }
+        if (er + g.nf < g.eh) { sr += b.re; si += b.im; }
+    }
+    return cpx{sr, si};
+}
+
 // ------------------------------------------------------------ adjoint column pass
 template <int LOGN, int CB>
 __global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ E,
@@ -934,16 +998,45 @@ __global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ 
     const int item = blockIdx.y;
     const int c0 = blockIdx.x * CB;
     const cpx *Ei = E + (int64_t)item * g.ext_stride;
-    for (int e = tid; e < N * CB; e += NT) {
-        const int cc = e >> LOGN, t1 = e & (N - 1);
-        const int t2 = c0 + cc;
-        cpx v = cpx{0, 0};
-        if (t2 < g.rw) {
-            const cpx h = alias_sum(g, Ei, t1, t2);
-            const cpx m = alias_sum(g, Ei, (N - t1) & (N - 1), (N - t2) & (N - 1));
-            v = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
+    if (g.eh <= 2 * g.nf && g.ew <= g.nf) {
+        // every cell has at most two aliases (rows t and t + n_f of one column): the loads of
+        // COL_LOADS cells are issued together, then summed in the order of alias_sum
+        for (int e0 = tid; e0 < N * CB; e0 += COL_LOADS * NT) {
+            cpx h0[COL_LOADS], h1[COL_LOADS], m0[COL_LOADS], m1[COL_LOADS];
+#pragma unroll
+            for (int u = 0; u < COL_LOADS; ++u) {
+                const int e = e0 + u * NT, cc = e >> LOGN, t1 = e & (N - 1), t2 = c0 + cc;
+                h0[u] = h1[u] = m0[u] = m1[u] = cpx{0, 0};
+                if (e < N * CB && t2 < g.rw) {
+                    alias_pair(g, Ei, t1, t2, h0[u], h1[u]);
+                    alias_pair(g, Ei, (N - t1) & (N - 1), (N - t2) & (N - 1), m0[u], m1[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < COL_LOADS; ++u) {
+                const int e = e0 + u * NT, cc = e >> LOGN, t1 = e & (N - 1), t2 = c0 + cc;
+                if (e >= N * CB) break;
+                cpx v = cpx{0, 0};
+                if (t2 < g.rw) {
+                    const cpx h = pair_sum(g, t1, t2, h0[u], h1[u]);
+                    const cpx m = pair_sum(g, (N - t1) & (N - 1), (N - t2) & (N - 1), m0[u], m1[u]);
+                    v = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
+                }
+                buf[t1 * CB + cc] = v;
+            }
         }
-        buf[t1 * CB + cc] = v;
+    } else {
+        for (int e = tid; e < N * CB; e += NT) {
+            const int cc = e >> LOGN, t1 = e & (N - 1);
+            const int t2 = c0 + cc;
+            cpx v = cpx{0, 0};
+            if (t2 < g.rw) {
+                const cpx h = alias_sum(g, Ei, t1, t2);
+                const cpx m = alias_sum(g, Ei, (N - t1) & (N - 1), (N - t2) & (N - 1));
+                v = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
+            }
+            buf[t1 * CB + cc] = v;
+        }
     }
     twr.store(tws);
     __syncthreads();
