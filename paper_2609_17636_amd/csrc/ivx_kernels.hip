@@ -1068,19 +1068,30 @@ __global__ __launch_bounds__(NT) void k_row_inv(Geom g, const cpx *__restrict__ 
     const int nk = g.nk;
     const cpx *X = R + (int64_t)item * g.r_stride + (int64_t)a0 * g.rw;
     const cpx *Y = X + g.rw;
-    for (int kk = tid; kk < N; kk += NT) {
-        cpx x, y;
-        if (kk <= N / 2) {
-            x = X[kk];
-            y = Y[kk];
-            if (kk == 0 || kk == N / 2) { x.im = real(0); y.im = real(0); }
-        } else {
-            x = X[N - kk];
-            y = Y[N - kk];
-            x.im = -x.im;
-            y.im = -y.im;
+    for (int k0 = tid; k0 < N; k0 += COL_LOADS * NT) {
+        cpx xv[COL_LOADS], yv[COL_LOADS];
+#pragma unroll
+        for (int u = 0; u < COL_LOADS; ++u) {
+            const int kk = k0 + u * NT;
+            if (kk < N) {
+                const int src = kk <= N / 2 ? kk : N - kk;
+                xv[u] = X[src];
+                yv[u] = Y[src];
+            }
         }
-        buf[kk] = cpx{x.re - y.im, x.im + y.re}; // x + i y
+#pragma unroll
+        for (int u = 0; u < COL_LOADS; ++u) {
+            const int kk = k0 + u * NT;
+            if (kk >= N) break;
+            cpx x = xv[u], y = yv[u];
+            if (kk <= N / 2) {
+                if (kk == 0 || kk == N / 2) { x.im = real(0); y.im = real(0); }
+            } else {
+                x.im = -x.im;
+                y.im = -y.im;
+            }
+            buf[kk] = cpx{x.re - y.im, x.im + y.re}; // x + i y
+        }
     }
     twr.store(tws);
     __syncthreads();
@@ -1186,6 +1197,8 @@ struct SkyArgs {
     int adjoint_only;
 };
 
+constexpr int SKY_LOADS = 8; // CSR entries per lane in flight in k_sky
+
 __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
     __shared__ real xs[SKY_T + 4][SKY_T + 5];
     __shared__ real dxs[SKY_T + 2][SKY_T + 3];
@@ -1227,9 +1240,20 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
         const int slice = (blockIdx.y * gridDim.x + blockIdx.x) * (NT / 64) + (tid >> 6);
         const int e0 = a.cptr[slice], len = (a.cptr[slice + 1] - e0) >> 6;
         const CsrEnt *en = a.cent + e0 + (tid & 63);
-        for (int t = 0; t < len; ++t) {
-            const CsrEnt q = en[t * 64];
-            gsum += q.w * a.gp[(int64_t)q.off + coff];
+        // SKY_LOADS entries, then their SKY_LOADS gathers, are requested before the first is
+        // used; the products are added in entry order
+        for (int t0 = 0; t0 < len; t0 += SKY_LOADS) {
+            CsrEnt q[SKY_LOADS];
+            real v[SKY_LOADS];
+#pragma unroll
+            for (int u = 0; u < SKY_LOADS; ++u)
+                if (t0 + u < len) q[u] = en[(t0 + u) * 64];
+#pragma unroll
+            for (int u = 0; u < SKY_LOADS; ++u)
+                if (t0 + u < len) v[u] = a.gp[(int64_t)q[u].off + coff];
+#pragma unroll
+            for (int u = 0; u < SKY_LOADS; ++u)
+                if (t0 + u < len) gsum += q[u].w * v[u];
         }
         if (reg) {
             const real d = dxs[ti + 1][tj + 1];
