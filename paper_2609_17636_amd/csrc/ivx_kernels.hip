@@ -147,13 +147,15 @@ __device__ __forceinline__ void fft_lds(cpx *buf, const cpx *tw) {
     }
 }
 
-// Global loads each thread of a column pass issues before it waits for the first: with two
+// Global loads each thread of a column pass issues before it waits for the first: with a few
 // blocks of LDS-resident columns per compute unit, one load at a time leaves the latency of
 // every row exposed.
 constexpr int COL_LOADS = 8;
 
+// Columns per block of a column pass: at most 32 KB of LDS columns, so that four blocks share
+// a compute unit (at 1024-point columns 4 per block measured faster than 8 and 2).
 template <int LOGN> constexpr int col_batch() {
-    constexpr int b = 65536 / ((1 << LOGN) * (int)sizeof(cpx));
+    constexpr int b = 32768 / ((1 << LOGN) * (int)sizeof(cpx));
     return b > 16 ? 16 : (b < 1 ? 1 : b);
 }
 
@@ -1381,7 +1383,7 @@ hipError_t launch_image_rows(const Geom &g, const real *sky, const real *beams, 
     return hipGetLastError();
 }
 
-// Columns per block: as wide as the LDS allows for coalesced row segments, but narrow
+// Columns per block: col_batch's width (wider blocks write longer row segments), but narrow
 // enough that the launch has about two blocks per compute unit.
 template <int LOGN> static int pick_cb(const Geom &g) {
     int cb = col_batch<LOGN>();
