@@ -70,11 +70,12 @@ def test_float_build_reaches_the_host_optimum(c1r):
     dev = DeviceSolver(plan).solve()
     host = solve(plan, maxiter=15000)
     print("device", dev.fun, dev.nit, dev.nfev, dev.message, "host", host.fun, host.nit, host.nfev, host.message)
-    # near the optimum the FP32 objective's rounding can defeat the line search; scipy then
-    # stops with an abnormal line search too, and the two loops must agree on that as well
+    # near the optimum the FP32 objective's rounding decides whether a line search still
+    # finds a decrease, so either loop may stop on an abnormal line search or on its
+    # relative-reduction test (which of the two depends on the summation order of the
+    # objective); both must have stopped at the same objective value
     assert dev.message in ("pgtol", "ftol", "abnormal")
-    if dev.message == "abnormal":
-        assert host.message.upper().startswith("ABNORMAL")
+    assert host.message.upper().startswith(("ABNORMAL", "CONVERGENCE"))
     assert dev.fun == pytest.approx(host.fun, rel=1e-6)
     assert float(dev.x.min()) >= 0.0
 
