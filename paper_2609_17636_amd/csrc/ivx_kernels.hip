@@ -705,12 +705,12 @@ __device__ __forceinline__ float row_sum4(float x) {
 }
 
 // KW > 0 fixes the kernel width at compile time (the footprint loops unroll without
-// per-lane width tests); KW = 0 reads it from the geometry.
-template <int MODE, int KW>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_gridmx(GridArgs a) {
+// per-lane width tests); KW = 0 reads it from the geometry.  OCC is the occupancy the
+// register allocation aims for: 7 waves per SIMD (72 VGPRs) pays on launches of many work
+// items, 6 (a freer schedule) on launches that fill the chip about once.
+template <int MODE, int KW, int OCC>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_gridmx(GridArgs a) {
     __shared__ float PX[16 * MX_LD], PY[16 * MX_LD];
-    __shared__ float ZX[16], ZY[16];
-    __shared__ int IX[16], IY[16];
     __shared__ float WRr[16], WRi[16];
     const int64_t wid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     if (wid >= a.n_work) return;
@@ -749,15 +749,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     // records of a batch (lanes 0-15); two sets rotate so that the next batch's records are
     // in flight while the current batch is processed, with no register copies
     struct MxRec {
-        VisCoord c;
-        cpx y;
+        VisCoord c; // coordinates of visibility l / 4 of the batch (every lane)
+        cpx y;      // data, weight, caller index of visibility l (lanes 0-15)
         float w;
         int p;
     };
     auto fetch = [&](MxRec &r, int v0) {
-        const int vi = v0 + c16;
+        const int vi = v0 + c16, vw = v0 + (l >> 2);
+        if (vw < n) r.c = crd[vw];
         if (l < 16 && vi < n) {
-            r.c = crd[vi];
             if (MODE == MODE_OBJ) { r.y = vis[vi]; r.w = wgt[vi]; }
             if (MODE == MODE_ADJ) { r.w = wgt[vi]; r.p = perm[vi]; }
             if (MODE == MODE_FWD) r.p = perm[vi];
@@ -765,24 +765,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     };
     auto batch = [&](const MxRec &r, int v0) {
         const bool ok = l < 16 && v0 + c16 < n;
-        if (l < 16) {
-            int ix, iy;
-            real fx, fy;
-            decode(r.c, ix, iy, fx, fy);
-            ZX[l] = zoff + fx;
-            ZY[l] = zoff + fy;
-            IX[l] = ok ? ix : -64; // no footprint: every weight of the row is zero
-            IY[l] = ok ? iy : -64;
-            if (MODE == MODE_ADJ) {
-                float yr = 0.f, yi = 0.f;
-                if (ok) {
-                    const cpx y = caller_in[r.p < 0 ? ~r.p : r.p];
-                    yr = r.w * y.re;
-                    yi = r.w * (r.p < 0 ? -y.im : y.im);
-                }
-                WRr[l] = yr;
-                WRi[l] = yi;
+        if (MODE == MODE_ADJ && l < 16) {
+            float yr = 0.f, yi = 0.f;
+            if (ok) {
+                const cpx y = caller_in[r.p < 0 ? ~r.p : r.p];
+                yr = r.w * y.re;
+                yi = r.w * (r.p < 0 ? -y.im : y.im);
             }
+            WRr[l] = yr;
+            WRi[l] = yi;
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -792,11 +783,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
         }
         wave_sync();
         {
-            // the W nonzero weights per visibility and axis: lane (m = l / 4, k = l % 4 + 4 j)
+            // the W nonzero weights per visibility and axis: lane (m = l / 4, k = l % 4 + 4 j),
+            // from the coordinates each lane decoded itself (no hand-off through LDS)
             const int m = l >> 2;
-            const int ixm = IX[m], iym = IY[m];
-            const float zxm = ZX[m], zym = ZY[m];
-            if (ixm >= 0) {
+            if (v0 + m < n) {
+                int ixm, iym;
+                real fx, fy;
+                decode(r.c, ixm, iym, fx, fy);
+                const float zxm = zoff + fx, zym = zoff + fy;
 #pragma unroll
                 for (int j = 0; j < (KW > 0 ? (KW + 3) / 4 : 4); ++j) {
                     const int k = (l & 3) + 4 * j;
@@ -1515,12 +1509,21 @@ hipError_t prepare_grid(const Geom &g, int nwave, int variant) {
 }
 
 #ifndef IVX_REAL_DOUBLE
-template <int KW> void launch_gridmx(int mode, dim3 grid, const GridArgs &a, hipStream_t st) {
+template <int KW, int OCC> void launch_gridmx_occ(int mode, dim3 grid, const GridArgs &a, hipStream_t st) {
     switch (mode) {
-    case MODE_OBJ: k_gridmx<MODE_OBJ, KW><<<grid, 64, 0, st>>>(a); break;
-    case MODE_FWD: k_gridmx<MODE_FWD, KW><<<grid, 64, 0, st>>>(a); break;
-    default: k_gridmx<MODE_ADJ, KW><<<grid, 64, 0, st>>>(a); break;
+    case MODE_OBJ: k_gridmx<MODE_OBJ, KW, OCC><<<grid, 64, 0, st>>>(a); break;
+    case MODE_FWD: k_gridmx<MODE_FWD, KW, OCC><<<grid, 64, 0, st>>>(a); break;
+    default: k_gridmx<MODE_ADJ, KW, OCC><<<grid, 64, 0, st>>>(a); break;
     }
+}
+
+// Work items beyond which the 7-waves-per-SIMD build is used (about four rounds of waves
+// on 1,024 SIMDs).
+constexpr int64_t GRIDMX_OCC7_ITEMS = 32768;
+
+template <int KW> void launch_gridmx(int mode, dim3 grid, const GridArgs &a, hipStream_t st) {
+    if (a.n_work >= GRIDMX_OCC7_ITEMS) launch_gridmx_occ<KW, 7>(mode, grid, a, st);
+    else launch_gridmx_occ<KW, 6>(mode, grid, a, st);
 }
 #endif
 
