@@ -154,6 +154,20 @@ constexpr int COL_LOADS = 8;
 
 // Columns per block of a column pass: at most 32 KB of LDS columns, so that four blocks share
 // a compute unit (at 1024-point columns 4 per block measured faster than 8 and 2).
+// Work index of a column-pass block.  Blocks are dealt to the eight XCDs round-robin by
+// launch index; block b takes work index (b % 8) * per + b / 8 of the (item, column group)
+// pairs, so each XCD runs one contiguous range of them and neighbouring column groups, which
+// share the cache lines of their row segments, meet in the same L2.  The launch has
+// 8 * per blocks; false for the padding blocks past the last pair.
+template <int CB> __device__ __forceinline__ bool col_block(const Geom &g, int &item, int &c0) {
+    const int64_t ngrp = (g.rw + CB - 1) / CB, total = ngrp * g.C * g.P, per = (total + 7) / 8;
+    const int64_t b = blockIdx.x, w = (b & 7) * per + (b >> 3);
+    if (w >= total) return false;
+    item = (int)(w / ngrp);
+    c0 = (int)(w - (w / ngrp) * ngrp) * CB;
+    return true;
+}
+
 template <int LOGN> constexpr int col_batch() {
     constexpr int b = 32768 / ((1 << LOGN) * (int)sizeof(cpx));
     return b > 16 ? 16 : (b < 1 ? 1 : b);
@@ -233,8 +247,8 @@ __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ 
     __shared__ int ent_src[MAXE];
     __shared__ int n_ent;
     const int tid = threadIdx.x;
-    const int item = blockIdx.y;
-    const int c0 = blockIdx.x * CB;
+    int item, c0;
+    if (!col_block<CB>(g, item, c0)) return;
     const int nk = g.nk;
     for (int i = tid; i < CB * N; i += NT) buf[i] = cpx{0, 0};
     if (tid == 0) {
@@ -991,8 +1005,8 @@ __global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ 
     TwStage<LOGN> twr;
     twr.fetch(tw);
     const int tid = threadIdx.x;
-    const int item = blockIdx.y;
-    const int c0 = blockIdx.x * CB;
+    int item, c0;
+    if (!col_block<CB>(g, item, c0)) return;
     const cpx *Ei = E + (int64_t)item * g.ext_stride;
     if (g.eh <= 2 * g.nf && g.ew <= g.nf) {
         // every cell has at most two aliases (rows t and t + n_f of one column): the loads of
@@ -1385,6 +1399,13 @@ template <int LOGN> static int pick_cb(const Geom &g) {
     return cb;
 }
 
+// Launch size of a column pass: (item, column group) pairs rounded up to a multiple of 8
+// (see col_block).
+static dim3 col_grid(const Geom &g, int cb) {
+    const int64_t total = (int64_t)((g.rw + cb - 1) / cb) * n_items(g);
+    return dim3((unsigned)(8 * ((total + 7) / 8)));
+}
+
 #define IVX_CB_SWITCH(CBV, ...)                                                   \
     switch (CBV) {                                                                \
     case 1: { constexpr int B = 1; __VA_ARGS__; } break;                          \
@@ -1398,8 +1419,7 @@ hipError_t launch_col_fwd(const Geom &g, const cpx *R, const cpx *tw, cpx *ext, 
     IVX_LOGN_SWITCH(g.logn, {
         const int cb = pick_cb<L>(g);
         IVX_CB_SWITCH(cb, {
-            dim3 grid((g.rw + B - 1) / B, n_items(g));
-            k_col_fwd<L, B><<<grid, NT, 0, st>>>(g, R, tw, ext);
+            k_col_fwd<L, B><<<col_grid(g, B), NT, 0, st>>>(g, R, tw, ext);
         });
     });
     return hipGetLastError();
@@ -1409,8 +1429,7 @@ hipError_t launch_col_inv(const Geom &g, const cpx *E, const cpx *tw, cpx *R, hi
     IVX_LOGN_SWITCH(g.logn, {
         const int cb = pick_cb<L>(g);
         IVX_CB_SWITCH(cb, {
-            dim3 grid((g.rw + B - 1) / B, n_items(g));
-            k_col_inv<L, B><<<grid, NT, 0, st>>>(g, E, tw, R);
+            k_col_inv<L, B><<<col_grid(g, B), NT, 0, st>>>(g, E, tw, R);
         });
     });
     return hipGetLastError();
