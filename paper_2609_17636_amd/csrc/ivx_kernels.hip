@@ -1215,8 +1215,16 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
     __shared__ double red[NT / 64];
     const Geom &g = a.g;
     const int N = g.N;
-    const int c = blockIdx.z;
-    const int i0 = blockIdx.y * SKY_T, j0 = blockIdx.x * SKY_T;
+    // XCD-aware block order (as col_block): each XCD takes a contiguous band of (channel,
+    // tile row, tile column) triples, so neighbouring tiles, whose CSR entries gather from the
+    // same lines of g', share an L2
+    const int nb = (N + SKY_T - 1) / SKY_T;
+    const int64_t total = (int64_t)nb * nb * g.C, per = (total + 7) / 8;
+    const int64_t bw = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (bw >= total) return;
+    const int bx = (int)(bw % nb), by = (int)((bw / nb) % nb);
+    const int c = (int)(bw / ((int64_t)nb * nb));
+    const int i0 = by * SKY_T, j0 = bx * SKY_T;
     const int tid = threadIdx.x;
     const int ti = tid / SKY_T, tj = tid - (tid / SKY_T) * SKY_T;
     const real *x = a.sky + (int64_t)c * N * N;
@@ -1247,7 +1255,7 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
         const int64_t coff = (int64_t)c * g.nk * g.nk;
         (void)p;
         // this wave's slice: entries lane-contiguous, padded with zero weights
-        const int slice = (blockIdx.y * gridDim.x + blockIdx.x) * (NT / 64) + (tid >> 6);
+        const int slice = (by * nb + bx) * (NT / 64) + (tid >> 6);
         const int e0 = a.cptr[slice], len = (a.cptr[slice + 1] - e0) >> 6;
         const CsrEnt *en = a.cent + e0 + (tid & 63);
         // SKY_LOADS entries, then their SKY_LOADS gathers, are requested before the first is
@@ -1287,7 +1295,7 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
         if (tid == 0) {
             double s = 0.0;
             for (int w = 0; w < NT / 64; ++w) s += red[w];
-            a.rpart[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+            a.rpart[bw] = s;
         }
     }
 }
@@ -1604,7 +1612,8 @@ hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int3
     const int nb = (g.N + SKY_T - 1) / SKY_T;
     SkyArgs a{g, sky, gp, cptr, cent, lambda_r, lambda_s, E, gB, rb, sd_n, stride, offset, grad, rpart,
               adjoint_only ? 1 : 0};
-    k_sky<<<dim3(nb, nb, g.C), NT, 0, st>>>(a);
+    const int64_t total = (int64_t)nb * nb * g.C;
+    k_sky<<<dim3((unsigned)(8 * ((total + 7) / 8))), NT, 0, st>>>(a);
     return hipGetLastError();
 }
 
