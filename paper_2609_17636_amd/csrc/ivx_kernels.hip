@@ -1215,12 +1215,14 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
     __shared__ double red[NT / 64];
     const Geom &g = a.g;
     const int N = g.N;
-    // XCD-aware block order (as col_block): each XCD takes a contiguous band of (channel,
-    // tile row, tile column) triples, so neighbouring tiles, whose CSR entries gather from the
-    // same lines of g', share an L2
+    // XCD-aware block order (as col_block) on cubes: each XCD takes a contiguous band of
+    // (channel, tile row, tile column) triples, so neighbouring tiles, whose CSR entries
+    // gather from the same lines of g', share an L2.  With few channels a band is a strip
+    // of one image whose pointing overlap (and so CSR length) varies, which unbalances the
+    // XCDs: the launch order is kept there.
     const int nb = (N + SKY_T - 1) / SKY_T;
     const int64_t total = (int64_t)nb * nb * g.C, per = (total + 7) / 8;
-    const int64_t bw = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int64_t bw = g.C >= 8 ? (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3) : (int64_t)blockIdx.x;
     if (bw >= total) return;
     const int bx = (int)(bw % nb), by = (int)((bw / nb) % nb);
     const int c = (int)(bw / ((int64_t)nb * nb));
