@@ -7,14 +7,16 @@
 //   k_col_fwd     column FFT of the n_sub non-zero rows, written to an extended grid that
 //                 carries the periodic wrap in rows and the Hermitian mirror in columns,
 //                 so a footprint never needs a modulo;
-//   k_grid        per fine-grid tile: stage the grid window in LDS, interpolate every
-//                 visibility (degridding), form the residual and its weighted square
-//                 (Sect. 2.2, J_k), and spread w * r back into per-wave LDS accumulators
-//                 (no global atomics); the window is written to a private slot.
+//   k_gridmx /    per fine-grid tile: interpolate every visibility from the grid window
+//   k_grid        (degridding), form the residual and its weighted square (Sect. 2.2,
+//                 J_k), and spread w * r back into the window's accumulation (matrix-core
+//                 products in registers, or per-wave LDS accumulators; no global atomics);
+//                 the window is written to a private slot.
 // Adjoint direction (gradient, Sect. 3.4):
-//   k_fold        sum the slots covering each cell and symmetrise H -> (H + conj H(-t))/2,
-//                 which makes the real part of the adjoint a half-spectrum inverse FFT;
-//   k_col_inv     inverse column FFT, keeping the n_sub rows of the sub-image;
+//   k_ext_sum     sum the slots covering each cell of the extended grid (the fold);
+//   k_col_inv     alias sum and symmetrisation H -> (H + conj H(-t))/2 as it loads, which
+//                 makes the real part of the adjoint a half-spectrum inverse FFT; inverse
+//                 column FFT, keeping the n_sub rows of the sub-image;
 //   k_row_inv     inverse row FFT of two rows at once, crop, deapodization x beam x flux;
 //   k_sky         transpose of the bilinear reprojection (gather over a pixel-major CSR,
 //                 fixed order), plus the Laplacian regulariser (Eq. 3) and the single-dish
