@@ -199,6 +199,20 @@ def test_c4_objective_at_zero(c4, c4plan):
     assert abs(terms[0] - (q0 + c4.lambda_s * k0)) <= 1e-6 * terms[0]
 
 
+def test_c4_repeat_is_bitwise(c4, c4plan):
+    """No pass uses atomics and every reduction has a fixed order, so two evaluations of the
+    full cube agree bit for bit (at this size the 7-waves-per-SIMD gridder build and the
+    XCD-ordered column and sky passes run)."""
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    peak = float(np.max(c4.x_true)) if c4.x_true is not None else 1.0
+    x = torch.rand((c4.n_chan, c4.n_sky, c4.n_sky), generator=gen, device="cuda") * peak
+    t1, g1 = c4plan.objective_grad(x)
+    t2, g2 = c4plan.objective_grad(x)
+    print(f"[c4 repeat] Q_tot {t1[0]:.12e} {t2[0]:.12e}", flush=True)
+    assert np.array_equal(t1, t2)
+    assert torch.equal(g1, g2)
+
+
 def test_c4_gradient_at_zero_sampled(c4, c4plan):
     zero = torch.zeros((c4.n_chan, c4.n_sky, c4.n_sky), dtype=torch.float32, device="cuda")
     _, grad = c4plan.objective_grad(zero)
