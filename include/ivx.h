@@ -126,7 +126,9 @@ ivx_status ivx_plan_set_data(ivx_plan *plan, const ivx_real *uv, const ivx_real 
                              const ivx_real *sd_map, void *stream);
 
 /* As ivx_plan_set_data for a spectral cube whose channels share one uv track per
- * pointing (Sect. 2.2: the same baselines observed at every frequency):
+ * pointing (Sect. 2.1, Eq. vis: each channel's model uses the pointing's baselines in
+ * wavelengths at that channel's frequency, so one track scaled by nu_c / nu_ref serves
+ * every channel):
  *   uv      [sum_k M_k][2]  pointing k's samples at rows pt_k .. pt_k + M_k - 1 (pointing
  *                           order), in wavelengths at a reference frequency
  *   weight  [sum_k M_k]     natural weights, the same for every channel

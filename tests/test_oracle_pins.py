@@ -128,6 +128,35 @@ def test_adjoint_identity(oracle_mod):
     assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + np.abs(f).sum() * np.abs(c).sum())
 
 
+def test_dft_adjoint_pixels_matches_the_full_adjoint(oracle_mod):
+    """O5 at selected pixels equals the whole-image adjoint at those pixels (corners, the
+    phase centre and random interior pixels of a 16 x 16 grid, uv beyond Nyquist)."""
+    rng = np.random.default_rng(16)
+    n, delta = 16, 8 * synth.ARCSEC
+    uv = _rand_uv(rng, 50, delta)
+    c = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+    full = oracle_mod.dft_adjoint(c, uv, delta, n)
+    pix = np.array([[0, 0], [0, n - 1], [n - 1, 0], [n - 1, n - 1], [n // 2, n // 2], [3, 11], [11, 3]]
+                   + [list(rng.integers(0, n, 2)) for _ in range(9)])
+    got = oracle_mod.dft_adjoint_pixels(c, uv, delta, n, pix)
+    np.testing.assert_allclose(got, full[pix[:, 0], pix[:, 1]], rtol=0, atol=1e-12)
+
+
+def test_dft_adjoint_pixels_brute_force_tiny(oracle_mod):
+    """Every pixel of a 4 x 4 sub-image from pure-Python exponentials of the full phase
+    (row index a pairs with v, column index b with u; sign +)."""
+    n, delta = 4, 12 * synth.ARCSEC
+    uv = np.array([[1234.5, -987.25], [-40000.0, 51234.0], [0.0, 77.0]])
+    coef = np.array([0.3 - 1.1j, 2.0 + 0.5j, -0.7 + 0.25j])
+    pix = np.array([[a, b] for a in range(n) for b in range(n)])
+    want = []
+    for a, b in pix:
+        l, m = (b - n / 2) * delta, (a - n / 2) * delta
+        want.append(sum((cc * cmath.exp(2j * math.pi * (u * l + v * m))).real for cc, (u, v) in zip(coef, uv)))
+    got = oracle_mod.dft_adjoint_pixels(coef, uv, delta, n, pix)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+
+
 # ----------------------------------------------------------------------------- O1 / O6
 
 def test_reproject_integer_translation_is_crop(oracle_mod):
@@ -248,6 +277,22 @@ def test_sd_adjoint_identity(oracle_mod):
     assert abs(lhs - rhs) < 1e-12 * np.abs(x).sum()
 
 
+def test_sd_term_at_zero_sky_closed_form(oracle_mod):
+    """K(0) = 1/2 sum T^2 / sigma_sd^2 and grad K(0) = -B^T S^T T / sigma_sd^2 (Sect. 2.4):
+    the absolute scale of the fusion term, which a finite-difference test alone leaves free
+    (a sigma vs sigma^2 slip in both K and its gradient would pass one)."""
+    rng = np.random.default_rng(17)
+    G, *_ = _sd_geom()
+    t_map = rng.uniform(0.0, 5.0, size=(8, 8))
+    for sigma in (0.37, 2.0):
+        K, g = oracle_mod.sd_term(np.zeros((128, 128)), t_map, sigma, G)
+        assert K == pytest.approx(0.5 * float(np.sum(t_map ** 2)) / sigma ** 2, rel=1e-14)
+        # the gradient at zero pairs with the delta response: <e_ij, grad> = -sum T g g / s^2
+        i, j = 40, 70
+        want = -sum(t_map[p, q] * G[p, i] * G[q, j] for p in range(8) for q in range(8)) / sigma ** 2
+        assert g[i, j] == pytest.approx(want, rel=1e-12, abs=1e-18)
+
+
 # ----------------------------------------------------------------------------- O4 / O9
 
 @pytest.fixture(scope="module")
@@ -255,6 +300,33 @@ def mini(oracle_mod):
     p = synth.config_c3_mini()
     oracle_mod.synthesize(p)
     return p
+
+
+def test_adjoint_image_is_the_transpose_of_model_vis(oracle_mod, mini):
+    """Re <model_vis(x), W v> = <x, adjoint_image(v)> over every pointing and channel of the
+    overlapping mini mosaic (flagged entries carry garbage and must be skipped by both)."""
+    rng = np.random.default_rng(18)
+    x = rng.uniform(0, 50, size=mini.x_true.shape)
+    v = rng.standard_normal(mini.n_vis) + 1j * rng.standard_normal(mini.n_vis)
+    v[mini.flags == 1] = 1e30
+    mv = oracle_mod.model_vis(mini, x)
+    live = mini.flags == 0
+    lhs = float(np.sum((np.conj(mv) * mini.weight * v)[live]).real)
+    rhs = float(np.sum(x * oracle_mod.adjoint_image(mini, v)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_adjoint_image_of_the_data_is_minus_the_gradient_at_zero(oracle_mod, mini):
+    """adjoint_image(y) = -grad Q(0) with lambda_r = lambda_s = 0 (Sect. 2.2: at x = 0 the
+    residual is -y), the relation the dirty mosaic and the adjoint parity tests rely on."""
+    import copy
+
+    q = copy.copy(mini)
+    q.lambda_r = q.lambda_s = 0.0
+    _, g0 = oracle_mod.objective_grad(q, np.zeros_like(q.x_true))
+    d = oracle_mod.adjoint_image(q, q.vis)
+    np.testing.assert_allclose(d, -g0, rtol=0, atol=1e-12 * np.abs(g0).max())
+
 
 
 def test_data_term_at_zero_sky(oracle_mod, mini):

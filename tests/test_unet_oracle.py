@@ -71,6 +71,22 @@ def test_pool_and_up_adjoints():
     assert g[0, 0, 0, 0] == 1 and g.sum() == 1
 
 
+def test_maxpool2_forward_values_explicit_loop():
+    """Forward values of the 2 x 2 max pool against an explicit loop over every window
+    (negative values included, so a pool of |x| or a sum would fail)."""
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((2, 6, 8, 3)) - 0.5
+    y = U.maxpool2(x)
+    assert y.shape == (2, 3, 4, 3)
+    for n in range(2):
+        for i in range(3):
+            for j in range(4):
+                for c in range(3):
+                    want = max(x[n, 2 * i, 2 * j, c], x[n, 2 * i, 2 * j + 1, c],
+                               x[n, 2 * i + 1, 2 * j, c], x[n, 2 * i + 1, 2 * j + 1, c])
+                    assert y[n, i, j, c] == want
+
+
 def test_adam_first_step_is_signed_lr():
     p = np.array([1.0, -2.0, 3.0])
     g = np.array([0.5, -4.0, 1e-3])
