@@ -209,6 +209,12 @@ ivx_status ivx_stage_times(ivx_plan *plan, double *ms, int64_t *n_eval);
 ivx_status ivx_set_blocking(ivx_plan *plan, int32_t tile, int32_t waves, int32_t chunk,
                             int32_t lanes, int32_t vpi, void *stream);
 
+/* Register budget of the matrix-core gridder (blockings with 64 lanes per visibility): the
+ * build compiled for 6 or 7 resident waves per SIMD, or 0 (the default) to use 7 from
+ * 32,768 work items up and 6 below.  Results are identical for both builds (same
+ * arithmetic in the same order); only the schedule changes.  IVX_EINVAL otherwise. */
+ivx_status ivx_set_gridder_occupancy(ivx_plan *plan, int32_t waves_per_simd);
+
 /* Plan facts, host array of 16 int64: {n_fine, kernel_width, tile, n_work_items,
  * n_live_vis, n_slots, device_bytes, n_items, ext_rows, ext_cols, graph_nodes,
  * window, waves_per_block, max_vis_per_work_item, lanes_per_visibility,

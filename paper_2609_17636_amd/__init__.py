@@ -47,7 +47,7 @@ class _Problem(ctypes.Structure):
 EXPORTS = ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_forward", "ivx_adjoint",
            "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_last_error", "ivx_version",
            "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking",
-           "ivx_plan_set_vis")
+           "ivx_plan_set_vis", "ivx_set_gridder_occupancy")
 
 STAGES = ("image_rows", "col_fwd", "grid", "fold", "col_inv", "row_inv", "sd", "sky", "final")
 
@@ -77,12 +77,14 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
     lib.ivx_set_graph.argtypes = [vp, ctypes.c_int]
     lib.ivx_set_blocking.argtypes = [vp, i32, i32, i32, i32, i32, vp]
     lib.ivx_plan_set_vis.argtypes = [vp, vp, vp, vp]
+    lib.ivx_set_gridder_occupancy.argtypes = [vp, i32]
     lib.ivx_stage_times.argtypes = [vp, vp, vp]
     lib.ivx_last_error.restype = ctypes.c_char_p
     lib.ivx_last_error.argtypes = []
     for f in ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_forward",
               "ivx_adjoint", "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_set_timing",
-              "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking", "ivx_plan_set_vis"):
+              "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking", "ivx_plan_set_vis",
+              "ivx_set_gridder_occupancy"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ivx_version.restype = ctypes.c_int
     lib.ivx_real_size.restype = ctypes.c_int
@@ -288,6 +290,10 @@ class Plan:
         """Explicit gridding blocking (see ivx_set_blocking); accuracy-neutral."""
         self._check(self.lib.ivx_set_blocking(self._h, int(tile), int(waves), int(chunk), int(lanes), int(vpi),
                                               _stream_ptr(stream)))
+
+    def set_gridder_occupancy(self, waves_per_simd: int):
+        """Matrix-core gridder build: 6 or 7 waves per SIMD, 0 = by work-item count."""
+        self._check(self.lib.ivx_set_gridder_occupancy(self._h, int(waves_per_simd)))
 
     def set_graph(self, enable: bool):
         """Replay objective evaluations from a captured HIP graph (default) or launch eagerly."""

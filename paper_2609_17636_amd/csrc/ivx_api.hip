@@ -118,6 +118,7 @@ struct ivx_plan {
     int lanes = 16;
     int vpi = 2;
     int chunk_max = 256;
+    int occupancy = GRIDMX_OCC_AUTO; // matrix-core gridder register budget (waves per SIMD)
     int tile_fixed = 0;
     std::vector<real> dq_host;
     std::vector<cpx> tw_host;
@@ -671,7 +672,7 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
     {
         StageTimer t(p, st, IVX_STAGE_GRID);
         IVX_HIP(launch_grid(MODE_OBJ, g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff, p->d_ext,
-                            p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, st));
+                            p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, p->occupancy, st));
     }
     {
         StageTimer t(p, st, IVX_STAGE_FOLD);
@@ -866,6 +867,15 @@ ivx_status ivx_set_blocking(ivx_plan *p, int32_t tile, int32_t waves, int32_t ch
         ivx_status s = build_bins(p, (hipStream_t)stream);
         if (s != IVX_OK) return s;
     }
+    return IVX_OK;
+}
+
+ivx_status ivx_set_gridder_occupancy(ivx_plan *p, int32_t waves_per_simd) {
+    if (!p) return fail(IVX_EINVAL, "plan is NULL");
+    if (!(waves_per_simd == 0 || waves_per_simd == 6 || waves_per_simd == 7))
+        return fail(IVX_EINVAL, "waves_per_simd must be 0 (automatic), 6 or 7");
+    p->occupancy = waves_per_simd;
+    drop_graph(p); // the captured launches name the build
     return IVX_OK;
 }
 
@@ -1246,7 +1256,7 @@ ivx_status ivx_forward(ivx_plan *p, const ivx_real *sky, ivx_real *model_vis, vo
     if ((s = run_forward_half(p, sky, st)) != IVX_OK) return s;
     IVX_HIP(launch_zero(model_vis, p->m_total * 2 * (int64_t)sizeof(real), st));
     IVX_HIP(launch_grid(MODE_FWD, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff, p->d_ext,
-                        p->d_slots, p->d_jpart, nullptr, reinterpret_cast<cpx *>(model_vis), p->nwave, p->lanes * 10 + p->vpi, st));
+                        p->d_slots, p->d_jpart, nullptr, reinterpret_cast<cpx *>(model_vis), p->nwave, p->lanes * 10 + p->vpi, p->occupancy, st));
     return IVX_OK;
 }
 
@@ -1256,7 +1266,7 @@ ivx_status ivx_adjoint(ivx_plan *p, const ivx_real *vis, ivx_real *image, void *
     if (!image || (!vis && p->m_total > 0)) return fail(IVX_EINVAL, "vis and image are required");
     hipStream_t st = (hipStream_t)stream;
     IVX_HIP(launch_grid(MODE_ADJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff, p->d_ext,
-                        p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave, p->lanes * 10 + p->vpi, st));
+                        p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave, p->lanes * 10 + p->vpi, p->occupancy, st));
     if ((s = run_adjoint_half(p, st)) != IVX_OK) return s;
     IVX_HIP(launch_sky(p->g, image, p->d_gp, p->d_cptr, p->d_cent, real(0), real(0), nullptr, nullptr, 0, 0, 1, 0,
                        image, p->d_rpart, true, st));
@@ -1315,7 +1325,7 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
             if (r > 0 && (s = run_forward_half(p, sky, st)) != IVX_OK) break;
             IVX_HIP(hipEventRecord(e0, st));
             IVX_HIP(launch_grid(MODE_OBJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff,
-                                p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, st));
+                                p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, p->occupancy, st));
             IVX_HIP(launch_fold(p->g, p->d_tslot, p->d_slots, p->d_ext, st));
             IVX_HIP(hipEventRecord(e1, st));
             IVX_HIP(hipEventSynchronize(e1));

@@ -84,7 +84,7 @@ hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work
                        const VisCoord *crd, const cpx *vis, const real *wgt,
                        const int32_t *perm, const int64_t *boff, const cpx *ext, cpx *slots, double *jpart,
                        const cpx *caller_in, cpx *caller_out, int nwave, int variant,
-                       hipStream_t st);
+                       int occupancy, hipStream_t st);
 // adjoint extended grid: the windows summed into `ext` (the forward extended grid, which
 // the gridding pass has consumed by then)
 hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, hipStream_t st);
@@ -152,6 +152,9 @@ hipError_t sort_pairs(void *temp, size_t &temp_bytes, const uint64_t *kin, uint6
 // per work item): selected by lanes = GRID_MFMA_LANES, variant = GRID_MFMA_VARIANT.
 constexpr int GRID_MFMA_LANES = 64;
 constexpr int GRID_MFMA_VARIANT = 10 * GRID_MFMA_LANES + 1;
+// Register budget of the matrix-core gridder build: waves per SIMD it is compiled for (6 or 7),
+// or 0 to choose by the number of work items.
+constexpr int GRIDMX_OCC_AUTO = 0;
 // Raise the dynamic-LDS limit of the gridding kernels for this geometry (call before any
 // stream capture).
 // variant = 10 * lanes per visibility (8 or 16) + visibilities per group per iteration (1, 2)

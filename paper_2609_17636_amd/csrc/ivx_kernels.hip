@@ -1552,8 +1552,9 @@ template <int KW, int OCC> void launch_gridmx_occ(int mode, dim3 grid, const Gri
 // on 1,024 SIMDs).
 constexpr int64_t GRIDMX_OCC7_ITEMS = 32768;
 
-template <int KW> void launch_gridmx(int mode, dim3 grid, const GridArgs &a, hipStream_t st) {
-    if (a.n_work >= GRIDMX_OCC7_ITEMS) launch_gridmx_occ<KW, 7>(mode, grid, a, st);
+template <int KW> void launch_gridmx(int mode, dim3 grid, const GridArgs &a, int occ, hipStream_t st) {
+    if (occ == GRIDMX_OCC_AUTO) occ = a.n_work >= GRIDMX_OCC7_ITEMS ? 7 : 6;
+    if (occ == 7) launch_gridmx_occ<KW, 7>(mode, grid, a, st);
     else launch_gridmx_occ<KW, 6>(mode, grid, a, st);
 }
 #endif
@@ -1561,7 +1562,8 @@ template <int KW> void launch_gridmx(int mode, dim3 grid, const GridArgs &a, hip
 hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
                        const cpx *vis, const real *wgt, const int32_t *perm, const int64_t *boff, const cpx *ext,
                        cpx *slots, double *jpart, const cpx *caller_in, cpx *caller_out, int nwave, int variant,
-                       hipStream_t st) {
+                       int occupancy, hipStream_t st) {
+    if (!(occupancy == GRIDMX_OCC_AUTO || occupancy == 6 || occupancy == 7)) return hipErrorInvalidValue;
     if (n_work <= 0) return hipSuccess;
     if (nwave < 1 || nwave > NT / 64) return hipErrorInvalidValue;
     GridArgs a{g, work, crd, vis, wgt, perm, boff, ext, slots, jpart, caller_in, caller_out, nwave, n_work};
@@ -1573,9 +1575,9 @@ hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work
         const unsigned gx = (unsigned)n_work < GRID_ROW ? (unsigned)n_work : GRID_ROW;
         const dim3 grid(gx, (unsigned)((n_work + gx - 1) / gx));
         switch (g.W) {
-        case 7: launch_gridmx<7>(mode, grid, a, st); break;
-        case 8: launch_gridmx<8>(mode, grid, a, st); break;
-        default: launch_gridmx<0>(mode, grid, a, st); break;
+        case 7: launch_gridmx<7>(mode, grid, a, occupancy, st); break;
+        case 8: launch_gridmx<8>(mode, grid, a, occupancy, st); break;
+        default: launch_gridmx<0>(mode, grid, a, occupancy, st); break;
         }
         return hipGetLastError();
 #endif

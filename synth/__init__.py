@@ -465,6 +465,22 @@ class CubeProblem:
     def weight_of(self, k: int) -> np.ndarray:
         return self.weight[int(self.pt_offsets[k]):int(self.pt_offsets[k + 1])]
 
+    def block_problem(self, k: int, c: int, x: Optional[np.ndarray] = None) -> Problem:
+        """One (pointing, channel) block as a one-pointing, one-channel Problem with channel
+        c's sky (x[c], or x_true[c]) and single-dish map."""
+        s = self.block(k, c)
+        xs = self.x_true if x is None else x
+        xc = np.zeros((1, self.n_sky, self.n_sky)) if xs is None else np.asarray(xs[c:c + 1], dtype=np.float64)
+        return Problem(
+            name=f"{self.name}-k{k}-c{c}", n_chan=1, n_sky=self.n_sky, pixel_rad=self.pixel_rad, n_point=1,
+            n_sub=self.n_sub, flux_scale=self.flux_scale[c:c + 1], lambda_r=self.lambda_r, lambda_s=self.lambda_s,
+            uv=self.uv_of(k, c), vis_offsets=np.array([0, s.stop - s.start], dtype=np.int64),
+            weight=self.weight_of(k), flags=self.flags[s], beams=self.beams[k:k + 1], interp=self.interp[k:k + 1],
+            x_true=xc, noise=np.zeros(0), noise_rule=("abs", 1.0), sd_n=self.sd_n, sd_stride=self.sd_stride,
+            sd_offset=self.sd_offset, sd_fwhm_rad=self.sd_fwhm_rad, sd_sigma=self.sd_sigma,
+            sd_map=None if self.sd_map is None else self.sd_map[c:c + 1], sd_noise_frac=self.sd_noise_frac,
+            vis=self.vis[s], meta=dict(self.meta))
+
     def expand(self) -> Problem:
         """The same data as a per-block Problem (FP64 uv per block); small cubes only."""
         uv = np.concatenate([self.uv_of(k, c) for k in range(self.n_point) for c in range(self.n_chan)])

@@ -115,3 +115,29 @@ def test_c3_adjoint_identity(c3, plan):
     lhs = float(np.sum(Ax * v))
     rhs = float(np.sum(x * AHv))
     assert abs(lhs - rhs) <= 1e-4 * np.sqrt(np.sum(Ax ** 2) * np.sum(v.astype(np.float64) ** 2))
+
+
+def _quadratic_identity(plan, x, label):
+    """Q_tot is quadratic in x, so Q(x) - Q(0) = 1/2 <x, G(x) + G(0)> exactly, whatever the
+    data: a property of the objective mode at a non-zero sky that holds at any size.  With
+    Q(0) and G(0) pinned against the oracle and the forward pinned on sampled visibilities,
+    a degrid that disagreed with its spread would break it."""
+    zero = torch.zeros_like(x)
+    t0, g0 = plan.objective_grad(zero)
+    g0 = g0.double()
+    t1, g1 = plan.objective_grad(x)
+    xd = x.double()
+    lhs = t1[0] - t0[0]
+    rhs = 0.5 * float(torch.sum(xd * (g1.double() + g0)).item())
+    print(f"[{label} quadratic identity] Q(x)-Q(0) {lhs:.9e} vs 1/2<x,G(x)+G(0)> {rhs:.9e} "
+          f"rel {abs(lhs - rhs) / (abs(t1[0]) + abs(t0[0])):.2e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-5 * (abs(t1[0]) + abs(t0[0]))
+
+
+def test_c3_objective_mode_at_a_nonzero_sky(c3, plan):
+    """The autotuned mosaic launch (7-waves-per-SIMD build above 32,768 work items) at a
+    uniform 0-50 K sky."""
+    assert plan.info()["n_work_items"] >= 32768
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    x = torch.rand((c3.n_chan, c3.n_sky, c3.n_sky), generator=gen, device="cuda") * 50.0
+    _quadratic_identity(plan, x, "c3")

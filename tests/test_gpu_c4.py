@@ -16,6 +16,7 @@ import time
 import numpy as np
 import pytest
 
+import bench
 import oracle
 import synth
 
@@ -162,7 +163,7 @@ def c4plan(c4):
     t0 = time.perf_counter()
     plan = Plan.from_problem(c4, tile=10)
     plan.set_cube_data(c4)
-    plan.set_blocking(10, 1, 512, 64, 1)  # the benchmark's blocking for the cube
+    plan.set_blocking(*[int(v) for v in bench.CUBE_BLOCKING.split(",")])  # the benchmark's blocking
     torch.cuda.synchronize()
     info = plan.info()
     print(f"[c4] plan in {time.perf_counter() - t0:.1f} s: {info}", flush=True)
@@ -264,3 +265,28 @@ def test_c4_forward_sampled(c4, c4plan):
     del out
     print(f"[c4 forward sampled] rel {max(errs):.2e}", flush=True)
     assert max(errs) <= 1e-5
+
+
+def _quadratic_identity(plan, x, label):
+    """Q_tot is quadratic in x, so Q(x) - Q(0) = 1/2 <x, G(x) + G(0)> exactly, whatever the
+    data: a property of the objective mode at a non-zero sky that holds at any size.  With
+    Q(0) and G(0) pinned against the oracle and the forward pinned on sampled visibilities,
+    a degrid that disagreed with its spread would break it."""
+    zero = torch.zeros_like(x)
+    t0, g0 = plan.objective_grad(zero)
+    g0 = g0.double()
+    t1, g1 = plan.objective_grad(x)
+    xd = x.double()
+    lhs = t1[0] - t0[0]
+    rhs = 0.5 * float(torch.sum(xd * (g1.double() + g0)).item())
+    print(f"[{label} quadratic identity] Q(x)-Q(0) {lhs:.9e} vs 1/2<x,G(x)+G(0)> {rhs:.9e} "
+          f"rel {abs(lhs - rhs) / (abs(t1[0]) + abs(t0[0])):.2e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-5 * (abs(t1[0]) + abs(t0[0]))
+
+
+def test_c4_objective_mode_at_a_nonzero_sky(c4, c4plan):
+    """The benchmark's cube launch (every work item in one launch, 7-waves-per-SIMD
+    gridder build) at a uniform 0-50 K sky."""
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    x = torch.rand((c4.n_chan, c4.n_sky, c4.n_sky), generator=gen, device="cuda") * 50.0
+    _quadratic_identity(c4plan, x, "c4")

@@ -9,6 +9,7 @@ Tolerance: relative 1e-5 (FP32 build) and 1e-10 (FP64 build) on Q_tot, on the gr
 import numpy as np
 import pytest
 
+import bench
 import oracle
 import synth
 
@@ -210,8 +211,50 @@ def test_adjoint_of_matrix_core_gridder(mini, blocking):
     assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.sum(w * (Ax ** 2).sum(axis=1)) * np.sum(w * (v ** 2).sum(axis=1)))
 
 
-def test_objective_c2_subsampled(c2_sub):
-    _check_objective(c2_sub, "f32", "c2-sub")
+@pytest.mark.parametrize("blocking", [None, bench.SINGLE_BLOCKING])
+def test_objective_c2_subsampled(c2_sub, blocking):
+    """The 512^2 single-pointing geometry on 25,200 visibilities, with the default blocking
+    (vector gridder) and with the benchmark's matrix-core blocking."""
+    kw = {}
+    if blocking is not None:
+        t = [int(v) for v in blocking.split(",")]
+        plan = _plan(c2_sub, "f32")
+        plan.set_blocking(*t)
+        tol = TOL["f32"]
+        for name, x in _points(c2_sub).items():
+            want_t, want_g = oracle.objective_grad(c2_sub, x)
+            terms, grad = _eval(plan, x)
+            rq = abs(terms[0] - want_t["Q_tot"]) / want_t["Q_tot"]
+            print(f"[c2-sub {blocking}] x={name} relQ {rq:.2e} relG {rel(grad, want_g):.2e}", flush=True)
+            assert rq <= tol
+            if name != "true":
+                assert rel(grad, want_g) <= tol
+        return
+    _check_objective(c2_sub, "f32", "c2-sub", **kw)
+
+
+@pytest.mark.parametrize("width", [6, 7, 8])
+@pytest.mark.parametrize("occupancy", [6, 7])
+def test_matrix_core_gridder_widths_and_builds(mini, width, occupancy):
+    """Both register budgets of the matrix-core gridder (the 7-waves-per-SIMD build runs on
+    every large launch) and the kernel widths it is compiled for, plus the run-time width
+    path, on the overlapping mini mosaic: objective, gradient and model visibilities
+    element by element.  The largest tile that keeps the window within 16 x 16 and short
+    chunks give several work items per tile."""
+    plan = _plan(mini, "f32", kernel_width=width)
+    plan.set_blocking(17 - width, 1, 32, 64, 1)
+    plan.set_gridder_occupancy(occupancy)
+    x = _points(mini)["rand"]
+    want_t, want_g = oracle.objective_grad(mini, x)
+    terms, grad = _eval(plan, x)
+    rq = abs(terms[0] - want_t["Q_tot"]) / want_t["Q_tot"]
+    print(f"[mini W={width} occ={occupancy}] relQ {rq:.2e} relG {rel(grad, want_g):.2e}", flush=True)
+    assert rq <= TOL["f32"]
+    assert rel(grad, want_g) <= TOL["f32"]
+    v = plan.forward(torch.tensor(x, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    mv = oracle.model_vis(mini, x)
+    live = mini.flags == 0
+    assert rel(v[live, 0] + 1j * v[live, 1], mv[live]) <= TOL["f32"]
 
 
 def test_objective_empty_and_uneven_blocks():
@@ -298,3 +341,47 @@ def test_c2_full_adjoint_identity(c2_full):
     lhs = np.sum(Ax * v)
     rhs = np.sum(x * AHv)
     assert abs(lhs - rhs) <= 1e-4 * np.sqrt(np.sum(Ax ** 2) * np.sum(v ** 2.0))
+
+
+# ------------------------------------------ the benchmark's single-pointing configuration
+
+@pytest.fixture(scope="module")
+def c2_bench():
+    """Full 512^2 / 630,000-visibility single-pointing problem with oracle model data plus
+    1% noise (the same generator and seed as the benchmark's single-pointing workload)."""
+    return oracle.synthesize(synth.config_c2())
+
+
+def test_c2_full_bench_configuration_against_the_oracle(c2_bench):
+    """The single-pointing benchmark's launch configuration (matrix-core blocking, captured
+    graph replayed) against the full FP64 oracle evaluation: Q_tot, Q and R within 1e-5
+    relative and the whole gradient within 1e-5 relative in 2-norm, at the benchmark's
+    sky (uniform 0-50 K) and at the true sky (there against max(|G(x)|, |G(0)|), the
+    near-converged criterion, with G(0) = -adjoint_image(y) since the regulariser's
+    gradient vanishes at zero)."""
+    p = c2_bench
+    plan = _plan(p, "f32")
+    plan.set_blocking(*[int(v) for v in bench.SINGLE_BLOCKING.split(",")])
+    rng = np.random.default_rng(0)
+    x_bench = rng.uniform(0, 50, size=p.x_true.shape)
+    g0norm = np.linalg.norm(oracle.adjoint_image(p, p.vis))
+    for name, x in (("bench", x_bench), ("true", p.x_true)):
+        want_t, want_g = oracle.objective_grad(p, x)
+        sky = torch.tensor(x, dtype=torch.float32, device="cuda")
+        grad = torch.empty_like(sky)
+        t1, _ = plan.objective_grad(sky, grad=grad)
+        g1 = grad.double().cpu().numpy()
+        t2, _ = plan.objective_grad(sky, grad=grad)  # graph replay
+        assert np.array_equal(t1, t2) and np.array_equal(g1, grad.double().cpu().numpy())
+        assert plan.info()["graph_nodes"] > 0
+        rq = abs(t1[0] - want_t["Q_tot"]) / want_t["Q_tot"]
+        eg = rel(g1, want_g)
+        print(f"[c2-full bench {name}] relQ {rq:.2e} relR {abs(t1[3] - want_t['R']) / want_t['R']:.2e} "
+              f"relG {eg:.2e} |dG|/|G(0)| {np.linalg.norm(g1 - want_g) / g0norm:.2e}", flush=True)
+        assert rq <= TOL["f32"]
+        assert abs(t1[1] - want_t["Q"]) <= TOL["f32"] * want_t["Q_tot"]
+        assert abs(t1[3] - want_t["R"]) <= TOL["f32"] * want_t["R"]
+        if name == "true":
+            assert np.linalg.norm(g1 - want_g) <= TOL["f32"] * max(np.linalg.norm(want_g), g0norm)
+        else:
+            assert eg <= TOL["f32"]
