@@ -131,3 +131,28 @@ def test_shared_uv_arguments_are_checked_before_any_device_call():
     with pytest.raises(IvxError) as e:
         plan2.set_data_shared(uv, w, [1.0, 1.01], vis, beams, interp)
     assert e.value.code == -1 and "same visibility count" in str(e.value)
+
+
+def test_noalloc_weight_gradient_rejects_shapes_beyond_its_scratch():
+    """The allocation-free weight gradient refuses, before any device work, a shape whose
+    split partials exceed its static array (CPU: the check precedes every HIP call)."""
+    import ctypes
+
+    import paper_2609_17636_amd as ivx
+
+    lib = ivx.load_library("f32")
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    f = lib.ivx_nn_conv3x3_grad_weight_noalloc
+    f.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp]
+    f.restype = ctypes.c_int
+    lib.ivx_nn_conv3x3_grad_weight_noalloc_capacity.restype = ctypes.c_int64
+    lib.ivx_nn_conv3x3_grad_weight_scratch_floats.argtypes = [i32] * 5
+    lib.ivx_nn_conv3x3_grad_weight_scratch_floats.restype = ctypes.c_int64
+    cap = lib.ivx_nn_conv3x3_grad_weight_noalloc_capacity()
+    shape = (1, 64, 64, 256, 256)
+    assert lib.ivx_nn_conv3x3_grad_weight_scratch_floats(*shape) > cap
+    code = f(ctypes.c_void_p(16), ctypes.c_void_p(16), *shape, ctypes.c_void_p(16), ctypes.c_void_p(16), None)
+    assert code == -1
+    msg = lib.ivx_last_error().decode()
+    assert "static scratch" in msg and str(cap) in msg
+    assert f(None, None, *shape, None, None, None) == -1
