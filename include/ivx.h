@@ -215,6 +215,14 @@ ivx_status ivx_set_blocking(ivx_plan *plan, int32_t tile, int32_t waves, int32_t
  * arithmetic in the same order); only the schedule changes.  IVX_EINVAL otherwise. */
 ivx_status ivx_set_gridder_occupancy(ivx_plan *plan, int32_t waves_per_simd);
 
+/* Adjoint of the gridding stage: the per-tile windows are either summed straight into the
+ * inverse column FFT (one kernel; IVX_STAGE_FOLD then takes no time) or written to the
+ * extended grid by the fold and read back by the column pass.  enable = 1 (the default) fuses
+ * where the fine grid allows it and the plan has enough (pointing, channel) blocks for the
+ * fused launch to be faster (mosaics, cubes); 2 fuses wherever the grid allows; 0 never.
+ * Results are identical (the same sums in the same order).  IVX_EINVAL otherwise. */
+ivx_status ivx_set_fused_fold(ivx_plan *plan, int enable);
+
 /* Plan facts, host array of 16 int64: {n_fine, kernel_width, tile, n_work_items,
  * n_live_vis, n_slots, device_bytes, n_items, ext_rows, ext_cols, graph_nodes,
  * window, waves_per_block, max_vis_per_work_item, lanes_per_visibility,

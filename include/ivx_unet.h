@@ -67,6 +67,24 @@ ivx_status ivx_nn_conv3x3(const float *x, int32_t n, int32_t h, int32_t w, int32
 ivx_status ivx_nn_conv3x3_grad_weight(const float *x, const float *dy, int32_t n, int32_t h,
                                       int32_t w, int32_t cin, int32_t cout, float *dw, float *db,
                                       void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving or training loops, harnesses that forbid hipMalloc): the same weight and bias
+ * gradient as ivx_nn_conv3x3_grad_weight, same arguments and results, with its split
+ * partials in a static device array of ivx_nn_conv3x3_grad_weight_noalloc_capacity()
+ * floats (32 MiB, one copy per device, held until the process ends) instead of a buffer
+ * allocated per call.  It calls no hipMalloc or hipFree and does not synchronise: the
+ * work is queued on `stream`.  IVX_EINVAL (nothing launched) when the shape needs more
+ * partials than the array holds (ivx_nn_conv3x3_grad_weight_scratch_floats gives the
+ * need).  All calls on one device share its array: calls that overlap on one device
+ * (other streams, other threads) race and must be ordered by the caller. */
+ivx_status ivx_nn_conv3x3_grad_weight_noalloc(const float *x, const float *dy, int32_t n,
+                                              int32_t h, int32_t w, int32_t cin, int32_t cout,
+                                              float *dw, float *db, void *stream);
+int64_t ivx_nn_conv3x3_grad_weight_noalloc_capacity(void);
+/* Floats of split partials the weight gradient needs for this shape (-1 if invalid). */
+int64_t ivx_nn_conv3x3_grad_weight_scratch_floats(int32_t n, int32_t h, int32_t w, int32_t cin,
+                                                  int32_t cout);
+
 /* Weights of the transposed correlation: wt[c][a][b][o] = W[o][2-a][2-b][c] (bf16 bits). */
 ivx_status ivx_nn_conv3x3_flip(const uint16_t *weight, int32_t cin, int32_t cout, uint16_t *flipped,
                                void *stream);

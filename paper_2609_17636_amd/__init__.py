@@ -47,7 +47,7 @@ class _Problem(ctypes.Structure):
 EXPORTS = ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_forward", "ivx_adjoint",
            "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_last_error", "ivx_version",
            "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking",
-           "ivx_plan_set_vis", "ivx_set_gridder_occupancy")
+           "ivx_plan_set_vis", "ivx_set_gridder_occupancy", "ivx_set_fused_fold")
 
 STAGES = ("image_rows", "col_fwd", "grid", "fold", "col_inv", "row_inv", "sd", "sky", "final")
 
@@ -78,13 +78,14 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
     lib.ivx_set_blocking.argtypes = [vp, i32, i32, i32, i32, i32, vp]
     lib.ivx_plan_set_vis.argtypes = [vp, vp, vp, vp]
     lib.ivx_set_gridder_occupancy.argtypes = [vp, i32]
+    lib.ivx_set_fused_fold.argtypes = [vp, ctypes.c_int]
     lib.ivx_stage_times.argtypes = [vp, vp, vp]
     lib.ivx_last_error.restype = ctypes.c_char_p
     lib.ivx_last_error.argtypes = []
     for f in ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_forward",
               "ivx_adjoint", "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_set_timing",
               "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking", "ivx_plan_set_vis",
-              "ivx_set_gridder_occupancy"):
+              "ivx_set_gridder_occupancy", "ivx_set_fused_fold"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ivx_version.restype = ctypes.c_int
     lib.ivx_real_size.restype = ctypes.c_int
@@ -294,6 +295,12 @@ class Plan:
     def set_gridder_occupancy(self, waves_per_simd: int):
         """Matrix-core gridder build: 6 or 7 waves per SIMD, 0 = by work-item count."""
         self._check(self.lib.ivx_set_gridder_occupancy(self._h, int(waves_per_simd)))
+
+    def set_fused_fold(self, mode: int):
+        """Sum the gridding windows inside the inverse column pass: 1 where it pays (default),
+        2 wherever the grid allows, 0 never (through the extended grid); results are
+        identical."""
+        self._check(self.lib.ivx_set_fused_fold(self._h, int(mode)))
 
     def set_graph(self, enable: bool):
         """Replay objective evaluations from a captured HIP graph (default) or launch eagerly."""

@@ -119,6 +119,7 @@ struct ivx_plan {
     int vpi = 2;
     int chunk_max = 256;
     int occupancy = GRIDMX_OCC_AUTO; // matrix-core gridder register budget (waves per SIMD)
+    int fused_fold = 1;              // slot fold inside the inverse column pass: 0 never, 1 when it pays, 2 always
     int tile_fixed = 0;
     std::vector<real> dq_host;
     std::vector<cpx> tw_host;
@@ -617,10 +618,28 @@ ivx_status run_forward_half(ivx_plan *p, const real *sky, hipStream_t st) {
     return IVX_OK;
 }
 
+bool use_fused_fold(const ivx_plan *p) {
+    if (!p->fused_fold || !fold_fusable(p->g)) return false;
+    return p->fused_fold == 2 || fold_fusion_pays(p->g);
+}
+
+// Slots -> inverse column FFT output R: one fused kernel, or the fold into the extended grid
+// followed by the column pass.
+ivx_status run_fold_col_inv(ivx_plan *p, hipStream_t st) {
+    const Geom &g = p->g;
+    if (use_fused_fold(p)) {
+        IVX_HIP(launch_col_inv_slots(g, p->d_tslot, p->d_slots, p->d_tw, p->d_R, st));
+    } else {
+        IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, st));
+        IVX_HIP(launch_col_inv(g, p->d_ext, p->d_tw, p->d_R, st));
+    }
+    return IVX_OK;
+}
+
 ivx_status run_adjoint_half(ivx_plan *p, hipStream_t st) {
     const Geom &g = p->g;
-    IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, st));
-    IVX_HIP(launch_col_inv(g, p->d_ext, p->d_tw, p->d_R, st));
+    ivx_status s = run_fold_col_inv(p, st);
+    if (s != IVX_OK) return s;
     IVX_HIP(launch_row_inv(g, p->d_R, p->d_beams, p->d_fscale, p->d_dq, p->d_tw, p->d_gp, st));
     return IVX_OK;
 }
@@ -674,11 +693,14 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
         IVX_HIP(launch_grid(MODE_OBJ, g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff, p->d_ext,
                             p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, p->occupancy, st));
     }
-    {
-        StageTimer t(p, st, IVX_STAGE_FOLD);
-        IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, st));
-    }
-    {
+    if (use_fused_fold(p)) {
+        StageTimer t(p, st, IVX_STAGE_COL_INV); // the fold happens inside this stage
+        IVX_HIP(launch_col_inv_slots(g, p->d_tslot, p->d_slots, p->d_tw, p->d_R, st));
+    } else {
+        {
+            StageTimer t(p, st, IVX_STAGE_FOLD);
+            IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, st));
+        }
         StageTimer t(p, st, IVX_STAGE_COL_INV);
         IVX_HIP(launch_col_inv(g, p->d_ext, p->d_tw, p->d_R, st));
     }
@@ -876,6 +898,14 @@ ivx_status ivx_set_gridder_occupancy(ivx_plan *p, int32_t waves_per_simd) {
         return fail(IVX_EINVAL, "waves_per_simd must be 0 (automatic), 6 or 7");
     p->occupancy = waves_per_simd;
     drop_graph(p); // the captured launches name the build
+    return IVX_OK;
+}
+
+ivx_status ivx_set_fused_fold(ivx_plan *p, int enable) {
+    if (!p) return fail(IVX_EINVAL, "plan is NULL");
+    if (enable < 0 || enable > 2) return fail(IVX_EINVAL, "enable must be 0, 1 or 2");
+    p->fused_fold = enable;
+    drop_graph(p);
     return IVX_OK;
 }
 
@@ -1294,7 +1324,8 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
                     if (tile_fits(p, T, nw, lanes))
                         for (int ch : chunks) cands.push_back(Cand{T, nw, ch, lanes, vpi});
     if (cands.empty()) return fail(IVX_EINVAL, "no tile candidate fits");
-    // the tiling only changes the gridding stage and the slot reduction: time those two on
+    // the tiling only changes the gridding stage and the slot reduction (with the inverse column
+    // pass when the two are fused): time those on
     // the plan's own data (zero sky), keep the fastest; the result is accuracy-neutral
     real *sky = nullptr;
     const int64_t nsky = (int64_t)p->g.C * p->g.N * p->g.N;
@@ -1326,7 +1357,7 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
             IVX_HIP(hipEventRecord(e0, st));
             IVX_HIP(launch_grid(MODE_OBJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff,
                                 p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, p->occupancy, st));
-            IVX_HIP(launch_fold(p->g, p->d_tslot, p->d_slots, p->d_ext, st));
+            if ((s = run_fold_col_inv(p, st)) != IVX_OK) break;
             IVX_HIP(hipEventRecord(e1, st));
             IVX_HIP(hipEventSynchronize(e1));
             IVX_HIP(hipEventElapsedTime(&ms, e0, e1));

@@ -90,6 +90,13 @@ hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work
 hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, hipStream_t st);
 // inverse column FFT of the symmetrised half plane, folded from the adjoint extended grid
 hipError_t launch_col_inv(const Geom &g, const cpx *E, const cpx *tw, cpx *R, hipStream_t st);
+// The slot fold and the inverse column pass in one kernel (no extended grid written); only for
+// grids where fold_fusable(g) holds (every cell has at most two row aliases and one column
+// alias); fold_fusion_pays(g): the launch has enough (item, column group) blocks to be faster.
+bool fold_fusable(const Geom &g);
+bool fold_fusion_pays(const Geom &g);
+hipError_t launch_col_inv_slots(const Geom &g, const int32_t *tslot, const cpx *slots, const cpx *tw, cpx *R,
+                                hipStream_t st);
 hipError_t launch_row_inv(const Geom &g, const cpx *R, const real *beams, const real *fscale,
                           const real *dq, const cpx *tw, real *gp, hipStream_t st);
 hipError_t launch_sd_rows(const Geom &g, const real *sky, const real *gB, int rb, int sd_n,

@@ -27,6 +27,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 namespace ivx {
@@ -731,6 +733,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
     const int64_t wid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     if (wid >= a.n_work) return;
     const WorkItem wi = a.work[wid];
+    if (wi.count <= 0) return; // (the work list holds no empty items)
     const Geom &g = a.g;
     const int l = threadIdx.x, c16 = l & 15, g4 = l >> 4;
     const int W = KW > 0 ? KW : g.W, win = g.win;
@@ -770,14 +773,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
         float w;
         int p;
     };
+    // Every lane loads, at indices clamped to the last record (a batch past the end reloads
+    // it and ignores it): with no per-lane branches around the loads the wait before a batch
+    // covers only that batch's own loads, not the prefetch issued just before it.
     auto fetch = [&](MxRec &r, int v0) {
-        const int vi = v0 + c16, vw = v0 + (l >> 2);
-        if (vw < n) r.c = crd[vw];
-        if (l < 16 && vi < n) {
-            if (MODE == MODE_OBJ) { r.y = vis[vi]; r.w = wgt[vi]; }
-            if (MODE == MODE_ADJ) { r.w = wgt[vi]; r.p = perm[vi]; }
-            if (MODE == MODE_FWD) r.p = perm[vi];
-        }
+        const int vi = min(v0 + c16, n - 1), vw = min(v0 + (l >> 2), n - 1);
+        r.c = crd[vw];
+        if (MODE == MODE_OBJ) { r.y = vis[vi]; r.w = wgt[vi]; }
+        if (MODE == MODE_ADJ) { r.w = wgt[vi]; r.p = perm[vi]; }
+        if (MODE == MODE_FWD) r.p = perm[vi];
     };
     auto batch = [&](const MxRec &r, int v0) {
         const bool ok = l < 16 && v0 + c16 < n;
@@ -862,10 +866,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
     MxRec ra{}, rb{};
     fetch(ra, 0);
     for (int v0 = 0; v0 < n; v0 += 32) {
-        if (v0 + 16 < n) fetch(rb, v0 + 16);
+        fetch(rb, v0 + 16);
         batch(ra, v0);
         if (v0 + 16 >= n) break;
-        if (v0 + 32 < n) fetch(ra, v0 + 32);
+        fetch(ra, v0 + 32);
         batch(rb, v0 + 16);
     }
     if (MODE == MODE_FWD) return;
@@ -1046,6 +1050,195 @@ __global__ __launch_bounds__(NT) void k_col_inv(Geom g, const cpx *__restrict__ 
                 const cpx h = alias_sum(g, Ei, t1, t2);
                 const cpx m = alias_sum(g, Ei, (N - t1) & (N - 1), (N - t2) & (N - 1));
                 v = cpx{real(0.5) * (h.re + m.re), real(0.5) * (h.im - m.im)};
+            }
+            buf[t1 * CB + cc] = v;
+        }
+    }
+    twr.store(tws);
+    __syncthreads();
+    fft_lds<LOGN, CB, true>(buf, tws);
+    cpx *Ri = R + (int64_t)item * g.r_stride;
+    const int nk = g.nk;
+    for (int e = tid; e < nk * CB; e += NT) {
+        const int a = e / CB, cc = e - (e / CB) * CB;
+        if (c0 + cc < g.rw) Ri[(int64_t)a * g.rw + c0 + cc] = buf[((a - nk / 2) & (N - 1)) * CB + cc];
+    }
+}
+
+// ------------------------------------------- adjoint column pass straight from the slots
+// k_ext_sum followed by k_col_inv without the extended grid in between: the block of a column
+// group forms every extended cell its columns need from the slots that cover it (quadrant by
+// quadrant, slot by slot, as k_ext_sum adds them), adds the second row alias and the
+// Hermitian mirror in the order of k_col_inv, and runs the inverse column FFT.  The slot
+// columns of a cell's tile are read by the one block that owns the cell's column, as whole
+// 8-byte-per-row runs, instead of being written to and read back from the extended grid.
+// Valid when every cell has at most two row aliases and one column alias (eh <= 2 n_f,
+// ew <= n_f); the launcher falls back to the two-kernel path otherwise.
+
+// Slot range and in-window offset of quadrant q of extended cell (er, ec): the window of tile
+// (er / T - (q >> 1), ec / T - (q & 1)) covers the cell when the offset stays in the window.
+__device__ __forceinline__ void cell_quadrant(const Geom &g, const int32_t *__restrict__ ts, int er, int ec, int q,
+                                              int &lo, int &cnt, int &off) {
+    const int vy = er / g.T, vx = ec / g.T;
+    const int r = er - vy * g.T, c = ec - vx * g.T;
+    const int ty = vy - (q >> 1), tx = vx - (q & 1);
+    const int lr = r + (q >> 1) * g.T, lc = c + (q & 1) * g.T;
+    lo = 0;
+    cnt = 0;
+    off = lc * g.win + lr;
+    if (ty >= 0 && tx >= 0 && ty < g.nty && tx < g.ntx && lr < g.win && lc < g.win) {
+        lo = ts[ty * g.ntx + tx];
+        cnt = ts[ty * g.ntx + tx + 1] - lo;
+    }
+}
+
+// Extended cell (er, ec) summed from the slots, in k_ext_sum's order (cells outside the
+// extended grid are 0).
+__device__ __forceinline__ cpx ext_cell(const Geom &g, const int32_t *__restrict__ ts, const cpx *__restrict__ slots,
+                                        int er, int ec) {
+    real sr = real(0), si = real(0);
+    if (er >= g.eh || ec >= g.ew) return cpx{sr, si};
+    for (int q = 0; q < 4; ++q) {
+        int lo, cnt, off;
+        cell_quadrant(g, ts, er, ec, q, lo, cnt, off);
+        for (int k = 0; k < cnt; ++k) {
+            const cpx h = slots[(int64_t)(lo + k) * g.win_stride + off];
+            sr += h.re;
+            si += h.im;
+        }
+    }
+    return cpx{sr, si};
+}
+
+// alias_pair + pair_sum of k_col_inv with the cells formed from the slots.
+__device__ __forceinline__ cpx alias_from_slots(const Geom &g, const int32_t *__restrict__ ts,
+                                                const cpx *__restrict__ slots, int t1, int t2) {
+    const int msk = g.nf - 1;
+    const int ec = (t2 + g.O) & msk, er = (t1 + g.O) & msk;
+    real sr = real(0), si = real(0);
+    if (ec < g.ew) {
+        if (er < g.eh) {
+            const cpx a = ext_cell(g, ts, slots, er, ec);
+            sr += a.re;
+            si += a.im;
+        }
+        if (er + g.nf < g.eh) {
+            const cpx b = ext_cell(g, ts, slots, er + g.nf, ec);
+            sr += b.re;
+            si += b.im;
+        }
+    }
+    return cpx{sr, si};
+}
+
+// Cells per thread whose slot loads are in flight together, and columns per block of the fused
+// pass: two and two measured fastest on the spectral cube (four cells per thread, or wider
+// blocks, cost registers or LDS and with them the loads in flight per compute unit).
+#ifndef IVX_FOLD_CELLS
+#define IVX_FOLD_CELLS 2
+#endif
+#ifndef IVX_FOLD_CB
+#define IVX_FOLD_CB 2
+#endif
+constexpr int FOLD_CELLS = IVX_FOLD_CELLS;
+
+template <int LOGN, int CB>
+__global__ __launch_bounds__(NT) void k_col_inv_slots(Geom g, const int32_t *__restrict__ tslot,
+                                                      const cpx *__restrict__ slots, const cpx *__restrict__ tw,
+                                                      cpx *__restrict__ R) {
+    constexpr int N = 1 << LOGN;
+    // tile rows of the grid: (n_f + O) / T + 1 with T >= 4 and O <= 8
+    constexpr int MAXROWS = (N + 8) / 4 + 2;
+    __shared__ cpx buf[CB * N];
+    __shared__ cpx tws[tw_len<LOGN>()];
+    // slot-list prefix of tile columns vxa - 1 .. vxa + 2 in every tile row: the tiles whose
+    // windows reach this block's columns (CB <= T consecutive columns lie in at most two
+    // tile columns)
+    __shared__ int rng[MAXROWS][4];
+    TwStage<LOGN> twr;
+    twr.fetch(tw);
+    const int tid = threadIdx.x;
+    int item, c0;
+    if (!col_block<CB>(g, item, c0)) return;
+    const int32_t *ts = tslot + (int64_t)item * (g.nty * g.ntx + 1);
+    const int msk = N - 1;
+    const int vxa = (c0 + g.O) / g.T;
+    for (int e = tid; e < g.nty * 4; e += NT) {
+        const int ty = e >> 2, tx = vxa - 1 + (e & 3);
+        rng[ty][e & 3] = (tx >= 0 && tx <= g.ntx) ? ts[ty * g.ntx + tx] : 0;
+    }
+    __syncthreads();
+    const float inv_t = 1.0f / (float)g.T;
+    for (int e0 = tid; e0 < N * CB; e0 += FOLD_CELLS * NT) {
+        // the quadrant lists of FOLD_CELLS cells (first row alias) from the LDS table, then
+        // the first slot of every quadrant of every cell requested together, then the sums in
+        // k_ext_sum's order
+        int lo[FOLD_CELLS][4], cnt[FOLD_CELLS][4], off[FOLD_CELLS][4];
+        cpx first[FOLD_CELLS][4];
+#pragma unroll
+        for (int u = 0; u < FOLD_CELLS; ++u) {
+            const int e = e0 + u * NT, cc = e >> LOGN, t1 = e & msk, t2 = c0 + cc;
+            const int er = (t1 + g.O) & msk, ec = (t2 + g.O) & msk;
+            const bool live = e < N * CB && t2 < g.rw && er < g.eh && ec < g.ew;
+            const int vy = (int)(((float)er + 0.5f) * inv_t), vx = (int)(((float)ec + 0.5f) * inv_t);
+            const int r = er - vy * g.T, c = ec - vx * g.T;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ty = vy - (q >> 1), tx = vx - (q & 1);
+                const int lr = r + (q >> 1) * g.T, lc = c + (q & 1) * g.T;
+                const int j = tx - (vxa - 1);
+                lo[u][q] = 0;
+                cnt[u][q] = 0;
+                off[u][q] = lc * g.win + lr;
+                if (live && ty >= 0 && tx >= 0 && ty < g.nty && tx < g.ntx && lr < g.win && lc < g.win) {
+                    lo[u][q] = rng[ty][j];
+                    cnt[u][q] = rng[ty][j + 1] - lo[u][q];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < FOLD_CELLS; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                first[u][q] = cnt[u][q] > 0 ? slots[(int64_t)lo[u][q] * g.win_stride + off[u][q]] : cpx{0, 0};
+#pragma unroll
+        for (int u = 0; u < FOLD_CELLS; ++u) {
+            const int e = e0 + u * NT, cc = e >> LOGN, t1 = e & msk, t2 = c0 + cc;
+            if (e >= N * CB) break;
+            cpx v = cpx{0, 0};
+            if (t2 < g.rw) {
+                // extended cell of the first row alias
+                real ar = real(0), ai = real(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (cnt[u][q] > 0) {
+                        ar += first[u][q].re;
+                        ai += first[u][q].im;
+                        for (int k = 1; k < cnt[u][q]; ++k) {
+                            const cpx h = slots[(int64_t)(lo[u][q] + k) * g.win_stride + off[u][q]];
+                            ar += h.re;
+                            ai += h.im;
+                        }
+                    }
+                }
+                // pair_sum: the first alias (present when inside the grid), then the second
+                const int er = (t1 + g.O) & msk, ec = (t2 + g.O) & msk;
+                real hr = real(0), hi = real(0);
+                if (ec < g.ew) {
+                    if (er < g.eh) {
+                        hr += ar;
+                        hi += ai;
+                    }
+                    if (er + g.nf < g.eh) {
+                        const cpx b = ext_cell(g, ts, slots, er + g.nf, ec);
+                        hr += b.re;
+                        hi += b.im;
+                    }
+                }
+                // the Hermitian mirror: extended columns outside this block's tile columns, only
+                // near t2 = 0 and t2 = n_f / 2
+                const cpx m = alias_from_slots(g, ts, slots, (N - t1) & msk, (N - t2) & msk);
+                v = cpx{real(0.5) * (hr + m.re), real(0.5) * (hi - m.im)};
             }
             buf[t1 * CB + cc] = v;
         }
@@ -1442,6 +1635,29 @@ hipError_t launch_col_inv(const Geom &g, const cpx *E, const cpx *tw, cpx *R, hi
         const int cb = pick_cb<L>(g);
         IVX_CB_SWITCH(cb, {
             k_col_inv<L, B><<<col_grid(g, B), NT, 0, st>>>(g, E, tw, R);
+        });
+    });
+    return hipGetLastError();
+}
+
+// The fused pass has one block per (item, column group): worth it once that fills the chip
+// several times over (the two-kernel fold has more, smaller blocks for few-item plans).
+constexpr int64_t FUSED_FOLD_MIN_BLOCKS = 2048;
+
+bool fold_fusable(const Geom &g) { return g.eh <= 2 * g.nf && g.ew <= g.nf; }
+
+bool fold_fusion_pays(const Geom &g) {
+    const int64_t ngrp = (g.rw + IVX_FOLD_CB - 1) / IVX_FOLD_CB;
+    return ngrp * g.C * g.P >= FUSED_FOLD_MIN_BLOCKS;
+}
+
+hipError_t launch_col_inv_slots(const Geom &g, const int32_t *tslot, const cpx *slots, const cpx *tw, cpx *R,
+                                hipStream_t st) {
+    if (!fold_fusable(g)) return hipErrorInvalidValue;
+    IVX_LOGN_SWITCH(g.logn, {
+        const int cb = std::min(pick_cb<L>(g), IVX_FOLD_CB);
+        IVX_CB_SWITCH(cb, {
+            k_col_inv_slots<L, B><<<col_grid(g, B), NT, 0, st>>>(g, tslot, slots, tw, R);
         });
     });
     return hipGetLastError();

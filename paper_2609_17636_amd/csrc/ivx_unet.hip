@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -747,6 +748,38 @@ hipError_t conv3x3_grad_weight(const float *x, const float *dy, int n, int h, in
 
 } // namespace
 
+// ------------------------------------------------- allocation-free weight gradient
+// Split partials of ivx_nn_conv3x3_grad_weight_noalloc live in this file-scope array: one
+// copy on every device the library runs on, held until the process ends.  In host code the
+// array's name is not a device address; its address on the current device comes from
+// hipGetSymbolAddress, taken once per device and kept.  Every call on a device shares that
+// device's copy (the partials are fully written before they are read, so nothing has to
+// start at zero); calls that overlap on one device race.
+constexpr int64_t NOALLOC_PART_FLOATS = int64_t(8) << 20; // 32 MiB
+static __device__ __align__(256) float scratch[NOALLOC_PART_FLOATS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call there).
+hipError_t scratch_on_current_device(float **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = static_cast<float *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
 // ======================================================================= network
 struct ConvLayer {
     int cin, cout, h, w;       // input channels, output channels, spatial size
@@ -1116,6 +1149,33 @@ ivx_status ivx_nn_conv3x3_grad_weight(const float *x, const float *dy, int32_t n
     (void)hipFree(part);
     if (e != hipSuccess) return set_error(IVX_EHIP, std::string("conv3x3_grad_weight: ") + hipGetErrorString(e));
     return IVX_OK;
+}
+
+ivx_status ivx_nn_conv3x3_grad_weight_noalloc(const float *x, const float *dy, int32_t n, int32_t h, int32_t w,
+                                              int32_t cin, int32_t cout, float *dw, float *db, void *stream) {
+    if (!x || !dy || !dw || !db || n < 1 || h < 1 || w < 1 || cin < 1 || cout < 1)
+        return set_error(IVX_EINVAL, "bad conv3x3_grad_weight_noalloc arguments");
+    const int64_t need = gw_part_len(n, h, w, cin, cout);
+    if (need > NOALLOC_PART_FLOATS)
+        return set_error(IVX_EINVAL, "conv3x3_grad_weight_noalloc: this shape needs " + std::to_string(need) +
+                                         " floats of split partials, more than the " +
+                                         std::to_string(NOALLOC_PART_FLOATS) +
+                                         " of the static scratch (use ivx_nn_conv3x3_grad_weight)");
+    float *part = nullptr;
+    hipError_t e = scratch_on_current_device(&part);
+    if (e != hipSuccess)
+        return set_error(IVX_EHIP, std::string("conv3x3_grad_weight_noalloc: hipGetSymbolAddress: ") +
+                                       hipGetErrorString(e));
+    e = conv3x3_grad_weight(x, dy, n, h, w, cin, cout, part, dw, db, (hipStream_t)stream);
+    if (e != hipSuccess) return set_error(IVX_EHIP, std::string("conv3x3_grad_weight_noalloc: ") + hipGetErrorString(e));
+    return IVX_OK;
+}
+
+int64_t ivx_nn_conv3x3_grad_weight_noalloc_capacity(void) { return NOALLOC_PART_FLOATS; }
+
+int64_t ivx_nn_conv3x3_grad_weight_scratch_floats(int32_t n, int32_t h, int32_t w, int32_t cin, int32_t cout) {
+    if (n < 1 || h < 1 || w < 1 || cin < 1 || cout < 1) return -1;
+    return gw_part_len(n, h, w, cin, cout);
 }
 
 ivx_status ivx_nn_conv3x3_flip(const uint16_t *weight, int32_t cin, int32_t cout, uint16_t *flipped, void *stream) {

@@ -385,3 +385,26 @@ def test_c2_full_bench_configuration_against_the_oracle(c2_bench):
             assert np.linalg.norm(g1 - want_g) <= TOL["f32"] * max(np.linalg.norm(want_g), g0norm)
         else:
             assert eg <= TOL["f32"]
+
+
+@pytest.mark.parametrize("blocking", [(8, 1, 128, 64, 1), (9, 1, 32, 64, 1), (12, 4, 512, 16, 2), (8, 1, 128, 8, 1)])
+def test_fused_fold_equals_the_extended_grid_path(mini, blocking):
+    """Summing the gridding windows inside the inverse column pass gives the same gradient,
+    bit for bit, as writing the extended grid and reading it back (same sums, same order),
+    for several tilings (several work items per tile, row aliases, Hermitian mirrors)."""
+    plan = _plan(mini, "f32")
+    plan.set_blocking(*blocking)
+    x = torch.tensor(_points(mini)["rand"], dtype=torch.float32, device="cuda")
+    plan.set_fused_fold(2)
+    t1, g1 = plan.objective_grad(x)
+    g1 = g1.cpu().numpy()
+    plan.set_fused_fold(0)
+    t2, g2 = plan.objective_grad(x)
+    assert np.array_equal(t1, t2)
+    assert np.array_equal(g1, g2.cpu().numpy())
+    v = torch.tensor(np.random.default_rng(9).standard_normal((mini.n_vis, 2)), dtype=torch.float32, device="cuda")
+    a2 = plan.adjoint(v).cpu().numpy()
+    plan.set_fused_fold(2)
+    assert np.array_equal(plan.adjoint(v).cpu().numpy(), a2)
+    with pytest.raises(Exception):
+        plan.set_fused_fold(3)
