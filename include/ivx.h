@@ -157,6 +157,26 @@ ivx_status ivx_plan_set_vis(ivx_plan *plan, const ivx_real *vis, const ivx_real 
 ivx_status ivx_objective_grad(ivx_plan *plan, const ivx_real *sky, ivx_real *grad,
                               double *terms, void *stream);
 
+/* The objective and its gradient as two halves, for a reverse-mode caller (the paper obtains
+ * the gradient of Q_tot by automatic differentiation, Sect. 3.4; here the reverse pass is the
+ * hand-written adjoint):
+ *   ivx_objective           Q_tot terms only (no gradient work: nothing is spread).
+ *   ivx_objective_forward   the terms, and the weighted residuals spread into the plan's
+ *                           per-tile windows (the forward model, residual and data term share
+ *                           one pass over the visibilities with the spread).
+ *   ivx_objective_backward  the rest of the gradient from those windows: inverse FFTs, beam
+ *                           and reprojection transpose summed over pointings, regulariser and
+ *                           single-dish gradients, all multiplied by `scale` (the incoming
+ *                           gradient of the caller's loss with respect to Q_tot).
+ * forward + backward(scale = 1) gives the terms and gradient of ivx_objective_grad (the same
+ * sums).  backward needs the same `sky` pointer as the forward it follows and no other call on
+ * the plan in between (IVX_ESTATE otherwise); it consumes the windows, so each forward allows
+ * one backward.  terms: 4 doubles {Q_tot, Q, K, R}, host (synchronises) or device. */
+ivx_status ivx_objective(ivx_plan *plan, const ivx_real *sky, double *terms, void *stream);
+ivx_status ivx_objective_forward(ivx_plan *plan, const ivx_real *sky, double *terms, void *stream);
+ivx_status ivx_objective_backward(ivx_plan *plan, const ivx_real *sky, ivx_real *grad, double scale,
+                                  void *stream);
+
 /* Model visibilities V(sky) of every block in the caller's original order (flagged
  * entries are written as 0).  sky: device [C][N][N]; model_vis: device [M][2]. */
 ivx_status ivx_forward(ivx_plan *plan, const ivx_real *sky, ivx_real *model_vis,
@@ -166,6 +186,12 @@ ivx_status ivx_forward(ivx_plan *plan, const ivx_real *sky, ivx_real *model_vis,
  * the transpose of ivx_forward with the natural weights; it equals -grad Q at x = 0
  * when v = y.  vis: device [M][2] caller order; image: device [C][N][N], overwritten. */
 ivx_status ivx_adjoint(ivx_plan *plan, const ivx_real *vis, ivx_real *image, void *stream);
+
+/* Transpose of ivx_forward without weights (the vector-Jacobian product of the forward model,
+ * Sect. 2.1): image = Re sum_k P_k^T s_c A_k F^H v for v in the caller's order ([M][2]; flagged
+ * entries ignored).  For a cotangent g of the model visibilities, <g, ivx_forward(x)> =
+ * <image, x>.  vis: device [M][2]; image: device [C][N][N], overwritten. */
+ivx_status ivx_forward_adjoint(ivx_plan *plan, const ivx_real *vis, ivx_real *image, void *stream);
 
 /* Time the gridding stage and its slot reduction for candidate blockings (tile edge,
  * waves per block, visibilities per work item) that fit the LDS, and keep the fastest.

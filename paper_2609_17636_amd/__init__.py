@@ -19,7 +19,7 @@ import numpy as np
 
 from .build import lib_path
 
-__all__ = ["Plan", "Objective", "solve", "DeviceSolver", "UNet", "load_library", "IvxError", "STATUS", "STAGES"]
+__all__ = ["Plan", "Objective", "ForwardModel", "solve", "DeviceSolver", "UNet", "load_library", "IvxError", "STATUS", "STAGES"]
 
 STATUS = {0: "IVX_OK", -1: "IVX_EINVAL", -2: "IVX_ENOMEM", -3: "IVX_EHIP", -4: "IVX_ENONFINITE",
           -5: "IVX_ESTATE"}
@@ -47,7 +47,8 @@ class _Problem(ctypes.Structure):
 EXPORTS = ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_forward", "ivx_adjoint",
            "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_last_error", "ivx_version",
            "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking",
-           "ivx_plan_set_vis", "ivx_set_gridder_occupancy", "ivx_set_fused_fold")
+           "ivx_plan_set_vis", "ivx_set_gridder_occupancy", "ivx_set_fused_fold", "ivx_objective",
+           "ivx_objective_forward", "ivx_objective_backward", "ivx_forward_adjoint")
 
 STAGES = ("image_rows", "col_fwd", "grid", "fold", "col_inv", "row_inv", "sd", "sky", "final")
 
@@ -79,13 +80,18 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
     lib.ivx_plan_set_vis.argtypes = [vp, vp, vp, vp]
     lib.ivx_set_gridder_occupancy.argtypes = [vp, i32]
     lib.ivx_set_fused_fold.argtypes = [vp, ctypes.c_int]
+    lib.ivx_objective.argtypes = [vp, vp, vp, vp]
+    lib.ivx_objective_forward.argtypes = [vp, vp, vp, vp]
+    lib.ivx_objective_backward.argtypes = [vp, vp, vp, dbl, vp]
+    lib.ivx_forward_adjoint.argtypes = [vp, vp, vp, vp]
     lib.ivx_stage_times.argtypes = [vp, vp, vp]
     lib.ivx_last_error.restype = ctypes.c_char_p
     lib.ivx_last_error.argtypes = []
     for f in ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_forward",
               "ivx_adjoint", "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_set_timing",
               "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking", "ivx_plan_set_vis",
-              "ivx_set_gridder_occupancy", "ivx_set_fused_fold"):
+              "ivx_set_gridder_occupancy", "ivx_set_fused_fold", "ivx_objective", "ivx_objective_forward",
+              "ivx_objective_backward", "ivx_forward_adjoint"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ivx_version.restype = ctypes.c_int
     lib.ivx_real_size.restype = ctypes.c_int
@@ -264,6 +270,43 @@ class Plan:
                                                 _stream_ptr(stream)))
         return terms, grad
 
+    def objective(self, sky, terms=None, stream=None):
+        """Q_tot terms {Q_tot, Q, K, R} only (no gradient work); host float64 array or the given
+        device tensor."""
+        sky = sky.to(self.torch_dtype).contiguous()
+        if terms is None:
+            terms = np.zeros(4, dtype=np.float64)
+        self._check(self.lib.ivx_objective(self._h, _ptr(sky), _ptr(terms), _stream_ptr(stream)))
+        return terms
+
+    def objective_forward(self, sky, terms=None, stream=None):
+        """First half of a reverse-mode evaluation (see ivx_objective_forward): the terms, with
+        the plan holding what objective_backward needs.  `sky` must stay alive and unchanged
+        until that call."""
+        assert sky.dtype == self.torch_dtype and sky.is_contiguous()
+        if terms is None:
+            terms = np.zeros(4, dtype=np.float64)
+        self._check(self.lib.ivx_objective_forward(self._h, _ptr(sky), _ptr(terms), _stream_ptr(stream)))
+        return terms
+
+    def objective_backward(self, sky, grad=None, scale=1.0, stream=None):
+        """Second half: scale * dQ_tot/dx at the sky of the preceding objective_forward."""
+        torch = _torch()
+        if grad is None:
+            grad = torch.empty_like(sky)
+        self._check(self.lib.ivx_objective_backward(self._h, _ptr(sky), _ptr(grad), float(scale),
+                                                    _stream_ptr(stream)))
+        return grad
+
+    def forward_adjoint(self, vis, out=None, stream=None):
+        """Unweighted transpose of forward: Re sum_k P_k^T s A_k F^H vis, cuda tensor [C][N][N]."""
+        torch = _torch()
+        vis = vis.to(self.torch_dtype).contiguous()
+        if out is None:
+            out = torch.empty((self.n_chan, self.n_sky, self.n_sky), dtype=self.torch_dtype, device=vis.device)
+        self._check(self.lib.ivx_forward_adjoint(self._h, _ptr(vis), _ptr(out), _stream_ptr(stream)))
+        return out
+
     def forward(self, sky, out=None, stream=None):
         """Model visibilities in caller order, cuda tensor [M][2] (flagged entries 0)."""
         torch = _torch()
@@ -329,45 +372,59 @@ class Plan:
         return {k: int(v) for k, v in zip(keys, a)}
 
 
-def _objective_function():
+def _autograd_functions():
     torch = _torch()
 
     class Objective(torch.autograd.Function):
-        """Q_tot(x) as a differentiable scalar.  The forward pass runs the fused HIP
-        evaluation, whose adjoint half (spread, inverse FFTs, reprojection transpose,
-        regulariser and single-dish gradients) is the hand-written backward; backward only
-        scales that gradient by grad_output."""
+        """Q_tot(x) as a differentiable scalar (Eq. fusion_cost).  Forward: the value alone
+        (ivx_objective) when x needs no gradient, else ivx_objective_forward, whose pass over
+        the visibilities also spreads the weighted residuals.  Backward: the hand-written
+        adjoint half, ivx_objective_backward, scaled by the incoming gradient (the paper gets
+        this gradient by automatic differentiation, Sect. 3.4)."""
 
         @staticmethod
         def forward(ctx, x, plan):
-            terms, grad = plan.objective_grad(x)
-            ctx.save_for_backward(grad)
+            xs = x.detach().to(plan.torch_dtype).contiguous()
+            if ctx.needs_input_grad[0]:
+                terms = plan.objective_forward(xs)
+                ctx.plan = plan
+                ctx.in_dtype = x.dtype
+                ctx.save_for_backward(xs)
+            else:
+                terms = plan.objective(xs)
             return torch.tensor(terms[0], dtype=torch.float64, device=x.device)
 
         @staticmethod
         def backward(ctx, gout):
-            (grad,) = ctx.saved_tensors
-            return (gout.to(grad.dtype) * grad), None
+            (xs,) = ctx.saved_tensors
+            grad = ctx.plan.objective_backward(xs, scale=float(gout))
+            return grad.to(ctx.in_dtype), None
 
-    return Objective
+    class ForwardModel(torch.autograd.Function):
+        """Model visibilities V(x) [M][2] in the caller's order (ivx_forward, Sect. 2.1); the
+        backward pass is the unweighted transpose ivx_forward_adjoint."""
+
+        @staticmethod
+        def forward(ctx, x, plan):
+            ctx.plan = plan
+            ctx.in_dtype = x.dtype
+            return plan.forward(x.detach())
+
+        @staticmethod
+        def backward(ctx, g):
+            return ctx.plan.forward_adjoint(g.contiguous()).to(ctx.in_dtype), None
+
+    return {"Objective": Objective, "ForwardModel": ForwardModel}
 
 
-class _Lazy:
-    _obj = None
-
-    def __get__(self, inst, owner):
-        if _Lazy._obj is None:
-            _Lazy._obj = _objective_function()
-        return _Lazy._obj
-
-
-class _Namespace:
-    Objective = _Lazy()
+_AUTOGRAD = {}
 
 
 def __getattr__(name):
-    if name == "Objective":
-        return _Namespace.Objective
+    if name in ("Objective", "ForwardModel"):
+        if not _AUTOGRAD:
+            _AUTOGRAD.update(_autograd_functions())
+        return _AUTOGRAD[name]
     raise AttributeError(name)
 
 

@@ -120,6 +120,10 @@ struct ivx_plan {
     int chunk_max = 256;
     int occupancy = GRIDMX_OCC_AUTO; // matrix-core gridder register budget (waves per SIMD)
     int fused_fold = 1;              // slot fold inside the inverse column pass: 0 never, 1 when it pays, 2 always
+    // every call that reuses the evaluation buffers advances the epoch; ivx_objective_backward
+    // needs the buffers exactly as ivx_objective_forward left them
+    uint64_t epoch = 0, fwd_epoch = ~0ull;
+    const void *fwd_sky = nullptr;
     int tile_fixed = 0;
     std::vector<real> dq_host;
     std::vector<cpx> tw_host;
@@ -611,6 +615,13 @@ ivx_status check_plan(const ivx_plan *p) {
     return IVX_OK;
 }
 
+// check_plan for a call that overwrites the evaluation buffers
+ivx_status check_plan_use(ivx_plan *p) {
+    ivx_status s = check_plan(p);
+    if (s == IVX_OK) ++p->epoch;
+    return s;
+}
+
 ivx_status run_forward_half(ivx_plan *p, const real *sky, hipStream_t st) {
     const Geom &g = p->g;
     IVX_HIP(launch_image_rows(g, sky, p->d_beams, p->d_interp, p->d_fscale, p->d_dq, p->d_tw, p->d_R, st));
@@ -721,13 +732,71 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
         StageTimer t(p, st, IVX_STAGE_SKY);
         IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r,
                            sd ? (real)p->d.lambda_s : real(0), p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride,
-                           p->d.sd_offset, grad, p->d_rpart, false, st));
+                           p->d.sd_offset, grad, p->d_rpart, SKY_FULL, real(1), st));
     }
     {
         StageTimer t(p, st, IVX_STAGE_FINAL);
         IVX_HIP(launch_final(p->d_jpart, p->n_work, p->d_jpart + p->n_work, p->d_rpart, p->n_rpart, p->d_kpart,
                              sd ? p->n_kpart : 0,
                              p->d.lambda_r, sd ? p->d.lambda_s : 0.0, p->d_terms, terms_dev, st));
+    }
+    return IVX_OK;
+}
+
+// Forward half of an evaluation: the visibility model, residual and data term (MODE_OBJ also
+// spreads the weighted residual into the slots for a following adjoint half, MODE_VAL does
+// not), the single-dish model and residual, the regulariser value, and the four totals.
+ivx_status eval_value(ivx_plan *p, const real *sky, double *terms_dev, int grid_mode, hipStream_t st) {
+    const Geom &g = p->g;
+    IVX_HIP(launch_image_rows(g, sky, p->d_beams, p->d_interp, p->d_fscale, p->d_dq, p->d_tw, p->d_R, st));
+    IVX_HIP(launch_col_fwd(g, p->d_R, p->d_tw, p->d_ext, st));
+    IVX_HIP(launch_grid(grid_mode, g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff,
+                        p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi,
+                        p->occupancy, st));
+    const bool sd = sd_active(p);
+    if (sd) {
+        IVX_HIP(launch_sd_rows(g, sky, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_U, st));
+        IVX_HIP(launch_sd_cols(g, p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_sdmap,
+                               (real)(1.0 / (p->d.sd_sigma * p->d.sd_sigma)), p->d_E, p->d_kpart, st));
+        if (grid_mode == MODE_OBJ)
+            IVX_HIP(launch_sd_back(g, p->d_E, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_U, st));
+    }
+    IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r, real(0), nullptr, nullptr, 0, 0, 1,
+                       0, nullptr, p->d_rpart, SKY_VALUE, real(1), st));
+    IVX_HIP(launch_final(p->d_jpart, p->n_work, p->d_jpart + p->n_work, p->d_rpart, p->n_rpart, p->d_kpart,
+                         sd ? p->n_kpart : 0, p->d.lambda_r, sd ? p->d.lambda_s : 0.0, p->d_terms, terms_dev, st));
+    return IVX_OK;
+}
+
+// Adjoint half after eval_value(MODE_OBJ): slots -> inverse FFTs -> reprojection transpose,
+// plus the regulariser and single-dish gradients, all multiplied by `scale`.
+ivx_status eval_gradient(ivx_plan *p, const real *sky, real *grad, real scale, hipStream_t st) {
+    const Geom &g = p->g;
+    ivx_status s = run_adjoint_half(p, st);
+    if (s != IVX_OK) return s;
+    const bool sd = sd_active(p);
+    IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r, sd ? (real)p->d.lambda_s : real(0),
+                       p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, grad, p->d_rpart,
+                       SKY_FULL, scale, st));
+    return IVX_OK;
+}
+
+// Device pointer for `terms` (written by the last kernel) or nullptr for host memory.
+double *device_terms(double *terms) {
+    if (!terms) return nullptr;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, terms) == hipSuccess) {
+        if (attr.type == hipMemoryTypeDevice) return terms;
+    } else {
+        (void)hipGetLastError();
+    }
+    return nullptr;
+}
+
+ivx_status copy_terms(ivx_plan *p, double *terms, double *terms_dev, hipStream_t st) {
+    if (terms && !terms_dev) {
+        IVX_HIP(hipMemcpyAsync(terms, p->d_terms, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        IVX_HIP(hipStreamSynchronize(st));
     }
     return IVX_OK;
 }
@@ -880,6 +949,7 @@ ivx_status ivx_set_blocking(ivx_plan *p, int32_t tile, int32_t waves, int32_t ch
         (lanes == GRID_MFMA_LANES && vpi != 1))
         return fail(IVX_EINVAL, "blocking out of range");
     if (!tile_fits(p, tile, waves, lanes)) return fail(IVX_EINVAL, "blocking does not fit the LDS");
+    ++p->epoch;
     p->nwave = waves;
     p->chunk_max = chunk;
     p->lanes = lanes;
@@ -1026,6 +1096,7 @@ ivx_status set_data_impl(ivx_plan *p, const VisSource &src, bool shared, const i
     for (size_t i = 0; i < h_beams.size(); ++i)
         if (!std::isfinite((double)h_beams[i])) return fail(IVX_ENONFINITE, "beams hold a non-finite value");
     free_all(p);
+    ++p->epoch;
     p->shared_uv = shared;
     p->pt_off.assign(g.P + 1, 0);
     for (int k = 0; k < g.P; ++k)
@@ -1178,7 +1249,7 @@ fail_free:
 extern "C" {
 
 ivx_status ivx_plan_set_vis(ivx_plan *p, const ivx_real *vis, const ivx_real *weight, void *stream) {
-    ivx_status s = check_plan(p);
+    ivx_status s = check_plan_use(p);
     if (s != IVX_OK) return s;
     if (!vis && p->m_total > 0) return fail(IVX_EINVAL, "vis is required");
     hipStream_t st = (hipStream_t)stream;
@@ -1227,20 +1298,12 @@ ivx_status ivx_plan_set_vis(ivx_plan *p, const ivx_real *vis, const ivx_real *we
 }
 
 ivx_status ivx_objective_grad(ivx_plan *p, const ivx_real *sky, ivx_real *grad, double *terms, void *stream) {
-    ivx_status s = check_plan(p);
+    ivx_status s = check_plan_use(p);
     if (s != IVX_OK) return s;
     if (!sky || !grad) return fail(IVX_EINVAL, "sky and grad are required");
     hipStream_t st = (hipStream_t)stream;
     // device `terms` is written by the last kernel itself; host `terms` gets a copy
-    double *terms_dev = nullptr;
-    if (terms) {
-        hipPointerAttribute_t attr;
-        if (hipPointerGetAttributes(&attr, terms) == hipSuccess) {
-            if (attr.type == hipMemoryTypeDevice) terms_dev = terms;
-        } else {
-            (void)hipGetLastError();
-        }
-    }
+    double *terms_dev = device_terms(terms);
     if (p->use_graph && p->timing_mask == 0) {
         if (!(p->gexec && p->g_sky == sky && p->g_grad == grad && p->g_terms == terms_dev)) {
             drop_graph(p);
@@ -1271,15 +1334,11 @@ ivx_status ivx_objective_grad(ivx_plan *p, const ivx_real *sky, ivx_real *grad, 
     } else {
         if ((s = eval_objective(p, sky, grad, terms_dev, st)) != IVX_OK) return s;
     }
-    if (terms && !terms_dev) {
-        IVX_HIP(hipMemcpyAsync(terms, p->d_terms, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-        IVX_HIP(hipStreamSynchronize(st));
-    }
-    return IVX_OK;
+    return copy_terms(p, terms, terms_dev, st);
 }
 
 ivx_status ivx_forward(ivx_plan *p, const ivx_real *sky, ivx_real *model_vis, void *stream) {
-    ivx_status s = check_plan(p);
+    ivx_status s = check_plan_use(p);
     if (s != IVX_OK) return s;
     if (!sky || (!model_vis && p->m_total > 0)) return fail(IVX_EINVAL, "sky and model_vis are required");
     hipStream_t st = (hipStream_t)stream;
@@ -1291,7 +1350,7 @@ ivx_status ivx_forward(ivx_plan *p, const ivx_real *sky, ivx_real *model_vis, vo
 }
 
 ivx_status ivx_adjoint(ivx_plan *p, const ivx_real *vis, ivx_real *image, void *stream) {
-    ivx_status s = check_plan(p);
+    ivx_status s = check_plan_use(p);
     if (s != IVX_OK) return s;
     if (!image || (!vis && p->m_total > 0)) return fail(IVX_EINVAL, "vis and image are required");
     hipStream_t st = (hipStream_t)stream;
@@ -1299,12 +1358,60 @@ ivx_status ivx_adjoint(ivx_plan *p, const ivx_real *vis, ivx_real *image, void *
                         p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave, p->lanes * 10 + p->vpi, p->occupancy, st));
     if ((s = run_adjoint_half(p, st)) != IVX_OK) return s;
     IVX_HIP(launch_sky(p->g, image, p->d_gp, p->d_cptr, p->d_cent, real(0), real(0), nullptr, nullptr, 0, 0, 1, 0,
-                       image, p->d_rpart, true, st));
+                       image, p->d_rpart, SKY_ADJOINT, real(1), st));
+    return IVX_OK;
+}
+
+ivx_status ivx_objective(ivx_plan *p, const ivx_real *sky, double *terms, void *stream) {
+    ivx_status s = check_plan_use(p);
+    if (s != IVX_OK) return s;
+    if (!sky || !terms) return fail(IVX_EINVAL, "sky and terms are required");
+    hipStream_t st = (hipStream_t)stream;
+    double *terms_dev = device_terms(terms);
+    if ((s = eval_value(p, sky, terms_dev, MODE_VAL, st)) != IVX_OK) return s;
+    return copy_terms(p, terms, terms_dev, st);
+}
+
+ivx_status ivx_objective_forward(ivx_plan *p, const ivx_real *sky, double *terms, void *stream) {
+    ivx_status s = check_plan_use(p);
+    if (s != IVX_OK) return s;
+    if (!sky || !terms) return fail(IVX_EINVAL, "sky and terms are required");
+    hipStream_t st = (hipStream_t)stream;
+    double *terms_dev = device_terms(terms);
+    if ((s = eval_value(p, sky, terms_dev, MODE_OBJ, st)) != IVX_OK) return s;
+    p->fwd_epoch = p->epoch;
+    p->fwd_sky = sky;
+    return copy_terms(p, terms, terms_dev, st);
+}
+
+ivx_status ivx_objective_backward(ivx_plan *p, const ivx_real *sky, ivx_real *grad, double scale, void *stream) {
+    ivx_status s = check_plan(p);
+    if (s != IVX_OK) return s;
+    if (!sky || !grad) return fail(IVX_EINVAL, "sky and grad are required");
+    if (!std::isfinite(scale)) return fail(IVX_EINVAL, "scale must be finite");
+    if (p->fwd_epoch != p->epoch || p->fwd_sky != sky)
+        return fail(IVX_ESTATE, "ivx_objective_backward must follow ivx_objective_forward of the same sky with no "
+                                "other call on the plan in between");
+    ++p->epoch; // the adjoint half consumes the slots: a second backward needs a new forward
+    return eval_gradient(p, sky, grad, (real)scale, (hipStream_t)stream);
+}
+
+ivx_status ivx_forward_adjoint(ivx_plan *p, const ivx_real *vis, ivx_real *image, void *stream) {
+    ivx_status s = check_plan_use(p);
+    if (s != IVX_OK) return s;
+    if (!image || (!vis && p->m_total > 0)) return fail(IVX_EINVAL, "vis and image are required");
+    hipStream_t st = (hipStream_t)stream;
+    IVX_HIP(launch_grid(MODE_ADJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff,
+                        p->d_ext, p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave,
+                        p->lanes * 10 + p->vpi, p->occupancy, st, true));
+    if ((s = run_adjoint_half(p, st)) != IVX_OK) return s;
+    IVX_HIP(launch_sky(p->g, image, p->d_gp, p->d_cptr, p->d_cent, real(0), real(0), nullptr, nullptr, 0, 0, 1, 0,
+                       image, p->d_rpart, SKY_ADJOINT, real(1), st));
     return IVX_OK;
 }
 
 ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, void *stream) {
-    ivx_status s = check_plan(p);
+    ivx_status s = check_plan_use(p);
     if (s != IVX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     struct Cand { int T, nwave, chunk, lanes, vpi; };

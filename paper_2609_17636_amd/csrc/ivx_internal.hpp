@@ -64,7 +64,10 @@ struct Geom {
     int64_t win_stride;   // win * win (slot size)
 };
 
-enum GridMode { MODE_OBJ = 0, MODE_FWD = 1, MODE_ADJ = 2 };
+// Gridding modes: the objective (degrid, residual, data term, spread), the forward model
+// alone, the adjoint alone (spread of given visibilities), and the data term alone (degrid
+// and residual, nothing spread: an objective value without its gradient).
+enum GridMode { MODE_OBJ = 0, MODE_FWD = 1, MODE_ADJ = 2, MODE_VAL = 3 };
 
 // Sky pass tiling: blocks of SKY_T x SKY_T pixels, 256 threads, thread t at row t / SKY_T,
 // column t % SKY_T of the block; the reprojection transpose is stored per wave ("slice":
@@ -84,7 +87,7 @@ hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work
                        const VisCoord *crd, const cpx *vis, const real *wgt,
                        const int32_t *perm, const int64_t *boff, const cpx *ext, cpx *slots, double *jpart,
                        const cpx *caller_in, cpx *caller_out, int nwave, int variant,
-                       int occupancy, hipStream_t st);
+                       int occupancy, hipStream_t st, bool unweighted = false);
 // adjoint extended grid: the windows summed into `ext` (the forward extended grid, which
 // the gridding pass has consumed by then)
 hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, hipStream_t st);
@@ -107,10 +110,13 @@ hipError_t launch_sd_cols(const Geom &g, const real *U, const real *gB, int rb, 
 // V[c][p][j] = sum_q g(o + q S - j) E[c][p][q] (column half of the single-dish adjoint)
 hipError_t launch_sd_back(const Geom &g, const real *E, const real *gB, int rb, int sd_n, int stride, int offset,
                           real *V, hipStream_t st);
+// Sky pass modes: the whole gradient and R; the reprojection transpose alone (adjoint); R
+// alone (no gradient written).  The gradient is multiplied by `scale`.
+enum SkyMode { SKY_FULL = 0, SKY_ADJOINT = 1, SKY_VALUE = 2 };
 hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int32_t *cptr,
                       const CsrEnt *cent, real lambda_r, real lambda_s, const real *E,
                       const real *gB, int rb, int sd_n, int stride, int offset, real *grad,
-                      double *rpart, bool adjoint_only, hipStream_t st);
+                      double *rpart, int mode, real scale, hipStream_t st);
 int sky_blocks(const Geom &g);
 // FP64 reduction of all partials into {Q_tot, Q, K, R} (terms, and terms_user if non-null).
 // jpart: per-work-item partials of J; scratch: final_scratch(nj) doubles (may be 0)

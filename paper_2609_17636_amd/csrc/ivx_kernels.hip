@@ -358,6 +358,7 @@ struct GridArgs {
     cpx *caller_out;
     int nwave;
     int n_work;
+    int unweighted; // adjoint mode: spread the given visibilities without the natural weights
 };
 
 // Work items per row of the gridding launch: the dispatch packet counts work-items of one
@@ -447,6 +448,8 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     const int nwave = a.nwave;
     const int ngroups = nwave * GPW;
     cpx *Fw = reinterpret_cast<cpx *>(smem_raw);
+    constexpr bool SPREAD = MODE == MODE_OBJ || MODE == MODE_ADJ;
+    constexpr bool DATA = MODE == MODE_OBJ || MODE == MODE_VAL; // residual against the data
     cpx *Hw = Fw + (MODE == MODE_ADJ ? 0 : wsz);
     const int64_t wid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     if (wid >= a.n_work) return; // tail of the last row: the whole block leaves together
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
             Fw[cc * ldw + r] = F[cc * g.eh + r];
         }
     }
-    if (MODE != MODE_FWD) {
+    if (SPREAD) {
         for (int e = tid; e < ngroups * wsz; e += blockDim.x) Hw[e] = cpx{0, 0};
     }
     __syncthreads();
@@ -520,8 +523,8 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
             r[u].y = cpx{0, 0};
             r[u].w = real(0);
             r[u].p = 0;
-            if (MODE == MODE_OBJ) { r[u].y = at(vis, vn); r[u].w = at(wgt, vn); }
-            if (MODE == MODE_ADJ) { r[u].w = at(wgt, vn); r[u].p = at(perm, vn); }
+            if (DATA) { r[u].y = at(vis, vn); r[u].w = at(wgt, vn); }
+            if (MODE == MODE_ADJ) { r[u].w = a.unweighted ? real(1) : at(wgt, vn); r[u].p = at(perm, vn); }
             if (MODE == MODE_FWD) { r[u].p = at(perm, vn); }
         }
     };
@@ -608,7 +611,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         real cre[VPI], cim[VPI];
 #pragma unroll
         for (int u = 0; u < VPI; ++u) {
-            if (MODE == MODE_OBJ) {
+            if (DATA) {
                 const real rr = ar[u] - cur[u].y.re, ri = ai[u] - cur[u].y.im;
                 if (valid[u] && t == 0) jacc += cur[u].w * (rr * rr + ri * ri); // halved at the end
                 const real ww = cur[u].w * wxj[u];
@@ -623,7 +626,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         }
         // spread: the visibilities of one iteration go in program order, so a cell shared
         // by two of them (owned by different lanes) sees both updates
-        if (colok) {
+        if (SPREAD && colok) {
 #pragma unroll
             for (int u = 0; u < VPI; ++u) {
 #pragma unroll
@@ -656,19 +659,21 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         step(r2, it + 2);
     }
     if (MODE == MODE_FWD) return;
-    __syncthreads();
-    cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride; // column-major window
-    for (int e = tid; e < win * win; e += blockDim.x) {
-        const int cc = (int)(((float)e + 0.5f) * inv_win), r = e - cc * win;
-        real sr = real(0), si = real(0);
-        for (int q = 0; q < ngroups; ++q) {
-            const cpx hh = Hw[q * wsz + cc * ldw + r];
-            sr += hh.re;
-            si += hh.im;
+    if (SPREAD) {
+        __syncthreads();
+        cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride; // column-major window
+        for (int e = tid; e < win * win; e += blockDim.x) {
+            const int cc = (int)(((float)e + 0.5f) * inv_win), r = e - cc * win;
+            real sr = real(0), si = real(0);
+            for (int q = 0; q < ngroups; ++q) {
+                const cpx hh = Hw[q * wsz + cc * ldw + r];
+                sr += hh.re;
+                si += hh.im;
+            }
+            Sl[e] = cpx{sr, si};
         }
-        Sl[e] = cpx{sr, si};
     }
-    if (MODE == MODE_OBJ) {
+    if (DATA) {
         double d = 0.5 * (double)jacc;
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) d += __shfl_xor(d, m, 64);
@@ -737,6 +742,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
     const Geom &g = a.g;
     const int l = threadIdx.x, c16 = l & 15, g4 = l >> 4;
     const int W = KW > 0 ? KW : g.W, win = g.win;
+    constexpr bool SPREAD = MODE == MODE_OBJ || MODE == MODE_ADJ;
+    constexpr bool DATA = MODE == MODE_OBJ || MODE == MODE_VAL; // residual against the data
     const float zoff = 0.5f * (float)W - 1.f;
     const float inv_hw = 2.f / (float)W;
     const float beta2 = g.beta * 1.4426950408889634f;
@@ -779,8 +786,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
     auto fetch = [&](MxRec &r, int v0) {
         const int vi = min(v0 + c16, n - 1), vw = min(v0 + (l >> 2), n - 1);
         r.c = crd[vw];
-        if (MODE == MODE_OBJ) { r.y = vis[vi]; r.w = wgt[vi]; }
-        if (MODE == MODE_ADJ) { r.w = wgt[vi]; r.p = perm[vi]; }
+        if (DATA) { r.y = vis[vi]; r.w = wgt[vi]; }
+        if (MODE == MODE_ADJ) { r.w = a.unweighted ? 1.f : wgt[vi]; r.p = perm[vi]; }
         if (MODE == MODE_FWD) r.p = perm[vi];
     };
     auto batch = [&](const MxRec &r, int v0) {
@@ -848,10 +855,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
             if (l < 16) {
                 const float rr = vr - r.y.re, ri = vi - r.y.im;
                 if (ok) jacc += r.w * (rr * rr + ri * ri); // halved at the end
-                WRr[l] = ok ? r.w * rr : 0.f;
-                WRi[l] = ok ? r.w * ri : 0.f;
+                if (SPREAD) {
+                    WRr[l] = ok ? r.w * rr : 0.f;
+                    WRi[l] = ok ? r.w * ri : 0.f;
+                }
             }
             wave_sync();
+            if (!SPREAD) return;
         }
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
@@ -873,13 +883,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
         batch(rb, v0 + 16);
     }
     if (MODE == MODE_FWD) return;
-    cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride; // column-major window
+    if (SPREAD) {
+        cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride; // column-major window
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int r = 4 * g4 + v;
-        if (r < win && c16 < win) Sl[c16 * win + r] = cpx{hre[v], him[v]};
+        for (int v = 0; v < 4; ++v) {
+            const int r = 4 * g4 + v;
+            if (r < win && c16 < win) Sl[c16 * win + r] = cpx{hre[v], him[v]};
+        }
     }
-    if (MODE == MODE_OBJ) {
+    if (DATA) {
         double d = 0.5 * (double)jacc;
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) d += __shfl_xor(d, m, 64);
@@ -1399,7 +1411,8 @@ struct SkyArgs {
     int rb, sd_n, stride, offset;
     real *grad;
     double *rpart;
-    int adjoint_only;
+    int mode;   // SkyMode
+    real scale; // gradient multiplier
 };
 
 constexpr int SKY_LOADS = 8; // CSR entries per lane in flight in k_sky
@@ -1425,8 +1438,9 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
     const int tid = threadIdx.x;
     const int ti = tid / SKY_T, tj = tid - (tid / SKY_T) * SKY_T;
     const real *x = a.sky + (int64_t)c * N * N;
-    const bool reg = (a.lambda_r != real(0)) && !a.adjoint_only;
-    const bool sd = (a.lambda_s != real(0)) && (a.sd_n > 0) && !a.adjoint_only;
+    const bool adjoint_only = a.mode == SKY_ADJOINT, value_only = a.mode == SKY_VALUE;
+    const bool reg = (a.lambda_r != real(0)) && !adjoint_only;
+    const bool sd = (a.lambda_s != real(0)) && (a.sd_n > 0) && !adjoint_only && !value_only;
     double rloc = 0.0;
     if (reg) {
         for (int e = tid; e < (SKY_T + 4) * (SKY_T + 4); e += NT) {
@@ -1446,7 +1460,12 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
         __syncthreads();
     }
     const int i = i0 + ti, j = j0 + tj;
-    if (i < N && j < N) {
+    if (value_only) {
+        if (reg && i < N && j < N) {
+            const real d = dxs[ti + 1][tj + 1];
+            rloc = 0.5 * (double)d * (double)d;
+        }
+    } else if (i < N && j < N) {
         real gsum = real(0);
         const int64_t p = (int64_t)i * N + j;
         const int64_t coff = (int64_t)c * g.nk * g.nk;
@@ -1483,9 +1502,9 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
             for (int pp = p0; pp <= p1; ++pp) s += a.gB[o + pp * S - i + rb] * Vc[(int64_t)pp * N + j];
             gsum += a.lambda_s * s;
         }
-        a.grad[(int64_t)c * N * N + p] = gsum;
+        a.grad[(int64_t)c * N * N + p] = a.scale == real(1) ? gsum : a.scale * gsum;
     }
-    if (!a.adjoint_only) {
+    if (!adjoint_only) {
         for (int m = 32; m >= 1; m >>= 1) rloc += __shfl_xor(rloc, m, 64);
         if ((tid & 63) == 0) red[tid >> 6] = rloc;
         __syncthreads();
@@ -1692,6 +1711,7 @@ static hipError_t launch_grid_wg(int mode, const GridArgs &a, int n_work, hipStr
     switch (mode) {
     case MODE_OBJ: k_grid<W, MODE_OBJ, G, VPI><<<grid, threads, (1 + ng) * wsz, st>>>(a); break;
     case MODE_FWD: k_grid<W, MODE_FWD, G, VPI><<<grid, threads, wsz, st>>>(a); break;
+    case MODE_VAL: k_grid<W, MODE_VAL, G, VPI><<<grid, threads, wsz, st>>>(a); break;
     default: k_grid<W, MODE_ADJ, G, VPI><<<grid, threads, ng * wsz, st>>>(a); break;
     }
     return hipGetLastError();
@@ -1706,6 +1726,9 @@ template <int W, int G, int VPI> static hipError_t prepare_grid_wg(const Geom &g
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)((1 + ng) * wsz))) != hipSuccess)
         return e;
     if ((e = hipFuncSetAttribute((const void *)k_grid<W, MODE_FWD, G, VPI>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)wsz)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)k_grid<W, MODE_VAL, G, VPI>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)wsz)) != hipSuccess)
         return e;
     return hipFuncSetAttribute((const void *)k_grid<W, MODE_ADJ, G, VPI>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1760,6 +1783,7 @@ template <int KW, int OCC> void launch_gridmx_occ(int mode, dim3 grid, const Gri
     switch (mode) {
     case MODE_OBJ: k_gridmx<MODE_OBJ, KW, OCC><<<grid, 64, 0, st>>>(a); break;
     case MODE_FWD: k_gridmx<MODE_FWD, KW, OCC><<<grid, 64, 0, st>>>(a); break;
+    case MODE_VAL: k_gridmx<MODE_VAL, KW, OCC><<<grid, 64, 0, st>>>(a); break;
     default: k_gridmx<MODE_ADJ, KW, OCC><<<grid, 64, 0, st>>>(a); break;
     }
 }
@@ -1778,11 +1802,12 @@ template <int KW> void launch_gridmx(int mode, dim3 grid, const GridArgs &a, int
 hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
                        const cpx *vis, const real *wgt, const int32_t *perm, const int64_t *boff, const cpx *ext,
                        cpx *slots, double *jpart, const cpx *caller_in, cpx *caller_out, int nwave, int variant,
-                       int occupancy, hipStream_t st) {
+                       int occupancy, hipStream_t st, bool unweighted) {
     if (!(occupancy == GRIDMX_OCC_AUTO || occupancy == 6 || occupancy == 7)) return hipErrorInvalidValue;
     if (n_work <= 0) return hipSuccess;
     if (nwave < 1 || nwave > NT / 64) return hipErrorInvalidValue;
-    GridArgs a{g, work, crd, vis, wgt, perm, boff, ext, slots, jpart, caller_in, caller_out, nwave, n_work};
+    GridArgs a{g, work, crd, vis, wgt, perm, boff, ext, slots, jpart, caller_in, caller_out, nwave, n_work,
+               unweighted ? 1 : 0};
     if (variant == GRID_MFMA_VARIANT) {
 #ifdef IVX_REAL_DOUBLE
         return hipErrorInvalidValue;
@@ -1830,10 +1855,9 @@ int sky_blocks(const Geom &g) {
 
 hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int32_t *cptr, const CsrEnt *cent,
                       real lambda_r, real lambda_s, const real *E, const real *gB, int rb, int sd_n, int stride,
-                      int offset, real *grad, double *rpart, bool adjoint_only, hipStream_t st) {
+                      int offset, real *grad, double *rpart, int mode, real scale, hipStream_t st) {
     const int nb = (g.N + SKY_T - 1) / SKY_T;
-    SkyArgs a{g, sky, gp, cptr, cent, lambda_r, lambda_s, E, gB, rb, sd_n, stride, offset, grad, rpart,
-              adjoint_only ? 1 : 0};
+    SkyArgs a{g, sky, gp, cptr, cent, lambda_r, lambda_s, E, gB, rb, sd_n, stride, offset, grad, rpart, mode, scale};
     const int64_t total = (int64_t)nb * nb * g.C;
     k_sky<<<dim3((unsigned)(8 * ((total + 7) / 8))), NT, 0, st>>>(a);
     return hipGetLastError();
