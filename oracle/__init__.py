@@ -22,6 +22,10 @@ FP64, in the order of the paper:
   O8 sd_term             T~ = S(B (x) x), K = 1/2 ||(T~ - T)/sigma_sd||^2,
                          grad = B^T S^T (T~ - T)/sigma_sd^2             (Sect. 2.4)
   O9 objective_grad      Q_tot = Q + lambda_s K + lambda_r R           (Eq. fusion_cost)
+                         + lambda_nu R_nu, R_nu = 1/2 sum_c ||x_{c+1} - x_c||^2: a spectral
+                         smoothness term coupling adjacent channels (one of the regulariser
+                         extensions the paper names in Sect. 2.3 and its prospects; the form
+                         is this repository's reading, the paper gives none)
 
 The readings taken where the paper is silent (pixel <-> (l, m) mapping, bilinear
 convention, boundary handling, single-dish sampling and normalisation, weights) are the
@@ -176,6 +180,22 @@ def regulariser(x: np.ndarray):
     return 0.5 * float(np.sum(dx * dx)), laplacian(dx)
 
 
+# ----------------------------------------------------------------------------- spectral term
+
+def spectral_term(x: np.ndarray):
+    """R_nu = 1/2 sum_{c=0}^{C-2} sum_r (x[c+1, r] - x[c, r])^2 over the cube [C][N][N] and its
+    gradient: dR_nu/dx[c] = (x[c] - x[c-1]) [c >= 1] - (x[c+1] - x[c]) [c <= C-2]."""
+    x = np.asarray(x, dtype=np.float64)
+    g = np.zeros_like(x)
+    val = 0.0
+    for c in range(x.shape[0] - 1):
+        d = x[c + 1] - x[c]
+        val += 0.5 * float(np.sum(d * d))
+        g[c] -= d
+        g[c + 1] += d
+    return val, g
+
+
 # ----------------------------------------------------------------------------- O8
 
 def sd_beam_taps(fwhm_rad: float, pixel_rad: float):
@@ -301,7 +321,13 @@ def objective_grad(p, x: np.ndarray):
             kc, gk = sd_term(x[c], p.sd_map[c], p.sd_sigma, G)     # O8
             K += kc
             grad[c] += p.lambda_s * gk
-    terms = {"Q": Q, "K": K, "R": R, "Q_tot": Q + p.lambda_s * K + p.lambda_r * R}  # O9
+    lam_nu = float(getattr(p, "lambda_nu", 0.0))
+    Nu = 0.0
+    if lam_nu != 0.0:
+        Nu, gnu = spectral_term(x)
+        grad += lam_nu * gnu
+    terms = {"Q": Q, "K": K, "R": R, "Nu": Nu,
+             "Q_tot": Q + p.lambda_s * K + p.lambda_r * R + lam_nu * Nu}  # O9
     return terms, grad
 
 

@@ -67,6 +67,7 @@ class Problem:
     sd_map: Optional[np.ndarray] = None  # [C][sd_n][sd_n] float32
     sd_noise_frac: float = 0.01
     vis: Optional[np.ndarray] = None  # [M] complex64, filled by attach_data
+    lambda_nu: float = 0.0  # spectral smoothness weight (couples adjacent channels)
     meta: dict = field(default_factory=dict)
 
     @property
@@ -443,6 +444,7 @@ class CubeProblem:
     sd_sigma: float = 0.0
     sd_map: Optional[np.ndarray] = None
     sd_noise_frac: float = 0.01
+    lambda_nu: float = 0.0  # spectral smoothness weight (couples adjacent channels)
     meta: dict = field(default_factory=dict)
 
     @property
@@ -493,7 +495,8 @@ class CubeProblem:
             flags=self.flags, beams=self.beams, interp=self.interp, x_true=np.asarray(x, dtype=np.float64),
             noise=np.zeros(0), noise_rule=("abs", 1.0), sd_n=self.sd_n, sd_stride=self.sd_stride,
             sd_offset=self.sd_offset, sd_fwhm_rad=self.sd_fwhm_rad, sd_sigma=self.sd_sigma,
-            sd_map=self.sd_map, sd_noise_frac=self.sd_noise_frac, vis=self.vis, meta=dict(self.meta))
+            sd_map=self.sd_map, sd_noise_frac=self.sd_noise_frac, vis=self.vis, lambda_nu=self.lambda_nu,
+            meta=dict(self.meta))
 
 
 def channel_freqs(n_chan: int, centre_hz: float, width_hz: float) -> np.ndarray:

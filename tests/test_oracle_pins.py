@@ -445,3 +445,62 @@ def test_point_source_flux_recovery_without_regulariser(oracle_mod):
         sigma = 4.0 / np.sqrt(np.sum(w) * (p.flux_scale[0] * A) ** 2)
         assert abs(x[a - 1:a + 2, b - 1:b + 2].sum() - p.x_true[0, a, b]) <= 3 * sigma
     assert x.min() >= 0.0
+
+
+# ----------------------------------------------------------------------------- spectral term
+
+def test_spectral_term_closed_forms(oracle_mod):
+    """R_nu = 1/2 sum_c ||x_{c+1} - x_c||^2: zero on a channel-constant cube, 1/2 (C-1) N^2 s^2
+    on a ramp x_c = c s with gradient -s / 0 / +s on the first / inner / last channels, and a
+    delta in one channel gives value d^2 and gradient 2d, -d, -d (one-sided at the ends)."""
+    rng = np.random.default_rng(60)
+    C, N = 5, 6
+    flat = np.repeat(rng.standard_normal((1, N, N)), C, axis=0)
+    v, g = oracle_mod.spectral_term(flat)
+    assert v == 0.0 and np.all(g == 0.0)
+    s = 0.75
+    ramp = np.repeat((np.arange(C) * s)[:, None, None], N, axis=1).repeat(N, axis=2)
+    v, g = oracle_mod.spectral_term(ramp)
+    assert v == pytest.approx(0.5 * (C - 1) * N * N * s * s, rel=1e-15)
+    np.testing.assert_allclose(g[0], -s)
+    np.testing.assert_allclose(g[1:-1], 0.0, atol=1e-15)
+    np.testing.assert_allclose(g[-1], s)
+    d = 1.3
+    for c0, want in ((2, (2 * d, -d, -d)), (0, (d, None, -d)), (C - 1, (d, -d, None))):
+        x = np.zeros((C, N, N))
+        x[c0, 2, 3] = d
+        v, g = oracle_mod.spectral_term(x)
+        assert v == pytest.approx((1.0 if c0 in (0, C - 1) else 2.0) * 0.5 * d * d, rel=1e-15)
+        assert g[c0, 2, 3] == pytest.approx(want[0])
+        if want[1] is not None:
+            assert g[c0 - 1, 2, 3] == pytest.approx(want[1])
+        if want[2] is not None:
+            assert g[c0 + 1, 2, 3] == pytest.approx(want[2])
+        assert np.count_nonzero(g) == (3 if c0 not in (0, C - 1) else 2)
+    assert oracle_mod.spectral_term(rng.standard_normal((1, N, N)))[0] == 0.0
+
+
+def test_objective_with_spectral_term_matches_finite_differences(oracle_mod):
+    """The full objective of a 4-channel mosaic with the spectral term on: central differences
+    (exact for a quadratic) at pixels of the first, an inner and the last channel."""
+    p = synth.config_c4_mini()
+    e = p.expand()
+    e.vis = p.vis
+    e.lambda_nu = 0.37
+    synth.attach_sd(e, oracle_mod.sd_model(e, e.x_true))
+    rng = np.random.default_rng(61)
+    x = rng.uniform(0, 50, size=e.x_true.shape)
+    t, g = oracle_mod.objective_grad(e, x)
+    assert t["Nu"] > 0 and t["Q_tot"] == pytest.approx(t["Q"] + e.lambda_s * t["K"] + e.lambda_r * t["R"]
+                                                        + e.lambda_nu * t["Nu"], rel=1e-15)
+    worst = 0.0
+    for c in (0, 1, e.n_chan - 1):
+        for _ in range(2):
+            i, j = rng.integers(0, e.n_sky, 2)
+            h = 0.5
+            xp, xm = x.copy(), x.copy()
+            xp[c, i, j] += h
+            xm[c, i, j] -= h
+            fd = (oracle_mod.objective_grad(e, xp)[0]["Q_tot"] - oracle_mod.objective_grad(e, xm)[0]["Q_tot"]) / (2 * h)
+            worst = max(worst, abs(fd - g[c, i, j]) / max(abs(g[c, i, j]), 1e-3 * np.abs(g).max()))
+    assert worst < 1e-7, worst
