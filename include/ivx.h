@@ -5,6 +5,7 @@
  * What is evaluated (Sect. 2.1, 2.2, 2.4; Eq. Q, Eq. 3, Eq. fusion_cost):
  *
  *   Q_tot(x) = sum_{k,c} J_kc(x) + lambda_s sum_c K_c(x) + lambda_r sum_c R_c(x)
+ *              + lambda_nu R_nu(x)
  *
  *   J_kc = 1/2 sum_j w_j | V_j - y_j |^2   over the unflagged visibilities of pointing k,
  *          channel c, with w_j = 1/sigma_j^2 (the SIGMA column, Sect. 2.2) and the model
@@ -21,6 +22,9 @@
  *          with a unit-sum Gaussian single-dish beam (FWHM sd_fwhm_rad, truncated at
  *          4 sigma, zero padding), point-sampled at rows/cols sd_offset + p*sd_stride
  *          (fusion term, Sect. 2.4).
+ *   R_nu = 1/2 sum_{c=0}^{C-2} || x_{c+1} - x_c ||^2, a spectral smoothness term coupling
+ *          adjacent channels (an extension of the regulariser family of Sect. 2.2-2.3; the
+ *          paper's own solves keep channels independent, lambda_nu = 0).
  *
  * The gradient returned is dQ_tot/dx over the whole cube, in the same layout as x.
  * The visibility model is evaluated with a non-uniform FFT (exponential-of-semicircle
@@ -70,7 +74,7 @@ typedef double ivx_real;
 typedef float ivx_real;
 #endif
 
-#define IVX_VERSION 1
+#define IVX_VERSION 2
 
 typedef enum {
     IVX_OK = 0,
@@ -104,6 +108,7 @@ typedef struct {
     int32_t fine_size;          /* fine grid n_f, power of two >= 2 n_sub (0 = auto) */
     int32_t tile;               /* gridding tile edge in fine cells (0 = auto) */
     int32_t reserved;           /* must be 0 */
+    double lambda_nu;           /* spectral smoothness weight, >= 0 (0 = channels independent) */
 } ivx_problem;
 
 /* Validate `d`, choose the NUFFT parameters and allocate the plan.  No device memory is
@@ -254,6 +259,10 @@ ivx_status ivx_set_fused_fold(ivx_plan *plan, int enable);
  * window, waves_per_block, max_vis_per_work_item, lanes_per_visibility,
  * visibilities_per_group_iteration}. */
 ivx_status ivx_plan_info(const ivx_plan *plan, int64_t *info16);
+
+/* The terms of the last evaluation on the plan's stream, host array of 5 doubles: {Q_tot, Q,
+ * K, R, R_nu} (the evaluation calls return the first four).  Synchronises `stream`. */
+ivx_status ivx_last_terms(ivx_plan *plan, double *terms5, void *stream);
 
 /* Release every resource of the plan (NULL is accepted). */
 ivx_status ivx_plan_destroy(ivx_plan *plan);

@@ -40,7 +40,7 @@ class _Problem(ctypes.Structure):
         ("sd_n", ctypes.c_int32), ("sd_stride", ctypes.c_int32), ("sd_offset", ctypes.c_int32),
         ("sd_fwhm_rad", ctypes.c_double), ("sd_sigma", ctypes.c_double), ("nufft_eps", ctypes.c_double),
         ("kernel_width", ctypes.c_int32), ("fine_size", ctypes.c_int32), ("tile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("lambda_nu", ctypes.c_double),
     ]
 
 
@@ -48,7 +48,7 @@ EXPORTS = ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_fo
            "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_last_error", "ivx_version",
            "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking",
            "ivx_plan_set_vis", "ivx_set_gridder_occupancy", "ivx_set_fused_fold", "ivx_objective",
-           "ivx_objective_forward", "ivx_objective_backward", "ivx_forward_adjoint")
+           "ivx_objective_forward", "ivx_objective_backward", "ivx_forward_adjoint", "ivx_last_terms")
 
 STAGES = ("image_rows", "col_fwd", "grid", "fold", "col_inv", "row_inv", "sd", "sky", "final")
 
@@ -84,6 +84,7 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
     lib.ivx_objective_forward.argtypes = [vp, vp, vp, vp]
     lib.ivx_objective_backward.argtypes = [vp, vp, vp, dbl, vp]
     lib.ivx_forward_adjoint.argtypes = [vp, vp, vp, vp]
+    lib.ivx_last_terms.argtypes = [vp, vp, vp]
     lib.ivx_stage_times.argtypes = [vp, vp, vp]
     lib.ivx_last_error.restype = ctypes.c_char_p
     lib.ivx_last_error.argtypes = []
@@ -91,7 +92,7 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
               "ivx_adjoint", "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_set_timing",
               "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking", "ivx_plan_set_vis",
               "ivx_set_gridder_occupancy", "ivx_set_fused_fold", "ivx_objective", "ivx_objective_forward",
-              "ivx_objective_backward", "ivx_forward_adjoint"):
+              "ivx_objective_backward", "ivx_forward_adjoint", "ivx_last_terms"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ivx_version.restype = ctypes.c_int
     lib.ivx_real_size.restype = ctypes.c_int
@@ -136,7 +137,7 @@ class Plan:
 
     def __init__(self, n_chan, n_sky, pixel_rad, n_point, n_sub, vis_offsets, flux_scale,
                  lambda_r=0.0, lambda_s=0.0, sd_n=0, sd_stride=0, sd_offset=0, sd_fwhm_rad=0.0,
-                 sd_sigma=0.0, precision="f32", nufft_eps=0.0, kernel_width=0, fine_size=0, tile=0):
+                 sd_sigma=0.0, precision="f32", nufft_eps=0.0, kernel_width=0, fine_size=0, tile=0, lambda_nu=0.0):
         self.lib = load_library(precision)
         self.precision = precision
         self.np_real = np.float32 if precision == "f32" else np.float64
@@ -154,6 +155,8 @@ class Plan:
         d.sd_n, d.sd_stride, d.sd_offset = int(sd_n), int(sd_stride), int(sd_offset)
         d.sd_fwhm_rad, d.sd_sigma, d.nufft_eps = float(sd_fwhm_rad), float(sd_sigma), float(nufft_eps)
         d.kernel_width, d.fine_size, d.tile, d.reserved = int(kernel_width), int(fine_size), int(tile), 0
+        d.lambda_nu = float(lambda_nu)
+        self.lambda_nu = float(lambda_nu)
         h = ctypes.c_void_p()
         self._check(self.lib.ivx_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -165,7 +168,7 @@ class Plan:
                    lambda_r=p.lambda_r, lambda_s=p.lambda_s if sd_on else 0.0,
                    sd_n=p.sd_n if sd_on else 0, sd_stride=p.sd_stride if sd_on else 0,
                    sd_offset=p.sd_offset if sd_on else 0, sd_fwhm_rad=p.sd_fwhm_rad if sd_on else 0.0,
-                   sd_sigma=p.sd_sigma if sd_on else 0.0, **kw)
+                   sd_sigma=p.sd_sigma if sd_on else 0.0, lambda_nu=float(getattr(p, "lambda_nu", 0.0)), **kw)
 
     # -------------------------------------------------------------------- plumbing
     def _check(self, code):
@@ -362,6 +365,12 @@ class Plan:
         n = np.zeros(1, dtype=np.int64)
         self._check(self.lib.ivx_stage_times(self._h, ms.ctypes.data, n.ctypes.data))
         return dict(zip(STAGES, ms.tolist())), int(n[0])
+
+    def last_terms(self, stream=None) -> np.ndarray:
+        """{Q_tot, Q, K, R, R_nu} of the last evaluation (synchronises the stream)."""
+        t = np.zeros(5, dtype=np.float64)
+        self._check(self.lib.ivx_last_terms(self._h, t.ctypes.data, _stream_ptr(stream)))
+        return t
 
     def info(self) -> dict:
         a = np.zeros(16, dtype=np.int64)

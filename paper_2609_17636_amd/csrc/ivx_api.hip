@@ -157,6 +157,7 @@ struct ivx_plan {
     CsrEnt *d_cent = nullptr;  // and entries
     real *d_sdmap = nullptr, *d_gB = nullptr, *d_U = nullptr, *d_E = nullptr;
     double *d_jpart = nullptr, *d_rpart = nullptr, *d_kpart = nullptr, *d_terms = nullptr;
+    double *d_npart = nullptr; // spectral-term partial per sky block
     int n_rpart = 0, n_kpart = 0;
     size_t dev_bytes = 0;
     // per-tile device arrays that depend on the tile size
@@ -228,6 +229,7 @@ void free_all(ivx_plan *p) {
     p->d_cent = nullptr;
     p->d_sdmap = p->d_gB = p->d_U = p->d_E = nullptr;
     p->d_jpart = p->d_rpart = p->d_kpart = p->d_terms = nullptr;
+    p->d_npart = nullptr;
     p->has_data = false;
 }
 
@@ -657,6 +659,9 @@ ivx_status run_adjoint_half(ivx_plan *p, hipStream_t st) {
 
 bool sd_active(const ivx_plan *p) { return p->d.lambda_s != 0.0 && p->d.sd_n > 0; }
 
+// weight of the spectral term as the sky pass sees it (0 when it is off or there is one channel)
+real spec_weight(const ivx_plan *p) { return p->g.C > 1 ? (real)p->d.lambda_nu : real(0); }
+
 // Event pair around one stage when timing is on (start before the launch, stop after).
 hipEvent_t next_event(ivx_plan *p) {
     if (p->ev_next == p->ev_pool.size()) {
@@ -732,13 +737,13 @@ ivx_status eval_objective(ivx_plan *p, const real *sky, real *grad, double *term
         StageTimer t(p, st, IVX_STAGE_SKY);
         IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r,
                            sd ? (real)p->d.lambda_s : real(0), p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride,
-                           p->d.sd_offset, grad, p->d_rpart, SKY_FULL, real(1), st));
+                           p->d.sd_offset, grad, p->d_rpart, SKY_FULL, real(1), st, spec_weight(p), p->d_npart));
     }
     {
         StageTimer t(p, st, IVX_STAGE_FINAL);
         IVX_HIP(launch_final(p->d_jpart, p->n_work, p->d_jpart + p->n_work, p->d_rpart, p->n_rpart, p->d_kpart,
-                             sd ? p->n_kpart : 0,
-                             p->d.lambda_r, sd ? p->d.lambda_s : 0.0, p->d_terms, terms_dev, st));
+                             sd ? p->n_kpart : 0, p->d_npart, spec_weight(p) != real(0) ? p->n_rpart : 0,
+                             p->d.lambda_r, sd ? p->d.lambda_s : 0.0, p->d.lambda_nu, p->d_terms, terms_dev, st));
     }
     return IVX_OK;
 }
@@ -762,9 +767,10 @@ ivx_status eval_value(ivx_plan *p, const real *sky, double *terms_dev, int grid_
             IVX_HIP(launch_sd_back(g, p->d_E, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_U, st));
     }
     IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r, real(0), nullptr, nullptr, 0, 0, 1,
-                       0, nullptr, p->d_rpart, SKY_VALUE, real(1), st));
+                       0, nullptr, p->d_rpart, SKY_VALUE, real(1), st, spec_weight(p), p->d_npart));
     IVX_HIP(launch_final(p->d_jpart, p->n_work, p->d_jpart + p->n_work, p->d_rpart, p->n_rpart, p->d_kpart,
-                         sd ? p->n_kpart : 0, p->d.lambda_r, sd ? p->d.lambda_s : 0.0, p->d_terms, terms_dev, st));
+                         sd ? p->n_kpart : 0, p->d_npart, spec_weight(p) != real(0) ? p->n_rpart : 0, p->d.lambda_r,
+                         sd ? p->d.lambda_s : 0.0, p->d.lambda_nu, p->d_terms, terms_dev, st));
     return IVX_OK;
 }
 
@@ -777,7 +783,7 @@ ivx_status eval_gradient(ivx_plan *p, const real *sky, real *grad, real scale, h
     const bool sd = sd_active(p);
     IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r, sd ? (real)p->d.lambda_s : real(0),
                        p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, grad, p->d_rpart,
-                       SKY_FULL, scale, st));
+                       SKY_FULL, scale, st, spec_weight(p), p->d_npart));
     return IVX_OK;
 }
 
@@ -835,6 +841,7 @@ ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out) {
     if (!d->vis_offsets || !d->flux_scale) return fail(IVX_EINVAL, "vis_offsets and flux_scale are required");
     if (!(d->lambda_r >= 0.0) || !(d->lambda_s >= 0.0) || !std::isfinite(d->lambda_r) || !std::isfinite(d->lambda_s))
         return fail(IVX_EINVAL, "lambda_r and lambda_s must be finite and >= 0");
+    if (!(d->lambda_nu >= 0.0) || !std::isfinite(d->lambda_nu)) return fail(IVX_EINVAL, "lambda_nu must be finite and >= 0");
     if (d->reserved != 0) return fail(IVX_EINVAL, "reserved must be 0");
     const int64_t nb = (int64_t)d->n_point * d->n_chan;
     if (nb > (1 << 24)) return fail(IVX_EINVAL, "too many (pointing, channel) blocks");
@@ -1009,6 +1016,16 @@ ivx_status ivx_stage_times(ivx_plan *p, double *ms, int64_t *n_eval) {
     return IVX_OK;
 }
 
+ivx_status ivx_last_terms(ivx_plan *p, double *terms5, void *stream) {
+    ivx_status s = check_plan(p);
+    if (s != IVX_OK) return s;
+    if (!terms5) return fail(IVX_EINVAL, "terms5 is required");
+    hipStream_t st = (hipStream_t)stream;
+    IVX_HIP(hipMemcpyAsync(terms5, p->d_terms, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+    IVX_HIP(hipStreamSynchronize(st));
+    return IVX_OK;
+}
+
 ivx_status ivx_plan_destroy(ivx_plan *plan) {
     if (!plan) return IVX_OK;
     for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
@@ -1110,9 +1127,10 @@ ivx_status set_data_impl(ivx_plan *p, const VisSource &src, bool shared, const i
     if ((s = dalloc(p, &p->d_interp, h_interp.size())) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_R, (size_t)n_items * g.r_stride)) != IVX_OK) goto fail_free;
     if ((s = dalloc(p, &p->d_gp, (size_t)n_items * nk2)) != IVX_OK) goto fail_free;
-    if ((s = dalloc(p, &p->d_terms, 4)) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_terms, 5)) != IVX_OK) goto fail_free;
     p->n_rpart = sky_blocks(g);
     if ((s = dalloc(p, &p->d_rpart, p->n_rpart)) != IVX_OK) goto fail_free;
+    if ((s = dalloc(p, &p->d_npart, p->n_rpart)) != IVX_OK) goto fail_free;
     {
         std::vector<real> fs(g.C);
         for (int c = 0; c < g.C; ++c) fs[c] = (real)p->fscale[c];

@@ -113,17 +113,21 @@ hipError_t launch_sd_back(const Geom &g, const real *E, const real *gB, int rb, 
 // Sky pass modes: the whole gradient and R; the reprojection transpose alone (adjoint); R
 // alone (no gradient written).  The gradient is multiplied by `scale`.
 enum SkyMode { SKY_FULL = 0, SKY_ADJOINT = 1, SKY_VALUE = 2 };
+// lambda_nu != 0 adds the spectral term (channels c - 1 and c + 1 of the sky are read) and its
+// per-block values go to npart (one double per sky block, like rpart).
 hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int32_t *cptr,
                       const CsrEnt *cent, real lambda_r, real lambda_s, const real *E,
                       const real *gB, int rb, int sd_n, int stride, int offset, real *grad,
-                      double *rpart, int mode, real scale, hipStream_t st);
+                      double *rpart, int mode, real scale, hipStream_t st, real lambda_nu = real(0),
+                      double *npart = nullptr);
 int sky_blocks(const Geom &g);
 // FP64 reduction of all partials into {Q_tot, Q, K, R} (terms, and terms_user if non-null).
 // jpart: per-work-item partials of J; scratch: final_scratch(nj) doubles (may be 0)
 int final_scratch(int nj);
+// terms receives {Q_tot, Q, K, R, R_nu} (5 doubles), terms_user the first four.
 hipError_t launch_final(const double *jpart, int nj, double *scratch, const double *rpart, int nr,
-                        const double *kpart, int nkp, double lambda_r, double lambda_s, double *terms,
-                        double *terms_user, hipStream_t st);
+                        const double *kpart, int nkp, const double *npart, int nnp, double lambda_r,
+                        double lambda_s, double lambda_nu, double *terms, double *terms_user, hipStream_t st);
 hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st);
 
 // ---------------------------------------------------------------- plan-time binning

@@ -1413,6 +1413,8 @@ struct SkyArgs {
     double *rpart;
     int mode;   // SkyMode
     real scale; // gradient multiplier
+    real lambda_nu;
+    double *npart;
 };
 
 constexpr int SKY_LOADS = 8; // CSR entries per lane in flight in k_sky
@@ -1441,6 +1443,8 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
     const bool adjoint_only = a.mode == SKY_ADJOINT, value_only = a.mode == SKY_VALUE;
     const bool reg = (a.lambda_r != real(0)) && !adjoint_only;
     const bool sd = (a.lambda_s != real(0)) && (a.sd_n > 0) && !adjoint_only && !value_only;
+    const bool spec = (a.lambda_nu != real(0)) && !adjoint_only && g.C > 1;
+    double nloc = 0.0;
     double rloc = 0.0;
     if (reg) {
         for (int e = tid; e < (SKY_T + 4) * (SKY_T + 4); e += NT) {
@@ -1460,6 +1464,18 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
         __syncthreads();
     }
     const int i = i0 + ti, j = j0 + tj;
+    // spectral term: this pixel in the neighbouring channels
+    real xc = real(0), xm = real(0), xp = real(0);
+    if (spec && i < N && j < N) {
+        const int64_t pix = (int64_t)i * N + j, cs = (int64_t)N * N;
+        xc = x[pix];
+        if (c > 0) xm = x[pix - cs];
+        if (c + 1 < g.C) {
+            xp = x[pix + cs];
+            const real d = xp - xc;
+            nloc = 0.5 * (double)d * (double)d;
+        }
+    }
     if (value_only) {
         if (reg && i < N && j < N) {
             const real d = dxs[ti + 1][tj + 1];
@@ -1502,6 +1518,12 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
             for (int pp = p0; pp <= p1; ++pp) s += a.gB[o + pp * S - i + rb] * Vc[(int64_t)pp * N + j];
             gsum += a.lambda_s * s;
         }
+        if (spec) {
+            real ds = real(0);
+            if (c > 0) ds += xc - xm;
+            if (c + 1 < g.C) ds -= xp - xc;
+            gsum += a.lambda_nu * ds;
+        }
         a.grad[(int64_t)c * N * N + p] = a.scale == real(1) ? gsum : a.scale * gsum;
     }
     if (!adjoint_only) {
@@ -1512,6 +1534,17 @@ __global__ __launch_bounds__(NT) void k_sky(SkyArgs a) {
             double s = 0.0;
             for (int w = 0; w < NT / 64; ++w) s += red[w];
             a.rpart[bw] = s;
+        }
+        if (spec) {
+            __syncthreads(); // red is reused
+            for (int m = 32; m >= 1; m >>= 1) nloc += __shfl_xor(nloc, m, 64);
+            if ((tid & 63) == 0) red[tid >> 6] = nloc;
+            __syncthreads();
+            if (tid == 0) {
+                double s = 0.0;
+                for (int w = 0; w < NT / 64; ++w) s += red[w];
+                a.npart[bw] = s;
+            }
         }
     }
 }
@@ -1547,11 +1580,12 @@ constexpr int FINAL_PER = 1024; // work-item partials per pre-reduction block
 __global__ __launch_bounds__(NT_FINAL) void k_final(const double *__restrict__ jpart, int nj,
                                                     const double *__restrict__ rpart, int nr,
                                                     const double *__restrict__ kpart, int nkp,
-                                                    double lambda_r, double lambda_s, double *terms,
-                                                    double *terms_user) {
-    __shared__ double sh[3][NT_FINAL / 64];
+                                                    const double *__restrict__ npart, int nnp,
+                                                    double lambda_r, double lambda_s, double lambda_nu,
+                                                    double *terms, double *terms_user) {
+    __shared__ double sh[4][NT_FINAL / 64];
     const int tid = threadIdx.x;
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
     // each thread sums its strided entries in index order; 8 loads are issued before they
     // are added, so their latencies overlap instead of chaining
     auto strided_sum = [&](const double *__restrict__ p, int n, double &acc) {
@@ -1568,24 +1602,27 @@ __global__ __launch_bounds__(NT_FINAL) void k_final(const double *__restrict__ j
     strided_sum(jpart, nj, v[0]);
     strided_sum(rpart, nr, v[1]);
     strided_sum(kpart, nkp, v[2]);
+    strided_sum(npart, nnp, v[3]);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 4; ++q) {
         for (int m = 32; m >= 1; m >>= 1) v[q] += __shfl_xor(v[q], m, 64);
         if ((tid & 63) == 0) sh[q][tid >> 6] = v[q];
     }
     __syncthreads();
     if (tid == 0) {
-        double Q = 0.0, R = 0.0, K = 0.0;
+        double Q = 0.0, R = 0.0, K = 0.0, Nu = 0.0;
         for (int w = 0; w < NT_FINAL / 64; ++w) {
             Q += sh[0][w];
             R += sh[1][w];
             K += sh[2][w];
+            Nu += sh[3][w];
         }
-        const double t4[4] = {Q + lambda_s * K + lambda_r * R, Q, K, R};
-        for (int q = 0; q < 4; ++q) {
-            terms[q] = t4[q];
-            if (terms_user) terms_user[q] = t4[q];
-        }
+        double qt = Q + lambda_s * K + lambda_r * R;
+        if (lambda_nu != 0.0) qt += lambda_nu * Nu;
+        const double t5[5] = {qt, Q, K, R, Nu};
+        for (int q = 0; q < 5; ++q) terms[q] = t5[q];
+        if (terms_user)
+            for (int q = 0; q < 4; ++q) terms_user[q] = t5[q];
     }
 }
 
@@ -1855,9 +1892,12 @@ int sky_blocks(const Geom &g) {
 
 hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int32_t *cptr, const CsrEnt *cent,
                       real lambda_r, real lambda_s, const real *E, const real *gB, int rb, int sd_n, int stride,
-                      int offset, real *grad, double *rpart, int mode, real scale, hipStream_t st) {
+                      int offset, real *grad, double *rpart, int mode, real scale, hipStream_t st, real lambda_nu,
+                      double *npart) {
     const int nb = (g.N + SKY_T - 1) / SKY_T;
-    SkyArgs a{g, sky, gp, cptr, cent, lambda_r, lambda_s, E, gB, rb, sd_n, stride, offset, grad, rpart, mode, scale};
+    if (lambda_nu != real(0) && !npart) return hipErrorInvalidValue;
+    SkyArgs a{g,    sky,  gp,    cptr,  cent,      lambda_r, lambda_s, E, gB, rb, sd_n, stride, offset, grad, rpart,
+              mode, scale, lambda_nu, npart};
     const int64_t total = (int64_t)nb * nb * g.C;
     k_sky<<<dim3((unsigned)(8 * ((total + 7) / 8))), NT, 0, st>>>(a);
     return hipGetLastError();
@@ -1866,8 +1906,8 @@ hipError_t launch_sky(const Geom &g, const real *sky, const real *gp, const int3
 int final_scratch(int nj) { return nj > 32 * FINAL_PER ? (nj + FINAL_PER - 1) / FINAL_PER : 0; }
 
 hipError_t launch_final(const double *jpart, int nj, double *scratch, const double *rpart, int nr,
-                        const double *kpart, int nkp, double lambda_r, double lambda_s, double *terms,
-                        double *terms_user, hipStream_t st) {
+                        const double *kpart, int nkp, const double *npart, int nnp, double lambda_r,
+                        double lambda_s, double lambda_nu, double *terms, double *terms_user, hipStream_t st) {
     const int nb = final_scratch(nj);
     if (nb > 0) {
         // long per-work-item lists (large mosaics): pre-reduce in fixed blocks first
@@ -1875,7 +1915,8 @@ hipError_t launch_final(const double *jpart, int nj, double *scratch, const doub
         jpart = scratch;
         nj = nb;
     }
-    k_final<<<1, NT_FINAL, 0, st>>>(jpart, nj, rpart, nr, kpart, nkp, lambda_r, lambda_s, terms, terms_user);
+    k_final<<<1, NT_FINAL, 0, st>>>(jpart, nj, rpart, nr, kpart, nkp, npart, nnp, lambda_r, lambda_s, lambda_nu, terms,
+                                    terms_user);
     return hipGetLastError();
 }
 

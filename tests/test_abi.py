@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(precision):
     assert len(names) >= 30
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.ivx_version() == 1
+    assert lib.ivx_version() == 2
     assert lib.ivx_real_size() == (4 if precision == "f32" else 8)
 
 

@@ -81,6 +81,37 @@ def test_c4_mini_objective_and_gradient(mini, precision):
         assert rel(grad, want_g) <= tol
 
 
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_c4_mini_spectral_term(mini, precision):
+    """The spectral smoothness term couples adjacent channels: the terms (with R_nu from
+    ivx_last_terms) and the gradient against the oracle, for the fused evaluation, the
+    value-only evaluation and the forward/backward split."""
+    import copy
+
+    q = copy.copy(mini)
+    q.lambda_nu = 0.25
+    e = q.expand()
+    plan = _cube_plan(q, precision)
+    tol = TOL[precision]
+    rng = np.random.default_rng(47)
+    x = rng.uniform(0, 50, size=e.x_true.shape)
+    want_t, want_g = oracle.objective_grad(e, x)
+    assert want_t["Nu"] > 0
+    terms, grad = _eval(plan, x)
+    t5 = plan.last_terms()
+    print(f"[c4-mini spectral {precision}] relQ {abs(terms[0] - want_t['Q_tot']) / want_t['Q_tot']:.2e} "
+          f"relNu {abs(t5[4] - want_t['Nu']) / want_t['Nu']:.2e} relG {rel(grad, want_g):.2e}", flush=True)
+    assert abs(terms[0] - want_t["Q_tot"]) <= tol * want_t["Q_tot"]
+    assert abs(t5[4] - want_t["Nu"]) <= tol * want_t["Nu"]
+    assert np.array_equal(t5[:4], terms)
+    assert rel(grad, want_g) <= tol
+    xt = torch.tensor(x, dtype=plan.torch_dtype, device="cuda")
+    assert np.array_equal(plan.objective(xt), terms)
+    plan.objective_forward(xt)
+    g2 = plan.objective_backward(xt).double().cpu().numpy()
+    assert np.array_equal(g2, grad)
+
+
 def test_c4_mini_forward_uses_each_channel_scale(mini):
     e = mini.expand()
     plan = _cube_plan(mini)
