@@ -99,3 +99,45 @@ def resample_beam(beam: np.ndarray, beam_delta: float, n_sub: int, sub_delta: fl
     nb = beam.shape[0]
     L, M = pixel_lm(n_sub, sub_delta)
     return bilinear(beam, M / beam_delta + nb // 2, L / beam_delta + nb // 2)
+
+
+def linear_mosaic(sub_images: np.ndarray, beams: np.ndarray, deproj: np.ndarray, pb_min: float = 0.0):
+    """Eq. linear and Eq. pb_eff (Sect. 4.4.1): every pointing's image I'_k (sub_images
+    [P][C][n][n]) and beam A_k ([P][n][n]) are sampled at the sky pixels' positions in its
+    sub-image (deproj [P][N][N][2], Eq. sin_deprojection; bilinear, 0 outside), and
+    I = sum_k A_k^2 I'_k / sum_k A_k^2 where sqrt(sum_k A_k^2) >= pb_min (0 elsewhere);
+    A_eff = sqrt(sum_k A_k^2).  Returns (image [C][N][N], A_eff [N][N])."""
+    P, C = sub_images.shape[:2]
+    N = deproj.shape[1]
+    num = np.zeros((C, N, N))
+    den = np.zeros((N, N))
+    for k in range(P):
+        rows, cols = deproj[k][..., 0].astype(np.float64), deproj[k][..., 1].astype(np.float64)
+        A = bilinear(beams[k], rows, cols)
+        den += A * A
+        for c in range(C):
+            num[c] += A * A * bilinear(sub_images[k, c], rows, cols)
+    keep = (den > 0) & (den >= pb_min * pb_min)
+    image = np.where(keep[None], num / np.where(keep, den, 1.0)[None], 0.0)
+    return image, np.sqrt(den)
+
+
+def feather_transfer(n: int, delta: float, theta: float) -> np.ndarray:
+    """B(k) = exp(-2 pi^2 sigma^2 |k|^2), sigma = theta / (2 sqrt(2 ln 2)) (App. B), on the
+    n x n FFT frequency grid of pixel size delta (cycles per radian)."""
+    sigma = theta / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+    f = np.fft.fftfreq(n, d=delta)
+    k2 = f[:, None] ** 2 + f[None, :] ** 2
+    return np.exp(-2.0 * np.pi ** 2 * sigma ** 2 * k2)
+
+
+def feather(interf: np.ndarray, single_dish: np.ndarray, delta: float, theta: float) -> np.ndarray:
+    """App. B: I_comb = F^-1[B F[I_SD] + (1 - B) F[I_int]] per channel ([C][n][n] maps)."""
+    interf = np.asarray(interf, dtype=np.float64)
+    single_dish = np.asarray(single_dish, dtype=np.float64)
+    B = feather_transfer(interf.shape[-1], delta, theta)
+    out = np.empty_like(interf)
+    for c in range(interf.shape[0]):
+        comb = B * np.fft.fft2(single_dish[c]) + (1.0 - B) * np.fft.fft2(interf[c])
+        out[c] = np.fft.ifft2(comb).real
+    return out

@@ -92,3 +92,61 @@ def test_beam_resampling_special_cases():
     np.testing.assert_allclose(out[ok], want[ok], atol=1e-14)
     # outside the beam image: 0
     assert D.resample_beam(beam, 1 * ARCSEC, 64, 30 * ARCSEC)[0, 0] == 0.0
+
+
+def test_feather_special_cases():
+    """B(0) = 1 and B + (1 - B) = 1: equal maps come back unchanged and the total flux is the
+    single dish's; one Fourier mode of the interferometric map alone is scaled by 1 - B(k),
+    with B(k) = exp(-2 pi^2 sigma^2 k^2), sigma = theta / (2 sqrt(2 ln 2)); theta = 0 keeps
+    the single-dish map."""
+    rng = np.random.default_rng(4)
+    n, delta, theta = 64, 30 * ARCSEC, 20 * 60 * ARCSEC
+    a = rng.standard_normal((2, n, n))
+    np.testing.assert_allclose(D.feather(a, a, delta, theta), a, atol=1e-12)
+    sd = rng.standard_normal((1, n, n)) + 3.0
+    out = D.feather(a[:1], sd, delta, theta)
+    assert out.mean() == pytest.approx(sd.mean(), rel=1e-12)
+    p, q = 5, 3
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    mode = np.cos(2 * np.pi * (q * i + p * j) / n)[None]
+    sigma = theta / (2 * np.sqrt(2 * np.log(2)))
+    k2 = (p * p + q * q) / (n * delta) ** 2
+    want = (1 - np.exp(-2 * np.pi ** 2 * sigma ** 2 * k2)) * mode
+    np.testing.assert_allclose(D.feather(mode, np.zeros_like(mode), delta, theta), want, atol=1e-12)
+    np.testing.assert_allclose(D.feather(a[:1], sd, delta, 0.0), sd, atol=1e-12)
+
+
+def test_linear_mosaic_special_cases():
+    """One pointing under a constant beam returns its (deprojected) image, a plane being
+    sampled exactly; pointings that all see the same constant give that constant wherever
+    covered; A_eff is sqrt(sum A_k^2); pixels below pb_min are 0."""
+    ra0, dec0 = 1.38, -1.205
+    d = 30 * ARCSEC
+    N, n = 96, 48
+    dg, _ = D.deprojection_grid(N, d, ra0, dec0, n, d, ra0, dec0)
+    a, b = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float), indexing="ij")
+    plane = 1.0 + 0.02 * a - 0.01 * b
+    img, peff = D.linear_mosaic(plane[None, None], np.full((1, n, n), 0.5), dg[None])
+    inner = (dg[..., 0] >= 0) & (dg[..., 0] <= n - 1) & (dg[..., 1] >= 0) & (dg[..., 1] <= n - 1)
+    want = 1.0 + 0.02 * dg[..., 0] - 0.01 * dg[..., 1]
+    np.testing.assert_allclose(img[0][inner], want[inner], atol=1e-12)
+    np.testing.assert_allclose(peff[inner], 0.5, atol=1e-14)
+    rak = ra0 + 4 * d / np.cos(dec0)
+    dg2, _ = D.deprojection_grid(N, d, ra0, dec0, n, d, rak, dec0)
+    beams = np.stack([np.full((n, n), 0.5), np.full((n, n), 0.8)])
+    img, peff = D.linear_mosaic(np.full((2, 1, n, n), 3.0), beams, np.stack([dg, dg2]))
+    # pixels whose bilinear taps lie wholly inside or wholly outside each sub-image (at an edge
+    # the zero padding weighs beam and image alike, so their ratio is not the constant)
+    clean = np.ones((N, N), dtype=bool)
+    for g in (dg, dg2):
+        inside = (g[..., 0] >= 0) & (g[..., 0] <= n - 1) & (g[..., 1] >= 0) & (g[..., 1] <= n - 1)
+        outside = (g[..., 0] <= -1) | (g[..., 0] >= n) | (g[..., 1] <= -1) | (g[..., 1] >= n)
+        clean &= inside | outside
+    both = clean & (peff > 0)
+    assert both.sum() > 1000
+    np.testing.assert_allclose(img[0][both], 3.0, atol=1e-12)
+    np.testing.assert_allclose(peff[both & (np.abs(dg2[..., 0] - 24) < 20) & (np.abs(dg[..., 0] - 24) < 20)
+                                    & (np.abs(dg2[..., 1] - 24) < 20) & (np.abs(dg[..., 1] - 24) < 20)],
+                               np.sqrt(0.25 + 0.64), atol=1e-12)
+    img, _ = D.linear_mosaic(np.full((2, 1, n, n), 3.0), beams, np.stack([dg, dg2]), pb_min=0.9)
+    assert np.all(img[0][peff < 0.9] == 0.0) and np.all(np.abs(img[0][both & (peff >= 0.9)] - 3.0) < 1e-12)
