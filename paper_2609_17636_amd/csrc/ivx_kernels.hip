@@ -1630,6 +1630,100 @@ __global__ __launch_bounds__(NT) void k_zero(uint32_t *p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) p[i] = 0u;
 }
 
+// ------------------------------------------------------------------------ feathering
+// App. B: out = F^-1[B F[sd] + (1 - B) F[int]] = int + F^-1[B F[sd - int]] (B real and even),
+// per channel of n x n maps: a real row FFT of the difference (two rows packed in one complex
+// transform, half spectrum kept), a column FFT, the Gaussian transfer function
+// B(k) = exp(-2 pi^2 sigma^2 |k|^2), the inverse column FFT, and the inverse row FFT, added to
+// the interferometric map with the 1 / n^2 of the unscaled transform pair.  Work: the
+// half-spectra [C][n][n/2 + 1] complex.  Twiddles are formed in LDS from FP64 sincospi.
+template <int LOGN> __device__ __forceinline__ void tw_fill(cpx *tws) {
+    constexpr int N = 1 << LOGN;
+    for (int t = threadIdx.x; t < tw_len<LOGN>(); t += NT) {
+        double sv, cv;
+        sincospi(-2.0 * (double)t / (double)N, &sv, &cv);
+        tws[t] = cpx{(real)cv, (real)sv};
+    }
+}
+
+template <int LOGN>
+__global__ __launch_bounds__(NT) void k_feather_rows(const real *__restrict__ interf, const real *__restrict__ sd,
+                                                     cpx *__restrict__ work) {
+    constexpr int N = 1 << LOGN, RW = N / 2 + 1;
+    __shared__ cpx buf[N];
+    __shared__ cpx tws[tw_len<LOGN>()];
+    const int c = blockIdx.y, a0 = 2 * blockIdx.x;
+    const int64_t base = ((int64_t)c * N + a0) * N;
+    for (int b = threadIdx.x; b < N; b += NT)
+        buf[b] = cpx{sd[base + b] - interf[base + b], sd[base + N + b] - interf[base + N + b]};
+    tw_fill<LOGN>(tws);
+    __syncthreads();
+    fft_lds<LOGN, 1, false>(buf, tws);
+    cpx *W0 = work + ((int64_t)c * N + a0) * RW, *W1 = W0 + RW;
+    for (int kk = threadIdx.x; kk < RW; kk += NT) {
+        const cpx z = buf[kk], zm = buf[(N - kk) & (N - 1)];
+        W0[kk] = cpx{real(0.5) * (z.re + zm.re), real(0.5) * (z.im - zm.im)};
+        W1[kk] = cpx{real(0.5) * (z.im + zm.im), real(0.5) * (zm.re - z.re)};
+    }
+}
+
+template <int LOGN, int CB>
+__global__ __launch_bounds__(NT) void k_feather_cols(cpx *__restrict__ work, double knorm2) {
+    constexpr int N = 1 << LOGN, RW = N / 2 + 1;
+    __shared__ cpx buf[CB * N];
+    __shared__ cpx tws[tw_len<LOGN>()];
+    const int c = blockIdx.y, c0 = blockIdx.x * CB;
+    cpx *Wc = work + (int64_t)c * N * RW;
+    for (int e = threadIdx.x; e < N * CB; e += NT) {
+        const int q = e / CB, cc = e - q * CB;
+        buf[q * CB + cc] = c0 + cc < RW ? Wc[(int64_t)q * RW + c0 + cc] : cpx{0, 0};
+    }
+    tw_fill<LOGN>(tws);
+    __syncthreads();
+    fft_lds<LOGN, CB, false>(buf, tws);
+    // B(k) with k^2 = (p^2 + q^2) / (n delta)^2; knorm2 = 2 pi^2 sigma^2 / (n delta)^2
+    for (int e = threadIdx.x; e < N * CB; e += NT) {
+        const int q = e / CB, cc = e - q * CB;
+        const int qs = q < N / 2 ? q : q - N, ps = c0 + cc;
+        const real bk = (real)exp(-knorm2 * ((double)ps * ps + (double)qs * qs));
+        buf[e] = cpx{bk * buf[e].re, bk * buf[e].im};
+    }
+    __syncthreads();
+    fft_lds<LOGN, CB, true>(buf, tws);
+    for (int e = threadIdx.x; e < N * CB; e += NT) {
+        const int q = e / CB, cc = e - q * CB;
+        if (c0 + cc < RW) Wc[(int64_t)q * RW + c0 + cc] = buf[q * CB + cc];
+    }
+}
+
+template <int LOGN>
+__global__ __launch_bounds__(NT) void k_feather_rows_inv(const real *__restrict__ interf, const cpx *__restrict__ work,
+                                                         real *__restrict__ out) {
+    constexpr int N = 1 << LOGN, RW = N / 2 + 1;
+    __shared__ cpx buf[N];
+    __shared__ cpx tws[tw_len<LOGN>()];
+    const int c = blockIdx.y, a0 = 2 * blockIdx.x;
+    const cpx *X = work + ((int64_t)c * N + a0) * RW, *Y = X + RW;
+    for (int kk = threadIdx.x; kk < N; kk += NT) {
+        const int src = kk <= N / 2 ? kk : N - kk;
+        cpx x = X[src], y = Y[src];
+        if (kk > N / 2) {
+            x.im = -x.im;
+            y.im = -y.im;
+        }
+        buf[kk] = cpx{x.re - y.im, x.im + y.re}; // x + i y
+    }
+    tw_fill<LOGN>(tws);
+    __syncthreads();
+    fft_lds<LOGN, 1, true>(buf, tws);
+    const real sc = real(1) / ((real)N * (real)N);
+    const int64_t base = ((int64_t)c * N + a0) * N;
+    for (int b = threadIdx.x; b < N; b += NT) {
+        out[base + b] = interf[base + b] + sc * buf[b].re;
+        out[base + N + b] = interf[base + N + b] + sc * buf[b].im;
+    }
+}
+
 // ===================================================================== launchers
 
 #define IVX_LOGN_SWITCH(LOGN_VAR, ...)                       \
@@ -1917,6 +2011,25 @@ hipError_t launch_final(const double *jpart, int nj, double *scratch, const doub
     }
     k_final<<<1, NT_FINAL, 0, st>>>(jpart, nj, rpart, nr, kpart, nkp, npart, nnp, lambda_r, lambda_s, lambda_nu, terms,
                                     terms_user);
+    return hipGetLastError();
+}
+
+int64_t feather_work_bytes(int n_chan, int n) { return (int64_t)n_chan * n * (n / 2 + 1) * (int64_t)sizeof(cpx); }
+
+hipError_t launch_feather(int n_chan, int n, double delta, double theta, const real *interf, const real *sd, real *out,
+                          void *work, hipStream_t st) {
+    int logn = 0;
+    while ((1 << logn) < n) ++logn;
+    cpx *w = static_cast<cpx *>(work);
+    const double sigma = theta / (2.0 * sqrt(2.0 * log(2.0)));
+    const double knorm2 = 2.0 * M_PI * M_PI * sigma * sigma / ((double)n * delta * (double)n * delta);
+    const int rw = n / 2 + 1;
+    IVX_LOGN_SWITCH(logn, {
+        constexpr int CB = col_batch<L>();
+        k_feather_rows<L><<<dim3(n / 2, n_chan), NT, 0, st>>>(interf, sd, w);
+        k_feather_cols<L, CB><<<dim3((rw + CB - 1) / CB, n_chan), NT, 0, st>>>(w, knorm2);
+        k_feather_rows_inv<L><<<dim3(n / 2, n_chan), NT, 0, st>>>(interf, w, out);
+    });
     return hipGetLastError();
 }
 

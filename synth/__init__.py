@@ -381,7 +381,7 @@ def mosaic(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_rows: int, n
         x_true=x, noise=noise, noise_rule=("frac_peak", 0.01),
         sd_n=sd_n, sd_stride=sd_stride, sd_offset=sd_stride // 2,
         sd_fwhm_rad=sd_fwhm_arcmin * ARCMIN,
-        meta={"seed": seed, "freq_hz": freq_hz, "centres": centres},
+        meta={"seed": seed, "freq_hz": freq_hz, "centres": centres, "fwhm_rad": fwhm_px * pix},
     )
 
 
