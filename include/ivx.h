@@ -198,12 +198,24 @@ ivx_status ivx_adjoint(ivx_plan *plan, const ivx_real *vis, ivx_real *image, voi
  * <image, x>.  vis: device [M][2]; image: device [C][N][N], overwritten. */
 ivx_status ivx_forward_adjoint(ivx_plan *plan, const ivx_real *vis, ivx_real *image, void *stream);
 
-/* Time the gridding stage and its slot reduction for candidate blockings (tile edge,
- * waves per block, visibilities per work item) that fit the LDS, and keep the fastest.
- * The result is accuracy-neutral: only the blocking changes.  budget_ms bounds the time
- * spent; *chosen_tile (host, may be NULL) receives the tile edge kept.  The candidates
- * are timed on this plan's data. */
+/* Time whole evaluations of this plan's data (at a zero sky) for candidate blockings (tile
+ * edge, waves per block, visibilities per work item, gridder variant) that fit the LDS, and
+ * keep the fastest.  When the plan was created with kernel_width = 0 and fine_size = 0, the
+ * candidates also cover NUFFT geometries: on the plan's fine grid and on grids of half and
+ * twice its size, the narrowest kernel whose accuracy probe (ivx_nufft_probe) meets the
+ * plan's target -- nufft_eps when it was given, else the probe value of the plan's own
+ * geometry -- so the choice never makes the transform less accurate than that target.
+ * Blockings alone are accuracy-neutral.  budget_ms bounds the time spent; *chosen_tile
+ * (host, may be NULL) receives the tile edge kept; ivx_plan_info reports the kernel width
+ * and fine grid. */
 ivx_status ivx_autotune(ivx_plan *plan, double budget_ms, int32_t *chosen_tile, void *stream);
+
+/* Accuracy probe of a NUFFT geometry (sub-image edge n_sub, fine grid n_fine, kernel width):
+ * the largest error, over the sub-image frequencies and positions within one fine cell, of
+ * the one-dimensional transform of a unit point source computed with the library's spreading
+ * kernel and deapodization, against its closed form exp(-2 pi i k x / n_fine) (Sect. 2.1's
+ * model for one source).  The two-dimensional error is at most about twice this. */
+ivx_status ivx_nufft_probe(int32_t n_sub, int32_t n_fine, int32_t kernel_width, double *err);
 
 /* ivx_objective_grad records its launches into a HIP graph on first use and replays it
  * while the (sky, grad) pointers stay the same (a new pair re-captures).  enable = 0

@@ -48,7 +48,8 @@ EXPORTS = ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_fo
            "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_last_error", "ivx_version",
            "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking",
            "ivx_plan_set_vis", "ivx_set_gridder_occupancy", "ivx_set_fused_fold", "ivx_objective",
-           "ivx_objective_forward", "ivx_objective_backward", "ivx_forward_adjoint", "ivx_last_terms")
+           "ivx_objective_forward", "ivx_objective_backward", "ivx_forward_adjoint", "ivx_last_terms",
+           "ivx_nufft_probe")
 
 STAGES = ("image_rows", "col_fwd", "grid", "fold", "col_inv", "row_inv", "sd", "sky", "final")
 
@@ -85,6 +86,7 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
     lib.ivx_objective_backward.argtypes = [vp, vp, vp, dbl, vp]
     lib.ivx_forward_adjoint.argtypes = [vp, vp, vp, vp]
     lib.ivx_last_terms.argtypes = [vp, vp, vp]
+    lib.ivx_nufft_probe.argtypes = [i32, i32, i32, vp]
     lib.ivx_stage_times.argtypes = [vp, vp, vp]
     lib.ivx_last_error.restype = ctypes.c_char_p
     lib.ivx_last_error.argtypes = []
@@ -92,7 +94,7 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
               "ivx_adjoint", "ivx_autotune", "ivx_plan_info", "ivx_plan_destroy", "ivx_set_timing",
               "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking", "ivx_plan_set_vis",
               "ivx_set_gridder_occupancy", "ivx_set_fused_fold", "ivx_objective", "ivx_objective_forward",
-              "ivx_objective_backward", "ivx_forward_adjoint", "ivx_last_terms"):
+              "ivx_objective_backward", "ivx_forward_adjoint", "ivx_last_terms", "ivx_nufft_probe"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ivx_version.restype = ctypes.c_int
     lib.ivx_real_size.restype = ctypes.c_int
@@ -130,6 +132,16 @@ def _stream_ptr(stream=None) -> Optional[int]:
         return None
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream
+
+
+def nufft_probe(n_sub: int, n_fine: int, kernel_width: int, precision: str = "f32") -> float:
+    """ivx_nufft_probe: worst one-dimensional error of a unit point source's transform."""
+    lib = load_library(precision)
+    e = np.zeros(1)
+    code = lib.ivx_nufft_probe(int(n_sub), int(n_fine), int(kernel_width), e.ctypes.data)
+    if code != 0:
+        raise IvxError(code, lib.ivx_last_error().decode())
+    return float(e[0])
 
 
 class Plan:

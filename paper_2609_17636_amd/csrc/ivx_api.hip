@@ -137,6 +137,9 @@ struct ivx_plan {
     std::vector<int64_t> pt_off;      // shared_uv: pointing offsets into uv / weights
     // tiling the records are currently sorted for, and their per-(block, tile) counts
     int bin_T = 0, bin_ntx = 0, bin_ntiles = 0;
+    int bin_W = 0, bin_nf = 0;        // kernel width and fine grid the records are binned for
+    bool geometry_auto = false;       // W and n_f chosen by the library (the autotuner may change them)
+    double eps_target = 0.0;          // accuracy the autotuner's geometries must reach
     std::vector<int32_t> tcount;      // [n_items][bin_ntiles]
     // device memory
     std::vector<DevBuf> bufs;
@@ -220,6 +223,7 @@ void free_all(ivx_plan *p) {
     p->d_boff = nullptr;
     p->d_tstart = nullptr;
     p->bin_T = p->bin_ntx = p->bin_ntiles = 0;
+    p->bin_W = p->bin_nf = 0;
     p->tcount.clear();
     p->d_work = nullptr;
     p->d_tslot = nullptr;
@@ -286,6 +290,92 @@ bool tile_fits(const ivx_plan *p, int T, int nwave, int lanes) {
     g.ldw = pick_ldw(g.win, g.W, lanes);
     if (lanes == 8 && g.W > 8) return false;
     return grid_lds_bytes(g, nwave, lanes) <= 80 * 1024; // two blocks per 160 KB compute unit
+}
+
+// NUFFT geometry: fine grid n_f, kernel width W, kernel shape beta (scaled from the 2.30 W of
+// two-fold oversampling), deapodization 1 / phi_hat at the sub-image frequencies, twiddles.
+void set_geometry_fields(ivx_plan *p, int W, int nf) {
+    Geom &g = p->g;
+    g.nf = nf;
+    g.logn = ilog2(nf);
+    g.rw = nf / 2 + 1;
+    g.W = W;
+    g.O = (W + 1) / 2;
+    const double sigma = (double)nf / g.nk;
+    p->beta = 2.30 * W * (1.0 - 1.0 / (2.0 * sigma)) / 0.75;
+    g.beta = (real)p->beta;
+    g.r_stride = (int64_t)g.nk * g.rw;
+    g.hs_stride = (int64_t)g.nf * g.rw;
+    std::vector<double> gx, gw;
+    gauss_legendre(std::max(64, 8 * W), gx, gw);
+    p->dq_host.resize(g.nk);
+    for (int a = 0; a < g.nk; ++a) {
+        const double kap = 2.0 * M_PI * (a - g.nk / 2) / nf;
+        p->dq_host[a] = (real)(1.0 / es_phihat(kap, W, p->beta, gx, gw));
+    }
+    p->tw_host.resize(nf);
+    for (int t = 0; t < nf; ++t) {
+        const double th = -2.0 * M_PI * t / nf;
+        p->tw_host[t] = cpx{(real)std::cos(th), (real)std::sin(th)};
+    }
+}
+
+// Accuracy probe of a geometry: the largest error, over the sub-image's frequencies k and
+// positions x in one fine cell, of the one-dimensional transform of a unit point source that
+// the plan's spreading kernel and deapodization compute,
+//   | dq(k) sum_t phi(x - t) exp(-2 pi i k t / n_f) - exp(-2 pi i k x / n_f) |,
+// against its closed form (the second term).  A two-dimensional transform is separable, so
+// its error is at most about twice this.
+double nufft_probe_error(int nk, int nf, int W) {
+    const double sigma = (double)nf / nk;
+    const double beta = 2.30 * W * (1.0 - 1.0 / (2.0 * sigma)) / 0.75;
+    std::vector<double> gx, gw;
+    gauss_legendre(std::max(64, 8 * W), gx, gw);
+    double worst = 0.0;
+    const int nx = 33;
+    std::vector<double> phi(W);
+    for (int ix = 0; ix < nx; ++ix) {
+        const double x = (double)ix / (nx - 1);
+        const double t0 = std::floor(x - 0.5 * W) + 1.0;
+        for (int t = 0; t < W; ++t) phi[t] = es_phi(x - (t0 + t), W, beta);
+        for (int k = -nk / 2; k < nk / 2; ++k) {
+            const double dq = 1.0 / es_phihat(2.0 * M_PI * k / nf, W, beta, gx, gw);
+            double re = 0.0, im = 0.0;
+            for (int t = 0; t < W; ++t) {
+                const double th = -2.0 * M_PI * k * (t0 + t) / nf;
+                re += phi[t] * std::cos(th);
+                im += phi[t] * std::sin(th);
+            }
+            const double th = -2.0 * M_PI * k * x / nf;
+            worst = std::max(worst, std::hypot(dq * re - std::cos(th), dq * im - std::sin(th)));
+        }
+    }
+    return worst;
+}
+
+// Switch a plan with data to another fine grid / kernel width: new tables and row-FFT buffers
+// (allocated before anything is released, so a failure leaves the plan as it was); the
+// records are re-binned by the next build_bins.
+ivx_status apply_geometry(ivx_plan *p, int W, int nf) {
+    if (W == p->g.W && nf == p->g.nf) return IVX_OK;
+    const int64_t n_items = (int64_t)p->g.C * p->g.P;
+    cpx *tw = nullptr, *R = nullptr;
+    ivx_status s;
+    if ((s = dalloc(p, &tw, nf)) != IVX_OK) return s;
+    if ((s = dalloc(p, &R, (size_t)n_items * p->g.nk * (nf / 2 + 1))) != IVX_OK) {
+        free_one(p, tw);
+        return s;
+    }
+    drop_graph(p);
+    free_one(p, p->d_tw);
+    free_one(p, p->d_R);
+    p->d_tw = tw;
+    p->d_R = R;
+    set_geometry_fields(p, W, nf);
+    IVX_HIP(hipMemcpy(p->d_dq, p->dq_host.data(), p->g.nk * sizeof(real), hipMemcpyHostToDevice));
+    IVX_HIP(hipMemcpy(p->d_tw, p->tw_host.data(), nf * sizeof(cpx), hipMemcpyHostToDevice));
+    ++p->epoch;
+    return IVX_OK;
 }
 
 // Default blocking: the widest block (4 waves) and a 16-cell tile when they fit the LDS
@@ -382,6 +472,8 @@ ivx_status store_counts(ivx_plan *p, const int32_t *d_counts, int ntiles, int32_
     p->bin_T = p->g.T;
     p->bin_ntx = p->g.ntx;
     p->bin_ntiles = ntiles;
+    p->bin_W = p->g.W;
+    p->bin_nf = p->g.nf;
     return IVX_OK;
 }
 
@@ -502,8 +594,10 @@ ivx_status rebin(ivx_plan *p, hipStream_t st) {
     size_t sort_bytes = 0;
     IVX_HIP(sort_pairs(nullptr, sort_bytes, nullptr, nullptr, nullptr, nullptr, (int)std::max<int64_t>(maxn, 1),
                        end_bit, st));
-    TmpBuf k1, k2, v1, v2, foot, temp, counts, sc, sv, sw, sp;
-    if (k1.get(maxn * sizeof(uint64_t)) != hipSuccess || k2.get(maxn * sizeof(uint64_t)) != hipSuccess ||
+    const bool regeom = p->bin_W != g.W || p->bin_nf != g.nf;
+    TmpBuf k1, k2, v1, v2, foot, temp, counts, sc, sv, sw, sp, fr;
+    if ((regeom && fr.get(maxn * sizeof(double2)) != hipSuccess) ||
+        k1.get(maxn * sizeof(uint64_t)) != hipSuccess || k2.get(maxn * sizeof(uint64_t)) != hipSuccess ||
         v1.get(maxn * sizeof(uint32_t)) != hipSuccess || v2.get(maxn * sizeof(uint32_t)) != hipSuccess ||
         foot.get(maxn * sizeof(int2)) != hipSuccess || temp.get(sort_bytes) != hipSuccess ||
         counts.get((size_t)n_items * ntiles * sizeof(int32_t)) != hipSuccess ||
@@ -520,16 +614,17 @@ ivx_status rebin(ivx_plan *p, hipStream_t st) {
     for (int b = 0; b < n_items; ++b) {
         const int64_t L0 = p->block_live[b], n = p->block_live[b + 1] - L0;
         if (n == 0) continue;
+        const Regeom rg{(double)g.nf / (double)p->bin_nf, 0.5 * p->bin_W, 0.5 * g.W, (p->bin_W + 1) / 2, g.O};
         IVX_HIP(launch_rekey(n, p->d_crd + L0, p->d_perm + L0, p->d_tstart + (size_t)b * (p->bin_ntiles + 1),
                              p->bin_ntiles, p->bin_ntx, p->bin_T, g.ntx, g.T, k1.as<uint64_t>(), v1.as<uint32_t>(),
-                             foot.as<int2>(), st));
+                             foot.as<int2>(), st, regeom ? &rg : nullptr, regeom ? fr.as<double2>() : nullptr));
         size_t tb = sort_bytes;
         IVX_HIP(sort_pairs(temp.p, tb, k1.as<uint64_t>(), k2.as<uint64_t>(), v1.as<uint32_t>(), v2.as<uint32_t>(),
                            (int)n, end_bit, st));
         IVX_HIP(launch_rebin_emit(n, k2.as<uint64_t>(), v2.as<uint32_t>(), foot.as<int2>(), p->d_crd + L0,
                                   p->d_vis + L0, p->d_wgt + L0, p->d_perm + L0, g.ntx, g.T, sc.as<VisCoord>(),
                                   sv.as<cpx>(), sw.as<real>(), sp.as<int32_t>(),
-                                  counts.as<int32_t>() + (size_t)b * ntiles, st));
+                                  counts.as<int32_t>() + (size_t)b * ntiles, st, regeom ? fr.as<double2>() : nullptr));
         IVX_HIP(hipMemcpyAsync(p->d_crd + L0, sc.p, n * sizeof(VisCoord), hipMemcpyDeviceToDevice, st));
         IVX_HIP(hipMemcpyAsync(p->d_vis + L0, sv.p, n * sizeof(cpx), hipMemcpyDeviceToDevice, st));
         IVX_HIP(hipMemcpyAsync(p->d_wgt + L0, sw.p, n * sizeof(real), hipMemcpyDeviceToDevice, st));
@@ -605,7 +700,7 @@ ivx_status build_work(ivx_plan *p, hipStream_t st) {
 // blocking) or set_data before the next evaluation.
 ivx_status build_bins(ivx_plan *p, hipStream_t st) {
     ivx_status s = IVX_OK;
-    if (p->bin_T != p->g.T) s = rebin(p, st);
+    if (p->bin_T != p->g.T || p->bin_W != p->g.W || p->bin_nf != p->g.nf) s = rebin(p, st);
     if (s == IVX_OK) s = build_work(p, st);
     p->has_data = s == IVX_OK;
     return s;
@@ -879,9 +974,6 @@ ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out) {
         delete p;
         return fail(IVX_EINVAL, "fine_size must be a power of two in [64, 2048] and >= 1.25 n_sub");
     }
-    g.nf = nf;
-    g.logn = ilog2(nf);
-    g.rw = nf / 2 + 1;
     const double sigma = (double)nf / d->n_sub;
     int W = d->kernel_width;
     if (W == 0) {
@@ -894,13 +986,9 @@ ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out) {
         delete p;
         return fail(IVX_EINVAL, "kernel_width must be in [4, 16]");
     }
-    g.W = W;
-    g.O = (W + 1) / 2;
-    // shape parameter scaled from the 2.30 W of two-fold oversampling
-    p->beta = 2.30 * W * (1.0 - 1.0 / (2.0 * sigma)) / 0.75;
-    g.beta = (real)p->beta;
-    g.r_stride = (int64_t)g.nk * g.rw;
-    g.hs_stride = (int64_t)g.nf * g.rw;
+    set_geometry_fields(p, W, nf);
+    p->geometry_auto = d->kernel_width == 0 && d->fine_size == 0;
+    p->eps_target = d->nufft_eps > 0.0 ? d->nufft_eps : nufft_probe_error(g.nk, nf, W);
     p->tile_fixed = d->tile;
     bool ok = false;
     if (d->tile == 0) {
@@ -917,19 +1005,6 @@ ivx_status ivx_plan_create(const ivx_problem *d, ivx_plan **out) {
     if (!ok) {
         delete p;
         return fail(IVX_EINVAL, "tile must be >= kernel_width and fit the LDS");
-    }
-    // deapodization 1 / phi_hat(2 pi p / nf) for p = a - n/2, a in [0, n)
-    std::vector<double> gx, gw;
-    gauss_legendre(std::max(64, 8 * W), gx, gw);
-    p->dq_host.resize(g.nk);
-    for (int a = 0; a < g.nk; ++a) {
-        const double kap = 2.0 * M_PI * (a - g.nk / 2) / nf;
-        p->dq_host[a] = (real)(1.0 / es_phihat(kap, W, p->beta, gx, gw));
-    }
-    p->tw_host.resize(nf);
-    for (int t = 0; t < nf; ++t) {
-        const double th = -2.0 * M_PI * t / nf;
-        p->tw_host[t] = cpx{(real)std::cos(th), (real)std::sin(th)};
     }
     if (d->sd_n > 0) {
         const double sig = d->sd_fwhm_rad / (2.0 * std::sqrt(2.0 * std::log(2.0)));
@@ -1432,75 +1507,120 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     ivx_status s = check_plan_use(p);
     if (s != IVX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    struct Cand { int T, nwave, chunk, lanes, vpi; };
-    std::vector<Cand> cands;
+    struct Cand { int W, nf, T, nwave, chunk, lanes, vpi; };
+    // NUFFT geometries: the plan's own, and when the library chose it, the narrowest kernel on
+    // the plan's fine grid and on the grids of half and twice its size whose accuracy probe
+    // meets the plan's target (the requested nufft_eps, else the accuracy of the plan's own
+    // geometry): the result stays as accurate as requested while the cost may change
+    std::vector<std::pair<int, int>> geoms;
+    if (p->geometry_auto) {
+        for (int nf : {p->g.nf, p->g.nf / 2, p->g.nf * 2}) {
+            if (nf < 64 || nf > 2048 || nf * 4 < p->g.nk * 5) continue;
+            for (int W = 4; W <= 16; ++W) {
+                if (nufft_probe_error(p->g.nk, nf, W) > p->eps_target) continue;
+                geoms.push_back({W, nf});
+                break;
+            }
+        }
+    }
+    // the plan's own geometry when it meets the target (a plan created with a width its
+    // requested accuracy does not support is moved to one that does), or when it is fixed
+    if (geoms.empty() || nufft_probe_error(p->g.nk, p->g.nf, p->g.W) <= p->eps_target) {
+        bool have = false;
+        for (const auto &gm : geoms) have = have || (gm.first == p->g.W && gm.second == p->g.nf);
+        if (!have) geoms.insert(geoms.begin(), {p->g.W, p->g.nf});
+    }
     const int tiles[] = {8, 12, 16, 24, 32};
     const int waves[] = {4, 2, 1};
     const int chunks[] = {128, 256, 512};
-    // the matrix-core gridder first (one wave per work item, windows of at most 16 x 16):
-    // it is the fastest where it fits, and the search may stop at the time budget
-    for (int T = 17 - p->g.W; T >= p->g.W; --T)
-        if (tile_fits(p, T, 1, GRID_MFMA_LANES))
-            for (int ch : chunks) cands.push_back(Cand{T, 1, ch, GRID_MFMA_LANES, 1});
-    for (int lanes : {16, 8})
-        for (int vpi : {2, 1})
-            for (int T : tiles)
-                for (int nw : waves)
-                    if (tile_fits(p, T, nw, lanes))
-                        for (int ch : chunks) cands.push_back(Cand{T, nw, ch, lanes, vpi});
-    if (cands.empty()) return fail(IVX_EINVAL, "no tile candidate fits");
-    // the tiling only changes the gridding stage and the slot reduction (with the inverse column
-    // pass when the two are fused): time those on
-    // the plan's own data (zero sky), keep the fastest; the result is accuracy-neutral
-    real *sky = nullptr;
+    auto blockings = [&](int W, int nf) {
+        std::vector<Cand> c;
+        // the matrix-core gridder first (one wave per work item, windows of at most 16 x 16):
+        // it is the fastest where it fits, and the search may stop at the time budget
+        for (int T = 17 - W; T >= W; --T)
+            if (tile_fits(p, T, 1, GRID_MFMA_LANES))
+                for (int ch : chunks) c.push_back(Cand{W, nf, T, 1, ch, GRID_MFMA_LANES, 1});
+        for (int lanes : {16, 8})
+            for (int vpi : {2, 1})
+                for (int T : tiles)
+                    for (int nw : waves)
+                        if (tile_fits(p, T, nw, lanes))
+                            for (int ch : chunks) c.push_back(Cand{W, nf, T, nw, ch, lanes, vpi});
+        return c;
+    };
+    // whole evaluations at a zero sky on the plan's own data (the geometry changes the FFT
+    // passes too); the fastest candidate is kept
+    real *sky = nullptr, *grad = nullptr;
     const int64_t nsky = (int64_t)p->g.C * p->g.N * p->g.N;
     IVX_HIP(hipMalloc(&sky, nsky * sizeof(real)));
+    if (hipMalloc(&grad, nsky * sizeof(real)) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(sky);
+        return fail(IVX_ENOMEM, "autotune buffers");
+    }
     IVX_HIP(hipMemsetAsync(sky, 0, nsky * sizeof(real), st));
     hipEvent_t e0, e1;
     IVX_HIP(hipEventCreate(&e0));
     IVX_HIP(hipEventCreate(&e1));
     const auto t_start = std::chrono::steady_clock::now();
     double best_ms = 1e300;
-    Cand best{p->g.T, p->nwave, p->chunk_max, p->lanes, p->vpi};
-    for (const Cand &c : cands) {
-        p->nwave = c.nwave;
-        p->lanes = c.lanes;
-        p->vpi = c.vpi;
-        p->chunk_max = c.chunk;
-        set_tile(p, c.T);
-        if ((s = build_bins(p, st)) == IVX_ENOMEM) {
-            s = IVX_OK; // this blocking does not fit next to the data: skip it
+    Cand best{p->g.W, p->g.nf, p->g.T, p->nwave, p->chunk_max, p->lanes, p->vpi};
+    const uint32_t mask = p->timing_mask;
+    p->timing_mask = 0;
+    bool out_of_time = false;
+    for (const auto &gm : geoms) {
+        if (out_of_time) break;
+        if ((s = apply_geometry(p, gm.first, gm.second)) == IVX_ENOMEM) {
+            s = IVX_OK; // this geometry does not fit next to the data: skip it
             continue;
         }
         if (s != IVX_OK) break;
-        if ((s = run_forward_half(p, sky, st)) != IVX_OK) break;
-        float ms = 0.f, tot = 0.f;
-        const int reps = 5;
-        for (int r = 0; r < reps + 1; ++r) {
-            // the fold overwrites the forward grid: rebuild it (untimed) for every repetition
-            if (r > 0 && (s = run_forward_half(p, sky, st)) != IVX_OK) break;
-            IVX_HIP(hipEventRecord(e0, st));
-            IVX_HIP(launch_grid(MODE_OBJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff,
-                                p->d_ext, p->d_slots, p->d_jpart, nullptr, nullptr, p->nwave, p->lanes * 10 + p->vpi, p->occupancy, st));
-            if ((s = run_fold_col_inv(p, st)) != IVX_OK) break;
-            IVX_HIP(hipEventRecord(e1, st));
-            IVX_HIP(hipEventSynchronize(e1));
-            IVX_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (r > 0) tot += ms;
+        const int lanes0 = p->lanes;
+        std::vector<Cand> cands = blockings(gm.first, gm.second);
+        p->lanes = lanes0;
+        for (const Cand &c : cands) {
+            p->nwave = c.nwave;
+            p->lanes = c.lanes;
+            p->vpi = c.vpi;
+            p->chunk_max = c.chunk;
+            set_tile(p, c.T);
+            if ((s = build_bins(p, st)) == IVX_ENOMEM) {
+                s = IVX_OK; // this blocking does not fit next to the data: skip it
+                continue;
+            }
+            if (s != IVX_OK) break;
+            float ms = 0.f, tot = 0.f;
+            const int reps = 3;
+            for (int r = 0; r < reps + 1; ++r) {
+                IVX_HIP(hipEventRecord(e0, st));
+                if ((s = eval_objective(p, sky, grad, nullptr, st)) != IVX_OK) break;
+                IVX_HIP(hipEventRecord(e1, st));
+                IVX_HIP(hipEventSynchronize(e1));
+                IVX_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (r > 0) tot += ms;
+            }
+            if (s != IVX_OK) break;
+            const double avg = tot / reps;
+            if (avg < best_ms) {
+                best_ms = avg;
+                best = c;
+            }
+            const double spent =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+            if (spent > budget_ms) {
+                out_of_time = true;
+                break;
+            }
         }
         if (s != IVX_OK) break;
-        const double avg = tot / reps;
-        if (avg < best_ms) {
-            best_ms = avg;
-            best = c;
-        }
-        const double spent = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-        if (spent > budget_ms) break;
     }
+    p->timing_mask = mask;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(sky);
+    (void)hipFree(grad);
     if (s != IVX_OK) return s;
+    if ((s = apply_geometry(p, best.W, best.nf)) != IVX_OK) return s;
     p->nwave = best.nwave;
     p->lanes = best.lanes;
     p->vpi = best.vpi;
@@ -1508,6 +1628,13 @@ ivx_status ivx_autotune(ivx_plan *p, double budget_ms, int32_t *chosen_tile, voi
     set_tile(p, best.T);
     if ((s = build_bins(p, st)) != IVX_OK) return s;
     if (chosen_tile) *chosen_tile = best.T;
+    return IVX_OK;
+}
+
+extern "C" ivx_status ivx_nufft_probe(int32_t n_sub, int32_t n_fine, int32_t kernel_width, double *err) {
+    if (!err || n_sub < 4 || (n_sub & 1) || n_fine < n_sub || kernel_width < 2 || kernel_width > 16)
+        return fail(IVX_EINVAL, "bad ivx_nufft_probe arguments");
+    *err = nufft_probe_error(n_sub, n_fine, kernel_width);
     return IVX_OK;
 }
 

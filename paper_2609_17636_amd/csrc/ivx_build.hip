@@ -67,6 +67,17 @@ __device__ __forceinline__ void coord_cells(const VisCoord &c, int &ix, int &iy)
 #endif
 }
 
+// fractional offsets of a record
+__device__ __forceinline__ void coord_fracs(const VisCoord &c, double &fx, double &fy) {
+#ifdef IVX_REAL_DOUBLE
+    fx = c.fx;
+    fy = c.fy;
+#else
+    fx = (double)(c.xq & 0xFFFFFFu) * 5.9604644775390625e-08; // 2^-24
+    fy = (double)(c.yq & 0xFFFFFFu) * 5.9604644775390625e-08;
+#endif
+}
+
 __device__ __forceinline__ VisCoord move_coord(const VisCoord &c, int ix, int iy) {
 #ifdef IVX_REAL_DOUBLE
     return VisCoord{(uint32_t)ix, (uint32_t)iy, c.fx, c.fy};
@@ -151,7 +162,8 @@ __global__ __launch_bounds__(BT) void k_rekey(int64_t n, const VisCoord *__restr
                                               const int32_t *__restrict__ perm, const int32_t *__restrict__ tstart,
                                               int ntiles_old, int ntx_old, int T_old, int ntx_new, int T_new,
                                               uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                              int2 *__restrict__ foot) {
+                                              int2 *__restrict__ foot, Regeom rg, double2 *__restrict__ frac) {
+#pragma clang fp contract(off)
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= n) return;
     int lo = 0, hi = ntiles_old - 1; // last tile t with tstart[t] <= i
@@ -163,7 +175,19 @@ __global__ __launch_bounds__(BT) void k_rekey(int64_t n, const VisCoord *__restr
     int ix, iy;
     coord_cells(crd[i], ix, iy);
     const int ty = lo / ntx_old, tx = lo - ty * ntx_old;
-    const int er0 = ty * T_old + iy, ec0 = tx * T_old + ix;
+    int er0 = ty * T_old + iy, ec0 = tx * T_old + ix;
+    if (frac) {
+        // fine-grid position under the old geometry, scaled to the new grid, split for the new width
+        double fx, fy;
+        coord_fracs(crd[i], fx, fy);
+        const double gx = ((double)(ec0 - 1 - rg.O_old) + fx + rg.hw_old) * rg.ratio;
+        const double gy = ((double)(er0 - 1 - rg.O_old) + fy + rg.hw_old) * rg.ratio;
+        const double sx = gx - rg.hw_new, sy = gy - rg.hw_new;
+        const double flx = floor(sx), fly = floor(sy);
+        ec0 = (int)flx + 1 + rg.O_new;
+        er0 = (int)fly + 1 + rg.O_new;
+        frac[i] = double2{sx - flx, sy - fly};
+    }
     const uint32_t tile = (uint32_t)((er0 / T_new) * ntx_new + ec0 / T_new);
     const int32_t p = perm[i];
     const uint32_t src = (uint32_t)(p < 0 ? ~p : p);
@@ -178,14 +202,16 @@ __global__ __launch_bounds__(BT) void k_rebin_emit(int64_t n, const uint64_t *__
                                                    const real *__restrict__ wgt, const int32_t *__restrict__ perm,
                                                    int ntx, int T, VisCoord *__restrict__ crd_o,
                                                    cpx *__restrict__ vis_o, real *__restrict__ wgt_o,
-                                                   int32_t *__restrict__ perm_o, int32_t *__restrict__ counts) {
+                                                   int32_t *__restrict__ perm_o, int32_t *__restrict__ counts,
+                                                   const double2 *__restrict__ frac) {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= n) return;
     const uint32_t o = vals[i];
     const int tile = (int)(keys[i] >> 32);
     const int ty = tile / ntx, tx = tile - ty * ntx;
     const int2 f = foot[o];
-    crd_o[i] = move_coord(crd[o], f.y - tx * T, f.x - ty * T);
+    if (frac) crd_o[i] = make_coord(f.y - tx * T, f.x - ty * T, frac[o].x, frac[o].y);
+    else crd_o[i] = move_coord(crd[o], f.y - tx * T, f.x - ty * T);
     vis_o[i] = vis[o];
     wgt_o[i] = wgt[o];
     perm_o[i] = perm[o];
@@ -244,20 +270,22 @@ hipError_t launch_bin_emit(int64_t n, const uint64_t *keys, const real *uv, doub
 
 hipError_t launch_rekey(int64_t n, const VisCoord *crd, const int32_t *perm, const int32_t *tstart, int ntiles_old,
                         int ntx_old, int T_old, int ntx_new, int T_new, uint64_t *keys, uint32_t *vals, int2 *foot,
-                        hipStream_t st) {
+                        hipStream_t st, const Regeom *rg, double2 *frac) {
     if (n <= 0) return hipSuccess;
+    if ((rg == nullptr) != (frac == nullptr)) return hipErrorInvalidValue;
+    const Regeom r = rg ? *rg : Regeom{1.0, 0.0, 0.0, 0, 0};
     k_rekey<<<grid1(n), BT, 0, st>>>(n, crd, perm, tstart, ntiles_old, ntx_old, T_old, ntx_new, T_new, keys, vals,
-                                     foot);
+                                     foot, r, frac);
     return hipGetLastError();
 }
 
 hipError_t launch_rebin_emit(int64_t n, const uint64_t *keys, const uint32_t *vals, const int2 *foot,
                              const VisCoord *crd, const cpx *vis, const real *wgt, const int32_t *perm, int ntx,
                              int T, VisCoord *crd_o, cpx *vis_o, real *wgt_o, int32_t *perm_o, int32_t *counts,
-                             hipStream_t st) {
+                             hipStream_t st, const double2 *frac) {
     if (n <= 0) return hipSuccess;
     k_rebin_emit<<<grid1(n), BT, 0, st>>>(n, keys, vals, foot, crd, vis, wgt, perm, ntx, T, crd_o, vis_o, wgt_o,
-                                          perm_o, counts);
+                                          perm_o, counts, frac);
     return hipGetLastError();
 }
 

@@ -149,13 +149,21 @@ hipError_t launch_bin_emit(int64_t n, const uint64_t *keys, const real *uv, doub
                            const real *w, const BinGeom &b, VisCoord *crd, cpx *svis, real *swgt, int32_t *perm,
                            int32_t *counts, hipStream_t st);
 // keys of a block's records for tile edge T_new (tstart: the block's old tile prefix)
+// A change of the fine grid and kernel width as well (frac != nullptr): each record's fine-grid
+// position g = footprint start - 1 - O + frac + W/2 is recovered, scaled by nf_new / nf_old and
+// split again for the new width; the new fractions go to frac (x, y).
+struct Regeom {
+    double ratio;          // nf_new / nf_old
+    double hw_old, hw_new; // W / 2
+    int O_old, O_new;      // extended-grid offsets
+};
 hipError_t launch_rekey(int64_t n, const VisCoord *crd, const int32_t *perm, const int32_t *tstart, int ntiles_old,
                         int ntx_old, int T_old, int ntx_new, int T_new, uint64_t *keys, uint32_t *vals, int2 *foot,
-                        hipStream_t st);
+                        hipStream_t st, const Regeom *rg = nullptr, double2 *frac = nullptr);
 hipError_t launch_rebin_emit(int64_t n, const uint64_t *keys, const uint32_t *vals, const int2 *foot,
                              const VisCoord *crd, const cpx *vis, const real *wgt, const int32_t *perm, int ntx,
                              int T, VisCoord *crd_o, cpx *vis_o, real *wgt_o, int32_t *perm_o, int32_t *counts,
-                             hipStream_t st);
+                             hipStream_t st, const double2 *frac = nullptr);
 // sorted data of one block from the caller's block arrays (w may be NULL: weights kept)
 hipError_t launch_gather_block(int64_t n, const int32_t *perm, const real *vis, const real *w, cpx *svis,
                                real *swgt, unsigned int *bad, hipStream_t st);

@@ -156,3 +156,16 @@ def test_noalloc_weight_gradient_rejects_shapes_beyond_its_scratch():
     msg = lib.ivx_last_error().decode()
     assert "static scratch" in msg and str(cap) in msg
     assert f(None, None, *shape, None, None, None) == -1
+
+
+def test_nufft_probe_is_monotone_and_brackets_the_widths():
+    """The accuracy probe of the autotuner falls with the kernel width and with the
+    oversampling factor, and places the widths the library uses on the right side of its
+    accuracy targets (sigma = 2: W = 8 below 1e-6, W = 6 above 1e-5)."""
+    import paper_2609_17636_amd as ivx
+
+    for nk, nf in ((64, 128), (384, 1024), (384, 512)):
+        e = [ivx.nufft_probe(nk, nf, W) for W in range(4, 13)]
+        assert all(a > b for a, b in zip(e, e[1:])), (nk, nf, e)
+    assert ivx.nufft_probe(64, 256, 7) < ivx.nufft_probe(64, 128, 7) < ivx.nufft_probe(96, 128, 7)
+    assert ivx.nufft_probe(64, 128, 8) < 1e-6 < 1e-5 < ivx.nufft_probe(64, 128, 6)

@@ -408,3 +408,47 @@ def test_fused_fold_equals_the_extended_grid_path(mini, blocking):
     assert np.array_equal(plan.adjoint(v).cpu().numpy(), a2)
     with pytest.raises(Exception):
         plan.set_fused_fold(3)
+
+
+def test_forward_error_within_the_accuracy_probe(mini):
+    """For several kernel widths, the largest error of the HIP forward model against the
+    oracle's direct DFT stays within the probe's bound: 2 x probe(W) x sum |f| per
+    visibility (the two-dimensional transform of sum_p f_p unit sources), FP64 build."""
+    import paper_2609_17636_amd as ivx
+
+    rng = np.random.default_rng(81)
+    x = rng.uniform(0, 50, size=mini.x_true.shape)
+    want = oracle.model_vis(mini, x)
+    live = mini.flags == 0
+    fsum = max(float(np.abs(oracle.beam_weighted_subimage(mini, x[0], k, 0)).sum()) for k in range(mini.n_point))
+    for W in (5, 6, 7, 8):
+        plan = _plan(mini, "f64", kernel_width=W)
+        got = plan.forward(torch.tensor(x, dtype=torch.float64, device="cuda")).cpu().numpy()
+        err = float(np.abs((got[:, 0] + 1j * got[:, 1] - want)[live]).max())
+        bound = 2 * ivx.nufft_probe(mini.n_sub, plan.info()["n_fine"], W) * fsum
+        print(f"[probe W={W}] max |dV| {err:.3e} bound {bound:.3e}", flush=True)
+        assert err <= bound
+
+
+def test_autotune_chooses_an_accurate_geometry():
+    """Geometry search of the autotuner: a mosaic with 48^2 sub-images (sigma = 8/3) asks for
+    nufft_eps = 1e-5; the width the plan is created with (5, from the exponential estimate)
+    fails the probe, so the tuner must move to a geometry that meets it, and the objective then
+    meets 1e-5 against the oracle."""
+    import paper_2609_17636_amd as ivx
+
+    p = oracle.synthesize(synth.mosaic("w-mini", 3111, 128, 30.0, 2, 2, 30.0, 30.0, 48, (30, 60), 0.3))
+    plan = _plan(p, "f32", nufft_eps=1e-5)
+    w0 = plan.info()["kernel_width"]
+    assert ivx.nufft_probe(48, plan.info()["n_fine"], w0) > 1e-5
+    plan.autotune(20000.0)
+    info = plan.info()
+    probe = ivx.nufft_probe(48, info["n_fine"], info["kernel_width"])
+    print(f"[autotune geometry] created W={w0}; chose W={info['kernel_width']} n_f={info['n_fine']} "
+          f"tile={info['tile']} lanes={info['lanes']} probe {probe:.2e}", flush=True)
+    assert probe <= 1e-5
+    x = np.random.default_rng(82).uniform(0, 50, size=p.x_true.shape)
+    want_t, want_g = oracle.objective_grad(p, x)
+    terms, grad = _eval(plan, x)
+    assert abs(terms[0] - want_t["Q_tot"]) <= 1e-5 * want_t["Q_tot"]
+    assert rel(grad, want_g) <= 1e-5
