@@ -250,30 +250,51 @@ def unet_flops(levels=4, base=32, height=256, width=256, in_ch=4) -> float:
 
 
 # ----------------------------------------------------------------------------- timing
-def time_to_tolerance(m: Mosaic, net, seed: int, j_star: float, maxiter: int = 15000, x_mean=None):
+def time_to_tolerance(m: Mosaic, net, seed: int, j_star: float, maxiter: int = 15000, x_mean=None, order: int = 0):
     """Cold and warm time-to-tolerance on field `seed` (data loaded here, untimed).  With
-    `x_mean` (sky, K) a third solve starts from that fixed image: the no-learning baseline."""
+    `x_mean` (sky, K) a third solve starts from that fixed image: the no-learning baseline.
+    `order` rotates which start is solved first (cold, warm, mean for order 0), so that no
+    start always runs on a cold cache or right after another solve."""
     import torch
 
     target = (1.0 + TOL) * j_star
     m.simulate(seed)
     torch.cuda.synchronize()
-    cold = m.solve(maxiter=maxiter, target=target)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    d = m.dirty()
-    x0 = predict(net, d)
-    torch.cuda.synchronize()
-    t_pred = time.perf_counter() - t0
-    warm = m.solve(x0=x0, maxiter=maxiter, target=target, t_start=t0)
-    row = {"seed": seed, "j_star": j_star,
+    res = {}
+
+    def run_cold():
+        res["cold"] = m.solve(maxiter=maxiter, target=target)
+        torch.cuda.synchronize()
+
+    def run_warm():
+        t0 = time.perf_counter()
+        d = m.dirty()
+        x0 = predict(net, d)
+        torch.cuda.synchronize()
+        res["t_pred"] = time.perf_counter() - t0
+        res["warm"] = m.solve(x0=x0, maxiter=maxiter, target=target, t_start=t0)
+        torch.cuda.synchronize()
+
+    def run_mean():
+        res["mean"] = m.solve(x0=x_mean, maxiter=maxiter, target=target)
+        torch.cuda.synchronize()
+
+    steps = [run_cold, run_warm] + ([run_mean] if x_mean is not None else [])
+    k = order % len(steps)
+    for f in steps[k:] + steps[:k]:
+        f()
+    cold, warm, t_pred = res["cold"], res["warm"], res["t_pred"]
+    row = {"seed": seed, "j_star": j_star, "order": k,
            "cold_s": cold.seconds if cold.reached_target else float("inf"), "cold_nfev": cold.nfev,
            "warm_s": warm.seconds if warm.reached_target else float("inf"), "warm_nfev": warm.nfev,
            "warm_overhead_s": t_pred, "q_warm_start": warm.history[0][1] if warm.history else float("nan"),
            "q_cold_start": cold.history[0][1] if cold.history else float("nan")}
     if x_mean is not None:
-        mean = m.solve(x0=x_mean, maxiter=maxiter, target=target)
+        mean = res["mean"]
         row.update({"mean_s": mean.seconds if mean.reached_target else float("inf"), "mean_nfev": mean.nfev})
+    for name in ("cold", "warm") + (("mean",) if x_mean is not None else ()):
+        r = res[name]
+        row[f"{name}_ms_per_eval"] = 1e3 * r.seconds / max(r.nfev, 1) if np.isfinite(r.seconds) else float("nan")
     return row
 
 
@@ -296,7 +317,9 @@ def summarise(rows):
             "warm_nfev_median": float(np.median([r["warm_nfev"] for r in rows])),
             "warm_overhead_s_median": float(np.median([r["warm_overhead_s"] for r in rows])),
             "mean_image_s_median": q([r.get("mean_s", np.nan) for r in rows], 50),
-            "mean_image_nfev_median": q([r.get("mean_nfev", np.nan) for r in rows], 50)}
+            "mean_image_nfev_median": q([r.get("mean_nfev", np.nan) for r in rows], 50),
+            "ms_per_eval_median": {k: q([r.get(f"{k}_ms_per_eval", np.nan) for r in rows], 50)
+                                   for k in ("cold", "warm", "mean")}}
 
 
 # ----------------------------------------------------------------------------- command line
@@ -407,8 +430,8 @@ def main(argv=None):
 
 def _measure(a, m, net, hv, x_mean, report, t0, log):
     rows = []
-    for r in hv:
-        rows.append(time_to_tolerance(m, net, r["seed"], r["fun"], a.jstar_iters, x_mean=x_mean))
+    for i, r in enumerate(hv):
+        rows.append(time_to_tolerance(m, net, r["seed"], r["fun"], a.jstar_iters, x_mean=x_mean, order=i))
         w = rows[-1]
         log(f"seed {r['seed']}: cold {w['cold_s']:.3f} s ({w['cold_nfev']} evals), warm {w['warm_s']:.3f} s "
             f"({w['warm_nfev']} evals), mean image {w['mean_s']:.3f} s ({w['mean_nfev']} evals)")
