@@ -12,10 +12,14 @@ FP64, in the order of the paper:
                          the precomputed grid (Sect. 2.1, Eq. sin_projection; Sect. 3.3)
   O2 beam                f = s * A_k * x'                              (Sect. 2.1)
   O3 dft_forward         direct non-uniform DFT, coplanar model        (Sect. 2.1)
+     dft_forward_w       the full model of Eq. vis: the 1/n factor and the phase
+                         w (n - 1) of every pixel, n = sqrt(1 - l^2 - m^2) (Sect. 2.1);
+                         used for every block when the problem carries w
   O4 data term           r = V - y,  J_k = 1/2 sum w |r|^2,  w = 1/sigma^2
                                                                         (Sect. 2.2, Eq. Q)
   O5 dft_adjoint         explicit adjoint of O3 (real part)            (Sect. 3.4: the
                          gradient of Q_tot)
+     dft_adjoint_w       explicit adjoint of dft_forward_w (real part)
   O6 reproject_adjoint   transpose of O1 (scatter of the bilinear weights)
   O7 regulariser         R = sum_c 1/2 ||D x_c||^2 with the 3x3 Laplacian d, zero padding;
                          grad = D (D x)                                  (Sect. 2.2, Eq. 3)
@@ -69,6 +73,13 @@ def _load():
         lib.orc_dft_adjoint_pixels.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, dp,
                                                ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), dp]
         lib.orc_dft_adjoint_pixels.restype = None
+        lib.orc_dft_forward_w.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_int64, dp, dp]
+        lib.orc_dft_forward_w.restype = None
+        lib.orc_dft_adjoint_w.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, dp, dp]
+        lib.orc_dft_adjoint_w.restype = None
+        lib.orc_dft_adjoint_w_pixels.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, dp,
+                                                 ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), dp]
+        lib.orc_dft_adjoint_w_pixels.restype = None
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -118,6 +129,72 @@ def dft_adjoint_pixels(coef: np.ndarray, uv: np.ndarray, delta: float, n: int, p
         _load().orc_dft_adjoint_pixels(int(n), float(delta), uv.shape[0], _dp(uv), _dp(cc), pix.shape[0],
                                        pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(out))
     return out
+
+
+def _check_uvw(uvw: np.ndarray, n: int, delta: float) -> np.ndarray:
+    uvw = np.ascontiguousarray(uvw, dtype=np.float64).reshape(-1, 3)
+    c = n // 2
+    r2 = ((n - 1 - c) ** 2 + c ** 2) * float(delta) ** 2
+    assert r2 < 1.0, "every pixel must lie inside the unit circle of direction cosines"
+    return uvw
+
+
+def dft_forward_w(f: np.ndarray, uvw: np.ndarray, delta: float) -> np.ndarray:
+    """O3 with the w-term (Eq. vis): V_j = sum_{a,b} f[a,b] / n_ab
+    exp(-2 pi i (u_j l_b + v_j m_a + w_j (n_ab - 1))), l_b = (b - n/2) delta,
+    m_a = (a - n/2) delta, n_ab = sqrt(1 - l_b^2 - m_a^2)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    n = f.shape[0]
+    assert f.shape == (n, n)
+    uvw = _check_uvw(uvw, n, delta)
+    out = np.empty((uvw.shape[0], 2), dtype=np.float64)
+    if uvw.shape[0]:
+        _load().orc_dft_forward_w(n, float(delta), _dp(f), uvw.shape[0], _dp(uvw), _dp(out))
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def dft_adjoint_w(coef: np.ndarray, uvw: np.ndarray, delta: float, n: int) -> np.ndarray:
+    """Adjoint of dft_forward_w on real images: g[a,b] = Re sum_j c_j / n_ab
+    exp(+2 pi i (u_j l_b + v_j m_a + w_j (n_ab - 1)))."""
+    coef = np.asarray(coef, dtype=np.complex128).ravel()
+    cc = np.ascontiguousarray(np.stack([coef.real, coef.imag], axis=1))
+    uvw = _check_uvw(uvw, n, delta)
+    g = np.zeros((n, n), dtype=np.float64)
+    if uvw.shape[0]:
+        _load().orc_dft_adjoint_w(int(n), float(delta), uvw.shape[0], _dp(uvw), _dp(cc), _dp(g))
+    return g
+
+
+def dft_adjoint_w_pixels(coef: np.ndarray, uvw: np.ndarray, delta: float, n: int, pixels) -> np.ndarray:
+    """dft_adjoint_w at selected pixels (a, b) only: one direct sum over all visibilities each."""
+    coef = np.asarray(coef, dtype=np.complex128).ravel()
+    cc = np.ascontiguousarray(np.stack([coef.real, coef.imag], axis=1))
+    uvw = _check_uvw(uvw, n, delta)
+    pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+    out = np.zeros(pix.shape[0])
+    if uvw.shape[0] and pix.shape[0]:
+        _load().orc_dft_adjoint_w_pixels(int(n), float(delta), uvw.shape[0], _dp(uvw), _dp(cc), pix.shape[0],
+                                         pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(out))
+    return out
+
+
+def block_forward(p, f: np.ndarray, s: slice, live: np.ndarray) -> np.ndarray:
+    """Model visibilities of the live samples of block s: the full model (dft_forward_w)
+    when the problem carries w coordinates, else the coplanar one (dft_forward)."""
+    w = getattr(p, "w", None)
+    if w is None:
+        return dft_forward(f, p.uv[s][live], p.pixel_rad)
+    uvw = np.concatenate([p.uv[s][live].astype(np.float64), w[s][live].astype(np.float64)[:, None]], axis=1)
+    return dft_forward_w(f, uvw, p.pixel_rad)
+
+
+def block_adjoint(p, coef: np.ndarray, s: slice, live: np.ndarray) -> np.ndarray:
+    """Adjoint of block_forward for the live samples of block s (an n_sub^2 image)."""
+    w = getattr(p, "w", None)
+    if w is None:
+        return dft_adjoint(coef, p.uv[s][live], p.pixel_rad, p.n_sub)
+    uvw = np.concatenate([p.uv[s][live].astype(np.float64), w[s][live].astype(np.float64)[:, None]], axis=1)
+    return dft_adjoint_w(coef, uvw, p.pixel_rad, p.n_sub)
 
 
 # ----------------------------------------------------------------------------- O1 / O6
@@ -266,7 +343,7 @@ def model_vis(p, x: np.ndarray) -> np.ndarray:
             live = _live(p, s)
             f = beam_weighted_subimage(p, x[c], k, c)
             v = np.zeros(s.stop - s.start, dtype=np.complex128)
-            v[live] = dft_forward(f, p.uv[s][live], p.pixel_rad)
+            v[live] = block_forward(p, f, s, live)
             out[s] = v
     return out
 
@@ -283,7 +360,7 @@ def adjoint_image(p, vis: np.ndarray, weighted: bool = True) -> np.ndarray:
                 continue
             live = _live(p, s)
             coef = vis[s][live] * (p.weight[s][live].astype(np.float64) if weighted else 1.0)
-            gk = dft_adjoint(coef, p.uv[s][live], p.pixel_rad, p.n_sub)
+            gk = block_adjoint(p, coef, s, live)
             gk *= p.flux_scale[c] * p.beams[k].astype(np.float64)
             g[c] += reproject_adjoint(gk, p.interp[k], p.n_sky)
     return g
@@ -300,13 +377,12 @@ def objective_grad(p, x: np.ndarray):
             if s.stop == s.start:
                 continue
             live = _live(p, s)
-            uv = p.uv[s][live]
             y = p.vis[s][live].astype(np.complex128)
             w = p.weight[s][live].astype(np.float64)
             f = beam_weighted_subimage(p, x[c], k, c)            # O1, O2
-            r = dft_forward(f, uv, p.pixel_rad) - y               # O3, O4
+            r = block_forward(p, f, s, live) - y                  # O3, O4
             Q += 0.5 * float(np.sum(w * (r.real ** 2 + r.imag ** 2)))
-            gk = dft_adjoint(w * r, uv, p.pixel_rad, p.n_sub)     # O5
+            gk = block_adjoint(p, w * r, s, live)                 # O5
             gk *= p.flux_scale[c] * p.beams[k].astype(np.float64)
             grad[c] += reproject_adjoint(gk, p.interp[k], p.n_sky)  # O6
     R = 0.0

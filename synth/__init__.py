@@ -69,6 +69,7 @@ class Problem:
     vis: Optional[np.ndarray] = None  # [M] complex64, filled by attach_data
     lambda_nu: float = 0.0  # spectral smoothness weight (couples adjacent channels)
     meta: dict = field(default_factory=dict)
+    w: Optional[np.ndarray] = None  # [M] float32, wavelengths; None: the coplanar model
 
     @property
     def n_vis(self) -> int:
@@ -109,11 +110,11 @@ def baselines(enu: np.ndarray) -> np.ndarray:
     return enu[j] - enu[i]
 
 
-def uv_tracks(bl_en: np.ndarray, n_time: int, dec: float, freq_hz: float,
-              lat: float = ASKAP_LAT, ha_hours: float = 6.0) -> np.ndarray:
-    """Earth-rotation synthesis tracks (textbook ENU -> XYZ -> uv rotation), time-major:
-    returns [n_time * n_bl][2] (u, v) in wavelengths, hour angle uniform over
-    [-ha/2, +ha/2].  The w coordinate is not formed (coplanar model, Sect. 2.1)."""
+def uvw_tracks(bl_en: np.ndarray, n_time: int, dec: float, freq_hz: float,
+               lat: float = ASKAP_LAT, ha_hours: float = 6.0) -> np.ndarray:
+    """Earth-rotation synthesis tracks (textbook ENU -> XYZ -> uvw rotation), time-major:
+    returns [n_time * n_bl][3] (u, v, w) in wavelengths, hour angle uniform over
+    [-ha/2, +ha/2]."""
     east, north = bl_en[:, 0], bl_en[:, 1]
     X = -np.sin(lat) * north
     Y = east
@@ -122,8 +123,15 @@ def uv_tracks(bl_en: np.ndarray, n_time: int, dec: float, freq_hz: float,
     sH, cH = np.sin(ha)[:, None], np.cos(ha)[:, None]
     u = sH * X[None, :] + cH * Y[None, :]
     v = -np.sin(dec) * cH * X[None, :] + np.sin(dec) * sH * Y[None, :] + np.cos(dec) * Z[None, :]
+    w = np.cos(dec) * cH * X[None, :] - np.cos(dec) * sH * Y[None, :] + np.sin(dec) * Z[None, :]
     lam = C_LIGHT / freq_hz
-    return np.stack([u.ravel(), v.ravel()], axis=1) / lam
+    return np.stack([u.ravel(), v.ravel(), w.ravel()], axis=1) / lam
+
+
+def uv_tracks(bl_en: np.ndarray, n_time: int, dec: float, freq_hz: float,
+              lat: float = ASKAP_LAT, ha_hours: float = 6.0) -> np.ndarray:
+    """The (u, v) columns of :func:`uvw_tracks` (the coplanar model of Sect. 2.1 uses no w)."""
+    return np.ascontiguousarray(uvw_tracks(bl_en, n_time, dec, freq_hz, lat, ha_hours)[:, :2])
 
 
 # ----------------------------------------------------------------------------- skies
@@ -283,14 +291,16 @@ def attach_sd_level(p, level: float = 25.0):
 def single_pointing(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_time: int,
                     n_keep: Optional[int], sky: str, lambda_r: float, noise_rule,
                     freq_hz: float = 1.4e9, fwhm_deg: float = 1.0, flag_rate: float = 0.0,
-                    n_ant: int = 36, radius_m: float = 3000.0, n_src: int = 5) -> Problem:
-    """One pointing, one channel, identity interpolation grid (sub-image = sky)."""
+                    n_ant: int = 36, radius_m: float = 3000.0, n_src: int = 5, w_term: bool = False) -> Problem:
+    """One pointing, one channel, identity interpolation grid (sub-image = sky); w_term:
+    the problem carries the w coordinate of every sample (the full model of Eq. vis)."""
     st = _streams(seed, _STREAMS)
     pix = pixel_arcsec * ARCSEC
     enu = antenna_layout(st["layout"], n_ant, radius_m)
-    uv = uv_tracks(baselines(enu), n_time, LMC_DEC, freq_hz)
+    uvw = uvw_tracks(baselines(enu), n_time, LMC_DEC, freq_hz)
     if n_keep is not None:
-        uv = uv[:n_keep]
+        uvw = uvw[:n_keep]
+    uv = np.ascontiguousarray(uvw[:, :2])
     m = uv.shape[0]
     if sky == "points":
         x = np.zeros((1, n_sky, n_sky))
@@ -316,6 +326,7 @@ def single_pointing(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_tim
         interp=identity_interp(n_sky)[None].astype(np.float32),
         x_true=x, noise=noise, noise_rule=noise_rule,
         meta={"seed": seed, "freq_hz": freq_hz, "fwhm_deg": fwhm_deg},
+        w=uvw[:, 2].astype(np.float32) if w_term else None,
     )
 
 
@@ -337,10 +348,12 @@ def mosaic(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_rows: int, n
            pitch_px: float, fwhm_px: float, n_sub: int, time_range, flag_max: float,
            n_chan: int = 1, lambda_r: float = 1e-2, lambda_s: float = 1.0,
            sd_n: int = 64, sd_fwhm_arcmin: float = 16.0, freq_hz: float = 1.4e9,
-           n_keep: Optional[int] = None, max_vis_per_block: Optional[int] = None) -> Problem:
+           n_keep: Optional[int] = None, max_vis_per_block: Optional[int] = None,
+           w_term: bool = False) -> Problem:
     """Hexagonal mosaic of Gaussian-beam pointings over one sky (Sect. 4.4 geometry):
     each pointing has its own track length T_k ~ U{time_range} and flag rate
-    f_k ~ U[0, flag_max] (Bernoulli per visibility), giving uneven counts."""
+    f_k ~ U[0, flag_max] (Bernoulli per visibility), giving uneven counts.  w_term: the
+    problem carries the w coordinate of every sample (the full model of Eq. vis)."""
     st = _streams(seed, _STREAMS)
     pix = pixel_arcsec * ARCSEC
     enu = antenna_layout(st["layout"], 36, 3000.0)
@@ -351,21 +364,23 @@ def mosaic(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_rows: int, n
         x = lognormal_field(grf_k3(st["field"], n_sky))[None]
     else:
         x = ar1_cube(st["field"], n_chan, n_sky)
-    beams, grids, uvs, flags, offs = [], [], [], [], [0]
+    beams, grids, uvs, ws, flags, offs = [], [], [], [], [], [0]
     pb = gaussian_pb(n_sub, pix, fwhm_px * pix)
     for k in range(P):
         g, (rak, deck) = sin_interp(n_sky, n_sub, pix, centres[k])
         grids.append(g)
         beams.append(pb)
         n_t = int(st["tracks"].integers(time_range[0], time_range[1] + 1))
-        uvk = uv_tracks(bl, n_t, deck, freq_hz)
+        uvwk = uvw_tracks(bl, n_t, deck, freq_hz)
         if n_keep is not None:
-            uvk = uvk[:n_keep]
+            uvwk = uvwk[:n_keep]
         if max_vis_per_block is not None:
-            uvk = uvk[:max_vis_per_block]
+            uvwk = uvwk[:max_vis_per_block]
+        uvk = uvwk[:, :2]
         fr = st["flags"].uniform(0.0, flag_max)
         for c in range(n_chan):
             uvs.append(uvk)
+            ws.append(uvwk[:, 2])
             flags.append((st["flags"].uniform(size=uvk.shape[0]) < fr).astype(np.uint8))
             offs.append(offs[-1] + uvk.shape[0])
     uv = np.concatenate(uvs).astype(np.float32)
@@ -382,6 +397,7 @@ def mosaic(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_rows: int, n
         sd_n=sd_n, sd_stride=sd_stride, sd_offset=sd_stride // 2,
         sd_fwhm_rad=sd_fwhm_arcmin * ARCMIN,
         meta={"seed": seed, "freq_hz": freq_hz, "centres": centres, "fwhm_rad": fwhm_px * pix},
+        w=np.concatenate(ws).astype(np.float32) if w_term else None,
     )
 
 
@@ -446,6 +462,7 @@ class CubeProblem:
     sd_noise_frac: float = 0.01
     lambda_nu: float = 0.0  # spectral smoothness weight (couples adjacent channels)
     meta: dict = field(default_factory=dict)
+    w: Optional[np.ndarray] = None  # [sum M_k] float32 at the reference frequency, or None
 
     @property
     def n_vis(self) -> int:
@@ -458,6 +475,13 @@ class CubeProblem:
     def block(self, k: int, c: int) -> slice:
         i = k * self.n_chan + c
         return slice(int(self.vis_offsets[i]), int(self.vis_offsets[i + 1]))
+
+    def w_of(self, k: int, c: int) -> Optional[np.ndarray]:
+        """FP64 w of block (k, c) at the channel's frequency, or None (coplanar model)."""
+        if self.w is None:
+            return None
+        s = slice(int(self.pt_offsets[k]), int(self.pt_offsets[k + 1]))
+        return self.w[s].astype(np.float64) * self.uv_scale[c]
 
     def uv_of(self, k: int, c: int) -> np.ndarray:
         """FP64 uv of block (k, c), wavelengths at the channel's frequency."""
@@ -481,12 +505,14 @@ class CubeProblem:
             x_true=xc, noise=np.zeros(0), noise_rule=("abs", 1.0), sd_n=self.sd_n, sd_stride=self.sd_stride,
             sd_offset=self.sd_offset, sd_fwhm_rad=self.sd_fwhm_rad, sd_sigma=self.sd_sigma,
             sd_map=None if self.sd_map is None else self.sd_map[c:c + 1], sd_noise_frac=self.sd_noise_frac,
-            vis=self.vis[s], meta=dict(self.meta))
+            vis=self.vis[s], meta=dict(self.meta), w=self.w_of(k, c))
 
     def expand(self) -> Problem:
         """The same data as a per-block Problem (FP64 uv per block); small cubes only."""
         uv = np.concatenate([self.uv_of(k, c) for k in range(self.n_point) for c in range(self.n_chan)])
         w = np.concatenate([self.weight_of(k) for k in range(self.n_point) for c in range(self.n_chan)])
+        ww = None if self.w is None else np.concatenate(
+            [self.w_of(k, c) for k in range(self.n_point) for c in range(self.n_chan)])
         x = self.x_true if self.x_true is not None else np.zeros((self.n_chan, self.n_sky, self.n_sky))
         return Problem(
             name=self.name, n_chan=self.n_chan, n_sky=self.n_sky, pixel_rad=self.pixel_rad,
@@ -496,7 +522,7 @@ class CubeProblem:
             noise=np.zeros(0), noise_rule=("abs", 1.0), sd_n=self.sd_n, sd_stride=self.sd_stride,
             sd_offset=self.sd_offset, sd_fwhm_rad=self.sd_fwhm_rad, sd_sigma=self.sd_sigma,
             sd_map=self.sd_map, sd_noise_frac=self.sd_noise_frac, vis=self.vis, lambda_nu=self.lambda_nu,
-            meta=dict(self.meta))
+            meta=dict(self.meta), w=ww)
 
 
 def channel_freqs(n_chan: int, centre_hz: float, width_hz: float) -> np.ndarray:
@@ -508,13 +534,14 @@ def cube(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_rows: int, n_c
          fwhm_px: float, n_sub: int, n_time: int, n_chan: int, flag_max: float, centre_hz: float,
          width_hz: float, ref_hz: float = 1.4e9, lambda_r: float = 1e-2, lambda_s: float = 1.0,
          sd_n: int = 64, sd_fwhm_arcmin: float = 16.0, n_keep: Optional[int] = None, with_field: bool = True,
-         threads: Optional[int] = None) -> CubeProblem:
+         threads: Optional[int] = None, w_term: bool = False) -> CubeProblem:
     """Hexagonal mosaic observed in n_chan channels: one uv track per pointing (n_time
     samples x 630 baselines at ref_hz, scaled by nu_c / ref_hz per channel), flag rate
     f_kc ~ U[0, flag_max] per (pointing, channel) with Bernoulli flags, channel-correlated
     log-normal cube (AR(1), rho = 0.9), Rayleigh-Jeans flux scale per channel.  The
     visibilities are unit-variance complex noise; flags and noise of block b are drawn
-    from SeedSequence([seed, b]) so the blocks can be filled by parallel threads."""
+    from SeedSequence([seed, b]) so the blocks can be filled by parallel threads.  w_term:
+    each track also carries its w coordinate (the full model of Eq. vis)."""
     from concurrent.futures import ThreadPoolExecutor
 
     st = _streams(seed, _STREAMS)
@@ -525,15 +552,16 @@ def cube(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_rows: int, n_c
     P = centres.shape[0]
     x = ar1_cube(st["field"], n_chan, n_sky).astype(np.float32) if with_field else None
     pb = gaussian_pb(n_sub, pix, fwhm_px * pix)
-    grids, uvs, pt = [], [], [0]
+    grids, uvs, ws, pt = [], [], [], [0]
     for k in range(P):
         g, (rak, deck) = sin_interp(n_sky, n_sub, pix, centres[k])
         grids.append(g)
-        uvk = uv_tracks(bl, n_time, deck, ref_hz)
+        uvwk = uvw_tracks(bl, n_time, deck, ref_hz)
         if n_keep is not None:
-            uvk = uvk[:n_keep]
-        uvs.append(uvk)
-        pt.append(pt[-1] + uvk.shape[0])
+            uvwk = uvwk[:n_keep]
+        uvs.append(uvwk[:, :2])
+        ws.append(uvwk[:, 2])
+        pt.append(pt[-1] + uvwk.shape[0])
     freqs = channel_freqs(n_chan, centre_hz, width_hz)
     rates = st["flags"].uniform(0.0, flag_max, size=(P, n_chan))
     mk = np.diff(np.array(pt))
@@ -562,6 +590,7 @@ def cube(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_rows: int, n_c
         x_true=x, vis=vis, sd_n=sd_n, sd_stride=sd_stride, sd_offset=sd_stride // 2,
         sd_fwhm_rad=sd_fwhm_arcmin * ARCMIN,
         meta={"seed": seed, "freqs": freqs, "ref_hz": ref_hz, "centres": centres, "flag_rates": rates},
+        w=np.concatenate(ws).astype(np.float32) if w_term else None,
     )
 
 
