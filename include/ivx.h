@@ -74,7 +74,7 @@ typedef double ivx_real;
 typedef float ivx_real;
 #endif
 
-#define IVX_VERSION 2
+#define IVX_VERSION 3
 
 typedef enum {
     IVX_OK = 0,
@@ -145,6 +145,37 @@ ivx_status ivx_plan_set_data_shared(ivx_plan *plan, const ivx_real *uv, const iv
                                     const double *uv_scale, const ivx_real *vis,
                                     const uint8_t *flags, const ivx_real *beams,
                                     const ivx_real *interp, const ivx_real *sd_map, void *stream);
+
+/* The full forward model of Sect. 2.1, Eq. vis: every pixel of a sub-image also carries the
+ * factor 1/n and the phase w (n - 1), n = sqrt(1 - l^2 - m^2) of pixel (a, b):
+ *   V_j = sum_{a,b} s_c A_k x'_kc[a][b] / n_ab exp(-2 pi i (u_j l_b + v_j m_a + w_j (n_ab - 1))).
+ * The coplanar model above is its small-angle form, whose phase error grows as pi |w| theta^2
+ * with the distance theta from the phase centre (Sect. 2.1).
+ *   w        [M] (or [sum_k M_k] for a plan set with ivx_plan_set_data_shared, scaled by
+ *            uv_scale[c] like uv), wavelengths, caller order, host or device; NULL returns the
+ *            plan to the coplanar model.
+ *   w_width  w kernel width in planes, 0: max(the plan's kernel width, 8); 2..16.
+ *   w_sigma  oversampling of the w planes, 0: 2.0; 1.25..8.
+ * After this call ivx_objective_grad, ivx_objective, ivx_objective_forward / _backward,
+ * ivx_forward, ivx_adjoint and ivx_forward_adjoint evaluate the full model: w-stacking over
+ * planes w_p = w0 + p dw, dw = 1 / (w_sigma X) (X the range of n - 1 over the sub-image),
+ * interpolated in w with the same exponential-of-semicircle kernel and deapodized by its
+ * Fourier transform, so the w direction reaches the (u, v) transform's accuracy at that
+ * oversampling.  Cost per evaluation: one complex FFT pair per plane and block (the widest
+ * block's plane count, ivx_plan_w_info) plus w_width passes over every visibility each way;
+ * evaluations run as eager launches (no captured graph).  Device memory added: 12 B (float
+ * build; 24 B FP64) per live visibility, one n_sub x extended-column complex buffer per block,
+ * a copy of w, and three n_sub^2 tables.
+ * Errors: IVX_ESTATE before a successful set_data (set_data drops the w coordinates: call
+ * again after it); IVX_EINVAL for a width or oversampling out of range, a sub-image pixel
+ * outside the unit circle, a block spanning more than 255 planes, or work items longer than
+ * 2048 visibilities (choose a smaller chunk with ivx_set_blocking); IVX_ENONFINITE if an
+ * unflagged w is not finite.  On failure the plan keeps the coplanar model. */
+ivx_status ivx_plan_set_w(ivx_plan *plan, const ivx_real *w, int32_t w_width, double w_sigma, void *stream);
+
+/* Geometry of the full model: info[6] = {enabled (0/1), planes of the widest block, dw
+ * (wavelengths), x_c (the centre of the n - 1 range), w_width, w_sigma}. */
+ivx_status ivx_plan_w_info(const ivx_plan *plan, double *info);
 
 /* Replace the visibility data (and, if `weight` is non-NULL, the weights) of a plan whose
  * uv coverage, flags, beams and grids stay the same: vis [M][2] and weight [M] (or

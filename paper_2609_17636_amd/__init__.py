@@ -49,7 +49,7 @@ EXPORTS = ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_fo
            "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking",
            "ivx_plan_set_vis", "ivx_set_gridder_occupancy", "ivx_set_fused_fold", "ivx_objective",
            "ivx_objective_forward", "ivx_objective_backward", "ivx_forward_adjoint", "ivx_last_terms",
-           "ivx_nufft_probe")
+           "ivx_nufft_probe", "ivx_plan_set_w", "ivx_plan_w_info")
 
 STAGES = ("image_rows", "col_fwd", "grid", "fold", "col_inv", "row_inv", "sd", "sky", "final")
 
@@ -87,6 +87,8 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
     lib.ivx_forward_adjoint.argtypes = [vp, vp, vp, vp]
     lib.ivx_last_terms.argtypes = [vp, vp, vp]
     lib.ivx_nufft_probe.argtypes = [i32, i32, i32, vp]
+    lib.ivx_plan_set_w.argtypes = [vp, vp, i32, dbl, vp]
+    lib.ivx_plan_w_info.argtypes = [vp, vp]
     lib.ivx_stage_times.argtypes = [vp, vp, vp]
     lib.ivx_last_error.restype = ctypes.c_char_p
     lib.ivx_last_error.argtypes = []
@@ -245,6 +247,18 @@ class Plan:
         self._check(self.lib.ivx_plan_set_data_shared(self._h, _ptr(uv_), _ptr(w_), sc.ctypes.data, _ptr(vis_),
                                                        _ptr(fl), _ptr(b_), _ptr(g_), _ptr(sd_),
                                                        _stream_ptr(stream)))
+
+    def set_w(self, w, w_width: int = 0, w_sigma: float = 0.0, stream=None):
+        """The full forward model of Eq. vis (1/n factor and w phase): w [M] (or [sum_k M_k] for
+        a shared-uv plan) in wavelengths, caller order; None returns to the coplanar model."""
+        w_ = self._real(w)
+        self._check(self.lib.ivx_plan_set_w(self._h, _ptr(w_), int(w_width), float(w_sigma), _stream_ptr(stream)))
+
+    def w_info(self) -> dict:
+        a = np.zeros(6, dtype=np.float64)
+        self._check(self.lib.ivx_plan_w_info(self._h, a.ctypes.data))
+        return {"enabled": bool(a[0]), "planes": int(a[1]), "dw": float(a[2]), "x_centre": float(a[3]),
+                "w_width": int(a[4]), "w_sigma": float(a[5])}
 
     def set_vis(self, vis, weight=None, stream=None):
         """New data (and weights) for the same observation: cuda tensors [M][2] (or complex

@@ -179,6 +179,25 @@ struct ivx_plan {
     void *g_grad = nullptr;
     double *g_terms = nullptr;
     int64_t graph_nodes = 0;
+    // full forward model (w-stacked planes); set by ivx_plan_set_w, dropped by set_data
+    bool w_on = false;
+    int w_W = 0;                      // w kernel width in planes
+    double w_sigma = 2.0, w_beta = 0.0, w_dw = 0.0, w_xc = 0.0, w_X = 0.0;
+    int w_planes = 0;                 // planes of the block with the widest w range
+    uint64_t work_version = 0;        // advanced by every new work list
+    uint64_t w_version = ~0ull;       // work list the plane coordinates were sorted for
+    std::vector<double> uv_scale;     // shared uv: the channel scales of the caller's tracks
+    std::vector<double> w0_host;
+    std::vector<int32_t> np_host;
+    real *d_wsrc = nullptr;           // the caller's w, caller layout
+    WZ *d_wz = nullptr;               // plane coordinate of every record
+    cpx *d_wacc = nullptr;            // per-record plane accumulator / adjoint coefficient
+    cpx *d_wR = nullptr;              // row-pass buffer of the planes
+    size_t wR_count = 0;
+    double *d_wxp = nullptr, *d_wtp = nullptr;
+    real *d_wcorr = nullptr;
+    double *d_w0 = nullptr;
+    int32_t *d_wnp = nullptr;
 };
 
 namespace {
@@ -235,6 +254,17 @@ void free_all(ivx_plan *p) {
     p->d_jpart = p->d_rpart = p->d_kpart = p->d_terms = nullptr;
     p->d_npart = nullptr;
     p->has_data = false;
+    p->w_on = false;
+    p->w_version = ~0ull;
+    p->w_planes = 0;
+    p->d_wsrc = nullptr;
+    p->d_wz = nullptr;
+    p->d_wacc = p->d_wR = nullptr;
+    p->wR_count = 0;
+    p->d_wxp = p->d_wtp = nullptr;
+    p->d_wcorr = nullptr;
+    p->d_w0 = nullptr;
+    p->d_wnp = nullptr;
 }
 
 void free_one(ivx_plan *p, void *ptr) {
@@ -691,6 +721,7 @@ ivx_status build_work(ivx_plan *p, hipStream_t st) {
         IVX_HIP(hipMemcpyAsync(p->d_work, work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
     IVX_HIP(hipMemcpyAsync(p->d_tslot, tslot.data(), tslot.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     IVX_HIP(hipStreamSynchronize(st)); // host vectors die at return
+    ++p->work_version;
     return IVX_OK;
 }
 
@@ -879,6 +910,233 @@ ivx_status eval_gradient(ivx_plan *p, const real *sky, real *grad, real scale, h
     IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r, sd ? (real)p->d.lambda_s : real(0),
                        p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, grad, p->d_rpart,
                        SKY_FULL, scale, st, spec_weight(p), p->d_npart));
+    return IVX_OK;
+}
+
+// ---------------------------------------------------------------- full forward model
+// The w kernel (W_w planes, oversampling sigma_w) and the per-pixel tables of the sub-image:
+// x' = (n - 1) - x_c, dw x', and 1 / (n Phi(dw x')).  Fails if a pixel lies outside the unit
+// circle of direction cosines.
+ivx_status w_tables(ivx_plan *p, int Ww, double sigma) {
+    const Geom &g = p->g;
+    const int nk = g.nk, c = nk / 2;
+    const double delta = p->d.pixel_rad;
+    const int64_t nk2 = (int64_t)nk * nk;
+    std::vector<double> nm1(nk2), nn(nk2);
+    double xmin = 0.0;
+    for (int a = 0; a < nk; ++a)
+        for (int b = 0; b < nk; ++b) {
+            const double l = (b - c) * delta, m = (a - c) * delta, r2 = l * l + m * m;
+            if (!(r2 < 1.0)) return fail(IVX_EINVAL, "a sub-image pixel lies outside the unit circle of direction cosines");
+            const double n = std::sqrt(1.0 - r2);
+            nn[(size_t)a * nk + b] = n;
+            nm1[(size_t)a * nk + b] = -r2 / (1.0 + n);
+            xmin = std::min(xmin, nm1[(size_t)a * nk + b]);
+        }
+    if (!(xmin < 0.0)) return fail(IVX_EINVAL, "the sub-image has no extent in n - 1");
+    p->w_W = Ww;
+    p->w_sigma = sigma;
+    p->w_beta = 2.30 * Ww * (1.0 - 1.0 / (2.0 * sigma)) / 0.75;
+    p->w_xc = 0.5 * xmin;
+    p->w_X = -xmin;
+    p->w_dw = 1.0 / (sigma * p->w_X);
+    std::vector<double> gx, gw, xp(nk2), tp(nk2);
+    std::vector<real> corr(nk2);
+    gauss_legendre(std::max(64, 8 * Ww), gx, gw);
+    for (int64_t i = 0; i < nk2; ++i) {
+        xp[i] = nm1[i] - p->w_xc;
+        tp[i] = p->w_dw * xp[i];
+        corr[i] = (real)(1.0 / (nn[i] * es_phihat(2.0 * M_PI * tp[i], Ww, p->w_beta, gx, gw)));
+    }
+    ivx_status s;
+    if (!p->d_wxp) {
+        if ((s = dalloc(p, &p->d_wxp, nk2)) != IVX_OK || (s = dalloc(p, &p->d_wtp, nk2)) != IVX_OK ||
+            (s = dalloc(p, &p->d_wcorr, nk2)) != IVX_OK)
+            return s;
+    }
+    IVX_HIP(hipMemcpy(p->d_wxp, xp.data(), nk2 * sizeof(double), hipMemcpyHostToDevice));
+    IVX_HIP(hipMemcpy(p->d_wtp, tp.data(), nk2 * sizeof(double), hipMemcpyHostToDevice));
+    IVX_HIP(hipMemcpy(p->d_wcorr, corr.data(), nk2 * sizeof(real), hipMemcpyHostToDevice));
+    return IVX_OK;
+}
+
+// The caller's w of block b (device copy) and its scale.
+const real *w_source(const ivx_plan *p, int b, double &scale) {
+    const int k = b / p->g.C, c = b - (b / p->g.C) * p->g.C;
+    if (p->shared_uv) {
+        scale = p->uv_scale[c];
+        return p->d_wsrc + p->pt_off[k];
+    }
+    scale = 1.0;
+    return p->d_wsrc + p->offsets[b];
+}
+
+// Plane coordinates of the records for the current work list: per-block w range and plane
+// count, zeta of every record, and the records of each work item sorted by zeta.  Runs when
+// the work list changed since the last preparation.
+ivx_status w_prepare(ivx_plan *p, hipStream_t st) {
+    if (!p->w_on || p->w_version == p->work_version) return IVX_OK;
+    const Geom &g = p->g;
+    const int n_items = g.C * g.P;
+    if (p->chunk_max > WSORT_MAX)
+        return fail(IVX_EINVAL, "the full model needs work items of at most " + std::to_string(WSORT_MAX) +
+                                    " visibilities: set a smaller chunk with ivx_set_blocking");
+    const int wrb = wrange_blocks();
+    TmpBuf part, bad;
+    IVX_HIP(part.get((size_t)n_items * wrb * 2 * sizeof(double)));
+    IVX_HIP(bad.get(sizeof(unsigned int)));
+    double *pmin = part.as<double>(), *pmax = pmin + (size_t)n_items * wrb;
+    for (int b = 0; b < n_items; ++b) {
+        const int64_t L0 = p->block_live[b], n = p->block_live[b + 1] - L0;
+        double scale;
+        const real *ws = w_source(p, b, scale);
+        IVX_HIP(launch_wrange(n, p->d_perm + L0, ws, scale, pmin + (size_t)b * wrb, pmax + (size_t)b * wrb, st));
+    }
+    std::vector<double> hp((size_t)n_items * wrb * 2);
+    IVX_HIP(hipMemcpyAsync(hp.data(), part.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    IVX_HIP(hipStreamSynchronize(st));
+    p->w0_host.assign(n_items, 0.0);
+    p->np_host.assign(n_items, 0);
+    int planes = 0;
+    const double dw = p->w_dw;
+    const int W = p->w_W;
+    for (int b = 0; b < n_items; ++b) {
+        if (p->block_live[b + 1] == p->block_live[b]) continue;
+        double lo = INFINITY, hi = -INFINITY;
+        for (int i = 0; i < wrb; ++i) {
+            lo = std::min(lo, hp[(size_t)b * wrb + i]);
+            hi = std::max(hi, hp[(size_t)n_items * wrb + (size_t)b * wrb + i]);
+        }
+        if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(IVX_ENONFINITE, "w holds a non-finite value");
+        const double span = (hi - lo) / dw;
+        const double np = std::floor(span - 0.5) + W + 1;
+        if (np > (double)WZ_MAX_PLANES)
+            return fail(IVX_EINVAL, "block " + std::to_string(b) + " spans " + std::to_string((int64_t)np) +
+                                        " w planes (at most " + std::to_string(WZ_MAX_PLANES) +
+                                        "): lower w_sigma or the sub-image extent");
+        p->np_host[b] = (int32_t)np;
+        p->w0_host[b] = lo - dw * 0.5 * (W - 1);
+        planes = std::max(planes, (int)np);
+    }
+    ivx_status s;
+    if (!p->d_w0) {
+        if ((s = dalloc(p, &p->d_w0, n_items)) != IVX_OK || (s = dalloc(p, &p->d_wnp, n_items)) != IVX_OK) return s;
+    }
+    if (!p->d_wz) {
+        const size_t L = (size_t)std::max<int64_t>(p->m_live, 1);
+        if ((s = dalloc(p, &p->d_wz, L)) != IVX_OK || (s = dalloc(p, &p->d_wacc, L)) != IVX_OK) return s;
+    }
+    const size_t wr = (size_t)n_items * g.nk * g.ew;
+    if (wr != p->wR_count) {
+        if (p->d_wR) free_one(p, p->d_wR);
+        p->d_wR = nullptr;
+        p->wR_count = 0;
+        if ((s = dalloc(p, &p->d_wR, wr)) != IVX_OK) return s;
+        p->wR_count = wr;
+    }
+    IVX_HIP(hipMemcpyAsync(p->d_w0, p->w0_host.data(), n_items * sizeof(double), hipMemcpyHostToDevice, st));
+    IVX_HIP(hipMemcpyAsync(p->d_wnp, p->np_host.data(), n_items * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    IVX_HIP(hipMemsetAsync(bad.p, 0, sizeof(unsigned int), st));
+    for (int b = 0; b < n_items; ++b) {
+        const int64_t L0 = p->block_live[b], n = p->block_live[b + 1] - L0;
+        double scale;
+        const real *ws = w_source(p, b, scale);
+        IVX_HIP(launch_wzeta(n, p->d_perm + L0, ws, scale, p->w0_host[b], 1.0 / dw, p->d_wz + L0, bad.as<unsigned int>(),
+                             st));
+    }
+    IVX_HIP(launch_wsort(p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_wz, st));
+    IVX_HIP(prepare_wgrid(g, p->nwave));
+    unsigned int hb = 0;
+    IVX_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(hb), hipMemcpyDeviceToHost, st));
+    IVX_HIP(hipStreamSynchronize(st)); // host vectors die at return
+    if (hb) return fail(IVX_ENONFINITE, "a w value is not finite");
+    p->w_planes = planes;
+    p->w_version = p->work_version;
+    return IVX_OK;
+}
+
+WGeom wgeom(const ivx_plan *p) {
+    const Geom &g = p->g;
+    return WGeom{p->d_wnp, p->d_w0, p->d_wxp, p->d_wtp, p->d_wcorr, p->w_dw, p->w_xc, std::min(g.ew, g.nf),
+                 (int64_t)g.nk * g.ew};
+}
+
+WPlane wplane(const ivx_plan *p, int plane, bool adjoint) {
+    return WPlane{p->d_wz, adjoint ? nullptr : p->d_wacc, adjoint ? p->d_wacc : nullptr, plane, p->w_W, p->w_beta};
+}
+
+// Sky -> per-record sum over planes of the w-kernel-weighted plane transforms (d_wacc).
+ivx_status w_forward_planes(ivx_plan *p, const real *sky, hipStream_t st) {
+    const Geom &g = p->g;
+    const WGeom wg = wgeom(p);
+    IVX_HIP(launch_zero(p->d_wacc, std::max<int64_t>(p->m_live, 1) * (int64_t)sizeof(cpx), st));
+    for (int pl = 0; pl < p->w_planes; ++pl) {
+        IVX_HIP(launch_wplane_fwd(g, wg, pl, sky, p->d_beams, p->d_interp, p->d_fscale, p->d_dq, p->d_tw, p->d_wR,
+                                  p->d_ext, st));
+        IVX_HIP(launch_wgrid(MODE_WFWD, g, p->d_work, p->n_work, p->d_crd, p->d_ext, p->d_slots, wplane(p, pl, false),
+                             p->nwave, st));
+    }
+    return IVX_OK;
+}
+
+// Per-record adjoint coefficients (d_wacc) -> image gradient of every block (d_gp).
+ivx_status w_adjoint_planes(ivx_plan *p, hipStream_t st) {
+    const Geom &g = p->g;
+    const WGeom wg = wgeom(p);
+    if (p->w_planes == 0)
+        IVX_HIP(launch_zero(p->d_gp, (int64_t)g.C * g.P * g.nk * g.nk * (int64_t)sizeof(real), st));
+    for (int pl = 0; pl < p->w_planes; ++pl) {
+        IVX_HIP(launch_wgrid(MODE_WADJ, g, p->d_work, p->n_work, p->d_crd, p->d_ext, p->d_slots, wplane(p, pl, true),
+                             p->nwave, st));
+        IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, st));
+        IVX_HIP(launch_wplane_inv(g, wg, pl, p->d_ext, p->d_beams, p->d_fscale, p->d_dq, p->d_tw, p->d_wR, p->d_gp, st));
+    }
+    return IVX_OK;
+}
+
+// eval_value / eval_gradient of the full model.
+ivx_status eval_value_w(ivx_plan *p, const real *sky, double *terms_dev, bool keep_sd_adjoint, hipStream_t st) {
+    const Geom &g = p->g;
+    ivx_status s = w_forward_planes(p, sky, st);
+    if (s != IVX_OK) return s;
+    IVX_HIP(launch_wresid(p->d_work, p->n_work, wgeom(p), p->d_wz, p->d_vis, p->d_wgt, p->d_wacc, p->d_jpart, st));
+    const bool sd = sd_active(p);
+    if (sd) {
+        IVX_HIP(launch_sd_rows(g, sky, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_U, st));
+        IVX_HIP(launch_sd_cols(g, p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_sdmap,
+                               (real)(1.0 / (p->d.sd_sigma * p->d.sd_sigma)), p->d_E, p->d_kpart, st));
+        if (keep_sd_adjoint)
+            IVX_HIP(launch_sd_back(g, p->d_E, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_U, st));
+    }
+    IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r, real(0), nullptr, nullptr, 0, 0, 1,
+                       0, nullptr, p->d_rpart, SKY_VALUE, real(1), st, spec_weight(p), p->d_npart));
+    IVX_HIP(launch_final(p->d_jpart, p->n_work, p->d_jpart + p->n_work, p->d_rpart, p->n_rpart, p->d_kpart,
+                         sd ? p->n_kpart : 0, p->d_npart, spec_weight(p) != real(0) ? p->n_rpart : 0, p->d.lambda_r,
+                         sd ? p->d.lambda_s : 0.0, p->d.lambda_nu, p->d_terms, terms_dev, st));
+    return IVX_OK;
+}
+
+ivx_status eval_gradient_w(ivx_plan *p, const real *sky, real *grad, real scale, hipStream_t st) {
+    const Geom &g = p->g;
+    ivx_status s = w_adjoint_planes(p, st);
+    if (s != IVX_OK) return s;
+    const bool sd = sd_active(p);
+    IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r, sd ? (real)p->d.lambda_s : real(0),
+                       p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, grad, p->d_rpart,
+                       SKY_FULL, scale, st, spec_weight(p), p->d_npart));
+    return IVX_OK;
+}
+
+// ivx_adjoint / ivx_forward_adjoint of the full model: caller coefficients (times the natural
+// weights unless `unweighted`) -> planes -> reprojection transpose into `image`.
+ivx_status w_adjoint_call(ivx_plan *p, const real *vis, real *image, bool unweighted, hipStream_t st) {
+    ivx_status s = w_prepare(p, st);
+    if (s != IVX_OK) return s;
+    IVX_HIP(launch_win(p->d_work, p->n_work, wgeom(p), p->d_wz, p->d_perm, p->d_boff, p->d_wgt, unweighted,
+                       reinterpret_cast<const cpx *>(vis), p->d_wacc, st));
+    if ((s = w_adjoint_planes(p, st)) != IVX_OK) return s;
+    IVX_HIP(launch_sky(p->g, image, p->d_gp, p->d_cptr, p->d_cent, real(0), real(0), nullptr, nullptr, 0, 0, 1, 0,
+                       image, p->d_rpart, SKY_ADJOINT, real(1), st));
     return IVX_OK;
 }
 
@@ -1159,6 +1417,44 @@ ivx_status ivx_plan_set_data_shared(ivx_plan *p, const ivx_real *uv, const ivx_r
     return set_data_impl(p, src, true, beams, interp, sd_map, stream);
 }
 
+ivx_status ivx_plan_set_w(ivx_plan *p, const ivx_real *w, int32_t w_width, double w_sigma, void *stream) {
+    g_last_error.clear();
+    if (!p) return fail(IVX_EINVAL, "plan is NULL");
+    if (!p->has_data) return fail(IVX_ESTATE, "ivx_plan_set_data has not succeeded on this plan");
+    drop_graph(p);
+    ++p->epoch;
+    if (!w) {
+        p->w_on = false;
+        return IVX_OK;
+    }
+    const int Ww = w_width ? w_width : std::max(p->g.W, 8);
+    const double sigma = w_sigma != 0.0 ? w_sigma : 2.0;
+    if (Ww < 2 || Ww > 16) return fail(IVX_EINVAL, "w_width must be 0 or in [2, 16]");
+    if (!std::isfinite(sigma) || sigma < 1.25 || sigma > 8.0) return fail(IVX_EINVAL, "w_sigma must be 0 or in [1.25, 8]");
+    hipStream_t st = (hipStream_t)stream;
+    IVX_HIP(hipStreamSynchronize(st));
+    p->w_on = false;
+    ivx_status s = w_tables(p, Ww, sigma);
+    if (s != IVX_OK) return s;
+    const int64_t n = p->shared_uv ? p->pt_off.back() : p->m_total;
+    if (!p->d_wsrc && (s = dalloc(p, &p->d_wsrc, (size_t)std::max<int64_t>(n, 1))) != IVX_OK) return s;
+    if (n > 0) IVX_HIP(hipMemcpy(p->d_wsrc, w, n * sizeof(real), hipMemcpyDefault));
+    p->w_on = true;
+    p->w_version = ~0ull;
+    if ((s = w_prepare(p, st)) != IVX_OK) {
+        p->w_on = false;
+        return s;
+    }
+    return IVX_OK;
+}
+
+ivx_status ivx_plan_w_info(const ivx_plan *p, double *info) {
+    if (!p || !info) return fail(IVX_EINVAL, "plan and info must be non-NULL");
+    const double v[6] = {p->w_on ? 1.0 : 0.0, (double)p->w_planes, p->w_dw, p->w_xc, (double)p->w_W, p->w_sigma};
+    std::memcpy(info, v, sizeof(v));
+    return IVX_OK;
+}
+
 } // extern "C"
 
 namespace {
@@ -1190,6 +1486,8 @@ ivx_status set_data_impl(ivx_plan *p, const VisSource &src, bool shared, const i
     free_all(p);
     ++p->epoch;
     p->shared_uv = shared;
+    p->uv_scale.clear();
+    if (shared) p->uv_scale.assign(src.scale, src.scale + g.C);
     p->pt_off.assign(g.P + 1, 0);
     for (int k = 0; k < g.P; ++k)
         p->pt_off[k + 1] = p->pt_off[k] + (p->offsets[(size_t)k * g.C + 1] - p->offsets[(size_t)k * g.C]);
@@ -1397,6 +1695,12 @@ ivx_status ivx_objective_grad(ivx_plan *p, const ivx_real *sky, ivx_real *grad, 
     hipStream_t st = (hipStream_t)stream;
     // device `terms` is written by the last kernel itself; host `terms` gets a copy
     double *terms_dev = device_terms(terms);
+    if (p->w_on) { // full model: eager launches, one pass per w plane
+        if ((s = w_prepare(p, st)) != IVX_OK) return s;
+        if ((s = eval_value_w(p, sky, terms_dev, true, st)) != IVX_OK) return s;
+        if ((s = eval_gradient_w(p, sky, grad, real(1), st)) != IVX_OK) return s;
+        return copy_terms(p, terms, terms_dev, st);
+    }
     if (p->use_graph && p->timing_mask == 0) {
         if (!(p->gexec && p->g_sky == sky && p->g_grad == grad && p->g_terms == terms_dev)) {
             drop_graph(p);
@@ -1435,6 +1739,13 @@ ivx_status ivx_forward(ivx_plan *p, const ivx_real *sky, ivx_real *model_vis, vo
     if (s != IVX_OK) return s;
     if (!sky || (!model_vis && p->m_total > 0)) return fail(IVX_EINVAL, "sky and model_vis are required");
     hipStream_t st = (hipStream_t)stream;
+    if (p->w_on) {
+        if ((s = w_prepare(p, st)) != IVX_OK || (s = w_forward_planes(p, sky, st)) != IVX_OK) return s;
+        IVX_HIP(launch_zero(model_vis, p->m_total * 2 * (int64_t)sizeof(real), st));
+        IVX_HIP(launch_wout(p->d_work, p->n_work, wgeom(p), p->d_wz, p->d_perm, p->d_boff, p->d_wacc,
+                            reinterpret_cast<cpx *>(model_vis), st));
+        return IVX_OK;
+    }
     if ((s = run_forward_half(p, sky, st)) != IVX_OK) return s;
     IVX_HIP(launch_zero(model_vis, p->m_total * 2 * (int64_t)sizeof(real), st));
     IVX_HIP(launch_grid(MODE_FWD, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff, p->d_ext,
@@ -1447,6 +1758,7 @@ ivx_status ivx_adjoint(ivx_plan *p, const ivx_real *vis, ivx_real *image, void *
     if (s != IVX_OK) return s;
     if (!image || (!vis && p->m_total > 0)) return fail(IVX_EINVAL, "vis and image are required");
     hipStream_t st = (hipStream_t)stream;
+    if (p->w_on) return w_adjoint_call(p, vis, image, false, st);
     IVX_HIP(launch_grid(MODE_ADJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff, p->d_ext,
                         p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave, p->lanes * 10 + p->vpi, p->occupancy, st));
     if ((s = run_adjoint_half(p, st)) != IVX_OK) return s;
@@ -1461,7 +1773,11 @@ ivx_status ivx_objective(ivx_plan *p, const ivx_real *sky, double *terms, void *
     if (!sky || !terms) return fail(IVX_EINVAL, "sky and terms are required");
     hipStream_t st = (hipStream_t)stream;
     double *terms_dev = device_terms(terms);
-    if ((s = eval_value(p, sky, terms_dev, MODE_VAL, st)) != IVX_OK) return s;
+    if (p->w_on) {
+        if ((s = w_prepare(p, st)) != IVX_OK || (s = eval_value_w(p, sky, terms_dev, false, st)) != IVX_OK) return s;
+    } else if ((s = eval_value(p, sky, terms_dev, MODE_VAL, st)) != IVX_OK) {
+        return s;
+    }
     return copy_terms(p, terms, terms_dev, st);
 }
 
@@ -1471,7 +1787,11 @@ ivx_status ivx_objective_forward(ivx_plan *p, const ivx_real *sky, double *terms
     if (!sky || !terms) return fail(IVX_EINVAL, "sky and terms are required");
     hipStream_t st = (hipStream_t)stream;
     double *terms_dev = device_terms(terms);
-    if ((s = eval_value(p, sky, terms_dev, MODE_OBJ, st)) != IVX_OK) return s;
+    if (p->w_on) {
+        if ((s = w_prepare(p, st)) != IVX_OK || (s = eval_value_w(p, sky, terms_dev, true, st)) != IVX_OK) return s;
+    } else if ((s = eval_value(p, sky, terms_dev, MODE_OBJ, st)) != IVX_OK) {
+        return s;
+    }
     p->fwd_epoch = p->epoch;
     p->fwd_sky = sky;
     return copy_terms(p, terms, terms_dev, st);
@@ -1486,6 +1806,7 @@ ivx_status ivx_objective_backward(ivx_plan *p, const ivx_real *sky, ivx_real *gr
         return fail(IVX_ESTATE, "ivx_objective_backward must follow ivx_objective_forward of the same sky with no "
                                 "other call on the plan in between");
     ++p->epoch; // the adjoint half consumes the slots: a second backward needs a new forward
+    if (p->w_on) return eval_gradient_w(p, sky, grad, (real)scale, (hipStream_t)stream);
     return eval_gradient(p, sky, grad, (real)scale, (hipStream_t)stream);
 }
 
@@ -1494,6 +1815,7 @@ ivx_status ivx_forward_adjoint(ivx_plan *p, const ivx_real *vis, ivx_real *image
     if (s != IVX_OK) return s;
     if (!image || (!vis && p->m_total > 0)) return fail(IVX_EINVAL, "vis and image are required");
     hipStream_t st = (hipStream_t)stream;
+    if (p->w_on) return w_adjoint_call(p, vis, image, true, st);
     IVX_HIP(launch_grid(MODE_ADJ, p->g, p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_boff,
                         p->d_ext, p->d_slots, p->d_jpart, reinterpret_cast<const cpx *>(vis), nullptr, p->nwave,
                         p->lanes * 10 + p->vpi, p->occupancy, st, true));

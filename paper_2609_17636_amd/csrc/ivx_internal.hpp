@@ -66,8 +66,33 @@ struct Geom {
 
 // Gridding modes: the objective (degrid, residual, data term, spread), the forward model
 // alone, the adjoint alone (spread of given visibilities), and the data term alone (degrid
-// and residual, nothing spread: an objective value without its gradient).
-enum GridMode { MODE_OBJ = 0, MODE_FWD = 1, MODE_ADJ = 2, MODE_VAL = 3 };
+// and residual, nothing spread: an objective value without its gradient).  The two w-plane
+// modes serve the w-stacked full model: degrid one w plane and add it, weighted by the
+// visibility's w kernel, to a per-record accumulator (MODE_WFWD); spread per-record
+// coefficients times the w kernel into one w plane (MODE_WADJ).
+enum GridMode { MODE_OBJ = 0, MODE_FWD = 1, MODE_ADJ = 2, MODE_VAL = 3, MODE_WFWD = 4, MODE_WADJ = 5 };
+
+// w coordinate of a sorted record in units of w planes, zeta = (w - w0_b) / dw, with w folded
+// like the record (negated when (u, v) was): float build 8.24 fixed point (plane index in the
+// top 8 bits), double build plain double.
+#ifdef IVX_REAL_DOUBLE
+typedef double WZ;
+#else
+typedef uint32_t WZ;
+#endif
+constexpr int WZ_MAX_PLANES = 255; // planes a block may span (float build: 8-bit plane index)
+
+// One w plane of a w-stacked gridding pass: the records' plane coordinates (sorted within each
+// work item), the per-record accumulator (MODE_WFWD) or coefficients (MODE_WADJ), the plane
+// index and the w kernel (width W in planes, shape beta).
+struct WPlane {
+    const WZ *wz;
+    cpx *acc;
+    const cpx *q;
+    int plane;
+    int W;
+    double beta;
+};
 
 // Sky pass tiling: blocks of SKY_T x SKY_T pixels, 256 threads, thread t at row t / SKY_T,
 // column t % SKY_T of the block; the reprojection transpose is stored per wave ("slice":
@@ -172,6 +197,50 @@ hipError_t sort_keys(void *temp, size_t &temp_bytes, const uint64_t *in, uint64_
                      hipStream_t st);
 hipError_t sort_pairs(void *temp, size_t &temp_bytes, const uint64_t *kin, uint64_t *kout, const uint32_t *vin,
                       uint32_t *vout, int n, int end_bit, hipStream_t st);
+
+// Geometry of the w-stacked full model, passed by value to its kernels.
+struct WGeom {
+    const int32_t *np;  // [n_items] planes of each block (0: no live visibility)
+    const double *w0;   // [n_items] w of plane 0 of each block (wavelengths)
+    const double *xp;   // [nk^2] x' = (n - 1) - x_c of every sub-image pixel
+    const double *tp;   // [nk^2] dw x'
+    const real *corr;   // [nk^2] 1 / (n Phi(dw x')): the 1/n factor and the w deapodization
+    double dw, xc;      // plane spacing (wavelengths) and the centre x_c of the n - 1 range
+    int ncol;           // distinct frequency columns of the extended grid, min(ew, nf)
+    int64_t r_stride;   // nk * ew: row-pass buffer per block
+};
+constexpr int WSORT_MAX = 2048; // records per work item the plane-coordinate sort handles
+
+// w-stacked passes (ivx_wstack.hip).  Plan time: per-block (min, max) partials of the folded w
+// (wrange_blocks() pairs per launch), the plane coordinate of every record, the per-work-item
+// sort.  Per plane: forward row + column passes into the extended grid; adjoint column + row
+// passes accumulating the image gradient into gp.  Per record: residual / data term /
+// adjoint coefficients, the model to caller order, caller coefficients to records.
+int wrange_blocks();
+hipError_t launch_wrange(int64_t n, const int32_t *perm, const real *wsrc, double scale, double *pmin, double *pmax,
+                         hipStream_t st);
+hipError_t launch_wzeta(int64_t n, const int32_t *perm, const real *wsrc, double scale, double w0, double inv_dw,
+                        WZ *out, unsigned int *bad, hipStream_t st);
+hipError_t launch_wsort(const WorkItem *work, int n_work, VisCoord *crd, cpx *vis, real *wgt, int32_t *perm, WZ *wz,
+                        hipStream_t st);
+hipError_t launch_wplane_fwd(const Geom &g, const WGeom &wg, int plane, const real *sky, const real *beams,
+                             const real *interp, const real *fscale, const real *dq, const cpx *tw, cpx *R, cpx *ext,
+                             hipStream_t st);
+hipError_t launch_wplane_inv(const Geom &g, const WGeom &wg, int plane, const cpx *ext, const real *beams,
+                             const real *fscale, const real *dq, const cpx *tw, cpx *R, real *gp, hipStream_t st);
+hipError_t launch_wresid(const WorkItem *work, int n_work, const WGeom &wg, const WZ *wz, const cpx *vis,
+                         const real *wgt, cpx *acc, double *jpart, hipStream_t st);
+hipError_t launch_wout(const WorkItem *work, int n_work, const WGeom &wg, const WZ *wz, const int32_t *perm,
+                       const int64_t *boff, const cpx *acc, cpx *out, hipStream_t st);
+hipError_t launch_win(const WorkItem *work, int n_work, const WGeom &wg, const WZ *wz, const int32_t *perm,
+                      const int64_t *boff, const real *wgt, bool unweighted, const cpx *in, cpx *q, hipStream_t st);
+
+// w-stacked gridding pass of one plane (vector gridder, 16-lane groups, one visibility per
+// group per iteration), mode MODE_WFWD or MODE_WADJ; prepare_wgrid raises the dynamic-LDS
+// limit of both (call before any stream capture).
+hipError_t launch_wgrid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
+                        const cpx *ext, cpx *slots, const WPlane &wp, int nwave, hipStream_t st);
+hipError_t prepare_wgrid(const Geom &g, int nwave);
 
 // Gridding on the matrix cores (float build, windows of at most 16 x 16 cells, one wave
 // per work item): selected by lanes = GRID_MFMA_LANES, variant = GRID_MFMA_VARIANT.

@@ -24,6 +24,7 @@
 // The NUFFT is the exponential-of-semicircle scheme of Barnett et al. (2019): kernel
 // phi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1)), deapodization by its Fourier transform.
 #include "ivx_internal.hpp"
+#include "ivx_fft.hpp"
 
 #include <math.h>
 
@@ -32,166 +33,6 @@
 #include <type_traits>
 
 namespace ivx {
-
-constexpr int NT = 256; // threads per block of every kernel
-
-__device__ __forceinline__ cpx cmul(cpx a, cpx b) {
-    return cpx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-__device__ __forceinline__ cpx cadd(cpx a, cpx b) { return cpx{a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cpx csub(cpx a, cpx b) { return cpx{a.re - b.re, a.im - b.im}; }
-
-// ------------------------------------------------------------------------------ FFT
-// In-LDS Stockham autosort FFT (mixed radix 2 then 4) of CB interleaved transforms of
-// length N = 2^LOGN: element i of transform c is buf[i * CB + c].  Each stage reads all
-// of a thread's butterfly inputs into registers, synchronises, then writes the outputs,
-// so the transform runs in place.  Twiddles come from a table tw[t] = exp(-2 pi i t / N),
-// t < 3N/4, staged in LDS through TwStage (conjugated for the inverse); no scaling is
-// applied in either direction.
-template <int LOGN> constexpr int tw_len() { return 3 * (1 << LOGN) / 4; }
-
-// The twiddle table is fetched into registers at the start of a kernel and stored to LDS
-// only after the kernel's own data loads have been issued, so the two global-memory
-// latencies overlap instead of following each other.
-template <int LOGN> struct TwStage {
-    static constexpr int PER = (tw_len<LOGN>() + NT - 1) / NT;
-    cpx v[PER];
-    __device__ __forceinline__ void fetch(const cpx *__restrict__ tw) {
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int i = threadIdx.x + u * NT;
-            if (i < tw_len<LOGN>()) v[u] = tw[i];
-        }
-    }
-    __device__ __forceinline__ void store(cpx *tws) const {
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int i = threadIdx.x + u * NT;
-            if (i < tw_len<LOGN>()) tws[i] = v[u];
-        }
-    }
-};
-
-template <int LOGN, int CB, bool INV>
-__device__ __forceinline__ void fft_lds(cpx *buf, const cpx *tw) {
-    constexpr int N = 1 << LOGN;
-    const int tid = threadIdx.x;
-    int Ns = 1;
-    if constexpr (LOGN & 1) {
-        constexpr int TOT = CB * (N / 2);
-        constexpr int BPT = (TOT + NT - 1) / NT;
-        cpx v0[BPT], v1[BPT];
-#pragma unroll
-        for (int t = 0; t < BPT; ++t) {
-            const int u = tid + t * NT;
-            if (u < TOT) {
-                const int c = u % CB, jj = u / CB;
-                v0[t] = buf[jj * CB + c];
-                v1[t] = buf[(jj + N / 2) * CB + c];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int t = 0; t < BPT; ++t) {
-            const int u = tid + t * NT;
-            if (u < TOT) {
-                const int c = u % CB, jj = u / CB;
-                buf[(2 * jj) * CB + c] = cadd(v0[t], v1[t]);
-                buf[(2 * jj + 1) * CB + c] = csub(v0[t], v1[t]);
-            }
-        }
-        __syncthreads();
-        Ns = 2;
-    }
-#pragma unroll
-    for (int s = 0; s < LOGN / 2; ++s) {
-        constexpr int TOT = CB * (N / 4);
-        constexpr int BPT = (TOT + NT - 1) / NT;
-        cpx v[BPT][4];
-        const int st = N / (4 * Ns);
-#pragma unroll
-        for (int t = 0; t < BPT; ++t) {
-            const int u = tid + t * NT;
-            if (u < TOT) {
-                const int c = u % CB, jj = u / CB;
-                const int k = jj & (Ns - 1);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    cpx x = buf[(jj + r * (N / 4)) * CB + c];
-                    if (r > 0) {
-                        cpx w = tw[k * r * st];
-                        if (INV) w.im = -w.im;
-                        x = cmul(x, w);
-                    }
-                    v[t][r] = x;
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int t = 0; t < BPT; ++t) {
-            const int u = tid + t * NT;
-            if (u < TOT) {
-                const int c = u % CB, jj = u / CB;
-                const int k = jj & (Ns - 1);
-                const cpx a0 = v[t][0], a1 = v[t][1], a2 = v[t][2], a3 = v[t][3];
-                const cpx s02 = cadd(a0, a2), d02 = csub(a0, a2);
-                const cpx s13 = cadd(a1, a3), d13 = csub(a1, a3);
-                // forward: y1 = d02 - i d13, y3 = d02 + i d13; inverse swaps the signs
-                const cpx id13 = INV ? cpx{-d13.im, d13.re} : cpx{d13.im, -d13.re};
-                const int o = ((jj - k) << 2) + k;
-                buf[o * CB + c] = cadd(s02, s13);
-                buf[(o + Ns) * CB + c] = cadd(d02, id13);
-                buf[(o + 2 * Ns) * CB + c] = csub(s02, s13);
-                buf[(o + 3 * Ns) * CB + c] = csub(d02, id13);
-            }
-        }
-        __syncthreads();
-        Ns *= 4;
-    }
-}
-
-// Global loads each thread of a column pass issues before it waits for the first: with a few
-// blocks of LDS-resident columns per compute unit, one load at a time leaves the latency of
-// every row exposed.
-constexpr int COL_LOADS = 8;
-
-// Columns per block of a column pass: at most 32 KB of LDS columns, so that four blocks share
-// a compute unit (at 1024-point columns 4 per block measured faster than 8 and 2).
-// Work index of a column-pass block.  Blocks are dealt to the eight XCDs round-robin by
-// launch index; block b takes work index (b % 8) * per + b / 8 of the (item, column group)
-// pairs, so each XCD runs one contiguous range of them and neighbouring column groups, which
-// share the cache lines of their row segments, meet in the same L2.  The launch has
-// 8 * per blocks; false for the padding blocks past the last pair.
-template <int CB> __device__ __forceinline__ bool col_block(const Geom &g, int &item, int &c0) {
-    const int64_t ngrp = (g.rw + CB - 1) / CB, total = ngrp * g.C * g.P, per = (total + 7) / 8;
-    const int64_t b = blockIdx.x, w = (b & 7) * per + (b >> 3);
-    if (w >= total) return false;
-    item = (int)(w / ngrp);
-    c0 = (int)(w - (w / ngrp) * ngrp) * CB;
-    return true;
-}
-
-template <int LOGN> constexpr int col_batch() {
-    constexpr int b = 32768 / ((1 << LOGN) * (int)sizeof(cpx));
-    return b > 16 ? 16 : (b < 1 ? 1 : b);
-}
-
-// --------------------------------------------------------------------- reprojection
-// Bilinear sample at (row sy, col sx); pixel (i, j) sits at (i, j); outside pixels are 0.
-__device__ __forceinline__ real bilinear(const real *__restrict__ sky, int N, real sy, real sx) {
-    if (!(sy > real(-1) && sy < real(N) && sx > real(-1) && sx < real(N))) return real(0);
-    const real fi = floor(sy), fj = floor(sx);
-    const int i0 = (int)fi, j0 = (int)fj;
-    const real fy = sy - fi, fx = sx - fj;
-    const bool r0 = i0 >= 0, r1 = i0 + 1 < N, c0 = j0 >= 0, c1 = j0 + 1 < N;
-    const real *p = sky + (int64_t)i0 * N + j0;
-    const real x00 = (r0 && c0) ? p[0] : real(0);
-    const real x01 = (r0 && c1) ? p[1] : real(0);
-    const real x10 = (r1 && c0) ? p[N] : real(0);
-    const real x11 = (r1 && c1) ? p[N + 1] : real(0);
-    return (real(1) - fy) * ((real(1) - fx) * x00 + fx * x01) + fy * ((real(1) - fx) * x10 + fx * x11);
-}
 
 // --------------------------------------------------------------- forward row pass
 template <int LOGN>
@@ -359,7 +200,43 @@ struct GridArgs {
     int nwave;
     int n_work;
     int unweighted; // adjoint mode: spread the given visibilities without the natural weights
+    // w-plane modes
+    const WZ *wz;
+    cpx *wacc;
+    const cpx *wq;
+    int wplane;
+    int wW;
+    real wbeta2; // w kernel shape, scaled like beta2 below
 };
+
+// Signed distance, in planes, of a record's w from plane p.
+__device__ __forceinline__ real wz_dist(WZ z, int p) {
+#ifdef IVX_REAL_DOUBLE
+    return z - (double)p;
+#else
+    return (real)((int)(z >> 24) - p) + (real)(z & 0xFFFFFFu) * real(5.9604644775390625e-08);
+#endif
+}
+
+// First record of a work item's (sorted) list whose plane coordinate reaches the given
+// number of half planes: lower bound of zeta >= h2 / 2.
+__device__ __forceinline__ int wz_lower(const WZ *__restrict__ z, int n, int h2) {
+#ifdef IVX_REAL_DOUBLE
+    const double key = 0.5 * (double)h2;
+#else
+    const int64_t k = (int64_t)h2 << 23;
+    if (k <= 0) return 0;
+    if (k > (int64_t)0xFFFFFFFFll) return n;
+    const uint32_t key = (uint32_t)k;
+#endif
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (z[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
 
 // Work items per row of the gridding launch: the dispatch packet counts work-items of one
 // grid dimension in 32 bits, so long work lists (spectral cubes) wrap into blockIdx.y.
@@ -448,9 +325,11 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     const int nwave = a.nwave;
     const int ngroups = nwave * GPW;
     cpx *Fw = reinterpret_cast<cpx *>(smem_raw);
-    constexpr bool SPREAD = MODE == MODE_OBJ || MODE == MODE_ADJ;
+    constexpr bool WPL = MODE == MODE_WFWD || MODE == MODE_WADJ; // one w plane of the full model
+    constexpr bool NOGRID = MODE == MODE_ADJ || MODE == MODE_WADJ; // the grid window is not read
+    constexpr bool SPREAD = MODE == MODE_OBJ || MODE == MODE_ADJ || MODE == MODE_WADJ;
     constexpr bool DATA = MODE == MODE_OBJ || MODE == MODE_VAL; // residual against the data
-    cpx *Hw = Fw + (MODE == MODE_ADJ ? 0 : wsz);
+    cpx *Hw = Fw + (NOGRID ? 0 : wsz);
     const int64_t wid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     if (wid >= a.n_work) return; // tail of the last row: the whole block leaves together
     const WorkItem wi = a.work[wid];
@@ -458,7 +337,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     // e = cc * win + r without an integer division: (e + 1/2) / win is never within float
     // rounding of an integer for e < 2^16
     const float inv_win = 1.0f / (float)win;
-    if (MODE != MODE_ADJ) {
+    if (!NOGRID) {
         const cpx *F = a.ext + (int64_t)wi.item * g.ext_stride + (int64_t)(wi.tx * g.T) * g.eh + wi.ty * g.T;
         for (int e = tid; e < win * win; e += blockDim.x) {
             const int cc = (int)(((float)e + 0.5f) * inv_win), r = e - cc * win;
@@ -487,10 +366,18 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     const real zoff = real(0.5) * real(W) - real(1);
     real jacc = real(0);
 
-    // this group's segment of the tile's list, walked VPI visibilities at a time
-    const int seg = (wi.count + ngroups - 1) / ngroups;
-    const int v0 = gid * seg;
-    const int v1 = min(wi.count, v0 + seg);
+    // this group's segment of the tile's list, walked VPI visibilities at a time; a w plane
+    // only takes the records whose w kernel reaches it, zeta in [p - W_w / 2, p + W_w / 2),
+    // a contiguous range of the work item's list (sorted by zeta)
+    int base = 0, cnt = wi.count;
+    if constexpr (WPL) {
+        const WZ *z = a.wz + wi.begin;
+        base = wz_lower(z, wi.count, 2 * a.wplane - a.wW);
+        cnt = wz_lower(z, wi.count, 2 * a.wplane + a.wW) - base;
+    }
+    const int seg = (cnt + ngroups - 1) / ngroups;
+    const int v0 = base + gid * seg;
+    const int v1 = min(base + cnt, v0 + seg);
     const int nit = (seg + VPI - 1) / VPI;
     const VisCoord *crd = a.crd + wi.begin;
     const cpx *vis = a.vis + wi.begin;
@@ -526,6 +413,11 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
             if (DATA) { r[u].y = at(vis, vn); r[u].w = at(wgt, vn); }
             if (MODE == MODE_ADJ) { r[u].w = a.unweighted ? real(1) : at(wgt, vn); r[u].p = at(perm, vn); }
             if (MODE == MODE_FWD) { r[u].p = at(perm, vn); }
+            if constexpr (WPL) {
+                // w carries the record's w-kernel weight for this plane, y its coefficient
+                r[u].w = es_kernel(wz_dist(at(a.wz + wi.begin, vn), a.wplane), real(2) / real(a.wW), a.wbeta2);
+                if (MODE == MODE_WADJ) r[u].y = at(a.wq + wi.begin, vn);
+            }
         }
     };
 
@@ -578,7 +470,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
             ar[u] = real(0);
             ai[u] = real(0);
         }
-        if (MODE != MODE_ADJ) {
+        if (!NOGRID) {
             if (colok) {
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
@@ -608,6 +500,21 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
             }
             return;
         }
+        if (MODE == MODE_WFWD) {
+            // planes run as successive launches and a record belongs to one group of one work
+            // item: a plain read-modify-write, in plane order
+#pragma unroll
+            for (int u = 0; u < VPI; ++u) {
+                if (valid[u] && t == 0) {
+                    cpx *o = a.wacc + wi.begin + (v0 + it * VPI + u);
+                    cpx ov = *o;
+                    ov.re += cur[u].w * ar[u];
+                    ov.im += cur[u].w * ai[u];
+                    *o = ov;
+                }
+            }
+            return;
+        }
         real cre[VPI], cim[VPI];
 #pragma unroll
         for (int u = 0; u < VPI; ++u) {
@@ -617,6 +524,9 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
                 const real ww = cur[u].w * wxj[u];
                 cre[u] = ww * rr;
                 cim[u] = ww * ri;
+            } else if (MODE == MODE_WADJ) {
+                cre[u] = cur[u].w * cur[u].y.re * wxj[u];
+                cim[u] = cur[u].w * cur[u].y.im * wxj[u];
             } else {
                 cpx y = caller_in[cur[u].p < 0 ? ~cur[u].p : cur[u].p];
                 if (cur[u].p < 0) y.im = -y.im;
@@ -658,7 +568,7 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
         if (it + 4 < nit) load(r1, it + 4);
         step(r2, it + 2);
     }
-    if (MODE == MODE_FWD) return;
+    if (MODE == MODE_FWD || MODE == MODE_WFWD) return;
     if (SPREAD) {
         __syncthreads();
         cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride; // column-major window
@@ -1899,6 +1809,76 @@ static hipError_t dispatch(bool prepare, int variant, int mode, const GridArgs &
     case 16: return dispatch_w<16>(prepare, variant, mode, a, n_work, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+// w-plane passes: 16-lane groups, one visibility per group per iteration, any kernel width.
+template <int W> static hipError_t wgrid_w(bool prepare, int mode, const GridArgs &a, int n_work, hipStream_t st) {
+    const size_t wsz = (size_t)a.g.win * a.g.ldw * sizeof(cpx);
+    const int ng = 4 * a.nwave;
+    if (prepare) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_grid<W, MODE_WFWD, 16, 1>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)wsz);
+        if (e != hipSuccess) return e;
+        return hipFuncSetAttribute((const void *)k_grid<W, MODE_WADJ, 16, 1>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)(ng * wsz));
+    }
+    const unsigned gx = (unsigned)n_work < GRID_ROW ? (unsigned)n_work : GRID_ROW;
+    const dim3 grid(gx, (unsigned)((n_work + gx - 1) / gx));
+    if (mode == MODE_WFWD) k_grid<W, MODE_WFWD, 16, 1><<<grid, 64 * a.nwave, wsz, st>>>(a);
+    else k_grid<W, MODE_WADJ, 16, 1><<<grid, 64 * a.nwave, ng * wsz, st>>>(a);
+    return hipGetLastError();
+}
+
+static hipError_t wgrid_dispatch(bool prepare, int mode, const GridArgs &a, int n_work, hipStream_t st) {
+    switch (a.g.W) {
+    case 4: return wgrid_w<4>(prepare, mode, a, n_work, st);
+    case 5: return wgrid_w<5>(prepare, mode, a, n_work, st);
+    case 6: return wgrid_w<6>(prepare, mode, a, n_work, st);
+    case 7: return wgrid_w<7>(prepare, mode, a, n_work, st);
+    case 8: return wgrid_w<8>(prepare, mode, a, n_work, st);
+    case 9: return wgrid_w<9>(prepare, mode, a, n_work, st);
+    case 10: return wgrid_w<10>(prepare, mode, a, n_work, st);
+    case 11: return wgrid_w<11>(prepare, mode, a, n_work, st);
+    case 12: return wgrid_w<12>(prepare, mode, a, n_work, st);
+    case 13: return wgrid_w<13>(prepare, mode, a, n_work, st);
+    case 14: return wgrid_w<14>(prepare, mode, a, n_work, st);
+    case 15: return wgrid_w<15>(prepare, mode, a, n_work, st);
+    case 16: return wgrid_w<16>(prepare, mode, a, n_work, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t prepare_wgrid(const Geom &g, int nwave) {
+    GridArgs a{};
+    a.g = g;
+    a.nwave = nwave;
+    return wgrid_dispatch(true, MODE_WFWD, a, 0, nullptr);
+}
+
+hipError_t launch_wgrid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
+                        const cpx *ext, cpx *slots, const WPlane &wp, int nwave, hipStream_t st) {
+    if (mode != MODE_WFWD && mode != MODE_WADJ) return hipErrorInvalidValue;
+    if (n_work <= 0) return hipSuccess;
+    if (nwave < 1 || nwave > NT / 64 || wp.W < 2 || wp.W > 16) return hipErrorInvalidValue;
+    GridArgs a{};
+    a.g = g;
+    a.work = work;
+    a.crd = crd;
+    a.ext = ext;
+    a.slots = slots;
+    a.nwave = nwave;
+    a.n_work = n_work;
+    a.wz = wp.wz;
+    a.wacc = wp.acc;
+    a.wq = wp.q;
+    a.wplane = wp.plane;
+    a.wW = wp.W;
+#ifdef IVX_REAL_DOUBLE
+    a.wbeta2 = wp.beta;
+#else
+    a.wbeta2 = (real)(wp.beta * 1.4426950408889634);
+#endif
+    return wgrid_dispatch(false, mode, a, n_work, st);
 }
 
 hipError_t prepare_grid(const Geom &g, int nwave, int variant) {

@@ -409,12 +409,21 @@ def config_c3(seed: int = 3001, time_range=(1400, 2000), n_keep=None) -> Problem
                   0.3, n_keep=n_keep)
 
 
-def config_c3_mini(seed: int = 3101) -> Problem:
+def config_c3_mini(seed: int = 3101, w_term: bool = False) -> Problem:
     """Reduced mosaic with the C3 structure (hex footprint, SIN grids, uneven flagged
     counts, SD map) at a size the oracle evaluates in seconds: 2x2 pointings, 128^2 sky,
     64^2 sub-images, 30-60 samples x 630 baselines."""
     return mosaic("c3-mini", seed, 128, 30.0, 2, 2, 30.0, 30.0, 64, (30, 60), 0.3,
-                  sd_n=16, sd_fwhm_arcmin=4.0)
+                  sd_n=16, sd_fwhm_arcmin=4.0, w_term=w_term)
+
+
+def config_w_single(seed: int = 6001, n_sky: int = 64, pixel_arcsec: float = 60.0, n_time: int = 8) -> Problem:
+    """Single pointing with the w coordinate of every sample (the full model of Eq. vis) on a
+    wide field: 64^2 sky at 60 arcsec (a 64 arcmin sub-image, 0.75 deg to the corners, where
+    the phase the coplanar model drops reaches several radians on the long baselines),
+    630 baselines x 8 samples, k^-3 log-normal sky, noise 1% of peak, lambda_r = 1e-2."""
+    return single_pointing("w-single-64", seed, n_sky, pixel_arcsec, n_time, None, "diffuse", 1e-2,
+                           ("frac_peak", 0.01), w_term=True)
 
 
 def config_c5_geometry(seed: int = 5001) -> Problem:
@@ -604,12 +613,12 @@ def config_c4(seed: int = 4001, n_chan: int = 128, n_time: int = 1800, with_fiel
                 1402e6, 2.315e3, with_field=with_field, threads=threads)
 
 
-def config_c4_mini(seed: int = 4101) -> CubeProblem:
+def config_c4_mini(seed: int = 4101, w_term: bool = False) -> CubeProblem:
     """The cube structure at a size the oracle evaluates in seconds: 2x2 pointings on a
     128^2 sky, 64^2 sub-images, 4 channels 25 MHz apart (uv scales 0.97-1.03, so a wrong
     channel scale shows), 40 samples x 630 baselines per pointing, 0-30% flags."""
     return cube("c4-mini", seed, 128, 30.0, 2, 2, 30.0, 30.0, 64, 40, 4, 0.3, 1.4e9, 25e6,
-                sd_n=16, sd_fwhm_arcmin=4.0)
+                sd_n=16, sd_fwhm_arcmin=4.0, w_term=w_term)
 
 
 CONFIGS = {

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(precision):
     assert len(names) >= 30
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.ivx_version() == 2
+    assert lib.ivx_version() == 3
     assert lib.ivx_real_size() == (4 if precision == "f32" else 8)
 
 
@@ -169,3 +169,15 @@ def test_nufft_probe_is_monotone_and_brackets_the_widths():
         assert all(a > b for a, b in zip(e, e[1:])), (nk, nf, e)
     assert ivx.nufft_probe(64, 256, 7) < ivx.nufft_probe(64, 128, 7) < ivx.nufft_probe(96, 128, 7)
     assert ivx.nufft_probe(64, 128, 8) < 1e-6 < 1e-5 < ivx.nufft_probe(64, 128, 6)
+
+
+def test_full_model_needs_data_and_checks_its_arguments():
+    """ivx_plan_set_w before set_data is a state error; the plan stays coplanar."""
+    p = Plan(**_args())
+    with pytest.raises(IvxError) as e:
+        p.set_w(np.zeros(10, np.float32))
+    assert e.value.code == -5 and "set_data" in str(e.value)
+    assert p.w_info()["enabled"] is False
+    lib = load_library()
+    assert lib.ivx_plan_set_w(None, None, 0, 0.0, None) == -1
+    assert lib.ivx_plan_w_info(None, None) == -1
