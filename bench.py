@@ -42,6 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # group) that the plan autotuner selects for each workload; fixed so that the counter
 # measurements committed beside the benchmark describe the kernel configuration it runs.
 SINGLE_BLOCKING = "8,1,256,64,1"
+MOSAIC_W_BLOCKING = "16,1,2048,16,1"     # the full model runs the vector gridder per w plane
+MOSAIC_W_BLOCKING64 = (16, 1, 2048, 16, 1)
 CUBE_BLOCKING = "10,1,512,64,1"
 METRIC = "visibilities/s fwd+adjoint NUFFT; time-to-tol cold vs learned warm start"
 KERNEL_SRC = os.path.join(ROOT, "paper_2609_17636_amd", "csrc", "ivx_kernels.hip")
@@ -107,6 +109,23 @@ def measured_traffic(workload: str, blocking: str):
     if kv.get("blocking") != blocking:
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def wstack_algorithmic_bytes(n_live, winfo, info, n_sub):
+    """Algorithmic HBM bytes of one full-model evaluation.  Gridding (both directions, all
+    planes): each live visibility meets W_w planes; per meeting the degrid pass reads its
+    coordinates (8 B) and plane coordinate (4 B) and updates its accumulator (8 B read, 8 B
+    written), the spread pass reads coordinates, plane coordinate and coefficient (20 B); every
+    plane's extended grid (n_items x eh x ew complex, 8 B) is read once by the degrid pass and
+    written once by the spread.  The evaluation adds, per plane, the row-pass buffer written
+    and read in both directions and the extended grid written by the forward column pass and
+    read by the adjoint one."""
+    planes, ww = winfo["planes"], winfo["w_width"]
+    grid_cells = info["n_items"] * info["ext_rows"] * info["ext_cols"]
+    row_cells = info["n_items"] * n_sub * info["ext_cols"]
+    grid = ww * n_live * (28 + 20) + 2 * planes * grid_cells * 8
+    evaluation = grid + planes * (2 * 2 * row_cells + 2 * grid_cells) * 8
+    return float(grid), float(evaluation)
 
 
 def copy_probe(steps: int):
@@ -285,24 +304,28 @@ def run_single(args):
     print(json.dumps(out), flush=True)
 
 
-def run_mosaic(args):
+def run_mosaic(args, w_term: bool = False):
     """The 36-pointing mosaic: 1024^2 sky at 30", 6 x 6 hex of 1 deg beams, 384^2
     sub-images, 1400-2000 samples x 630 baselines per pointing with 0-30% flags (about 34 M
     live visibilities), 64 x 64 single-dish map, lambda_r = 1e-2, lambda_s = 1.  Data from the
-    FP64 HIP forward of the true sky plus 1% noise per pointing."""
+    FP64 HIP forward of the true sky plus 1% noise per pointing.  w_term: the full model of
+    Eq. vis (w-stacked; the sub-images reach 2.3 deg from their phase centres)."""
     import torch
 
     import synth
     from paper_2609_17636_amd import Plan
 
     dev = torch.device("cuda:0")
-    p = synth.config_c3()
+    p = synth.config_c3(w_term=w_term)
     synth.attach_sd_level(p)
     p.vis = np.zeros(p.n_vis, dtype=np.complex64)
     print(f"# workload {p.name}: N={p.n_sky} vis={p.n_vis} live={int((p.flags == 0).sum())}", file=sys.stderr,
           flush=True)
     plan64 = Plan.from_problem(p, precision="f64")
     plan64.set_problem_data(p)
+    if w_term:
+        plan64.set_blocking(*MOSAIC_W_BLOCKING64)
+        plan64.set_w(p.w)
     mv = plan64.forward(torch.tensor(p.x_true, dtype=torch.float64, device=dev)).cpu().numpy()
     del plan64
     synth.attach_data(p, mv[:, 0] + 1j * mv[:, 1])
@@ -310,8 +333,13 @@ def run_mosaic(args):
     plan.set_problem_data(p)
     if args.blocking:
         plan.set_blocking(*[int(v) for v in args.blocking.split(",")])
+    elif w_term:
+        plan.set_blocking(*[int(v) for v in MOSAIC_W_BLOCKING.split(",")])
     else:
         plan.autotune(3000.0)
+    if w_term:
+        plan.set_w(p.w)
+        print(f"# w planes {plan.w_info()}", file=sys.stderr, flush=True)
     info = plan.info()
     print(f"# plan {info}", file=sys.stderr, flush=True)
     rng = np.random.default_rng(0)
@@ -320,10 +348,16 @@ def run_mosaic(args):
     n_live = info["n_live_vis"]
     alg = grid_algorithmic_bytes(n_live, info["n_fine"], n_items=info["n_items"])
     ev = evaluation_algorithmic_bytes(n_live * 20, info["n_items"], info["n_fine"], p.n_sub, 1, p.n_sky)
+    if w_term:
+        alg, ev = wstack_algorithmic_bytes(n_live, plan.w_info(), info, p.n_sub)
     out = result_line(args, n_live, m, info,
                       "36-pointing mosaic, 1024^2 sky at 30 arcsec, 384^2 sub-images, "
-                      f"{n_live} live visibilities, single-dish 64x64, lambda_r=1e-2, lambda_s=1",
+                      f"{n_live} live visibilities, single-dish 64x64, lambda_r=1e-2, lambda_s=1"
+                      + (", full model of Eq. vis (w-stacked)" if w_term else ""),
                       {"n_sky": p.n_sky}, alg, ev, None)
+    if w_term:
+        out["roofline"]["kernel"] = "k_grid w-plane modes (all planes, both directions)"
+        out["config"]["w_planes"] = plan.w_info()
     print(f"# {m['ms']:.4f} ms/eval, grid {m['grid_ms']:.4f} ms/launch, Q_tot={m['q_tot']:.6e}", file=sys.stderr,
           flush=True)
     print(json.dumps(out), flush=True)
@@ -391,10 +425,11 @@ def main():
                     help="tile,waves,chunk,lanes,vpi of the gridding kernel (default: the autotuner's choice "
                          f"for the workload, recorded: cube {CUBE_BLOCKING}, single {SINGLE_BLOCKING})")
     ap.add_argument("--autotune", action="store_true", help="run the plan autotuner instead of --blocking")
-    ap.add_argument("--workload", default="cube", choices=("cube", "single", "mosaic"),
+    ap.add_argument("--workload", default="cube", choices=("cube", "single", "mosaic", "mosaic-w"),
                     help="cube: the 128-channel spectral cube (default, the largest single-GPU "
                          "configuration); single: the 512^2 single-pointing problem; mosaic: the "
-                         "one-channel 36-pointing mosaic")
+                         "one-channel 36-pointing mosaic; mosaic-w: the same with the full model of "
+                         "Eq. vis")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.steps)
@@ -403,7 +438,8 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library runs on one "
               f"GPU (sharding channels and pointings across GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
-    {"cube": run_cube, "single": run_single, "mosaic": run_mosaic}[args.workload](args)
+    {"cube": run_cube, "single": run_single, "mosaic": run_mosaic,
+     "mosaic-w": lambda a: run_mosaic(a, w_term=True)}[args.workload](args)
 
 
 if __name__ == "__main__":

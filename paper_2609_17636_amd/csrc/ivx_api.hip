@@ -1071,8 +1071,16 @@ ivx_status w_forward_planes(ivx_plan *p, const real *sky, hipStream_t st) {
     const WGeom wg = wgeom(p);
     IVX_HIP(launch_zero(p->d_wacc, std::max<int64_t>(p->m_live, 1) * (int64_t)sizeof(cpx), st));
     for (int pl = 0; pl < p->w_planes; ++pl) {
-        IVX_HIP(launch_wplane_fwd(g, wg, pl, sky, p->d_beams, p->d_interp, p->d_fscale, p->d_dq, p->d_tw, p->d_wR,
-                                  p->d_ext, st));
+        {
+            StageTimer t(p, st, IVX_STAGE_IMAGE_ROWS);
+            IVX_HIP(launch_wplane_rows(g, wg, pl, sky, p->d_beams, p->d_interp, p->d_fscale, p->d_dq, p->d_tw,
+                                       p->d_wR, st));
+        }
+        {
+            StageTimer t(p, st, IVX_STAGE_COL_FWD);
+            IVX_HIP(launch_wplane_cols(g, wg, pl, p->d_wR, p->d_tw, p->d_ext, st));
+        }
+        StageTimer t(p, st, IVX_STAGE_GRID);
         IVX_HIP(launch_wgrid(MODE_WFWD, g, p->d_work, p->n_work, p->d_crd, p->d_ext, p->d_slots, wplane(p, pl, false),
                              p->nwave, st));
     }
@@ -1086,10 +1094,21 @@ ivx_status w_adjoint_planes(ivx_plan *p, hipStream_t st) {
     if (p->w_planes == 0)
         IVX_HIP(launch_zero(p->d_gp, (int64_t)g.C * g.P * g.nk * g.nk * (int64_t)sizeof(real), st));
     for (int pl = 0; pl < p->w_planes; ++pl) {
-        IVX_HIP(launch_wgrid(MODE_WADJ, g, p->d_work, p->n_work, p->d_crd, p->d_ext, p->d_slots, wplane(p, pl, true),
-                             p->nwave, st));
-        IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, st));
-        IVX_HIP(launch_wplane_inv(g, wg, pl, p->d_ext, p->d_beams, p->d_fscale, p->d_dq, p->d_tw, p->d_wR, p->d_gp, st));
+        {
+            StageTimer t(p, st, IVX_STAGE_GRID);
+            IVX_HIP(launch_wgrid(MODE_WADJ, g, p->d_work, p->n_work, p->d_crd, p->d_ext, p->d_slots,
+                                 wplane(p, pl, true), p->nwave, st));
+        }
+        {
+            StageTimer t(p, st, IVX_STAGE_FOLD);
+            IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, st));
+        }
+        {
+            StageTimer t(p, st, IVX_STAGE_COL_INV);
+            IVX_HIP(launch_wplane_cols_inv(g, wg, pl, p->d_ext, p->d_tw, p->d_wR, st));
+        }
+        StageTimer t(p, st, IVX_STAGE_ROW_INV);
+        IVX_HIP(launch_wplane_rows_inv(g, wg, pl, p->d_wR, p->d_beams, p->d_fscale, p->d_dq, p->d_tw, p->d_gp, st));
     }
     return IVX_OK;
 }
@@ -1097,11 +1116,16 @@ ivx_status w_adjoint_planes(ivx_plan *p, hipStream_t st) {
 // eval_value / eval_gradient of the full model.
 ivx_status eval_value_w(ivx_plan *p, const real *sky, double *terms_dev, bool keep_sd_adjoint, hipStream_t st) {
     const Geom &g = p->g;
+    if (p->timing_mask) p->timed_evals++;
     ivx_status s = w_forward_planes(p, sky, st);
     if (s != IVX_OK) return s;
-    IVX_HIP(launch_wresid(p->d_work, p->n_work, wgeom(p), p->d_wz, p->d_vis, p->d_wgt, p->d_wacc, p->d_jpart, st));
+    {
+        StageTimer t(p, st, IVX_STAGE_GRID);
+        IVX_HIP(launch_wresid(p->d_work, p->n_work, wgeom(p), p->d_wz, p->d_vis, p->d_wgt, p->d_wacc, p->d_jpart, st));
+    }
     const bool sd = sd_active(p);
     if (sd) {
+        StageTimer t(p, st, IVX_STAGE_SD);
         IVX_HIP(launch_sd_rows(g, sky, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_U, st));
         IVX_HIP(launch_sd_cols(g, p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, p->d_sdmap,
                                (real)(1.0 / (p->d.sd_sigma * p->d.sd_sigma)), p->d_E, p->d_kpart, st));
@@ -1121,6 +1145,7 @@ ivx_status eval_gradient_w(ivx_plan *p, const real *sky, real *grad, real scale,
     ivx_status s = w_adjoint_planes(p, st);
     if (s != IVX_OK) return s;
     const bool sd = sd_active(p);
+    StageTimer t(p, st, IVX_STAGE_SKY);
     IVX_HIP(launch_sky(g, sky, p->d_gp, p->d_cptr, p->d_cent, (real)p->d.lambda_r, sd ? (real)p->d.lambda_s : real(0),
                        p->d_U, p->d_gB, p->sd_rb, p->d.sd_n, p->d.sd_stride, p->d.sd_offset, grad, p->d_rpart,
                        SKY_FULL, scale, st, spec_weight(p), p->d_npart));

@@ -223,11 +223,15 @@ hipError_t launch_wzeta(int64_t n, const int32_t *perm, const real *wsrc, double
                         WZ *out, unsigned int *bad, hipStream_t st);
 hipError_t launch_wsort(const WorkItem *work, int n_work, VisCoord *crd, cpx *vis, real *wgt, int32_t *perm, WZ *wz,
                         hipStream_t st);
-hipError_t launch_wplane_fwd(const Geom &g, const WGeom &wg, int plane, const real *sky, const real *beams,
-                             const real *interp, const real *fscale, const real *dq, const cpx *tw, cpx *R, cpx *ext,
-                             hipStream_t st);
-hipError_t launch_wplane_inv(const Geom &g, const WGeom &wg, int plane, const cpx *ext, const real *beams,
-                             const real *fscale, const real *dq, const cpx *tw, cpx *R, real *gp, hipStream_t st);
+hipError_t launch_wplane_rows(const Geom &g, const WGeom &wg, int plane, const real *sky, const real *beams,
+                              const real *interp, const real *fscale, const real *dq, const cpx *tw, cpx *R,
+                              hipStream_t st);
+hipError_t launch_wplane_cols(const Geom &g, const WGeom &wg, int plane, const cpx *R, const cpx *tw, cpx *ext,
+                              hipStream_t st);
+hipError_t launch_wplane_cols_inv(const Geom &g, const WGeom &wg, int plane, const cpx *ext, const cpx *tw, cpx *R,
+                                  hipStream_t st);
+hipError_t launch_wplane_rows_inv(const Geom &g, const WGeom &wg, int plane, const cpx *R, const real *beams,
+                                  const real *fscale, const real *dq, const cpx *tw, real *gp, hipStream_t st);
 hipError_t launch_wresid(const WorkItem *work, int n_work, const WGeom &wg, const WZ *wz, const cpx *vis,
                          const real *wgt, cpx *acc, double *jpart, hipStream_t st);
 hipError_t launch_wout(const WorkItem *work, int n_work, const WGeom &wg, const WZ *wz, const int32_t *perm,

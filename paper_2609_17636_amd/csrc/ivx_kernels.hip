@@ -337,6 +337,24 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     // e = cc * win + r without an integer division: (e + 1/2) / win is never within float
     // rounding of an integer for e < 2^16
     const float inv_win = 1.0f / (float)win;
+    // a w plane only takes the records whose w kernel reaches it, zeta in [p - W_w / 2,
+    // p + W_w / 2): a contiguous range of the work item's list (sorted by zeta).  Most work
+    // items meet a plane with no such record: the degrid pass then has nothing to do and the
+    // spread pass writes a zero window (the values are block-uniform, so the whole block
+    // leaves together).
+    int base = 0, cnt = wi.count;
+    if constexpr (WPL) {
+        const WZ *z = a.wz + wi.begin;
+        base = wz_lower(z, wi.count, 2 * a.wplane - a.wW);
+        cnt = wz_lower(z, wi.count, 2 * a.wplane + a.wW) - base;
+        if (cnt == 0) {
+            if (MODE == MODE_WADJ) {
+                cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride;
+                for (int e = tid; e < win * win; e += blockDim.x) Sl[e] = cpx{0, 0};
+            }
+            return;
+        }
+    }
     if (!NOGRID) {
         const cpx *F = a.ext + (int64_t)wi.item * g.ext_stride + (int64_t)(wi.tx * g.T) * g.eh + wi.ty * g.T;
         for (int e = tid; e < win * win; e += blockDim.x) {
@@ -366,15 +384,8 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     const real zoff = real(0.5) * real(W) - real(1);
     real jacc = real(0);
 
-    // this group's segment of the tile's list, walked VPI visibilities at a time; a w plane
-    // only takes the records whose w kernel reaches it, zeta in [p - W_w / 2, p + W_w / 2),
-    // a contiguous range of the work item's list (sorted by zeta)
-    int base = 0, cnt = wi.count;
-    if constexpr (WPL) {
-        const WZ *z = a.wz + wi.begin;
-        base = wz_lower(z, wi.count, 2 * a.wplane - a.wW);
-        cnt = wz_lower(z, wi.count, 2 * a.wplane + a.wW) - base;
-    }
+    // this group's segment of the tile's list (of the plane's range), walked VPI visibilities
+    // at a time
     const int seg = (cnt + ngroups - 1) / ngroups;
     const int v0 = base + gid * seg;
     const int v1 = min(base + cnt, v0 + seg);

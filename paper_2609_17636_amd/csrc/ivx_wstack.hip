@@ -396,23 +396,31 @@ dim3 work_grid(int n_work) {
     return dim3(gx, (unsigned)((n_work + gx - 1) / gx));
 }
 
-template <int LOGN> hipError_t wplane_fwd_n(const Geom &g, const WGeom &wg, int plane, const real *sky,
-                                            const real *beams, const real *interp, const real *fscale,
-                                            const real *dq, const cpx *tw, cpx *R, cpx *ext, hipStream_t st) {
-    const int items = g.C * g.P;
-    k_wimage_rows<LOGN><<<dim3(g.nk, items), NT, 0, st>>>(g, wg, plane, sky, beams, interp, fscale, dq, tw, R);
-    constexpr int CB = col_batch<LOGN>();
-    k_wcol_fwd<LOGN, CB><<<dim3((g.ew + CB - 1) / CB, items), NT, 0, st>>>(g, wg, plane, R, tw, ext);
+template <int LOGN> hipError_t wrows_n(const Geom &g, const WGeom &wg, int plane, const real *sky, const real *beams,
+                                       const real *interp, const real *fscale, const real *dq, const cpx *tw, cpx *R,
+                                       hipStream_t st) {
+    k_wimage_rows<LOGN><<<dim3(g.nk, g.C * g.P), NT, 0, st>>>(g, wg, plane, sky, beams, interp, fscale, dq, tw, R);
     return hipGetLastError();
 }
 
-template <int LOGN> hipError_t wplane_inv_n(const Geom &g, const WGeom &wg, int plane, const cpx *ext,
-                                            const real *beams, const real *fscale, const real *dq, const cpx *tw,
-                                            cpx *R, real *gp, hipStream_t st) {
-    const int items = g.C * g.P;
+template <int LOGN> hipError_t wcols_n(const Geom &g, const WGeom &wg, int plane, const cpx *R, const cpx *tw,
+                                       cpx *ext, hipStream_t st) {
     constexpr int CB = col_batch<LOGN>();
-    k_wcol_inv<LOGN, CB><<<dim3((wg.ncol + CB - 1) / CB, items), NT, 0, st>>>(g, wg, plane, ext, tw, R);
-    k_wrow_inv<LOGN><<<dim3(g.nk, items), NT, 0, st>>>(g, wg, plane, R, beams, fscale, dq, tw, gp);
+    k_wcol_fwd<LOGN, CB><<<dim3((g.ew + CB - 1) / CB, g.C * g.P), NT, 0, st>>>(g, wg, plane, R, tw, ext);
+    return hipGetLastError();
+}
+
+template <int LOGN> hipError_t wcols_inv_n(const Geom &g, const WGeom &wg, int plane, const cpx *ext, const cpx *tw,
+                                           cpx *R, hipStream_t st) {
+    constexpr int CB = col_batch<LOGN>();
+    k_wcol_inv<LOGN, CB><<<dim3((wg.ncol + CB - 1) / CB, g.C * g.P), NT, 0, st>>>(g, wg, plane, ext, tw, R);
+    return hipGetLastError();
+}
+
+template <int LOGN> hipError_t wrows_inv_n(const Geom &g, const WGeom &wg, int plane, const cpx *R, const real *beams,
+                                           const real *fscale, const real *dq, const cpx *tw, real *gp,
+                                           hipStream_t st) {
+    k_wrow_inv<LOGN><<<dim3(g.nk, g.C * g.P), NT, 0, st>>>(g, wg, plane, R, beams, fscale, dq, tw, gp);
     return hipGetLastError();
 }
 
@@ -451,19 +459,33 @@ hipError_t launch_wsort(const WorkItem *work, int n_work, VisCoord *crd, cpx *vi
     default: return hipErrorInvalidValue;                                                                      \
     }
 
-hipError_t launch_wplane_fwd(const Geom &g, const WGeom &wg, int plane, const real *sky, const real *beams,
-                             const real *interp, const real *fscale, const real *dq, const cpx *tw, cpx *R, cpx *ext,
-                             hipStream_t st) {
-#define IVX_WF(L) wplane_fwd_n<L>(g, wg, plane, sky, beams, interp, fscale, dq, tw, R, ext, st)
-    IVX_LOGN_SWITCH(IVX_WF)
-#undef IVX_WF
+hipError_t launch_wplane_rows(const Geom &g, const WGeom &wg, int plane, const real *sky, const real *beams,
+                              const real *interp, const real *fscale, const real *dq, const cpx *tw, cpx *R,
+                              hipStream_t st) {
+#define IVX_W(L) wrows_n<L>(g, wg, plane, sky, beams, interp, fscale, dq, tw, R, st)
+    IVX_LOGN_SWITCH(IVX_W)
+#undef IVX_W
 }
 
-hipError_t launch_wplane_inv(const Geom &g, const WGeom &wg, int plane, const cpx *ext, const real *beams,
-                             const real *fscale, const real *dq, const cpx *tw, cpx *R, real *gp, hipStream_t st) {
-#define IVX_WI(L) wplane_inv_n<L>(g, wg, plane, ext, beams, fscale, dq, tw, R, gp, st)
-    IVX_LOGN_SWITCH(IVX_WI)
-#undef IVX_WI
+hipError_t launch_wplane_cols(const Geom &g, const WGeom &wg, int plane, const cpx *R, const cpx *tw, cpx *ext,
+                              hipStream_t st) {
+#define IVX_W(L) wcols_n<L>(g, wg, plane, R, tw, ext, st)
+    IVX_LOGN_SWITCH(IVX_W)
+#undef IVX_W
+}
+
+hipError_t launch_wplane_cols_inv(const Geom &g, const WGeom &wg, int plane, const cpx *ext, const cpx *tw, cpx *R,
+                                  hipStream_t st) {
+#define IVX_W(L) wcols_inv_n<L>(g, wg, plane, ext, tw, R, st)
+    IVX_LOGN_SWITCH(IVX_W)
+#undef IVX_W
+}
+
+hipError_t launch_wplane_rows_inv(const Geom &g, const WGeom &wg, int plane, const cpx *R, const real *beams,
+                                  const real *fscale, const real *dq, const cpx *tw, real *gp, hipStream_t st) {
+#define IVX_W(L) wrows_inv_n<L>(g, wg, plane, R, beams, fscale, dq, tw, gp, st)
+    IVX_LOGN_SWITCH(IVX_W)
+#undef IVX_W
 }
 #undef IVX_LOGN_SWITCH
 

@@ -18,7 +18,7 @@ import sqlite3
 
 
 def _short(name: str) -> str:
-    return re.sub(r"\(.*", "", name)
+    return re.sub(r"\(.*", "", name.replace("(anonymous namespace)::", ""))
 
 
 def kernel_rows(db: str):

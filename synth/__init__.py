@@ -401,12 +401,12 @@ def mosaic(name: str, seed: int, n_sky: int, pixel_arcsec: float, n_rows: int, n
     )
 
 
-def config_c3(seed: int = 3001, time_range=(1400, 2000), n_keep=None) -> Problem:
+def config_c3(seed: int = 3001, time_range=(1400, 2000), n_keep=None, w_term: bool = False) -> Problem:
     """36 pointings (6x6 hex, 1 deg pitch = 120 px at 30 arcsec) over a 1024^2 sky, 1 deg
     PB, 384^2 sub-images, T_k ~ U{1400..2000} samples x 630 baselines, 0-30% flags,
     64x64 single-dish map under a 16 arcmin beam, lambda_r = 1e-2, lambda_s = 1."""
     return mosaic("c3-mosaic-36x1024", seed, 1024, 30.0, 6, 6, 120.0, 120.0, 384, time_range,
-                  0.3, n_keep=n_keep)
+                  0.3, n_keep=n_keep, w_term=w_term)
 
 
 def config_c3_mini(seed: int = 3101, w_term: bool = False) -> Problem:
