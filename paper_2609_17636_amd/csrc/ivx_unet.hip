@@ -4,11 +4,13 @@
 //
 // Implicit GEMM of a 3x3 convolution, NHWC: rows = output pixels p, columns = output
 // channels o, reduction index k = (dy * 3 + dx) * Cin + c.  A[p][k] is the input pixel
-// shifted by (dy - 1, dx - 1) (zero outside), B[k][o] = W[o][dy][dx][c].  One wave owns
-// 16 pixels x 16*NTW channels and issues v_mfma_f32_16x16x16_bf16 per 16-wide k step:
-//   A operand : lane l holds A[l % 16][4 (l / 16) + v], v = 0..3 (4 consecutive channels)
-//   B operand : lane l holds B[4 (l / 16) + v][l % 16]  (4 consecutive weights of one o)
-//   result    : lane l holds D[4 (l / 16) + v][l % 16]
+// shifted by (dy - 1, dx - 1) (zero outside), B[k][o] = W[o][dy][dx][c].  The products run on
+// gfx950's v_mfma_f32_16x16x32_bf16, one per 32-wide k step of a 16 x 16 output tile:
+//   A operand : lane l holds A[l % 16][8 (l / 16) + v], v = 0..7 (8 consecutive k)
+//   B operand : lane l holds B[8 (l / 16) + v][l % 16]  (the same 8 k of one column)
+//   result    : lane l holds D[4 (l / 16) + v][l % 16], v = 0..3
+// (A and B give each lane the same k indices, so the product does not depend on the order in
+// which the instruction walks them.)
 // The transposed correlation (gradient of the input) is the same kernel on flipped
 // weights, and the weight gradient is a second implicit GEMM (rows o, columns k, reduction
 // over pixels) split over pixel ranges with a fixed-order reduction of the partials.
@@ -33,8 +35,18 @@ namespace {
 
 constexpr int NT = 256;
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// 8 bf16 values (as raw 16-bit patterns, element 0 in the low half of word 0) as an operand
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
+__device__ __forceinline__ uint4 pack8(const uint16_t *e) {
+    return uint4{e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16), e[4] | ((uint32_t)e[5] << 16),
+                 e[6] | ((uint32_t)e[7] << 16)};
+}
+__device__ __forceinline__ f32x4 mma(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -66,32 +78,35 @@ __global__ __launch_bounds__(NT) void k_conv3x3(const float *__restrict__ x, int
     f32x4 acc[NTW];
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        const int k = k0 + 4 * kq;
-        bf16x4 a = {0, 0, 0, 0};
-        if (pv && k < K) {
-            const int tap = k / cin, c = k - (k / cin) * cin;
-            const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
-            if (yy >= 0 && yy < h && xx >= 0 && xx < w) {
-                const float4 v = *reinterpret_cast<const float4 *>(x + (((int64_t)pn * h + yy) * w + xx) * cin + c);
-                a[0] = (short)f2bf(v.x);
-                a[1] = (short)f2bf(v.y);
-                a[2] = (short)f2bf(v.z);
-                a[3] = (short)f2bf(v.w);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        // the lane's 8 k: two runs of 4 channels (cin % 4 == 0: each run stays in one tap)
+        uint16_t ae[8];
+#pragma unroll
+        for (int hlf = 0; hlf < 2; ++hlf) {
+            const int k = k0 + 8 * kq + 4 * hlf;
+            float4 v = float4{0.f, 0.f, 0.f, 0.f};
+            if (pv && k < K) {
+                const int tap = k / cin, c = k - (k / cin) * cin;
+                const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+                if (yy >= 0 && yy < h && xx >= 0 && xx < w)
+                    v = *reinterpret_cast<const float4 *>(x + (((int64_t)pn * h + yy) * w + xx) * cin + c);
             }
+            ae[4 * hlf + 0] = f2bf(v.x);
+            ae[4 * hlf + 1] = f2bf(v.y);
+            ae[4 * hlf + 2] = f2bf(v.z);
+            ae[4 * hlf + 3] = f2bf(v.w);
         }
+        const bf16x8 a = as_bf16x8(pack8(ae));
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
             const int co = cobase + t * 16 + row;
-            bf16x4 b = {0, 0, 0, 0};
-            if (co < cout && k < K) {
-                const uint2 u = *reinterpret_cast<const uint2 *>(wt + (int64_t)co * K + k);
-                b[0] = (short)(u.x & 0xFFFFu);
-                b[1] = (short)(u.x >> 16);
-                b[2] = (short)(u.y & 0xFFFFu);
-                b[3] = (short)(u.y >> 16);
+            uint2 u[2] = {uint2{0u, 0u}, uint2{0u, 0u}};
+#pragma unroll
+            for (int hlf = 0; hlf < 2; ++hlf) {
+                const int k = k0 + 8 * kq + 4 * hlf;
+                if (co < cout && k < K) u[hlf] = *reinterpret_cast<const uint2 *>(wt + (int64_t)co * K + k);
             }
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            acc[t] = mma(a, as_bf16x8(uint4{u[0].x, u[0].y, u[1].x, u[1].y}), acc[t]);
         }
     }
 #pragma unroll
@@ -116,8 +131,8 @@ __global__ __launch_bounds__(NT) void k_conv3x3(const float *__restrict__ x, int
 // LDS-tiled implicit GEMM for the 3x3 convolution: block tile 64 pixels x BN channels
 // (BN = 32 NJ), k chunks of 32 staged in LDS as bf16 (A: [pixel][k], B: [channel][k], rows
 // padded to 40 elements), 4 waves in a 2 x 2 arrangement, each wave 2 x NJ tiles of
-// v_mfma_f32_16x16x16_bf16.  The next chunk's global loads are issued before the current
-// chunk's matrix products.
+// v_mfma_f32_16x16x32_bf16 (one per chunk).  The next chunk's global loads are issued before
+// the current chunk's matrix products.
 constexpr int TBM = 64, TBK = 32, TLD = 40;
 template <int NJ>
 __global__ __launch_bounds__(NT) void k_conv3x3_tiled(const float *__restrict__ x, int n, int h, int w, int cin,
@@ -214,21 +229,18 @@ __global__ __launch_bounds__(NT) void k_conv3x3_tiled(const float *__restrict__ 
         sstore();
         __syncthreads();
         if (kc + 1 < nch) gload((kc + 1) * TBK);
+        static_assert(TBK == 32, "one 16x16x32 product per chunk");
+        bf16x8 af[2], bfr[NJ];
 #pragma unroll
-        for (int ks = 0; ks < TBK / 16; ++ks) {
-            bf16x4 af[2], bfr[NJ];
+        for (int i = 0; i < 2; ++i)
+            af[i] = as_bf16x8(*reinterpret_cast<const uint4 *>(&As[(wr * 32 + i * 16 + row) * TLD + 8 * kq]));
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                af[i] = *reinterpret_cast<const bf16x4 *>(&As[(wr * 32 + i * 16 + row) * TLD + ks * 16 + 4 * kq]);
+        for (int j = 0; j < NJ; ++j)
+            bfr[j] = as_bf16x8(*reinterpret_cast<const uint4 *>(&Bs[(wc * 16 * NJ + j * 16 + row) * TLD + 8 * kq]));
 #pragma unroll
-            for (int j = 0; j < NJ; ++j)
-                bfr[j] = *reinterpret_cast<const bf16x4 *>(&Bs[(wc * 16 * NJ + j * 16 + row) * TLD + ks * 16 + 4 * kq]);
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < NJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
-        }
+            for (int j = 0; j < NJ; ++j) acc[i][j] = mma(af[i], bfr[j], acc[i][j]);
     }
     // ---- epilogue: D row (pixel) 4 kq + v, column (channel) = row index of the lane
 #pragma unroll
@@ -279,16 +291,16 @@ __global__ __launch_bounds__(NT) void k_conv3x3_gw(const float *__restrict__ x, 
     f32x4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int64_t pb = p0; pb < p1; pb += 16) {
-        bf16x4 a = {0, 0, 0, 0};
-        bf16x4 b[4];
+    for (int64_t pb = p0; pb < p1; pb += 32) {
+        uint16_t a[8], b[4][8];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) b[t] = bf16x4{0, 0, 0, 0};
+        for (int v = 0; v < 8; ++v) {
+            a[v] = 0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t p = pb + 4 * q + v;
+            for (int t = 0; t < 4; ++t) b[t][v] = 0;
+            const int64_t p = pb + 8 * q + v;
             if (p >= p1) continue;
-            if (co < cout) a[v] = (short)f2bf(dy[p * cout + co]);
+            if (co < cout) a[v] = f2bf(dy[p * cout + co]);
             const int pn = (int)(p / ((int64_t)h * w));
             const int r = (int)(p - (int64_t)pn * h * w);
             const int py = r / w, px = r - (r / w) * w;
@@ -296,11 +308,12 @@ __global__ __launch_bounds__(NT) void k_conv3x3_gw(const float *__restrict__ x, 
             for (int t = 0; t < 4; ++t) {
                 const int yy = py + tapy[t], xx = px + tapx[t];
                 if (kv[t] && yy >= 0 && yy < h && xx >= 0 && xx < w)
-                    b[t][v] = (short)f2bf(x[(((int64_t)pn * h + yy) * w + xx) * cin + tc[t]]);
+                    b[t][v] = f2bf(x[(((int64_t)pn * h + yy) * w + xx) * cin + tc[t]]);
             }
         }
+        const bf16x8 av = as_bf16x8(pack8(a));
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[t], 0, 0, 0);
+        for (int t = 0; t < 4; ++t) acc[t] = mma(av, as_bf16x8(pack8(b[t])), acc[t]);
     }
     // D rows = output channels (4 q + v of this wave's 16), columns = k
 #pragma unroll
@@ -318,8 +331,8 @@ __global__ __launch_bounds__(NT) void k_conv3x3_gw(const float *__restrict__ x, 
 // Weight and bias gradient partials, LDS-tiled: block (k tile of 64, o tile of 64, pixel
 // range z of `ps` pixels).  The pixel range is walked in chunks of 32: dy (A, [o][pixel]) and
 // the im2col view of x (B, [k][pixel]) are staged in LDS as bf16, transposed so that each
-// lane's four reduction elements are contiguous; 4 waves in a 2 x 2 arrangement each own
-// 32 x 32 outputs (2 x 2 tiles of v_mfma_f32_16x16x16_bf16).  Blocks of the first k tile also
+// lane's eight reduction elements are contiguous; 4 waves in a 2 x 2 arrangement each own
+// 32 x 32 outputs (2 x 2 tiles of v_mfma_f32_16x16x32_bf16, one product per chunk).  Blocks of the first k tile also
 // sum dy in FP32 for the bias.  part[z] = [dw partial (cout x K) | db partial (cout)].
 // Requires cin % 4 == 0 and cout % 4 == 0.
 constexpr int GW_PC = 32, GW_LD = 40, GW_TARGET_BLOCKS = 2048, GW_MIN_PIX = 256;
@@ -386,20 +399,17 @@ __global__ __launch_bounds__(NT) void k_conv3x3_gw_tiled(const float *__restrict
         sstore();
         __syncthreads();
         if (pc + GW_PC < p1) gload(pc + GW_PC);
+        static_assert(GW_PC == 32, "one 16x16x32 product per chunk");
+        bf16x8 af[2], bfr[2];
 #pragma unroll
-        for (int ks = 0; ks < GW_PC / 16; ++ks) {
-            bf16x4 af[2], bfr[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                af[i] = *reinterpret_cast<const bf16x4 *>(&As[(wr * 32 + i * 16 + row) * GW_LD + ks * 16 + 4 * kq]);
-                bfr[i] = *reinterpret_cast<const bf16x4 *>(&Bs[(wc * 32 + i * 16 + row) * GW_LD + ks * 16 + 4 * kq]);
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < 2; ++i) {
+            af[i] = as_bf16x8(*reinterpret_cast<const uint4 *>(&As[(wr * 32 + i * 16 + row) * GW_LD + 8 * kq]));
+            bfr[i] = as_bf16x8(*reinterpret_cast<const uint4 *>(&Bs[(wc * 32 + i * 16 + row) * GW_LD + 8 * kq]));
         }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = mma(af[i], bfr[j], acc[i][j]);
     }
     float *pz = part + (int64_t)blockIdx.z * len;
     // D row (o) 4 kq + v, column (k) = the lane's row index
@@ -585,41 +595,74 @@ __global__ __launch_bounds__(NT) void k_pad_input(const float *__restrict__ x, i
 }
 
 // 1x1 head: y[p] = b + sum_c w[c] x[p][c]
+// Head (1x1 convolution to one channel) on c-channel pixels, c % 4 == 0: G = c / 4 threads per
+// pixel hold 4 channels each (float4 loads, contiguous across the threads of a block), NT / G
+// pixels per block; the per-pixel and per-channel sums run over LDS in a fixed order.
 __global__ __launch_bounds__(NT) void k_head(const float *__restrict__ x, int c, int64_t P, const float *__restrict__ wt,
                                              const float *__restrict__ b, float *__restrict__ y) {
-    const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (p >= P) return;
-    float s = b[0];
-    for (int k = 0; k < c; ++k) s += wt[k] * x[p * c + k];
-    y[p] = s;
+    __shared__ float sh[NT];
+    const int G = c >> 2, ppb = NT / G;
+    const int t = threadIdx.x, g = t % G, lp = t / G;
+    const int64_t p = (int64_t)blockIdx.x * ppb + lp;
+    float s = 0.f;
+    if (lp < ppb && p < P) {
+        const float4 v = *reinterpret_cast<const float4 *>(x + p * c + 4 * g); // c % 4 == 0: aligned
+        s = wt[4 * g] * v.x + wt[4 * g + 1] * v.y + wt[4 * g + 2] * v.z + wt[4 * g + 3] * v.w;
+    }
+    sh[t] = s;
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * ppb + t;
+    if (t < ppb && q < P) {
+        float acc = b[0];
+        for (int i = 0; i < G; ++i) acc += sh[t * G + i];
+        y[q] = acc;
+    }
 }
 
-// head backward: dx[p][c] = w[c] dy[p] [x > 0]; per-block partials of dw[c] and db
+// head backward: dx[p][k] = w[k] dy[p] [x > 0]; per-block partials of dw[k] = sum_p dy x[p][k]
+// and db = sum_p dy (blocks walk the pixels grid-stride; part[block][0..c]).
+constexpr int HEAD_BLOCKS = 512;
 __global__ __launch_bounds__(NT) void k_head_grad(const float *__restrict__ x, int c, int64_t P,
                                                   const float *__restrict__ wt, const float *__restrict__ dy,
                                                   float *__restrict__ dx, float *__restrict__ part) {
-    __shared__ float sh[NT];
-    const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
-    const float g = p < P ? dy[p] : 0.f;
-    for (int k = 0; k <= c; ++k) {
-        float v = 0.f;
-        if (p < P) {
-            if (k < c) {
-                const float xv = x[p * c + k];
-                dx[p * c + k] = xv > 0.f ? wt[k] * g : 0.f;
-                v = g * xv;
-            } else {
-                v = g;
+    __shared__ float4 sw[NT];
+    __shared__ float sb[NT];
+    const int G = c >> 2, ppb = NT / G;
+    const int t = threadIdx.x, g = t % G, lp = t / G;
+    const bool act = lp < ppb;
+    const float4 w4 = act ? float4{wt[4 * g], wt[4 * g + 1], wt[4 * g + 2], wt[4 * g + 3]} : float4{0.f, 0.f, 0.f, 0.f};
+    float4 a4 = float4{0.f, 0.f, 0.f, 0.f};
+    float ab = 0.f;
+    if (act) {
+        for (int64_t p = (int64_t)blockIdx.x * ppb + lp; p < P; p += (int64_t)gridDim.x * ppb) {
+            const float gy = dy[p];
+            const float4 v = *reinterpret_cast<const float4 *>(x + p * c + 4 * g);
+            *reinterpret_cast<float4 *>(dx + p * c + 4 * g) =
+                float4{v.x > 0.f ? w4.x * gy : 0.f, v.y > 0.f ? w4.y * gy : 0.f, v.z > 0.f ? w4.z * gy : 0.f,
+                       v.w > 0.f ? w4.w * gy : 0.f};
+            a4.x += gy * v.x;
+            a4.y += gy * v.y;
+            a4.z += gy * v.z;
+            a4.w += gy * v.w;
+            ab += gy;
+        }
+    }
+    sw[t] = a4;
+    sb[t] = ab;
+    __syncthreads();
+    float *pz = part + (int64_t)blockIdx.x * (c + 1);
+    for (int k = t; k <= c; k += NT) {
+        float s = 0.f;
+        if (k < c) {
+            const int gg = k >> 2, e = k & 3;
+            for (int i = 0; i < ppb; ++i) {
+                const float4 v = sw[i * G + gg];
+                s += e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
             }
+        } else {
+            for (int i = 0; i < ppb; ++i) s += sb[i * G];
         }
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int m = NT / 2; m >= 1; m >>= 1) {
-            if (threadIdx.x < m) sh[threadIdx.x] += sh[threadIdx.x + m];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (c + 1) + k] = sh[0];
-        __syncthreads();
+        pz[k] = s;
     }
 }
 
@@ -658,14 +701,20 @@ __global__ __launch_bounds__(NT) void k_sum_double(const double *__restrict__ pa
 }
 
 // head gradient partials -> grads (fixed order)
-__global__ void k_head_reduce(const float *__restrict__ part, int nblk, int c, float *__restrict__ dw,
-                              float *__restrict__ db) {
-    const int k = threadIdx.x;
-    if (k > c) return;
-    float s = 0.f;
-    for (int i = 0; i < nblk; ++i) s += part[(int64_t)i * (c + 1) + k];
-    if (k < c) dw[k] = s;
-    else db[0] = s;
+// One wave per output k: lane i sums partials i, i + 64, ... in order, then a fixed xor tree.
+__global__ __launch_bounds__(NT) void k_head_reduce(const float *__restrict__ part, int nblk, int c,
+                                                    float *__restrict__ dw, float *__restrict__ db) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = wave; k <= c; k += NT / 64) {
+        float s = 0.f;
+        for (int i = lane; i < nblk; i += 64) s += part[(int64_t)i * (c + 1) + k];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+        if (lane == 0) {
+            if (k < c) dw[k] = s;
+            else db[0] = s;
+        }
+    }
 }
 
 // Adam (Kingma & Ba 2015) with bias correction folded into lr_t and eps_t
@@ -870,7 +919,9 @@ hipError_t forward(ivx_unet *u, const float *x, int B, hipStream_t st) {
         hcur = u->db[l];
     }
     const float *top = u->L > 1 ? u->db[0] : u->eb[0];
-    k_head<<<nblocks(P0), NT, 0, st>>>(top, u->ch[0], P0, u->params + u->head_w, u->params + u->head_b, u->out);
+    const int hppb = NT / (u->ch[0] / 4);
+    k_head<<<(unsigned)((P0 + hppb - 1) / hppb), NT, 0, st>>>(top, u->ch[0], P0, u->params + u->head_w,
+                                                            u->params + u->head_b, u->out);
     return hipGetLastError();
 }
 
@@ -891,9 +942,10 @@ hipError_t backward(ivx_unet *u, int B, hipStream_t st) {
     const int64_t P0 = (int64_t)B * u->H * u->W;
     const float *top = u->L > 1 ? u->db[0] : u->eb[0];
     float *gtop = u->L > 1 ? u->g_db[0] : u->g_eb[0];
-    const unsigned hb = nblocks(P0);
+    const int hppb = NT / (u->ch[0] / 4);
+    const unsigned hb = (unsigned)std::min<int64_t>(HEAD_BLOCKS, (P0 + hppb - 1) / hppb);
     k_head_grad<<<hb, NT, 0, st>>>(top, u->ch[0], P0, u->params + u->head_w, u->gout, gtop, u->head_part);
-    k_head_reduce<<<1, 64, 0, st>>>(u->head_part, (int)hb, u->ch[0], u->grads + u->head_w, u->grads + u->head_b);
+    k_head_reduce<<<1, NT, 0, st>>>(u->head_part, (int)hb, u->ch[0], u->grads + u->head_w, u->grads + u->head_b);
     // decoder, top level first
     for (int l = 0; l <= u->L - 2; ++l) {
         const int h = lvl_h(u, l), w = lvl_w(u, l);
@@ -1022,7 +1074,7 @@ ivx_status ivx_unet_create(int32_t levels, int32_t base, int32_t max_batch, int3
     }
     for (const ConvLayer &c : u->conv) maxpart = std::max<int64_t>(maxpart, gw_part_len((int)B, c.h, c.w, c.cin, c.cout));
     if ((s = ualloc(u, &u->part, maxpart)) || (s = ualloc(u, &u->out, P0)) || (s = ualloc(u, &u->gout, P0)) ||
-        (s = ualloc(u, &u->head_part, (int64_t)nblocks(P0) * (u->ch[0] + 1))) ||
+        (s = ualloc(u, &u->head_part, (int64_t)HEAD_BLOCKS * (u->ch[0] + 1))) ||
         (s = ualloc(u, &u->loss_part, (int64_t)nblocks(P0))) || (s = ualloc(u, &u->loss, 1)))
         return fail(s);
     u->part_len = maxpart;

@@ -323,6 +323,31 @@ def summarise(rows):
 
 
 # ----------------------------------------------------------------------------- command line
+def train_throughput(batch: int = 16, steps: int = 50, warmup: int = 5) -> dict:
+    """Training steps of the warm-start network (forward, backward, Adam) on a random batch of
+    256^2 fields: milliseconds per step and the convolutions' rate against the dense bf16 matrix
+    peak of MI355X (2.5 PFLOP/s)."""
+    import torch
+
+    from .unet import UNet
+
+    net = UNet(levels=4, base=32, max_batch=batch, height=256, width=256, seed=0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    d = torch.rand((batch, 256, 256), generator=g, device="cuda")
+    x = torch.rand((batch, 256, 256), generator=g, device="cuda")
+    for _ in range(warmup):
+        net.train_step(d, x, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(d, x, 1e-4)
+    torch.cuda.synchronize()
+    step_ms = 1e3 * (time.perf_counter() - t0) / steps
+    tflops = 3 * unet_flops() * batch / (step_ms * 1e-3) / 1e12
+    return {"batch": batch, "steps": steps, "train_step_ms": step_ms, "conv_tflops": tflops,
+            "peak_tflops": 2500.0, "frac": tflops / 2500.0}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--train", type=int, default=512, help="training fields (seeds 0..N-1)")
@@ -337,7 +362,9 @@ def main(argv=None):
     ap.add_argument("--val", type=int, default=0,
                     help="training fields held back to select the epoch (validation, not the held-out test set)")
     ap.add_argument("--lr-final", type=float, default=None, help="cosine step-size schedule from --lr to this")
-    ap.add_argument("--phase", default="all", choices=("all", "train", "measure"))
+    ap.add_argument("--phase", default="all", choices=("all", "train", "measure", "throughput"),
+                    help="throughput: time --steps training steps of the network on random fields only")
+    ap.add_argument("--steps", type=int, default=50, help="--phase throughput: timed training steps")
     ap.add_argument("--save", default="", help="--phase train: directory for the network, mean image and J*")
     ap.add_argument("--load", default="", help="--phase measure: directory written by --phase train")
     a = ap.parse_args(argv)
@@ -351,6 +378,9 @@ def main(argv=None):
 
     import os
 
+    if a.phase == "throughput":
+        print(json.dumps(train_throughput(a.batch, a.steps)), flush=True)
+        return
     t0 = time.perf_counter()
     m = Mosaic()
     log(f"mosaic ready ({time.perf_counter() - t0:.1f} s): {m.plan.info()}")
