@@ -375,6 +375,7 @@ def run_cube(args):
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     p = synth.config_c4(with_field=False)
+    p.lambda_nu = float(args.lambda_nu)
     synth.attach_sd_level(p)
     n_total, n_track = p.n_vis, int(p.pt_offsets[-1])
     print(f"# workload {p.name}: N={p.n_sky} C={p.n_chan} P={p.n_point} vis={n_total} "
@@ -401,7 +402,7 @@ def run_cube(args):
     out = result_line(args, n_live, m, info,
                       "spectral cube, 128 channels x 36 pointings, 1024^2 sky at 30 arcsec, 384^2 sub-images, "
                       f"shared uv per pointing, {n_live} live visibilities, single-dish 64x64 per channel, "
-                      "lambda_r=1e-2, lambda_s=1",
+                      "lambda_r=1e-2, lambda_s=1" + (f", lambda_nu={p.lambda_nu:g}" if p.lambda_nu else ""),
                       {"n_sky": p.n_sky, "n_chan": p.n_chan, "n_point": p.n_point, "device_bytes": info["device_bytes"]},
                       alg, ev, measured_traffic("cube", blocking_of(info)))
     print(f"# {m['ms']:.2f} ms/eval (graph), {m['ms_eager']:.2f} eager, grid {m['grid_ms']:.2f} ms/launch, "
@@ -425,6 +426,8 @@ def main():
                     help="tile,waves,chunk,lanes,vpi of the gridding kernel (default: the autotuner's choice "
                          f"for the workload, recorded: cube {CUBE_BLOCKING}, single {SINGLE_BLOCKING})")
     ap.add_argument("--autotune", action="store_true", help="run the plan autotuner instead of --blocking")
+    ap.add_argument("--lambda-nu", type=float, default=0.0,
+                    help="cube only: weight of the spectral smoothness term (0: the paper's independent channels)")
     ap.add_argument("--workload", default="cube", choices=("cube", "single", "mosaic", "mosaic-w"),
                     help="cube: the 128-channel spectral cube (default, the largest single-GPU "
                          "configuration); single: the 512^2 single-pointing problem; mosaic: the "

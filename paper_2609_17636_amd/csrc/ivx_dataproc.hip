@@ -108,28 +108,60 @@ __global__ __launch_bounds__(BT) void k_resample_beam(const real *__restrict__ i
     out[(int64_t)k * n_sub * n_sub + e] = sample(in + (int64_t)k * nb * nb, nb, nb, row, col);
 }
 
-// one thread per (channel, sky pixel); pointings summed in index order
+// One thread per (sky pixel, group of MOS_CG channels): per pointing the deprojected position,
+// the bilinear taps and the beam weight are formed once and applied to every channel of the
+// group (the per-channel sums run over the pointings in index order, as before).
+constexpr int MOS_CG = 16;
 __global__ __launch_bounds__(BT) void k_linear_mosaic(int P, int C, int n_sub, const real *__restrict__ sub,
                                                       const real *__restrict__ beams, int N,
                                                       const real *__restrict__ deproj, real pb_min2,
                                                       real *__restrict__ image, real *__restrict__ pb_eff) {
-    const int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x;
+    const int64_t r = (int64_t)blockIdx.x * BT + threadIdx.x;
     const int64_t NN = (int64_t)N * N;
-    if (e >= NN * C) return;
-    const int c = (int)(e / NN);
-    const int64_t r = e - (int64_t)c * NN;
+    if (r >= NN) return;
+    const int c0 = blockIdx.y * MOS_CG;
+    const int cn = min(MOS_CG, C - c0);
     const int64_t n2 = (int64_t)n_sub * n_sub;
-    real num = real(0), den = real(0);
+    real num[MOS_CG];
+#pragma unroll
+    for (int q = 0; q < MOS_CG; ++q) num[q] = real(0);
+    real den = real(0);
     for (int k = 0; k < P; ++k) {
         const real row = deproj[((int64_t)k * NN + r) * 2], col = deproj[((int64_t)k * NN + r) * 2 + 1];
-        const real A = sample(beams + (int64_t)k * n2, n_sub, n_sub, row, col);
+        if (!(row > real(-1) && row < real(n_sub) && col > real(-1) && col < real(n_sub))) continue;
+        const real fr = floor(row), fc = floor(col);
+        const int i0 = (int)fr, j0 = (int)fc;
+        const real fy = row - fr, fx = col - fc;
+        const bool r0 = i0 >= 0, r1 = i0 + 1 < n_sub, q0 = j0 >= 0, q1 = j0 + 1 < n_sub;
+        const real w00 = (r0 && q0) ? (real(1) - fy) * (real(1) - fx) : real(0);
+        const real w01 = (r0 && q1) ? (real(1) - fy) * fx : real(0);
+        const real w10 = (r1 && q0) ? fy * (real(1) - fx) : real(0);
+        const real w11 = (r1 && q1) ? fy * fx : real(0);
+        // clamped tap offsets: a weight is zero wherever its tap is outside
+        const int64_t o00 = (int64_t)max(i0, 0) * n_sub + max(j0, 0);
+        const int64_t o01 = (int64_t)max(i0, 0) * n_sub + min(j0 + 1, n_sub - 1);
+        const int64_t o10 = (int64_t)min(i0 + 1, n_sub - 1) * n_sub + max(j0, 0);
+        const int64_t o11 = (int64_t)min(i0 + 1, n_sub - 1) * n_sub + min(j0 + 1, n_sub - 1);
+        auto tap = [&](const real *img) {
+            return (real(1) - fy) * ((real(1) - fx) * (w00 != real(0) ? img[o00] : real(0)) +
+                                      fx * (w01 != real(0) ? img[o01] : real(0))) +
+                   fy * ((real(1) - fx) * (w10 != real(0) ? img[o10] : real(0)) +
+                         fx * (w11 != real(0) ? img[o11] : real(0)));
+        };
+        const real A = tap(beams + (int64_t)k * n2);
         if (A == real(0)) continue;
-        const real I = sample(sub + ((int64_t)k * C + c) * n2, n_sub, n_sub, row, col);
-        num += A * A * I;
-        den += A * A;
+        const real A2 = A * A;
+        const real *sk = sub + ((int64_t)k * C + c0) * n2;
+#pragma unroll
+        for (int q = 0; q < MOS_CG; ++q)
+            if (q < cn) num[q] += A2 * tap(sk + (int64_t)q * n2);
+        den += A2;
     }
-    image[e] = (den > real(0) && den >= pb_min2) ? num / den : real(0);
-    if (pb_eff && c == 0) pb_eff[r] = sqrt(den);
+    const bool keep = den > real(0) && den >= pb_min2;
+#pragma unroll
+    for (int q = 0; q < MOS_CG; ++q)
+        if (q < cn) image[(int64_t)(c0 + q) * NN + r] = keep ? num[q] / den : real(0);
+    if (pb_eff && blockIdx.y == 0) pb_eff[r] = sqrt(den);
 }
 
 unsigned blocks(int64_t n) { return (unsigned)((n + BT - 1) / BT); }
@@ -202,9 +234,9 @@ ivx_status ivx_linear_mosaic(int32_t n_point, int32_t n_chan, int32_t n_sub, con
     if (n_point < 1 || n_chan < 1 || n_sub < 4 || n_sky < 4 || !sub_images || !beams || !deproj || !image ||
         !(pb_min >= 0.0) || !std::isfinite(pb_min))
         return set_error(IVX_EINVAL, "bad ivx_linear_mosaic arguments");
-    const int64_t tot = (int64_t)n_sky * n_sky * n_chan;
-    k_linear_mosaic<<<blocks(tot), BT, 0, (hipStream_t)stream>>>(n_point, n_chan, n_sub, sub_images, beams, n_sky,
-                                                                 deproj, (real)(pb_min * pb_min), image, pb_eff);
+    const dim3 grid(blocks((int64_t)n_sky * n_sky), (unsigned)((n_chan + MOS_CG - 1) / MOS_CG));
+    k_linear_mosaic<<<grid, BT, 0, (hipStream_t)stream>>>(n_point, n_chan, n_sub, sub_images, beams, n_sky, deproj,
+                                                          (real)(pb_min * pb_min), image, pb_eff);
     return hip_status(hipGetLastError(), "k_linear_mosaic");
 }
 

@@ -129,3 +129,67 @@ def feather(interf, single_dish, delta, theta, out=None):
     _check(lib, lib.ivx_feather(C, n, float(delta), float(theta), a.data_ptr(), s.data_ptr(), out.data_ptr(),
                                 work.data_ptr(), _stream()))
     return out
+
+
+def bench(n_point_side: int = 6, n_sky: int = 1024, n_sub: int = 384, n_chan: int = 128, reps: int = 10) -> dict:
+    """Device time of each data-processor and image-domain call at the spectral cube's
+    geometry (36 pointings of 384^2 over a 1024^2 sky at 30 arcsec, 128 channels): grids,
+    deprojection grids, beam resampling from 512^2 beam images, the linear mosaic of 36 x 128
+    sub-images and the feathering of 128 maps.  Algorithmic bytes: each array read or written
+    once (the bilinear taps of a sub-image and the gathers of the mosaic count their source
+    once); the fraction is against the 8 TB/s HBM peak."""
+    import time
+
+    torch = _torch()
+    arcsec = np.pi / (180.0 * 3600.0)
+    delta = 30.0 * arcsec
+    ra0, dec0 = 1.387, -1.2049
+    pitch = 120.0 * delta
+    c = n_point_side
+    centres = np.array([[ra0 + ((j - (c - 1) / 2) * pitch + (0.5 * pitch if i % 2 else 0.0)) / np.cos(dec0),
+                         dec0 + (i - (c - 1) / 2) * pitch * np.sqrt(3) / 2] for i in range(c) for j in range(c)])
+    P = centres.shape[0]
+    g = torch.Generator(device="cuda").manual_seed(0)
+    nb = 512
+    beams_in = torch.rand((P, nb, nb), generator=g, device="cuda")
+    sub = torch.rand((P, n_chan, n_sub, n_sub), generator=g, device="cuda")
+    maps = torch.rand((n_chan, n_sky, n_sky), generator=g, device="cuda")
+    sd = torch.rand((n_chan, n_sky, n_sky), generator=g, device="cuda")
+    out = {}
+
+    def timed(name, fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"ms": ms, "algorithmic_bytes": float(nbytes), "achieved_gbs": gbs, "frac": gbs / 8000.0}
+        return r
+
+    grids = timed("sin_grids", lambda: sin_grids(n_sky, delta, ra0, dec0, centres, n_sub, delta), P * n_sub * n_sub * 8)
+    dep = timed("deprojection_grids", lambda: deprojection_grids(n_sky, delta, ra0, dec0, centres, n_sub, delta),
+                P * n_sky * n_sky * 8)
+    beams = timed("resample_beams", lambda: resample_beams(beams_in, 20.0 * arcsec, n_sub, delta),
+                  P * (nb * nb + n_sub * n_sub) * 4)
+    timed("linear_mosaic", lambda: linear_mosaic(sub, beams, dep, 0.2),
+          P * n_sky * n_sky * 8 + P * (n_chan + 1) * n_sub * n_sub * 4 + (n_chan + 1) * n_sky * n_sky * 4)
+    timed("feather", lambda: feather(maps, sd, delta, 30.0 * 60.0 * arcsec),
+          n_chan * n_sky * n_sky * (3 * 4 + 2 * 8))
+    del grids
+    out["geometry"] = {"n_point": P, "n_sky": n_sky, "n_sub": n_sub, "n_chan": n_chan, "beam_image": nb,
+                       "reps": reps}
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="device time of the data-processor and image-domain calls")
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--n-chan", type=int, default=128)
+    a = ap.parse_args()
+    print(json.dumps(bench(n_chan=a.n_chan, reps=a.reps)), flush=True)
