@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["ivx_api.hip", "ivx_build.hip", "ivx_kernels.hip", "ivx_unet.hip", "ivx_lbfgsb.hip", "ivx_dataproc.hip", "ivx_wstack.hip"]
+SOURCES = ["ivx_api.hip", "ivx_build.hip", "ivx_kernels.hip", "ivx_unet.hip", "ivx_lbfgsb.hip", "ivx_dataproc.hip", "ivx_wstack.hip", "ivx_sort.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -10,7 +10,6 @@
 // every sum the gridding pass forms, depends only on the data and the tile edge.
 #include "ivx_internal.hpp"
 
-#include <hipcub/hipcub.hpp>
 
 namespace ivx {
 
@@ -298,12 +297,20 @@ hipError_t launch_gather_block(int64_t n, const int32_t *perm, const real *vis, 
 
 hipError_t sort_keys(void *temp, size_t &temp_bytes, const uint64_t *in, uint64_t *out, int n, int end_bit,
                      hipStream_t st) {
-    return hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, in, out, n, 0, end_bit, st);
+    if (!temp) {
+        temp_bytes = radix_sort_temp_bytes(n, false);
+        return hipSuccess;
+    }
+    return radix_sort(temp, temp_bytes, in, out, nullptr, nullptr, n, end_bit, st);
 }
 
 hipError_t sort_pairs(void *temp, size_t &temp_bytes, const uint64_t *kin, uint64_t *kout, const uint32_t *vin,
                       uint32_t *vout, int n, int end_bit, hipStream_t st) {
-    return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, kin, kout, vin, vout, n, 0, end_bit, st);
+    if (!temp) {
+        temp_bytes = radix_sort_temp_bytes(n, true);
+        return hipSuccess;
+    }
+    return radix_sort(temp, temp_bytes, kin, kout, vin, vout, n, end_bit, st);
 }
 
 } // namespace ivx

@@ -192,7 +192,13 @@ hipError_t launch_rebin_emit(int64_t n, const uint64_t *keys, const uint32_t *va
 // sorted data of one block from the caller's block arrays (w may be NULL: weights kept)
 hipError_t launch_gather_block(int64_t n, const int32_t *perm, const real *vis, const real *w, cpx *svis,
                                real *swgt, unsigned int *bad, hipStream_t st);
-// hipCUB radix sorts over bits [0, end_bit); temp == NULL queries temp_bytes
+// Stable radix sort (ivx_sort.hip) of n 64-bit keys over bits [0, end_bit), with 32-bit values
+// when vin != NULL; kin / kout (vin / vout) must not overlap; temp holds
+// radix_sort_temp_bytes(n, vin != NULL) bytes.
+size_t radix_sort_temp_bytes(int n, bool pairs);
+hipError_t radix_sort(void *temp, size_t temp_bytes, const uint64_t *kin, uint64_t *kout, const uint32_t *vin,
+                      uint32_t *vout, int n, int end_bit, hipStream_t st);
+// radix sorts over bits [0, end_bit) for the binning; temp == NULL queries temp_bytes
 hipError_t sort_keys(void *temp, size_t &temp_bytes, const uint64_t *in, uint64_t *out, int n, int end_bit,
                      hipStream_t st);
 hipError_t sort_pairs(void *temp, size_t &temp_bytes, const uint64_t *kin, uint64_t *kout, const uint32_t *vin,

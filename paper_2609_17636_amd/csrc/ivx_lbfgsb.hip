@@ -18,7 +18,6 @@
 #include "ivx_internal.hpp"
 #include "ivx_lbfgsb.h"
 
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -930,14 +929,8 @@ ivx_status ivx_lbfgsb_create(ivx_plan *plan, int32_t m_max, ivx_lbfgsb **out) {
     if (!st) st = lb_alloc_t(s, &s->sky, (size_t)n);
     if (!st) st = lb_alloc_t(s, &s->grad, (size_t)n);
     if (!st) {
-        size_t bytes = 0;
-        if (hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, s->key, s->key2, s->val, s->val2, (int)n) != hipSuccess) {
-            (void)hipGetLastError();
-            st = set_error(IVX_EHIP, "radix sort size query failed");
-        } else {
-            s->sort_bytes = bytes;
-            st = lb_alloc(s, &s->sort_tmp, bytes);
-        }
+        s->sort_bytes = radix_sort_temp_bytes((int)n, true);
+        st = lb_alloc(s, &s->sort_tmp, s->sort_bytes);
     }
     if (!st && hipHostMalloc((void **)&s->host, SCAL * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -1059,8 +1052,10 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
                 } else {
                     const int64_t K = (int64_t)nbr, K1 = K + 1;
                     ++nwalk;
-                    LB_HIP(hipcub::DeviceRadixSort::SortPairs(s->sort_tmp, s->sort_bytes, s->key, s->key2, s->val,
-                                                              s->val2, (int)n, 0, 64, st));
+                    // breakpoints t >= 0 (or +inf): their IEEE bit patterns order as the values
+                    LB_HIP(radix_sort(s->sort_tmp, s->sort_bytes, reinterpret_cast<const uint64_t *>(s->key),
+                                      reinterpret_cast<uint64_t *>(s->key2), reinterpret_cast<const uint32_t *>(s->val),
+                                      reinterpret_cast<uint32_t *>(s->val2), (int)n, 64, st));
                     const unsigned GK = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (K1 + NT - 1) / NT));
                     Vec p0v{};
                     for (int j = 0; j < D; ++j) p0v.v[j] = p0[j];
