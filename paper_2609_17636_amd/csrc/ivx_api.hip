@@ -198,6 +198,8 @@ struct ivx_plan {
     real *d_wcorr = nullptr;
     double *d_w0 = nullptr;
     int32_t *d_wnp = nullptr;
+    int32_t *d_wcnt = nullptr;        // per-work-item record counts below each half plane (or NULL)
+    int wncnt = 0;
 };
 
 namespace {
@@ -265,6 +267,8 @@ void free_all(ivx_plan *p) {
     p->d_wcorr = nullptr;
     p->d_w0 = nullptr;
     p->d_wnp = nullptr;
+    p->d_wcnt = nullptr;
+    p->wncnt = 0;
 }
 
 void free_one(ivx_plan *p, void *ptr) {
@@ -1045,6 +1049,21 @@ ivx_status w_prepare(ivx_plan *p, hipStream_t st) {
                              st));
     }
     IVX_HIP(launch_wsort(p->d_work, p->n_work, p->d_crd, p->d_vis, p->d_wgt, p->d_perm, p->d_wz, st));
+    // the plane ranges of every work item as a table (two loads per work item and plane in the
+    // gridding passes instead of two binary searches), when it fits a modest budget
+    if (p->d_wcnt) free_one(p, p->d_wcnt);
+    p->d_wcnt = nullptr;
+    p->wncnt = 0;
+    {
+        const int ncnt = 2 * planes + W + 1;
+        const size_t bytes = (size_t)std::max(p->n_work, 1) * ncnt * sizeof(int32_t);
+        if (planes > 0 && bytes <= ((size_t)2 << 30) && dalloc(p, &p->d_wcnt, bytes / sizeof(int32_t)) == IVX_OK) {
+            p->wncnt = ncnt;
+            IVX_HIP(launch_wcounts(p->d_work, p->n_work, p->d_wz, ncnt, p->d_wcnt, st));
+        } else {
+            g_last_error.clear(); // the binary searches serve instead
+        }
+    }
     IVX_HIP(prepare_wgrid(g, p->nwave));
     unsigned int hb = 0;
     IVX_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(hb), hipMemcpyDeviceToHost, st));
@@ -1062,7 +1081,8 @@ WGeom wgeom(const ivx_plan *p) {
 }
 
 WPlane wplane(const ivx_plan *p, int plane, bool adjoint) {
-    return WPlane{p->d_wz, adjoint ? nullptr : p->d_wacc, adjoint ? p->d_wacc : nullptr, plane, p->w_W, p->w_beta};
+    return WPlane{p->d_wz, adjoint ? nullptr : p->d_wacc, adjoint ? p->d_wacc : nullptr, plane, p->w_W, p->w_beta,
+                  p->d_wcnt, p->wncnt};
 }
 
 // Sky -> per-record sum over planes of the w-kernel-weighted plane transforms (d_wacc).

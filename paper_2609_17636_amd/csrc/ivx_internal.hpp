@@ -92,6 +92,10 @@ struct WPlane {
     int plane;
     int W;
     double beta;
+    // optional per-work-item table of record counts below each half plane: cnt[wid * ncnt + h]
+    // = records of work item wid with zeta < h / 2, h = 0 .. ncnt - 1 (NULL: binary searches)
+    const int32_t *cnt;
+    int ncnt;
 };
 
 // Sky pass tiling: blocks of SKY_T x SKY_T pixels, 256 threads, thread t at row t / SKY_T,
@@ -229,6 +233,8 @@ hipError_t launch_wzeta(int64_t n, const int32_t *perm, const real *wsrc, double
                         WZ *out, unsigned int *bad, hipStream_t st);
 hipError_t launch_wsort(const WorkItem *work, int n_work, VisCoord *crd, cpx *vis, real *wgt, int32_t *perm, WZ *wz,
                         hipStream_t st);
+// the WPlane::cnt table of every work item (after launch_wsort)
+hipError_t launch_wcounts(const WorkItem *work, int n_work, const WZ *wz, int ncnt, int32_t *cnt, hipStream_t st);
 hipError_t launch_wplane_rows(const Geom &g, const WGeom &wg, int plane, const real *sky, const real *beams,
                               const real *interp, const real *fscale, const real *dq, const cpx *tw, cpx *R,
                               hipStream_t st);

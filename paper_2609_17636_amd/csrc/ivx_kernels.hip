@@ -207,6 +207,8 @@ struct GridArgs {
     int wplane;
     int wW;
     real wbeta2; // w kernel shape, scaled like beta2 below
+    const int32_t *wcnt; // record counts below each half plane per work item, or NULL
+    int wncnt;
 };
 
 // Signed distance, in planes, of a record's w from plane p.
@@ -344,9 +346,18 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
     // leaves together).
     int base = 0, cnt = wi.count;
     if constexpr (WPL) {
-        const WZ *z = a.wz + wi.begin;
-        base = wz_lower(z, wi.count, 2 * a.wplane - a.wW);
-        cnt = wz_lower(z, wi.count, 2 * a.wplane + a.wW) - base;
+        const int h0 = 2 * a.wplane - a.wW, h1 = 2 * a.wplane + a.wW;
+        if (a.wcnt) {
+            // two independent loads from the work item's table instead of two chains of
+            // dependent loads
+            const int32_t *c = a.wcnt + wid * (int64_t)a.wncnt;
+            base = h0 <= 0 ? 0 : (h0 >= a.wncnt ? wi.count : c[h0]);
+            cnt = (h1 <= 0 ? 0 : (h1 >= a.wncnt ? wi.count : c[h1])) - base;
+        } else {
+            const WZ *z = a.wz + wi.begin;
+            base = wz_lower(z, wi.count, h0);
+            cnt = wz_lower(z, wi.count, h1) - base;
+        }
         if (cnt == 0) {
             if (MODE == MODE_WADJ) {
                 cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride;
@@ -1884,6 +1895,8 @@ hipError_t launch_wgrid(int mode, const Geom &g, const WorkItem *work, int n_wor
     a.wq = wp.q;
     a.wplane = wp.plane;
     a.wW = wp.W;
+    a.wcnt = wp.cnt;
+    a.wncnt = wp.ncnt;
 #ifdef IVX_REAL_DOUBLE
     a.wbeta2 = wp.beta;
 #else

@@ -174,6 +174,31 @@ __global__ __launch_bounds__(NT) void k_wsort(const WorkItem *__restrict__ work,
     permute_words(reinterpret_cast<uint32_t *>(z), n, (int)(sizeof(WZ) / 4), idx, stage);
 }
 
+// cnt[wid][h] = records of work item wid with zeta < h / 2 (its records are sorted by zeta):
+// one binary search per (work item, h).
+__global__ __launch_bounds__(NT) void k_wcounts(const WorkItem *__restrict__ work, int n_work, const WZ *__restrict__ wz,
+                                                int ncnt, int32_t *__restrict__ cnt) {
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= (int64_t)n_work * ncnt) return;
+    const int64_t wid = e / ncnt;
+    const int h = (int)(e - wid * ncnt);
+    const WorkItem wi = work[wid];
+    const WZ *z = wz + wi.begin;
+#ifdef IVX_REAL_DOUBLE
+    const double key = 0.5 * (double)h;
+#else
+    const int64_t k = (int64_t)h << 23;
+    const uint32_t key = k > (int64_t)0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)k;
+#endif
+    int lo = 0, hi = wi.count;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (z[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    cnt[e] = lo;
+}
+
 // ------------------------------------------------------------------ plane passes
 template <int LOGN>
 __global__ __launch_bounds__(NT) void k_wimage_rows(Geom g, WGeom wg, int plane, const real *__restrict__ sky,
@@ -445,6 +470,13 @@ hipError_t launch_wsort(const WorkItem *work, int n_work, VisCoord *crd, cpx *vi
                         hipStream_t st) {
     if (n_work <= 0) return hipSuccess;
     k_wsort<<<work_grid(n_work), NT, 0, st>>>(work, n_work, crd, vis, wgt, perm, wz);
+    return hipGetLastError();
+}
+
+hipError_t launch_wcounts(const WorkItem *work, int n_work, const WZ *wz, int ncnt, int32_t *cnt, hipStream_t st) {
+    const int64_t tot = (int64_t)n_work * ncnt;
+    if (tot <= 0) return hipSuccess;
+    k_wcounts<<<(unsigned)((tot + NT - 1) / NT), NT, 0, st>>>(work, n_work, wz, ncnt, cnt);
     return hipGetLastError();
 }
 
