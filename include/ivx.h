@@ -74,7 +74,7 @@ typedef double ivx_real;
 typedef float ivx_real;
 #endif
 
-#define IVX_VERSION 3
+#define IVX_VERSION 4
 
 typedef enum {
     IVX_OK = 0,
@@ -247,6 +247,18 @@ ivx_status ivx_autotune(ivx_plan *plan, double budget_ms, int32_t *chosen_tile, 
  * kernel and deapodization, against its closed form exp(-2 pi i k x / n_fine) (Sect. 2.1's
  * model for one source).  The two-dimensional error is at most about twice this. */
 ivx_status ivx_nufft_probe(int32_t n_sub, int32_t n_fine, int32_t kernel_width, double *err);
+
+/* Stable radix sort of unsigned 64-bit keys on their bits [0, end_bit) (end_bit 1..64),
+ * optionally carrying one 32-bit value per key: the device sort behind the plan's binning
+ * of the visibility records (Sect. 2.3's gridding by tile) and behind the bounded solver's
+ * ordering of the breakpoints of the generalized Cauchy point (Sect. 3.4, Eq. L-BFGS-B).
+ * keys_in / keys_out (and vals_in / vals_out) are caller-owned device arrays of n entries
+ * that must not overlap; vals_in = NULL sorts keys only and ignores vals_out.  Keys that
+ * agree on the sorted bits keep their input order.  The call allocates and frees its own
+ * scratch (the plan and the solver keep theirs) and synchronises `stream`.  IVX_EINVAL for
+ * n outside [0, 2^31), end_bit outside 1..64 or a missing array; n = 0 does nothing. */
+ivx_status ivx_sort_u64(const uint64_t *keys_in, uint64_t *keys_out, const uint32_t *vals_in,
+                        uint32_t *vals_out, int64_t n, int32_t end_bit, void *stream);
 
 /* ivx_objective_grad records its launches into a HIP graph on first use and replays it
  * while the (sky, grad) pointers stay the same (a new pair re-captures).  enable = 0

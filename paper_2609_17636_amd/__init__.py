@@ -49,7 +49,7 @@ EXPORTS = ("ivx_plan_create", "ivx_plan_set_data", "ivx_objective_grad", "ivx_fo
            "ivx_real_size", "ivx_set_timing", "ivx_stage_times", "ivx_set_graph", "ivx_set_blocking",
            "ivx_plan_set_vis", "ivx_set_gridder_occupancy", "ivx_set_fused_fold", "ivx_objective",
            "ivx_objective_forward", "ivx_objective_backward", "ivx_forward_adjoint", "ivx_last_terms",
-           "ivx_nufft_probe", "ivx_plan_set_w", "ivx_plan_w_info")
+           "ivx_nufft_probe", "ivx_plan_set_w", "ivx_plan_w_info", "ivx_sort_u64")
 
 STAGES = ("image_rows", "col_fwd", "grid", "fold", "col_inv", "row_inv", "sd", "sky", "final")
 
@@ -89,6 +89,8 @@ def load_library(precision: str = "f32") -> ctypes.CDLL:
     lib.ivx_nufft_probe.argtypes = [i32, i32, i32, vp]
     lib.ivx_plan_set_w.argtypes = [vp, vp, i32, dbl, vp]
     lib.ivx_plan_w_info.argtypes = [vp, vp]
+    lib.ivx_sort_u64.argtypes = [vp, vp, vp, vp, i64, i32, vp]
+    lib.ivx_sort_u64.restype = ctypes.c_int
     lib.ivx_stage_times.argtypes = [vp, vp, vp]
     lib.ivx_last_error.restype = ctypes.c_char_p
     lib.ivx_last_error.argtypes = []
@@ -144,6 +146,26 @@ def nufft_probe(n_sub: int, n_fine: int, kernel_width: int, precision: str = "f3
     if code != 0:
         raise IvxError(code, lib.ivx_last_error().decode())
     return float(e[0])
+
+
+def sort_u64(keys, values=None, end_bit: int = 64, precision: str = "f32"):
+    """ivx_sort_u64: stable radix sort of a cuda int64 tensor (bit patterns taken as unsigned)
+    on bits [0, end_bit), optionally carrying a cuda int32 tensor.  Returns (keys, values)."""
+    torch = _torch()
+    lib = load_library(precision)
+    assert keys.is_cuda and keys.dtype == torch.int64 and keys.dim() == 1
+    keys = keys.contiguous()
+    out_k = torch.empty_like(keys)
+    out_v = None
+    if values is not None:
+        assert values.is_cuda and values.dtype == torch.int32 and values.shape == keys.shape
+        values = values.contiguous()
+        out_v = torch.empty_like(values)
+    code = lib.ivx_sort_u64(_ptr(keys), _ptr(out_k), _ptr(values), _ptr(out_v), keys.numel(), int(end_bit),
+                            _stream_ptr())
+    if code != 0:
+        raise IvxError(code, lib.ivx_last_error().decode())
+    return out_k, out_v
 
 
 class Plan:

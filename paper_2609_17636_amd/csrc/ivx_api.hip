@@ -2005,4 +2005,25 @@ extern "C" ivx_status ivx_nufft_probe(int32_t n_sub, int32_t n_fine, int32_t ker
     return IVX_OK;
 }
 
+extern "C" ivx_status ivx_sort_u64(const uint64_t *keys_in, uint64_t *keys_out, const uint32_t *vals_in,
+                                   uint32_t *vals_out, int64_t n, int32_t end_bit, void *stream) {
+    if (n < 0 || n > (int64_t)INT32_MAX || end_bit < 1 || end_bit > 64)
+        return fail(IVX_EINVAL, "ivx_sort_u64: n must be in [0, 2^31) and end_bit in [1, 64]");
+    if (n == 0) return IVX_OK;
+    if (!keys_in || !keys_out || (vals_in && !vals_out))
+        return fail(IVX_EINVAL, "ivx_sort_u64: keys_in, keys_out (and vals_out with vals_in) are required");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = radix_sort_temp_bytes((int)n, vals_in != nullptr);
+    void *temp = nullptr;
+    IVX_HIP(hipStreamSynchronize(st));
+    IVX_HIP(hipMalloc(&temp, bytes));
+    const hipError_t e = radix_sort(temp, bytes, keys_in, keys_out, vals_in, vals_in ? vals_out : nullptr, (int)n,
+                                    end_bit, st);
+    const hipError_t e2 = hipStreamSynchronize(st);
+    (void)hipFree(temp);
+    IVX_HIP(e);
+    IVX_HIP(e2);
+    return IVX_OK;
+}
+
 } // extern "C"

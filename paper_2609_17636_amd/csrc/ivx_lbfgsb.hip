@@ -90,27 +90,62 @@ __device__ __forceinline__ void block_reduce(double (&acc)[NV], int nv, int nsum
     }
 }
 
+// The rows are cut into FIN_CH consecutive chunks; thread (q, c) combines quantity q over
+// the rows of chunk c in block order, then out[q] combines the chunk results in chunk order.
+// The order is fixed (results do not depend on timing) and the loads of a chunk are
+// independent, so they are in flight together instead of one row latency after another.
+constexpr int FIN_CH = 16;
+constexpr int FIN_NV = MAXNV > MAXD * (MAXD + 1) / 2 ? MAXNV : MAXD * (MAXD + 1) / 2;
+
 __global__ __launch_bounds__(NT) void k_finish(const double *__restrict__ part, int nblk, int nv, int nsum,
                                                double *__restrict__ out) {
+    __shared__ double sh[FIN_CH][FIN_NV];
+    const int per = (nblk + FIN_CH - 1) / FIN_CH;
+    for (int e = threadIdx.x; e < nv * FIN_CH; e += NT) {
+        const int q = e % nv, c = e / nv;
+        const int b0 = c * per, b1 = min(nblk, b0 + per);
+        const bool add = q < nsum;
+        double v = add ? 0.0 : INF;
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) {
+            const double pv = part[(int64_t)b * nv + q];
+            v = add ? v + pv : fmin(v, pv);
+        }
+        sh[c][q] = v;
+    }
+    __syncthreads();
     for (int q = threadIdx.x; q < nv; q += NT) {
-        double v = part[q];
-        for (int b = 1; b < nblk; ++b) v = q < nsum ? v + part[(int64_t)b * nv + q] : fmin(v, part[(int64_t)b * nv + q]);
+        double v = sh[0][q];
+        for (int c = 1; c < FIN_CH; ++c) v = q < nsum ? v + sh[c][q] : fmin(v, sh[c][q]);
         out[q] = v;
     }
 }
 
+// The stored pairs at element i: ys[j] = Y_j[i], ss[j] = S_j[i] for j < k, zero after.
+// Unused slots read slot 0 (always allocated) and are masked by a select, so no load sits
+// behind a branch or next to its use: all 2 MAXM loads of a thread are in flight together
+// instead of one memory latency per stored pair.
+__device__ __forceinline__ void load_pairs(const double *__restrict__ S, const double *__restrict__ Y, int64_t n,
+                                           const Slots &sl, int64_t i, double (&ys)[MAXM], double (&ss)[MAXM]) {
+#pragma unroll
+    for (int j = 0; j < MAXM; ++j) {
+        const bool on = j < sl.k;
+        const int64_t o = (int64_t)(on ? sl.idx[j] : 0) * n + i;
+        const double yv = Y[o], sv = S[o];
+        ys[j] = on ? yv : 0.0;
+        ss[j] = on ? sv : 0.0;
+    }
+}
+
 // w_i . u with w_i = (Y_0[i] .. Y_{k-1}[i], theta S_0[i] .. theta S_{k-1}[i]),
-// u = (uy, us)
-__device__ __forceinline__ double wdot(const double *S, const double *Y, int64_t n, const Slots &sl, double theta,
-                                       const Half &uy, const Half &us, int64_t i) {
+// u = (uy, us) (entries of u past the stored pairs are zero)
+__device__ __forceinline__ double wdot(const double (&ys)[MAXM], const double (&ss)[MAXM], double theta,
+                                       const Half &uy, const Half &us) {
     double a = 0.0, b = 0.0;
 #pragma unroll
     for (int j = 0; j < MAXM; ++j) {
-        if (j < sl.k) {
-            const int64_t o = (int64_t)sl.idx[j] * n + i;
-            a += Y[o] * uy.v[j];
-            b += S[o] * us.v[j];
-        }
+        a += ys[j] * uy.v[j];
+        b += ss[j] * us.v[j];
     }
     return a + theta * b;
 }
@@ -166,7 +201,6 @@ __global__ __launch_bounds__(NT) void k_cp_init(const double *__restrict__ x, co
     double acc[MAXNV];
 #pragma unroll
     for (int q = 0; q < MAXNV; ++q) acc[q] = 0.0;
-    const int k = sl.k;
     double tmin = INF;
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
         const double gi = g[i];
@@ -182,13 +216,12 @@ __global__ __launch_bounds__(NT) void k_cp_init(const double *__restrict__ x, co
         acc[0] += di * di;
         acc[1] += br ? 1.0 : 0.0;
         acc[2] += fx ? 1.0 : 0.0;
+        double ys[MAXM], ss[MAXM];
+        load_pairs(S, Y, n, sl, i, ys, ss);
 #pragma unroll
         for (int j = 0; j < MAXM; ++j) {
-            if (j < k) {
-                const int64_t o = (int64_t)sl.idx[j] * n + i;
-                acc[3 + j] += Y[o] * di;
-                acc[3 + MAXM + j] += S[o] * di;
-            }
+            acc[3 + j] += ys[j] * di;
+            acc[3 + MAXM + j] += ss[j] * di;
         }
         if (br) tmin = fmin(tmin, ti);
     }
@@ -208,12 +241,13 @@ __global__ __launch_bounds__(NT) void k_cp_q(const double *__restrict__ skey, co
         if (j < K) {
             const int64_t b = sidx[j];
             const double gb = g[b];
+            double ys[MAXM], ss[MAXM];
+            load_pairs(S, Y, n, sl, b, ys, ss);
 #pragma unroll
             for (int c = 0; c < MAXM; ++c) {
                 if (c < sl.k) {
-                    const int64_t o = (int64_t)sl.idx[c] * n + b;
-                    Q[(int64_t)c * K1 + j] = gb * Y[o];
-                    Q[(int64_t)(sl.k + c) * K1 + j] = gb * theta * S[o];
+                    Q[(int64_t)c * K1 + j] = gb * ys[c];
+                    Q[(int64_t)(sl.k + c) * K1 + j] = gb * theta * ss[c];
                 }
             }
             DT[j] = skey[j] - (j > 0 ? skey[j - 1] : 0.0);
@@ -296,75 +330,124 @@ __global__ __launch_bounds__(NT) void k_scan_apply(const double *__restrict__ in
     }
 }
 
-// a_j = theta g_j^2 + 2 q_j.M P_j + q_j.M q_j  and  v_j = dt_j P_j  (P_j = p0 + Pex_j)
-__global__ __launch_bounds__(NT) void k_cp_a(const double *__restrict__ Q, const double *__restrict__ Pex,
-                                             const double *__restrict__ DT, const double *__restrict__ GB, int64_t K1,
-                                             int D, const double *__restrict__ Mdev, Vec p0, double theta,
-                                             double *__restrict__ A, double *__restrict__ V) {
-    __shared__ double Ms[MAXD * MAXD];
+// k_cp_a and k_cp_e give each breakpoint j a quad of lanes: lane r of the quad takes rows
+// a = r, r + 4, ... of M q_j, and the quad adds its four partial sums in a fixed order
+// ((l0 + l1) + (l2 + l3), the same bits on every lane).  Four times the waves of one lane
+// per breakpoint keep loads in flight while others compute.
+constexpr int QL = 4;               // lanes per breakpoint
+constexpr int RPL = MAXD / QL;      // rows of M per lane
+static_assert(MAXD % QL == 0, "rows must split evenly over the quad");
+
+__device__ __forceinline__ double quad_sum(double v) {
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    return v;
+}
+
+// M (zero past D) and p0 into LDS
+__device__ __forceinline__ void load_m(const double *__restrict__ Mdev, int D, double *Ms) {
     for (int e = threadIdx.x; e < MAXD * MAXD; e += NT) {
         const int a = e / MAXD, b = e % MAXD;
         Ms[e] = (a < D && b < D) ? Mdev[a * D + b] : 0.0;
     }
+}
+
+// Rows a >= D of M are zero in LDS, so the rows past D of q, P and C (read from row 0 of
+// their arrays: finite values) contribute exactly nothing and need no mask.  D = 0 (no
+// stored pairs) reads no rows at all: the arrays may not hold finite values yet.
+
+// a_j = theta g_j^2 + 2 q_j.M P_j + q_j.M q_j  and  v_j = dt_j P_j  (P_j = p0 + Pex_j)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_cp_a(const double *__restrict__ Q, const double *__restrict__ Pex,
+                                             const double *__restrict__ DT, const double *__restrict__ GB, int64_t K1,
+                                             int D, const double *__restrict__ Mdev, Vec p0, double theta,
+                                             double *__restrict__ A, double *__restrict__ V) {
+    __shared__ double Ms[MAXD * MAXD];
+    __shared__ double p0s[MAXD];
+    load_m(Mdev, D, Ms);
+    if (threadIdx.x < MAXD) p0s[threadIdx.x] = threadIdx.x < D ? p0.v[threadIdx.x] : 0.0;
     __syncthreads();
-    for (int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x; j < K1; j += (int64_t)gridDim.x * NT) {
-        double q[MAXD];
-#pragma unroll
-        for (int c = 0; c < MAXD; ++c) q[c] = c < D ? Q[(int64_t)c * K1 + j] : 0.0;
+    const int r = threadIdx.x & (QL - 1);
+    const int64_t stride = (int64_t)gridDim.x * (NT / QL);
+    // the quad shares j, so its lanes enter and leave the loop together
+    for (int64_t j = (int64_t)blockIdx.x * (NT / QL) + (threadIdx.x / QL); j < K1; j += stride) {
+        const double gb = GB[j], dt = DT[j];
         double qMP = 0.0, qMq = 0.0;
-        for (int a = 0; a < D; ++a) {
-            double mq = 0.0;
+        if (D > 0) {
+            double q[MAXD], P[RPL], qa[RPL];
 #pragma unroll
-            for (int b = 0; b < MAXD; ++b) mq += Ms[a * MAXD + b] * q[b];
-            const double Pa = p0.v[a] + Pex[(int64_t)a * K1 + j];
-            qMP += mq * Pa;
-            double qa = 0.0;
+            for (int c = 0; c < MAXD; ++c) q[c] = Q[(int64_t)(c < D ? c : 0) * K1 + j];
 #pragma unroll
-            for (int b = 0; b < MAXD; ++b) qa = (b == a) ? q[b] : qa;
-            qMq += mq * qa;
+            for (int t = 0; t < RPL; ++t) {
+                const int a = r + QL * t;
+                const int64_t o = (int64_t)(a < D ? a : 0) * K1 + j;
+                P[t] = p0s[a] + Pex[o];
+                qa[t] = Q[o]; // this lane's rows of q again (cache hits), not a register pick
+            }
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+                const int a = r + QL * t;
+                double mq = 0.0;
+#pragma unroll
+                for (int b = 0; b < MAXD; ++b) mq += Ms[a * MAXD + b] * q[b];
+                qMP += mq * P[t];
+                qMq += mq * qa[t];
+            }
+            // every lane stores all its rows: V has MAXD rows, those past D are never read, and a
+            // store guarded per lane made the compiler spill this kernel's registers
+#pragma unroll
+            for (int t = 0; t < RPL; ++t)
+                V[(int64_t)(r + QL * t) * K1 + j] = (dt < INF) ? dt * P[t] : 0.0;
         }
-        const double gb = GB[j];
-        A[j] = theta * gb * gb + 2.0 * qMP + qMq;
-        const double dt = DT[j];
-        for (int c = 0; c < D; ++c) {
-            const double Pc = p0.v[c] + Pex[(int64_t)c * K1 + j];
-            V[(int64_t)c * K1 + j] = (dt < INF) ? dt * Pc : 0.0;
-        }
+        qMP = quad_sum(qMP);
+        qMq = quad_sum(qMq);
+        if (r == 0) A[j] = theta * gb * gb + 2.0 * qMP + qMq;
     }
 }
 
 // e_j = dt_j f''_j + g_j^2 + theta g_j z_j - q_j.M C_{j+1},  C_{j+1} = Cex_j + v_j
-__global__ __launch_bounds__(NT) void k_cp_e(const double *__restrict__ Q, const double *__restrict__ Cex,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_cp_e(const double *__restrict__ Q, const double *__restrict__ Cex,
                                              const double *__restrict__ V, const double *__restrict__ Aex,
                                              const double *__restrict__ DT, const double *__restrict__ GB,
                                              const double *__restrict__ ZB, int64_t K1, int D,
                                              const double *__restrict__ Mdev, double fpp0, double theta,
                                              double *__restrict__ E) {
     __shared__ double Ms[MAXD * MAXD];
-    for (int e = threadIdx.x; e < MAXD * MAXD; e += NT) {
-        const int a = e / MAXD, b = e % MAXD;
-        Ms[e] = (a < D && b < D) ? Mdev[a * D + b] : 0.0;
-    }
+    load_m(Mdev, D, Ms);
     __syncthreads();
-    for (int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x; j < K1; j += (int64_t)gridDim.x * NT) {
+    const int r = threadIdx.x & (QL - 1);
+    const int64_t stride = (int64_t)gridDim.x * (NT / QL);
+    for (int64_t j = (int64_t)blockIdx.x * (NT / QL) + (threadIdx.x / QL); j < K1; j += stride) {
         const double dt = DT[j];
-        if (!(dt < INF)) {
-            E[j] = 0.0;
+        if (!(dt < INF)) { // uniform over the quad
+            if (r == 0) E[j] = 0.0;
             continue;
         }
-        double q[MAXD];
-#pragma unroll
-        for (int c = 0; c < MAXD; ++c) q[c] = c < D ? Q[(int64_t)c * K1 + j] : 0.0;
         double qMC = 0.0;
-        for (int a = 0; a < D; ++a) {
-            double mq = 0.0;
+        if (D > 0) {
+            double q[MAXD], C[RPL];
 #pragma unroll
-            for (int b = 0; b < MAXD; ++b) mq += Ms[a * MAXD + b] * q[b];
-            qMC += mq * (Cex[(int64_t)a * K1 + j] + V[(int64_t)a * K1 + j]);
+            for (int c = 0; c < MAXD; ++c) q[c] = Q[(int64_t)(c < D ? c : 0) * K1 + j];
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+                const int a = r + QL * t;
+                const int64_t o = (int64_t)(a < D ? a : 0) * K1 + j;
+                C[t] = Cex[o] + V[o];
+            }
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+                const int a = r + QL * t;
+                double mq = 0.0;
+#pragma unroll
+                for (int b = 0; b < MAXD; ++b) mq += Ms[a * MAXD + b] * q[b];
+                qMC += mq * C[t];
+            }
         }
-        const double gb = GB[j];
-        const double f2 = fpp0 - Aex[j];
-        E[j] = dt * f2 + gb * gb + theta * gb * ZB[j] - qMC;
+        qMC = quad_sum(qMC);
+        if (r == 0) {
+            const double gb = GB[j];
+            const double f2 = fpp0 - Aex[j];
+            E[j] = dt * f2 + gb * gb + theta * gb * ZB[j] - qMC;
+        }
     }
 }
 
@@ -426,18 +509,16 @@ __global__ __launch_bounds__(NT) void k_ss_r(const double *__restrict__ x, const
     double acc[MAXD];
 #pragma unroll
     for (int q = 0; q < MAXD; ++q) acc[q] = 0.0;
-    const int k = sl.k;
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        double ys[MAXM], ss[MAXM];
+        load_pairs(S, Y, n, sl, i, ys, ss);
         double ri = 0.0;
-        if (!fixed[i]) ri = g[i] + theta * (xc[i] - x[i]) - wdot(S, Y, n, sl, theta, mcy, mcs, i);
+        if (!fixed[i]) ri = g[i] + theta * (xc[i] - x[i]) - wdot(ys, ss, theta, mcy, mcs);
         r[i] = ri;
 #pragma unroll
         for (int j = 0; j < MAXM; ++j) {
-            if (j < k) {
-                const int64_t o = (int64_t)sl.idx[j] * n + i;
-                acc[j] += Y[o] * ri;
-                acc[MAXM + j] += S[o] * ri;
-            }
+            acc[j] += ys[j] * ri;
+            acc[MAXM + j] += ss[j] * ri;
         }
     }
     block_reduce<MAXD>(acc, MAXD, MAXD, part);
@@ -468,14 +549,29 @@ __global__ __launch_bounds__(NT) void k_ss_gram(const uint8_t *__restrict__ fixe
         pa[e] = a;
         pb[e] = a + p;
     }
+    __syncthreads(); // slot[] is read by every thread below
     for (int64_t r0 = (int64_t)blockIdx.x * GCH; r0 < n; r0 += (int64_t)gridDim.x * GCH) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < GCH * D; e += NT) {
+        // stage 64 rows x D columns: all of a thread's loads first (out-of-range entries read
+        // row 0 of slot 0 and are masked), then the LDS stores
+        constexpr int GIT = GCH * MAXD / NT;
+        double v[GIT];
+#pragma unroll
+        for (int it = 0; it < GIT; ++it) {
+            const int e = threadIdx.x + it * NT;
             const int rr = e % GCH, c = e / GCH;
             const int64_t i = r0 + rr;
-            double v = 0.0;
-            if (i < n && !fixed[i]) v = c < k ? Y[(int64_t)slot[c] * n + i] : S[(int64_t)slot[c - k] * n + i];
-            sh[rr][c] = v;
+            const bool on = c < D && i < n;
+            const int64_t ic = on ? i : 0;
+            const int sj = c < k ? slot[c] : slot[min(c - k, MAXM - 1)];
+            const double val = (c < k ? Y : S)[(int64_t)sj * n + ic];
+            const uint8_t fx = fixed[ic];
+            v[it] = (on && !fx) ? val : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < GIT; ++it) {
+            const int e = threadIdx.x + it * NT;
+            sh[e % GCH][e / GCH] = v[it];
         }
         __syncthreads();
 #pragma unroll
@@ -505,8 +601,10 @@ __global__ __launch_bounds__(NT) void k_ss_du(const double *__restrict__ x, cons
     double acc[2] = {0.0, INF};
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
         double dui = 0.0, xb = xc[i];
+        double ys[MAXM], ss[MAXM];
+        load_pairs(S, Y, n, sl, i, ys, ss);
         if (!fixed[i]) {
-            dui = -r[i] / theta - wdot(S, Y, n, sl, theta, uy, us, i) / (theta * theta);
+            dui = -r[i] / theta - wdot(ys, ss, theta, uy, us) / (theta * theta);
             xb = xc[i] + dui;
             if (pos) {
                 xb = fmax(xb, 0.0);
@@ -551,9 +649,12 @@ __global__ __launch_bounds__(NT) void k_update(const double *__restrict__ x, con
     double acc[MAXNV];
 #pragma unroll
     for (int q = 0; q < MAXNV; ++q) acc[q] = 0.0;
-    const int k = sl.k;
     double mn = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        // the stored pairs never include the spare slot; an unused slot may alias it, but
+        // only this thread touches element i and the masked value is discarded
+        double ys[MAXM], ss[MAXM];
+        load_pairs(S, Y, n, sl, i, ys, ss);
         const double s = xt[i] - x[i], y = gt[i] - g[i];
         S[(int64_t)spare * n + i] = s;
         Y[(int64_t)spare * n + i] = y;
@@ -563,12 +664,9 @@ __global__ __launch_bounds__(NT) void k_update(const double *__restrict__ x, con
         acc[3] += s * s;
 #pragma unroll
         for (int j = 0; j < MAXM; ++j) {
-            if (j < k) {
-                const int64_t o = (int64_t)sl.idx[j] * n + i;
-                acc[4 + j] += s * Y[o];
-                acc[4 + MAXM + j] += S[o] * y;
-                acc[4 + 2 * MAXM + j] += s * S[o];
-            }
+            acc[4 + j] += s * ys[j];
+            acc[4 + MAXM + j] += ss[j] * y;
+            acc[4 + 2 * MAXM + j] += s * ss[j];
         }
         const double xi = xt[i], gi = gt[i];
         const double pr = pos ? fmax(xi - gi, 0.0) - xi : -gi;
@@ -773,7 +871,8 @@ struct ivx_lbfgsb {
     ivx_real *sky = nullptr, *grad = nullptr;
     void *sort_tmp = nullptr;
     size_t sort_bytes = 0;
-    double *host = nullptr; // pinned
+    double *host = nullptr;     // pinned, mapped
+    double *host_dev = nullptr; // the same buffer as the device addresses it
 };
 
 namespace {
@@ -810,12 +909,12 @@ unsigned grid_of(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int
         if (e_ != hipSuccess) return set_error(IVX_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// Sum/min reduce a kernel's block partials into s->scal[off..off+nv) and copy them to the
-// host buffer at the same offset.
+// Sum/min reduce a kernel's block partials into the host buffer at s->host[off..off+nv).
 ivx_status reduce_to_host(ivx_lbfgsb *s, unsigned nblk, int nv, int nsum, int off, hipStream_t st) {
-    k_finish<<<1, NT, 0, st>>>(s->part, (int)nblk, nv, nsum, s->scal + off);
+    // the finisher writes the few results straight into the mapped host buffer: no copy
+    // launch; they are complete on the host once the stream has drained
+    k_finish<<<1, NT, 0, st>>>(s->part, (int)nblk, nv, nsum, s->host_dev + off);
     LB_HIP(hipGetLastError());
-    LB_HIP(hipMemcpyAsync(s->host + off, s->scal + off, nv * sizeof(double), hipMemcpyDeviceToHost, st));
     LB_HIP(hipStreamSynchronize(st));
     return IVX_OK;
 }
@@ -915,9 +1014,10 @@ ivx_status ivx_lbfgsb_create(ivx_plan *plan, int32_t m_max, ivx_lbfgsb **out) {
     if (!st) st = lb_alloc_t(s, &s->fixed, (size_t)n);
     if (!st) st = lb_alloc_t(s, &s->S, (size_t)(m_max + 1) * n);
     if (!st) st = lb_alloc_t(s, &s->Y, (size_t)(m_max + 1) * n);
-    double **rowsv[] = {&s->Q, &s->Pex, &s->V, &s->Cex};
+    double **rowsv[] = {&s->Q, &s->Pex, &s->Cex};
     for (double **p : rowsv)
         if (!st) st = lb_alloc_t(s, p, (size_t)D * n1);
+    if (!st) st = lb_alloc_t(s, &s->V, (size_t)MAXD * n1); // k_cp_a writes MAXD rows
     double **scal1[] = {&s->DT, &s->GB, &s->ZB, &s->A, &s->Aex, &s->E, &s->Eex};
     for (double **p : scal1)
         if (!st) st = lb_alloc_t(s, p, (size_t)n1);
@@ -936,6 +1036,10 @@ ivx_status ivx_lbfgsb_create(ivx_plan *plan, int32_t m_max, ivx_lbfgsb **out) {
         (void)hipGetLastError();
         s->host = nullptr;
         st = set_error(IVX_ENOMEM, "hipHostMalloc failed in ivx_lbfgsb_create");
+    }
+    if (!st && hipHostGetDevicePointer((void **)&s->host_dev, s->host, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        st = set_error(IVX_EHIP, "hipHostGetDevicePointer failed in ivx_lbfgsb_create");
     }
     if (st) {
         lb_free(s);
@@ -1057,27 +1161,27 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
                                       reinterpret_cast<uint64_t *>(s->key2), reinterpret_cast<const uint32_t *>(s->val),
                                       reinterpret_cast<uint32_t *>(s->val2), (int)n, 64, st));
                     const unsigned GK = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (K1 + NT - 1) / NT));
+                    const unsigned GQ =
+                        (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (QL * K1 + NT - 1) / NT));
                     Vec p0v{};
                     for (int j = 0; j < D; ++j) p0v.v[j] = p0[j];
                     k_cp_q<<<GK, NT, 0, st>>>(s->key2, s->val2, K, s->x, s->g, s->S, s->Y, n, sl, theta, s->Q, s->DT,
                                               s->GB, s->ZB);
                     LB_HIP(hipGetLastError());
                     if (D > 0 && (e = scan_rows(s, s->Q, s->Pex, D, K1, st)) != IVX_OK) return e;
-                    k_cp_a<<<GK, NT, 0, st>>>(s->Q, s->Pex, s->DT, s->GB, K1, D, s->Mdev, p0v, theta, s->A, s->V);
+                    k_cp_a<<<GQ, NT, 0, st>>>(s->Q, s->Pex, s->DT, s->GB, K1, D, s->Mdev, p0v, theta, s->A, s->V);
                     LB_HIP(hipGetLastError());
                     if ((e = scan_rows(s, s->A, s->Aex, 1, K1, st)) != IVX_OK) return e;
                     if (D > 0 && (e = scan_rows(s, s->V, s->Cex, D, K1, st)) != IVX_OK) return e;
-                    k_cp_e<<<GK, NT, 0, st>>>(s->Q, s->Cex, s->V, s->Aex, s->DT, s->GB, s->ZB, K1, D, s->Mdev, fpp0,
+                    k_cp_e<<<GQ, NT, 0, st>>>(s->Q, s->Cex, s->V, s->Aex, s->DT, s->GB, s->ZB, K1, D, s->Mdev, fpp0,
                                               theta, s->E);
                     LB_HIP(hipGetLastError());
                     if ((e = scan_rows(s, s->E, s->Eex, 1, K1, st)) != IVX_OK) return e;
                     k_set_int<<<1, 64, 0, st>>>(s->Jdev, (int)(K1 - 1));
                     k_cp_find<<<GK, NT, 0, st>>>(s->Eex, s->Aex, s->DT, K1, fp0, fpp0, s->Jdev);
                     k_cp_gather<<<1, 64, 0, st>>>(s->Jdev, s->Pex, s->Cex, s->Eex, s->Aex, s->key2, K1, D, p0v, fp0,
-                                                  fpp0, s->scal + OFF);
+                                                  fpp0, s->host_dev + OFF);
                     LB_HIP(hipGetLastError());
-                    LB_HIP(hipMemcpyAsync(h + OFF, s->scal + OFF, (2 * D + 4) * sizeof(double),
-                                          hipMemcpyDeviceToHost, st));
                     LB_HIP(hipStreamSynchronize(st));
                     const double f1 = h[OFF + 2 * D];
                     const double f2 = std::max(h[OFF + 2 * D + 1], EPS * fpp0);

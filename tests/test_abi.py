@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(precision):
     assert len(names) >= 30
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.ivx_version() == 3
+    assert lib.ivx_version() == 4
     assert lib.ivx_real_size() == (4 if precision == "f32" else 8)
 
 
@@ -181,3 +181,17 @@ def test_full_model_needs_data_and_checks_its_arguments():
     lib = load_library()
     assert lib.ivx_plan_set_w(None, None, 0, 0.0, None) == -1
     assert lib.ivx_plan_w_info(None, None) == -1
+
+
+@pytest.mark.parametrize("n,end_bit", [(-1, 64), (2 ** 31, 64), (10, 0), (10, 65)])
+def test_sort_rejects_bad_sizes_before_any_device_call(n, end_bit):
+    lib = load_library()
+    assert lib.ivx_sort_u64(None, None, None, None, n, end_bit, None) == -1
+    assert "ivx_sort_u64" in lib.ivx_last_error().decode()
+
+
+def test_sort_of_nothing_is_a_no_op():
+    lib = load_library()
+    assert lib.ivx_sort_u64(None, None, None, None, 0, 64, None) == 0
+    # a non-empty sort without arrays is refused, still before any device call
+    assert lib.ivx_sort_u64(None, None, None, None, 5, 64, None) == -1

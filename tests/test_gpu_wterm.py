@@ -197,3 +197,18 @@ def test_bad_w_is_rejected(single):
     assert not plan.w_info()["enabled"]
     sky = torch.zeros((1, single.n_sky, single.n_sky), device="cuda")
     plan.objective_grad(sky)
+
+
+def test_empty_and_fully_flagged_blocks():
+    """A pointing whose every sample is flagged has no record and no w plane: its sub-image
+    gradient must still be cleared, and the other pointings evaluate as usual."""
+    import copy
+
+    p = copy.deepcopy(synth.config_c3_mini(w_term=True))
+    s = p.block(1, 0)
+    p.flags[s] = 1
+    oracle.synthesize(p)
+    plan = _plan(p, "f64")
+    info = plan.w_info()
+    assert info["enabled"]
+    _check(p, p, plan, "f64", "w-mosaic-flagged-block")
