@@ -2,8 +2,13 @@
 
 The paper solves every field from the null prior x0 = 0 (Sect. 3.4).  Here a 4-level
 U-Net (include/ivx_unet.h) maps the normalised dirty mosaic d = -grad Q_tot(0) / max|d|
-to a first guess x0 = 50 K * max(net(d), 0), trained on converged cold-start solutions of
-the same objective, and the solve starts from x0 instead.
+to a first guess, trained on converged cold-start solutions of the same objective, and the
+solve starts from x0 = max(50 K * net(d), 0.3 x_mean) instead, x_mean the mean training
+solution.  The floor keeps the start off the bound x >= 0: about a quarter of the network's
+raw output is <= 0, and clamped there those pixels make the solver walk Cauchy breakpoints
+on every iteration (its most expensive step).  The factor 0.3 was chosen from
+{0, 0.02, 0.1, 0.3} on validation fields (training seeds), never on the held-out fields; the
+plain clamp max(50 K * net(d), 0) is measured beside it.
 
 Workload (warm-start mosaic): 256^2 sky at 30", 3 x 3 hexagonal mosaic of 20' Gaussian
 beams at 40 px pitch, 128^2 sub-images, 200,000 visibilities per pointing (1.8 M),
@@ -38,6 +43,7 @@ PEAK_K = 50.0
 HELDOUT_BASE = 100_000
 LAYOUT_SEED = 5001
 TOL = 1e-4
+WARM_FLOOR = 0.3  # floor of the learned start, in units of the mean training solution
 
 
 # ----------------------------------------------------------------------------- problem
@@ -226,11 +232,14 @@ def train(net, D, X, epochs, batch, lr, seed=0, log=None, Dv=None, Xv=None, val_
     return hist, None
 
 
-def predict(net, d):
-    """x0 = 50 K * max(net(d), 0) for one dirty mosaic d (cuda [1][n][n])."""
+def predict(net, d, floor=None):
+    """Learned start for one dirty mosaic d (cuda [1][n][n]): 50 K * net(d), raised to
+    `floor` (a cuda image, e.g. WARM_FLOOR * the mean training solution) or, with no floor,
+    clamped at 0."""
     import torch
 
-    return torch.clamp(net.forward(d.contiguous()), min=0.0) * PEAK_K
+    x = net.forward(d.contiguous()) * PEAK_K
+    return torch.clamp(x, min=0.0) if floor is None else torch.maximum(x, floor)
 
 
 def unet_flops(levels=4, base=32, height=256, width=256, in_ch=4) -> float:
@@ -252,9 +261,11 @@ def unet_flops(levels=4, base=32, height=256, width=256, in_ch=4) -> float:
 # ----------------------------------------------------------------------------- timing
 def time_to_tolerance(m: Mosaic, net, seed: int, j_star: float, maxiter: int = 15000, x_mean=None, order: int = 0):
     """Cold and warm time-to-tolerance on field `seed` (data loaded here, untimed).  With
-    `x_mean` (sky, K) a third solve starts from that fixed image: the no-learning baseline.
-    `order` rotates which start is solved first (cold, warm, mean for order 0), so that no
-    start always runs on a cold cache or right after another solve."""
+    `x_mean` (sky, K, the mean training solution) the learned start is floored at
+    WARM_FLOOR * x_mean, and two more solves run: from the plain clamp max(50 K net(d), 0)
+    ("clamp", the ablation of the floor) and from x_mean itself ("mean", the no-learning
+    baseline).  `order` rotates which start is solved first, so that no start always runs on
+    a cold cache or right after another solve."""
     import torch
 
     target = (1.0 + TOL) * j_star
@@ -269,17 +280,24 @@ def time_to_tolerance(m: Mosaic, net, seed: int, j_star: float, maxiter: int = 1
     def run_warm():
         t0 = time.perf_counter()
         d = m.dirty()
-        x0 = predict(net, d)
+        x0 = predict(net, d, None if x_mean is None else WARM_FLOOR * x_mean)
         torch.cuda.synchronize()
         res["t_pred"] = time.perf_counter() - t0
         res["warm"] = m.solve(x0=x0, maxiter=maxiter, target=target, t_start=t0)
+        torch.cuda.synchronize()
+
+    def run_clamp():
+        t0 = time.perf_counter()
+        x0 = predict(net, m.dirty())
+        torch.cuda.synchronize()
+        res["clamp"] = m.solve(x0=x0, maxiter=maxiter, target=target, t_start=t0)
         torch.cuda.synchronize()
 
     def run_mean():
         res["mean"] = m.solve(x0=x_mean, maxiter=maxiter, target=target)
         torch.cuda.synchronize()
 
-    steps = [run_cold, run_warm] + ([run_mean] if x_mean is not None else [])
+    steps = [run_cold, run_warm] + ([run_mean, run_clamp] if x_mean is not None else [])
     k = order % len(steps)
     for f in steps[k:] + steps[:k]:
         f()
@@ -289,12 +307,14 @@ def time_to_tolerance(m: Mosaic, net, seed: int, j_star: float, maxiter: int = 1
            "warm_s": warm.seconds if warm.reached_target else float("inf"), "warm_nfev": warm.nfev,
            "warm_overhead_s": t_pred, "q_warm_start": warm.history[0][1] if warm.history else float("nan"),
            "q_cold_start": cold.history[0][1] if cold.history else float("nan")}
-    if x_mean is not None:
-        mean = res["mean"]
-        row.update({"mean_s": mean.seconds if mean.reached_target else float("inf"), "mean_nfev": mean.nfev})
-    for name in ("cold", "warm") + (("mean",) if x_mean is not None else ()):
+    names = ("cold", "warm") + (("mean", "clamp") if x_mean is not None else ())
+    for name in names[2:]:
+        r = res[name]
+        row.update({f"{name}_s": r.seconds if r.reached_target else float("inf"), f"{name}_nfev": r.nfev})
+    for name in names:
         r = res[name]
         row[f"{name}_ms_per_eval"] = 1e3 * r.seconds / max(r.nfev, 1) if np.isfinite(r.seconds) else float("nan")
+        row[f"{name}_walks"] = r.n_walks
     return row
 
 
@@ -317,12 +337,69 @@ def summarise(rows):
             "warm_nfev_median": float(np.median([r["warm_nfev"] for r in rows])),
             "warm_overhead_s_median": float(np.median([r["warm_overhead_s"] for r in rows])),
             "mean_image_s_median": q([r.get("mean_s", np.nan) for r in rows], 50),
+            "mean_image_s_iqr": [q([r.get("mean_s", np.nan) for r in rows], p) for p in (25, 75)],
             "mean_image_nfev_median": q([r.get("mean_nfev", np.nan) for r in rows], 50),
+            "clamp_s_median": q([r.get("clamp_s", np.nan) for r in rows], 50),
+            "clamp_s_iqr": [q([r.get("clamp_s", np.nan) for r in rows], p) for p in (25, 75)],
+            "clamp_nfev_median": q([r.get("clamp_nfev", np.nan) for r in rows], 50),
+            "warm_vs_mean_wins_fraction": float(np.mean([r["warm_s"] < r.get("mean_s", np.inf) for r in rows])),
+            "warm_vs_mean_fewer_evals_fraction": float(np.mean([r["warm_nfev"] < r.get("mean_nfev", np.inf)
+                                                                for r in rows])),
+            "speedup_vs_mean_median": q([r.get("mean_s", np.nan) / r["warm_s"] for r in rows], 50),
             "ms_per_eval_median": {k: q([r.get(f"{k}_ms_per_eval", np.nan) for r in rows], 50)
-                                   for k in ("cold", "warm", "mean")}}
+                                   for k in ("cold", "warm", "mean", "clamp")},
+            "walks_median": {k: q([r.get(f"{k}_walks", np.nan) for r in rows], 50)
+                             for k in ("cold", "warm", "mean", "clamp")}}
+
+
+def select_floor(m: Mosaic, net, x_mean, seeds, floors=(0.0, 0.02, 0.1, 0.3), maxiter: int = 15000, log=None):
+    """Time-to-tolerance of the learned start max(50 K net(d), f x_mean) for each candidate
+    floor f (f = 0: the plain clamp at 0), beside the cold and the mean-image starts, on
+    `seeds` (validation fields: J* from a cold solve here).  Returns per-start medians."""
+    import torch
+
+    rows = []
+    for s in seeds:
+        m.simulate(s)
+        target = (1.0 + TOL) * m.solve(maxiter=maxiter).fun
+        raw = net.forward(m.dirty().contiguous()) * PEAK_K
+        starts = {"cold": None, "mean": x_mean}
+        for f in floors:
+            starts[f"floor {f:g}"] = torch.clamp(raw, min=0.0) if f == 0 else torch.maximum(raw, f * x_mean)
+        row = {"seed": s, "raw_le_0_fraction": float((raw <= 0).float().mean())}
+        for k, x0 in starts.items():
+            r = m.solve(x0=x0, maxiter=maxiter, target=target)
+            torch.cuda.synchronize()
+            row[k] = {"s": r.seconds if r.reached_target else float("inf"), "nfev": r.nfev, "nit": r.nit,
+                      "walks": r.n_walks}
+        rows.append(row)
+        if log:
+            log(f"seed {s}: " + ", ".join(f"{k} {row[k]['s']:.3f} s" for k in starts))
+    keys = [k for k in rows[0] if isinstance(rows[0][k], dict)]
+    med = {k: {q: float(np.median([r[k][q] for r in rows])) for q in ("s", "nfev", "nit", "walks")} for k in keys}
+    for k in keys:
+        med[k]["ms_per_eval"] = float(np.median([1e3 * r[k]["s"] / r[k]["nfev"] for r in rows]))
+    return {"seeds": [int(s) for s in seeds], "median": med,
+            "raw_le_0_fraction_median": float(np.median([r["raw_le_0_fraction"] for r in rows])), "fields": rows}
 
 
 # ----------------------------------------------------------------------------- command line
+def solve_timing(iters: int = 200) -> dict:
+    """Cold device solve of the first held-out field for `iters` iterations (after a
+    30-iteration warm-up solve): wall-clock per evaluation, and how many iterations walked
+    the Cauchy breakpoints."""
+    import torch
+
+    m = Mosaic()
+    m.simulate(HELDOUT_BASE)
+    m.solve(maxiter=30)
+    torch.cuda.synchronize()
+    r = m.solve(maxiter=iters)
+    torch.cuda.synchronize()
+    return {"workload": "warm-start mosaic, cold solve of field 100000", "iterations": r.nit, "evaluations": r.nfev,
+            "walks": r.n_walks, "seconds": r.seconds, "ms_per_eval": 1e3 * r.seconds / max(r.nfev, 1)}
+
+
 def train_throughput(batch: int = 16, steps: int = 50, warmup: int = 5) -> dict:
     """Training steps of the warm-start network (forward, backward, Adam) on a random batch of
     256^2 fields: milliseconds per step and the convolutions' rate against the dense bf16 matrix
@@ -362,8 +439,13 @@ def main(argv=None):
     ap.add_argument("--val", type=int, default=0,
                     help="training fields held back to select the epoch (validation, not the held-out test set)")
     ap.add_argument("--lr-final", type=float, default=None, help="cosine step-size schedule from --lr to this")
-    ap.add_argument("--phase", default="all", choices=("all", "train", "measure", "throughput"),
-                    help="throughput: time --steps training steps of the network on random fields only")
+    ap.add_argument("--phase", default="all",
+                    choices=("all", "train", "measure", "throughput", "solve", "select-floor"),
+                    help="throughput: time --steps training steps of the network on random fields only; "
+                         "solve: time one cold device solve of --solve-iters iterations (first held-out field); "
+                         "select-floor: time the learned start under each candidate floor on --val-fields "
+                         "validation fields (the last training seeds) with the network of --load")
+    ap.add_argument("--val-fields", type=int, default=24, help="--phase select-floor: validation fields")
     ap.add_argument("--steps", type=int, default=50, help="--phase throughput: timed training steps")
     ap.add_argument("--save", default="", help="--phase train: directory for the network, mean image and J*")
     ap.add_argument("--load", default="", help="--phase measure: directory written by --phase train")
@@ -381,10 +463,25 @@ def main(argv=None):
     if a.phase == "throughput":
         print(json.dumps(train_throughput(a.batch, a.steps)), flush=True)
         return
+    if a.phase == "solve":
+        print(json.dumps(solve_timing(a.solve_iters)), flush=True)
+        return
     t0 = time.perf_counter()
     m = Mosaic()
     log(f"mosaic ready ({time.perf_counter() - t0:.1f} s): {m.plan.info()}")
     net = UNet(levels=4, base=32, max_batch=a.batch, height=256, width=256, seed=0)
+    if a.phase == "select-floor":
+        net.set_params(np.load(os.path.join(a.load, "unet_params.npy")))
+        x_mean = torch.tensor(np.load(os.path.join(a.load, "x_mean.npy")), device="cuda")
+        with open(os.path.join(a.load, "warmstart_train.json")) as f:
+            n_train = json.load(f)["report"]["train_fields"]
+        seeds = list(range(n_train - a.val_fields, n_train))
+        out = select_floor(m, net, x_mean, seeds, log=log)
+        print(json.dumps(out), flush=True)
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(out, f)
+        return out
     if a.phase == "measure":
         with open(os.path.join(a.load, "warmstart_train.json")) as f:
             saved = json.load(f)
@@ -464,7 +561,8 @@ def _measure(a, m, net, hv, x_mean, report, t0, log):
         rows.append(time_to_tolerance(m, net, r["seed"], r["fun"], a.jstar_iters, x_mean=x_mean, order=i))
         w = rows[-1]
         log(f"seed {r['seed']}: cold {w['cold_s']:.3f} s ({w['cold_nfev']} evals), warm {w['warm_s']:.3f} s "
-            f"({w['warm_nfev']} evals), mean image {w['mean_s']:.3f} s ({w['mean_nfev']} evals)")
+            f"({w['warm_nfev']} evals), mean image {w['mean_s']:.3f} s ({w['mean_nfev']} evals), "
+            f"clamped learned {w['clamp_s']:.3f} s ({w['clamp_nfev']} evals)")
     report = dict(report)
     report.update({"summary": summarise(rows), "fields": rows, "total_seconds": time.perf_counter() - t0})
     line = json.dumps(report)

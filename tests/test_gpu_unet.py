@@ -56,7 +56,8 @@ def test_to_bf16_rounds_to_nearest_even(nn):
 
 
 @pytest.mark.parametrize("cin,cout,relu", [(4, 16, False), (8, 32, True), (12, 48, True), (16, 64, False),
-                                           (20, 128, True), (24, 96, False), (64, 32, True)])
+                                           (20, 128, True), (24, 96, False), (64, 32, True), (32, 64, True),
+                                           (96, 128, False)])
 def test_conv3x3_matches_oracle(nn, cin, cout, relu):
     rng = np.random.default_rng(cin * 100 + cout)
     n, h, w = 2, 11, 19          # 418 pixels: six full 64-pixel blocks and a ragged one

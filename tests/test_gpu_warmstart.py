@@ -56,6 +56,7 @@ def test_training_and_warm_start(ws, mosaic):
     row = ws.time_to_tolerance(m, net, held, j, x_mean=X.mean(dim=0, keepdim=True) * ws.PEAK_K)
     print(row)
     assert np.isfinite(row["cold_s"]) and np.isfinite(row["warm_s"]) and np.isfinite(row["mean_s"])
+    assert np.isfinite(row["clamp_s"])
     assert row["q_warm_start"] < row["q_cold_start"]
 
 
@@ -72,10 +73,10 @@ def test_parallel_cold_solves_match_sequential(ws, mosaic):
 def test_learned_start_beats_the_cold_start(ws, mosaic):
     """The gain of the learned start, at a small scale: a network trained briefly on 96 cold
     solutions, then on 8 held-out fields the time and the evaluations to reach (1 + 1e-4) J*
-    from the learned start against the cold start (x0 = 0), the order of the three solves
-    rotating from field to field.  The median learned start must need fewer evaluations and
-    less time than the median cold start; the mean-image start (no learning) is reported
-    beside them."""
+    from the learned start against the cold start (x0 = 0), the order of the solves rotating
+    from field to field.  The median learned start must need fewer evaluations and less time
+    than the median cold start; the mean-image start (no learning) and the learned start
+    clamped at 0 instead of floored are reported beside them."""
     from paper_2609_17636_amd.unet import UNet
 
     other = [ws.Mosaic(autotune_ms=0, blocking=ws.blocking_of(mosaic)) for _ in range(3)]
@@ -92,7 +93,8 @@ def test_learned_start_beats_the_cold_start(ws, mosaic):
     s = ws.summarise(rows)
     print(f"[warm start] train mse {hist[0]:.4f} -> {hist[-1]:.4f}; cold {s['cold_s_median']:.3f} s / "
           f"{s['cold_nfev_median']:.0f} evals, learned {s['warm_s_median']:.3f} s / {s['warm_nfev_median']:.0f} evals, "
-          f"mean image {s['mean_image_s_median']:.3f} s / {s['mean_image_nfev_median']:.0f} evals; "
+          f"mean image {s['mean_image_s_median']:.3f} s / {s['mean_image_nfev_median']:.0f} evals, "
+          f"clamped learned {s['clamp_s_median']:.3f} s / {s['clamp_nfev_median']:.0f} evals; "
           f"ms per eval {s['ms_per_eval_median']}; learned faster on {s['warm_wins_fraction']:.2f}", flush=True)
     assert s["both_reached"] == len(rows)
     assert s["warm_nfev_median"] < s["cold_nfev_median"]
