@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # group) that the plan autotuner selects for each workload; fixed so that the counter
 # measurements committed beside the benchmark describe the kernel configuration it runs.
 SINGLE_BLOCKING = "8,1,256,64,1"
-MOSAIC_W_BLOCKING = "16,1,2048,16,1"     # the full model runs the vector gridder per w plane
+MOSAIC_W_BLOCKING = "10,1,2048,64,1"     # the full model's w planes on the matrix cores (W 7)
 MOSAIC_W_BLOCKING64 = (16, 1, 2048, 16, 1)
 CUBE_BLOCKING = "10,1,512,64,1"
 METRIC = "visibilities/s fwd+adjoint NUFFT; time-to-tol cold vs learned warm start"
@@ -356,7 +356,7 @@ def run_mosaic(args, w_term: bool = False):
                       + (", full model of Eq. vis (w-stacked)" if w_term else ""),
                       {"n_sky": p.n_sky}, alg, ev, None)
     if w_term:
-        out["roofline"]["kernel"] = "k_grid w-plane modes (all planes, both directions)"
+        out["roofline"]["kernel"] = (grid_kernel_name(info) + " w-plane modes (all planes, both directions)")
         out["config"]["w_planes"] = plan.w_info()
     print(f"# {m['ms']:.4f} ms/eval, grid {m['grid_ms']:.4f} ms/launch, Q_tot={m['q_tot']:.6e}", file=sys.stderr,
           flush=True)

@@ -199,6 +199,8 @@ struct ivx_plan {
     double *d_w0 = nullptr;
     int32_t *d_wnp = nullptr;
     int32_t *d_wcnt = nullptr;        // per-work-item record counts below each half plane (or NULL)
+    uint8_t *d_wsact = nullptr;       // adjoint plane pass: slot windows written (1) or skipped (0)
+    int wsact_count = 0;
     int wncnt = 0;
 };
 
@@ -269,6 +271,8 @@ void free_all(ivx_plan *p) {
     p->d_wnp = nullptr;
     p->d_wcnt = nullptr;
     p->wncnt = 0;
+    p->d_wsact = nullptr;
+    p->wsact_count = 0;
 }
 
 void free_one(ivx_plan *p, void *ptr) {
@@ -1030,6 +1034,13 @@ ivx_status w_prepare(ivx_plan *p, hipStream_t st) {
         const size_t L = (size_t)std::max<int64_t>(p->m_live, 1);
         if ((s = dalloc(p, &p->d_wz, L)) != IVX_OK || (s = dalloc(p, &p->d_wacc, L)) != IVX_OK) return s;
     }
+    if (p->n_slots != p->wsact_count) {
+        if (p->d_wsact) free_one(p, p->d_wsact);
+        p->d_wsact = nullptr;
+        p->wsact_count = 0;
+        if ((s = dalloc(p, &p->d_wsact, (size_t)std::max(p->n_slots, 1))) != IVX_OK) return s;
+        p->wsact_count = p->n_slots;
+    }
     const size_t wr = (size_t)n_items * g.nk * g.ew;
     if (wr != p->wR_count) {
         if (p->d_wR) free_one(p, p->d_wR);
@@ -1082,7 +1093,7 @@ WGeom wgeom(const ivx_plan *p) {
 
 WPlane wplane(const ivx_plan *p, int plane, bool adjoint) {
     return WPlane{p->d_wz, adjoint ? nullptr : p->d_wacc, adjoint ? p->d_wacc : nullptr, plane, p->w_W, p->w_beta,
-                  p->d_wcnt, p->wncnt};
+                  p->d_wcnt, p->wncnt, adjoint ? p->d_wsact : nullptr};
 }
 
 // Sky -> per-record sum over planes of the w-kernel-weighted plane transforms (d_wacc).
@@ -1102,7 +1113,7 @@ ivx_status w_forward_planes(ivx_plan *p, const real *sky, hipStream_t st) {
         }
         StageTimer t(p, st, IVX_STAGE_GRID);
         IVX_HIP(launch_wgrid(MODE_WFWD, g, p->d_work, p->n_work, p->d_crd, p->d_ext, p->d_slots, wplane(p, pl, false),
-                             p->nwave, st));
+                             p->nwave, p->lanes * 10 + p->vpi, p->occupancy, st));
     }
     return IVX_OK;
 }
@@ -1117,11 +1128,11 @@ ivx_status w_adjoint_planes(ivx_plan *p, hipStream_t st) {
         {
             StageTimer t(p, st, IVX_STAGE_GRID);
             IVX_HIP(launch_wgrid(MODE_WADJ, g, p->d_work, p->n_work, p->d_crd, p->d_ext, p->d_slots,
-                                 wplane(p, pl, true), p->nwave, st));
+                                 wplane(p, pl, true), p->nwave, p->lanes * 10 + p->vpi, p->occupancy, st));
         }
         {
             StageTimer t(p, st, IVX_STAGE_FOLD);
-            IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, st));
+            IVX_HIP(launch_fold(g, p->d_tslot, p->d_slots, p->d_ext, st, p->d_wsact));
         }
         {
             StageTimer t(p, st, IVX_STAGE_COL_INV);

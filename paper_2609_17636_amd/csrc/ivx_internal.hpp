@@ -96,6 +96,9 @@ struct WPlane {
     // = records of work item wid with zeta < h / 2, h = 0 .. ncnt - 1 (NULL: binary searches)
     const int32_t *cnt;
     int ncnt;
+    // adjoint pass: per slot, 1 if its work item has records near the plane (window written),
+    // 0 if not (window left as it was: the fold skips it); NULL: every window is written
+    uint8_t *sact;
 };
 
 // Sky pass tiling: blocks of SKY_T x SKY_T pixels, 256 threads, thread t at row t / SKY_T,
@@ -119,7 +122,10 @@ hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work
                        int occupancy, hipStream_t st, bool unweighted = false);
 // adjoint extended grid: the windows summed into `ext` (the forward extended grid, which
 // the gridding pass has consumed by then)
-hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, hipStream_t st);
+// sact (may be NULL: every slot counts) flags the slots whose windows were written; the others
+// are skipped, which adds nothing to any cell (the sums are those of the written windows)
+hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, hipStream_t st,
+                       const uint8_t *sact = nullptr);
 // inverse column FFT of the symmetrised half plane, folded from the adjoint extended grid
 hipError_t launch_col_inv(const Geom &g, const cpx *E, const cpx *tw, cpx *R, hipStream_t st);
 // The slot fold and the inverse column pass in one kernel (no extended grid written); only for
@@ -251,11 +257,14 @@ hipError_t launch_wout(const WorkItem *work, int n_work, const WGeom &wg, const 
 hipError_t launch_win(const WorkItem *work, int n_work, const WGeom &wg, const WZ *wz, const int32_t *perm,
                       const int64_t *boff, const real *wgt, bool unweighted, const cpx *in, cpx *q, hipStream_t st);
 
-// w-stacked gridding pass of one plane (vector gridder, 16-lane groups, one visibility per
-// group per iteration), mode MODE_WFWD or MODE_WADJ; prepare_wgrid raises the dynamic-LDS
-// limit of both (call before any stream capture).
+// w-stacked gridding pass of one plane, mode MODE_WFWD or MODE_WADJ: on the matrix cores
+// when variant = GRID_MFMA_VARIANT (float build, windows of at most 16 x 16 cells; occupancy
+// as for launch_grid), else the vector gridder (16-lane groups, one visibility per group per
+// iteration, nwave waves per work item); prepare_wgrid raises the vector gridder's
+// dynamic-LDS limit (call before any stream capture).
 hipError_t launch_wgrid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
-                        const cpx *ext, cpx *slots, const WPlane &wp, int nwave, hipStream_t st);
+                        const cpx *ext, cpx *slots, const WPlane &wp, int nwave, int variant, int occupancy,
+                        hipStream_t st);
 hipError_t prepare_wgrid(const Geom &g, int nwave);
 
 // Gridding on the matrix cores (float build, windows of at most 16 x 16 cells, one wave

@@ -209,6 +209,7 @@ struct GridArgs {
     real wbeta2; // w kernel shape, scaled like beta2 below
     const int32_t *wcnt; // record counts below each half plane per work item, or NULL
     int wncnt;
+    uint8_t *wsact;      // adjoint plane pass: slot written (1) or skipped (0), or NULL
 };
 
 // Signed distance, in planes, of a record's w from plane p.
@@ -358,8 +359,9 @@ __global__ __launch_bounds__(NT) void k_grid(GridArgs a) {
             base = wz_lower(z, wi.count, h0);
             cnt = wz_lower(z, wi.count, h1) - base;
         }
+        if (MODE == MODE_WADJ && a.wsact && tid == 0) a.wsact[wi.slot] = cnt > 0 ? 1 : 0;
         if (cnt == 0) {
-            if (MODE == MODE_WADJ) {
+            if (MODE == MODE_WADJ && !a.wsact) {
                 cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride;
                 for (int e = tid; e < win * win; e += blockDim.x) Sl[e] = cpx{0, 0};
             }
@@ -663,6 +665,10 @@ __device__ __forceinline__ float row_sum4(float x) {
 // per-lane width tests); KW = 0 reads it from the geometry.  OCC is the occupancy the
 // register allocation aims for: 7 waves per SIMD (72 VGPRs) pays on launches of many work
 // items, 6 (a freer schedule) on launches that fill the chip about once.
+// The w-plane modes of the full model take, as the vector gridder's do, the plane's range of
+// the work item's records (sorted by plane coordinate) and weigh each record by its w kernel
+// at the plane: MODE_WFWD adds w_p V_m to the record's accumulator, MODE_WADJ spreads
+// w_p q_m (q the record's adjoint coefficient).
 template <int MODE, int KW, int OCC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_gridmx(GridArgs a) {
     __shared__ float PX[16 * MX_LD], PY[16 * MX_LD];
@@ -674,14 +680,42 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
     const Geom &g = a.g;
     const int l = threadIdx.x, c16 = l & 15, g4 = l >> 4;
     const int W = KW > 0 ? KW : g.W, win = g.win;
-    constexpr bool SPREAD = MODE == MODE_OBJ || MODE == MODE_ADJ;
+    constexpr bool WPL = MODE == MODE_WFWD || MODE == MODE_WADJ; // one w plane of the full model
+    constexpr bool NOGRID = MODE == MODE_ADJ || MODE == MODE_WADJ; // the grid window is not read
+    constexpr bool SPREAD = MODE == MODE_OBJ || MODE == MODE_ADJ || MODE == MODE_WADJ;
     constexpr bool DATA = MODE == MODE_OBJ || MODE == MODE_VAL; // residual against the data
+    // the records of this work item that the pass takes: all, or the plane's range
+    int base = 0, n = wi.count;
+    if constexpr (WPL) {
+        const int h0 = 2 * a.wplane - a.wW, h1 = 2 * a.wplane + a.wW;
+        if (a.wcnt) {
+            const int32_t *c = a.wcnt + wid * (int64_t)a.wncnt;
+            base = h0 <= 0 ? 0 : (h0 >= a.wncnt ? wi.count : c[h0]);
+            n = (h1 <= 0 ? 0 : (h1 >= a.wncnt ? wi.count : c[h1])) - base;
+        } else {
+            const WZ *z = a.wz + wi.begin;
+            base = wz_lower(z, wi.count, h0);
+            n = wz_lower(z, wi.count, h1) - base;
+        }
+        if (MODE == MODE_WADJ && a.wsact && l == 0) a.wsact[wi.slot] = n > 0 ? 1 : 0;
+        if (n == 0) { // (uniform over the wave) no record near the plane: no window, or a zero one
+            if (MODE == MODE_WADJ && !a.wsact) {
+                cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 4 * g4 + v;
+                    if (r < win && c16 < win) Sl[c16 * win + r] = cpx{0.f, 0.f};
+                }
+            }
+            return;
+        }
+    }
     const float zoff = 0.5f * (float)W - 1.f;
     const float inv_hw = 2.f / (float)W;
     const float beta2 = g.beta * 1.4426950408889634f;
     // window F[a][b] (tile rows a, columns b), lane holds F[c16][4 i + g4]
     float fr[4] = {0.f, 0.f, 0.f, 0.f}, fi[4] = {0.f, 0.f, 0.f, 0.f};
-    if (MODE != MODE_ADJ) {
+    if (!NOGRID) {
         const cpx *F = a.ext + (int64_t)wi.item * g.ext_stride + (int64_t)(wi.tx * g.T) * g.eh + wi.ty * g.T;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -695,11 +729,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
     }
     f32x4 hre = {0.f, 0.f, 0.f, 0.f}, him = {0.f, 0.f, 0.f, 0.f};
     float jacc = 0.f;
-    const int n = wi.count;
-    const VisCoord *crd = a.crd + wi.begin;
+    const VisCoord *crd = a.crd + wi.begin + base;
     const cpx *vis = a.vis + wi.begin;
     const real *wgt = a.wgt + wi.begin;
     const int32_t *perm = a.perm + wi.begin;
+    const WZ *wzp = WPL ? a.wz + wi.begin + base : nullptr;
+    cpx *wacc = MODE == MODE_WFWD ? a.wacc + wi.begin + base : nullptr;
+    const cpx *wq = MODE == MODE_WADJ ? a.wq + wi.begin + base : nullptr;
+    const float inv_hww = WPL ? 2.f / (float)a.wW : 0.f;
     cpx *caller_out = nullptr;
     const cpx *caller_in = nullptr;
     if (MODE == MODE_FWD) caller_out = a.caller_out + a.boff[wi.item];
@@ -721,6 +758,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
         if (DATA) { r.y = vis[vi]; r.w = wgt[vi]; }
         if (MODE == MODE_ADJ) { r.w = a.unweighted ? 1.f : wgt[vi]; r.p = perm[vi]; }
         if (MODE == MODE_FWD) r.p = perm[vi];
+        if constexpr (WPL) {
+            // w carries the record's w-kernel weight at this plane, y its coefficient
+            r.w = es_kernel(wz_dist(wzp[vi], a.wplane), inv_hww, a.wbeta2);
+            if (MODE == MODE_WADJ) r.y = wq[vi];
+        }
     };
     auto batch = [&](const MxRec &r, int v0) {
         const bool ok = l < 16 && v0 + c16 < n;
@@ -733,6 +775,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
             }
             WRr[l] = yr;
             WRi[l] = yi;
+        }
+        if (MODE == MODE_WADJ && l < 16) {
+            WRr[l] = ok ? r.w * r.y.re : 0.f;
+            WRi[l] = ok ? r.w * r.y.im : 0.f;
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -761,7 +807,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
             }
         }
         wave_sync();
-        if (MODE != MODE_ADJ) {
+        if (!NOGRID) {
             f32x4 qre = {0.f, 0.f, 0.f, 0.f}, qim = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -781,6 +827,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
             // every lane now holds V of visibility c16 of the batch
             if (MODE == MODE_FWD) {
                 if (ok) caller_out[r.p < 0 ? ~r.p : r.p] = cpx{vr, r.p < 0 ? -vi : vi};
+                wave_sync();
+                return;
+            }
+            if (MODE == MODE_WFWD) {
+                // planes run as successive launches and a record belongs to one work item: a
+                // plain read-modify-write, in plane order
+                if (l < 16 && ok) {
+                    cpx ov = wacc[v0 + c16];
+                    ov.re += r.w * vr;
+                    ov.im += r.w * vi;
+                    wacc[v0 + c16] = ov;
+                }
                 wave_sync();
                 return;
             }
@@ -814,7 +872,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
         fetch(ra, v0 + 32);
         batch(rb, v0 + 16);
     }
-    if (MODE == MODE_FWD) return;
+    if (MODE == MODE_FWD || MODE == MODE_WFWD) return;
     if (SPREAD) {
         cpx *Sl = a.slots + (int64_t)wi.slot * g.win_stride; // column-major window
 #pragma unroll
@@ -845,7 +903,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, 8))) vo
 constexpr int FOLD_LOADS = 8; // slot loads per thread in flight in k_ext_sum
 
 __global__ __launch_bounds__(NT) void k_ext_sum(Geom g, int tiles_per_block, const int32_t *__restrict__ tslot,
-                                                const cpx *__restrict__ slots, cpx *__restrict__ E) {
+                                                const cpx *__restrict__ slots, const uint8_t *__restrict__ sact,
+                                                cpx *__restrict__ E) {
     const int item = blockIdx.y;
     const int T = g.T, win = g.win, TT = T * T;
     const int nvx = g.ntx + 1, nvt = (g.nty + 1) * nvx;
@@ -886,18 +945,33 @@ __global__ __launch_bounds__(NT) void k_ext_sum(Geom g, int tiles_per_block, con
         real sr = real(0), si = real(0);
         for (int i0 = 0; i0 < p[4]; i0 += FOLD_LOADS) {
             cpx h[FOLD_LOADS];
+            int sl[FOLD_LOADS], oo[FOLD_LOADS];
+            bool on[FOLD_LOADS];
 #pragma unroll
             for (int u = 0; u < FOLD_LOADS; ++u) {
                 const int i = i0 + u;
                 const int q = (i >= p[1]) + (i >= p[2]) + (i >= p[3]);
                 const int pq = q == 0 ? p[0] : q == 1 ? p[1] : q == 2 ? p[2] : p[3];
                 const int lo = q == 0 ? s_lo[0] : q == 1 ? s_lo[1] : q == 2 ? s_lo[2] : s_lo[3];
-                const int oq = q == 0 ? off[0] : q == 1 ? off[1] : q == 2 ? off[2] : off[3];
-                if (i < p[4]) h[u] = slots[(int64_t)(lo + i - pq) * g.win_stride + oq];
+                oo[u] = q == 0 ? off[0] : q == 1 ? off[1] : q == 2 ? off[2] : off[3];
+                sl[u] = lo + i - pq;
+                on[u] = i < p[4];
+            }
+            // the flags and the windows of the batch are requested together (one memory latency
+            // per batch, not two); a window that was not written this pass may hold anything and
+            // is dropped by the select, never added
+            uint8_t f[FOLD_LOADS];
+#pragma unroll
+            for (int u = 0; u < FOLD_LOADS; ++u) {
+                f[u] = 1;
+                if (on[u]) {
+                    if (sact) f[u] = sact[sl[u]];
+                    h[u] = slots[(int64_t)sl[u] * g.win_stride + oo[u]];
+                }
             }
 #pragma unroll
             for (int u = 0; u < FOLD_LOADS; ++u) {
-                if (i0 + u < p[4]) {
+                if (on[u] && f[u]) {
                     sr += h[u].re;
                     si += h[u].im;
                 }
@@ -1745,10 +1819,11 @@ hipError_t launch_col_inv_slots(const Geom &g, const int32_t *tslot, const cpx *
     return hipGetLastError();
 }
 
-hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, hipStream_t st) {
+hipError_t launch_fold(const Geom &g, const int32_t *tslot, const cpx *slots, cpx *ext, hipStream_t st,
+                       const uint8_t *sact) {
     const int tpb = g.T * g.T >= NT ? 1 : NT / (g.T * g.T);
     const int nvt = (g.nty + 1) * (g.ntx + 1);
-    k_ext_sum<<<dim3((unsigned)((nvt + tpb - 1) / tpb), n_items(g)), NT, 0, st>>>(g, tpb, tslot, slots, ext);
+    k_ext_sum<<<dim3((unsigned)((nvt + tpb - 1) / tpb), n_items(g)), NT, 0, st>>>(g, tpb, tslot, slots, sact, ext);
     return hipGetLastError();
 }
 
@@ -1833,6 +1908,29 @@ static hipError_t dispatch(bool prepare, int variant, int mode, const GridArgs &
     }
 }
 
+#ifndef IVX_REAL_DOUBLE
+template <int KW, int OCC> void launch_gridmx_occ(int mode, dim3 grid, const GridArgs &a, hipStream_t st) {
+    switch (mode) {
+    case MODE_OBJ: k_gridmx<MODE_OBJ, KW, OCC><<<grid, 64, 0, st>>>(a); break;
+    case MODE_FWD: k_gridmx<MODE_FWD, KW, OCC><<<grid, 64, 0, st>>>(a); break;
+    case MODE_VAL: k_gridmx<MODE_VAL, KW, OCC><<<grid, 64, 0, st>>>(a); break;
+    case MODE_WFWD: k_gridmx<MODE_WFWD, KW, OCC><<<grid, 64, 0, st>>>(a); break;
+    case MODE_WADJ: k_gridmx<MODE_WADJ, KW, OCC><<<grid, 64, 0, st>>>(a); break;
+    default: k_gridmx<MODE_ADJ, KW, OCC><<<grid, 64, 0, st>>>(a); break;
+    }
+}
+
+// Work items beyond which the 7-waves-per-SIMD build is used (about four rounds of waves
+// on 1,024 SIMDs).
+constexpr int64_t GRIDMX_OCC7_ITEMS = 32768;
+
+template <int KW> void launch_gridmx(int mode, dim3 grid, const GridArgs &a, int occ, hipStream_t st) {
+    if (occ == GRIDMX_OCC_AUTO) occ = a.n_work >= GRIDMX_OCC7_ITEMS ? 7 : 6;
+    if (occ == 7) launch_gridmx_occ<KW, 7>(mode, grid, a, st);
+    else launch_gridmx_occ<KW, 6>(mode, grid, a, st);
+}
+#endif
+
 // w-plane passes: 16-lane groups, one visibility per group per iteration, any kernel width.
 template <int W> static hipError_t wgrid_w(bool prepare, int mode, const GridArgs &a, int n_work, hipStream_t st) {
     const size_t wsz = (size_t)a.g.win * a.g.ldw * sizeof(cpx);
@@ -1878,10 +1976,12 @@ hipError_t prepare_wgrid(const Geom &g, int nwave) {
 }
 
 hipError_t launch_wgrid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
-                        const cpx *ext, cpx *slots, const WPlane &wp, int nwave, hipStream_t st) {
+                        const cpx *ext, cpx *slots, const WPlane &wp, int nwave, int variant, int occupancy,
+                        hipStream_t st) {
     if (mode != MODE_WFWD && mode != MODE_WADJ) return hipErrorInvalidValue;
     if (n_work <= 0) return hipSuccess;
     if (nwave < 1 || nwave > NT / 64 || wp.W < 2 || wp.W > 16) return hipErrorInvalidValue;
+    if (!(occupancy == GRIDMX_OCC_AUTO || occupancy == 6 || occupancy == 7)) return hipErrorInvalidValue;
     GridArgs a{};
     a.g = g;
     a.work = work;
@@ -1897,11 +1997,27 @@ hipError_t launch_wgrid(int mode, const Geom &g, const WorkItem *work, int n_wor
     a.wW = wp.W;
     a.wcnt = wp.cnt;
     a.wncnt = wp.ncnt;
+    a.wsact = mode == MODE_WADJ ? wp.sact : nullptr;
 #ifdef IVX_REAL_DOUBLE
     a.wbeta2 = wp.beta;
 #else
     a.wbeta2 = (real)(wp.beta * 1.4426950408889634);
 #endif
+    if (variant == GRID_MFMA_VARIANT) {
+#ifdef IVX_REAL_DOUBLE
+        return hipErrorInvalidValue;
+#else
+        if (g.win > 16) return hipErrorInvalidValue;
+        const unsigned gx = (unsigned)n_work < GRID_ROW ? (unsigned)n_work : GRID_ROW;
+        const dim3 grid(gx, (unsigned)((n_work + gx - 1) / gx));
+        switch (g.W) {
+        case 7: launch_gridmx<7>(mode, grid, a, occupancy, st); break;
+        case 8: launch_gridmx<8>(mode, grid, a, occupancy, st); break;
+        default: launch_gridmx<0>(mode, grid, a, occupancy, st); break;
+        }
+        return hipGetLastError();
+#endif
+    }
     return wgrid_dispatch(false, mode, a, n_work, st);
 }
 
@@ -1913,26 +2029,6 @@ hipError_t prepare_grid(const Geom &g, int nwave, int variant) {
     return dispatch(true, variant, MODE_OBJ, a, 0, nullptr);
 }
 
-#ifndef IVX_REAL_DOUBLE
-template <int KW, int OCC> void launch_gridmx_occ(int mode, dim3 grid, const GridArgs &a, hipStream_t st) {
-    switch (mode) {
-    case MODE_OBJ: k_gridmx<MODE_OBJ, KW, OCC><<<grid, 64, 0, st>>>(a); break;
-    case MODE_FWD: k_gridmx<MODE_FWD, KW, OCC><<<grid, 64, 0, st>>>(a); break;
-    case MODE_VAL: k_gridmx<MODE_VAL, KW, OCC><<<grid, 64, 0, st>>>(a); break;
-    default: k_gridmx<MODE_ADJ, KW, OCC><<<grid, 64, 0, st>>>(a); break;
-    }
-}
-
-// Work items beyond which the 7-waves-per-SIMD build is used (about four rounds of waves
-// on 1,024 SIMDs).
-constexpr int64_t GRIDMX_OCC7_ITEMS = 32768;
-
-template <int KW> void launch_gridmx(int mode, dim3 grid, const GridArgs &a, int occ, hipStream_t st) {
-    if (occ == GRIDMX_OCC_AUTO) occ = a.n_work >= GRIDMX_OCC7_ITEMS ? 7 : 6;
-    if (occ == 7) launch_gridmx_occ<KW, 7>(mode, grid, a, st);
-    else launch_gridmx_occ<KW, 6>(mode, grid, a, st);
-}
-#endif
 
 hipError_t launch_grid(int mode, const Geom &g, const WorkItem *work, int n_work, const VisCoord *crd,
                        const cpx *vis, const real *wgt, const int32_t *perm, const int64_t *boff, const cpx *ext,

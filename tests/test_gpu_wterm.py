@@ -20,6 +20,8 @@ pytestmark = pytest.mark.gpu
 from paper_2609_17636_amd import IvxError, Plan  # noqa: E402
 
 TOL = {"f32": 1e-5, "f64": 1e-10}
+# the matrix-core gridder's w-plane modes (float build, windows of at most 16 x 16 cells)
+MX = "matrix-core"
 
 
 def rel(a, b):
@@ -56,7 +58,10 @@ def _plan(p, precision, blocking=None, w=True, **kw):
         plan.set_cube_data(p)
     else:
         plan.set_problem_data(p)
-    if blocking is not None:
+    if blocking == MX:
+        # the matrix-core gridder: the largest tile whose window (T + W - 1) fits 16 cells
+        plan.set_blocking(17 - plan.info()["kernel_width"], 1, 512, 64, 1)
+    elif blocking is not None:
         plan.set_blocking(*blocking)
     if w:
         plan.set_w(p.w)
@@ -142,18 +147,46 @@ def test_the_w_term_is_visible_at_this_tolerance(single):
     assert abs(full["Q"] - copl["Q"]) > 1e3 * TOL["f32"] * full["Q"]
 
 
-@pytest.mark.parametrize("precision", ["f32", "f64"])
-def test_mosaic_objective(mosaic, precision):
-    plan = _plan(mosaic, precision)
-    print(f"[w-mosaic] {plan.w_info()}", flush=True)
+PLANS = [("f32", None), ("f64", None), ("f32", MX)]
+PLAN_IDS = ["f32", "f64", "f32-matrix-core"]
+
+
+@pytest.mark.parametrize("precision,blocking", PLANS, ids=PLAN_IDS)
+def test_mosaic_objective(mosaic, precision, blocking):
+    plan = _plan(mosaic, precision, blocking)
+    print(f"[w-mosaic] {plan.w_info()} {plan.info()}", flush=True)
     _check(mosaic, mosaic, plan, precision, "w-mosaic")
 
 
-@pytest.mark.parametrize("precision", ["f32", "f64"])
-def test_cube_objective_shared_uv(cube, precision):
-    plan = _plan(cube, precision)
+@pytest.mark.parametrize("precision,blocking", PLANS, ids=PLAN_IDS)
+def test_cube_objective_shared_uv(cube, precision, blocking):
+    plan = _plan(cube, precision, blocking)
     print(f"[w-cube] {plan.w_info()}", flush=True)
     _check(cube, cube.expand(), plan, precision, "w-cube")
+
+
+def test_matrix_core_forward_and_adjoint_on_the_mosaic(mosaic):
+    """Model visibilities and the adjoint image of the w-plane modes on the matrix cores,
+    element by element against the oracle's direct sums (blocks with flags, several
+    pointings)."""
+    p = mosaic
+    plan = _plan(p, "f32", MX)
+    assert plan.info()["lanes"] == 64
+    sky = torch.tensor(p.x_true, dtype=plan.torch_dtype, device="cuda")
+    got = plan.forward(sky).double().cpu().numpy()
+    got = got[:, 0] + 1j * got[:, 1]
+    want = oracle.model_vis(p, p.x_true)
+    live = p.flags == 0
+    err = np.abs(got[live] - want[live]).max() / np.abs(want[live]).max()
+    print(f"[w-mx-forward] max err / max |V| {err:.2e}", flush=True)
+    assert err <= TOL["f32"]
+    rng = np.random.default_rng(8)
+    y = (rng.normal(size=p.n_vis) + 1j * rng.normal(size=p.n_vis)) * live
+    yt = torch.tensor(np.stack([y.real, y.imag], axis=1), dtype=plan.torch_dtype, device="cuda")
+    adj = plan.adjoint(yt).double().cpu().numpy()
+    want_a = oracle.adjoint_image(p, y)
+    print(f"[w-mx-adjoint] rel {rel(adj, want_a):.2e}", flush=True)
+    assert rel(adj, want_a) <= TOL["f32"]
 
 
 def test_value_and_split_evaluations_agree(mosaic):
