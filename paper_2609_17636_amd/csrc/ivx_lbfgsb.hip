@@ -60,6 +60,8 @@ constexpr int CP_NS = 3 + 2 * MAXM;      // k_cp_init: d.d, #breakpoints, #fixed
 constexpr int UP_NS = 4 + 3 * MAXM;      // k_update: s.y, y.y, g.s, s.s, s.Y, S.y, s.S | -pg
 constexpr int SCAL = 1024;               // doubles of the device/host scalar exchange buffers
 constexpr int OFF = 8;                   // reductions land at scal[OFF..]; scal[0..4) = terms
+constexpr int PART_R = RBLK * MAXD * (MAXD + 1) / 2; // W^T r partials beside the Gram matrix's
+static_assert(OFF + MAXD + MAXD * (MAXD + 1) / 2 <= SCAL, "the subspace results fit the exchange buffer");
 
 // ---------------------------------------------------------------- reductions
 // Each thread holds nv partials: entries [0, nsum) are sums, the rest minima.  Wave
@@ -1022,7 +1024,8 @@ ivx_status ivx_lbfgsb_create(ivx_plan *plan, int32_t m_max, ivx_lbfgsb **out) {
     for (double **p : scal1)
         if (!st) st = lb_alloc_t(s, p, (size_t)n1);
     if (!st) st = lb_alloc_t(s, &s->bsum, (size_t)D * nb + 1);
-    if (!st) st = lb_alloc_t(s, &s->part, (size_t)RBLK * std::max(MAXNV, MAXD * (MAXD + 1) / 2));
+    // block partials: one reduction's rows, or the Gram matrix's followed by W^T r's (PART_R on)
+    if (!st) st = lb_alloc_t(s, &s->part, (size_t)RBLK * (MAXD * (MAXD + 1) / 2 + MAXD));
     if (!st) st = lb_alloc_t(s, &s->scal, SCAL);
     if (!st) st = lb_alloc_t(s, &s->Mdev, (size_t)MAXD * MAXD);
     if (!st) st = lb_alloc_t(s, &s->Jdev, 1);
@@ -1210,24 +1213,26 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
                     if (a < k) mcy.v[a] = v;
                     else mcs.v[a - k] = v;
                 }
+                // W^T r and the Gram matrix of the free rows are independent: both kernels and
+                // both finishers, then one wait for the host (results land side by side)
+                const int np = D * (D + 1) / 2;
                 k_ss_r<<<G, NT, 0, st>>>(s->x, s->xc, s->g, s->fixed, s->S, s->Y, n, sl, theta, mcy, mcs, s->r,
-                                         s->part);
+                                         s->part + PART_R);
+                k_ss_gram<<<G, NT, 0, st>>>(s->fixed, s->S, s->Y, n, sl, s->part);
+                k_finish<<<1, NT, 0, st>>>(s->part + PART_R, (int)G, MAXD, MAXD, s->host_dev + OFF);
+                k_finish<<<1, NT, 0, st>>>(s->part, (int)G, np, np, s->host_dev + OFF + MAXD);
                 LB_HIP(hipGetLastError());
-                if ((e = reduce_to_host(s, G, MAXD, MAXD, OFF, st)) != IVX_OK) return e;
+                LB_HIP(hipStreamSynchronize(st));
                 std::vector<double> bvec(D);
                 for (int j = 0; j < k; ++j) {
                     bvec[j] = h[OFF + j];
                     bvec[k + j] = theta * h[OFF + MAXM + j];
                 }
-                const int np = D * (D + 1) / 2;
-                k_ss_gram<<<G, NT, 0, st>>>(s->fixed, s->S, s->Y, n, sl, s->part);
-                LB_HIP(hipGetLastError());
-                if ((e = reduce_to_host(s, G, np, np, OFF, st)) != IVX_OK) return e;
                 std::vector<double> A((size_t)D * D);
                 for (int a = 0, q = 0; a < D; ++a)
                     for (int b = a; b < D; ++b, ++q) {
                         const double sa = a < k ? 1.0 : theta, sb = b < k ? 1.0 : theta;
-                        A[a * D + b] = A[b * D + a] = sa * sb * h[OFF + q];
+                        A[a * D + b] = A[b * D + a] = sa * sb * h[OFF + MAXD + q];
                     }
                 // N u = v with N = I - M A / theta, v = M b
                 std::vector<double> N((size_t)D * D), v(D);
