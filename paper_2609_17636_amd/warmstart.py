@@ -432,7 +432,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--solve-iters", type=int, default=600, help="L-BFGS-B iterations of a training target")
+    ap.add_argument("--solve-iters", type=int, default=15000,
+                    help="iteration cap of a training target's cold solve (15000: run to the stopping rule)")
     ap.add_argument("--jstar-iters", type=int, default=15000, help="iteration cap of the J* solve")
     ap.add_argument("--out", default="", help="write the JSON report here too")
     ap.add_argument("--workers", type=int, default=8, help="host threads (plans) for the untimed cold solves")
