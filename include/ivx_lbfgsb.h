@@ -48,7 +48,9 @@ typedef struct {
     int32_t maxfun;      /* objective-evaluation cap (15000) */
     int32_t maxls;       /* evaluations per line search (20) */
     int32_t positivity;  /* 1: x >= 0 componentwise (the paper's bound); 0: unbounded (1) */
-    int32_t reserved;    /* 0 */
+    int32_t full_sort;   /* 1: every Cauchy search sorts all breakpoints; 0: first only those
+                            below a sampled threshold, in one workgroup, and all of them only
+                            when the minimiser lies beyond (same iterates either way) (0) */
     double ftol;         /* relative-reduction tolerance (2.220446049250313e-09) */
     double gtol;         /* projected-gradient infinity-norm tolerance (1e-5) */
     double target;       /* stop once f <= target; -INFINITY disables (-INFINITY) */
@@ -69,7 +71,7 @@ typedef struct {
     int64_t nit;         /* iterations */
     int64_t nfev;        /* objective evaluations */
     int32_t reason;      /* ivx_lbfgsb_reason */
-    int32_t reserved;
+    int32_t n_walks_full; /* of n_walks, those that sorted all breakpoints */
     int64_t n_walks;     /* Cauchy searches that crossed at least one breakpoint (sorted path) */
 } ivx_lbfgsb_result;
 

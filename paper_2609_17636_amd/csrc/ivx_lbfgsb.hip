@@ -60,6 +60,7 @@ constexpr int CP_NS = 3 + 2 * MAXM;      // k_cp_init: d.d, #breakpoints, #fixed
 constexpr int UP_NS = 4 + 3 * MAXM;      // k_update: s.y, y.y, g.s, s.s, s.Y, S.y, s.S | -pg
 constexpr int SCAL = 1024;               // doubles of the device/host scalar exchange buffers
 constexpr int OFF = 8;                   // reductions land at scal[OFF..]; scal[0..4) = terms
+constexpr int SEL_OUT = SCAL - 1;        // the breakpoint prefix length (k_cp_select)
 constexpr int PART_R = RBLK * MAXD * (MAXD + 1) / 2; // W^T r partials beside the Gram matrix's
 static_assert(OFF + MAXD + MAXD * (MAXD + 1) / 2 <= SCAL, "the subspace results fit the exchange buffer");
 
@@ -451,6 +452,122 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             E[j] = dt * f2 + gb * gb + theta * gb * ZB[j] - qMC;
         }
     }
+}
+
+// The breakpoints below a threshold tau, sorted, in one workgroup: exactly a prefix of the full
+// stable sort (ascending IEEE bit patterns, ties by variable index), because every breakpoint
+// below tau precedes every other one.  tau is the value of rank ~SEL_TARGET / (n / SEL_SAMPLES)
+// among SEL_SAMPLES keys at hashed positions (s * 2654435761 mod n: a fixed stride would alias
+// with the image rows), so that about SEL_TARGET breakpoints lie below it;
+// when all K finite breakpoints fit the LDS list, tau = +inf selects them all and the prefix is
+// the whole walk.  The gathered pairs arrive in any order (LDS atomic slots); each then moves
+// to its rank, the number of pairs smaller in (key, index) (unique pairs: a permutation, and no
+// dependence on the arrival order).  Counting ranks with broadcast LDS reads needs no barrier
+// between steps, unlike a sorting network.  out[0] = the prefix length, or -1 when more than
+// SEL_CAP breakpoints lie below tau.
+constexpr int SEL_NT = 1024;
+constexpr int SEL_CAP = 1024;
+constexpr int SEL_SAMPLES = 512;
+constexpr int SEL_TARGET = 192;
+constexpr uint64_t KEY_INF = 0x7FF0000000000000ull; // +inf, the key of a variable without breakpoint
+
+__global__ __launch_bounds__(SEL_NT) void k_cp_select(const uint64_t *__restrict__ key, int64_t n, int64_t K,
+                                                      uint64_t *__restrict__ skey, uint32_t *__restrict__ sidx,
+                                                      double *__restrict__ out) {
+    __shared__ uint64_t kb[SEL_CAP];
+    __shared__ uint32_t ib[SEL_CAP];
+    __shared__ int cnt;
+    __shared__ unsigned long long tau;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        tau = KEY_INF;
+        cnt = 0;
+    }
+    __syncthreads();
+    if (K > SEL_CAP) {
+        // the sample of rank r (0-based, ties by position): r + 1 rounds of a block minimum over
+        // the samples not taken yet
+        const int64_t ns = n < SEL_SAMPLES ? n : SEL_SAMPLES;
+        const int64_t stride = n / ns;
+        int64_t r = SEL_TARGET / stride;
+        r = r < 1 ? 1 : (r > ns - 1 ? ns - 1 : r);
+        uint64_t v = ~0ull;
+        if (tid < ns) v = key[(int64_t)(((uint64_t)tid * 2654435761ull) % (uint64_t)n)];
+        __shared__ uint64_t wmin[SEL_NT / 64];
+        __shared__ int wpos[SEL_NT / 64];
+        const int lane = tid & 63, wave = tid >> 6;
+        uint64_t last = ~0ull;
+        for (int64_t round = 0; round <= r; ++round) {
+            uint64_t m = v;
+            int pm = tid;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const uint64_t mo = __shfl_xor(m, o);
+                const int po = __shfl_xor(pm, o);
+                if (mo < m || (mo == m && po < pm)) {
+                    m = mo;
+                    pm = po;
+                }
+            }
+            if (lane == 0) {
+                wmin[wave] = m;
+                wpos[wave] = pm;
+            }
+            __syncthreads();
+            m = wmin[0];
+            pm = wpos[0];
+            for (int w = 1; w < SEL_NT / 64; ++w)
+                if (wmin[w] < m || (wmin[w] == m && wpos[w] < pm)) {
+                    m = wmin[w];
+                    pm = wpos[w];
+                }
+            last = m;
+            if (tid == pm) v = ~0ull; // taken
+            __syncthreads();
+        }
+        if (tid == 0) tau = last < KEY_INF ? last : KEY_INF;
+        __syncthreads();
+    }
+    const uint64_t t = tau;
+    // SEL_LOADS keys per thread requested together, then kept or passed over
+    constexpr int SEL_LOADS = 16;
+    for (int64_t i0 = 0; i0 < n; i0 += (int64_t)SEL_NT * SEL_LOADS) {
+        uint64_t kk[SEL_LOADS];
+#pragma unroll
+        for (int u = 0; u < SEL_LOADS; ++u) {
+            const int64_t i = i0 + (int64_t)u * SEL_NT + tid;
+            kk[u] = i < n ? key[i] : ~0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < SEL_LOADS; ++u) {
+            if (kk[u] < t) {
+                const int p = atomicAdd(&cnt, 1);
+                if (p < SEL_CAP) {
+                    kb[p] = kk[u];
+                    ib[p] = (uint32_t)(i0 + (int64_t)u * SEL_NT + tid);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int c = cnt;
+    if (c > SEL_CAP) { // (uniform) too many below the threshold: the caller sorts them all
+        if (tid == 0) out[0] = -1.0;
+        return;
+    }
+    for (int q = tid; q < c; q += SEL_NT) {
+        const uint64_t v = kb[q];
+        const uint32_t w = ib[q];
+        int rank = 0;
+#pragma unroll 16
+        for (int z = 0; z < c; ++z) {
+            const uint64_t u = kb[z];
+            rank += u < v || (u == v && ib[z] < w);
+        }
+        skey[rank] = v;
+        sidx[rank] = w;
+    }
+    if (tid == 0) out[0] = (double)c;
 }
 
 // first j whose segment holds the minimiser (j = K1 - 1 always qualifies)
@@ -986,7 +1103,7 @@ ivx_status ivx_lbfgsb_default_options(ivx_lbfgsb_options *o) {
     o->maxfun = 15000;
     o->maxls = 20;
     o->positivity = 1;
-    o->reserved = 0;
+    o->full_sort = 0;
     o->ftol = 2.220446049250313e-09;
     o->gtol = 1e-5;
     o->target = -INFINITY;
@@ -1076,7 +1193,7 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
     const int pos = opt.positivity ? 1 : 0;
     const auto t0 = std::chrono::steady_clock::now();
     double *h = s->host;
-    int64_t nfev = 0, nit = 0, nwalk = 0;
+    int64_t nfev = 0, nit = 0, nwalk = 0, nwalk_full = 0;
     double f = 0.0, pg = 0.0;
     int reason = IVX_LBFGSB_MAXITER;
 
@@ -1157,39 +1274,71 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
                     tc = std::max(dtm0, 0.0);
                     for (int j = 0; j < D; ++j) c[j] = tc * p0[j];
                 } else {
-                    const int64_t K = (int64_t)nbr, K1 = K + 1;
+                    const int64_t K = (int64_t)nbr;
                     ++nwalk;
-                    // breakpoints t >= 0 (or +inf): their IEEE bit patterns order as the values
-                    LB_HIP(radix_sort(s->sort_tmp, s->sort_bytes, reinterpret_cast<const uint64_t *>(s->key),
-                                      reinterpret_cast<uint64_t *>(s->key2), reinterpret_cast<const uint32_t *>(s->val),
-                                      reinterpret_cast<uint32_t *>(s->val2), (int)n, 64, st));
-                    const unsigned GK = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (K1 + NT - 1) / NT));
-                    const unsigned GQ =
-                        (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (QL * K1 + NT - 1) / NT));
                     Vec p0v{};
                     for (int j = 0; j < D; ++j) p0v.v[j] = p0[j];
-                    k_cp_q<<<GK, NT, 0, st>>>(s->key2, s->val2, K, s->x, s->g, s->S, s->Y, n, sl, theta, s->Q, s->DT,
-                                              s->GB, s->ZB);
-                    LB_HIP(hipGetLastError());
-                    if (D > 0 && (e = scan_rows(s, s->Q, s->Pex, D, K1, st)) != IVX_OK) return e;
-                    k_cp_a<<<GQ, NT, 0, st>>>(s->Q, s->Pex, s->DT, s->GB, K1, D, s->Mdev, p0v, theta, s->A, s->V);
-                    LB_HIP(hipGetLastError());
-                    if ((e = scan_rows(s, s->A, s->Aex, 1, K1, st)) != IVX_OK) return e;
-                    if (D > 0 && (e = scan_rows(s, s->V, s->Cex, D, K1, st)) != IVX_OK) return e;
-                    k_cp_e<<<GQ, NT, 0, st>>>(s->Q, s->Cex, s->V, s->Aex, s->DT, s->GB, s->ZB, K1, D, s->Mdev, fpp0,
-                                              theta, s->E);
-                    LB_HIP(hipGetLastError());
-                    if ((e = scan_rows(s, s->E, s->Eex, 1, K1, st)) != IVX_OK) return e;
-                    k_set_int<<<1, 64, 0, st>>>(s->Jdev, (int)(K1 - 1));
-                    k_cp_find<<<GK, NT, 0, st>>>(s->Eex, s->Aex, s->DT, K1, fp0, fpp0, s->Jdev);
-                    k_cp_gather<<<1, 64, 0, st>>>(s->Jdev, s->Pex, s->Cex, s->Eex, s->Aex, s->key2, K1, D, p0v, fp0,
-                                                  fpp0, s->host_dev + OFF);
+                    // the walk over the first Kw sorted breakpoints (key2 / val2), closed by a
+                    // last segment to +inf; writes J and the state at its segment
+                    int64_t J = 0;
+                    double f1 = 0.0, f2 = 0.0, told = 0.0;
+                    auto walk = [&](int64_t Kw) -> ivx_status {
+                        const int64_t K1 = Kw + 1;
+                        const unsigned GK = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (K1 + NT - 1) / NT));
+                        const unsigned GQ =
+                            (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (QL * K1 + NT - 1) / NT));
+                        ivx_status ew;
+                        k_cp_q<<<GK, NT, 0, st>>>(s->key2, s->val2, Kw, s->x, s->g, s->S, s->Y, n, sl, theta, s->Q,
+                                                  s->DT, s->GB, s->ZB);
+                        LB_HIP(hipGetLastError());
+                        if (D > 0 && (ew = scan_rows(s, s->Q, s->Pex, D, K1, st)) != IVX_OK) return ew;
+                        k_cp_a<<<GQ, NT, 0, st>>>(s->Q, s->Pex, s->DT, s->GB, K1, D, s->Mdev, p0v, theta, s->A, s->V);
+                        LB_HIP(hipGetLastError());
+                        if ((ew = scan_rows(s, s->A, s->Aex, 1, K1, st)) != IVX_OK) return ew;
+                        if (D > 0 && (ew = scan_rows(s, s->V, s->Cex, D, K1, st)) != IVX_OK) return ew;
+                        k_cp_e<<<GQ, NT, 0, st>>>(s->Q, s->Cex, s->V, s->Aex, s->DT, s->GB, s->ZB, K1, D, s->Mdev,
+                                                  fpp0, theta, s->E);
+                        LB_HIP(hipGetLastError());
+                        if ((ew = scan_rows(s, s->E, s->Eex, 1, K1, st)) != IVX_OK) return ew;
+                        k_set_int<<<1, 64, 0, st>>>(s->Jdev, (int)(K1 - 1));
+                        k_cp_find<<<GK, NT, 0, st>>>(s->Eex, s->Aex, s->DT, K1, fp0, fpp0, s->Jdev);
+                        k_cp_gather<<<1, 64, 0, st>>>(s->Jdev, s->Pex, s->Cex, s->Eex, s->Aex, s->key2, K1, D, p0v,
+                                                      fp0, fpp0, s->host_dev + OFF);
+                        LB_HIP(hipGetLastError());
+                        LB_HIP(hipStreamSynchronize(st));
+                        f1 = h[OFF + 2 * D];
+                        f2 = std::max(h[OFF + 2 * D + 1], EPS * fpp0);
+                        told = h[OFF + 2 * D + 2];
+                        J = (int64_t)h[OFF + 2 * D + 3];
+                        return IVX_OK;
+                    };
+                    // First the breakpoints below a sampled threshold, sorted in one workgroup (an
+                    // exact prefix of the full order; the minimiser usually lies within the first
+                    // few segments).  A segment found inside the prefix is the full walk's
+                    // segment; the prefix's closing segment is exact only when it holds every
+                    // breakpoint.  Otherwise (or when the prefix overflows) sort them all.
+                    bool done = false;
+                    if (!opt.full_sort) {
+                    k_cp_select<<<1, SEL_NT, 0, st>>>(reinterpret_cast<const uint64_t *>(s->key), n, K,
+                                                      reinterpret_cast<uint64_t *>(s->key2),
+                                                      reinterpret_cast<uint32_t *>(s->val2), s->host_dev + SEL_OUT);
                     LB_HIP(hipGetLastError());
                     LB_HIP(hipStreamSynchronize(st));
-                    const double f1 = h[OFF + 2 * D];
-                    const double f2 = std::max(h[OFF + 2 * D + 1], EPS * fpp0);
-                    const double told = h[OFF + 2 * D + 2];
-                    const int64_t J = (int64_t)h[OFF + 2 * D + 3];
+                    const double cs = h[SEL_OUT];
+                    if (cs >= 0.0) {
+                        const int64_t Kw = (int64_t)cs;
+                        if ((e = walk(Kw)) != IVX_OK) return e;
+                        done = J < Kw || Kw == K;
+                    }
+                    }
+                    if (!done) {
+                        ++nwalk_full;
+                        // breakpoints t >= 0 (or +inf): their IEEE bit patterns order as the values
+                        LB_HIP(radix_sort(s->sort_tmp, s->sort_bytes, reinterpret_cast<const uint64_t *>(s->key),
+                                          reinterpret_cast<uint64_t *>(s->key2), reinterpret_cast<const uint32_t *>(s->val),
+                                          reinterpret_cast<uint32_t *>(s->val2), (int)n, 64, st));
+                        if ((e = walk(K)) != IVX_OK) return e;
+                    }
                     const double dtm = std::max(-f1 / f2, 0.0);
                     tc = told + dtm;
                     for (int j = 0; j < D; ++j) c[j] = h[OFF + D + j] + dtm * h[OFF + j];
@@ -1401,7 +1550,7 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
     res->nit = nit;
     res->nfev = nfev;
     res->reason = reason;
-    res->reserved = 0;
+    res->n_walks_full = (int32_t)std::min<int64_t>(nwalk_full, INT32_MAX);
     res->n_walks = nwalk;
     return IVX_OK;
 }

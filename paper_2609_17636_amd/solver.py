@@ -84,13 +84,13 @@ def solve(plan, x0=None, maxiter=500, m=10, ftol=2.2e-9, gtol=1e-5, maxls=20, ta
 # ----------------------------------------------------------------------- device loop
 class _LbOptions(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("maxiter", ctypes.c_int32), ("maxfun", ctypes.c_int32),
-                ("maxls", ctypes.c_int32), ("positivity", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("maxls", ctypes.c_int32), ("positivity", ctypes.c_int32), ("full_sort", ctypes.c_int32),
                 ("ftol", ctypes.c_double), ("gtol", ctypes.c_double), ("target", ctypes.c_double)]
 
 
 class _LbResult(ctypes.Structure):
     _fields_ = [("f", ctypes.c_double), ("pg_norm", ctypes.c_double), ("nit", ctypes.c_int64),
-                ("nfev", ctypes.c_int64), ("reason", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("nfev", ctypes.c_int64), ("reason", ctypes.c_int32), ("n_walks_full", ctypes.c_int32),
                 ("n_walks", ctypes.c_int64)]
 
 
@@ -143,9 +143,12 @@ class DeviceSolver:
             pass
 
     def solve(self, x0=None, maxiter=15000, m=10, ftol=2.2204460492503131e-09, gtol=1e-5, maxls=20,
-              maxfun=15000, target=None, positivity=True, history=20000, stream=None, t_start=None):
+              maxfun=15000, target=None, positivity=True, history=20000, stream=None, t_start=None,
+              full_sort=False):
         """Minimise Q_tot from x0 (None: zeros; numpy or cuda tensor).  Returns a SolveResult
-        whose x is a cuda tensor [C][N][N] in the plan's precision."""
+        whose x is a cuda tensor [C][N][N] in the plan's precision.  full_sort: every Cauchy
+        search sorts all breakpoints (the default sorts a sampled prefix first; the iterates
+        are the same)."""
         import torch
 
         plan = self.plan
@@ -160,6 +163,7 @@ class DeviceSolver:
         self._check(self.lib.ivx_lbfgsb_default_options(ctypes.byref(o)))
         o.m, o.maxiter, o.maxfun, o.maxls = int(m), int(maxiter), int(maxfun), int(maxls)
         o.positivity = 1 if positivity else 0
+        o.full_sort = 1 if full_sort else 0
         o.ftol, o.gtol = float(ftol), float(gtol)
         o.target = float(target) if target is not None else float("-inf")
         fh = np.zeros(max(int(history), 0), dtype=np.float64)
@@ -180,4 +184,5 @@ class DeviceSolver:
                           seconds=time.perf_counter() - t0, history=hist, reached_target=(r.reason == 4))
         res.pg_norm = float(r.pg_norm)
         res.n_walks = int(r.n_walks)
+        res.n_walks_full = int(r.n_walks_full)
         return res

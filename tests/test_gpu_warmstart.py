@@ -99,3 +99,21 @@ def test_learned_start_beats_the_cold_start(ws, mosaic):
     assert s["both_reached"] == len(rows)
     assert s["warm_nfev_median"] < s["cold_nfev_median"]
     assert s["warm_s_median"] < s["cold_s_median"]
+
+
+def test_prefix_walk_gives_the_full_sort_iterates(ws, mosaic):
+    """The Cauchy search sorts only the breakpoints below a sampled threshold first (an exact
+    prefix of the full order) and all of them only when the minimiser lies beyond: the
+    iterates are bitwise those of sorting every breakpoint every time, on 65,536 variables
+    (tens of thousands of breakpoints per search), from a cold and from a flat start."""
+    mosaic.simulate(ws.HELDOUT_BASE + 7)
+    for x0 in (None, torch.full((1, mosaic.n, mosaic.n), 5.0, device="cuda")):
+        a = mosaic.solve(x0=x0, maxiter=150)
+        b = mosaic.solve(x0=x0, maxiter=150, full_sort=True)
+        print(f"[prefix walk] walks {a.n_walks} (full sorts {a.n_walks_full}) vs {b.n_walks} ({b.n_walks_full}); "
+              f"{1e3 * a.seconds / a.nfev:.3f} vs {1e3 * b.seconds / b.nfev:.3f} ms per evaluation", flush=True)
+        assert (a.nit, a.nfev, a.fun, a.n_walks) == (b.nit, b.nfev, b.fun, b.n_walks)
+        assert [f for _, f in a.history] == [f for _, f in b.history]
+        assert torch.equal(a.x, b.x)
+        assert b.n_walks_full == b.n_walks
+        assert a.n_walks_full < a.n_walks / 4
