@@ -50,7 +50,8 @@ typedef struct {
     int32_t positivity;  /* 1: x >= 0 componentwise (the paper's bound); 0: unbounded (1) */
     int32_t full_sort;   /* 1: every Cauchy search sorts all breakpoints; 0: first only those
                             below a sampled threshold, in one workgroup, and all of them only
-                            when the minimiser lies beyond (same iterates either way) (0) */
+                            when the minimiser lies beyond (same iterates either way; problems of
+                            more than 2^24 variables always sort all) (0) */
     double ftol;         /* relative-reduction tolerance (2.220446049250313e-09) */
     double gtol;         /* projected-gradient infinity-norm tolerance (1e-5) */
     double target;       /* stop once f <= target; -INFINITY disables (-INFINITY) */

@@ -470,6 +470,9 @@ constexpr int SEL_CAP = 1024;
 constexpr int SEL_SAMPLES = 512;
 constexpr int SEL_TARGET = 192;
 constexpr uint64_t KEY_INF = 0x7FF0000000000000ull; // +inf, the key of a variable without breakpoint
+// One workgroup reads every key: beyond this many variables the full sort's launches over the
+// whole chip cost less than that single read, and the search sorts everything at once.
+constexpr int64_t SEL_MAX_N = int64_t(1) << 24;
 
 __global__ __launch_bounds__(SEL_NT) void k_cp_select(const uint64_t *__restrict__ key, int64_t n, int64_t K,
                                                       uint64_t *__restrict__ skey, uint32_t *__restrict__ sidx,
@@ -1318,7 +1321,7 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
                     // segment; the prefix's closing segment is exact only when it holds every
                     // breakpoint.  Otherwise (or when the prefix overflows) sort them all.
                     bool done = false;
-                    if (!opt.full_sort) {
+                    if (!opt.full_sort && n <= SEL_MAX_N) {
                     k_cp_select<<<1, SEL_NT, 0, st>>>(reinterpret_cast<const uint64_t *>(s->key), n, K,
                                                       reinterpret_cast<uint64_t *>(s->key2),
                                                       reinterpret_cast<uint32_t *>(s->val2), s->host_dev + SEL_OUT);
