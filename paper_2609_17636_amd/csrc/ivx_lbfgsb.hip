@@ -360,7 +360,7 @@ __device__ __forceinline__ void load_m(const double *__restrict__ Mdev, int D, d
 // stored pairs) reads no rows at all: the arrays may not hold finite values yet.
 
 // a_j = theta g_j^2 + 2 q_j.M P_j + q_j.M q_j  and  v_j = dt_j P_j  (P_j = p0 + Pex_j)
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_cp_a(const double *__restrict__ Q, const double *__restrict__ Pex,
+__global__ __launch_bounds__(NT) void k_cp_a(const double *__restrict__ Q, const double *__restrict__ Pex,
                                              const double *__restrict__ DT, const double *__restrict__ GB, int64_t K1,
                                              int D, const double *__restrict__ Mdev, Vec p0, double theta,
                                              double *__restrict__ A, double *__restrict__ V) {
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 }
 
 // e_j = dt_j f''_j + g_j^2 + theta g_j z_j - q_j.M C_{j+1},  C_{j+1} = Cex_j + v_j
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_cp_e(const double *__restrict__ Q, const double *__restrict__ Cex,
+__global__ __launch_bounds__(NT) void k_cp_e(const double *__restrict__ Q, const double *__restrict__ Cex,
                                              const double *__restrict__ V, const double *__restrict__ Aex,
                                              const double *__restrict__ DT, const double *__restrict__ GB,
                                              const double *__restrict__ ZB, int64_t K1, int D,
