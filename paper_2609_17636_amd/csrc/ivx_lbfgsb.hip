@@ -67,22 +67,26 @@ static_assert(OFF + MAXD + MAXD * (MAXD + 1) / 2 <= SCAL, "the subspace results 
 // ---------------------------------------------------------------- reductions
 // Each thread holds nv partials: entries [0, nsum) are sums, the rest minima.  Wave
 // shuffles, then the block's waves in order, one row of `part` per block; finish_sums
-// adds the rows in block order.
+// adds the rows in block order.  The shuffle steps run over all quantities at once: the
+// exchanges of one step are independent and in flight together, where a chain per
+// quantity paid one LDS round trip per step and quantity (216 for 36 quantities).  Each
+// quantity is combined in the same order either way.  acc is overwritten.
 template <int NV>
 __device__ __forceinline__ void block_reduce(double (&acc)[NV], int nv, int nsum, double *__restrict__ part) {
     __shared__ double sh[NT / 64][NV];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        if (q < nv) {
-            double v = acc[q];
+    for (int off = 32; off >= 1; off >>= 1) {
+        double o[NV];
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double o = __shfl_xor(v, off);
-                v = q < nsum ? v + o : fmin(v, o);
-            }
-            if (lane == 0) sh[wave][q] = v;
-        }
+        for (int q = 0; q < NV; ++q) o[q] = q < nv ? __shfl_xor(acc[q], off) : 0.0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc[q] = q < nsum ? acc[q] + o[q] : fmin(acc[q], o[q]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            if (q < nv) sh[wave][q] = acc[q];
     }
     __syncthreads();
     if (threadIdx.x < nv) {
