@@ -99,29 +99,39 @@ __device__ __forceinline__ void block_reduce(double (&acc)[NV], int nv, int nsum
 
 // The rows are cut into FIN_CH consecutive chunks; thread (q, c) combines quantity q over
 // the rows of chunk c in block order, then out[q] combines the chunk results in chunk order.
-// The order is fixed (results do not depend on timing) and the loads of a chunk are
-// independent, so they are in flight together instead of one row latency after another.
+// The order is fixed (results do not depend on timing).  A chunk's rows are requested
+// FIN_U at a time with no load behind a branch (rows past the chunk read row 0 and are
+// dropped), and 1,024 threads take every (quantity, chunk) pair of the solver's largest
+// reductions in one to four rounds.
 constexpr int FIN_CH = 16;
+constexpr int FIN_NT = 1024;
+constexpr int FIN_U = 16;
 constexpr int FIN_NV = MAXNV > MAXD * (MAXD + 1) / 2 ? MAXNV : MAXD * (MAXD + 1) / 2;
 
-__global__ __launch_bounds__(NT) void k_finish(const double *__restrict__ part, int nblk, int nv, int nsum,
-                                               double *__restrict__ out) {
+__global__ __launch_bounds__(FIN_NT) void k_finish(const double *__restrict__ part, int nblk, int nv, int nsum,
+                                                   double *__restrict__ out) {
     __shared__ double sh[FIN_CH][FIN_NV];
     const int per = (nblk + FIN_CH - 1) / FIN_CH;
-    for (int e = threadIdx.x; e < nv * FIN_CH; e += NT) {
+    for (int e = threadIdx.x; e < nv * FIN_CH; e += FIN_NT) {
         const int q = e % nv, c = e / nv;
         const int b0 = c * per, b1 = min(nblk, b0 + per);
         const bool add = q < nsum;
         double v = add ? 0.0 : INF;
-#pragma unroll 8
-        for (int b = b0; b < b1; ++b) {
-            const double pv = part[(int64_t)b * nv + q];
-            v = add ? v + pv : fmin(v, pv);
+        for (int u0 = b0; u0 < b1; u0 += FIN_U) {
+            double pv[FIN_U];
+#pragma unroll
+            for (int u = 0; u < FIN_U; ++u) {
+                const int b = u0 + u;
+                pv[u] = part[(int64_t)(b < b1 ? b : 0) * nv + q];
+            }
+#pragma unroll
+            for (int u = 0; u < FIN_U; ++u)
+                if (u0 + u < b1) v = add ? v + pv[u] : fmin(v, pv[u]);
         }
         sh[c][q] = v;
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < nv; q += NT) {
+    for (int q = threadIdx.x; q < nv; q += FIN_NT) {
         double v = sh[0][q];
         for (int c = 1; c < FIN_CH; ++c) v = q < nsum ? v + sh[c][q] : fmin(v, sh[c][q]);
         out[q] = v;
@@ -466,9 +476,10 @@ __global__ __launch_bounds__(NT) void k_cp_e(const double *__restrict__ Q, const
 // when all K finite breakpoints fit the LDS list, tau = +inf selects them all and the prefix is
 // the whole walk.  The gathered pairs arrive in any order (LDS atomic slots); each then moves
 // to its rank, the number of pairs smaller in (key, index) (unique pairs: a permutation, and no
-// dependence on the arrival order).  Counting ranks with broadcast LDS reads needs no barrier
-// between steps, unlike a sorting network.  out[0] = the prefix length, or -1 when more than
-// SEL_CAP breakpoints lie below tau.
+// dependence on the arrival order).  A pair's count is split over
+// SEL_NT / c threads, each over its own run of the list, and the parts are summed with integer
+// LDS adds (exact in any order).  out[0] = the prefix length, or -1 when more than SEL_CAP
+// breakpoints lie below tau.
 constexpr int SEL_NT = 1024;
 constexpr int SEL_CAP = 1024;
 constexpr int SEL_SAMPLES = 512;
@@ -477,12 +488,14 @@ constexpr uint64_t KEY_INF = 0x7FF0000000000000ull; // +inf, the key of a variab
 // One workgroup reads every key: beyond this many variables the full sort's launches over the
 // whole chip cost less than that single read, and the search sorts everything at once.
 constexpr int64_t SEL_MAX_N = int64_t(1) << 24;
+static_assert(SEL_CAP <= SEL_NT, "one thread per gathered pair");
 
 __global__ __launch_bounds__(SEL_NT) void k_cp_select(const uint64_t *__restrict__ key, int64_t n, int64_t K,
                                                       uint64_t *__restrict__ skey, uint32_t *__restrict__ sidx,
                                                       double *__restrict__ out) {
     __shared__ uint64_t kb[SEL_CAP];
     __shared__ uint32_t ib[SEL_CAP];
+    __shared__ int rk[SEL_CAP];
     __shared__ int cnt;
     __shared__ unsigned long long tau;
     const int tid = threadIdx.x;
@@ -490,10 +503,11 @@ __global__ __launch_bounds__(SEL_NT) void k_cp_select(const uint64_t *__restrict
         tau = KEY_INF;
         cnt = 0;
     }
-    __syncthreads();
+    if (tid < SEL_CAP) rk[tid] = 0;
     if (K > SEL_CAP) {
         // the sample of rank r (0-based, ties by position): r + 1 rounds of a block minimum over
-        // the samples not taken yet
+        // the samples not taken yet (r is 1 for n = 65,536; counting every sample's rank reads
+        // ns^2 keys through LDS and was slower)
         const int64_t ns = n < SEL_SAMPLES ? n : SEL_SAMPLES;
         const int64_t stride = n / ns;
         int64_t r = SEL_TARGET / stride;
@@ -533,17 +547,20 @@ __global__ __launch_bounds__(SEL_NT) void k_cp_select(const uint64_t *__restrict
             __syncthreads();
         }
         if (tid == 0) tau = last < KEY_INF ? last : KEY_INF;
-        __syncthreads();
     }
+    __syncthreads(); // tau is set
     const uint64_t t = tau;
-    // SEL_LOADS keys per thread requested together, then kept or passed over
+    // SEL_LOADS keys per thread requested together, then kept or passed over.  Positions past
+    // the end read the last key and are masked by a select: a load behind a branch would wait
+    // for its own round trip before the next one is issued.
     constexpr int SEL_LOADS = 16;
     for (int64_t i0 = 0; i0 < n; i0 += (int64_t)SEL_NT * SEL_LOADS) {
         uint64_t kk[SEL_LOADS];
 #pragma unroll
         for (int u = 0; u < SEL_LOADS; ++u) {
             const int64_t i = i0 + (int64_t)u * SEL_NT + tid;
-            kk[u] = i < n ? key[i] : ~0ull;
+            const uint64_t kv = key[i < n ? i : n - 1];
+            kk[u] = i < n ? kv : ~0ull;
         }
 #pragma unroll
         for (int u = 0; u < SEL_LOADS; ++u) {
@@ -562,17 +579,28 @@ __global__ __launch_bounds__(SEL_NT) void k_cp_select(const uint64_t *__restrict
         if (tid == 0) out[0] = -1.0;
         return;
     }
-    for (int q = tid; q < c; q += SEL_NT) {
-        const uint64_t v = kb[q];
-        const uint32_t w = ib[q];
-        int rank = 0;
-#pragma unroll 16
-        for (int z = 0; z < c; ++z) {
-            const uint64_t u = kb[z];
-            rank += u < v || (u == v && ib[z] < w);
+    if (c > 0) {
+        const int P = SEL_NT / c; // >= 1 since c <= SEL_CAP <= SEL_NT
+        if (tid < P * c) {
+            const int q = tid % c, part = tid / c;
+            const int z0 = (int)((int64_t)c * part / P), z1 = (int)((int64_t)c * (part + 1) / P);
+            const uint64_t v = kb[q];
+            const uint32_t w = ib[q];
+            int below = 0;
+#pragma unroll 8
+            for (int z = z0; z < z1; ++z) {
+                const uint64_t u = kb[z];
+                const uint32_t iz = ib[z];
+                below += (int)(u < v) | ((int)(u == v) & (int)(iz < w));
+            }
+            atomicAdd(&rk[q], below);
         }
-        skey[rank] = v;
-        sidx[rank] = w;
+        __syncthreads();
+        if (tid < c) {
+            const int rank = rk[tid];
+            skey[rank] = kb[tid];
+            sidx[rank] = ib[tid];
+        }
     }
     if (tid == 0) out[0] = (double)c;
 }
@@ -678,20 +706,25 @@ __global__ __launch_bounds__(NT) void k_ss_gram(const uint8_t *__restrict__ fixe
     __syncthreads(); // slot[] is read by every thread below
     for (int64_t r0 = (int64_t)blockIdx.x * GCH; r0 < n; r0 += (int64_t)gridDim.x * GCH) {
         // stage 64 rows x D columns: all of a thread's loads first (out-of-range entries read
-        // row 0 of slot 0 and are masked), then the LDS stores
+        // row 0 and are masked), then the LDS stores.  A thread's row is the same at every
+        // step (NT is a multiple of GCH), so its flag byte is read once.
         constexpr int GIT = GCH * MAXD / NT;
+        static_assert(NT % GCH == 0, "one row per thread across the staging steps");
+        const int64_t i = r0 + threadIdx.x % GCH;
+        const int64_t ic = i < n ? i : 0;
+        const uint8_t fx = fixed[ic];
         double v[GIT];
 #pragma unroll
         for (int it = 0; it < GIT; ++it) {
-            const int e = threadIdx.x + it * NT;
-            const int rr = e % GCH, c = e / GCH;
-            const int64_t i = r0 + rr;
-            const bool on = c < D && i < n;
-            const int64_t ic = on ? i : 0;
+            const int c = (threadIdx.x + it * NT) / GCH;
             const int sj = c < k ? slot[c] : slot[min(c - k, MAXM - 1)];
-            const double val = (c < k ? Y : S)[(int64_t)sj * n + ic];
-            const uint8_t fx = fixed[ic];
-            v[it] = (on && !fx) ? val : 0.0;
+            v[it] = (c < k ? Y : S)[(int64_t)sj * n + ic];
+        }
+        const bool live = i < n && !fx;
+#pragma unroll
+        for (int it = 0; it < GIT; ++it) {
+            const int c = (threadIdx.x + it * NT) / GCH;
+            v[it] = (live && c < D) ? v[it] : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -726,20 +759,23 @@ __global__ __launch_bounds__(NT) void k_ss_du(const double *__restrict__ x, cons
                                               double *__restrict__ part) {
     double acc[2] = {0.0, INF};
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
-        double dui = 0.0, xb = xc[i];
+        // every load ahead of the branch (r holds 0 on the fixed rows), so none waits alone
+        const double xci = xc[i], ri = r[i], xi = x[i], gi = g[i];
+        const uint8_t fx = fixed[i];
         double ys[MAXM], ss[MAXM];
         load_pairs(S, Y, n, sl, i, ys, ss);
-        if (!fixed[i]) {
-            dui = -r[i] / theta - wdot(ys, ss, theta, uy, us) / (theta * theta);
-            xb = xc[i] + dui;
+        double dui = 0.0, xb = xci;
+        if (!fx) {
+            dui = -ri / theta - wdot(ys, ss, theta, uy, us) / (theta * theta);
+            xb = xci + dui;
             if (pos) {
                 xb = fmax(xb, 0.0);
-                if (dui < 0.0) acc[1] = fmin(acc[1], -xc[i] / dui);
+                if (dui < 0.0) acc[1] = fmin(acc[1], -xci / dui);
             }
         }
         du[i] = dui;
         xbar[i] = xb;
-        acc[0] += (xb - x[i]) * g[i];
+        acc[0] += (xb - xi) * gi;
     }
     block_reduce<2>(acc, 2, 1, part);
 }
@@ -1039,7 +1075,7 @@ unsigned grid_of(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int
 ivx_status reduce_to_host(ivx_lbfgsb *s, unsigned nblk, int nv, int nsum, int off, hipStream_t st) {
     // the finisher writes the few results straight into the mapped host buffer: no copy
     // launch; they are complete on the host once the stream has drained
-    k_finish<<<1, NT, 0, st>>>(s->part, (int)nblk, nv, nsum, s->host_dev + off);
+    k_finish<<<1, FIN_NT, 0, st>>>(s->part, (int)nblk, nv, nsum, s->host_dev + off);
     LB_HIP(hipGetLastError());
     LB_HIP(hipStreamSynchronize(st));
     return IVX_OK;
@@ -1211,7 +1247,7 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
         ivx_status e = ivx_objective_grad(s->plan, s->sky, s->grad, s->scal, st);
         if (e != IVX_OK) return e;
         k_take_grad<<<G, NT, 0, st>>>(s->grad, xcur, dvec, n, pos, gdst, s->part);
-        k_finish<<<1, NT, 0, st>>>(s->part, (int)G, 2, 1, s->scal + OFF);
+        k_finish<<<1, FIN_NT, 0, st>>>(s->part, (int)G, 2, 1, s->scal + OFF);
         LB_HIP(hipGetLastError());
         LB_HIP(hipMemcpyAsync(h, s->scal, (OFF + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
         LB_HIP(hipStreamSynchronize(st));
@@ -1375,8 +1411,8 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
                 k_ss_r<<<G, NT, 0, st>>>(s->x, s->xc, s->g, s->fixed, s->S, s->Y, n, sl, theta, mcy, mcs, s->r,
                                          s->part + PART_R);
                 k_ss_gram<<<G, NT, 0, st>>>(s->fixed, s->S, s->Y, n, sl, s->part);
-                k_finish<<<1, NT, 0, st>>>(s->part + PART_R, (int)G, MAXD, MAXD, s->host_dev + OFF);
-                k_finish<<<1, NT, 0, st>>>(s->part, (int)G, np, np, s->host_dev + OFF + MAXD);
+                k_finish<<<1, FIN_NT, 0, st>>>(s->part + PART_R, (int)G, MAXD, MAXD, s->host_dev + OFF);
+                k_finish<<<1, FIN_NT, 0, st>>>(s->part, (int)G, np, np, s->host_dev + OFF + MAXD);
                 LB_HIP(hipGetLastError());
                 LB_HIP(hipStreamSynchronize(st));
                 std::vector<double> bvec(D);
