@@ -84,7 +84,7 @@ __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ 
                                                 const cpx *__restrict__ tw, cpx *__restrict__ ext) {
     constexpr int N = 1 << LOGN;
     constexpr int MAXE = 8 * CB;
-    __shared__ cpx buf[CB * N];
+    __shared__ cpx buf[CB * N + 1]; // + a sink cell for the stores of positions past the end
     __shared__ cpx tws[tw_len<LOGN>()];
     TwStage<LOGN> twr;
     twr.fetch(tw);
@@ -119,18 +119,22 @@ __global__ __launch_bounds__(NT) void k_col_fwd(Geom g, const cpx *__restrict__ 
     __syncthreads();
     const cpx *Ri = R + (int64_t)item * g.r_stride;
     // COL_LOADS rows of the source per thread are requested before the first is stored, so
-    // that a block keeps that many loads per lane in flight instead of one
+    // that a block keeps that many loads per lane in flight instead of one.  Loads and stores
+    // are unconditional (positions past the end read element 0 and store to the sink cell):
+    // with either behind a branch the compiler waits for each load before issuing the next.
     for (int e0 = tid; e0 < nk * CB; e0 += COL_LOADS * NT) {
         cpx v[COL_LOADS];
 #pragma unroll
         for (int u = 0; u < COL_LOADS; ++u) {
             const int e = e0 + u * NT, a = e / CB, cc = e - (e / CB) * CB;
-            if (e < nk * CB && c0 + cc < g.rw) v[u] = Ri[(int64_t)a * g.rw + c0 + cc];
+            const bool ok = e < nk * CB && c0 + cc < g.rw;
+            v[u] = Ri[ok ? (int64_t)a * g.rw + c0 + cc : 0];
         }
 #pragma unroll
         for (int u = 0; u < COL_LOADS; ++u) {
             const int e = e0 + u * NT, a = e / CB, cc = e - (e / CB) * CB;
-            if (e < nk * CB && c0 + cc < g.rw) buf[((a - nk / 2) & (N - 1)) * CB + cc] = v[u];
+            const bool ok = e < nk * CB && c0 + cc < g.rw;
+            buf[ok ? ((a - nk / 2) & (N - 1)) * CB + cc : CB * N] = v[u];
         }
     }
     twr.store(tws);
@@ -1185,6 +1189,9 @@ __global__ __launch_bounds__(NT) void k_col_inv_slots(Geom g, const int32_t *__r
         const int ty = e >> 2, tx = vxa - 1 + (e & 3);
         rng[ty][e & 3] = (tx >= 0 && tx <= g.ntx) ? ts[ty * g.ntx + tx] : 0;
     }
+    // the item's first slot (a valid address for the loads of empty quadrants), if it has any
+    const int32_t s_first = ts[0];
+    const bool any_slot = ts[g.nty * g.ntx] > s_first;
     __syncthreads();
     const float inv_t = 1.0f / (float)g.T;
     for (int e0 = tid; e0 < N * CB; e0 += FOLD_CELLS * NT) {
@@ -1214,11 +1221,26 @@ __global__ __launch_bounds__(NT) void k_col_inv_slots(Geom g, const int32_t *__r
                 }
             }
         }
+        // every load unconditional (an empty quadrant reads the item's first slot and scales it
+        // by 0; a select would be turned back into a branch around the load): a load behind a
+        // branch waits for its own round trip before the next is issued
+        if (any_slot) {
 #pragma unroll
-        for (int u = 0; u < FOLD_CELLS; ++u)
+            for (int u = 0; u < FOLD_CELLS; ++u)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                first[u][q] = cnt[u][q] > 0 ? slots[(int64_t)lo[u][q] * g.win_stride + off[u][q]] : cpx{0, 0};
+                for (int q = 0; q < 4; ++q) {
+                    const bool on = cnt[u][q] > 0;
+                    const int64_t at = on ? (int64_t)lo[u][q] * g.win_stride + off[u][q] : (int64_t)s_first * g.win_stride;
+                    const cpx h = slots[at];
+                    const real keep = on ? real(1) : real(0);
+                    first[u][q] = cpx{h.re * keep, h.im * keep};
+                }
+        } else {
+#pragma unroll
+            for (int u = 0; u < FOLD_CELLS; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) first[u][q] = cpx{0, 0};
+        }
 #pragma unroll
         for (int u = 0; u < FOLD_CELLS; ++u) {
             const int e = e0 + u * NT, cc = e >> LOGN, t1 = e & msk, t2 = c0 + cc;

@@ -47,9 +47,20 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t *__restrict__ 
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_NT * items;
-    for (int r = 0; r < items; ++r) {
-        const int64_t i = base + r * RS_NT + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(int)(keys[i] >> shift) & dmask], 1);
+    // RS_HU keys per thread requested together; past the end a thread reads key 0 and adds 0
+    // (with the load or the add behind a branch, each key would wait for its own round trip)
+    constexpr int RS_HU = 8;
+    for (int r0 = 0; r0 < items; r0 += RS_HU) {
+        uint64_t kv[RS_HU];
+        bool ok[RS_HU];
+#pragma unroll
+        for (int u = 0; u < RS_HU; ++u) {
+            const int64_t i = base + (int64_t)(r0 + u) * RS_NT + threadIdx.x;
+            ok[u] = r0 + u < items && i < n;
+            kv[u] = keys[ok[u] ? i : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < RS_HU; ++u) atomicAdd(&cnt[(int)(kv[u] >> shift) & dmask], ok[u] ? 1 : 0);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
