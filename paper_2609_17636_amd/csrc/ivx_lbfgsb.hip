@@ -58,11 +58,14 @@ struct Half {
 // Fixed layouts of the reduced quantities (entries past the stored pairs stay zero).
 constexpr int CP_NS = 3 + 2 * MAXM;      // k_cp_init: d.d, #breakpoints, #fixed, Y.d, S.d | t_min
 constexpr int UP_NS = 4 + 3 * MAXM;      // k_update: s.y, y.y, g.s, s.s, s.Y, S.y, s.S | -pg
-constexpr int SCAL = 1024;               // doubles of the device/host scalar exchange buffers
+constexpr int SCAL = 2048;               // doubles of the device/host scalar exchange buffers
 constexpr int OFF = 8;                   // reductions land at scal[OFF..]; scal[0..4) = terms
 constexpr int SEL_OUT = SCAL - 1;        // the breakpoint prefix length (k_cp_select)
+// the host's M for the next walk (k_cp_init moves it to Mdev), after the subspace results
+constexpr int MOFF = (OFF + MAXD + MAXD * (MAXD + 1) / 2 + 63) / 64 * 64;
 constexpr int PART_R = RBLK * MAXD * (MAXD + 1) / 2; // W^T r partials beside the Gram matrix's
-static_assert(OFF + MAXD + MAXD * (MAXD + 1) / 2 <= SCAL, "the subspace results fit the exchange buffer");
+static_assert(OFF + MAXD + MAXD * (MAXD + 1) / 2 <= MOFF && MOFF + MAXD * MAXD <= SEL_OUT,
+              "the subspace results, M and the prefix length fit the exchange buffer apart");
 
 // ---------------------------------------------------------------- reductions
 // Each thread holds nv partials: entries [0, nsum) are sums, the rest minima.  Wave
@@ -108,8 +111,12 @@ constexpr int FIN_NT = 1024;
 constexpr int FIN_U = 16;
 constexpr int FIN_NV = MAXNV > MAXD * (MAXD + 1) / 2 ? MAXNV : MAXD * (MAXD + 1) / 2;
 
+// Also copies ncopy doubles from copy_src to copy_dst (the objective's terms, taken along to the
+// host buffer by the same launch).
 __global__ __launch_bounds__(FIN_NT) void k_finish(const double *__restrict__ part, int nblk, int nv, int nsum,
-                                                   double *__restrict__ out) {
+                                                   double *__restrict__ out, const double *__restrict__ copy_src = nullptr,
+                                                   int ncopy = 0, double *__restrict__ copy_dst = nullptr) {
+    if (threadIdx.x < ncopy) copy_dst[threadIdx.x] = copy_src[threadIdx.x];
     __shared__ double sh[FIN_CH][FIN_NV];
     const int per = (nblk + FIN_CH - 1) / FIN_CH;
     for (int e = threadIdx.x; e < nv * FIN_CH; e += FIN_NT) {
@@ -214,7 +221,11 @@ __global__ __launch_bounds__(NT) void k_cp_init(const double *__restrict__ x, co
                                                 int pos, const double *__restrict__ S, const double *__restrict__ Y,
                                                 Slots sl, double *__restrict__ t, double *__restrict__ d,
                                                 double *__restrict__ key, int *__restrict__ val,
-                                                uint8_t *__restrict__ fixed, double *__restrict__ part) {
+                                                uint8_t *__restrict__ fixed, double *__restrict__ part,
+                                                const double *__restrict__ msrc, int nm, double *__restrict__ mdst) {
+    // block 0 also moves the host's M (mapped memory) to the device copy the walk reads
+    if (blockIdx.x == 0)
+        for (int e = threadIdx.x; e < nm; e += NT) mdst[e] = msrc[e];
     double acc[MAXNV];
 #pragma unroll
     for (int q = 0; q < MAXNV; ++q) acc[q] = 0.0;
@@ -1247,9 +1258,9 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
         ivx_status e = ivx_objective_grad(s->plan, s->sky, s->grad, s->scal, st);
         if (e != IVX_OK) return e;
         k_take_grad<<<G, NT, 0, st>>>(s->grad, xcur, dvec, n, pos, gdst, s->part);
-        k_finish<<<1, FIN_NT, 0, st>>>(s->part, (int)G, 2, 1, s->scal + OFF);
+        // g.d and |pg| and the four terms land in the mapped host buffer: no copy launch
+        k_finish<<<1, FIN_NT, 0, st>>>(s->part, (int)G, 2, 1, s->host_dev + OFF, s->scal, 4, s->host_dev);
         LB_HIP(hipGetLastError());
-        LB_HIP(hipMemcpyAsync(h, s->scal, (OFF + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
         LB_HIP(hipStreamSynchronize(st));
         fval = h[0];
         gd = h[OFF];
@@ -1288,11 +1299,11 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
             const Slots sl = mem.slots();
             const int k = mem.k, D = 2 * k;
             const double theta = mem.theta;
-            if (k > 0) LB_HIP(hipMemcpyAsync(s->Mdev, mem.M.data(), (size_t)D * D * sizeof(double),
-                                             hipMemcpyHostToDevice, st));
+            // M goes through the mapped host buffer (the stream has drained: no kernel reads it)
+            if (k > 0) std::copy(mem.M.begin(), mem.M.begin() + (size_t)D * D, h + MOFF);
             // ---- generalized Cauchy point
             k_cp_init<<<G, NT, 0, st>>>(s->x, s->g, n, pos, s->S, s->Y, sl, s->t, s->d, s->key, s->val, s->fixed,
-                                        s->part);
+                                        s->part, s->host_dev + MOFF, k > 0 ? D * D : 0, s->Mdev);
             LB_HIP(hipGetLastError());
             if ((e = reduce_to_host(s, G, CP_NS + 1, CP_NS, OFF, st)) != IVX_OK) return e;
             const double dd = h[OFF], nbr = h[OFF + 1], nfix0 = h[OFF + 2], tmin = h[OFF + CP_NS];
