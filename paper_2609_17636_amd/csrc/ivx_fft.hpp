@@ -154,18 +154,48 @@ template <int LOGN> constexpr int col_batch() {
 
 // --------------------------------------------------------------------- reprojection
 // Bilinear sample at (row sy, col sx); pixel (i, j) sits at (i, j); outside pixels are 0.
-__device__ __forceinline__ real bilinear(const real *__restrict__ sky, int N, real sy, real sx) {
-    if (!(sy > real(-1) && sy < real(N) && sx > real(-1) && sx < real(N))) return real(0);
-    const real fi = floor(sy), fj = floor(sx);
+// Branch-free: a tap outside the image reads a clamped pixel inside it and is scaled by 0, and
+// a sample outside (or a NaN coordinate) evaluates at (0, 0) and is scaled by 0, so the loads
+// of several samples can be in flight together (behind a branch each would wait for the last).
+// Taps: the four pixel offsets (row-major, N^2 < 2^31) and their 0/1 masks; combine() forms
+// the sample from the four loaded pixels.
+struct BilinearTaps {
+    int o[4];
+    real m[4];
+    real fy, fx, in;
+    __device__ __forceinline__ real combine(real p00, real p01, real p10, real p11) const {
+        const real x00 = p00 * m[0], x01 = p01 * m[1], x10 = p10 * m[2], x11 = p11 * m[3];
+        const real v = (real(1) - fy) * ((real(1) - fx) * x00 + fx * x01) + fy * ((real(1) - fx) * x10 + fx * x11);
+        return v * in;
+    }
+};
+
+__device__ __forceinline__ BilinearTaps bilinear_taps(int N, real sy, real sx) {
+    BilinearTaps t;
+    const bool in = sy > real(-1) && sy < real(N) && sx > real(-1) && sx < real(N);
+    const real cy = in ? sy : real(0), cx = in ? sx : real(0);
+    const real fi = floor(cy), fj = floor(cx);
     const int i0 = (int)fi, j0 = (int)fj;
-    const real fy = sy - fi, fx = sx - fj;
+    t.fy = cy - fi;
+    t.fx = cx - fj;
+    t.in = in ? real(1) : real(0);
     const bool r0 = i0 >= 0, r1 = i0 + 1 < N, c0 = j0 >= 0, c1 = j0 + 1 < N;
-    const real *p = sky + (int64_t)i0 * N + j0;
-    const real x00 = (r0 && c0) ? p[0] : real(0);
-    const real x01 = (r0 && c1) ? p[1] : real(0);
-    const real x10 = (r1 && c0) ? p[N] : real(0);
-    const real x11 = (r1 && c1) ? p[N + 1] : real(0);
-    return (real(1) - fy) * ((real(1) - fx) * x00 + fx * x01) + fy * ((real(1) - fx) * x10 + fx * x11);
+    const int ia = (r0 ? i0 : 0) * N, ib = (r1 ? i0 + 1 : N - 1) * N;
+    const int ja = c0 ? j0 : 0, jb = c1 ? j0 + 1 : N - 1;
+    t.o[0] = ia + ja;
+    t.o[1] = ia + jb;
+    t.o[2] = ib + ja;
+    t.o[3] = ib + jb;
+    t.m[0] = (r0 && c0) ? real(1) : real(0);
+    t.m[1] = (r0 && c1) ? real(1) : real(0);
+    t.m[2] = (r1 && c0) ? real(1) : real(0);
+    t.m[3] = (r1 && c1) ? real(1) : real(0);
+    return t;
+}
+
+__device__ __forceinline__ real bilinear(const real *__restrict__ sky, int N, real sy, real sx) {
+    const BilinearTaps t = bilinear_taps(N, sy, sx);
+    return t.combine(sky[t.o[0]], sky[t.o[1]], sky[t.o[2]], sky[t.o[3]]);
 }
 
 } // namespace ivx

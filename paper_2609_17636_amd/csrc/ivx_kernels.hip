@@ -43,7 +43,7 @@ __global__ __launch_bounds__(NT) void k_image_rows(Geom g, const real *__restric
                                                    const real *__restrict__ dq,
                                                    const cpx *__restrict__ tw, cpx *__restrict__ R) {
     constexpr int N = 1 << LOGN;
-    __shared__ cpx buf[N];
+    __shared__ cpx buf[N + 1]; // + a sink cell for the stores of positions past the end
     __shared__ cpx tws[tw_len<LOGN>()];
     TwStage<LOGN> twr;
     twr.fetch(tw);
@@ -59,11 +59,45 @@ __global__ __launch_bounds__(NT) void k_image_rows(Geom g, const real *__restric
     for (int i = tid; i < N; i += NT) buf[i] = cpx{0, 0};
     __syncthreads();
     const real q0 = s * dq[a0], q1 = s * dq[a0 + 1];
-    for (int b = tid; b < nk; b += NT) {
-        const int64_t e0 = (int64_t)a0 * nk + b, e1 = e0 + nk;
-        const real f0 = q0 * dq[b] * A[e0] * bilinear(x, g.N, G[2 * e0], G[2 * e0 + 1]);
-        const real f1 = q1 * dq[b] * A[e1] * bilinear(x, g.N, G[2 * e1], G[2 * e1 + 1]);
-        buf[(b - nk / 2) & (N - 1)] = cpx{f0, f1};
+    // IR_U columns per thread: their beam values and sample positions are requested together,
+    // then every sky tap of both rows (positions past the end read column 0 and store to the
+    // sink cell): two round trips instead of two per row and column
+    constexpr int IR_U = 2;
+    for (int b0 = tid; b0 < nk; b0 += IR_U * NT) {
+        real dv[IR_U], a_0[IR_U], a_1[IR_U], y0[IR_U], x0[IR_U], y1[IR_U], x1[IR_U];
+#pragma unroll
+        for (int u = 0; u < IR_U; ++u) {
+            const int b = b0 + u * NT < nk ? b0 + u * NT : 0;
+            const int64_t e0 = (int64_t)a0 * nk + b, e1 = e0 + nk;
+            dv[u] = dq[b];
+            a_0[u] = A[e0];
+            a_1[u] = A[e1];
+            y0[u] = G[2 * e0];
+            x0[u] = G[2 * e0 + 1];
+            y1[u] = G[2 * e1];
+            x1[u] = G[2 * e1 + 1];
+        }
+        BilinearTaps t0[IR_U], t1[IR_U];
+        real p0[IR_U][4], p1[IR_U][4];
+#pragma unroll
+        for (int u = 0; u < IR_U; ++u) {
+            t0[u] = bilinear_taps(g.N, y0[u], x0[u]);
+            t1[u] = bilinear_taps(g.N, y1[u], x1[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < IR_U; ++u)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                p0[u][j] = x[t0[u].o[j]];
+                p1[u][j] = x[t1[u].o[j]];
+            }
+#pragma unroll
+        for (int u = 0; u < IR_U; ++u) {
+            const int b = b0 + u * NT;
+            const real f0 = q0 * dv[u] * a_0[u] * t0[u].combine(p0[u][0], p0[u][1], p0[u][2], p0[u][3]);
+            const real f1 = q1 * dv[u] * a_1[u] * t1[u].combine(p1[u][0], p1[u][1], p1[u][2], p1[u][3]);
+            buf[b < nk ? (b - nk / 2) & (N - 1) : N] = cpx{f0, f1};
+        }
     }
     twr.store(tws);
     __syncthreads();

@@ -384,20 +384,25 @@ def select_floor(m: Mosaic, net, x_mean, seeds, floors=(0.0, 0.02, 0.1, 0.3), ma
 
 
 # ----------------------------------------------------------------------------- command line
-def solve_timing(iters: int = 200) -> dict:
+def solve_timing(iters: int = 200, repeats: int = 5) -> dict:
     """Cold device solve of the first held-out field for `iters` iterations (after a
-    30-iteration warm-up solve): wall-clock per evaluation, and how many iterations walked
-    the Cauchy breakpoints."""
+    30-iteration warm-up solve), repeated: wall-clock per evaluation (median and minimum over
+    the repeats; every repeat runs the same iterates), and how many iterations walked the
+    Cauchy breakpoints."""
     import torch
 
     m = Mosaic()
     m.simulate(HELDOUT_BASE)
     m.solve(maxiter=30)
     torch.cuda.synchronize()
-    r = m.solve(maxiter=iters)
-    torch.cuda.synchronize()
+    runs = []
+    for _ in range(max(repeats, 1)):
+        r = m.solve(maxiter=iters)
+        torch.cuda.synchronize()
+        runs.append(1e3 * r.seconds / max(r.nfev, 1))
     return {"workload": "warm-start mosaic, cold solve of field 100000", "iterations": r.nit, "evaluations": r.nfev,
-            "walks": r.n_walks, "seconds": r.seconds, "ms_per_eval": 1e3 * r.seconds / max(r.nfev, 1)}
+            "walks": r.n_walks, "seconds": r.seconds, "repeats": len(runs), "ms_per_eval": float(np.median(runs)),
+            "ms_per_eval_min": min(runs)}
 
 
 def train_throughput(batch: int = 16, steps: int = 50, warmup: int = 5) -> dict:
