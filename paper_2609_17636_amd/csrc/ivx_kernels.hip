@@ -1210,7 +1210,7 @@ __global__ __launch_bounds__(NT) void k_col_inv_slots(Geom g, const int32_t *__r
     // slot-list prefix of tile columns vxa - 1 .. vxa + 2 in every tile row: the tiles whose
     // windows reach this block's columns (CB <= T consecutive columns lie in at most two
     // tile columns)
-    __shared__ int rng[MAXROWS][4];
+    __shared__ int rng[MAXROWS + 1][4]; // + a sink row for the stores of entries past the end
     TwStage<LOGN> twr;
     twr.fetch(tw);
     const int tid = threadIdx.x;
@@ -1219,9 +1219,23 @@ __global__ __launch_bounds__(NT) void k_col_inv_slots(Geom g, const int32_t *__r
     const int32_t *ts = tslot + (int64_t)item * (g.nty * g.ntx + 1);
     const int msk = N - 1;
     const int vxa = (c0 + g.O) / g.T;
-    for (int e = tid; e < g.nty * 4; e += NT) {
-        const int ty = e >> 2, tx = vxa - 1 + (e & 3);
-        rng[ty][e & 3] = (tx >= 0 && tx <= g.ntx) ? ts[ty * g.ntx + tx] : 0;
+    // the prefix entries, RNG_U per thread requested together (loads clamped to entry 0,
+    // stores past the end into the sink row; a guarded load would wait for the previous one)
+    constexpr int RNG_U = 2;
+    for (int e0 = tid; e0 < g.nty * 4; e0 += RNG_U * NT) {
+        int32_t pv[RNG_U];
+#pragma unroll
+        for (int u = 0; u < RNG_U; ++u) {
+            const int e = e0 + u * NT, ty = e >> 2, tx = vxa - 1 + (e & 3);
+            const bool ok = e < g.nty * 4 && tx >= 0 && tx <= g.ntx;
+            pv[u] = ts[ok ? ty * g.ntx + tx : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < RNG_U; ++u) {
+            const int e = e0 + u * NT, ty = e >> 2, tx = vxa - 1 + (e & 3);
+            const bool ok = e < g.nty * 4 && tx >= 0 && tx <= g.ntx;
+            rng[e < g.nty * 4 ? ty : MAXROWS][e & 3] = ok ? pv[u] : 0;
+        }
     }
     // the item's first slot (a valid address for the loads of empty quadrants), if it has any
     const int32_t s_first = ts[0];
