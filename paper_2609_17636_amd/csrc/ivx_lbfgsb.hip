@@ -350,7 +350,9 @@ __global__ __launch_bounds__(NT) void k_scan_apply(const double *__restrict__ in
         s += v[e];
     }
     double tot;
-    double run = bsum[(int64_t)row * nb + blockIdx.x] + block_exscan(s, tot);
+    // bsum null: a single segment, whose carry is 0
+    const double carry = bsum ? bsum[(int64_t)row * nb + blockIdx.x] : 0.0;
+    double run = carry + block_exscan(s, tot);
     for (int e = 0; e < 4; ++e) {
         const int64_t j = base + e;
         if (j < L) out[(int64_t)row * L + j] = run;
@@ -1094,9 +1096,15 @@ ivx_status reduce_to_host(ivx_lbfgsb *s, unsigned nblk, int nv, int nsum, int of
 
 ivx_status scan_rows(ivx_lbfgsb *s, const double *in, double *out, int rows, int64_t L, hipStream_t st) {
     const int nb = (int)((L + SEG - 1) / SEG);
-    k_scan_sums<<<dim3(nb, rows), NT, 0, st>>>(in, L, nb, s->bsum);
-    k_scan_bsums<<<rows, NT, 0, st>>>(s->bsum, nb);
-    k_scan_apply<<<dim3(nb, rows), NT, 0, st>>>(in, L, nb, s->bsum, out);
+    if (nb == 1) {
+        // one segment per row (every walk over a sampled prefix): the apply pass alone, with
+        // the carry 0 that the two segment passes would have produced
+        k_scan_apply<<<dim3(1, rows), NT, 0, st>>>(in, L, 1, nullptr, out);
+    } else {
+        k_scan_sums<<<dim3(nb, rows), NT, 0, st>>>(in, L, nb, s->bsum);
+        k_scan_bsums<<<rows, NT, 0, st>>>(s->bsum, nb);
+        k_scan_apply<<<dim3(nb, rows), NT, 0, st>>>(in, L, nb, s->bsum, out);
+    }
     LB_HIP(hipGetLastError());
     return IVX_OK;
 }
