@@ -20,8 +20,10 @@
 
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <limits>
 #include <string>
 #include <vector>
@@ -61,10 +63,11 @@ constexpr int UP_NS = 4 + 3 * MAXM;      // k_update: s.y, y.y, g.s, s.s, s.Y, S
 constexpr int SCAL = 2048;               // doubles of the device/host scalar exchange buffers
 constexpr int OFF = 8;                   // reductions land at scal[OFF..]; scal[0..4) = terms
 constexpr int SEL_OUT = SCAL - 1;        // the breakpoint prefix length (k_cp_select)
+constexpr int FLAG = SCAL - 2;           // the sequence number of the last published result
 // the host's M for the next walk (k_cp_init moves it to Mdev), after the subspace results
 constexpr int MOFF = (OFF + MAXD + MAXD * (MAXD + 1) / 2 + 63) / 64 * 64;
 constexpr int PART_R = RBLK * MAXD * (MAXD + 1) / 2; // W^T r partials beside the Gram matrix's
-static_assert(OFF + MAXD + MAXD * (MAXD + 1) / 2 <= MOFF && MOFF + MAXD * MAXD <= SEL_OUT,
+static_assert(OFF + MAXD + MAXD * (MAXD + 1) / 2 <= MOFF && MOFF + MAXD * MAXD <= FLAG,
               "the subspace results, M and the prefix length fit the exchange buffer apart");
 
 // ---------------------------------------------------------------- reductions
@@ -100,6 +103,22 @@ __device__ __forceinline__ void block_reduce(double (&acc)[NV], int nv, int nsum
     }
 }
 
+// The last kernel before each host wait publishes its results: every wave waits until its
+// own stores are acknowledged, and after the barrier thread 0 writes them back to system
+// scope, then writes the call's sequence number to the flag in the mapped host buffer, on
+// which the host spins instead of waiting for the stream to drain.  One workgroup only; flag
+// null publishes nothing.
+__device__ __forceinline__ void publish(uint64_t *flag, uint64_t seq) {
+    if (!flag) return; // (uniform)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence_system();
+        *reinterpret_cast<volatile uint64_t *>(flag) = seq;
+        __threadfence_system();
+    }
+}
+
 // The rows are cut into FIN_CH consecutive chunks; thread (q, c) combines quantity q over
 // the rows of chunk c in block order, then out[q] combines the chunk results in chunk order.
 // The order is fixed (results do not depend on timing).  A chunk's rows are requested
@@ -114,8 +133,9 @@ constexpr int FIN_NV = MAXNV > MAXD * (MAXD + 1) / 2 ? MAXNV : MAXD * (MAXD + 1)
 // Also copies ncopy doubles from copy_src to copy_dst (the objective's terms, taken along to the
 // host buffer by the same launch).
 __global__ __launch_bounds__(FIN_NT) void k_finish(const double *__restrict__ part, int nblk, int nv, int nsum,
-                                                   double *__restrict__ out, const double *__restrict__ copy_src = nullptr,
-                                                   int ncopy = 0, double *__restrict__ copy_dst = nullptr) {
+                                                   double *__restrict__ out, const double *__restrict__ copy_src,
+                                                   int ncopy, double *__restrict__ copy_dst, uint64_t *flag,
+                                                   uint64_t seq) {
     if (threadIdx.x < ncopy) copy_dst[threadIdx.x] = copy_src[threadIdx.x];
     __shared__ double sh[FIN_CH][FIN_NV];
     const int per = (nblk + FIN_CH - 1) / FIN_CH;
@@ -143,6 +163,7 @@ __global__ __launch_bounds__(FIN_NT) void k_finish(const double *__restrict__ pa
         for (int c = 1; c < FIN_CH; ++c) v = q < nsum ? v + sh[c][q] : fmin(v, sh[c][q]);
         out[q] = v;
     }
+    publish(flag, seq);
 }
 
 // The stored pairs at element i: ys[j] = Y_j[i], ss[j] = S_j[i] for j < k, zero after.
@@ -505,7 +526,7 @@ static_assert(SEL_CAP <= SEL_NT, "one thread per gathered pair");
 
 __global__ __launch_bounds__(SEL_NT) void k_cp_select(const uint64_t *__restrict__ key, int64_t n, int64_t K,
                                                       uint64_t *__restrict__ skey, uint32_t *__restrict__ sidx,
-                                                      double *__restrict__ out) {
+                                                      double *__restrict__ out, uint64_t *flag, uint64_t seq) {
     __shared__ uint64_t kb[SEL_CAP];
     __shared__ uint32_t ib[SEL_CAP];
     __shared__ int rk[SEL_CAP];
@@ -590,6 +611,7 @@ __global__ __launch_bounds__(SEL_NT) void k_cp_select(const uint64_t *__restrict
     const int c = cnt;
     if (c > SEL_CAP) { // (uniform) too many below the threshold: the caller sorts them all
         if (tid == 0) out[0] = -1.0;
+        publish(flag, seq);
         return;
     }
     if (c > 0) {
@@ -616,6 +638,7 @@ __global__ __launch_bounds__(SEL_NT) void k_cp_select(const uint64_t *__restrict
         }
     }
     if (tid == 0) out[0] = (double)c;
+    publish(flag, seq);
 }
 
 // first j whose segment holds the minimiser (j = K1 - 1 always qualifies)
@@ -634,7 +657,7 @@ __global__ __launch_bounds__(NT) void k_cp_find(const double *__restrict__ Eex, 
 __global__ void k_cp_gather(const int *__restrict__ Jin, const double *__restrict__ Pex,
                             const double *__restrict__ Cex, const double *__restrict__ Eex,
                             const double *__restrict__ Aex, const double *__restrict__ skey, int64_t K1, int D,
-                            Vec p0, double fp0, double fpp0, double *__restrict__ out) {
+                            Vec p0, double fp0, double fpp0, double *__restrict__ out, uint64_t *flag, uint64_t seq) {
     const int J = *Jin;
     const int c = threadIdx.x;
     if (c < D) {
@@ -647,6 +670,7 @@ __global__ void k_cp_gather(const int *__restrict__ Jin, const double *__restric
         out[2 * D + 2] = J > 0 ? skey[J - 1] : 0.0;
         out[2 * D + 3] = (double)J;
     }
+    publish(flag, seq);
 }
 
 __global__ void k_set_int(int *__restrict__ p, int v) {
@@ -1048,6 +1072,7 @@ struct ivx_lbfgsb {
     size_t sort_bytes = 0;
     double *host = nullptr;     // pinned, mapped
     double *host_dev = nullptr; // the same buffer as the device addresses it
+    uint64_t seq = 0;           // the last sequence number handed to a publishing kernel
 };
 
 namespace {
@@ -1084,14 +1109,36 @@ unsigned grid_of(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int
         if (e_ != hipSuccess) return set_error(IVX_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+uint64_t *flag_dev(ivx_lbfgsb *s) { return reinterpret_cast<uint64_t *>(s->host_dev + FLAG); }
+
+// Waits until the kernel handed sequence number seq has published its results.  The host
+// spins on the flag in the mapped buffer; past 20 ms (a slow call, or a kernel that failed)
+// it waits for the stream, which also reports any error.
+ivx_status wait_published(ivx_lbfgsb *s, uint64_t seq, hipStream_t st) {
+    const volatile uint64_t *f = reinterpret_cast<const volatile uint64_t *>(s->host + FLAG);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t i = 0;; ++i) {
+        if (*f == seq) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return IVX_OK;
+        }
+        if ((i & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) break;
+    }
+    LB_HIP(hipStreamSynchronize(st));
+    if (*f != seq) return set_error(IVX_EHIP, "a solver kernel completed without publishing its result");
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return IVX_OK;
+}
+
 // Sum/min reduce a kernel's block partials into the host buffer at s->host[off..off+nv).
 ivx_status reduce_to_host(ivx_lbfgsb *s, unsigned nblk, int nv, int nsum, int off, hipStream_t st) {
-    // the finisher writes the few results straight into the mapped host buffer: no copy
-    // launch; they are complete on the host once the stream has drained
-    k_finish<<<1, FIN_NT, 0, st>>>(s->part, (int)nblk, nv, nsum, s->host_dev + off);
+    // the finisher writes the few results straight into the mapped host buffer (no copy
+    // launch) and publishes them
+    const uint64_t q = ++s->seq;
+    k_finish<<<1, FIN_NT, 0, st>>>(s->part, (int)nblk, nv, nsum, s->host_dev + off, nullptr, 0, nullptr,
+                                   flag_dev(s), q);
     LB_HIP(hipGetLastError());
-    LB_HIP(hipStreamSynchronize(st));
-    return IVX_OK;
+    return wait_published(s, q, st);
 }
 
 ivx_status scan_rows(ivx_lbfgsb *s, const double *in, double *out, int rows, int64_t L, hipStream_t st) {
@@ -1219,6 +1266,7 @@ ivx_status ivx_lbfgsb_create(ivx_plan *plan, int32_t m_max, ivx_lbfgsb **out) {
         s->host = nullptr;
         st = set_error(IVX_ENOMEM, "hipHostMalloc failed in ivx_lbfgsb_create");
     }
+    if (!st) std::memset(s->host, 0, SCAL * sizeof(double)); // the flag starts below every sequence number
     if (!st && hipHostGetDevicePointer((void **)&s->host_dev, s->host, 0) != hipSuccess) {
         (void)hipGetLastError();
         st = set_error(IVX_EHIP, "hipHostGetDevicePointer failed in ivx_lbfgsb_create");
@@ -1267,9 +1315,11 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
         if (e != IVX_OK) return e;
         k_take_grad<<<G, NT, 0, st>>>(s->grad, xcur, dvec, n, pos, gdst, s->part);
         // g.d and |pg| and the four terms land in the mapped host buffer: no copy launch
-        k_finish<<<1, FIN_NT, 0, st>>>(s->part, (int)G, 2, 1, s->host_dev + OFF, s->scal, 4, s->host_dev);
+        const uint64_t q = ++s->seq;
+        k_finish<<<1, FIN_NT, 0, st>>>(s->part, (int)G, 2, 1, s->host_dev + OFF, s->scal, 4, s->host_dev,
+                                       flag_dev(s), q);
         LB_HIP(hipGetLastError());
-        LB_HIP(hipStreamSynchronize(st));
+        if ((e = wait_published(s, q, st)) != IVX_OK) return e;
         fval = h[0];
         gd = h[OFF];
         pgn = -h[OFF + 1];
@@ -1364,10 +1414,11 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
                         if ((ew = scan_rows(s, s->E, s->Eex, 1, K1, st)) != IVX_OK) return ew;
                         k_set_int<<<1, 64, 0, st>>>(s->Jdev, (int)(K1 - 1));
                         k_cp_find<<<GK, NT, 0, st>>>(s->Eex, s->Aex, s->DT, K1, fp0, fpp0, s->Jdev);
+                        const uint64_t q = ++s->seq;
                         k_cp_gather<<<1, 64, 0, st>>>(s->Jdev, s->Pex, s->Cex, s->Eex, s->Aex, s->key2, K1, D, p0v,
-                                                      fp0, fpp0, s->host_dev + OFF);
+                                                      fp0, fpp0, s->host_dev + OFF, flag_dev(s), q);
                         LB_HIP(hipGetLastError());
-                        LB_HIP(hipStreamSynchronize(st));
+                        if ((ew = wait_published(s, q, st)) != IVX_OK) return ew;
                         f1 = h[OFF + 2 * D];
                         f2 = std::max(h[OFF + 2 * D + 1], EPS * fpp0);
                         told = h[OFF + 2 * D + 2];
@@ -1381,11 +1432,16 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
                     // breakpoint.  Otherwise (or when the prefix overflows) sort them all.
                     bool done = false;
                     if (!opt.full_sort && n <= SEL_MAX_N) {
+                    const uint64_t q = ++s->seq;
                     k_cp_select<<<1, SEL_NT, 0, st>>>(reinterpret_cast<const uint64_t *>(s->key), n, K,
                                                       reinterpret_cast<uint64_t *>(s->key2),
-                                                      reinterpret_cast<uint32_t *>(s->val2), s->host_dev + SEL_OUT);
+                                                      reinterpret_cast<uint32_t *>(s->val2), s->host_dev + SEL_OUT,
+                                                      flag_dev(s), q);
                     LB_HIP(hipGetLastError());
-                    LB_HIP(hipStreamSynchronize(st));
+                    {
+                        const ivx_status es = wait_published(s, q, st);
+                        if (es != IVX_OK) return es;
+                    }
                     const double cs = h[SEL_OUT];
                     if (cs >= 0.0) {
                         const int64_t Kw = (int64_t)cs;
@@ -1430,10 +1486,17 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
                 k_ss_r<<<G, NT, 0, st>>>(s->x, s->xc, s->g, s->fixed, s->S, s->Y, n, sl, theta, mcy, mcs, s->r,
                                          s->part + PART_R);
                 k_ss_gram<<<G, NT, 0, st>>>(s->fixed, s->S, s->Y, n, sl, s->part);
-                k_finish<<<1, FIN_NT, 0, st>>>(s->part + PART_R, (int)G, MAXD, MAXD, s->host_dev + OFF);
-                k_finish<<<1, FIN_NT, 0, st>>>(s->part, (int)G, np, np, s->host_dev + OFF + MAXD);
+                // both publish (the first one's stores are fenced too); the host waits for the second
+                const uint64_t q1 = ++s->seq, q2 = ++s->seq;
+                k_finish<<<1, FIN_NT, 0, st>>>(s->part + PART_R, (int)G, MAXD, MAXD, s->host_dev + OFF, nullptr, 0,
+                                               nullptr, flag_dev(s), q1);
+                k_finish<<<1, FIN_NT, 0, st>>>(s->part, (int)G, np, np, s->host_dev + OFF + MAXD, nullptr, 0, nullptr,
+                                               flag_dev(s), q2);
                 LB_HIP(hipGetLastError());
-                LB_HIP(hipStreamSynchronize(st));
+                {
+                    const ivx_status es = wait_published(s, q2, st);
+                    if (es != IVX_OK) return es;
+                }
                 std::vector<double> bvec(D);
                 for (int j = 0; j < k; ++j) {
                     bvec[j] = h[OFF + j];
