@@ -74,7 +74,7 @@ typedef double ivx_real;
 typedef float ivx_real;
 #endif
 
-#define IVX_VERSION 4
+#define IVX_VERSION 5
 
 typedef enum {
     IVX_OK = 0,

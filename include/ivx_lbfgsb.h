@@ -52,6 +52,11 @@ typedef struct {
                             below a sampled threshold, in one workgroup, and all of them only
                             when the minimiser lies beyond (same iterates either way; problems of
                             more than 2^24 variables always sort all) (0) */
+    int32_t stream_wait; /* 1: the host reads each step's results after the stream has drained;
+                            0: as soon as the step's last kernel has published them, by spinning
+                            on a sequence number it writes into the mapped host buffer, falling
+                            back to the stream wait after 20 ms (same iterates either way) (0) */
+    int32_t reserved;    /* 0 */
     double ftol;         /* relative-reduction tolerance (2.220446049250313e-09) */
     double gtol;         /* projected-gradient infinity-norm tolerance (1e-5) */
     double target;       /* stop once f <= target; -INFINITY disables (-INFINITY) */

@@ -1073,6 +1073,7 @@ struct ivx_lbfgsb {
     double *host = nullptr;     // pinned, mapped
     double *host_dev = nullptr; // the same buffer as the device addresses it
     uint64_t seq = 0;           // the last sequence number handed to a publishing kernel
+    bool stream_wait = false;   // this solve reads results after the stream drains
 };
 
 namespace {
@@ -1112,12 +1113,13 @@ unsigned grid_of(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int
 uint64_t *flag_dev(ivx_lbfgsb *s) { return reinterpret_cast<uint64_t *>(s->host_dev + FLAG); }
 
 // Waits until the kernel handed sequence number seq has published its results.  The host
-// spins on the flag in the mapped buffer; past 20 ms (a slow call, or a kernel that failed)
-// it waits for the stream, which also reports any error.
+// spins on the flag in the mapped buffer; past 20 ms (a slow call, or a kernel that failed),
+// or at once when the solve asked for stream waits, it waits for the stream, which also
+// reports any error.
 ivx_status wait_published(ivx_lbfgsb *s, uint64_t seq, hipStream_t st) {
     const volatile uint64_t *f = reinterpret_cast<const volatile uint64_t *>(s->host + FLAG);
     const auto t0 = std::chrono::steady_clock::now();
-    for (uint32_t i = 0;; ++i) {
+    for (uint32_t i = 0; !s->stream_wait; ++i) {
         if (*f == seq) {
             std::atomic_thread_fence(std::memory_order_acquire);
             return IVX_OK;
@@ -1213,6 +1215,8 @@ ivx_status ivx_lbfgsb_default_options(ivx_lbfgsb_options *o) {
     o->maxls = 20;
     o->positivity = 1;
     o->full_sort = 0;
+    o->stream_wait = 0;
+    o->reserved = 0;
     o->ftol = 2.220446049250313e-09;
     o->gtol = 1e-5;
     o->target = -INFINITY;
@@ -1303,6 +1307,7 @@ ivx_status ivx_lbfgsb_solve(ivx_lbfgsb *s, ivx_real *xio, const ivx_lbfgsb_optio
     const int pos = opt.positivity ? 1 : 0;
     const auto t0 = std::chrono::steady_clock::now();
     double *h = s->host;
+    s->stream_wait = opt.stream_wait != 0;
     int64_t nfev = 0, nit = 0, nwalk = 0, nwalk_full = 0;
     double f = 0.0, pg = 0.0;
     int reason = IVX_LBFGSB_MAXITER;

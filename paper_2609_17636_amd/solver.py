@@ -85,7 +85,7 @@ def solve(plan, x0=None, maxiter=500, m=10, ftol=2.2e-9, gtol=1e-5, maxls=20, ta
 class _LbOptions(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("maxiter", ctypes.c_int32), ("maxfun", ctypes.c_int32),
                 ("maxls", ctypes.c_int32), ("positivity", ctypes.c_int32), ("full_sort", ctypes.c_int32),
-                ("ftol", ctypes.c_double), ("gtol", ctypes.c_double), ("target", ctypes.c_double)]
+                ("stream_wait", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ftol", ctypes.c_double), ("gtol", ctypes.c_double), ("target", ctypes.c_double)]
 
 
 class _LbResult(ctypes.Structure):
@@ -144,11 +144,12 @@ class DeviceSolver:
 
     def solve(self, x0=None, maxiter=15000, m=10, ftol=2.2204460492503131e-09, gtol=1e-5, maxls=20,
               maxfun=15000, target=None, positivity=True, history=20000, stream=None, t_start=None,
-              full_sort=False):
+              full_sort=False, stream_wait=False):
         """Minimise Q_tot from x0 (None: zeros; numpy or cuda tensor).  Returns a SolveResult
         whose x is a cuda tensor [C][N][N] in the plan's precision.  full_sort: every Cauchy
         search sorts all breakpoints (the default sorts a sampled prefix first; the iterates
-        are the same)."""
+        are the same).  stream_wait: the host reads each step's results after the stream has
+        drained instead of spinning on the flag the step publishes (the same iterates)."""
         import torch
 
         plan = self.plan
@@ -164,6 +165,7 @@ class DeviceSolver:
         o.m, o.maxiter, o.maxfun, o.maxls = int(m), int(maxiter), int(maxfun), int(maxls)
         o.positivity = 1 if positivity else 0
         o.full_sort = 1 if full_sort else 0
+        o.stream_wait = 1 if stream_wait else 0
         o.ftol, o.gtol = float(ftol), float(gtol)
         o.target = float(target) if target is not None else float("-inf")
         fh = np.zeros(max(int(history), 0), dtype=np.float64)

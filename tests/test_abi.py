@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(precision):
     assert len(names) >= 30
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.ivx_version() == 4
+    assert lib.ivx_version() == 5
     assert lib.ivx_real_size() == (4 if precision == "f32" else 8)
 
 
@@ -55,6 +55,23 @@ def test_descriptor_layout_matches_header(tmp_path, real_double):
     assert off_fwhm == ivx._Problem.sd_fwhm_rad.offset
     assert off_res == ivx._Problem.reserved.offset
     assert rs == (8 if real_double else 4)
+
+
+def test_solver_structs_match_header(tmp_path):
+    """The solver's options and result as the ctypes binding lays them out."""
+    from paper_2609_17636_amd.solver import _LbOptions, _LbResult
+
+    c = tmp_path / "probe_lb.c"
+    c.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ivx_lbfgsb.h"\n'
+                 'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(ivx_lbfgsb_options),'
+                 ' offsetof(ivx_lbfgsb_options, stream_wait), offsetof(ivx_lbfgsb_options, ftol),'
+                 ' offsetof(ivx_lbfgsb_options, target), sizeof(ivx_lbfgsb_result),'
+                 ' offsetof(ivx_lbfgsb_result, n_walks));return 0;}\n')
+    exe = tmp_path / "probe_lb"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()))
+    assert got == [ctypes.sizeof(_LbOptions), _LbOptions.stream_wait.offset, _LbOptions.ftol.offset,
+                   _LbOptions.target.offset, ctypes.sizeof(_LbResult), _LbResult.n_walks.offset]
 
 
 def _args(**over):

@@ -117,3 +117,17 @@ def test_prefix_walk_gives_the_full_sort_iterates(ws, mosaic):
         assert torch.equal(a.x, b.x)
         assert b.n_walks_full == b.n_walks
         assert a.n_walks_full < a.n_walks / 4
+
+
+def test_published_results_give_the_stream_wait_iterates(ws, mosaic):
+    """The host reads each solver step's results as soon as the step's last kernel has
+    published them (a sequence number in the mapped buffer) instead of after the stream has
+    drained: bitwise the same iterates as waiting for the stream, on the same solve."""
+    mosaic.simulate(ws.HELDOUT_BASE + 9)
+    a = mosaic.solve(maxiter=120)
+    b = mosaic.solve(maxiter=120, stream_wait=True)
+    print(f"[published waits] {1e3 * a.seconds / a.nfev:.3f} vs {1e3 * b.seconds / b.nfev:.3f} ms per evaluation "
+          f"(stream waits)", flush=True)
+    assert (a.nit, a.nfev, a.fun, a.n_walks, a.n_walks_full) == (b.nit, b.nfev, b.fun, b.n_walks, b.n_walks_full)
+    assert [f for _, f in a.history] == [f for _, f in b.history]
+    assert torch.equal(a.x, b.x)
